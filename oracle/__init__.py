@@ -1,0 +1,290 @@
+"""CPU oracle for the particle-mesh QUMOND solve (Angus et al., arXiv:1201.3185, Sec. 2).
+
+TEST INFRASTRUCTURE ONLY: the plain FP64 judge of the HIP library.  It shares no
+code with the product package and may be imported only by the test suite, the
+smoke check and the benchmark's CPU-baseline leg.
+
+The arithmetic lives in ``qumond_oracle.c`` (single-threaded, ``gcc -O2
+-ffp-contract=off``); this module builds it on demand, declares its C
+signatures, and chains the steps in the order of Sec. 2:
+
+    step 1  CIC density per box           (cic_deposit, rhs_from_q)
+    step 2  Newtonian FMG, box by box     (fmg, outer BC, BC from coarser box)
+    step 3  Eq. 2 source per box          (mond_source)
+    step 4  QUMOND FMG, box by box        (fmg)
+    then    finite-difference gravity + CIC interpolation (gather)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qumond_oracle.c")
+_SO = os.path.join(_HERE, "_qumond_oracle.so")
+
+# Units: kpc, Msun, km/s.  G in kpc (km/s)^2 / Msun; a0 = 3.6 (km/s)^2/pc (Eq. 2).
+G_KPC = 4.300917270e-6
+A0_KPC = 3600.0
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle shared object with gcc (no FMA contraction)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c99",
+             "-D_DEFAULT_SOURCE", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(build())
+        d, i, i64, vp = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+        sig = {
+            "orc_nu": (d, [d]),
+            "orc_fixed_shift": (i, [d]),
+            "orc_cic_deposit": (i64, [i, d, i64, vp, vp, vp, vp, i, vp]),
+            "orc_rhs_from_q": (None, [i, d, d, i, vp, vp]),
+            "orc_phi_point_newton": (d, [d, d, d]),
+            "orc_phi_point_mond": (d, [d, d, d, d]),
+            "orc_bc_outer": (None, [i, d, i, d, d, d, vp]),
+            "orc_bc_from_coarse": (None, [i, d, vp, d, vp]),
+            "orc_rbgs_colour": (None, [i, d, vp, vp, i]),
+            "orc_rbgs_sweep": (None, [i, d, vp, vp]),
+            "orc_residual": (None, [i, d, vp, vp, vp]),
+            "orc_interior_sumsq": (d, [i, vp]),
+            "orc_restrict_fw": (None, [i, vp, vp]),
+            "orc_prolong_add": (None, [i, vp, vp]),
+            "orc_interp": (None, [i, vp, vp]),
+            "orc_fmg": (i, [i, d, vp, vp, i, i, i, i, d, vp, vp]),
+            "orc_vcycles": (d, [i, d, vp, vp, i, i, i]),
+            "orc_mond_source": (None, [i, d, d, vp, vp]),
+            "orc_gather": (None, [i, i, vp, vp, i64, vp, vp, vp, d, d, d, d, i, vp, vp, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------- pointwise
+
+def nu(y):
+    """Eq. 2 interpolating function, elementwise."""
+    return np.vectorize(lib().orc_nu, otypes=[np.float64])(np.asarray(y, dtype=np.float64))
+
+
+def fixed_shift(total_mass: float) -> int:
+    return int(lib().orc_fixed_shift(float(total_mass)))
+
+
+def phi_point_newton(r, G=G_KPC, M=1.0):
+    return np.vectorize(lambda rr: lib().orc_phi_point_newton(rr, G, M), otypes=[np.float64])(r)
+
+
+def phi_point_mond(r, G=G_KPC, M=1.0, a0=A0_KPC):
+    return np.vectorize(lambda rr: lib().orc_phi_point_mond(rr, G, M, a0), otypes=[np.float64])(r)
+
+
+# ----------------------------------------------------------------- per box
+
+def cic_deposit(n, L, x, y, z, m, shift):
+    """Step 1 in fixed point: int64 grid [n,n,n] (z,y,x order) and the count inside."""
+    x, y, z, m = _f64(x), _f64(y), _f64(z), _f64(m)
+    q = np.zeros((n, n, n), dtype=np.int64)
+    inside = lib().orc_cic_deposit(n, float(L), len(x), _p(x), _p(y), _p(z), _p(m), int(shift), _p(q))
+    return q, int(inside)
+
+
+def rhs_from_q(n, L, q, shift, G=G_KPC):
+    f = np.zeros((n, n, n))
+    q = np.ascontiguousarray(q, dtype=np.int64)
+    lib().orc_rhs_from_q(n, float(L), float(G), int(shift), _p(q), _p(f))
+    return f
+
+
+def bc_outer(u, L, mode, G=G_KPC, a0=A0_KPC, M=0.0):
+    """mode 0 zero, 1 Newtonian monopole, 2 QUMOND monopole (boundary nodes only)."""
+    n = u.shape[0]
+    lib().orc_bc_outer(n, float(L), int(mode), float(G), float(a0), float(M), _p(u))
+    return u
+
+
+def bc_from_coarse(uc, Lc, uf, Lf):
+    n = uc.shape[0]
+    uc = _f64(uc)
+    lib().orc_bc_from_coarse(n, float(Lc), _p(uc), float(Lf), _p(uf))
+    return uf
+
+
+def rbgs_colour(f, u, h, colour):
+    lib().orc_rbgs_colour(u.shape[0], float(h), _p(_f64(f)), _p(u), int(colour))
+    return u
+
+
+def rbgs_sweep(f, u, h):
+    lib().orc_rbgs_sweep(u.shape[0], float(h), _p(_f64(f)), _p(u))
+    return u
+
+
+def residual(f, u, h):
+    r = np.zeros_like(u)
+    lib().orc_residual(u.shape[0], float(h), _p(_f64(f)), _p(_f64(u)), _p(r))
+    return r
+
+
+def restrict_fw(rf):
+    nc = (rf.shape[0] + 1) // 2
+    fc = np.zeros((nc, nc, nc))
+    lib().orc_restrict_fw(rf.shape[0], _p(_f64(rf)), _p(fc))
+    return fc
+
+
+def prolong_add(uc, uf):
+    lib().orc_prolong_add(uc.shape[0], _p(_f64(uc)), _p(uf))
+    return uf
+
+
+def interp(uc, uf):
+    lib().orc_interp(uc.shape[0], _p(_f64(uc)), _p(uf))
+    return uf
+
+
+def fmg(f, u, L, npre=2, npost=2, ncycle=6, max_extra=50, tol=1e-10):
+    """FMG in place on u (boundary = Dirichlet values). Returns (status, relres, extra)."""
+    f = _f64(f)
+    rr = ctypes.c_double(0.0)
+    ex = ctypes.c_int(0)
+    st = lib().orc_fmg(u.shape[0], float(L), _p(f), _p(u), npre, npost, ncycle, max_extra,
+                       float(tol), ctypes.byref(rr), ctypes.byref(ex))
+    return int(st), float(rr.value), int(ex.value)
+
+
+def vcycles(f, u, L, ncyc, npre=2, npost=2):
+    return float(lib().orc_vcycles(u.shape[0], float(L), _p(_f64(f)), _p(u), npre, npost, ncyc))
+
+
+def mond_source(phin, L, a0=A0_KPC):
+    phin = _f64(phin)
+    S = np.zeros_like(phin)
+    lib().orc_mond_source(phin.shape[0], float(L), float(a0), _p(phin), _p(S))
+    return S
+
+
+def gather(phis, Ls, x, y, z, frac=0.2, G=G_KPC, a0=A0_KPC, M=0.0, mond=True):
+    """Accelerations (ax, ay, az) and the box index used (255 = monopole)."""
+    n = phis[0].shape[0]
+    nbox = len(phis)
+    phis = [_f64(p) for p in phis]
+    ptrs = (ctypes.c_void_p * nbox)(*[p.ctypes.data for p in phis])
+    Ls_a = _f64(Ls)
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    np_ = len(x)
+    ax, ay, az = np.zeros(np_), np.zeros(np_), np.zeros(np_)
+    used = np.zeros(np_, dtype=np.uint8)
+    lib().orc_gather(nbox, n, _p(Ls_a), ctypes.cast(ptrs, ctypes.c_void_p), np_, _p(x), _p(y), _p(z),
+                     float(frac), float(G), float(a0), float(M), int(bool(mond)),
+                     _p(ax), _p(ay), _p(az), _p(used))
+    return ax, ay, az, used
+
+
+def rotation_curve_points(R, naz=16):
+    """Midplane sample points: naz azimuths per radius, phi_k = 2 pi k / naz."""
+    R = np.asarray(R, dtype=np.float64)
+    phi = 2.0 * np.pi * np.arange(naz) / naz
+    x = (R[:, None] * np.cos(phi)[None, :]).ravel()
+    y = (R[:, None] * np.sin(phi)[None, :]).ravel()
+    return x, y, np.zeros_like(x)
+
+
+def vc2_from_acc(x, y, ax, ay, nR, naz=16):
+    """Eq. 4: v_c^2 = R dPhi/dR = -(x a_x + y a_y), averaged over the azimuths."""
+    return (-(x * ax + y * ay)).reshape(nR, naz).mean(axis=1)
+
+
+# ------------------------------------------------------------ the pipeline
+
+@dataclass
+class OracleConfig:
+    n: int
+    box_side: list                # kpc, outermost first, each half the previous
+    G: float = G_KPC
+    a0: float = A0_KPC
+    npre: int = 2
+    npost: int = 2
+    ncycle_fmg: int = 6
+    max_vcycles: int = 50
+    tol_rel: float = 1e-10
+    outer_bc: int = 1             # 0 zero, 1 monopole
+    gather_frac: float = 0.2
+    fixed_shift: int = 0          # 0 = from the total mass
+
+
+@dataclass
+class OracleResult:
+    q: list = field(default_factory=list)
+    f: list = field(default_factory=list)
+    phin: list = field(default_factory=list)
+    S: list = field(default_factory=list)
+    phi: list = field(default_factory=list)
+    info_newton: list = field(default_factory=list)
+    info_mond: list = field(default_factory=list)
+    n_outside: int = 0
+    shift: int = 0
+
+
+def solve_chain(cfg: OracleConfig, rhs: list, mond: bool, M: float):
+    """Steps 2 and 4: FMG box by box, the outer box from its Dirichlet value,
+    every inner box from the converged solution of the next coarser one."""
+    out, info = [], []
+    for b, Lb in enumerate(cfg.box_side):
+        u = np.zeros((cfg.n,) * 3)
+        if b == 0:
+            mode = 0 if cfg.outer_bc == 0 else (2 if mond else 1)
+            bc_outer(u, Lb, mode, cfg.G, cfg.a0, M)
+        else:
+            bc_from_coarse(out[b - 1], cfg.box_side[b - 1], u, Lb)
+        st, rr, ex = fmg(rhs[b], u, Lb, cfg.npre, cfg.npost, cfg.ncycle_fmg, cfg.max_vcycles, cfg.tol_rel)
+        out.append(u)
+        info.append((st, rr, ex))
+    return out, info
+
+
+def run_pipeline(cfg: OracleConfig, x, y, z, m, total_mass: float) -> OracleResult:
+    res = OracleResult()
+    shift = cfg.fixed_shift if cfg.fixed_shift else fixed_shift(total_mass)
+    res.shift = shift
+    inside_outer = None
+    for b, Lb in enumerate(cfg.box_side):
+        q, inside = cic_deposit(cfg.n, Lb, x, y, z, m, shift)
+        if b == 0:
+            inside_outer = inside
+        res.q.append(q)
+        res.f.append(rhs_from_q(cfg.n, Lb, q, shift, cfg.G))
+    res.n_outside = len(np.asarray(x)) - inside_outer
+    res.phin, res.info_newton = solve_chain(cfg, res.f, False, total_mass)
+    res.S = [mond_source(p, Lb, cfg.a0) for p, Lb in zip(res.phin, cfg.box_side)]
+    res.phi, res.info_mond = solve_chain(cfg, res.S, True, total_mass)
+    return res
