@@ -1,0 +1,149 @@
+#!/usr/bin/env python3
+"""Throughput of the particle-mesh QUMOND solve on one MI355X.
+
+One step is one pass of the whole path over one synthetic galaxy already
+resident in HBM: CIC deposit -> Newtonian FMG -> Eq. 2 source -> QUMOND FMG ->
+force gather at every particle, all through the C ABI of libqumond.so.
+
+Workload: two-component exponential disk (stars Md = 5e10 Msun, Rd = 3 kpc,
+sech^2 height 0.3 kpc; gas Mg = 1e10 Msun, Rg = 6 kpc, height 0.15 kpc),
+1e6 particles, four nested 129^3 boxes of 400/200/100/50 kpc with a monopole
+outer boundary, 2+2 red-black sweeps and 6 V-cycles per FMG level, both solves
+to 1e-10 relative residual, in FP64.
+
+value = grid points of all boxes / wall time of one step (host syncs of the
+stopping tests included).  The roofline object reports the red-black
+smoother (the dominant kernel): algorithmic bytes (read u, read f, write u)
+of its launches divided by their summed durations, from hipEvents recorded by
+the library around each launch on the solve's stream during a second pass of
+the same K steps.  cpu_baseline times the CPU oracle (single thread) on one
+full step of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+METRIC = "QUMOND solve grid-pts/s & wall time to 1e-6 rel residual: plain FP64 vs mixed+learned"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def smoother_traffic(per_launch_alg_bytes):
+    """HBM traffic per smoother launch from committed rocprofv3 counter runs,
+    valid only while the kernel source is unchanged (null otherwise)."""
+    path = os.path.join(HERE, "profiles", "smoother_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(HERE, "paper_1201_3185_amd", "csrc", "grid_kernels.hip"), "rb").read()
+    if rec.get("grid_kernels_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile-pass", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a design "
+              "described in DESIGN.md and is not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    sys.path.insert(0, HERE)
+    from paper_1201_3185_amd import qumond as Q
+    from paper_1201_3185_amd import synth
+
+    torch.cuda.set_device(0)
+    n, sides, npart = 129, [400.0, 200.0, 100.0, 50.0], 1_000_000
+    log(f"generating {npart} particles")
+    p = synth.two_component_disk(npart, synth.seed_for(2))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    x, y, z, m = dev(p.x), dev(p.y), dev(p.z), dev(p.m)
+    M = p.total_mass
+    cfg = Q.Config(n=n, box_side=sides, tol_rel=1e-10)
+    ctx = Q.Context(cfg)
+    infos = {}
+
+    def step():
+        ctx.deposit(x, y, z, m, M, count_outside=False)
+        infos["newton"] = ctx.solve_newton()
+        ctx.mond_source()
+        infos["mond"] = ctx.solve_mond()
+        return ctx.gather_forces(x, y, z, 1, with_box=False)
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    pts = len(sides) * n ** 3
+    value = pts / (ms * 1e-3)
+    log(f"{ms:.3f} ms/step, {value:.4g} grid-pts/s")
+
+    roof = None
+    if not args.no_profile_pass:
+        ctx.profile_enable(True)
+        for _ in range(args.steps):
+            step()
+        st = ctx.profile_read()
+        ctx.profile_enable(False)
+        avg_ms = st["total_ms"] / max(st["launches"], 1)
+        per_launch = st["alg_bytes"] / max(st["launches"], 1)
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        tr = smoother_traffic(per_launch)
+        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
+                "kernel": "rbgs_zmarch (all levels)", "launches_per_step": st["launches"] // args.steps,
+                "avg_launch_us": round(avg_ms * 1e3, 3), "alg_bytes_per_launch": per_launch}
+        log(f"smoother: {st['launches']} launches, avg {avg_ms * 1e3:.2f} us, {achieved:.1f} GB/s algorithmic")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        log("timing the CPU oracle on one full step")
+        oc = O.OracleConfig(n=n, box_side=sides, tol_rel=1e-10)
+        c0 = time.perf_counter()
+        res = O.run_pipeline(oc, p.x, p.y, p.z, p.m, M)
+        O.gather(res.phi, sides, p.x, p.y, p.z, M=M, mond=True)
+        c1 = time.perf_counter()
+        cpu = {"value": pts / (c1 - c0), "unit": "grid-pts/s", "cores": 1, "kind": "oracle",
+               "sample": "one full step of the same workload (deposit, both FMG solves to 1e-10, source, "
+                         f"gather of all particles) in {c1 - c0:.1f} s, single-threaded C"}
+        log(f"oracle: {c1 - c0:.2f} s")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "grid-pts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "two-component exponential disk, 1e6 particles, 4 nested 129^3 boxes "
+                               "(400/200/100/50 kpc), monopole outer BC, FP64 FMG to 1e-10",
+                   "n": n, "boxes_kpc": sides, "particles": npart, "tol_rel": 1e-10, "ncycle_fmg": 6,
+                   "npre": 2, "npost": 2, "precision": "fp64"},
+        "vcycles_after_fmg": {"newton": infos["newton"]["vcycles"], "mond": infos["mond"]["vcycles"]},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

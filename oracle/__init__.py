@@ -65,6 +65,7 @@ def lib():
             "orc_rbgs_sweep": (None, [i, d, vp, vp]),
             "orc_residual": (None, [i, d, vp, vp, vp]),
             "orc_interior_sumsq": (d, [i, vp]),
+            "orc_boundary_coupling_sumsq": (d, [i, d, vp]),
             "orc_restrict_fw": (None, [i, vp, vp]),
             "orc_prolong_add": (None, [i, vp, vp]),
             "orc_interp": (None, [i, vp, vp]),

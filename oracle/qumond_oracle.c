@@ -343,13 +343,40 @@ static int log2_exact(int m)
     return ((1 << J) == m) ? J : -1;
 }
 
+/* Sum over interior nodes of (sum of the node's boundary neighbours / h^2)^2:
+ * the norm of the right-hand side the Dirichlet values alone contribute. */
+double orc_boundary_coupling_sumsq(int n, double h, const double *u)
+{
+    const double ih2 = 1.0 / (h * h);
+    double s = 0.0;
+    for (int k = 1; k < n - 1; k++)
+        for (int j = 1; j < n - 1; j++)
+            for (int i = 1; i < n - 1; i++) {
+                double b = 0.0;
+                if (i == 1) b += u[ID3(n, 0, j, k)];
+                if (i == n - 2) b += u[ID3(n, n - 1, j, k)];
+                if (j == 1) b += u[ID3(n, i, 0, k)];
+                if (j == n - 2) b += u[ID3(n, i, n - 1, k)];
+                if (k == 1) b += u[ID3(n, i, j, 0)];
+                if (k == n - 2) b += u[ID3(n, i, j, n - 1)];
+                b *= ih2;
+                s += b * b;
+            }
+    return s;
+}
+
+/* Relative residual of the stopping test: ||f - A_h u||_2 / ||f||_2 over the
+ * interior; for a source-free problem (||f|| = 0) the denominator is the norm
+ * of the boundary-value contribution, and if that is 0 too the test is on the
+ * absolute residual. */
 static double relres_of(mg_t *mg, double fnorm)
 {
     const int n = lvl_n(mg->J);
     const double h = mg->L / (double)(n - 1);
     orc_residual(n, h, mg->f[mg->J], mg->u[mg->J], mg->r);
     double rn = sqrt(orc_interior_sumsq(n, mg->r));
-    return fnorm > 0.0 ? rn / fnorm : rn;
+    double den = fnorm > 0.0 ? fnorm : sqrt(orc_boundary_coupling_sumsq(n, h, mg->u[mg->J]));
+    return den > 0.0 ? rn / den : rn;
 }
 
 static int mg_alloc(mg_t *mg, int n, double L, const double *f, double *u, int npre, int npost)
@@ -392,7 +419,7 @@ static void mg_free(mg_t *mg)
  *     Dirichlet corrections on coarser levels);
  *  5. then further finest-level V-cycles while
  *     ||f - A_h u||_2 / ||f||_2 (interior) > tol, at most max_extra of them
- *     (tol = 0: fixed schedule).  A zero ||f|| makes the test absolute.
+ *     (tol = 0: fixed schedule); see relres_of for a source-free box.
  * Returns 0 when converged (or fixed schedule), 1 when max_extra was hit,
  * -1 on a bad size.  *relres_out gets the final relative residual and
  * *extra_out the number of extra cycles. */

@@ -1,0 +1,452 @@
+// C ABI of the QUMOND particle-mesh solver: configuration checks, the
+// per-context grids of every nested box, the call-order state machine, and the
+// box-by-box chaining of Sec. 2 (outer Dirichlet value, then each inner box's
+// boundary interpolated from the coarser box's converged solution).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/qumond.h"
+#include "common.h"
+#include "mg.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+qumond_status fail(qumond_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+qumond_status hip_fail(hipError_t e, const char *where)
+{
+    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? QUMOND_ERR_OOM : QUMOND_ERR_HIP;
+}
+
+enum Stage { ST_CREATED = 0, ST_DEPOSITED = 1, ST_NEWTON = 2, ST_SOURCE = 3, ST_MOND = 4 };
+
+struct Box {
+    double L = 0, h = 0;
+    long long *q = nullptr;
+    double *f = nullptr, *phin = nullptr, *S = nullptr, *phi = nullptr;
+};
+
+}  // namespace
+
+void qm_set_last_error(const char *msg) { g_last_error = msg; }
+
+struct qumond_ctx {
+    qumond_config cfg;
+    hipStream_t s = nullptr;
+    int n = 0;
+    size_t N = 0;
+    Box box[QUMOND_MAX_BOX];
+    double *scratch = nullptr;           // finest-size ping-pong partner
+    qm::Multigrid<double> mg;
+    double total_mass = 0.0;
+    int shift = 0;
+    int stage = ST_CREATED;
+    unsigned long long *d_count = nullptr;
+    unsigned long long *h_count = nullptr;  // pinned
+    std::vector<void *> owned;
+    int64_t bytes = 0;
+
+    hipError_t alloc(void **p, size_t b)
+    {
+        hipError_t e = hipMalloc(p, b);
+        if (e == hipSuccess) {
+            owned.push_back(*p);
+            bytes += (int64_t)b;
+        }
+        return e;
+    }
+};
+
+extern "C" {
+
+void qumond_default_config(qumond_config *cfg)
+{
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->n = 65;
+    cfg->nbox = 1;
+    cfg->box_side[0] = 100.0;
+    cfg->G = 4.300917270e-6;
+    cfg->a0 = 3600.0;
+    cfg->npre = 2;
+    cfg->npost = 2;
+    cfg->ncycle_fmg = 6;
+    cfg->max_vcycles = 50;
+    cfg->tol_rel = 1e-10;
+    cfg->precision = QUMOND_FP64;
+    cfg->outer_bc = QUMOND_BC_MONOPOLE;
+    cfg->gather_frac = 0.2;
+    cfg->fixed_shift = 0;
+    cfg->use_graphs = 0;
+}
+
+qumond_status qumond_validate_config(const qumond_config *c)
+{
+    if (!c) return fail(QUMOND_ERR_INVALID, "config is NULL");
+    if (c->n < 5 || c->n > 1025 || qm::log2_exact(c->n - 1) < 2)
+        return fail(QUMOND_ERR_INVALID, "n must be 2^J + 1 with 5 <= n <= 1025");
+    if (c->nbox < 1 || c->nbox > QUMOND_MAX_BOX) return fail(QUMOND_ERR_INVALID, "nbox must be in 1..16");
+    for (int b = 0; b < c->nbox; ++b) {
+        if (!(c->box_side[b] > 0.0) || !std::isfinite(c->box_side[b]))
+            return fail(QUMOND_ERR_INVALID, "box_side must be finite and positive");
+        if (b > 0 && std::fabs(c->box_side[b] - 0.5 * c->box_side[b - 1]) > 1e-12 * c->box_side[b - 1])
+            return fail(QUMOND_ERR_INVALID, "each box_side must be half the previous one");
+    }
+    if (!(c->G > 0.0) || !std::isfinite(c->G)) return fail(QUMOND_ERR_INVALID, "G must be finite and positive");
+    if (!(c->a0 >= 0.0) || !std::isfinite(c->a0)) return fail(QUMOND_ERR_INVALID, "a0 must be finite and >= 0");
+    if (c->npre < 0 || c->npre > 8 || c->npost < 0 || c->npost > 8 || c->npre + c->npost < 1)
+        return fail(QUMOND_ERR_INVALID, "npre, npost must be in 0..8 with npre + npost >= 1");
+    if (c->ncycle_fmg < 1 || c->ncycle_fmg > 64) return fail(QUMOND_ERR_INVALID, "ncycle_fmg must be in 1..64");
+    if (c->max_vcycles < 0 || c->max_vcycles > 10000) return fail(QUMOND_ERR_INVALID, "max_vcycles must be in 0..10000");
+    if (!(c->tol_rel >= 0.0) || !std::isfinite(c->tol_rel)) return fail(QUMOND_ERR_INVALID, "tol_rel must be >= 0");
+    if (c->precision != QUMOND_FP64 && c->precision != QUMOND_MIXED)
+        return fail(QUMOND_ERR_INVALID, "precision must be QUMOND_FP64 or QUMOND_MIXED");
+    if (c->outer_bc != QUMOND_BC_ZERO && c->outer_bc != QUMOND_BC_MONOPOLE)
+        return fail(QUMOND_ERR_INVALID, "outer_bc must be QUMOND_BC_ZERO or QUMOND_BC_MONOPOLE");
+    if (!(c->gather_frac > 0.0 && c->gather_frac < 0.5))
+        return fail(QUMOND_ERR_INVALID, "gather_frac must be in (0, 0.5)");
+    if (c->fixed_shift < 0 || c->fixed_shift > 120) return fail(QUMOND_ERR_INVALID, "fixed_shift must be in 0..120");
+    return QUMOND_OK;
+}
+
+const char *qumond_status_string(qumond_status s)
+{
+    switch (s) {
+    case QUMOND_OK: return "ok";
+    case QUMOND_ERR_INVALID: return "invalid argument";
+    case QUMOND_ERR_STATE: return "call out of order";
+    case QUMOND_ERR_OOM: return "device out of memory";
+    case QUMOND_ERR_HIP: return "HIP runtime error";
+    case QUMOND_ERR_NOT_CONVERGED: return "not converged";
+    case QUMOND_ERR_RANGE: return "value out of range";
+    }
+    return "unknown status";
+}
+
+const char *qumond_last_error(void) { return g_last_error.c_str(); }
+
+qumond_status qumond_destroy(qumond_ctx *ctx)
+{
+    if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
+    (void)hipStreamSynchronize(ctx->s);
+    ctx->mg.release();
+    for (void *p : ctx->owned) (void)hipFree(p);
+    if (ctx->h_count) (void)hipHostFree(ctx->h_count);
+    delete ctx;
+    return QUMOND_OK;
+}
+
+qumond_status qumond_create(const qumond_config *cfg, void *hip_stream, qumond_ctx **out)
+{
+    if (!out) return fail(QUMOND_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    qumond_status st = qumond_validate_config(cfg);
+    if (st != QUMOND_OK) return st;
+    qumond_ctx *c = new (std::nothrow) qumond_ctx();
+    if (!c) return fail(QUMOND_ERR_OOM, "host allocation failed");
+    c->cfg = *cfg;
+    c->s = (hipStream_t)hip_stream;
+    c->n = cfg->n;
+    c->N = (size_t)c->n * c->n * c->n;
+    hipError_t e;
+    for (int b = 0; b < cfg->nbox; ++b) {
+        Box &B = c->box[b];
+        B.L = cfg->box_side[b];
+        B.h = B.L / (double)(c->n - 1);
+        if ((e = c->alloc((void **)&B.q, c->N * sizeof(long long))) != hipSuccess ||
+            (e = c->alloc((void **)&B.f, c->N * sizeof(double))) != hipSuccess ||
+            (e = c->alloc((void **)&B.phin, c->N * sizeof(double))) != hipSuccess ||
+            (e = c->alloc((void **)&B.S, c->N * sizeof(double))) != hipSuccess ||
+            (e = c->alloc((void **)&B.phi, c->N * sizeof(double))) != hipSuccess) {
+            qumond_status r = hip_fail(e, "qumond_create: hipMalloc");
+            qumond_destroy(c);
+            return r;
+        }
+    }
+    if ((e = c->alloc((void **)&c->scratch, c->N * sizeof(double))) != hipSuccess ||
+        (e = c->alloc((void **)&c->d_count, sizeof(unsigned long long))) != hipSuccess ||
+        (e = hipHostMalloc((void **)&c->h_count, sizeof(unsigned long long), hipHostMallocDefault)) != hipSuccess ||
+        (e = c->mg.init(c->n, cfg->npre, cfg->npost, c->s)) != hipSuccess) {
+        qumond_status r = hip_fail(e, "qumond_create: allocation");
+        qumond_destroy(c);
+        return r;
+    }
+    for (int b = 0; b < cfg->nbox; ++b) {
+        qm::launch_fill<long long>(c->box[b].q, c->N, 0LL, c->s);
+        qm::launch_fill<double>(c->box[b].f, c->N, 0.0, c->s);
+        qm::launch_fill<double>(c->box[b].phin, c->N, 0.0, c->s);
+        qm::launch_fill<double>(c->box[b].S, c->N, 0.0, c->s);
+        qm::launch_fill<double>(c->box[b].phi, c->N, 0.0, c->s);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) {
+        qumond_status r = hip_fail(e, "qumond_create: launch");
+        qumond_destroy(c);
+        return r;
+    }
+    *out = c;
+    return QUMOND_OK;
+}
+
+qumond_status qumond_profile_enable(qumond_ctx *ctx, int32_t on)
+{
+    if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
+    ctx->mg.prof.on = on != 0;
+    return QUMOND_OK;
+}
+
+qumond_status qumond_profile_read(qumond_ctx *ctx, qumond_kernel_stats *out)
+{
+    if (!ctx || !out) return fail(QUMOND_ERR_INVALID, "NULL argument");
+    hipError_t e = hipStreamSynchronize(ctx->s);
+    if (e != hipSuccess) return hip_fail(e, "qumond_profile_read");
+    qm::SmootherProfile &p = ctx->mg.prof;
+    out->launches = (int64_t)p.used;
+    out->total_ms = 0.0;
+    out->alg_bytes = 0.0;
+    for (size_t i = 0; i < p.used; ++i) {
+        float ms = 0.0f;
+        if ((e = hipEventElapsedTime(&ms, p.ev[2 * i], p.ev[2 * i + 1])) != hipSuccess)
+            return hip_fail(e, "qumond_profile_read: elapsed");
+        out->total_ms += ms;
+        out->alg_bytes += p.bytes[i];
+    }
+    p.used = 0;
+    p.bytes.clear();
+    return QUMOND_OK;
+}
+
+int64_t qumond_device_bytes(const qumond_ctx *ctx) { return ctx ? ctx->bytes + (int64_t)ctx->mg.bytes : 0; }
+
+static int fixed_shift_for(double total_mass)
+{
+    int e;
+    const double mant = std::frexp(total_mass, &e);
+    const int ceil_log2 = (mant == 0.5) ? e - 1 : e;
+    return 62 - ceil_log2 - 1;
+}
+
+qumond_status qumond_deposit(qumond_ctx *ctx, const double *x, const double *y, const double *z, const double *m,
+                             int64_t np, double total_mass, int64_t *n_outside)
+{
+    if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
+    if (np < 0) return fail(QUMOND_ERR_INVALID, "np must be >= 0");
+    if (np > 0 && (!x || !y || !z || !m)) return fail(QUMOND_ERR_INVALID, "particle arrays must not be NULL");
+    if (!(total_mass > 0.0) || !std::isfinite(total_mass))
+        return fail(QUMOND_ERR_INVALID, "total_mass must be finite and positive");
+    const int shift = ctx->cfg.fixed_shift ? ctx->cfg.fixed_shift : fixed_shift_for(total_mass);
+    if (std::ldexp(total_mass, shift) >= 9.2e18) return fail(QUMOND_ERR_RANGE, "fixed_shift overflows 64 bits");
+    ctx->shift = shift;
+    ctx->total_mass = total_mass;
+    qm::DepositArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nbox = ctx->cfg.nbox;
+    a.n = ctx->n;
+    a.scale = std::ldexp(1.0, shift);
+    for (int b = 0; b < a.nbox; ++b) {
+        const Box &B = ctx->box[b];
+        a.box[b].L = B.L;
+        a.box[b].xmin = -0.5 * B.L;
+        a.box[b].inv_h = (double)(ctx->n - 1) / B.L;
+        a.box[b].h = B.h;
+        a.q[b] = (unsigned long long *)B.q;
+        qm::launch_fill<long long>(B.q, ctx->N, 0LL, ctx->s);
+    }
+    qm::launch_fill<unsigned long long>(ctx->d_count, 1, 0ULL, ctx->s);
+    qm::launch_deposit(a, x, y, z, m, np, ctx->d_count, ctx->s);
+    const double four_pi_G = 4.0 * M_PI * ctx->cfg.G;
+    for (int b = 0; b < a.nbox; ++b)
+        qm::launch_rhs_from_q(ctx->n, ctx->box[b].h, four_pi_G, shift, ctx->box[b].q, ctx->box[b].f, ctx->s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "qumond_deposit: launch");
+    if (n_outside) {
+        if ((e = hipMemcpyAsync(ctx->h_count, ctx->d_count, sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->s)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(ctx->s)) != hipSuccess)
+            return hip_fail(e, "qumond_deposit: count");
+        *n_outside = np - (int64_t)*ctx->h_count;
+    }
+    ctx->stage = ST_DEPOSITED;
+    return QUMOND_OK;
+}
+
+// FMG chain over the boxes for one of the two potentials.
+static qumond_status solve_chain(qumond_ctx *ctx, bool mond, qumond_solve_info *info)
+{
+    const qumond_config &c = ctx->cfg;
+    const double GM = c.G * ctx->total_mass;
+    bool all_ok = true;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->nbox = c.nbox;
+    }
+    for (int b = 0; b < c.nbox; ++b) {
+        Box &B = ctx->box[b];
+        double *u = mond ? B.phi : B.phin;
+        double *f = mond ? B.S : B.f;
+        if (b == 0) {
+            const int mode = c.outer_bc == QUMOND_BC_ZERO ? 0 : (mond ? 2 : 1);
+            qm::launch_bc_outer(ctx->n, B.L, mode, GM, c.a0, u, ctx->scratch, ctx->s);
+        } else {
+            const double *uc = mond ? ctx->box[b - 1].phi : ctx->box[b - 1].phin;
+            qm::launch_bc_from_coarse(ctx->n, uc, u, ctx->scratch, ctx->s);
+        }
+        ctx->mg.bind(B.L, u, ctx->scratch, f);
+        ctx->mg.fmg(c.ncycle_fmg);
+        double rr = 0.0;
+        hipError_t e = ctx->mg.relres(rr);
+        if (e != hipSuccess) return hip_fail(e, "solve: FMG");
+        const double rr0 = rr;
+        int extra = 0;
+        while (c.tol_rel > 0.0 && rr > c.tol_rel && extra < c.max_vcycles) {
+            ctx->mg.finest_cycle();
+            ++extra;
+            if ((e = ctx->mg.relres(rr)) != hipSuccess) return hip_fail(e, "solve: V-cycle");
+        }
+        ctx->mg.finish();
+        const bool ok = !(c.tol_rel > 0.0 && !(rr <= c.tol_rel));
+        all_ok = all_ok && ok;
+        if (info) {
+            info->vcycles[b] = extra;
+            info->relres0[b] = rr0;
+            info->relres[b] = rr;
+            info->converged[b] = ok ? 1 : 0;
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "solve: launch");
+    if (!all_ok) return fail(QUMOND_ERR_NOT_CONVERGED, "relative residual above tol_rel after max_vcycles");
+    return QUMOND_OK;
+}
+
+qumond_status qumond_solve_newton(qumond_ctx *ctx, qumond_solve_info *info)
+{
+    if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
+    if (ctx->stage < ST_DEPOSITED) return fail(QUMOND_ERR_STATE, "qumond_solve_newton before qumond_deposit");
+    qumond_status st = solve_chain(ctx, false, info);
+    if (st == QUMOND_OK || st == QUMOND_ERR_NOT_CONVERGED) ctx->stage = ST_NEWTON;
+    return st;
+}
+
+qumond_status qumond_mond_source(qumond_ctx *ctx)
+{
+    if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
+    if (ctx->stage < ST_NEWTON) return fail(QUMOND_ERR_STATE, "qumond_mond_source before qumond_solve_newton");
+    for (int b = 0; b < ctx->cfg.nbox; ++b)
+        qm::launch_mond_source(ctx->n, ctx->box[b].h, ctx->cfg.a0, ctx->box[b].phin, ctx->box[b].S, ctx->s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "qumond_mond_source: launch");
+    ctx->stage = ST_SOURCE;
+    return QUMOND_OK;
+}
+
+qumond_status qumond_solve_mond(qumond_ctx *ctx, const void *guess, int32_t guess_kind, qumond_solve_info *info)
+{
+    if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
+    if (ctx->stage < ST_SOURCE) return fail(QUMOND_ERR_STATE, "qumond_solve_mond before qumond_mond_source");
+    if (guess_kind < QUMOND_GUESS_NONE || guess_kind > QUMOND_GUESS_BF16)
+        return fail(QUMOND_ERR_INVALID, "unknown guess_kind");
+    if (guess_kind != QUMOND_GUESS_NONE && !guess) return fail(QUMOND_ERR_INVALID, "guess is NULL");
+    if (guess_kind != QUMOND_GUESS_NONE) return fail(QUMOND_ERR_INVALID, "initial guesses are not supported yet");
+    qumond_status st = solve_chain(ctx, true, info);
+    if (st == QUMOND_OK || st == QUMOND_ERR_NOT_CONVERGED) ctx->stage = ST_MOND;
+    return st;
+}
+
+static qm::GatherArgs gather_args(const qumond_ctx *ctx, int which)
+{
+    qm::GatherArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nbox = ctx->cfg.nbox;
+    a.n = ctx->n;
+    for (int b = 0; b < a.nbox; ++b) {
+        const Box &B = ctx->box[b];
+        a.box[b].L = B.L;
+        a.box[b].xmin = -0.5 * B.L;
+        a.box[b].inv_h = (double)(ctx->n - 1) / B.L;
+        a.box[b].h = B.h;
+        a.phi[b] = which ? B.phi : B.phin;
+    }
+    a.frac = ctx->cfg.gather_frac;
+    a.GM = ctx->cfg.G * ctx->total_mass;
+    a.a0 = ctx->cfg.a0;
+    a.mond = which;
+    return a;
+}
+
+qumond_status qumond_gather_forces(qumond_ctx *ctx, const double *x, const double *y, const double *z, int64_t np,
+                                   int32_t which, double *ax, double *ay, double *az, uint8_t *box_used)
+{
+    if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
+    if (which != 0 && which != 1) return fail(QUMOND_ERR_INVALID, "which must be 0 (Newton) or 1 (QUMOND)");
+    if (np < 0) return fail(QUMOND_ERR_INVALID, "np must be >= 0");
+    if (np > 0 && (!x || !y || !z || !ax || !ay || !az)) return fail(QUMOND_ERR_INVALID, "array is NULL");
+    if (ctx->stage < (which ? ST_MOND : ST_NEWTON)) return fail(QUMOND_ERR_STATE, "potential not solved yet");
+    qm::launch_gather(gather_args(ctx, which), x, y, z, np, ax, ay, az, box_used, ctx->s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "qumond_gather_forces: launch");
+    return QUMOND_OK;
+}
+
+qumond_status qumond_rotation_curve(qumond_ctx *ctx, const double *R, int32_t nR, int32_t naz, int32_t which,
+                                    double *vc2)
+{
+    if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
+    if (which != 0 && which != 1) return fail(QUMOND_ERR_INVALID, "which must be 0 or 1");
+    if (nR < 0 || naz < 1 || naz > 1024) return fail(QUMOND_ERR_INVALID, "need nR >= 0 and 1 <= naz <= 1024");
+    if (nR > 0 && (!R || !vc2)) return fail(QUMOND_ERR_INVALID, "array is NULL");
+    if (ctx->stage < (which ? ST_MOND : ST_NEWTON)) return fail(QUMOND_ERR_STATE, "potential not solved yet");
+    qm::launch_rotation_curve(gather_args(ctx, which), R, nR, naz, vc2, ctx->s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "qumond_rotation_curve: launch");
+    return QUMOND_OK;
+}
+
+static void *field_ptr(qumond_ctx *ctx, int box, int field)
+{
+    Box &B = ctx->box[box];
+    switch (field) {
+    case QUMOND_FIELD_RHO_FIXED: return B.q;
+    case QUMOND_FIELD_RHS: return B.f;
+    case QUMOND_FIELD_PHI_N: return B.phin;
+    case QUMOND_FIELD_SOURCE: return B.S;
+    case QUMOND_FIELD_PHI: return B.phi;
+    }
+    return nullptr;
+}
+
+qumond_status qumond_get_field(qumond_ctx *ctx, int32_t box, int32_t field, void *dst)
+{
+    if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
+    if (box < 0 || box >= ctx->cfg.nbox) return fail(QUMOND_ERR_INVALID, "box out of range");
+    if (field < QUMOND_FIELD_RHO_FIXED || field > QUMOND_FIELD_PHI) return fail(QUMOND_ERR_INVALID, "unknown field");
+    if (!dst) return fail(QUMOND_ERR_INVALID, "dst is NULL");
+    hipError_t e = hipMemcpyAsync(dst, field_ptr(ctx, box, field), ctx->N * 8, hipMemcpyDeviceToDevice, ctx->s);
+    if (e != hipSuccess) return hip_fail(e, "qumond_get_field");
+    return QUMOND_OK;
+}
+
+qumond_status qumond_set_field(qumond_ctx *ctx, int32_t box, int32_t field, const void *src)
+{
+    if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
+    if (box < 0 || box >= ctx->cfg.nbox) return fail(QUMOND_ERR_INVALID, "box out of range");
+    if (field < QUMOND_FIELD_RHS || field > QUMOND_FIELD_PHI)
+        return fail(QUMOND_ERR_INVALID, "settable fields: RHS, PHI_N, SOURCE, PHI");
+    if (!src) return fail(QUMOND_ERR_INVALID, "src is NULL");
+    hipError_t e = hipMemcpyAsync(field_ptr(ctx, box, field), src, ctx->N * 8, hipMemcpyDeviceToDevice, ctx->s);
+    if (e != hipSuccess) return hip_fail(e, "qumond_set_field");
+    static const int stage_of[] = {ST_DEPOSITED, ST_DEPOSITED, ST_NEWTON, ST_SOURCE, ST_MOND};
+    ctx->stage = stage_of[field];
+    return QUMOND_OK;
+}
+
+}  // extern "C"

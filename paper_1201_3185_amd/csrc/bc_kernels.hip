@@ -1,0 +1,87 @@
+// Dirichlet boundary values (Sec. 2, nested refinement of Angus et al.).
+//
+// The outermost box carries either zero (the paper's box 2^10 times the
+// galaxy) or the monopole of the total mass: -G M / r for the Newtonian
+// potential, and for the QUMOND potential the radial integral of
+// nu(g_N/a0) g_N with g_N = G M / r^2,
+//   -GM/(2r) - sqrt(GM) sqrt(GM + 4 a0 r^2)/(2r) + sqrt(GM a0) asinh(2 r sqrt(a0/GM)),
+// which tends to -GM/r at small r and reduces to it for a0 = 0.
+// An inner box has half the side of the coarser one and the same n, so its
+// node i lies at coarse coordinate (n-1)/4 + i/2: on a coarse node for even
+// i, halfway between two for odd i; the boundary value is the trilinear
+// interpolant of the coarser box's solution, with weights 1 or 1/2.
+#include "common.h"
+
+namespace qm {
+
+__device__ __forceinline__ void bface_node(int n, int t, int &i, int &j, int &k)
+{
+    const int nn = n * n;
+    const int face = t / nn, r = t - face * nn;
+    const int a = r % n, b = r / n;
+    switch (face) {
+    case 0: i = 0; j = a; k = b; break;
+    case 1: i = n - 1; j = a; k = b; break;
+    case 2: j = 0; i = a; k = b; break;
+    case 3: j = n - 1; i = a; k = b; break;
+    case 4: k = 0; i = a; j = b; break;
+    default: k = n - 1; i = a; j = b; break;
+    }
+}
+
+__global__ void bc_outer_k(int n, double L, int mode, double GM, double a0, double *__restrict__ u0, double *__restrict__ u1)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 6 * n * n) return;
+    int i, j, k;
+    bface_node(n, t, i, j, k);
+    const double h = L / (double)(n - 1);
+    const double x = -0.5 * L + i * h, y = -0.5 * L + j * h, z = -0.5 * L + k * h;
+    const double r = sqrt(x * x + y * y + z * z);
+    double v = 0.0;
+    if (mode == 1) {
+        v = -GM / r;
+    } else if (mode == 2) {
+        v = -GM / (2.0 * r) - sqrt(GM) * sqrt(GM + 4.0 * a0 * r * r) / (2.0 * r) + sqrt(GM * a0) * asinh(2.0 * r * sqrt(a0 / GM));
+    }
+    const size_t p = id3(n, i, j, k);
+    u0[p] = v;
+    if (u1) u1[p] = v;
+}
+
+void launch_bc_outer(int n, double L, int mode, double GM, double a0, double *u0, double *u1, hipStream_t s)
+{
+    const int cnt = 6 * n * n;
+    hipLaunchKernelGGL(bc_outer_k, dim3((cnt + 255) / 256), dim3(256), 0, s, n, L, mode, GM, a0, u0, u1);
+}
+
+__global__ void bc_from_coarse_k(int n, const double *__restrict__ uc, double *__restrict__ u0, double *__restrict__ u1)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 6 * n * n) return;
+    int i, j, k;
+    bface_node(n, t, i, j, k);
+    const int off = (n - 1) / 4;
+    const int ia = off + (i >> 1), ib = off + ((i + 1) >> 1);
+    const int ja = off + (j >> 1), jb = off + ((j + 1) >> 1);
+    const int ka = off + (k >> 1), kb = off + ((k + 1) >> 1);
+    const double wia = (i & 1) ? 0.5 : 1.0, wib = (i & 1) ? 0.5 : 0.0;
+    const double wja = (j & 1) ? 0.5 : 1.0, wjb = (j & 1) ? 0.5 : 0.0;
+    const double wka = (k & 1) ? 0.5 : 1.0, wkb = (k & 1) ? 0.5 : 0.0;
+    const double xa = wia * uc[id3(n, ia, ja, ka)] + wib * uc[id3(n, ib, ja, ka)];
+    const double xb = wia * uc[id3(n, ia, jb, ka)] + wib * uc[id3(n, ib, jb, ka)];
+    const double xc = wia * uc[id3(n, ia, ja, kb)] + wib * uc[id3(n, ib, ja, kb)];
+    const double xd = wia * uc[id3(n, ia, jb, kb)] + wib * uc[id3(n, ib, jb, kb)];
+    const double v = wka * (wja * xa + wjb * xb) + wkb * (wja * xc + wjb * xd);
+    const size_t p = id3(n, i, j, k);
+    u0[p] = v;
+    if (u1) u1[p] = v;
+}
+
+void launch_bc_from_coarse(int n, const double *uc, double *u0, double *u1, hipStream_t s)
+{
+    const int cnt = 6 * n * n;
+    hipLaunchKernelGGL(bc_from_coarse_k, dim3((cnt + 255) / 256), dim3(256), 0, s, n, uc, u0, u1);
+}
+
+}  // namespace qm

@@ -1,0 +1,79 @@
+// Internal declarations of the gfx950 QUMOND library: grid indexing, the
+// per-box descriptors handed to particle kernels by value, and the host
+// launchers each kernel file exports to the multigrid driver and the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace qm {
+
+constexpr int kMaxBox = 16;
+
+__host__ __device__ __forceinline__ size_t id3(int n, int i, int j, int k)
+{
+    return (size_t)i + (size_t)n * ((size_t)j + (size_t)n * (size_t)k);
+}
+
+// Geometry of one box as the particle kernels see it.
+struct BoxGeom {
+    double L;       // side, kpc
+    double xmin;    // -L/2
+    double inv_h;   // (n-1)/L
+    double h;       // L/(n-1)
+};
+
+struct DepositArgs {
+    int nbox, n;
+    BoxGeom box[kMaxBox];
+    unsigned long long *q[kMaxBox];
+    double scale;   // 2^s
+};
+
+struct GatherArgs {
+    int nbox, n;
+    BoxGeom box[kMaxBox];
+    const double *phi[kMaxBox];
+    double frac, GM, a0;
+    int mond;
+};
+
+// ---- grid_kernels.hip (templated on the storage type: double or float)
+template <typename T> void launch_rbgs(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s);
+template <typename T> void launch_residual_restrict(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1,
+                                                   hipStream_t s);
+template <typename T> void launch_restrict(int nf, const T *src, T *dst, hipStream_t s);
+template <typename T> void launch_prolong_add(int nc, const T *uc, T *uf, hipStream_t s);
+template <typename T> void launch_interp(int nc, const T *uc, T *uf, hipStream_t s);
+template <typename T> void launch_inject_boundary(int nfine, const T *ufine, int nl, T *u0, T *u1, hipStream_t s);
+template <typename T> void launch_fill(T *p, size_t count, T v, hipStream_t s);
+template <typename T> void launch_boundary_copy(int n, const T *src, T *dst, hipStream_t s);
+// Coarse tail: all levels with n <= 17 inside one workgroup's LDS.  mode 0: one
+// V-cycle of the top level (correction, zero boundary); mode 1: FMG from 3^3 up to
+// the top level with ncycle V-cycles per level (boundary of u = Dirichlet values).
+template <typename T> void launch_coarse_tail(int ltop, double L, const T *f, T *u, int npre, int npost, int ncycle,
+                                             int mode, int nrep, hipStream_t s);
+// Sums over interior nodes of (f - A_h u)^2, f^2 and of the squared boundary-value
+// contribution: per-block partials (3 per block), then one block in fixed order,
+// into out[0..2] (device doubles).
+template <typename T> void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial, double *out,
+                                             hipStream_t s);
+constexpr int kNormBlocks = 512;
+
+// ---- bc_kernels.hip
+// mode 0 zero, 1 Newtonian monopole -GM/r, 2 QUMOND monopole.
+void launch_bc_outer(int n, double L, int mode, double GM, double a0, double *u0, double *u1, hipStream_t s);
+void launch_bc_from_coarse(int n, const double *uc, double *u0, double *u1, hipStream_t s);
+
+// ---- particle_kernels.hip
+void launch_deposit(const DepositArgs &a, const double *x, const double *y, const double *z, const double *m,
+                    int64_t np, unsigned long long *inside_count, hipStream_t s);
+void launch_rhs_from_q(int n, double h, double four_pi_G, int shift, const long long *q, double *f, hipStream_t s);
+void launch_gather(const GatherArgs &a, const double *x, const double *y, const double *z, int64_t np, double *ax,
+                   double *ay, double *az, uint8_t *box_used, hipStream_t s);
+void launch_rotation_curve(const GatherArgs &a, const double *R, int nR, int naz, double *vc2, hipStream_t s);
+
+// ---- source_kernel.hip
+void launch_mond_source(int n, double h, double a0, const double *phin, double *S, hipStream_t s);
+
+}  // namespace qm

@@ -1,0 +1,606 @@
+// Multigrid kernels for gfx950 (Sec. 2 of Angus et al.: FMG with red-black
+// Gauss-Seidel for the 7-point Laplacian on vertex-centred n = 2^J + 1 grids).
+//
+// Smoother design.  One launch performs a whole red-black sweep out of place
+// (u_in -> u_out).  Each workgroup owns a TX x TY column tile and marches up a
+// range of z planes, keeping five planes of the tile plus a two-node ring in
+// LDS.  A plane first holds the old values; the red pass overwrites its red
+// entries (red = (i+j+k) even, updated first) over the tile and a one-node
+// ring, which only needs old black values, so the black pass on the tile then
+// finds every new red neighbour in LDS.  Red values on the ring are recomputed
+// by the neighbouring tiles from the same old values, so the result equals a
+// plain red pass followed by a black pass, with u read once and written once
+// (24 bytes per point in FP64).  Reading u_in and writing u_out avoids any
+// race between tiles; the driver alternates two buffers.
+#include "common.h"
+
+namespace qm {
+
+// ------------------------------------------------------------------ smoother
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY)
+rbgs_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2, int kchunk)
+{
+    constexpr int PX = TX + 4, PY = TY + 4, NS = 5, NT = TX * TY;
+    __shared__ T pl[NS][PX * PY];
+    const int tid = threadIdx.x;
+    const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
+    const int kb = 1 + blockIdx.z * kchunk;
+    if (kb > n - 2) return;
+    const int ke = min(kb + kchunk - 1, n - 2);
+
+    auto load = [&](int k) {
+        T *P = pl[k % NS];
+        for (int t = tid; t < PX * PY; t += NT) {
+            const int a = t % PX, b = t / PX;
+            const int i = i0 - 2 + a, j = j0 - 2 + b;
+            T v = T(0);
+            if (i < n && j < n && i >= 0 && j >= 0) v = uin[id3(n, i, j, k)];
+            P[t] = v;
+        }
+    };
+    // red nodes of plane k on the tile plus a one-node ring
+    auto red = [&](int k) {
+        T *P = pl[k % NS];
+        const T *Pm = pl[(k - 1) % NS];
+        const T *Pp = pl[(k + 1) % NS];
+        constexpr int HALF = (TX + 2) / 2;
+        for (int t = tid; t < HALF * (TY + 2); t += NT) {
+            const int b = 1 + t / HALF;
+            const int j = j0 - 2 + b;
+            const int a = ((((i0 - 1) + j + k) & 1) ? 2 : 1) + 2 * (t % HALF);
+            const int i = i0 - 2 + a;
+            if (i < 1 || i > n - 2 || j < 1 || j > n - 2) continue;
+            const int c = b * PX + a;
+            const T s = P[c - 1] + P[c + 1] + P[c - PX] + P[c + PX] + Pm[c] + Pp[c];
+            P[c] = (s - h2 * f[id3(n, i, j, k)]) / T(6);
+        }
+    };
+    // black nodes of plane k on the tile; store the whole tile row of plane k
+    auto black_store = [&](int k) {
+        const T *P = pl[k % NS];
+        const T *Pm = pl[(k - 1) % NS];
+        const T *Pp = pl[(k + 1) % NS];
+        for (int t = tid; t < TX * TY; t += NT) {
+            const int a = 2 + t % TX, b = 2 + t / TX;
+            const int i = i0 - 2 + a, j = j0 - 2 + b;
+            if (i > n - 2 || j > n - 2) continue;
+            const int c = b * PX + a;
+            T v;
+            if (((i + j + k) & 1) == 0) {
+                v = P[c];
+            } else {
+                const T s = P[c - 1] + P[c + 1] + P[c - PX] + P[c + PX] + Pm[c] + Pp[c];
+                v = (s - h2 * f[id3(n, i, j, k)]) / T(6);
+            }
+            uout[id3(n, i, j, k)] = v;
+        }
+    };
+
+    if (kb >= 2) load(kb - 2);
+    load(kb - 1);
+    load(kb);
+    load(kb + 1);
+    if (kb + 2 <= n - 1) load(kb + 2);
+    __syncthreads();
+    if (kb - 1 >= 1) red(kb - 1);
+    red(kb);
+    if (kb + 1 <= n - 2) red(kb + 1);
+    __syncthreads();
+    for (int k = kb; k <= ke; ++k) {
+        const bool more = (k + 2 <= n - 2) && (k + 2 <= ke + 1);
+        if (more) load(k + 3);
+        black_store(k);
+        __syncthreads();
+        if (more) red(k + 2);
+        __syncthreads();
+    }
+}
+
+template <typename T, int TX, int TY>
+static void rbgs_launch(int n, double h, const T *f, const T *uin, T *uout, int kchunk, hipStream_t s)
+{
+    const int m = n - 2;
+    dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, (m + kchunk - 1) / kchunk);
+    hipLaunchKernelGGL((rbgs_zmarch<T, TX, TY>), grid, dim3(TX * TY), 0, s, uin, uout, f, n, T(h * h), kchunk);
+}
+
+template <typename T>
+void launch_rbgs(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s)
+{
+    if (n <= 33) rbgs_launch<T, 32, 8>(n, h, f, uin, uout, 4, s);
+    else if (n <= 65) rbgs_launch<T, 64, 4>(n, h, f, uin, uout, 8, s);
+    else if (n <= 129) rbgs_launch<T, 64, 4>(n, h, f, uin, uout, 16, s);
+    else if (n <= 257) rbgs_launch<T, 64, 4>(n, h, f, uin, uout, 64, s);
+    else rbgs_launch<T, 64, 4>(n, h, f, uin, uout, 128, s);
+}
+
+// ------------------------------------------------- residual and restriction
+
+// Coarse node (I,J,K): fc = sum_{a,b,c} w_a w_b w_c r(2I+a, 2J+b, 2K+c) with
+// r = f - A_h u, w = (1/4, 1/2, 1/4); coarse boundary 0.  Also zeroes the
+// coarse correction (uc0 everywhere, uc1 on the boundary).
+template <typename T>
+__global__ void residual_restrict_k(int nf, T ih2, const T *__restrict__ f, const T *__restrict__ u, T *__restrict__ fc,
+                                    T *__restrict__ uc0, T *__restrict__ uc1)
+{
+    const int nc = (nf + 1) / 2;
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    const int K = blockIdx.z * blockDim.z + threadIdx.z;
+    if (I >= nc || J >= nc || K >= nc) return;
+    const size_t C = id3(nc, I, J, K);
+    const bool bnd = I == 0 || J == 0 || K == 0 || I == nc - 1 || J == nc - 1 || K == nc - 1;
+    uc0[C] = T(0);
+    if (bnd) {
+        if (uc1) uc1[C] = T(0);
+        fc[C] = T(0);
+        return;
+    }
+    const size_t sy = (size_t)nf, sz = (size_t)nf * nf;
+    const T w[3] = {T(0.25), T(0.5), T(0.25)};
+    T acc = T(0);
+    for (int c = -1; c <= 1; ++c)
+        for (int b = -1; b <= 1; ++b)
+            for (int a = -1; a <= 1; ++a) {
+                const size_t p = id3(nf, 2 * I + a, 2 * J + b, 2 * K + c);
+                const T lap = (u[p - 1] + u[p + 1] + u[p - sy] + u[p + sy] + u[p - sz] + u[p + sz] - T(6) * u[p]) * ih2;
+                acc += (w[a + 1] * w[b + 1] * w[c + 1]) * (f[p] - lap);
+            }
+    fc[C] = acc;
+}
+
+template <typename T>
+__global__ void restrict_k(int nf, const T *__restrict__ src, T *__restrict__ dst)
+{
+    const int nc = (nf + 1) / 2;
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    const int K = blockIdx.z * blockDim.z + threadIdx.z;
+    if (I >= nc || J >= nc || K >= nc) return;
+    const size_t C = id3(nc, I, J, K);
+    if (I == 0 || J == 0 || K == 0 || I == nc - 1 || J == nc - 1 || K == nc - 1) {
+        dst[C] = T(0);
+        return;
+    }
+    const T w[3] = {T(0.25), T(0.5), T(0.25)};
+    T acc = T(0);
+    for (int c = -1; c <= 1; ++c)
+        for (int b = -1; b <= 1; ++b)
+            for (int a = -1; a <= 1; ++a)
+                acc += (w[a + 1] * w[b + 1] * w[c + 1]) * src[id3(nf, 2 * I + a, 2 * J + b, 2 * K + c)];
+    dst[C] = acc;
+}
+
+static dim3 grid3(int m, dim3 blk)
+{
+    return dim3((m + blk.x - 1) / blk.x, (m + blk.y - 1) / blk.y, (m + blk.z - 1) / blk.z);
+}
+
+template <typename T>
+void launch_residual_restrict(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1, hipStream_t s)
+{
+    const int nc = (nf + 1) / 2;
+    dim3 blk(16, 4, 4);
+    hipLaunchKernelGGL(residual_restrict_k<T>, grid3(nc, blk), blk, 0, s, nf, T(1.0 / (h * h)), f, u, fc, uc0, uc1);
+}
+
+template <typename T>
+void launch_restrict(int nf, const T *src, T *dst, hipStream_t s)
+{
+    const int nc = (nf + 1) / 2;
+    dim3 blk(16, 4, 4);
+    hipLaunchKernelGGL(restrict_k<T>, grid3(nc, blk), blk, 0, s, nf, src, dst);
+}
+
+// ------------------------------------------------------------- prolongation
+
+// Trilinear value of the coarse field at fine node (i,j,k): an even fine index
+// sits on coarse node i/2, an odd one halfway between (i-1)/2 and (i+1)/2.
+template <typename T>
+__device__ __forceinline__ T prolong_at(int nc, const T *__restrict__ uc, int i, int j, int k)
+{
+    const int ia = i >> 1, ib = (i + 1) >> 1, ja = j >> 1, jb = (j + 1) >> 1, ka = k >> 1, kb = (k + 1) >> 1;
+    const T wia = (i & 1) ? T(0.5) : T(1), wib = (i & 1) ? T(0.5) : T(0);
+    const T wja = (j & 1) ? T(0.5) : T(1), wjb = (j & 1) ? T(0.5) : T(0);
+    const T wka = (k & 1) ? T(0.5) : T(1), wkb = (k & 1) ? T(0.5) : T(0);
+    const T xa = wia * uc[id3(nc, ia, ja, ka)] + wib * uc[id3(nc, ib, ja, ka)];
+    const T xb = wia * uc[id3(nc, ia, jb, ka)] + wib * uc[id3(nc, ib, jb, ka)];
+    const T xc = wia * uc[id3(nc, ia, ja, kb)] + wib * uc[id3(nc, ib, ja, kb)];
+    const T xd = wia * uc[id3(nc, ia, jb, kb)] + wib * uc[id3(nc, ib, jb, kb)];
+    return wka * (wja * xa + wjb * xb) + wkb * (wja * xc + wjb * xd);
+}
+
+template <typename T, bool ADD>
+__global__ void prolong_k(int nc, const T *__restrict__ uc, T *__restrict__ uf)
+{
+    const int nf = 2 * nc - 1;
+    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = 1 + blockIdx.z * blockDim.z + threadIdx.z;
+    if (i > nf - 2 || j > nf - 2 || k > nf - 2) return;
+    const size_t p = id3(nf, i, j, k);
+    const T v = prolong_at(nc, uc, i, j, k);
+    if (ADD) uf[p] += v;
+    else uf[p] = v;
+}
+
+template <typename T>
+void launch_prolong_add(int nc, const T *uc, T *uf, hipStream_t s)
+{
+    const int nf = 2 * nc - 1;
+    dim3 blk(64, 2, 2);
+    hipLaunchKernelGGL((prolong_k<T, true>), grid3(nf - 2, blk), blk, 0, s, nc, uc, uf);
+}
+
+template <typename T>
+void launch_interp(int nc, const T *uc, T *uf, hipStream_t s)
+{
+    const int nf = 2 * nc - 1;
+    dim3 blk(64, 2, 2);
+    hipLaunchKernelGGL((prolong_k<T, false>), grid3(nf - 2, blk), blk, 0, s, nc, uc, uf);
+}
+
+// ------------------------------------------------------- boundary helpers
+
+// Boundary node number t in [0, 6 n^2) -> (i,j,k); edges are visited more
+// than once, always with the same value.
+__device__ __forceinline__ void face_node(int n, int t, int &i, int &j, int &k)
+{
+    const int nn = n * n;
+    const int face = t / nn, r = t - face * nn;
+    const int a = r % n, b = r / n;
+    switch (face) {
+    case 0: i = 0; j = a; k = b; break;
+    case 1: i = n - 1; j = a; k = b; break;
+    case 2: j = 0; i = a; k = b; break;
+    case 3: j = n - 1; i = a; k = b; break;
+    case 4: k = 0; i = a; j = b; break;
+    default: k = n - 1; i = a; j = b; break;
+    }
+}
+
+template <typename T>
+__global__ void inject_boundary_k(int nfine, const T *__restrict__ ufine, int nl, T *__restrict__ u0, T *__restrict__ u1)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 6 * nl * nl) return;
+    int i, j, k;
+    face_node(nl, t, i, j, k);
+    const int st = (nfine - 1) / (nl - 1);
+    const T v = ufine[id3(nfine, i * st, j * st, k * st)];
+    u0[id3(nl, i, j, k)] = v;
+    if (u1) u1[id3(nl, i, j, k)] = v;
+}
+
+template <typename T>
+void launch_inject_boundary(int nfine, const T *ufine, int nl, T *u0, T *u1, hipStream_t s)
+{
+    const int cnt = 6 * nl * nl;
+    hipLaunchKernelGGL(inject_boundary_k<T>, dim3((cnt + 255) / 256), dim3(256), 0, s, nfine, ufine, nl, u0, u1);
+}
+
+template <typename T>
+__global__ void boundary_copy_k(int n, const T *__restrict__ src, T *__restrict__ dst)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 6 * n * n) return;
+    int i, j, k;
+    face_node(n, t, i, j, k);
+    dst[id3(n, i, j, k)] = src[id3(n, i, j, k)];
+}
+
+template <typename T>
+void launch_boundary_copy(int n, const T *src, T *dst, hipStream_t s)
+{
+    const int cnt = 6 * n * n;
+    hipLaunchKernelGGL(boundary_copy_k<T>, dim3((cnt + 255) / 256), dim3(256), 0, s, n, src, dst);
+}
+
+template <typename T>
+__global__ void fill_k(T *p, size_t count, T v)
+{
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < count; t += (size_t)gridDim.x * blockDim.x)
+        p[t] = v;
+}
+
+template <typename T>
+void launch_fill(T *p, size_t count, T v, hipStream_t s)
+{
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks == 0) return;
+    hipLaunchKernelGGL(fill_k<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, count, v);
+}
+
+// ------------------------------------------------------------- coarse tail
+//
+// Every level with at most 17 points per side lives in the LDS of a single
+// workgroup (u and f of 17^3, 9^3, 5^3, 3^3: 5794 values each), so a V-cycle
+// or a whole FMG over these levels is one launch.  Level l has 2^l + 1 points.
+
+constexpr int kTailTop = 4;              // 17^3
+constexpr int kTailThreads = 1024;
+__host__ __device__ constexpr int tail_off(int l)
+{
+    return l <= 1 ? 0 : tail_off(l - 1) + ((1 << (l - 1)) + 1) * ((1 << (l - 1)) + 1) * ((1 << (l - 1)) + 1);
+}
+constexpr int kTailSize = tail_off(kTailTop + 1);
+
+template <typename T>
+struct TailLDS {
+    T *U, *F;
+    T L;
+    int npre, npost;
+    __device__ int nl(int l) const { return (1 << l) + 1; }
+    __device__ T *u(int l) const { return U + tail_off(l); }
+    __device__ T *fr(int l) const { return F + tail_off(l); }
+
+    __device__ void gs(int l, int colour) const
+    {
+        const int n = nl(l), m = n - 2;
+        const T h = L / T(n - 1), h2 = h * h;
+        T *uu = u(l);
+        const T *ff = fr(l);
+        const int cnt = m * m * m;
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+            const int i = 1 + t % m, j = 1 + (t / m) % m, k = 1 + t / (m * m);
+            if (((i + j + k) & 1) != colour) continue;
+            const int p = i + n * (j + n * k);
+            const T s = uu[p - 1] + uu[p + 1] + uu[p - n] + uu[p + n] + uu[p - n * n] + uu[p + n * n];
+            uu[p] = (s - h2 * ff[p]) / T(6);
+        }
+        __syncthreads();
+    }
+    __device__ void sweeps(int l, int ns) const
+    {
+        for (int s = 0; s < ns; ++s) {
+            gs(l, 0);
+            gs(l, 1);
+        }
+    }
+    // exact solve of the single interior node of the 3^3 level, in FP64
+    __device__ void exact() const
+    {
+        if (threadIdx.x == 0) {
+            T *uu = u(1);
+            const T *ff = fr(1);
+            const double h = double(L) / 2.0;
+            const int p = 13;
+            const double s = double(uu[p - 1]) + double(uu[p + 1]) + double(uu[p - 3]) + double(uu[p + 3]) +
+                             double(uu[p - 9]) + double(uu[p + 9]);
+            uu[p] = T((s - h * h * double(ff[p])) / 6.0);
+        }
+        __syncthreads();
+    }
+    // fc = FW(f - A u) on level l-1, uc = 0
+    __device__ void resid_restrict(int l) const
+    {
+        const int n = nl(l), nc = nl(l - 1);
+        const T h = L / T(n - 1), ih2 = T(1) / (h * h);
+        const T *uu = u(l);
+        const T *ff = fr(l);
+        T *fc = fr(l - 1);
+        T *uc = u(l - 1);
+        const int cnt = nc * nc * nc;
+        const T w[3] = {T(0.25), T(0.5), T(0.25)};
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+            const int I = t % nc, J = (t / nc) % nc, K = t / (nc * nc);
+            uc[t] = T(0);
+            if (I == 0 || J == 0 || K == 0 || I == nc - 1 || J == nc - 1 || K == nc - 1) {
+                fc[t] = T(0);
+                continue;
+            }
+            T acc = T(0);
+            for (int c = -1; c <= 1; ++c)
+                for (int b = -1; b <= 1; ++b)
+                    for (int a = -1; a <= 1; ++a) {
+                        const int p = (2 * I + a) + n * ((2 * J + b) + n * (2 * K + c));
+                        const T lap =
+                            (uu[p - 1] + uu[p + 1] + uu[p - n] + uu[p + n] + uu[p - n * n] + uu[p + n * n] - T(6) * uu[p]) * ih2;
+                        acc += (w[a + 1] * w[b + 1] * w[c + 1]) * (ff[p] - lap);
+                    }
+            fc[t] = acc;
+        }
+        __syncthreads();
+    }
+    __device__ void restrict_f(int l) const   // f_{l-1} = FW(f_l)
+    {
+        const int n = nl(l), nc = nl(l - 1);
+        const T *ff = fr(l);
+        T *fc = fr(l - 1);
+        const int cnt = nc * nc * nc;
+        const T w[3] = {T(0.25), T(0.5), T(0.25)};
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+            const int I = t % nc, J = (t / nc) % nc, K = t / (nc * nc);
+            if (I == 0 || J == 0 || K == 0 || I == nc - 1 || J == nc - 1 || K == nc - 1) {
+                fc[t] = T(0);
+                continue;
+            }
+            T acc = T(0);
+            for (int c = -1; c <= 1; ++c)
+                for (int b = -1; b <= 1; ++b)
+                    for (int a = -1; a <= 1; ++a)
+                        acc += (w[a + 1] * w[b + 1] * w[c + 1]) * ff[(2 * I + a) + n * ((2 * J + b) + n * (2 * K + c))];
+            fc[t] = acc;
+        }
+        __syncthreads();
+    }
+    __device__ void prolong(int lc, bool add) const   // level lc -> lc+1 interior
+    {
+        const int nc = nl(lc), n = nl(lc + 1), m = n - 2;
+        const T *uc = u(lc);
+        T *uf = u(lc + 1);
+        const int cnt = m * m * m;
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+            const int i = 1 + t % m, j = 1 + (t / m) % m, k = 1 + t / (m * m);
+            const T v = prolong_at(nc, uc, i, j, k);
+            const int p = i + n * (j + n * k);
+            uf[p] = add ? uf[p] + v : v;
+        }
+        __syncthreads();
+    }
+    __device__ void inject(int l, int top) const   // boundary of level l from level top
+    {
+        const int n = nl(l), nt = nl(top), st = (nt - 1) / (n - 1);
+        T *uu = u(l);
+        const T *ut = u(top);
+        const int cnt = n * n * n;
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+            const int i = t % n, j = (t / n) % n, k = t / (n * n);
+            const bool bnd = i == 0 || j == 0 || k == 0 || i == n - 1 || j == n - 1 || k == n - 1;
+            uu[t] = bnd ? ut[(i * st) + nt * ((j * st) + nt * (k * st))] : T(0);
+        }
+        __syncthreads();
+    }
+    __device__ void vcycle(int top) const
+    {
+        for (int l = top; l >= 2; --l) {
+            sweeps(l, npre);
+            resid_restrict(l);
+        }
+        exact();
+        for (int l = 2; l <= top; ++l) {
+            prolong(l - 1, true);
+            sweeps(l, npost);
+        }
+    }
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kTailThreads)
+coarse_tail_k(int top, T L, const T *__restrict__ fg, T *__restrict__ ug, int npre, int npost, int ncycle, int mode,
+              int nrep)
+{
+    __shared__ T U[kTailSize];
+    __shared__ T F[kTailSize];
+    TailLDS<T> t{U, F, L, npre, npost};
+    const int n = t.nl(top), cnt = n * n * n;
+    for (int p = threadIdx.x; p < cnt; p += blockDim.x) {
+        t.u(top)[p] = ug[p];
+        t.fr(top)[p] = fg[p];
+    }
+    __syncthreads();
+    if (mode == 1) {
+        for (int l = top - 1; l >= 1; --l) t.restrict_f(l + 1);
+        for (int l = 1; l < top; ++l) t.inject(l, top);
+        t.exact();
+        for (int l = 2; l <= top; ++l) {
+            t.prolong(l - 1, false);
+            for (int c = 0; c < ncycle; ++c) t.vcycle(l);
+        }
+    } else {
+        for (int r = 0; r < nrep; ++r) t.vcycle(top);
+    }
+    for (int p = threadIdx.x; p < cnt; p += blockDim.x) ug[p] = t.u(top)[p];
+}
+
+template <typename T>
+void launch_coarse_tail(int ltop, double L, const T *f, T *u, int npre, int npost, int ncycle, int mode, int nrep,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(coarse_tail_k<T>, dim3(1), dim3(kTailThreads), 0, s, ltop, T(L), f, u, npre, npost, ncycle,
+                       mode, nrep);
+}
+
+// ------------------------------------------------------------------ norms
+
+template <int NT>
+__device__ __forceinline__ void block_sum3(double *sh, double &a, double &b, double &c)
+{
+    sh[threadIdx.x] = a;
+    sh[NT + threadIdx.x] = b;
+    sh[2 * NT + threadIdx.x] = c;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sh[threadIdx.x] += sh[threadIdx.x + w];
+            sh[NT + threadIdx.x] += sh[NT + threadIdx.x + w];
+            sh[2 * NT + threadIdx.x] += sh[2 * NT + threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    a = sh[0];
+    b = sh[NT];
+    c = sh[2 * NT];
+}
+
+// Per-block partial sums over interior nodes of (f - A_h u)^2, f^2 and the
+// squared boundary-value contribution (sum of boundary neighbours / h^2),
+// which scales the stopping test of a source-free box.
+template <typename T>
+__global__ void __launch_bounds__(256)
+resid_norms_partial_k(int n, double ih2, const T *__restrict__ f, const T *__restrict__ u, double *__restrict__ partial)
+{
+    __shared__ double sh[768];
+    const int m = n - 2;
+    const size_t cnt = (size_t)m * m * m;
+    const size_t sy = (size_t)n, sz = (size_t)n * n;
+    double sr = 0.0, sf = 0.0, sb = 0.0;
+    for (size_t t = blockIdx.x * (size_t)256 + threadIdx.x; t < cnt; t += (size_t)gridDim.x * 256) {
+        const int i = 1 + (int)(t % m), j = 1 + (int)((t / m) % m), k = 1 + (int)(t / ((size_t)m * m));
+        const size_t p = id3(n, i, j, k);
+        const double um = u[p - 1], up = u[p + 1], vm = u[p - sy], vp = u[p + sy], wm = u[p - sz], wp = u[p + sz];
+        const double lap = (um + up + vm + vp + wm + wp - 6.0 * (double)u[p]) * ih2;
+        const double fv = (double)f[p];
+        const double r = fv - lap;
+        sr += r * r;
+        sf += fv * fv;
+        if (i == 1 || j == 1 || k == 1 || i == n - 2 || j == n - 2 || k == n - 2) {
+            const double b = ((i == 1 ? um : 0.0) + (i == n - 2 ? up : 0.0) + (j == 1 ? vm : 0.0) +
+                              (j == n - 2 ? vp : 0.0) + (k == 1 ? wm : 0.0) + (k == n - 2 ? wp : 0.0)) * ih2;
+            sb += b * b;
+        }
+    }
+    block_sum3<256>(sh, sr, sf, sb);
+    if (threadIdx.x == 0) {
+        partial[3 * blockIdx.x] = sr;
+        partial[3 * blockIdx.x + 1] = sf;
+        partial[3 * blockIdx.x + 2] = sb;
+    }
+}
+
+__global__ void __launch_bounds__(256) norms_final_k(const double *__restrict__ partial, int nb, double *__restrict__ out)
+{
+    __shared__ double sh[768];
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int t = threadIdx.x; t < nb; t += 256) {
+        a += partial[3 * t];
+        b += partial[3 * t + 1];
+        c += partial[3 * t + 2];
+    }
+    block_sum3<256>(sh, a, b, c);
+    if (threadIdx.x == 0) {
+        out[0] = a;
+        out[1] = b;
+        out[2] = c;
+    }
+}
+
+template <typename T>
+void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(resid_norms_partial_k<T>, dim3(kNormBlocks), dim3(256), 0, s, n, 1.0 / (h * h), f, u, partial);
+    hipLaunchKernelGGL(norms_final_k, dim3(1), dim3(256), 0, s, partial, kNormBlocks, out);
+}
+
+// -------------------------------------------------------- instantiations
+#define QM_INST(T)                                                                                              \
+    template void launch_rbgs<T>(int, double, const T *, const T *, T *, hipStream_t);                         \
+    template void launch_residual_restrict<T>(int, double, const T *, const T *, T *, T *, T *, hipStream_t);  \
+    template void launch_restrict<T>(int, const T *, T *, hipStream_t);                                        \
+    template void launch_prolong_add<T>(int, const T *, T *, hipStream_t);                                     \
+    template void launch_interp<T>(int, const T *, T *, hipStream_t);                                          \
+    template void launch_inject_boundary<T>(int, const T *, int, T *, T *, hipStream_t);                       \
+    template void launch_fill<T>(T *, size_t, T, hipStream_t);                                                 \
+    template void launch_boundary_copy<T>(int, const T *, T *, hipStream_t);                                   \
+    template void launch_coarse_tail<T>(int, double, const T *, T *, int, int, int, int, int, hipStream_t);    \
+    template void launch_resid_norms<T>(int, double, const T *, const T *, double *, double *, hipStream_t);
+QM_INST(double)
+QM_INST(float)
+#undef QM_INST
+template void launch_fill<long long>(long long *, size_t, long long, hipStream_t);
+template void launch_fill<unsigned long long>(unsigned long long *, size_t, unsigned long long, hipStream_t);
+
+}  // namespace qm

@@ -1,0 +1,228 @@
+// Host-side full-multigrid schedule (Sec. 2 of Angus et al., after the
+// Numerical Recipes FMG cited there): rhs restricted to the coarse levels,
+// boundary values injected, the levels with at most 17 points per side solved
+// inside one workgroup (FMG bootstrap from the exact 3^3 solve), then for each
+// finer level trilinear interpolation and ncycle V(npre,npost) cycles, then
+// extra finest-level cycles under a relative-residual test.
+//
+// Every level keeps two buffers for u because the smoother works out of place;
+// `cur` says which one holds the iterate.  Both buffers carry the level's
+// boundary values (Dirichlet values on FMG levels, zero on correction levels).
+#pragma once
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace qm {
+
+inline int log2_exact(int m)
+{
+    int J = 0;
+    while ((1 << J) < m) ++J;
+    return ((1 << J) == m) ? J : -1;
+}
+
+constexpr int kTailLevel = 4;  // 17^3: the coarse tail kernel's top level
+
+template <typename T>
+struct Level {
+    int n = 0;
+    double h = 0.0;
+    T *u[2] = {nullptr, nullptr};
+    T *f = nullptr;
+    int cur = 0;
+};
+
+// Optional per-launch timing of the smoother (hipEvents on the solve stream)
+// with its algorithmic traffic: read u, read f, write u = 3 values per node.
+struct SmootherProfile {
+    bool on = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<double> bytes;
+    size_t used = 0;
+    void record_pair(hipStream_t s, hipEvent_t *a, hipEvent_t *b)
+    {
+        if (ev.size() < 2 * (used + 1)) {
+            hipEvent_t e0, e1;
+            (void)hipEventCreate(&e0);
+            (void)hipEventCreate(&e1);
+            ev.push_back(e0);
+            ev.push_back(e1);
+        }
+        *a = ev[2 * used];
+        *b = ev[2 * used + 1];
+        ++used;
+        (void)s;
+    }
+    void release()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+        bytes.clear();
+        used = 0;
+    }
+};
+
+template <typename T>
+struct Multigrid {
+    int J = 0, lt = 0;
+    double L = 0.0;
+    int npre = 2, npost = 2;
+    std::vector<Level<T>> lv;  // index = level, n = 2^l + 1
+    double *partial = nullptr, *norms = nullptr;
+    double *host_norms = nullptr;  // pinned, 3 doubles
+    hipStream_t s = nullptr;
+    size_t bytes = 0;
+    std::vector<void *> owned;
+    SmootherProfile prof;
+
+    hipError_t alloc(void **p, size_t b)
+    {
+        hipError_t e = hipMalloc(p, b);
+        if (e == hipSuccess) {
+            owned.push_back(*p);
+            bytes += b;
+        }
+        return e;
+    }
+
+    // Allocate the coarse levels lt..J-1 for a finest grid of n points per side.
+    hipError_t init(int n, int npre_, int npost_, hipStream_t stream)
+    {
+        J = log2_exact(n - 1);
+        lt = J < kTailLevel ? J : kTailLevel;
+        npre = npre_;
+        npost = npost_;
+        s = stream;
+        lv.assign(J + 1, Level<T>());
+        for (int l = 1; l <= J; ++l) lv[l].n = (1 << l) + 1;
+        for (int l = lt; l < J; ++l) {
+            const size_t N = (size_t)lv[l].n * lv[l].n * lv[l].n;
+            hipError_t e;
+            if ((e = alloc((void **)&lv[l].u[0], N * sizeof(T))) != hipSuccess) return e;
+            if ((e = alloc((void **)&lv[l].u[1], N * sizeof(T))) != hipSuccess) return e;
+            if ((e = alloc((void **)&lv[l].f, N * sizeof(T))) != hipSuccess) return e;
+        }
+        hipError_t e;
+        if ((e = alloc((void **)&partial, 3 * kNormBlocks * sizeof(double))) != hipSuccess) return e;
+        if ((e = alloc((void **)&norms, 3 * sizeof(double))) != hipSuccess) return e;
+        if ((e = hipHostMalloc((void **)&host_norms, 3 * sizeof(double), hipHostMallocDefault)) != hipSuccess) return e;
+        return hipSuccess;
+    }
+
+    void release()
+    {
+        prof.release();
+        for (void *p : owned) (void)hipFree(p);
+        owned.clear();
+        if (host_norms) (void)hipHostFree(host_norms);
+        host_norms = nullptr;
+        bytes = 0;
+    }
+
+    // Bind the finest level: u0 holds the iterate (and the result), u1 is the
+    // ping-pong partner; both must already hold the boundary values.
+    void bind(double box_side, T *u0, T *u1, T *f)
+    {
+        L = box_side;
+        for (int l = 1; l <= J; ++l) lv[l].h = L / (double)(lv[l].n - 1);
+        lv[J].u[0] = u0;
+        lv[J].u[1] = u1;
+        lv[J].f = f;
+        for (int l = 1; l <= J; ++l) lv[l].cur = 0;
+    }
+
+    void smooth(int l, int ns)
+    {
+        Level<T> &v = lv[l];
+        for (int i = 0; i < ns; ++i) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (prof.on) {
+                prof.record_pair(s, &e0, &e1);
+                prof.bytes.push_back(3.0 * sizeof(T) * (double)v.n * v.n * v.n);
+                (void)hipEventRecord(e0, s);
+            }
+            launch_rbgs<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], s);
+            if (prof.on) (void)hipEventRecord(e1, s);
+            v.cur ^= 1;
+        }
+    }
+
+    // One V-cycle with top level l (l > lt), zero-boundary corrections below.
+    void vcycle(int l)
+    {
+        Level<T> &v = lv[l];
+        smooth(l, npre);
+        Level<T> &c = lv[l - 1];
+        launch_residual_restrict<T>(v.n, v.h, v.f, v.u[v.cur], c.f, c.u[c.cur], c.u[1 - c.cur], s);
+        if (l - 1 == lt) launch_coarse_tail<T>(lt, L, c.f, c.u[c.cur], npre, npost, 1, 0, 1, s);
+        else vcycle(l - 1);
+        launch_prolong_add<T>(c.n, c.u[c.cur], v.u[v.cur], s);
+        smooth(l, npost);
+    }
+
+    // The finest-level cycle used after the FMG schedule.
+    void finest_cycle(int nrep = 1)
+    {
+        if (J <= lt) {
+            launch_coarse_tail<T>(J, L, lv[J].f, lv[J].u[lv[J].cur], npre, npost, 1, 0, nrep, s);
+            return;
+        }
+        for (int r = 0; r < nrep; ++r) vcycle(J);
+    }
+
+    // FMG with ncycle V-cycles per level.  The finest u's boundary holds the
+    // Dirichlet values.
+    void fmg(int ncycle)
+    {
+        Level<T> &F = lv[J];
+        if (J <= lt) {
+            launch_coarse_tail<T>(J, L, F.f, F.u[F.cur], npre, npost, ncycle, 1, 1, s);
+            return;
+        }
+        for (int l = J - 1; l >= lt; --l) launch_restrict<T>(lv[l + 1].n, lv[l + 1].f, lv[l].f, s);
+        for (int l = lt; l < J; ++l) launch_inject_boundary<T>(F.n, F.u[F.cur], lv[l].n, lv[l].u[0], lv[l].u[1], s);
+        Level<T> &t = lv[lt];
+        launch_coarse_tail<T>(lt, L, t.f, t.u[t.cur], npre, npost, ncycle, 1, 1, s);
+        for (int l = lt + 1; l <= J; ++l) {
+            Level<T> &c = lv[l - 1];
+            launch_interp<T>(c.n, c.u[c.cur], lv[l].u[lv[l].cur], s);
+            for (int k = 0; k < ncycle; ++k) vcycle(l);
+        }
+    }
+
+    // Enqueue the residual norms of the finest level into host_norms (needs a
+    // stream synchronisation before reading).
+    void enqueue_norms()
+    {
+        Level<T> &F = lv[J];
+        launch_resid_norms<T>(F.n, F.h, F.f, F.u[F.cur], partial, norms, s);
+        (void)hipMemcpyAsync(host_norms, norms, 3 * sizeof(double), hipMemcpyDeviceToHost, s);
+    }
+
+    hipError_t relres(double &out)
+    {
+        enqueue_norms();
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        // ||f - A u|| / ||f||; a source-free box is measured against the
+        // boundary-value contribution instead, and if that is 0 the residual is absolute.
+        const double rn = std::sqrt(host_norms[0]), fn = std::sqrt(host_norms[1]), bn = std::sqrt(host_norms[2]);
+        const double den = fn > 0.0 ? fn : bn;
+        out = den > 0.0 ? rn / den : rn;
+        return hipSuccess;
+    }
+
+    // Leave the result in u[0] of the finest level.
+    void finish()
+    {
+        Level<T> &F = lv[J];
+        if (F.cur == 1) {
+            (void)hipMemcpyAsync(F.u[0], F.u[1], (size_t)F.n * F.n * F.n * sizeof(T), hipMemcpyDeviceToDevice, s);
+            F.cur = 0;
+        }
+    }
+};
+
+}  // namespace qm

@@ -1,0 +1,339 @@
+"""Thin ctypes binding of libqumond.so (include/qumond.h, include/qumond_kernels.h).
+
+Argument marshalling only: torch tensors supply device memory and the HIP
+stream (``torch.cuda.current_stream()``); every step of the solve runs in the
+library's gfx950 kernels.  ``torch`` is imported before the library is loaded
+so both use the one HIP runtime in the process.  There is no fallback: if the
+library is missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import torch  # noqa: F401  (must precede loading libqumond.so: shared HIP runtime)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqumond.so")
+MAX_BOX = 16
+
+QUMOND_OK, QUMOND_ERR_INVALID, QUMOND_ERR_STATE, QUMOND_ERR_OOM, QUMOND_ERR_HIP, QUMOND_ERR_NOT_CONVERGED, \
+    QUMOND_ERR_RANGE = range(7)
+QUMOND_FP64, QUMOND_MIXED = 0, 1
+QUMOND_BC_ZERO, QUMOND_BC_MONOPOLE = 0, 1
+FIELD_RHO_FIXED, FIELD_RHS, FIELD_PHI_N, FIELD_SOURCE, FIELD_PHI = range(5)
+GUESS_NONE, GUESS_F64, GUESS_F32, GUESS_BF16 = range(4)
+
+
+class qumond_config(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("nbox", ctypes.c_int32), ("box_side", ctypes.c_double * MAX_BOX),
+        ("G", ctypes.c_double), ("a0", ctypes.c_double), ("npre", ctypes.c_int32), ("npost", ctypes.c_int32),
+        ("ncycle_fmg", ctypes.c_int32), ("max_vcycles", ctypes.c_int32), ("tol_rel", ctypes.c_double),
+        ("precision", ctypes.c_int32), ("outer_bc", ctypes.c_int32), ("gather_frac", ctypes.c_double),
+        ("fixed_shift", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
+    ]
+
+
+class qumond_solve_info(ctypes.Structure):
+    _fields_ = [
+        ("nbox", ctypes.c_int32), ("vcycles", ctypes.c_int32 * MAX_BOX), ("converged", ctypes.c_int32 * MAX_BOX),
+        ("refine_iters", ctypes.c_int32 * MAX_BOX), ("relres0", ctypes.c_double * MAX_BOX),
+        ("relres", ctypes.c_double * MAX_BOX), ("used_fallback", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        nb = self.nbox
+        return {"vcycles": list(self.vcycles[:nb]), "converged": list(self.converged[:nb]),
+                "refine_iters": list(self.refine_iters[:nb]), "relres0": list(self.relres0[:nb]),
+                "relres": list(self.relres[:nb]), "used_fallback": int(self.used_fallback)}
+
+
+class qumond_kernel_stats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double)]
+
+
+_P, _I32, _I64, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_SIGNATURES = {
+    "qumond_default_config": (None, [ctypes.POINTER(qumond_config)]),
+    "qumond_validate_config": (_I32, [ctypes.POINTER(qumond_config)]),
+    "qumond_create": (_I32, [ctypes.POINTER(qumond_config), _P, ctypes.POINTER(_P)]),
+    "qumond_destroy": (_I32, [_P]),
+    "qumond_deposit": (_I32, [_P, _P, _P, _P, _P, _I64, _D, ctypes.POINTER(_I64)]),
+    "qumond_solve_newton": (_I32, [_P, ctypes.POINTER(qumond_solve_info)]),
+    "qumond_mond_source": (_I32, [_P]),
+    "qumond_solve_mond": (_I32, [_P, _P, _I32, ctypes.POINTER(qumond_solve_info)]),
+    "qumond_gather_forces": (_I32, [_P, _P, _P, _P, _I64, _I32, _P, _P, _P, _P]),
+    "qumond_rotation_curve": (_I32, [_P, _P, _I32, _I32, _I32, _P]),
+    "qumond_get_field": (_I32, [_P, _I32, _I32, _P]),
+    "qumond_set_field": (_I32, [_P, _I32, _I32, _P]),
+    "qumond_device_bytes": (_I64, [_P]),
+    "qumond_profile_enable": (_I32, [_P, _I32]),
+    "qumond_profile_read": (_I32, [_P, ctypes.POINTER(qumond_kernel_stats)]),
+    "qumond_status_string": (ctypes.c_char_p, [_I32]),
+    "qumond_last_error": (ctypes.c_char_p, []),
+    "qumond_k_rbgs_sweep": (_I32, [_I32, _D, _P, _P, _P, _P]),
+    "qumond_k_residual_restrict": (_I32, [_I32, _D, _P, _P, _P, _P, _P, _P]),
+    "qumond_k_restrict": (_I32, [_I32, _P, _P, _P]),
+    "qumond_k_prolong_add": (_I32, [_I32, _P, _P, _P]),
+    "qumond_k_interp": (_I32, [_I32, _P, _P, _P]),
+    "qumond_k_mond_source": (_I32, [_I32, _D, _D, _P, _P, _P]),
+    "qumond_k_bc_from_coarse": (_I32, [_I32, _P, _P, _P]),
+    "qumond_k_resid_norms": (_I32, [_I32, _D, _P, _P, _P, _P]),
+    "qumond_k_fmg": (_I32, [_I32, _D, _P, _P, _I32, _I32, _I32, _I32, _D, ctypes.POINTER(_D),
+                            ctypes.POINTER(_I32), _P]),
+    "qumond_k_vcycles": (_I32, [_I32, _D, _P, _P, _I32, _I32, _I32, ctypes.POINTER(_D), _P]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libqumond.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1201_3185_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> List[str]:
+    return list(_SIGNATURES)
+
+
+class QumondError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib().qumond_last_error().decode()
+        super().__init__(f"{where}: {lib().qumond_status_string(status).decode()} ({msg})")
+
+
+def check(status: int, where: str, allow=()) -> int:
+    if status != QUMOND_OK and status not in allow:
+        raise QumondError(status, where)
+    return status
+
+
+@dataclass
+class Config:
+    n: int = 65
+    box_side: List[float] = field(default_factory=lambda: [100.0])
+    G: float = 4.300917270e-6
+    a0: float = 3600.0
+    npre: int = 2
+    npost: int = 2
+    ncycle_fmg: int = 6
+    max_vcycles: int = 50
+    tol_rel: float = 1e-10
+    precision: int = QUMOND_FP64
+    outer_bc: int = QUMOND_BC_MONOPOLE
+    gather_frac: float = 0.2
+    fixed_shift: int = 0
+    use_graphs: int = 0
+
+    def to_c(self) -> qumond_config:
+        c = qumond_config()
+        c.n, c.nbox = self.n, len(self.box_side)
+        for b, Lb in enumerate(self.box_side[:MAX_BOX]):
+            c.box_side[b] = Lb
+        c.G, c.a0, c.npre, c.npost = self.G, self.a0, self.npre, self.npost
+        c.ncycle_fmg, c.max_vcycles, c.tol_rel = self.ncycle_fmg, self.max_vcycles, self.tol_rel
+        c.precision, c.outer_bc, c.gather_frac = self.precision, self.outer_bc, self.gather_frac
+        c.fixed_shift, c.use_graphs = self.fixed_shift, self.use_graphs
+        return c
+
+
+def validate_config(cfg: Config) -> int:
+    c = cfg.to_c()
+    return lib().qumond_validate_config(ctypes.byref(c))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _f64(t: torch.Tensor, name: str) -> torch.Tensor:
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 device tensor")
+    return t
+
+
+def current_stream_handle() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """One solver context: the nested-box grids on the current device, bound to a stream."""
+
+    def __init__(self, cfg: Config, stream: Optional[torch.cuda.Stream] = None):
+        self.cfg = cfg
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._c = cfg.to_c()
+        h = ctypes.c_void_p()
+        check(lib().qumond_create(ctypes.byref(self._c), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+              "qumond_create")
+        self._h = h
+        self.n = cfg.n
+        self.nbox = len(cfg.box_side)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().qumond_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def device_bytes(self) -> int:
+        return int(lib().qumond_device_bytes(self._h))
+
+    def deposit(self, x, y, z, m, total_mass: Optional[float] = None, count_outside: bool = True):
+        np_ = x.numel()
+        for t, nm in ((x, "x"), (y, "y"), (z, "z"), (m, "m")):
+            _f64(t, nm)
+            if t.numel() != np_:
+                raise ValueError("particle arrays differ in length")
+        if total_mass is None:
+            total_mass = float(m.sum().item())
+        out = ctypes.c_int64(0)
+        check(lib().qumond_deposit(self._h, _ptr(x), _ptr(y), _ptr(z), _ptr(m), np_, float(total_mass),
+                                   ctypes.byref(out) if count_outside else None), "qumond_deposit")
+        return int(out.value) if count_outside else None
+
+    def solve_newton(self, allow_not_converged: bool = False) -> dict:
+        info = qumond_solve_info()
+        check(lib().qumond_solve_newton(self._h, ctypes.byref(info)), "qumond_solve_newton",
+              allow=(QUMOND_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+        return info.as_dict()
+
+    def mond_source(self):
+        check(lib().qumond_mond_source(self._h), "qumond_mond_source")
+
+    def solve_mond(self, guess: Optional[torch.Tensor] = None, allow_not_converged: bool = False) -> dict:
+        info = qumond_solve_info()
+        kind = GUESS_NONE
+        if guess is not None:
+            kind = {torch.float64: GUESS_F64, torch.float32: GUESS_F32, torch.bfloat16: GUESS_BF16}[guess.dtype]
+            if guess.numel() != self.nbox * self.n ** 3:
+                raise ValueError("guess must hold nbox * n^3 values")
+        check(lib().qumond_solve_mond(self._h, _ptr(guess), kind, ctypes.byref(info)), "qumond_solve_mond",
+              allow=(QUMOND_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+        return info.as_dict()
+
+    def gather_forces(self, x, y, z, which: int = 1, with_box: bool = True):
+        np_ = x.numel()
+        for t, nm in ((x, "x"), (y, "y"), (z, "z")):
+            _f64(t, nm)
+        ax = torch.empty_like(x)
+        ay = torch.empty_like(x)
+        az = torch.empty_like(x)
+        used = torch.empty(np_, dtype=torch.uint8, device=x.device) if with_box else None
+        check(lib().qumond_gather_forces(self._h, _ptr(x), _ptr(y), _ptr(z), np_, int(which), _ptr(ax), _ptr(ay),
+                                         _ptr(az), _ptr(used)), "qumond_gather_forces")
+        return ax, ay, az, used
+
+    def rotation_curve(self, R: torch.Tensor, naz: int = 16, which: int = 1) -> torch.Tensor:
+        _f64(R, "R")
+        vc2 = torch.empty_like(R)
+        check(lib().qumond_rotation_curve(self._h, _ptr(R), R.numel(), int(naz), int(which), _ptr(vc2)),
+              "qumond_rotation_curve")
+        return vc2
+
+    def get_field(self, box: int, fld: int) -> torch.Tensor:
+        dt = torch.int64 if fld == FIELD_RHO_FIXED else torch.float64
+        out = torch.empty((self.n,) * 3, dtype=dt, device="cuda")
+        check(lib().qumond_get_field(self._h, int(box), int(fld), _ptr(out)), "qumond_get_field")
+        return out
+
+    def profile_enable(self, on: bool = True):
+        check(lib().qumond_profile_enable(self._h, int(bool(on))), "qumond_profile_enable")
+
+    def profile_read(self) -> dict:
+        st = qumond_kernel_stats()
+        check(lib().qumond_profile_read(self._h, ctypes.byref(st)), "qumond_profile_read")
+        return {"launches": int(st.launches), "total_ms": float(st.total_ms), "alg_bytes": float(st.alg_bytes)}
+
+    def set_field(self, box: int, fld: int, src: torch.Tensor):
+        _f64(src, "src")
+        if src.numel() != self.n ** 3:
+            raise ValueError("field must hold n^3 values")
+        check(lib().qumond_set_field(self._h, int(box), int(fld), _ptr(src)), "qumond_set_field")
+
+
+# ----------------------------------------------------- single-grid entries
+
+def _s(stream=None):
+    return ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+
+
+def k_rbgs_sweep(f, u_in, u_out, h):
+    n = u_in.shape[0]
+    check(lib().qumond_k_rbgs_sweep(n, float(h), _ptr(f), _ptr(u_in), _ptr(u_out), _s()), "qumond_k_rbgs_sweep")
+
+
+def k_residual_restrict(f, u, h, fc, uc0, uc1=None):
+    check(lib().qumond_k_residual_restrict(u.shape[0], float(h), _ptr(f), _ptr(u), _ptr(fc), _ptr(uc0), _ptr(uc1),
+                                           _s()), "qumond_k_residual_restrict")
+
+
+def k_restrict(src, dst):
+    check(lib().qumond_k_restrict(src.shape[0], _ptr(src), _ptr(dst), _s()), "qumond_k_restrict")
+
+
+def k_prolong_add(uc, uf):
+    check(lib().qumond_k_prolong_add(uc.shape[0], _ptr(uc), _ptr(uf), _s()), "qumond_k_prolong_add")
+
+
+def k_interp(uc, uf):
+    check(lib().qumond_k_interp(uc.shape[0], _ptr(uc), _ptr(uf), _s()), "qumond_k_interp")
+
+
+def k_mond_source(phin, h, a0, S):
+    check(lib().qumond_k_mond_source(phin.shape[0], float(h), float(a0), _ptr(phin), _ptr(S), _s()),
+          "qumond_k_mond_source")
+
+
+def k_bc_from_coarse(uc, uf):
+    check(lib().qumond_k_bc_from_coarse(uc.shape[0], _ptr(uc), _ptr(uf), _s()), "qumond_k_bc_from_coarse")
+
+
+def k_resid_norms(f, u, h, out2):
+    check(lib().qumond_k_resid_norms(u.shape[0], float(h), _ptr(f), _ptr(u), _ptr(out2), _s()),
+          "qumond_k_resid_norms")
+
+
+def k_fmg(f, u, L, npre=2, npost=2, ncycle=6, max_extra=50, tol=1e-10):
+    rr = ctypes.c_double(0)
+    ex = ctypes.c_int32(0)
+    check(lib().qumond_k_fmg(u.shape[0], float(L), _ptr(f), _ptr(u), npre, npost, ncycle, max_extra, float(tol),
+                             ctypes.byref(rr), ctypes.byref(ex), _s()), "qumond_k_fmg")
+    return float(rr.value), int(ex.value)
+
+
+def k_vcycles(f, u, L, ncyc, npre=2, npost=2):
+    rr = ctypes.c_double(0)
+    check(lib().qumond_k_vcycles(u.shape[0], float(L), _ptr(f), _ptr(u), npre, npost, ncyc, ctypes.byref(rr), _s()),
+          "qumond_k_vcycles")
+    return float(rr.value)

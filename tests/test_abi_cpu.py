@@ -1,0 +1,85 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every entry
+point the headers declare, and rejects bad configurations and arguments
+before touching HIP (CPU only)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1201_3185_amd", "libqumond.so")
+
+
+def _declared():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names += re.findall(r"\b(qumond_[a-z0-9_]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def Q():
+    if not os.path.exists(LIB):
+        from paper_1201_3185_amd import build
+        build.build()
+    from paper_1201_3185_amd import qumond
+    return qumond
+
+
+def test_every_declared_symbol_is_exported(Q):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\b(qumond_[a-z0-9_]+)\b", out))
+    declared = _declared()
+    assert len(declared) >= 20
+    missing = [d for d in declared if d not in exported]
+    assert not missing, missing
+    assert set(declared) <= set(Q.exported_symbols())
+    Q.lib()  # loads, binds every signature
+
+
+def test_default_config_is_the_papers(Q):
+    c = Q.qumond_config()
+    Q.lib().qumond_default_config(ctypes.byref(c))
+    assert (c.n, c.nbox, c.npre, c.npost, c.ncycle_fmg) == (65, 1, 2, 2, 6)
+    assert c.a0 == 3600.0 and c.gather_frac == 0.2
+    assert Q.lib().qumond_validate_config(ctypes.byref(c)) == Q.QUMOND_OK
+
+
+@pytest.mark.parametrize("change", [
+    dict(n=64), dict(n=3), dict(n=2049), dict(box_side=[]), dict(box_side=[100.0, 60.0]),
+    dict(box_side=[-1.0]), dict(G=0.0), dict(a0=-1.0), dict(npre=0, npost=0), dict(npre=9),
+    dict(ncycle_fmg=0), dict(max_vcycles=-1), dict(tol_rel=-1e-3), dict(precision=7), dict(outer_bc=3),
+    dict(gather_frac=0.5), dict(gather_frac=0.0), dict(fixed_shift=-2),
+])
+def test_invalid_configs_rejected_without_gpu(Q, change):
+    cfg = Q.Config(**change)
+    assert Q.validate_config(cfg) == Q.QUMOND_ERR_INVALID
+    c = cfg.to_c()
+    h = ctypes.c_void_p()
+    assert Q.lib().qumond_create(ctypes.byref(c), None, ctypes.byref(h)) == Q.QUMOND_ERR_INVALID
+    assert not h.value
+    assert len(Q.lib().qumond_last_error()) > 0
+
+
+def test_valid_nested_configs(Q):
+    assert Q.validate_config(Q.Config(n=129, box_side=[400.0, 200.0, 100.0, 50.0])) == Q.QUMOND_OK
+    assert Q.validate_config(Q.Config(n=5, box_side=[1.0])) == Q.QUMOND_OK
+    assert Q.validate_config(Q.Config(n=513, box_side=[120.0], precision=Q.QUMOND_MIXED)) == Q.QUMOND_OK
+
+
+def test_null_handles_and_arguments(Q):
+    L = Q.lib()
+    assert L.qumond_destroy(None) == Q.QUMOND_ERR_INVALID
+    assert L.qumond_deposit(None, None, None, None, None, 0, 1.0, None) == Q.QUMOND_ERR_INVALID
+    assert L.qumond_solve_newton(None, None) == Q.QUMOND_ERR_INVALID
+    assert L.qumond_mond_source(None) == Q.QUMOND_ERR_INVALID
+    assert L.qumond_solve_mond(None, None, 0, None) == Q.QUMOND_ERR_INVALID
+    assert L.qumond_gather_forces(None, None, None, None, 0, 0, None, None, None, None) == Q.QUMOND_ERR_INVALID
+    assert L.qumond_k_rbgs_sweep(64, 1.0, None, None, None, None) == Q.QUMOND_ERR_INVALID
+    assert L.qumond_k_fmg(33, 1.0, None, None, 2, 2, 6, 0, 0.0, None, None, None) == Q.QUMOND_ERR_INVALID
+    assert L.qumond_status_string(Q.QUMOND_ERR_STATE) == b"call out of order"

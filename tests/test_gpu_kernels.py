@@ -1,0 +1,225 @@
+"""Kernel-by-kernel parity of the gfx950 library against the FP64 oracle.
+
+Each single-grid entry point of include/qumond_kernels.h is fed the same seeded
+input as the oracle routine for the same step of Sec. 2, at sizes that span
+one and several tiles with ragged tails (interior 3..255 points per side).
+Tolerances: transfers with dyadic weights agree to rounding of the sums
+(1e-15 of the field's scale); one Gauss-Seidel sweep, restriction and norms
+to 1e-14..1e-13 (only the order of a handful of FP64 operations differs);
+the face-flux source to 1e-12 of max|S| (a difference of fluxes).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1201_3185_amd import qumond as Q
+from tests.conftest import node_coords
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def rand_state(n, seed):
+    rng = np.random.default_rng(seed)
+    f = rng.standard_normal((n, n, n))
+    u = rng.standard_normal((n, n, n))
+    return f, u
+
+
+SIZES = [5, 9, 17, 33, 65, 129, 257]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_rbgs_sweep(n):
+    L = 10.0
+    h = L / (n - 1)
+    f, u = rand_state(n, n)
+    ref = u.copy()
+    O.rbgs_sweep(f, ref, h)
+    uin = dev(u)
+    uout = dev(u)          # boundary preset
+    Q.k_rbgs_sweep(dev(f), uin, uout, h)
+    got = host(uout)
+    assert rel(got, ref) < 1e-14
+    assert np.array_equal(got[0], u[0]) and np.array_equal(got[:, :, -1], u[:, :, -1])
+
+
+@pytest.mark.parametrize("n", [33, 129])
+def test_rbgs_many_sweeps(n):
+    L = 3.0
+    h = L / (n - 1)
+    f, u = rand_state(n, 100 + n)
+    ref = u.copy()
+    a, b = dev(u), dev(u)
+    fd = dev(f)
+    for s in range(6):
+        O.rbgs_sweep(f, ref, h)
+        Q.k_rbgs_sweep(fd, a, b, h)
+        a, b = b, a
+    assert rel(host(a), ref) < 1e-13
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_residual_restrict(n):
+    L = 7.0
+    h = L / (n - 1)
+    f, u = rand_state(n, 200 + n)
+    nc = (n + 1) // 2
+    ref = O.restrict_fw(O.residual(f, u, h))
+    fc = dev(np.full((nc,) * 3, 9.0))
+    uc0 = dev(np.full((nc,) * 3, 9.0))
+    uc1 = dev(np.full((nc,) * 3, 9.0))
+    Q.k_residual_restrict(dev(f), dev(u), h, fc, uc0, uc1)
+    assert rel(host(fc), ref) < 1e-13
+    assert np.all(host(uc0) == 0)
+    u1 = host(uc1)
+    assert np.all(u1[0] == 0) and np.all(u1[-1] == 0) and np.all(u1[:, 0] == 0) and np.all(u1[:, :, -1] == 0)
+    if nc > 2:
+        assert np.all(u1[1:-1, 1:-1, 1:-1] == 9.0)
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_restrict(n):
+    src = rand_state(n, 300 + n)[0]
+    nc = (n + 1) // 2
+    dst = dev(np.full((nc,) * 3, 5.0))
+    Q.k_restrict(dev(src), dst)
+    assert rel(host(dst), O.restrict_fw(src)) < 1e-14
+
+
+@pytest.mark.parametrize("nc", [3, 5, 9, 17, 33, 65, 129])
+def test_prolong_add_and_interp(nc):
+    nf = 2 * nc - 1
+    rng = np.random.default_rng(nc)
+    uc = rng.standard_normal((nc,) * 3)
+    uf = rng.standard_normal((nf,) * 3)
+    ref = O.prolong_add(uc, uf.copy())
+    d = dev(uf)
+    Q.k_prolong_add(dev(uc), d)
+    assert rel(host(d), ref) < 1e-15
+    ref = O.interp(uc, uf.copy())
+    d = dev(uf)
+    Q.k_interp(dev(uc), d)
+    got = host(d)
+    assert rel(got, ref) < 1e-15
+    assert np.array_equal(got[0], uf[0])
+
+
+@pytest.mark.parametrize("n", [5, 17, 33, 65, 129])
+def test_mond_source(n):
+    L = 20.0
+    h = L / (n - 1)
+    X, Y, Z = node_coords(n, L)
+    r = np.sqrt((X - 0.3) ** 2 + (Y + 0.1) ** 2 + (Z - 0.05) ** 2)
+    phin = -O.G_KPC * 3e10 / np.sqrt(r * r + 4.0)
+    ref = O.mond_source(phin, L)
+    S = dev(np.full((n,) * 3, 7.0))
+    Q.k_mond_source(dev(phin), h, O.A0_KPC, S)
+    got = host(S)
+    assert rel(got, ref) < 1e-12
+    assert np.all(got[0] == 0) and np.all(got[:, :, -1] == 0)
+    # rough field (random) and the a0 = 0 special case
+    rough = np.random.default_rng(n).standard_normal((n, n, n)) * 1e4
+    rough[n // 2, :, :] = rough[n // 2, 0, 0]   # a plane with zero in-plane gradient components
+    for a0 in (O.A0_KPC, 0.0):
+        ref = O.mond_source(rough, L, a0=a0)
+        Q.k_mond_source(dev(rough), h, a0, S)
+        assert rel(host(S), ref) < 1e-12
+
+
+def test_mond_source_zero_field_gives_zero_flux():
+    n, L = 17, 4.0
+    phin = np.full((n, n, n), -123.0)
+    S = dev(np.full((n,) * 3, 7.0))
+    Q.k_mond_source(dev(phin), L / (n - 1), O.A0_KPC, S)
+    assert np.all(host(S) == 0.0)
+
+
+@pytest.mark.parametrize("n", [5, 9, 33, 129])
+def test_bc_from_coarse(n):
+    Lc = 40.0
+    Xc, Yc, Zc = node_coords(n, Lc)
+    uc = np.sin(Xc / 7) * np.cos(Yc / 5) + Zc ** 2 / 100
+    ref = O.bc_from_coarse(uc, Lc, np.zeros((n,) * 3), Lc / 2)
+    d = dev(np.zeros((n,) * 3))
+    Q.k_bc_from_coarse(dev(uc), d)
+    assert rel(host(d), ref) < 1e-15
+
+
+@pytest.mark.parametrize("n", [5, 33, 129])
+def test_resid_norms(n):
+    L = 2.0
+    h = L / (n - 1)
+    f, u = rand_state(n, 400 + n)
+    r = O.residual(f, u, h)
+    out = torch.zeros(3, dtype=torch.float64, device="cuda")
+    Q.k_resid_norms(dev(f), dev(u), h, out)
+    got = host(out)
+    assert got[0] == pytest.approx((r[1:-1, 1:-1, 1:-1] ** 2).sum(), rel=1e-12)
+    assert got[1] == pytest.approx((f[1:-1, 1:-1, 1:-1] ** 2).sum(), rel=1e-12)
+    assert got[2] == pytest.approx(O.lib().orc_boundary_coupling_sumsq(n, h, O._p(np.ascontiguousarray(u))), rel=1e-12)
+    # bitwise reproducible
+    out2 = torch.zeros(3, dtype=torch.float64, device="cuda")
+    Q.k_resid_norms(dev(f), dev(u), h, out2)
+    assert np.array_equal(host(out2), got)
+
+
+def _bc_problem(n, L, seed):
+    rng = np.random.default_rng(seed)
+    f = rng.standard_normal((n, n, n))
+    u = np.zeros((n, n, n))
+    b = rng.standard_normal((n, n, n))
+    mask = np.ones((n, n, n), bool)
+    mask[1:-1, 1:-1, 1:-1] = False
+    u[mask] = b[mask]
+    return f, u
+
+
+@pytest.mark.parametrize("n", [5, 9, 17, 33, 65, 129])
+def test_fmg_fixed_schedule(n):
+    L = 10.0
+    f, u = _bc_problem(n, L, 500 + n)
+    ref = u.copy()
+    O.fmg(f, ref, L, ncycle=6, max_extra=0, tol=0.0)
+    d = dev(u)
+    rr, ex = Q.k_fmg(dev(f), d, L, ncycle=6, max_extra=0, tol=0.0)
+    assert ex == 0
+    assert rel(host(d), ref) < 1e-12
+
+
+@pytest.mark.parametrize("n", [17, 65])
+def test_fmg_tolerance_stop_same_cycles(n):
+    L = 1.0
+    f, u = _bc_problem(n, L, 600 + n)
+    ref = u.copy()
+    st, rr_o, ex_o = O.fmg(f, ref, L, ncycle=1, max_extra=30, tol=1e-9)
+    d = dev(u)
+    rr_g, ex_g = Q.k_fmg(dev(f), d, L, ncycle=1, max_extra=30, tol=1e-9)
+    assert ex_g == ex_o and rr_g <= 1e-9
+    assert rr_g == pytest.approx(rr_o, rel=1e-3)
+    assert rel(host(d), ref) < 1e-12
+
+
+@pytest.mark.parametrize("n", [9, 33, 129])
+def test_vcycles(n):
+    L = 5.0
+    f, u = _bc_problem(n, L, 700 + n)
+    ref = u.copy()
+    rr_o = O.vcycles(f, ref, L, 3)
+    d = dev(u)
+    rr_g = Q.k_vcycles(dev(f), d, L, 3)
+    assert rr_g == pytest.approx(rr_o, rel=1e-8)
+    assert rel(host(d), ref) < 1e-12

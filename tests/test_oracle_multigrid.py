@@ -198,3 +198,21 @@ def test_fmg_error_tracks_discretisation_error():
     assert max(ratio1) < 4.0 and max(ratio2) < 0.3
     assert max(ratio1) / min(ratio1) < 1.5
     assert 3.5 < errs[17] / errs[33] < 4.5 and 3.5 < errs[33] / errs[65] < 4.5
+
+
+def test_source_free_box_solves_harmonic_field():
+    """f = 0 with Dirichlet values from a harmonic quadratic: the 7-point scheme is
+    exact on quadratics, so the converged solution is the field itself; the
+    stopping test is then relative to the boundary-value contribution, whose norm
+    equals that of the residual of the boundary-only field."""
+    n, L = 33, 4.0
+    h = L / (n - 1)
+    X, Y, Z = node_coords(n, L)
+    exact = X * X - Y * Y + 2 * X * Z - 3 * Y + 1.0
+    u = exact.copy(); u[1:-1, 1:-1, 1:-1] = 0.0
+    r0 = O.residual(np.zeros_like(u), u, h)
+    bsum = O.lib().orc_boundary_coupling_sumsq(n, h, O._p(np.ascontiguousarray(u)))
+    assert bsum == pytest.approx((interior(r0) ** 2).sum(), rel=1e-13)
+    st, rr, extra = O.fmg(np.zeros_like(u), u, L, tol=1e-12, max_extra=40)
+    assert st == 0 and rr <= 1e-12
+    assert np.abs(u - exact).max() < 1e-11 * np.abs(exact).max()
