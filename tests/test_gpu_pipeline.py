@@ -57,13 +57,18 @@ def run_oracle(cfg: Q.Config, p, total_mass=None):
     return O.run_pipeline(oc, p.x, p.y, p.z, p.m, tm), oc
 
 
-def compare(g, o, cfg, check_cycles=True):
+def compare(g, o, cfg, check_cycles=True, s_tol=1e-10):
     nb = len(cfg.box_side)
     for b in range(nb):
         assert np.array_equal(g["q"][b], o.q[b]), f"int64 density differs in box {b}"
         assert rel(g["f"][b], o.f[b]) <= 1e-15
         assert rel(g["phin"][b], o.phin[b]) <= 1e-10
-        assert rel(g["S"][b], o.S[b]) <= 1e-10
+        # The source kernel on the GPU's own Phi_N (cross-fed) agrees to rounding.
+        h = cfg.box_side[b] / (cfg.n - 1)
+        assert rel(g["S"][b], O.mond_source(g["phin"][b], cfg.box_side[b], cfg.a0)) <= 1e-12
+        # Directly: S is a second difference of Phi_N, so where |S| is tiny (no
+        # matter) the solve-tolerance differences of Phi_N are amplified ~1/h^2.
+        assert rel(g["S"][b], o.S[b]) <= s_tol
         assert rel(g["phi"][b], o.phi[b]) <= 1e-10
         if check_cycles:
             assert g["newton"]["vcycles"][b] == o.info_newton[b][2]
@@ -165,13 +170,13 @@ def test_no_particles_and_all_outside():
     empty = synth.Particles(np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0))
     g = run_gpu(cfg, empty, total_mass=1e9)
     o, oc = run_oracle(cfg, empty, total_mass=1e9)
-    compare(g, o, cfg, check_cycles=False)
+    compare(g, o, cfg, check_cycles=False, s_tol=1e-7)
     assert np.all(g["q"][0] == 0) and g["n_outside"] == 0
     far = synth.Particles(np.array([50.0, -60.0, 5.0]), np.array([0.0, 0.0, 5.0]), np.array([0.0, 0.0, 0.0]),
                           np.array([1e9, 1e9, 1e9]))
     g = run_gpu(cfg, far)
     o, oc = run_oracle(cfg, far)
-    compare(g, o, cfg, check_cycles=False)
+    compare(g, o, cfg, check_cycles=False, s_tol=1e-7)
     assert g["n_outside"] == 3 and np.all(g["q"][0] == 0)
     # forces fall back to the monopole outside the box
     ax, ay, az, used = g["ctx"].gather_forces(dev([100.0]), dev([0.0]), dev([0.0]), 0)
