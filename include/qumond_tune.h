@@ -1,0 +1,46 @@
+/*
+ * qumond_tune.h -- launch-shape autotuning of the gfx950 smoother.
+ *
+ * The red-black smoother (the multigrid's dominant kernel, Sec. 2 of Angus et
+ * al., arXiv:1201.3185) can be launched with several column-tile shapes and
+ * z-march depths.  The library keeps one shape per level size (n = 2^J + 1)
+ * and precision.  qumond_autotune times every candidate shape on synthetic
+ * grids of each size from 33 up to n_max with hipEvents on the given stream
+ * (median of `reps` launches after one warm-up), installs the fastest, and
+ * optionally writes the table as JSON; qumond_tune_load installs a table a
+ * previous run wrote.  Shapes change only speed, never results (every shape
+ * computes the same red-black sweep).  Tuning allocates its own scratch grids
+ * and synchronises the stream.
+ */
+#ifndef QUMOND_TUNE_H
+#define QUMOND_TUNE_H
+
+#include <stdint.h>
+#include "qumond.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* variant: 0 = 32x8, 1 = 64x4, 2 = 64x8, 3 = 128x4, 4 = 32x16 columns per
+ * workgroup; kchunk: z planes per workgroup (0 = all).  fp32 selects the
+ * table of the single-precision smoother. */
+qumond_status qumond_tune_set(int32_t n, int32_t fp32, int32_t variant, int32_t kchunk);
+qumond_status qumond_tune_get(int32_t n, int32_t fp32, int32_t *variant, int32_t *kchunk);
+
+/* One smoother sweep with an explicit shape (see qumond_k_rbgs_sweep). */
+qumond_status qumond_k_rbgs_sweep_shape(int32_t n, double h, const double *f, const double *u_in, double *u_out,
+                                        int32_t variant, int32_t kchunk, void *stream);
+
+/* Time all shapes for n = 33, 65, ..., n_max (and both precisions if
+ * both != 0), install the fastest; json_path (host string, optional) receives
+ * the table.  best_us (host, optional, 11 entries) gets the FP64 time per
+ * sweep indexed by log2(n-1). */
+qumond_status qumond_autotune(int32_t n_max, int32_t both, int32_t reps, const char *json_path, double *best_us,
+                              void *stream);
+qumond_status qumond_tune_load(const char *json_path);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QUMOND_TUNE_H */

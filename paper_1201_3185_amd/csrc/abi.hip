@@ -53,6 +53,7 @@ struct qumond_ctx {
     int stage = ST_CREATED;
     unsigned long long *d_count = nullptr;
     unsigned long long *h_count = nullptr;  // pinned
+    unsigned long long *dep_scratch = nullptr;
     std::vector<void *> owned;
     int64_t bytes = 0;
 
@@ -174,6 +175,7 @@ qumond_status qumond_create(const qumond_config *cfg, void *hip_stream, qumond_c
         }
     }
     if ((e = c->alloc((void **)&c->scratch, c->N * sizeof(double))) != hipSuccess ||
+        (e = c->alloc((void **)&c->dep_scratch, qm::deposit_scratch_bytes(cfg->nbox))) != hipSuccess ||
         (e = c->alloc((void **)&c->d_count, sizeof(unsigned long long))) != hipSuccess ||
         (e = hipHostMalloc((void **)&c->h_count, sizeof(unsigned long long), hipHostMallocDefault)) != hipSuccess ||
         (e = c->mg.init(c->n, cfg->npre, cfg->npost, c->s)) != hipSuccess) {
@@ -252,7 +254,13 @@ qumond_status qumond_deposit(qumond_ctx *ctx, const double *x, const double *y, 
     a.nbox = ctx->cfg.nbox;
     a.n = ctx->n;
     a.scale = std::ldexp(1.0, shift);
+    a.scratch = ctx->dep_scratch;
+    const int win[3] = {qm::kWinX, qm::kWinY, qm::kWinZ};
     for (int b = 0; b < a.nbox; ++b) {
+        for (int d = 0; d < 3; ++d) {
+            const int o = (ctx->n - 1) / 2 - win[d] / 2;
+            a.w0[b][d] = o < 0 ? 0 : o;
+        }
         const Box &B = ctx->box[b];
         a.box[b].L = B.L;
         a.box[b].xmin = -0.5 * B.L;

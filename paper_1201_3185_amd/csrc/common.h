@@ -23,11 +23,20 @@ struct BoxGeom {
     double h;       // L/(n-1)
 };
 
+// LDS window of the deposit: every workgroup accumulates the corners that fall
+// in a kWinX x kWinY x kWinZ block of nodes around each box's centre (where a
+// galaxy's mass concentrates) in LDS, and writes it to its own scratch slab.
+constexpr int kWinX = 32, kWinY = 32, kWinZ = 8, kWin = kWinX * kWinY * kWinZ;
+constexpr int kDepositThreads = 1024;
+constexpr int kDepositMaxBlocks = 256;
+
 struct DepositArgs {
     int nbox, n;
     BoxGeom box[kMaxBox];
     unsigned long long *q[kMaxBox];
-    double scale;   // 2^s
+    int w0[kMaxBox][3];              // window origin node per box and axis
+    unsigned long long *scratch;     // [blocks][nbox][kWin]
+    double scale;                    // 2^s
 };
 
 struct GatherArgs {
@@ -39,7 +48,17 @@ struct GatherArgs {
 };
 
 // ---- grid_kernels.hip (templated on the storage type: double or float)
+// Smoother launch shape: tile variant (0: 32x8, 1: 64x4, 2: 64x8, 3: 128x4,
+// 4: 32x16 columns) and the number of z planes one workgroup marches through.
+struct SmootherShape {
+    int variant;
+    int kchunk;
+};
+constexpr int kSmootherVariants = 5;
 template <typename T> void launch_rbgs(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s);
+template <typename T> void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, SmootherShape sh,
+                                            hipStream_t s);
+template <typename T> SmootherShape &rbgs_shape(int n);   // the table entry used for n
 template <typename T> void launch_residual_restrict(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1,
                                                    hipStream_t s);
 template <typename T> void launch_restrict(int nf, const T *src, T *dst, hipStream_t s);
@@ -66,6 +85,8 @@ void launch_bc_outer(int n, double L, int mode, double GM, double a0, double *u0
 void launch_bc_from_coarse(int n, const double *uc, double *u0, double *u1, hipStream_t s);
 
 // ---- particle_kernels.hip
+// a.q must be zeroed; a.scratch must hold deposit_scratch_bytes(a.nbox) bytes.
+size_t deposit_scratch_bytes(int nbox);
 void launch_deposit(const DepositArgs &a, const double *x, const double *y, const double *z, const double *m,
                     int64_t np, unsigned long long *inside_count, hipStream_t s);
 void launch_rhs_from_q(int n, double h, double four_pi_G, int shift, const long long *q, double *f, hipStream_t s);

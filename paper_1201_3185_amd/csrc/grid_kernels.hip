@@ -23,77 +23,130 @@ __global__ void __launch_bounds__(TX *TY)
 rbgs_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2, int kchunk)
 {
     constexpr int PX = TX + 4, PY = TY + 4, NS = 5, NT = TX * TY;
-    __shared__ T pl[NS][PX * PY];
+    constexpr int PL = PX * PY;                  // values of one LDS plane (tile + two-node ring)
+    constexpr int NL = (PL + NT - 1) / NT;       // plane values loaded per thread
+    constexpr int HALF = (TX + 2) / 2;           // red nodes per row of tile + one-node ring
+    static_assert(HALF * (TY + 2) <= NT, "one red node per thread");
+    __shared__ T pl[NS][PL];
+    const T sixth = T(1) / T(6);
     const int tid = threadIdx.x;
     const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
     const int kb = 1 + blockIdx.z * kchunk;
     if (kb > n - 2) return;
     const int ke = min(kb + kchunk - 1, n - 2);
+    const size_t nn = (size_t)n * n;
 
-    auto load = [&](int k) {
+    // plane offsets of this thread's share of a plane load
+    int goff[NL];
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+        const int t = tid + r * NT;
+        const int a = t % PX, b = t / PX;
+        const int i = i0 - 2 + a, j = j0 - 2 + b;
+        goff[r] = (t < PL && i >= 0 && i < n && j >= 0 && j < n) ? i + n * j : -1;
+    }
+    // this thread's red node (tile + ring): row b_r, column depends on the plane's parity
+    const int b_r = 1 + tid / HALF, j_r = j0 - 2 + b_r, q_r = tid % HALF;
+    const bool red_thread = tid < HALF * (TY + 2) && j_r >= 1 && j_r <= n - 2;
+    auto red_a = [&](int k) { return ((((i0 - 1) + j_r + k) & 1) ? 2 : 1) + 2 * q_r; };
+    // this thread's tile node (black pass and store)
+    const int a_b = 2 + tid % TX, b_b = 2 + tid / TX;
+    const int i_b = i0 - 2 + a_b, j_b = j0 - 2 + b_b;
+    const bool tile_thread = i_b <= n - 2 && j_b <= n - 2;
+
+    auto load_now = [&](int k) {
         T *P = pl[k % NS];
-        for (int t = tid; t < PX * PY; t += NT) {
-            const int a = t % PX, b = t / PX;
-            const int i = i0 - 2 + a, j = j0 - 2 + b;
-            T v = T(0);
-            if (i < n && j < n && i >= 0 && j >= 0) v = uin[id3(n, i, j, k)];
-            P[t] = v;
+        const T *src = uin + (size_t)k * nn;
+#pragma unroll
+        for (int r = 0; r < NL; ++r) {
+            const int t = tid + r * NT;
+            if (t < PL) P[t] = goff[r] >= 0 ? src[goff[r]] : T(0);
         }
     };
-    // red nodes of plane k on the tile plus a one-node ring
-    auto red = [&](int k) {
+    T v[NL];
+    auto prefetch = [&](int k) {
+        const T *src = uin + (size_t)k * nn;
+#pragma unroll
+        for (int r = 0; r < NL; ++r) v[r] = goff[r] >= 0 ? src[goff[r]] : T(0);
+    };
+    auto commit = [&](int k) {
+        T *P = pl[k % NS];
+#pragma unroll
+        for (int r = 0; r < NL; ++r) {
+            const int t = tid + r * NT;
+            if (t < PL) P[t] = v[r];
+        }
+    };
+    // f at this thread's red node of plane k (0 if it has none)
+    auto f_red = [&](int k) {
+        const int i = i0 - 2 + red_a(k);
+        return (red_thread && i >= 1 && i <= n - 2) ? f[(size_t)k * nn + i + (size_t)n * j_r] : T(0);
+    };
+    auto f_black = [&](int k) {
+        return (tile_thread && ((i_b + j_b + k) & 1)) ? f[(size_t)k * nn + i_b + (size_t)n * j_b] : T(0);
+    };
+    auto red = [&](int k, T fv) {
+        const int a = red_a(k), i = i0 - 2 + a;
+        if (!red_thread || i < 1 || i > n - 2) return;
         T *P = pl[k % NS];
         const T *Pm = pl[(k - 1) % NS];
         const T *Pp = pl[(k + 1) % NS];
-        constexpr int HALF = (TX + 2) / 2;
-        for (int t = tid; t < HALF * (TY + 2); t += NT) {
-            const int b = 1 + t / HALF;
-            const int j = j0 - 2 + b;
-            const int a = ((((i0 - 1) + j + k) & 1) ? 2 : 1) + 2 * (t % HALF);
-            const int i = i0 - 2 + a;
-            if (i < 1 || i > n - 2 || j < 1 || j > n - 2) continue;
-            const int c = b * PX + a;
-            const T s = P[c - 1] + P[c + 1] + P[c - PX] + P[c + PX] + Pm[c] + Pp[c];
-            P[c] = (s - h2 * f[id3(n, i, j, k)]) / T(6);
-        }
+        const int c = b_r * PX + a;
+        const T s = P[c - 1] + P[c + 1] + P[c - PX] + P[c + PX] + Pm[c] + Pp[c];
+        P[c] = (s - h2 * fv) * sixth;
     };
-    // black nodes of plane k on the tile; store the whole tile row of plane k
-    auto black_store = [&](int k) {
+    auto black_store = [&](int k, T fv) {
+        if (!tile_thread) return;
         const T *P = pl[k % NS];
-        const T *Pm = pl[(k - 1) % NS];
-        const T *Pp = pl[(k + 1) % NS];
-        for (int t = tid; t < TX * TY; t += NT) {
-            const int a = 2 + t % TX, b = 2 + t / TX;
-            const int i = i0 - 2 + a, j = j0 - 2 + b;
-            if (i > n - 2 || j > n - 2) continue;
-            const int c = b * PX + a;
-            T v;
-            if (((i + j + k) & 1) == 0) {
-                v = P[c];
-            } else {
-                const T s = P[c - 1] + P[c + 1] + P[c - PX] + P[c + PX] + Pm[c] + Pp[c];
-                v = (s - h2 * f[id3(n, i, j, k)]) / T(6);
-            }
-            uout[id3(n, i, j, k)] = v;
+        const int c = b_b * PX + a_b;
+        T val;
+        if (((i_b + j_b + k) & 1) == 0) {
+            val = P[c];
+        } else {
+            const T *Pm = pl[(k - 1) % NS];
+            const T *Pp = pl[(k + 1) % NS];
+            const T s = P[c - 1] + P[c + 1] + P[c - PX] + P[c + PX] + Pm[c] + Pp[c];
+            val = (s - h2 * fv) * sixth;
         }
+        uout[(size_t)k * nn + i_b + (size_t)n * j_b] = val;
     };
 
-    if (kb >= 2) load(kb - 2);
-    load(kb - 1);
-    load(kb);
-    load(kb + 1);
-    if (kb + 2 <= n - 1) load(kb + 2);
+    // warm-up: planes kb-2..kb+2 and red of kb-1..kb+1
+    if (kb >= 2) load_now(kb - 2);
+    load_now(kb - 1);
+    load_now(kb);
+    load_now(kb + 1);
+    if (kb + 2 <= n - 1) load_now(kb + 2);
+    const T fr0 = kb - 1 >= 1 ? f_red(kb - 1) : T(0);
+    const T fr1 = f_red(kb);
+    const T fr2 = kb + 1 <= n - 2 ? f_red(kb + 1) : T(0);
     __syncthreads();
-    if (kb - 1 >= 1) red(kb - 1);
-    red(kb);
-    if (kb + 1 <= n - 2) red(kb + 1);
+    if (kb - 1 >= 1) red(kb - 1, fr0);
+    red(kb, fr1);
+    if (kb + 1 <= n - 2) red(kb + 1, fr2);
     __syncthreads();
+
+    auto need_red = [&](int k) { return (k + 2 <= n - 2) && (k + 2 <= ke + 1); };  // red(k+2) in iteration k
+    T fr_next = T(0), fb_next = f_black(kb);
+    if (need_red(kb)) {
+        prefetch(kb + 3);
+        fr_next = f_red(kb + 2);
+    }
     for (int k = kb; k <= ke; ++k) {
-        const bool more = (k + 2 <= n - 2) && (k + 2 <= ke + 1);
-        if (more) load(k + 3);
-        black_store(k);
+        const bool more = need_red(k);
+        if (more) commit(k + 3);
+        const T fb = fb_next, fr = fr_next;
+        // prefetch for iteration k+1 while this one computes
+        if (k + 1 <= ke) {
+            fb_next = f_black(k + 1);
+            if (need_red(k + 1)) {
+                prefetch(k + 4);
+                fr_next = f_red(k + 3);
+            }
+        }
+        black_store(k, fb);
         __syncthreads();
-        if (more) red(k + 2);
+        if (more) red(k + 2, fr);
         __syncthreads();
     }
 }
@@ -106,14 +159,51 @@ static void rbgs_launch(int n, double h, const T *f, const T *uin, T *uout, int 
     hipLaunchKernelGGL((rbgs_zmarch<T, TX, TY>), grid, dim3(TX * TY), 0, s, uin, uout, f, n, T(h * h), kchunk);
 }
 
+// Launch shapes of the smoother: tile variant and z-chunk per level size.
+// Defaults below; the autotuner (tune.hip) overwrites entries after timing them.
+static SmootherShape g_rbgs_shape[2][11];   // [fp32?][log2(n-1)]
+static bool g_rbgs_init = false;
+
+static void rbgs_defaults()
+{
+    for (int t = 0; t < 2; ++t)
+        for (int J = 0; J <= 10; ++J) {
+            SmootherShape &sh = g_rbgs_shape[t][J];
+            if (J <= 5) sh = {0, 4};
+            else if (J == 6) sh = {1, 8};
+            else if (J == 7) sh = {1, 8};
+            else if (J == 8) sh = {1, 32};
+            else sh = {1, 64};
+        }
+    g_rbgs_init = true;
+}
+
+template <typename T>
+SmootherShape &rbgs_shape(int n)
+{
+    if (!g_rbgs_init) rbgs_defaults();
+    int J = 0;
+    while ((1 << J) < n - 1) ++J;
+    return g_rbgs_shape[sizeof(T) == 4 ? 1 : 0][J > 10 ? 10 : J];
+}
+
+template <typename T>
+void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, SmootherShape sh, hipStream_t s)
+{
+    const int kc = sh.kchunk > 0 ? sh.kchunk : n;
+    switch (sh.variant) {
+    case 0: rbgs_launch<T, 32, 8>(n, h, f, uin, uout, kc, s); break;
+    case 2: rbgs_launch<T, 64, 8>(n, h, f, uin, uout, kc, s); break;
+    case 3: rbgs_launch<T, 128, 4>(n, h, f, uin, uout, kc, s); break;
+    case 4: rbgs_launch<T, 32, 16>(n, h, f, uin, uout, kc, s); break;
+    default: rbgs_launch<T, 64, 4>(n, h, f, uin, uout, kc, s); break;
+    }
+}
+
 template <typename T>
 void launch_rbgs(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s)
 {
-    if (n <= 33) rbgs_launch<T, 32, 8>(n, h, f, uin, uout, 4, s);
-    else if (n <= 65) rbgs_launch<T, 64, 4>(n, h, f, uin, uout, 8, s);
-    else if (n <= 129) rbgs_launch<T, 64, 4>(n, h, f, uin, uout, 16, s);
-    else if (n <= 257) rbgs_launch<T, 64, 4>(n, h, f, uin, uout, 64, s);
-    else rbgs_launch<T, 64, 4>(n, h, f, uin, uout, 128, s);
+    launch_rbgs_shape<T>(n, h, f, uin, uout, rbgs_shape<T>(n), s);
 }
 
 // ------------------------------------------------- residual and restriction
@@ -327,29 +417,36 @@ __host__ __device__ constexpr int tail_off(int l)
     return l <= 1 ? 0 : tail_off(l - 1) + ((1 << (l - 1)) + 1) * ((1 << (l - 1)) + 1) * ((1 << (l - 1)) + 1);
 }
 constexpr int kTailSize = tail_off(kTailTop + 1);
+constexpr int kTailTopN = (1 << kTailTop) + 1;
 
+// Lanes of the 1024-thread workgroup cover a 16 x 16 x 4 brick of nodes (i, j
+// from the lane, k strided by 4); colour passes use 8 x 16 x 8 with two nodes of
+// one colour per row pair.
 template <typename T>
 struct TailLDS {
-    T *U, *F;
+    T *U, *F, *R;
     T L;
     int npre, npost;
-    __device__ int nl(int l) const { return (1 << l) + 1; }
+    __device__ static int nl(int l) { return (1 << l) + 1; }
     __device__ T *u(int l) const { return U + tail_off(l); }
     __device__ T *fr(int l) const { return F + tail_off(l); }
 
     __device__ void gs(int l, int colour) const
     {
         const int n = nl(l), m = n - 2;
-        const T h = L / T(n - 1), h2 = h * h;
+        const T h = L / T(n - 1), h2 = h * h, sixth = T(1) / T(6);
         T *uu = u(l);
         const T *ff = fr(l);
-        const int cnt = m * m * m;
-        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-            const int i = 1 + t % m, j = 1 + (t / m) % m, k = 1 + t / (m * m);
-            if (((i + j + k) & 1) != colour) continue;
-            const int p = i + n * (j + n * k);
-            const T s = uu[p - 1] + uu[p + 1] + uu[p - n] + uu[p + n] + uu[p - n * n] + uu[p + n * n];
-            uu[p] = (s - h2 * ff[p]) / T(6);
+        const int tx = threadIdx.x & 7, ty = (threadIdx.x >> 3) & 15, tz = threadIdx.x >> 7;
+        const int j = 1 + ty;
+        if (j <= m) {
+            for (int k = 1 + tz; k <= m; k += 8) {
+                const int i = 1 + 2 * tx + ((colour + 1 + j + k) & 1);
+                if (i > m) continue;
+                const int p = i + n * (j + n * k);
+                const T s = uu[p - 1] + uu[p + 1] + uu[p - n] + uu[p + n] + uu[p - n * n] + uu[p + n * n];
+                uu[p] = (s - h2 * ff[p]) * sixth;
+            }
         }
         __syncthreads();
     }
@@ -374,34 +471,41 @@ struct TailLDS {
         }
         __syncthreads();
     }
-    // fc = FW(f - A u) on level l-1, uc = 0
+    // fc = FW(f - A u) on level l-1 and uc = 0: the residual of level l is staged in R
     __device__ void resid_restrict(int l) const
     {
-        const int n = nl(l), nc = nl(l - 1);
+        const int n = nl(l), m = n - 2, nc = nl(l - 1);
         const T h = L / T(n - 1), ih2 = T(1) / (h * h);
         const T *uu = u(l);
         const T *ff = fr(l);
+        const int li = threadIdx.x & 15, lj = (threadIdx.x >> 4) & 15, lk = threadIdx.x >> 8;
+        if (li < m && lj < m) {
+            const int i = 1 + li, j = 1 + lj;
+            for (int k = 1 + lk; k <= m; k += 4) {
+                const int p = i + n * (j + n * k);
+                R[p] = ff[p] - (uu[p - 1] + uu[p + 1] + uu[p - n] + uu[p + n] + uu[p - n * n] + uu[p + n * n] -
+                                T(6) * uu[p]) * ih2;
+            }
+        }
+        __syncthreads();
         T *fc = fr(l - 1);
         T *uc = u(l - 1);
-        const int cnt = nc * nc * nc;
         const T w[3] = {T(0.25), T(0.5), T(0.25)};
-        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-            const int I = t % nc, J = (t / nc) % nc, K = t / (nc * nc);
-            uc[t] = T(0);
-            if (I == 0 || J == 0 || K == 0 || I == nc - 1 || J == nc - 1 || K == nc - 1) {
-                fc[t] = T(0);
-                continue;
+        if (li < nc && lj < nc) {
+            for (int K = lk; K < nc; K += 4) {
+                const int C = li + nc * (lj + nc * K);
+                uc[C] = T(0);
+                if (li == 0 || lj == 0 || K == 0 || li == nc - 1 || lj == nc - 1 || K == nc - 1) {
+                    fc[C] = T(0);
+                    continue;
+                }
+                T acc = T(0);
+                for (int c = -1; c <= 1; ++c)
+                    for (int b = -1; b <= 1; ++b)
+                        for (int a = -1; a <= 1; ++a)
+                            acc += (w[a + 1] * w[b + 1] * w[c + 1]) * R[(2 * li + a) + n * ((2 * lj + b) + n * (2 * K + c))];
+                fc[C] = acc;
             }
-            T acc = T(0);
-            for (int c = -1; c <= 1; ++c)
-                for (int b = -1; b <= 1; ++b)
-                    for (int a = -1; a <= 1; ++a) {
-                        const int p = (2 * I + a) + n * ((2 * J + b) + n * (2 * K + c));
-                        const T lap =
-                            (uu[p - 1] + uu[p + 1] + uu[p - n] + uu[p + n] + uu[p - n * n] + uu[p + n * n] - T(6) * uu[p]) * ih2;
-                        acc += (w[a + 1] * w[b + 1] * w[c + 1]) * (ff[p] - lap);
-                    }
-            fc[t] = acc;
         }
         __syncthreads();
     }
@@ -410,20 +514,22 @@ struct TailLDS {
         const int n = nl(l), nc = nl(l - 1);
         const T *ff = fr(l);
         T *fc = fr(l - 1);
-        const int cnt = nc * nc * nc;
         const T w[3] = {T(0.25), T(0.5), T(0.25)};
-        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-            const int I = t % nc, J = (t / nc) % nc, K = t / (nc * nc);
-            if (I == 0 || J == 0 || K == 0 || I == nc - 1 || J == nc - 1 || K == nc - 1) {
-                fc[t] = T(0);
-                continue;
+        const int li = threadIdx.x & 15, lj = (threadIdx.x >> 4) & 15, lk = threadIdx.x >> 8;
+        if (li < nc && lj < nc) {
+            for (int K = lk; K < nc; K += 4) {
+                const int C = li + nc * (lj + nc * K);
+                if (li == 0 || lj == 0 || K == 0 || li == nc - 1 || lj == nc - 1 || K == nc - 1) {
+                    fc[C] = T(0);
+                    continue;
+                }
+                T acc = T(0);
+                for (int c = -1; c <= 1; ++c)
+                    for (int b = -1; b <= 1; ++b)
+                        for (int a = -1; a <= 1; ++a)
+                            acc += (w[a + 1] * w[b + 1] * w[c + 1]) * ff[(2 * li + a) + n * ((2 * lj + b) + n * (2 * K + c))];
+                fc[C] = acc;
             }
-            T acc = T(0);
-            for (int c = -1; c <= 1; ++c)
-                for (int b = -1; b <= 1; ++b)
-                    for (int a = -1; a <= 1; ++a)
-                        acc += (w[a + 1] * w[b + 1] * w[c + 1]) * ff[(2 * I + a) + n * ((2 * J + b) + n * (2 * K + c))];
-            fc[t] = acc;
         }
         __syncthreads();
     }
@@ -432,25 +538,28 @@ struct TailLDS {
         const int nc = nl(lc), n = nl(lc + 1), m = n - 2;
         const T *uc = u(lc);
         T *uf = u(lc + 1);
-        const int cnt = m * m * m;
-        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-            const int i = 1 + t % m, j = 1 + (t / m) % m, k = 1 + t / (m * m);
-            const T v = prolong_at(nc, uc, i, j, k);
-            const int p = i + n * (j + n * k);
-            uf[p] = add ? uf[p] + v : v;
+        const int li = threadIdx.x & 15, lj = (threadIdx.x >> 4) & 15, lk = threadIdx.x >> 8;
+        if (li < m && lj < m) {
+            const int i = 1 + li, j = 1 + lj;
+            for (int k = 1 + lk; k <= m; k += 4) {
+                const T v = prolong_at(nc, uc, i, j, k);
+                const int p = i + n * (j + n * k);
+                uf[p] = add ? uf[p] + v : v;
+            }
         }
         __syncthreads();
     }
-    __device__ void inject(int l, int top) const   // boundary of level l from level top
+    __device__ void inject(int l, int top) const   // boundary of level l from level top, interior 0
     {
         const int n = nl(l), nt = nl(top), st = (nt - 1) / (n - 1);
         T *uu = u(l);
         const T *ut = u(top);
-        const int cnt = n * n * n;
-        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-            const int i = t % n, j = (t / n) % n, k = t / (n * n);
-            const bool bnd = i == 0 || j == 0 || k == 0 || i == n - 1 || j == n - 1 || k == n - 1;
-            uu[t] = bnd ? ut[(i * st) + nt * ((j * st) + nt * (k * st))] : T(0);
+        const int li = threadIdx.x & 15, lj = (threadIdx.x >> 4) & 15, lk = threadIdx.x >> 8;
+        if (li < n && lj < n) {
+            for (int k = lk; k < n; k += 4) {
+                const bool bnd = li == 0 || lj == 0 || k == 0 || li == n - 1 || lj == n - 1 || k == n - 1;
+                uu[li + n * (lj + n * k)] = bnd ? ut[(li * st) + nt * ((lj * st) + nt * (k * st))] : T(0);
+            }
         }
         __syncthreads();
     }
@@ -475,7 +584,8 @@ coarse_tail_k(int top, T L, const T *__restrict__ fg, T *__restrict__ ug, int np
 {
     __shared__ T U[kTailSize];
     __shared__ T F[kTailSize];
-    TailLDS<T> t{U, F, L, npre, npost};
+    __shared__ T Rs[kTailTopN * kTailTopN * kTailTopN];
+    TailLDS<T> t{U, F, Rs, L, npre, npost};
     const int n = t.nl(top), cnt = n * n * n;
     for (int p = threadIdx.x; p < cnt; p += blockDim.x) {
         t.u(top)[p] = ug[p];
@@ -588,6 +698,8 @@ void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial
 // -------------------------------------------------------- instantiations
 #define QM_INST(T)                                                                                              \
     template void launch_rbgs<T>(int, double, const T *, const T *, T *, hipStream_t);                         \
+    template void launch_rbgs_shape<T>(int, double, const T *, const T *, T *, SmootherShape, hipStream_t);     \
+    template SmootherShape &rbgs_shape<T>(int);                                                                 \
     template void launch_residual_restrict<T>(int, double, const T *, const T *, T *, T *, T *, hipStream_t);  \
     template void launch_restrict<T>(int, const T *, T *, hipStream_t);                                        \
     template void launch_prolong_add<T>(int, const T *, T *, hipStream_t);                                     \

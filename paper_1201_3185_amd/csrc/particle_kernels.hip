@@ -11,50 +11,110 @@
 namespace qm {
 
 // ------------------------------------------------------------------ deposit
+//
+// Workgroup g takes a contiguous share of the particles.  For each box it
+// clears an LDS window of kWin nodes around the box centre, adds every corner
+// of the particles whose whole cloud lies in the window with LDS 64-bit
+// atomics, sends the other particles' corners to the grid with global 64-bit
+// atomics, and writes the window to its scratch slab.  A second kernel sums
+// the slabs of all workgroups into the grid.  Integer addition makes the
+// result independent of the order of every add.
 
-__global__ void __launch_bounds__(256)
-deposit_direct_k(DepositArgs A, const double *__restrict__ x, const double *__restrict__ y,
-                 const double *__restrict__ z, const double *__restrict__ m, int64_t np,
+__device__ __forceinline__ bool cic_cell(const BoxGeom &g, int n, double px, double py, double pz, int ic[3],
+                                         double w[3][2])
+{
+#pragma clang fp contract(off)
+    const double top = (double)(n - 1);
+    const double ux = (px - g.xmin) * g.inv_h;
+    const double uy = (py - g.xmin) * g.inv_h;
+    const double uz = (pz - g.xmin) * g.inv_h;
+    if (!(ux >= 0.0 && ux < top && uy >= 0.0 && uy < top && uz >= 0.0 && uz < top)) return false;
+    const double fx0 = floor(ux), fy0 = floor(uy), fz0 = floor(uz);
+    ic[0] = (int)fx0;
+    ic[1] = (int)fy0;
+    ic[2] = (int)fz0;
+    const double fx = ux - fx0, fy = uy - fy0, fz = uz - fz0;
+    w[0][0] = 1.0 - fx;
+    w[0][1] = fx;
+    w[1][0] = 1.0 - fy;
+    w[1][1] = fy;
+    w[2][0] = 1.0 - fz;
+    w[2][1] = fz;
+    return true;
+}
+
+__global__ void __launch_bounds__(kDepositThreads)
+deposit_window_k(DepositArgs A, const double *__restrict__ x, const double *__restrict__ y,
+                 const double *__restrict__ z, const double *__restrict__ m, int64_t np, int64_t per_block,
                  unsigned long long *__restrict__ inside_count)
 {
 #pragma clang fp contract(off)
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int in0 = 0;
-    if (p < np) {
-        const double px = x[p], py = y[p], pz = z[p], pm = m[p];
-        const double top = (double)(A.n - 1);
-        for (int b = 0; b < A.nbox; ++b) {
-            const BoxGeom g = A.box[b];
-            const double ux = (px - g.xmin) * g.inv_h;
-            const double uy = (py - g.xmin) * g.inv_h;
-            const double uz = (pz - g.xmin) * g.inv_h;
-            if (!(ux >= 0.0 && ux < top && uy >= 0.0 && uy < top && uz >= 0.0 && uz < top)) continue;
-            if (b == 0) in0 = 1;
-            const double fx0 = floor(ux), fy0 = floor(uy), fz0 = floor(uz);
-            const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
-            const double fx = ux - fx0, fy = uy - fy0, fz = uz - fz0;
-            const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
-            unsigned long long *q = A.q[b];
+    __shared__ unsigned long long W[kWin];
+    __shared__ unsigned int cnt_sh;
+    const int64_t p0 = (int64_t)blockIdx.x * per_block;
+    const int64_t p1 = min(np, p0 + per_block);
+    if (threadIdx.x == 0) cnt_sh = 0;
+    unsigned int in0 = 0;
+    for (int b = 0; b < A.nbox; ++b) {
+        for (int e = threadIdx.x; e < kWin; e += kDepositThreads) W[e] = 0ULL;
+        __syncthreads();
+        const BoxGeom g = A.box[b];
+        const int wx = A.w0[b][0], wy = A.w0[b][1], wz = A.w0[b][2];
+        unsigned long long *q = A.q[b];
+        for (int64_t p = p0 + threadIdx.x; p < p1; p += kDepositThreads) {
+            int ic[3];
+            double w[3][2];
+            if (!cic_cell(g, A.n, x[p], y[p], z[p], ic, w)) continue;
+            if (b == 0) ++in0;
+            const double pm = m[p];
+            const int lx = ic[0] - wx, ly = ic[1] - wy, lz = ic[2] - wz;
+            const bool inwin = lx >= 0 && lx < kWinX - 1 && ly >= 0 && ly < kWinY - 1 && lz >= 0 && lz < kWinZ - 1;
             for (int c = 0; c < 2; ++c)
                 for (int bb = 0; bb < 2; ++bb)
                     for (int a = 0; a < 2; ++a) {
-                        const double w = (wx[a] * wy[bb]) * wz[c];
-                        const long long qv = __double2ll_rn((w * pm) * A.scale);
-                        atomicAdd(q + id3(A.n, ix + a, iy + bb, iz + c), (unsigned long long)qv);
+                        const double wt = (w[0][a] * w[1][bb]) * w[2][c];
+                        const unsigned long long qv = (unsigned long long)__double2ll_rn((wt * pm) * A.scale);
+                        if (inwin) atomicAdd(&W[(lx + a) + kWinX * ((ly + bb) + kWinY * (lz + c))], qv);
+                        else atomicAdd(q + id3(A.n, ic[0] + a, ic[1] + bb, ic[2] + c), qv);
                     }
         }
+        __syncthreads();
+        unsigned long long *slab = A.scratch + ((size_t)blockIdx.x * A.nbox + b) * kWin;
+        for (int e = threadIdx.x; e < kWin; e += kDepositThreads) slab[e] = W[e];
+        __syncthreads();
     }
-    // one atomic per wavefront for the inside count
-    const unsigned long long mask = __ballot(in0);
-    if ((threadIdx.x & 63) == 0 && mask) atomicAdd(inside_count, (unsigned long long)__popcll(mask));
+    // particles inside the outermost box: one LDS and one global add per workgroup
+    atomicAdd(&cnt_sh, in0);
+    __syncthreads();
+    if (threadIdx.x == 0 && cnt_sh) atomicAdd(inside_count, (unsigned long long)cnt_sh);
 }
+
+__global__ void __launch_bounds__(256)
+deposit_reduce_k(DepositArgs A, int nblocks)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int b = blockIdx.y;
+    if (e >= kWin) return;
+    const int li = e % kWinX, lj = (e / kWinX) % kWinY, lk = e / (kWinX * kWinY);
+    const int i = A.w0[b][0] + li, j = A.w0[b][1] + lj, k = A.w0[b][2] + lk;
+    if (i >= A.n || j >= A.n || k >= A.n) return;
+    unsigned long long s = 0ULL;
+    for (int g = 0; g < nblocks; ++g) s += A.scratch[((size_t)g * A.nbox + b) * kWin + e];
+    if (s) A.q[b][id3(A.n, i, j, k)] += s;
+}
+
+size_t deposit_scratch_bytes(int nbox) { return (size_t)kDepositMaxBlocks * nbox * kWin * sizeof(unsigned long long); }
 
 void launch_deposit(const DepositArgs &a, const double *x, const double *y, const double *z, const double *m,
                     int64_t np, unsigned long long *inside_count, hipStream_t s)
 {
     if (np <= 0) return;
-    const int64_t blocks = (np + 255) / 256;
-    hipLaunchKernelGGL(deposit_direct_k, dim3((unsigned)blocks), dim3(256), 0, s, a, x, y, z, m, np, inside_count);
+    int64_t blocks = (np + kDepositThreads - 1) / kDepositThreads;
+    if (blocks > kDepositMaxBlocks) blocks = kDepositMaxBlocks;
+    const int64_t per_block = (np + blocks - 1) / blocks;
+    hipLaunchKernelGGL(deposit_window_k, dim3((unsigned)blocks), dim3(kDepositThreads), 0, s, a, x, y, z, m, np,
+                       per_block, inside_count);
+    hipLaunchKernelGGL(deposit_reduce_k, dim3((kWin + 255) / 256, a.nbox), dim3(256), 0, s, a, (int)blocks);
 }
 
 __global__ void rhs_from_q_k(size_t count, double inv_h3, double four_pi_G, int shift, const long long *__restrict__ q,

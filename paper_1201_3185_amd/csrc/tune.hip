@@ -1,0 +1,178 @@
+// Smoother launch-shape autotuner and its persisted table (qumond_tune.h).
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/qumond_tune.h"
+#include "common.h"
+#include "mg.h"
+
+void qm_set_last_error(const char *msg);
+
+namespace {
+
+qumond_status tfail(const std::string &m)
+{
+    qm_set_last_error(m.c_str());
+    return QUMOND_ERR_INVALID;
+}
+
+bool good_n(int n) { return n >= 5 && n <= 1025 && qm::log2_exact(n - 1) >= 2; }
+
+const int kChunks[] = {4, 8, 16, 32, 64, 128, 0};
+
+template <typename T>
+qumond_status tune_one(int n, int reps, hipStream_t s, double &best_us)
+{
+    const size_t N = (size_t)n * n * n;
+    T *f = nullptr, *u0 = nullptr, *u1 = nullptr;
+    if (hipMalloc((void **)&f, N * sizeof(T)) != hipSuccess || hipMalloc((void **)&u0, N * sizeof(T)) != hipSuccess ||
+        hipMalloc((void **)&u1, N * sizeof(T)) != hipSuccess) {
+        (void)hipFree(f);
+        (void)hipFree(u0);
+        qm_set_last_error("qumond_autotune: allocation failed");
+        return QUMOND_ERR_OOM;
+    }
+    qm::launch_fill<T>(f, N, T(1), s);
+    qm::launch_fill<T>(u0, N, T(0.5), s);
+    qm::launch_fill<T>(u1, N, T(0.5), s);
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    qm::SmootherShape best = qm::rbgs_shape<T>(n);
+    best_us = 1e30;
+    const double h = 1.0 / (n - 1);
+    for (int v = 0; v < qm::kSmootherVariants; ++v)
+        for (int kc : kChunks) {
+            if (kc != 0 && kc >= n - 2) continue;
+            const qm::SmootherShape sh{v, kc};
+            std::vector<float> t;
+            qm::launch_rbgs_shape<T>(n, h, f, u0, u1, sh, s);   // warm-up
+            for (int r = 0; r < reps; ++r) {
+                (void)hipEventRecord(e0, s);
+                qm::launch_rbgs_shape<T>(n, h, f, (r & 1) ? u1 : u0, (r & 1) ? u0 : u1, sh, s);
+                (void)hipEventRecord(e1, s);
+                (void)hipEventSynchronize(e1);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                t.push_back(ms);
+            }
+            std::sort(t.begin(), t.end());
+            const double us = 1e3 * t[t.size() / 2];
+            if (us < best_us) {
+                best_us = us;
+                best = sh;
+            }
+        }
+    qm::rbgs_shape<T>(n) = best;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(f);
+    (void)hipFree(u0);
+    (void)hipFree(u1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        qm_set_last_error(hipGetErrorString(e));
+        return QUMOND_ERR_HIP;
+    }
+    return QUMOND_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qumond_status qumond_tune_set(int32_t n, int32_t fp32, int32_t variant, int32_t kchunk)
+{
+    if (!good_n(n) || variant < 0 || variant >= qm::kSmootherVariants || kchunk < 0)
+        return tfail("qumond_tune_set: bad argument");
+    qm::SmootherShape sh{variant, kchunk};
+    if (fp32) qm::rbgs_shape<float>(n) = sh;
+    else qm::rbgs_shape<double>(n) = sh;
+    return QUMOND_OK;
+}
+
+qumond_status qumond_tune_get(int32_t n, int32_t fp32, int32_t *variant, int32_t *kchunk)
+{
+    if (!good_n(n) || !variant || !kchunk) return tfail("qumond_tune_get: bad argument");
+    const qm::SmootherShape sh = fp32 ? qm::rbgs_shape<float>(n) : qm::rbgs_shape<double>(n);
+    *variant = sh.variant;
+    *kchunk = sh.kchunk;
+    return QUMOND_OK;
+}
+
+qumond_status qumond_k_rbgs_sweep_shape(int32_t n, double h, const double *f, const double *u_in, double *u_out,
+                                        int32_t variant, int32_t kchunk, void *stream)
+{
+    if (!good_n(n) || !(h > 0.0) || !f || !u_in || !u_out || u_in == u_out || variant < 0 ||
+        variant >= qm::kSmootherVariants || kchunk < 0)
+        return tfail("qumond_k_rbgs_sweep_shape: bad argument");
+    qm::launch_rbgs_shape<double>(n, h, f, u_in, u_out, qm::SmootherShape{variant, kchunk}, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        qm_set_last_error(hipGetErrorString(e));
+        return QUMOND_ERR_HIP;
+    }
+    return QUMOND_OK;
+}
+
+qumond_status qumond_autotune(int32_t n_max, int32_t both, int32_t reps, const char *json_path, double *best_us,
+                              void *stream)
+{
+    if (!good_n(n_max) || reps < 1 || reps > 1000) return tfail("qumond_autotune: bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    std::string js = "{\"smoother\": [";
+    bool first = true;
+    for (int J = 5; (1 << J) + 1 <= n_max; ++J) {
+        const int n = (1 << J) + 1;
+        for (int prec = 0; prec < (both ? 2 : 1); ++prec) {
+            double us = 0.0;
+            qumond_status st = prec ? tune_one<float>(n, reps, s, us) : tune_one<double>(n, reps, s, us);
+            if (st != QUMOND_OK) return st;
+            if (!prec && best_us) best_us[J] = us;
+            const qm::SmootherShape sh = prec ? qm::rbgs_shape<float>(n) : qm::rbgs_shape<double>(n);
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "%s{\"n\": %d, \"fp32\": %d, \"variant\": %d, \"kchunk\": %d, \"us\": %.3f}",
+                          first ? "" : ", ", n, prec, sh.variant, sh.kchunk, us);
+            js += buf;
+            first = false;
+        }
+    }
+    js += "]}\n";
+    if (json_path) {
+        FILE *fp = std::fopen(json_path, "w");
+        if (!fp) return tfail("qumond_autotune: cannot write the table");
+        std::fputs(js.c_str(), fp);
+        std::fclose(fp);
+    }
+    return QUMOND_OK;
+}
+
+qumond_status qumond_tune_load(const char *json_path)
+{
+    if (!json_path) return tfail("qumond_tune_load: path is NULL");
+    FILE *fp = std::fopen(json_path, "r");
+    if (!fp) return tfail("qumond_tune_load: cannot open the table");
+    std::string txt;
+    char buf[4096];
+    size_t k;
+    while ((k = std::fread(buf, 1, sizeof buf, fp)) > 0) txt.append(buf, k);
+    std::fclose(fp);
+    size_t pos = 0;
+    int loaded = 0;
+    while ((pos = txt.find("{\"n\":", pos)) != std::string::npos) {
+        int n = 0, fp32 = 0, variant = 0, kchunk = 0;
+        if (std::sscanf(txt.c_str() + pos, "{\"n\": %d, \"fp32\": %d, \"variant\": %d, \"kchunk\": %d", &n, &fp32,
+                        &variant, &kchunk) == 4) {
+            if (qumond_tune_set(n, fp32, variant, kchunk) != QUMOND_OK) return QUMOND_ERR_INVALID;
+            ++loaded;
+        }
+        ++pos;
+    }
+    if (!loaded) return tfail("qumond_tune_load: no entries");
+    return QUMOND_OK;
+}
+
+}  // extern "C"

@@ -85,6 +85,11 @@ _SIGNATURES = {
     "qumond_k_fmg": (_I32, [_I32, _D, _P, _P, _I32, _I32, _I32, _I32, _D, ctypes.POINTER(_D),
                             ctypes.POINTER(_I32), _P]),
     "qumond_k_vcycles": (_I32, [_I32, _D, _P, _P, _I32, _I32, _I32, ctypes.POINTER(_D), _P]),
+    "qumond_tune_set": (_I32, [_I32, _I32, _I32, _I32]),
+    "qumond_tune_get": (_I32, [_I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "qumond_k_rbgs_sweep_shape": (_I32, [_I32, _D, _P, _P, _P, _I32, _I32, _P]),
+    "qumond_autotune": (_I32, [_I32, _I32, _I32, ctypes.c_char_p, ctypes.POINTER(_D), _P]),
+    "qumond_tune_load": (_I32, [ctypes.c_char_p]),
 }
 
 _lib = None
@@ -337,3 +342,34 @@ def k_vcycles(f, u, L, ncyc, npre=2, npost=2):
     check(lib().qumond_k_vcycles(u.shape[0], float(L), _ptr(f), _ptr(u), npre, npost, ncyc, ctypes.byref(rr), _s()),
           "qumond_k_vcycles")
     return float(rr.value)
+
+
+# ------------------------------------------------------------------ tuning
+
+SMOOTHER_VARIANTS = {0: (32, 8), 1: (64, 4), 2: (64, 8), 3: (128, 4), 4: (32, 16)}
+
+
+def tune_set(n, variant, kchunk, fp32=False):
+    check(lib().qumond_tune_set(int(n), int(bool(fp32)), int(variant), int(kchunk)), "qumond_tune_set")
+
+
+def tune_get(n, fp32=False):
+    v, k = ctypes.c_int32(0), ctypes.c_int32(0)
+    check(lib().qumond_tune_get(int(n), int(bool(fp32)), ctypes.byref(v), ctypes.byref(k)), "qumond_tune_get")
+    return int(v.value), int(k.value)
+
+
+def k_rbgs_sweep_shape(f, u_in, u_out, h, variant, kchunk):
+    check(lib().qumond_k_rbgs_sweep_shape(u_in.shape[0], float(h), _ptr(f), _ptr(u_in), _ptr(u_out), int(variant),
+                                          int(kchunk), _s()), "qumond_k_rbgs_sweep_shape")
+
+
+def autotune(n_max=513, both=True, reps=5, json_path=None):
+    best = (ctypes.c_double * 11)()
+    check(lib().qumond_autotune(int(n_max), int(bool(both)), int(reps), json_path.encode() if json_path else None,
+                                best, _s()), "qumond_autotune")
+    return {(1 << J) + 1: best[J] for J in range(5, 11) if best[J] > 0}
+
+
+def tune_load(json_path):
+    check(lib().qumond_tune_load(json_path.encode()), "qumond_tune_load")

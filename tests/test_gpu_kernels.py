@@ -223,3 +223,33 @@ def test_vcycles(n):
     rr_g = Q.k_vcycles(dev(f), d, L, 3)
     assert rr_g == pytest.approx(rr_o, rel=1e-8)
     assert rel(host(d), ref) < 1e-12
+
+
+@pytest.mark.parametrize("n", [33, 129])
+def test_every_smoother_shape_is_bitwise_identical(n):
+    """Launch shapes change only the schedule: each node's update is the same
+    sum in the same order, so every shape gives the same bits."""
+    L = 4.0
+    h = L / (n - 1)
+    f, u = rand_state(n, 800 + n)
+    fd, ud = dev(f), dev(u)
+    ref = dev(u)
+    Q.k_rbgs_sweep(fd, ud, ref, h)
+    ref = host(ref)
+    assert rel(ref, O.rbgs_sweep(f, u.copy(), h)) < 1e-14
+    for v in Q.SMOOTHER_VARIANTS:
+        for kc in (4, 16, 0):
+            out = dev(u)
+            Q.k_rbgs_sweep_shape(fd, ud, out, h, v, kc)
+            assert np.array_equal(host(out), ref), (v, kc)
+
+
+def test_autotune_installs_a_table(tmp_path):
+    before = Q.tune_get(65)
+    best = Q.autotune(n_max=65, both=True, reps=3, json_path=str(tmp_path / "t.json"))
+    assert set(best) == {33, 65} and all(v > 0 for v in best.values())
+    txt = (tmp_path / "t.json").read_text()
+    assert '"n": 65' in txt
+    Q.tune_set(65, *before)
+    Q.tune_load(str(tmp_path / "t.json"))
+    assert Q.tune_get(65) in [(v, k) for v in Q.SMOOTHER_VARIANTS for k in (4, 8, 16, 32, 64, 128, 0)]
