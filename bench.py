@@ -74,6 +74,9 @@ def main():
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     x, y, z, m = dev(p.x), dev(p.y), dev(p.z), dev(p.m)
     M = p.total_mass
+    log("autotuning smoother launch shapes (setup, not timed)")
+    tuned = Q.autotune(n_max=n, both=False, reps=5)
+    shapes = {str(k): {"single": Q.tune_get(k), "fused": Q.tune_get_fused(k)} for k in (33, 65, 129)}
     cfg = Q.Config(n=n, box_side=sides, tol_rel=1e-10)
     ctx = Q.Context(cfg)
     infos = {}
@@ -113,7 +116,7 @@ def main():
         tr = smoother_traffic(per_launch)
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
-                "kernel": "rbgs_zmarch (all levels)", "launches_per_step": st["launches"] // args.steps,
+                "kernel": "red-black smoother launches, all levels (fused two-sweep rbgs2_zmarch; 24 B/pt per launch)", "launches_per_step": st["launches"] // args.steps,
                 "avg_launch_us": round(avg_ms * 1e3, 3), "alg_bytes_per_launch": per_launch}
         log(f"smoother: {st['launches']} launches, avg {avg_ms * 1e3:.2f} us, {achieved:.1f} GB/s algorithmic")
 
@@ -140,6 +143,7 @@ def main():
                    "n": n, "boxes_kpc": sides, "particles": npart, "tol_rel": 1e-10, "ncycle_fmg": 6,
                    "npre": 2, "npost": 2, "precision": "fp64"},
         "vcycles_after_fmg": {"newton": infos["newton"]["vcycles"], "mond": infos["mond"]["vcycles"]},
+        "smoother_shapes": shapes,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

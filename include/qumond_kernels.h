@@ -26,6 +26,13 @@ extern "C" {
 qumond_status qumond_k_rbgs_sweep(int32_t n, double h, const double *f, const double *u_in, double *u_out,
                                   void *stream);
 
+/* Two sweeps in one launch (same result, bit for bit, as two calls of
+ * qumond_k_rbgs_sweep).  uc (optional): a coarse grid of (n+1)/2 points per side
+ * whose trilinear prolongation is added to u_in's interior first, as the
+ * coarse-grid correction of a V-cycle (qumond_k_prolong_add) does. */
+qumond_status qumond_k_rbgs_double_sweep(int32_t n, double h, const double *f, const double *u_in, double *u_out,
+                                         const double *uc, void *stream);
+
 /* Coarse rhs fc = full-weighting restriction of r = f - A_h u (27-point,
  * weights (1/4,1/2,1/4) per axis; 0 on the coarse boundary), and the coarse
  * correction zeroed: uc0 entirely, uc1 (optional) on its boundary nodes.

@@ -28,14 +28,18 @@ extern "C" {
 qumond_status qumond_tune_set(int32_t n, int32_t fp32, int32_t variant, int32_t kchunk);
 qumond_status qumond_tune_get(int32_t n, int32_t fp32, int32_t *variant, int32_t *kchunk);
 
+/* The same for the fused two-sweep smoother (variant 0 = 32x8, 1 = 64x4). */
+qumond_status qumond_tune_set_fused(int32_t n, int32_t fp32, int32_t variant, int32_t kchunk);
+qumond_status qumond_tune_get_fused(int32_t n, int32_t fp32, int32_t *variant, int32_t *kchunk);
+
 /* One smoother sweep with an explicit shape (see qumond_k_rbgs_sweep). */
 qumond_status qumond_k_rbgs_sweep_shape(int32_t n, double h, const double *f, const double *u_in, double *u_out,
                                         int32_t variant, int32_t kchunk, void *stream);
 
-/* Time all shapes for n = 33, 65, ..., n_max (and both precisions if
- * both != 0), install the fastest; json_path (host string, optional) receives
- * the table.  best_us (host, optional, 11 entries) gets the FP64 time per
- * sweep indexed by log2(n-1). */
+/* Time all shapes of both smoother kernels for n = 33, 65, ..., n_max (and
+ * both precisions if both != 0), install the fastest; json_path (host
+ * string, optional) receives the table.  best_us (host, optional, 11 entries)
+ * gets the FP64 time of one fused two-sweep launch indexed by log2(n-1). */
 qumond_status qumond_autotune(int32_t n_max, int32_t both, int32_t reps, const char *json_path, double *best_us,
                               void *stream);
 qumond_status qumond_tune_load(const char *json_path);

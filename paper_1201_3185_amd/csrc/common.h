@@ -59,6 +59,11 @@ template <typename T> void launch_rbgs(int n, double h, const T *f, const T *uin
 template <typename T> void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, SmootherShape sh,
                                             hipStream_t s);
 template <typename T> SmootherShape &rbgs_shape(int n);   // the table entry used for n
+// Two sweeps in one launch (variants 0: 32x8, 1: 64x4); with uc != NULL the
+// correction u += P uc (uc on the next coarser level) is applied first.
+template <typename T> void launch_rbgs2(int n, double h, const T *f, const T *uin, T *uout, const T *uc,
+                                       hipStream_t s);
+template <typename T> SmootherShape &rbgs2_shape(int n);
 template <typename T> void launch_residual_restrict(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1,
                                                    hipStream_t s);
 template <typename T> void launch_restrict(int nf, const T *src, T *dst, hipStream_t s);

@@ -16,6 +16,22 @@
 
 namespace qm {
 
+// Trilinear value of the coarse field at fine node (i,j,k): an even fine index
+// sits on coarse node i/2, an odd one halfway between (i-1)/2 and (i+1)/2.
+template <typename T>
+__device__ __forceinline__ T prolong_at(int nc, const T *__restrict__ uc, int i, int j, int k)
+{
+    const int ia = i >> 1, ib = (i + 1) >> 1, ja = j >> 1, jb = (j + 1) >> 1, ka = k >> 1, kb = (k + 1) >> 1;
+    const T wia = (i & 1) ? T(0.5) : T(1), wib = (i & 1) ? T(0.5) : T(0);
+    const T wja = (j & 1) ? T(0.5) : T(1), wjb = (j & 1) ? T(0.5) : T(0);
+    const T wka = (k & 1) ? T(0.5) : T(1), wkb = (k & 1) ? T(0.5) : T(0);
+    const T xa = wia * uc[id3(nc, ia, ja, ka)] + wib * uc[id3(nc, ib, ja, ka)];
+    const T xb = wia * uc[id3(nc, ia, jb, ka)] + wib * uc[id3(nc, ib, jb, ka)];
+    const T xc = wia * uc[id3(nc, ia, ja, kb)] + wib * uc[id3(nc, ib, ja, kb)];
+    const T xd = wia * uc[id3(nc, ia, jb, kb)] + wib * uc[id3(nc, ib, jb, kb)];
+    return wka * (wja * xa + wjb * xb) + wkb * (wja * xc + wjb * xd);
+}
+
 // ------------------------------------------------------------------ smoother
 
 template <typename T, int TX, int TY>
@@ -159,6 +175,167 @@ static void rbgs_launch(int n, double h, const T *f, const T *uin, T *uout, int 
     hipLaunchKernelGGL((rbgs_zmarch<T, TX, TY>), grid, dim3(TX * TY), 0, s, uin, uout, f, n, T(h * h), kchunk);
 }
 
+// ----------------------------------------------------- two fused sweeps
+//
+// Two red-black sweeps (A then B) in one pass: four stages one z plane
+// apart run behind each other in the march, each on a ring one node narrower
+// than the stage before (red A on the tile plus three nodes, black A plus two,
+// red B plus one, black B on the tile), so every stage finds the values it
+// needs in LDS.  A plane's LDS copy is updated in place: each stage writes one
+// colour and reads only the other, whose newest values are the ones the
+// sequential sweeps would read.  Each node update is the same expression as in
+// rbgs_zmarch, so the result equals two separate sweeps bit for bit.  With
+// PROLONG the coarse-grid correction u += P uc is applied to every interior
+// node as its plane is loaded (the post-smoothing of a V-cycle).
+template <typename T, int TX, int TY, bool PROLONG>
+__global__ void __launch_bounds__(TX *TY)
+rbgs2_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2, int kchunk,
+             const T *__restrict__ uc, int nc)
+{
+    constexpr int R = 4;                         // ring of the LDS planes
+    constexpr int PX = TX + 2 * R, PY = TY + 2 * R, NT = TX * TY;
+    constexpr int PL = PX * PY;
+    constexpr int FX = TX + 6, FY = TY + 6, FL = FX * FY;   // f on the ring-3 region
+    constexpr int NS = 7, NF = 5;
+    constexpr int NL = (PL + NT - 1) / NT, NFL = (FL + NT - 1) / NT;
+    __shared__ T pl[NS][PL];
+    __shared__ T fp[NF][FL];
+    const T sixth = T(1) / T(6);
+    const int tid = threadIdx.x;
+    const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
+    const int kb = 1 + blockIdx.z * kchunk;
+    if (kb > n - 2) return;
+    const int ke = min(kb + kchunk - 1, n - 2);
+    const size_t nn = (size_t)n * n;
+
+    int goff[NL], gi[NL], gj[NL];
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+        const int t = tid + r * NT;
+        const int a = t % PX, b = t / PX;
+        gi[r] = i0 - R + a;
+        gj[r] = j0 - R + b;
+        goff[r] = (t < PL && gi[r] >= 0 && gi[r] < n && gj[r] >= 0 && gj[r] < n) ? gi[r] + n * gj[r] : -1;
+    }
+    int foff[NFL];
+#pragma unroll
+    for (int r = 0; r < NFL; ++r) {
+        const int t = tid + r * NT;
+        const int a = t % FX, b = t / FX;
+        const int i = i0 - 3 + a, j = j0 - 3 + b;
+        foff[r] = (t < FL && i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2) ? i + n * j : -1;
+    }
+    T v[NL], w[NFL];
+    auto prefetch_u = [&](int k) {
+        const T *src = uin + (size_t)k * nn;
+        const bool inner_plane = k >= 1 && k <= n - 2;
+#pragma unroll
+        for (int r = 0; r < NL; ++r) {
+            T x = goff[r] >= 0 ? src[goff[r]] : T(0);
+            if (PROLONG && inner_plane && goff[r] >= 0 && gi[r] >= 1 && gi[r] <= n - 2 && gj[r] >= 1 && gj[r] <= n - 2)
+                x += prolong_at(nc, uc, gi[r], gj[r], k);
+            v[r] = x;
+        }
+    };
+    auto commit_u = [&](int k) {
+        T *P = pl[k % NS];
+#pragma unroll
+        for (int r = 0; r < NL; ++r) {
+            const int t = tid + r * NT;
+            if (t < PL) P[t] = v[r];
+        }
+    };
+    auto prefetch_f = [&](int k) {
+        const T *src = f + (size_t)k * nn;
+#pragma unroll
+        for (int r = 0; r < NFL; ++r) w[r] = foff[r] >= 0 ? src[foff[r]] : T(0);
+    };
+    auto commit_f = [&](int k) {
+        T *F = fp[k % NF];
+#pragma unroll
+        for (int r = 0; r < NFL; ++r) {
+            const int t = tid + r * NT;
+            if (t < FL) F[t] = w[r];
+        }
+    };
+    // one colour of plane k on the tile plus `ring` nodes
+    auto stage = [&](int k, int ring, int colour) {
+        T *P = pl[k % NS];
+        const T *Pm = pl[(k + NS - 1) % NS];
+        const T *Pp = pl[(k + 1) % NS];
+        const T *F = fp[k % NF];
+        const int hw = (TX + 2 * ring) / 2, rows = TY + 2 * ring, a0 = R - ring;
+        for (int t = tid; t < hw * rows; t += NT) {
+            const int b = a0 + t / hw;
+            const int j = j0 - R + b;
+            const int ia0 = i0 - R + a0;
+            const int a = a0 + (((ia0 + j + k) & 1) == colour ? 0 : 1) + 2 * (t % hw);
+            const int i = i0 - R + a;
+            if (i < 1 || i > n - 2 || j < 1 || j > n - 2) continue;
+            const int c = b * PX + a;
+            const T s = P[c - 1] + P[c + 1] + P[c - PX] + P[c + PX] + Pm[c] + Pp[c];
+            P[c] = (s - h2 * F[(b - 1) * FX + (a - 1)]) * sixth;
+        }
+    };
+    auto store = [&](int k) {
+        const T *P = pl[k % NS];
+        for (int t = tid; t < TX * TY; t += NT) {
+            const int a = R + t % TX, b = R + t / TX;
+            const int i = i0 - R + a, j = j0 - R + b;
+            if (i > n - 2 || j > n - 2) continue;
+            uout[(size_t)k * nn + i + (size_t)n * j] = P[b * PX + a];
+        }
+    };
+    auto in_u = [&](int k) { return k >= max(0, kb - 4) && k <= min(n - 1, ke + 4); };
+    auto in_f = [&](int k) { return k >= max(1, kb - 3) && k <= min(n - 2, ke + 3); };
+    auto in_stage = [&](int k, int lag) { return k >= max(1, kb - lag) && k <= min(n - 2, ke + lag); };
+
+    if (in_u(kb - 4)) prefetch_u(kb - 4);
+    if (in_f(kb - 5)) prefetch_f(kb - 5);
+    for (int k = kb - 8; k <= ke; ++k) {
+        if (in_u(k + 4)) commit_u(k + 4);
+        if (in_f(k + 3)) commit_f(k + 3);
+        if (in_u(k + 5)) prefetch_u(k + 5);
+        if (in_f(k + 4)) prefetch_f(k + 4);
+        __syncthreads();
+        if (in_stage(k + 3, 3)) stage(k + 3, 3, 0);      // red, sweep A
+        __syncthreads();
+        if (in_stage(k + 2, 2)) stage(k + 2, 2, 1);      // black, sweep A
+        __syncthreads();
+        if (in_stage(k + 1, 1)) stage(k + 1, 1, 0);      // red, sweep B
+        __syncthreads();
+        if (k >= kb) {
+            stage(k, 0, 1);                              // black, sweep B
+            __syncthreads();
+            store(k);
+        }
+    }
+}
+
+template <typename T, int TX, int TY>
+static void rbgs2_launch(int n, double h, const T *f, const T *uin, T *uout, int kchunk, const T *uc, hipStream_t s)
+{
+    const int m = n - 2;
+    dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, (m + kchunk - 1) / kchunk);
+    if (uc)
+        hipLaunchKernelGGL((rbgs2_zmarch<T, TX, TY, true>), grid, dim3(TX * TY), 0, s, uin, uout, f, n, T(h * h), kchunk,
+                           uc, (n + 1) / 2);
+    else
+        hipLaunchKernelGGL((rbgs2_zmarch<T, TX, TY, false>), grid, dim3(TX * TY), 0, s, uin, uout, f, n, T(h * h),
+                           kchunk, uc, (n + 1) / 2);
+}
+
+template <typename T>
+void launch_rbgs2(int n, double h, const T *f, const T *uin, T *uout, const T *uc, hipStream_t s)
+{
+    const SmootherShape sh = rbgs2_shape<T>(n);
+    const int kc = sh.kchunk > 0 ? sh.kchunk : n;
+    switch (sh.variant) {
+    case 0: rbgs2_launch<T, 32, 8>(n, h, f, uin, uout, kc, uc, s); break;
+    default: rbgs2_launch<T, 64, 4>(n, h, f, uin, uout, kc, uc, s); break;
+    }
+}
+
 // Launch shapes of the smoother: tile variant and z-chunk per level size.
 // Defaults below; the autotuner (tune.hip) overwrites entries after timing them.
 static SmootherShape g_rbgs_shape[2][11];   // [fp32?][log2(n-1)]
@@ -176,6 +353,28 @@ static void rbgs_defaults()
             else sh = {1, 64};
         }
     g_rbgs_init = true;
+}
+
+static SmootherShape g_rbgs2_shape[2][11];
+
+template <typename T>
+SmootherShape &rbgs2_shape(int n)
+{
+    static bool init = false;
+    if (!init) {
+        for (int t = 0; t < 2; ++t)
+            for (int J = 0; J <= 10; ++J) {
+                SmootherShape &sh = g_rbgs2_shape[t][J];
+                if (J <= 5) sh = {0, 8};
+                else if (J == 6) sh = {0, 16};
+                else if (J == 7) sh = {1, 16};
+                else sh = {1, 64};
+            }
+        init = true;
+    }
+    int J = 0;
+    while ((1 << J) < n - 1) ++J;
+    return g_rbgs2_shape[sizeof(T) == 4 ? 1 : 0][J > 10 ? 10 : J];
 }
 
 template <typename T>
@@ -285,22 +484,6 @@ void launch_restrict(int nf, const T *src, T *dst, hipStream_t s)
 }
 
 // ------------------------------------------------------------- prolongation
-
-// Trilinear value of the coarse field at fine node (i,j,k): an even fine index
-// sits on coarse node i/2, an odd one halfway between (i-1)/2 and (i+1)/2.
-template <typename T>
-__device__ __forceinline__ T prolong_at(int nc, const T *__restrict__ uc, int i, int j, int k)
-{
-    const int ia = i >> 1, ib = (i + 1) >> 1, ja = j >> 1, jb = (j + 1) >> 1, ka = k >> 1, kb = (k + 1) >> 1;
-    const T wia = (i & 1) ? T(0.5) : T(1), wib = (i & 1) ? T(0.5) : T(0);
-    const T wja = (j & 1) ? T(0.5) : T(1), wjb = (j & 1) ? T(0.5) : T(0);
-    const T wka = (k & 1) ? T(0.5) : T(1), wkb = (k & 1) ? T(0.5) : T(0);
-    const T xa = wia * uc[id3(nc, ia, ja, ka)] + wib * uc[id3(nc, ib, ja, ka)];
-    const T xb = wia * uc[id3(nc, ia, jb, ka)] + wib * uc[id3(nc, ib, jb, ka)];
-    const T xc = wia * uc[id3(nc, ia, ja, kb)] + wib * uc[id3(nc, ib, ja, kb)];
-    const T xd = wia * uc[id3(nc, ia, jb, kb)] + wib * uc[id3(nc, ib, jb, kb)];
-    return wka * (wja * xa + wjb * xb) + wkb * (wja * xc + wjb * xd);
-}
 
 template <typename T, bool ADD>
 __global__ void prolong_k(int nc, const T *__restrict__ uc, T *__restrict__ uf)
@@ -587,9 +770,23 @@ coarse_tail_k(int top, T L, const T *__restrict__ fg, T *__restrict__ ug, int np
     __shared__ T Rs[kTailTopN * kTailTopN * kTailTopN];
     TailLDS<T> t{U, F, Rs, L, npre, npost};
     const int n = t.nl(top), cnt = n * n * n;
-    for (int p = threadIdx.x; p < cnt; p += blockDim.x) {
-        t.u(top)[p] = ug[p];
-        t.fr(top)[p] = fg[p];
+    constexpr int PER = (kTailTopN * kTailTopN * kTailTopN + kTailThreads - 1) / kTailThreads;
+    T ru[PER], rf[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int p = threadIdx.x + r * kTailThreads;
+        if (p < cnt) {
+            ru[r] = ug[p];
+            rf[r] = fg[p];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int p = threadIdx.x + r * kTailThreads;
+        if (p < cnt) {
+            t.u(top)[p] = ru[r];
+            t.fr(top)[p] = rf[r];
+        }
     }
     __syncthreads();
     if (mode == 1) {
@@ -700,6 +897,8 @@ void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial
     template void launch_rbgs<T>(int, double, const T *, const T *, T *, hipStream_t);                         \
     template void launch_rbgs_shape<T>(int, double, const T *, const T *, T *, SmootherShape, hipStream_t);     \
     template SmootherShape &rbgs_shape<T>(int);                                                                 \
+    template SmootherShape &rbgs2_shape<T>(int);                                                                \
+    template void launch_rbgs2<T>(int, double, const T *, const T *, T *, const T *, hipStream_t);             \
     template void launch_residual_restrict<T>(int, double, const T *, const T *, T *, T *, T *, hipStream_t);  \
     template void launch_restrict<T>(int, const T *, T *, hipStream_t);                                        \
     template void launch_prolong_add<T>(int, const T *, T *, hipStream_t);                                     \

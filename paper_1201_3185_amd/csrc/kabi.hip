@@ -35,6 +35,15 @@ qumond_status qumond_k_rbgs_sweep(int32_t n, double h, const double *f, const do
     return kcheck("qumond_k_rbgs_sweep");
 }
 
+qumond_status qumond_k_rbgs_double_sweep(int32_t n, double h, const double *f, const double *u_in, double *u_out,
+                                         const double *uc, void *stream)
+{
+    if (!good_n(n) || !(h > 0.0) || !f || !u_in || !u_out || u_in == u_out)
+        return kfail("qumond_k_rbgs_double_sweep: bad argument");
+    qm::launch_rbgs2<double>(n, h, f, u_in, u_out, uc, (hipStream_t)stream);
+    return kcheck("qumond_k_rbgs_double_sweep");
+}
+
 qumond_status qumond_k_residual_restrict(int32_t nf, double h, const double *f, const double *u, double *fc,
                                          double *uc0, double *uc1, void *stream)
 {

@@ -76,6 +76,7 @@ struct Multigrid {
     size_t bytes = 0;
     std::vector<void *> owned;
     SmootherProfile prof;
+    bool fused = true;   // two sweeps per launch where possible
 
     hipError_t alloc(void **p, size_t b)
     {
@@ -133,18 +134,41 @@ struct Multigrid {
         for (int l = 1; l <= J; ++l) lv[l].cur = 0;
     }
 
-    void smooth(int l, int ns)
+    void time_begin(hipEvent_t *e0, hipEvent_t *e1, double bytes)
+    {
+        if (!prof.on) return;
+        prof.record_pair(s, e0, e1);
+        prof.bytes.push_back(bytes);
+        (void)hipEventRecord(*e0, s);
+    }
+    void time_end(hipEvent_t e1)
+    {
+        if (prof.on) (void)hipEventRecord(e1, s);
+    }
+
+    // ns red-black sweeps on level l; pairs of sweeps run as one fused launch.
+    // With uc != NULL the correction u += P uc is applied before the first sweep.
+    void smooth(int l, int ns, const T *uc = nullptr)
     {
         Level<T> &v = lv[l];
-        for (int i = 0; i < ns; ++i) {
+        const double pts = (double)v.n * v.n * v.n;
+        if (uc && ns < 2) {
+            launch_prolong_add<T>(lv[l - 1].n, uc, v.u[v.cur], s);
+            uc = nullptr;
+        }
+        while (ns > 0) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (prof.on) {
-                prof.record_pair(s, &e0, &e1);
-                prof.bytes.push_back(3.0 * sizeof(T) * (double)v.n * v.n * v.n);
-                (void)hipEventRecord(e0, s);
+            time_begin(&e0, &e1, 3.0 * sizeof(T) * pts);
+            if (ns >= 2 && fused) {
+                launch_rbgs2<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], uc, s);
+                ns -= 2;
+            } else {
+                if (uc) launch_prolong_add<T>(lv[l - 1].n, uc, v.u[v.cur], s);
+                launch_rbgs<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], s);
+                ns -= 1;
             }
-            launch_rbgs<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], s);
-            if (prof.on) (void)hipEventRecord(e1, s);
+            uc = nullptr;
+            time_end(e1);
             v.cur ^= 1;
         }
     }
@@ -158,8 +182,7 @@ struct Multigrid {
         launch_residual_restrict<T>(v.n, v.h, v.f, v.u[v.cur], c.f, c.u[c.cur], c.u[1 - c.cur], s);
         if (l - 1 == lt) launch_coarse_tail<T>(lt, L, c.f, c.u[c.cur], npre, npost, 1, 0, 1, s);
         else vcycle(l - 1);
-        launch_prolong_add<T>(c.n, c.u[c.cur], v.u[v.cur], s);
-        smooth(l, npost);
+        smooth(l, npost, c.u[c.cur]);
     }
 
     // The finest-level cycle used after the FMG schedule.

@@ -24,7 +24,7 @@ bool good_n(int n) { return n >= 5 && n <= 1025 && qm::log2_exact(n - 1) >= 2; }
 const int kChunks[] = {4, 8, 16, 32, 64, 128, 0};
 
 template <typename T>
-qumond_status tune_one(int n, int reps, hipStream_t s, double &best_us)
+qumond_status tune_one(int n, int reps, hipStream_t s, double &best_us, bool fused)
 {
     const size_t N = (size_t)n * n * n;
     T *f = nullptr, *u0 = nullptr, *u1 = nullptr;
@@ -41,18 +41,28 @@ qumond_status tune_one(int n, int reps, hipStream_t s, double &best_us)
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
-    qm::SmootherShape best = qm::rbgs_shape<T>(n);
+    qm::SmootherShape &slot = fused ? qm::rbgs2_shape<T>(n) : qm::rbgs_shape<T>(n);
+    qm::SmootherShape best = slot;
     best_us = 1e30;
     const double h = 1.0 / (n - 1);
-    for (int v = 0; v < qm::kSmootherVariants; ++v)
+    auto run = [&](const T *a, T *b, const qm::SmootherShape &sh) {
+        if (fused) {
+            slot = sh;
+            qm::launch_rbgs2<T>(n, h, f, a, b, nullptr, s);
+        } else {
+            qm::launch_rbgs_shape<T>(n, h, f, a, b, sh, s);
+        }
+    };
+    const int nvar = fused ? 2 : qm::kSmootherVariants;
+    for (int v = 0; v < nvar; ++v)
         for (int kc : kChunks) {
             if (kc != 0 && kc >= n - 2) continue;
             const qm::SmootherShape sh{v, kc};
             std::vector<float> t;
-            qm::launch_rbgs_shape<T>(n, h, f, u0, u1, sh, s);   // warm-up
+            run(u0, u1, sh);   // warm-up
             for (int r = 0; r < reps; ++r) {
                 (void)hipEventRecord(e0, s);
-                qm::launch_rbgs_shape<T>(n, h, f, (r & 1) ? u1 : u0, (r & 1) ? u0 : u1, sh, s);
+                run((r & 1) ? u1 : u0, (r & 1) ? u0 : u1, sh);
                 (void)hipEventRecord(e1, s);
                 (void)hipEventSynchronize(e1);
                 float ms = 0.f;
@@ -66,7 +76,7 @@ qumond_status tune_one(int n, int reps, hipStream_t s, double &best_us)
                 best = sh;
             }
         }
-    qm::rbgs_shape<T>(n) = best;
+    slot = best;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipFree(f);
@@ -103,6 +113,24 @@ qumond_status qumond_tune_get(int32_t n, int32_t fp32, int32_t *variant, int32_t
     return QUMOND_OK;
 }
 
+qumond_status qumond_tune_set_fused(int32_t n, int32_t fp32, int32_t variant, int32_t kchunk)
+{
+    if (!good_n(n) || variant < 0 || variant > 1 || kchunk < 0) return tfail("qumond_tune_set_fused: bad argument");
+    qm::SmootherShape sh{variant, kchunk};
+    if (fp32) qm::rbgs2_shape<float>(n) = sh;
+    else qm::rbgs2_shape<double>(n) = sh;
+    return QUMOND_OK;
+}
+
+qumond_status qumond_tune_get_fused(int32_t n, int32_t fp32, int32_t *variant, int32_t *kchunk)
+{
+    if (!good_n(n) || !variant || !kchunk) return tfail("qumond_tune_get_fused: bad argument");
+    const qm::SmootherShape sh = fp32 ? qm::rbgs2_shape<float>(n) : qm::rbgs2_shape<double>(n);
+    *variant = sh.variant;
+    *kchunk = sh.kchunk;
+    return QUMOND_OK;
+}
+
 qumond_status qumond_k_rbgs_sweep_shape(int32_t n, double h, const double *f, const double *u_in, double *u_out,
                                         int32_t variant, int32_t kchunk, void *stream)
 {
@@ -127,18 +155,22 @@ qumond_status qumond_autotune(int32_t n_max, int32_t both, int32_t reps, const c
     bool first = true;
     for (int J = 5; (1 << J) + 1 <= n_max; ++J) {
         const int n = (1 << J) + 1;
-        for (int prec = 0; prec < (both ? 2 : 1); ++prec) {
-            double us = 0.0;
-            qumond_status st = prec ? tune_one<float>(n, reps, s, us) : tune_one<double>(n, reps, s, us);
-            if (st != QUMOND_OK) return st;
-            if (!prec && best_us) best_us[J] = us;
-            const qm::SmootherShape sh = prec ? qm::rbgs_shape<float>(n) : qm::rbgs_shape<double>(n);
-            char buf[160];
-            std::snprintf(buf, sizeof buf, "%s{\"n\": %d, \"fp32\": %d, \"variant\": %d, \"kchunk\": %d, \"us\": %.3f}",
-                          first ? "" : ", ", n, prec, sh.variant, sh.kchunk, us);
-            js += buf;
-            first = false;
-        }
+        for (int prec = 0; prec < (both ? 2 : 1); ++prec)
+            for (int fz = 0; fz < 2; ++fz) {
+                double us = 0.0;
+                qumond_status st =
+                    prec ? tune_one<float>(n, reps, s, us, fz != 0) : tune_one<double>(n, reps, s, us, fz != 0);
+                if (st != QUMOND_OK) return st;
+                if (!prec && fz && best_us) best_us[J] = us;
+                const qm::SmootherShape sh = fz ? (prec ? qm::rbgs2_shape<float>(n) : qm::rbgs2_shape<double>(n))
+                                                : (prec ? qm::rbgs_shape<float>(n) : qm::rbgs_shape<double>(n));
+                char buf[200];
+                std::snprintf(buf, sizeof buf,
+                              "%s{\"n\": %d, \"fp32\": %d, \"fused\": %d, \"variant\": %d, \"kchunk\": %d, \"us\": %.3f}",
+                              first ? "" : ", ", n, prec, fz, sh.variant, sh.kchunk, us);
+                js += buf;
+                first = false;
+            }
     }
     js += "]}\n";
     if (json_path) {
@@ -163,10 +195,12 @@ qumond_status qumond_tune_load(const char *json_path)
     size_t pos = 0;
     int loaded = 0;
     while ((pos = txt.find("{\"n\":", pos)) != std::string::npos) {
-        int n = 0, fp32 = 0, variant = 0, kchunk = 0;
-        if (std::sscanf(txt.c_str() + pos, "{\"n\": %d, \"fp32\": %d, \"variant\": %d, \"kchunk\": %d", &n, &fp32,
-                        &variant, &kchunk) == 4) {
-            if (qumond_tune_set(n, fp32, variant, kchunk) != QUMOND_OK) return QUMOND_ERR_INVALID;
+        int n = 0, fp32 = 0, fz = 0, variant = 0, kchunk = 0;
+        if (std::sscanf(txt.c_str() + pos, "{\"n\": %d, \"fp32\": %d, \"fused\": %d, \"variant\": %d, \"kchunk\": %d",
+                        &n, &fp32, &fz, &variant, &kchunk) == 5) {
+            const qumond_status st = fz ? qumond_tune_set_fused(n, fp32, variant, kchunk)
+                                        : qumond_tune_set(n, fp32, variant, kchunk);
+            if (st != QUMOND_OK) return QUMOND_ERR_INVALID;
             ++loaded;
         }
         ++pos;

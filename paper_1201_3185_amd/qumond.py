@@ -75,6 +75,7 @@ _SIGNATURES = {
     "qumond_status_string": (ctypes.c_char_p, [_I32]),
     "qumond_last_error": (ctypes.c_char_p, []),
     "qumond_k_rbgs_sweep": (_I32, [_I32, _D, _P, _P, _P, _P]),
+    "qumond_k_rbgs_double_sweep": (_I32, [_I32, _D, _P, _P, _P, _P, _P]),
     "qumond_k_residual_restrict": (_I32, [_I32, _D, _P, _P, _P, _P, _P, _P]),
     "qumond_k_restrict": (_I32, [_I32, _P, _P, _P]),
     "qumond_k_prolong_add": (_I32, [_I32, _P, _P, _P]),
@@ -87,6 +88,8 @@ _SIGNATURES = {
     "qumond_k_vcycles": (_I32, [_I32, _D, _P, _P, _I32, _I32, _I32, ctypes.POINTER(_D), _P]),
     "qumond_tune_set": (_I32, [_I32, _I32, _I32, _I32]),
     "qumond_tune_get": (_I32, [_I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "qumond_tune_set_fused": (_I32, [_I32, _I32, _I32, _I32]),
+    "qumond_tune_get_fused": (_I32, [_I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "qumond_k_rbgs_sweep_shape": (_I32, [_I32, _D, _P, _P, _P, _I32, _I32, _P]),
     "qumond_autotune": (_I32, [_I32, _I32, _I32, ctypes.c_char_p, ctypes.POINTER(_D), _P]),
     "qumond_tune_load": (_I32, [ctypes.c_char_p]),
@@ -298,6 +301,11 @@ def k_rbgs_sweep(f, u_in, u_out, h):
     check(lib().qumond_k_rbgs_sweep(n, float(h), _ptr(f), _ptr(u_in), _ptr(u_out), _s()), "qumond_k_rbgs_sweep")
 
 
+def k_rbgs_double_sweep(f, u_in, u_out, h, uc=None):
+    check(lib().qumond_k_rbgs_double_sweep(u_in.shape[0], float(h), _ptr(f), _ptr(u_in), _ptr(u_out), _ptr(uc), _s()),
+          "qumond_k_rbgs_double_sweep")
+
+
 def k_residual_restrict(f, u, h, fc, uc0, uc1=None):
     check(lib().qumond_k_residual_restrict(u.shape[0], float(h), _ptr(f), _ptr(u), _ptr(fc), _ptr(uc0), _ptr(uc1),
                                            _s()), "qumond_k_residual_restrict")
@@ -356,6 +364,17 @@ def tune_set(n, variant, kchunk, fp32=False):
 def tune_get(n, fp32=False):
     v, k = ctypes.c_int32(0), ctypes.c_int32(0)
     check(lib().qumond_tune_get(int(n), int(bool(fp32)), ctypes.byref(v), ctypes.byref(k)), "qumond_tune_get")
+    return int(v.value), int(k.value)
+
+
+def tune_set_fused(n, variant, kchunk, fp32=False):
+    check(lib().qumond_tune_set_fused(int(n), int(bool(fp32)), int(variant), int(kchunk)), "qumond_tune_set_fused")
+
+
+def tune_get_fused(n, fp32=False):
+    v, k = ctypes.c_int32(0), ctypes.c_int32(0)
+    check(lib().qumond_tune_get_fused(int(n), int(bool(fp32)), ctypes.byref(v), ctypes.byref(k)),
+          "qumond_tune_get_fused")
     return int(v.value), int(k.value)
 
 

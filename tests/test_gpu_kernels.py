@@ -253,3 +253,41 @@ def test_autotune_installs_a_table(tmp_path):
     Q.tune_set(65, *before)
     Q.tune_load(str(tmp_path / "t.json"))
     assert Q.tune_get(65) in [(v, k) for v in Q.SMOOTHER_VARIANTS for k in (4, 8, 16, 32, 64, 128, 0)]
+
+
+@pytest.mark.parametrize("n", [5, 9, 17, 33, 65, 129, 257])
+def test_double_sweep_equals_two_sweeps_bitwise(n):
+    """The fused two-sweep kernel (four stages of one z-march) gives the same
+    bits as two single sweeps, and with a coarse correction the same bits as
+    prolong-add followed by two sweeps; both agree with the oracle."""
+    L = 6.0
+    h = L / (n - 1)
+    f, u = rand_state(n, 900 + n)
+    fd = dev(f)
+    a, b = dev(u), dev(u)
+    Q.k_rbgs_sweep(fd, a, b, h)
+    c = dev(u)
+    Q.k_rbgs_sweep(fd, b, c, h)
+    two = host(c)
+    out = dev(u)
+    Q.k_rbgs_double_sweep(fd, dev(u), out, h)
+    assert np.array_equal(host(out), two)
+    ref = u.copy()
+    O.rbgs_sweep(f, ref, h)
+    O.rbgs_sweep(f, ref, h)
+    assert rel(two, ref) < 1e-13
+    nc = (n + 1) // 2
+    uc = np.random.default_rng(n).standard_normal((nc,) * 3)
+    ucd = dev(uc)
+    p = dev(u)
+    Q.k_prolong_add(ucd, p)
+    q, r = dev(u), dev(u)
+    Q.k_rbgs_sweep(fd, p, q, h)
+    Q.k_rbgs_sweep(fd, q, r, h)
+    out = dev(u)
+    Q.k_rbgs_double_sweep(fd, dev(u), out, h, uc=ucd)
+    assert np.array_equal(host(out), host(r))
+    ref = O.prolong_add(uc, u.copy())
+    O.rbgs_sweep(f, ref, h)
+    O.rbgs_sweep(f, ref, h)
+    assert rel(host(out), ref) < 1e-13
