@@ -3,7 +3,9 @@
 
 One step is one pass of the whole path over one synthetic galaxy already
 resident in HBM: CIC deposit -> Newtonian FMG -> Eq. 2 source -> QUMOND FMG ->
-force gather at every particle, all through the C ABI of libqumond.so.
+force gather at every particle, all through the C ABI of libqumond.so
+(qumond_deposit, qumond_solve -- which overlaps the QUMOND chain of box b with
+the Newtonian solve of box b+1 -- and qumond_gather_forces).
 
 Workload: two-component exponential disk (stars Md = 5e10 Msun, Rd = 3 kpc,
 sech^2 height 0.3 kpc; gas Mg = 1e10 Msun, Rg = 6 kpc, height 0.15 kpc),
@@ -83,9 +85,7 @@ def main():
 
     def step():
         ctx.deposit(x, y, z, m, M, count_outside=False)
-        infos["newton"] = ctx.solve_newton()
-        ctx.mond_source()
-        infos["mond"] = ctx.solve_mond()
+        infos["newton"], infos["mond"] = ctx.solve()   # source + both FMG chains, overlapped
         return ctx.gather_forces(x, y, z, 1, with_box=False)
 
     log(f"warmup {args.warmup}")

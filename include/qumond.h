@@ -162,6 +162,16 @@ qumond_status qumond_mond_source(qumond_ctx *ctx);
  * the cycles FMG would have used plus max_vcycles.  Synchronises. */
 qumond_status qumond_solve_mond(qumond_ctx *ctx, const void *guess, int32_t guess_kind, qumond_solve_info *info);
 
+/* Steps 2-4 in one call with the two chains overlapped: the Newtonian solve
+ * of box b+1 runs concurrently with the source and QUMOND solve of box b (the
+ * QUMOND chain needs only box b's Phi_N and its own coarser box).  The
+ * Newtonian chain runs on the context's stream, the QUMOND chain on a second
+ * stream of default priority that the context creates on first use, driven by
+ * a worker thread.  Results equal qumond_solve_newton + qumond_mond_source +
+ * qumond_solve_mond bit for bit; on return the context's stream is ordered
+ * after all of it.  Either info (host) may be NULL.  Synchronises. */
+qumond_status qumond_solve(qumond_ctx *ctx, qumond_solve_info *info_newton, qumond_solve_info *info_mond);
+
 /* Accelerations -grad Phi (which = 0: Phi_N, 1: Phi) at np points.  Gravity
  * at nodes by central differences (one-sided second order on box faces),
  * weighted to the point with the cloud-in-cell weights.  Box choice (Sec. 3.1):

@@ -39,7 +39,9 @@ qumond_status qumond_k_rbgs_sweep_shape(int32_t n, double h, const double *f, co
 /* Time all shapes of both smoother kernels for n = 33, 65, ..., n_max (and
  * both precisions if both != 0), install the fastest; json_path (host
  * string, optional) receives the table.  best_us (host, optional, 11 entries)
- * gets the FP64 time of one fused two-sweep launch indexed by log2(n-1). */
+ * gets the FP64 time of one fused two-sweep launch indexed by log2(n-1).
+ * For each size it also records whether the multigrid should use the fused
+ * launch (faster than two single sweeps) or single sweeps. */
 qumond_status qumond_autotune(int32_t n_max, int32_t both, int32_t reps, const char *json_path, double *best_us,
                               void *stream);
 qumond_status qumond_tune_load(const char *json_path);

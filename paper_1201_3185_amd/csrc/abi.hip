@@ -2,11 +2,15 @@
 // per-context grids of every nested box, the call-order state machine, and the
 // box-by-box chaining of Sec. 2 (outer Dirichlet value, then each inner box's
 // boundary interpolated from the coarser box's converged solution).
+#include <atomic>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 
 #include "../../include/qumond.h"
 #include "common.h"
@@ -54,6 +58,13 @@ struct qumond_ctx {
     unsigned long long *d_count = nullptr;
     unsigned long long *h_count = nullptr;  // pinned
     unsigned long long *dep_scratch = nullptr;
+    // second solve chain (QUMOND potential) for qumond_solve, created on first use
+    bool chain2 = false;
+    hipStream_t s2 = nullptr;
+    qm::Multigrid<double> mg2;
+    double *scratch2 = nullptr;
+    hipEvent_t ev_newton[QUMOND_MAX_BOX] = {};
+    hipEvent_t ev_done = nullptr;
     std::vector<void *> owned;
     int64_t bytes = 0;
 
@@ -140,6 +151,14 @@ qumond_status qumond_destroy(qumond_ctx *ctx)
 {
     if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
     (void)hipStreamSynchronize(ctx->s);
+    if (ctx->chain2) {
+        (void)hipStreamSynchronize(ctx->s2);
+        ctx->mg2.release();
+        for (hipEvent_t e : ctx->ev_newton)
+            if (e) (void)hipEventDestroy(e);
+        if (ctx->ev_done) (void)hipEventDestroy(ctx->ev_done);
+        (void)hipStreamDestroy(ctx->s2);
+    }
     ctx->mg.release();
     for (void *p : ctx->owned) (void)hipFree(p);
     if (ctx->h_count) (void)hipHostFree(ctx->h_count);
@@ -203,6 +222,7 @@ qumond_status qumond_profile_enable(qumond_ctx *ctx, int32_t on)
 {
     if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
     ctx->mg.prof.on = on != 0;
+    ctx->mg2.prof.on = on != 0;
     return QUMOND_OK;
 }
 
@@ -211,23 +231,29 @@ qumond_status qumond_profile_read(qumond_ctx *ctx, qumond_kernel_stats *out)
     if (!ctx || !out) return fail(QUMOND_ERR_INVALID, "NULL argument");
     hipError_t e = hipStreamSynchronize(ctx->s);
     if (e != hipSuccess) return hip_fail(e, "qumond_profile_read");
-    qm::SmootherProfile &p = ctx->mg.prof;
-    out->launches = (int64_t)p.used;
+    if (ctx->chain2 && (e = hipStreamSynchronize(ctx->s2)) != hipSuccess) return hip_fail(e, "qumond_profile_read");
+    out->launches = 0;
     out->total_ms = 0.0;
     out->alg_bytes = 0.0;
-    for (size_t i = 0; i < p.used; ++i) {
-        float ms = 0.0f;
-        if ((e = hipEventElapsedTime(&ms, p.ev[2 * i], p.ev[2 * i + 1])) != hipSuccess)
-            return hip_fail(e, "qumond_profile_read: elapsed");
-        out->total_ms += ms;
-        out->alg_bytes += p.bytes[i];
+    for (qm::SmootherProfile *p : {&ctx->mg.prof, &ctx->mg2.prof}) {
+        out->launches += (int64_t)p->used;
+        for (size_t i = 0; i < p->used; ++i) {
+            float ms = 0.0f;
+            if ((e = hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1])) != hipSuccess)
+                return hip_fail(e, "qumond_profile_read: elapsed");
+            out->total_ms += ms;
+            out->alg_bytes += p->bytes[i];
+        }
+        p->used = 0;
+        p->bytes.clear();
     }
-    p.used = 0;
-    p.bytes.clear();
     return QUMOND_OK;
 }
 
-int64_t qumond_device_bytes(const qumond_ctx *ctx) { return ctx ? ctx->bytes + (int64_t)ctx->mg.bytes : 0; }
+int64_t qumond_device_bytes(const qumond_ctx *ctx)
+{
+    return ctx ? ctx->bytes + (int64_t)ctx->mg.bytes + (int64_t)ctx->mg2.bytes : 0;
+}
 
 static int fixed_shift_for(double total_mass)
 {
@@ -287,51 +313,72 @@ qumond_status qumond_deposit(qumond_ctx *ctx, const double *x, const double *y, 
     return QUMOND_OK;
 }
 
-// FMG chain over the boxes for one of the two potentials.
-static qumond_status solve_chain(qumond_ctx *ctx, bool mond, qumond_solve_info *info)
+// The solve resources of one chain: hierarchy, stream and ping-pong partner.
+struct Chain {
+    qm::Multigrid<double> *mg;
+    hipStream_t s;
+    double *scratch;
+};
+
+static void info_clear(qumond_solve_info *info, int nbox)
+{
+    if (!info) return;
+    std::memset(info, 0, sizeof(*info));
+    info->nbox = nbox;
+}
+
+// One box of one potential: Dirichlet values (outer value for box 0, the
+// coarser box's solution otherwise), FMG, then V-cycles under the stopping test.
+static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int b, qumond_solve_info *info, bool &ok)
 {
     const qumond_config &c = ctx->cfg;
     const double GM = c.G * ctx->total_mass;
-    bool all_ok = true;
+    Box &B = ctx->box[b];
+    double *u = mond ? B.phi : B.phin;
+    double *f = mond ? B.S : B.f;
+    if (b == 0) {
+        const int mode = c.outer_bc == QUMOND_BC_ZERO ? 0 : (mond ? 2 : 1);
+        qm::launch_bc_outer(ctx->n, B.L, mode, GM, c.a0, u, ch.scratch, ch.s);
+    } else {
+        const double *uc = mond ? ctx->box[b - 1].phi : ctx->box[b - 1].phin;
+        qm::launch_bc_from_coarse(ctx->n, uc, u, ch.scratch, ch.s);
+    }
+    ch.mg->bind(B.L, u, ch.scratch, f);
+    ch.mg->fmg(c.ncycle_fmg);
+    double rr = 0.0;
+    hipError_t e = ch.mg->relres(rr);
+    if (e != hipSuccess) return hip_fail(e, "solve: FMG");
+    const double rr0 = rr;
+    int extra = 0;
+    while (c.tol_rel > 0.0 && rr > c.tol_rel && extra < c.max_vcycles) {
+        ch.mg->finest_cycle();
+        ++extra;
+        if ((e = ch.mg->relres(rr)) != hipSuccess) return hip_fail(e, "solve: V-cycle");
+    }
+    ch.mg->finish();
+    ok = !(c.tol_rel > 0.0 && !(rr <= c.tol_rel));
     if (info) {
-        std::memset(info, 0, sizeof(*info));
-        info->nbox = c.nbox;
+        info->vcycles[b] = extra;
+        info->relres0[b] = rr0;
+        info->relres[b] = rr;
+        info->converged[b] = ok ? 1 : 0;
     }
-    for (int b = 0; b < c.nbox; ++b) {
-        Box &B = ctx->box[b];
-        double *u = mond ? B.phi : B.phin;
-        double *f = mond ? B.S : B.f;
-        if (b == 0) {
-            const int mode = c.outer_bc == QUMOND_BC_ZERO ? 0 : (mond ? 2 : 1);
-            qm::launch_bc_outer(ctx->n, B.L, mode, GM, c.a0, u, ctx->scratch, ctx->s);
-        } else {
-            const double *uc = mond ? ctx->box[b - 1].phi : ctx->box[b - 1].phin;
-            qm::launch_bc_from_coarse(ctx->n, uc, u, ctx->scratch, ctx->s);
-        }
-        ctx->mg.bind(B.L, u, ctx->scratch, f);
-        ctx->mg.fmg(c.ncycle_fmg);
-        double rr = 0.0;
-        hipError_t e = ctx->mg.relres(rr);
-        if (e != hipSuccess) return hip_fail(e, "solve: FMG");
-        const double rr0 = rr;
-        int extra = 0;
-        while (c.tol_rel > 0.0 && rr > c.tol_rel && extra < c.max_vcycles) {
-            ctx->mg.finest_cycle();
-            ++extra;
-            if ((e = ctx->mg.relres(rr)) != hipSuccess) return hip_fail(e, "solve: V-cycle");
-        }
-        ctx->mg.finish();
-        const bool ok = !(c.tol_rel > 0.0 && !(rr <= c.tol_rel));
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "solve: launch");
+    return QUMOND_OK;
+}
+
+// FMG chain over the boxes for one of the two potentials.
+static qumond_status solve_chain(qumond_ctx *ctx, bool mond, qumond_solve_info *info)
+{
+    info_clear(info, ctx->cfg.nbox);
+    const Chain ch{&ctx->mg, ctx->s, ctx->scratch};
+    bool all_ok = true;
+    for (int b = 0; b < ctx->cfg.nbox; ++b) {
+        bool ok = true;
+        qumond_status st = solve_box(ctx, ch, mond, b, info, ok);
+        if (st != QUMOND_OK) return st;
         all_ok = all_ok && ok;
-        if (info) {
-            info->vcycles[b] = extra;
-            info->relres0[b] = rr0;
-            info->relres[b] = rr;
-            info->converged[b] = ok ? 1 : 0;
-        }
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "solve: launch");
     if (!all_ok) return fail(QUMOND_ERR_NOT_CONVERGED, "relative residual above tol_rel after max_vcycles");
     return QUMOND_OK;
 }
@@ -368,6 +415,102 @@ qumond_status qumond_solve_mond(qumond_ctx *ctx, const void *guess, int32_t gues
     qumond_status st = solve_chain(ctx, true, info);
     if (st == QUMOND_OK || st == QUMOND_ERR_NOT_CONVERGED) ctx->stage = ST_MOND;
     return st;
+}
+
+// Steps 2-4 with the two chains overlapped: the Newtonian chain runs on the
+// context's stream in the calling thread; the QUMOND chain runs on a second
+// stream in a worker thread, box b starting (source, then solve) as soon as the
+// Newtonian solve of box b has completed on the device.  Same kernels, same
+// schedules: the fields equal those of the three separate calls bit for bit.
+static qumond_status ensure_chain2(qumond_ctx *ctx)
+{
+    if (ctx->chain2) return QUMOND_OK;
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&ctx->s2, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "qumond_solve: stream");
+    if ((e = ctx->mg2.init(ctx->n, ctx->cfg.npre, ctx->cfg.npost, ctx->s2)) != hipSuccess ||
+        (e = ctx->alloc((void **)&ctx->scratch2, ctx->N * sizeof(double))) != hipSuccess)
+        return hip_fail(e, "qumond_solve: allocation");
+    for (int b = 0; b < ctx->cfg.nbox; ++b)
+        if ((e = hipEventCreateWithFlags(&ctx->ev_newton[b], hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "qumond_solve: event");
+    if ((e = hipEventCreateWithFlags(&ctx->ev_done, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "qumond_solve: event");
+    ctx->mg2.prof.on = ctx->mg.prof.on;
+    ctx->chain2 = true;
+    return QUMOND_OK;
+}
+
+qumond_status qumond_solve(qumond_ctx *ctx, qumond_solve_info *info_newton, qumond_solve_info *info_mond)
+{
+    if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
+    if (ctx->stage < ST_DEPOSITED) return fail(QUMOND_ERR_STATE, "qumond_solve before qumond_deposit");
+    qumond_status st = ensure_chain2(ctx);
+    if (st != QUMOND_OK) return st;
+    const int nbox = ctx->cfg.nbox;
+    info_clear(info_newton, nbox);
+    info_clear(info_mond, nbox);
+    hipError_t e;
+    // the second stream must see everything already queued on the first (the deposit)
+    if ((e = hipEventRecord(ctx->ev_done, ctx->s)) != hipSuccess || (e = hipStreamWaitEvent(ctx->s2, ctx->ev_done, 0)) != hipSuccess)
+        return hip_fail(e, "qumond_solve: order");
+    std::mutex mu;
+    std::condition_variable cv;
+    int newton_done = 0;
+    bool abort = false;
+    qumond_status st_m = QUMOND_OK;
+    std::string err_m;
+    bool ok_m = true;
+    std::thread worker([&]() {
+        const Chain ch{&ctx->mg2, ctx->s2, ctx->scratch2};
+        for (int b = 0; b < nbox; ++b) {
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [&] { return newton_done > b || abort; });
+                if (newton_done <= b) return;   // the Newtonian chain failed
+            }
+            hipError_t we = hipStreamWaitEvent(ctx->s2, ctx->ev_newton[b], 0);
+            if (we != hipSuccess) {
+                st_m = hip_fail(we, "qumond_solve: wait");
+                err_m = g_last_error;
+                return;
+            }
+            qm::launch_mond_source(ctx->n, ctx->box[b].h, ctx->cfg.a0, ctx->box[b].phin, ctx->box[b].S, ctx->s2);
+            bool ok = true;
+            st_m = solve_box(ctx, ch, true, b, info_mond, ok);
+            if (st_m != QUMOND_OK) {
+                err_m = g_last_error;
+                return;
+            }
+            ok_m = ok_m && ok;
+        }
+    });
+    const Chain ch{&ctx->mg, ctx->s, ctx->scratch};
+    bool ok_n = true;
+    qumond_status st_n = QUMOND_OK;
+    for (int b = 0; b < nbox; ++b) {
+        bool ok = true;
+        st_n = solve_box(ctx, ch, false, b, info_newton, ok);
+        if (st_n == QUMOND_OK && (e = hipEventRecord(ctx->ev_newton[b], ctx->s)) != hipSuccess)
+            st_n = hip_fail(e, "qumond_solve: record");
+        if (st_n != QUMOND_OK) break;
+        ok_n = ok_n && ok;
+        std::lock_guard<std::mutex> lk(mu);
+        newton_done = b + 1;
+        cv.notify_all();
+    }
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (st_n != QUMOND_OK) abort = true;
+        cv.notify_all();
+    }
+    worker.join();
+    if (st_n != QUMOND_OK) return st_n;
+    if (st_m != QUMOND_OK) return fail(st_m, err_m);
+    // later work on the context's stream (the gather) must see the QUMOND chain
+    if ((e = hipEventRecord(ctx->ev_done, ctx->s2)) != hipSuccess || (e = hipStreamWaitEvent(ctx->s, ctx->ev_done, 0)) != hipSuccess)
+        return hip_fail(e, "qumond_solve: join");
+    ctx->stage = ST_MOND;
+    if (!ok_n || !ok_m) return fail(QUMOND_ERR_NOT_CONVERGED, "relative residual above tol_rel after max_vcycles");
+    return QUMOND_OK;
 }
 
 static qm::GatherArgs gather_args(const qumond_ctx *ctx, int which)

@@ -64,6 +64,9 @@ template <typename T> SmootherShape &rbgs_shape(int n);   // the table entry use
 template <typename T> void launch_rbgs2(int n, double h, const T *f, const T *uin, T *uout, const T *uc,
                                        hipStream_t s);
 template <typename T> SmootherShape &rbgs2_shape(int n);
+// Whether the multigrid uses the fused kernel on a level of n points per side
+// (set by the autotuner from measured times; n <= 65 by default).
+template <typename T> int &use_fused(int n);
 template <typename T> void launch_residual_restrict(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1,
                                                    hipStream_t s);
 template <typename T> void launch_restrict(int nf, const T *src, T *dst, hipStream_t s);

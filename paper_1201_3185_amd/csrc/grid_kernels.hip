@@ -356,6 +356,15 @@ static void rbgs_defaults()
 }
 
 static SmootherShape g_rbgs2_shape[2][11];
+static int g_use_fused[2][11] = {{1, 1, 1, 1, 1, 1, 1, 0, 0, 0, 0}, {1, 1, 1, 1, 1, 1, 1, 0, 0, 0, 0}};
+
+template <typename T>
+int &use_fused(int n)
+{
+    int J = 0;
+    while ((1 << J) < n - 1) ++J;
+    return g_use_fused[sizeof(T) == 4 ? 1 : 0][J > 10 ? 10 : J];
+}
 
 template <typename T>
 SmootherShape &rbgs2_shape(int n)
@@ -898,6 +907,7 @@ void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial
     template void launch_rbgs_shape<T>(int, double, const T *, const T *, T *, SmootherShape, hipStream_t);     \
     template SmootherShape &rbgs_shape<T>(int);                                                                 \
     template SmootherShape &rbgs2_shape<T>(int);                                                                \
+    template int &use_fused<T>(int);                                                                            \
     template void launch_rbgs2<T>(int, double, const T *, const T *, T *, const T *, hipStream_t);             \
     template void launch_residual_restrict<T>(int, double, const T *, const T *, T *, T *, T *, hipStream_t);  \
     template void launch_restrict<T>(int, const T *, T *, hipStream_t);                                        \

@@ -159,7 +159,7 @@ struct Multigrid {
         while (ns > 0) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             time_begin(&e0, &e1, 3.0 * sizeof(T) * pts);
-            if (ns >= 2 && fused) {
+            if (ns >= 2 && fused && use_fused<T>(v.n)) {
                 launch_rbgs2<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], uc, s);
                 ns -= 2;
             } else {

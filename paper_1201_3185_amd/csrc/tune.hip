@@ -155,7 +155,8 @@ qumond_status qumond_autotune(int32_t n_max, int32_t both, int32_t reps, const c
     bool first = true;
     for (int J = 5; (1 << J) + 1 <= n_max; ++J) {
         const int n = (1 << J) + 1;
-        for (int prec = 0; prec < (both ? 2 : 1); ++prec)
+        for (int prec = 0; prec < (both ? 2 : 1); ++prec) {
+            double us_pair[2] = {0.0, 0.0};
             for (int fz = 0; fz < 2; ++fz) {
                 double us = 0.0;
                 qumond_status st =
@@ -170,7 +171,16 @@ qumond_status qumond_autotune(int32_t n_max, int32_t both, int32_t reps, const c
                               first ? "" : ", ", n, prec, fz, sh.variant, sh.kchunk, us);
                 js += buf;
                 first = false;
+                us_pair[fz] = us;
             }
+            // fused launch (two sweeps) against two single sweeps
+            const int fuse = us_pair[1] < 2.0 * us_pair[0] ? 1 : 0;
+            if (prec) qm::use_fused<float>(n) = fuse;
+            else qm::use_fused<double>(n) = fuse;
+            char buf[96];
+            std::snprintf(buf, sizeof buf, ", {\"n\": %d, \"fp32\": %d, \"use_fused\": %d}", n, prec, fuse);
+            js += buf;
+        }
     }
     js += "]}\n";
     if (json_path) {
@@ -202,6 +212,16 @@ qumond_status qumond_tune_load(const char *json_path)
                                         : qumond_tune_set(n, fp32, variant, kchunk);
             if (st != QUMOND_OK) return QUMOND_ERR_INVALID;
             ++loaded;
+        }
+        ++pos;
+    }
+    pos = 0;
+    while ((pos = txt.find("{\"n\":", pos)) != std::string::npos) {
+        int n = 0, fp32 = 0, fuse = 0;
+        if (std::sscanf(txt.c_str() + pos, "{\"n\": %d, \"fp32\": %d, \"use_fused\": %d", &n, &fp32, &fuse) == 3 &&
+            good_n(n)) {
+            if (fp32) qm::use_fused<float>(n) = fuse ? 1 : 0;
+            else qm::use_fused<double>(n) = fuse ? 1 : 0;
         }
         ++pos;
     }

@@ -64,6 +64,7 @@ _SIGNATURES = {
     "qumond_deposit": (_I32, [_P, _P, _P, _P, _P, _I64, _D, ctypes.POINTER(_I64)]),
     "qumond_solve_newton": (_I32, [_P, ctypes.POINTER(qumond_solve_info)]),
     "qumond_mond_source": (_I32, [_P]),
+    "qumond_solve": (_I32, [_P, ctypes.POINTER(qumond_solve_info), ctypes.POINTER(qumond_solve_info)]),
     "qumond_solve_mond": (_I32, [_P, _P, _I32, ctypes.POINTER(qumond_solve_info)]),
     "qumond_gather_forces": (_I32, [_P, _P, _P, _P, _I64, _I32, _P, _P, _P, _P]),
     "qumond_rotation_curve": (_I32, [_P, _P, _I32, _I32, _I32, _P]),
@@ -249,6 +250,13 @@ class Context:
         check(lib().qumond_solve_mond(self._h, _ptr(guess), kind, ctypes.byref(info)), "qumond_solve_mond",
               allow=(QUMOND_ERR_NOT_CONVERGED,) if allow_not_converged else ())
         return info.as_dict()
+
+    def solve(self, allow_not_converged: bool = False):
+        """Steps 2-4 with the Newtonian and QUMOND chains overlapped on two streams."""
+        a, b = qumond_solve_info(), qumond_solve_info()
+        check(lib().qumond_solve(self._h, ctypes.byref(a), ctypes.byref(b)), "qumond_solve",
+              allow=(QUMOND_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+        return a.as_dict(), b.as_dict()
 
     def gather_forces(self, x, y, z, which: int = 1, with_box: bool = True):
         np_ = x.numel()
