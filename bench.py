@@ -50,6 +50,56 @@ def smoother_traffic(per_launch_alg_bytes):
     return rec.get("bytes_per_launch")
 
 
+def mixed_vs_fp64(Q, synth, torch, np, dev, reps=3):
+    """The metric's second part on the 513^3 workload (two-component disk,
+    1e7 particles, 120 kpc box, monopole boundary): wall time of deposit +
+    both solves (to 1e-6 FP64 relative residual) + gather, plain FP64 against
+    FP32 multigrid with FP64 refinement, and the 513^3 smoother's HBM roofline
+    from the FP64 run's smoother launches."""
+    n, L = 513, 120.0
+    log("513^3 workload: 1e7 particles")
+    p = synth.two_component_disk(10_000_000, synth.seed_for(3))
+    x, y, z, m = dev(p.x), dev(p.y), dev(p.z), dev(p.m)
+    out = {"workload": "two-component disk, 1e7 particles, one 513^3 box of 120 kpc, solves to 1e-6"}
+    fields = {}
+    Q.autotune(n_max=n, both=True, reps=3)
+    for name, prec in (("fp64", Q.QUMOND_FP64), ("mixed", Q.QUMOND_MIXED)):
+        ctx = Q.Context(Q.Config(n=n, box_side=[L], precision=prec, tol_rel=1e-6))
+        times = []
+        for r in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.deposit(x, y, z, m, p.total_mass, count_outside=False)
+            i_n, i_m = ctx.solve()
+            ctx.gather_forces(x, y, z, 1, with_box=False)
+            torch.cuda.synchronize()
+            if r:
+                times.append((time.perf_counter() - t0) * 1e3)
+        rec = {"ms": float(np.median(times)), "relres_newton": i_n["relres"][0], "relres_mond": i_m["relres"][0],
+               "cycles_newton": i_n["vcycles"][0], "cycles_mond": i_m["vcycles"][0]}
+        if name == "fp64":
+            ctx.profile_enable(True)
+            ctx.deposit(x, y, z, m, p.total_mass, count_outside=False)
+            ctx.solve()
+            st = ctx.profile_read()
+            ctx.profile_enable(False)
+            gbs = st["alg_bytes"] / (st["total_ms"] * 1e-3) / 1e9
+            rec["smoother_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                        "launches": st["launches"],
+                                        "avg_launch_us": round(1e3 * st["total_ms"] / max(st["launches"], 1), 2)}
+        fields[name] = ctx.get_field(0, Q.FIELD_PHI).cpu().numpy()
+        out[name] = rec
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    out["mixed_err_vs_fp64"] = float(np.abs(fields["mixed"] - fields["fp64"]).max() / np.abs(fields["fp64"]).max())
+    out["speedup_mixed"] = out["fp64"]["ms"] / out["mixed"]["ms"]
+    log(f"513^3: fp64 {out['fp64']['ms']:.1f} ms, mixed {out['mixed']['ms']:.1f} ms, "
+        f"err {out['mixed_err_vs_fp64']:.2e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,6 +107,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile-pass", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the 513^3 FP64-vs-mixed comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a design "
@@ -120,6 +171,10 @@ def main():
                 "avg_launch_us": round(avg_ms * 1e3, 3), "alg_bytes_per_launch": per_launch}
         log(f"smoother: {st['launches']} launches, avg {avg_ms * 1e3:.2f} us, {achieved:.1f} GB/s algorithmic")
 
+    mixed = None
+    if not args.no_mixed:
+        mixed = mixed_vs_fp64(Q, synth, torch, np, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -144,6 +199,7 @@ def main():
                    "npre": 2, "npost": 2, "precision": "fp64"},
         "vcycles_after_fmg": {"newton": infos["newton"]["vcycles"], "mond": infos["mond"]["vcycles"]},
         "smoother_shapes": shapes,
+        "mixed_vs_fp64_513": mixed,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

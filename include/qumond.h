@@ -59,6 +59,12 @@ typedef enum {
     QUMOND_ERR_RANGE = 6           /* value out of the representable range (e.g. fixed-point overflow) */
 } qumond_status;
 
+/* QUMOND_MIXED: each solve starts from an FP32 FMG (FP32 smoothing,
+ * restriction and prolongation; the 3^3 solve in FP64) and then repeats FP64
+ * residual correction: r = f - A u in FP64, scaled by its RMS s, one FP32
+ * V-cycle for A e = r/s with zero boundary values, u += s e in FP64, until the
+ * FP64 relative residual meets tol_rel (max_vcycles refinements at most).
+ * The Eq. 2 source stays FP64. */
 typedef enum { QUMOND_FP64 = 0, QUMOND_MIXED = 1 } qumond_precision;
 typedef enum { QUMOND_BC_ZERO = 0, QUMOND_BC_MONOPOLE = 1 } qumond_outer_bc;
 

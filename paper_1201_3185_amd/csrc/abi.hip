@@ -34,6 +34,15 @@ qumond_status hip_fail(hipError_t e, const char *where)
 
 enum Stage { ST_CREATED = 0, ST_DEPOSITED = 1, ST_NEWTON = 2, ST_SOURCE = 3, ST_MOND = 4 };
 
+// FP32 multigrid of the mixed-precision solve: hierarchy, the finest level's
+// two buffers (initial FMG iterate, then corrections) and its right-hand side
+// (FP32 rhs for the FMG, then the scaled FP64 residual).
+struct Mixed {
+    qm::Multigrid<float> mg;
+    float *a[2] = {nullptr, nullptr};
+    float *r = nullptr;
+};
+
 struct Box {
     double L = 0, h = 0;
     long long *q = nullptr;
@@ -52,6 +61,7 @@ struct qumond_ctx {
     Box box[QUMOND_MAX_BOX];
     double *scratch = nullptr;           // finest-size ping-pong partner
     qm::Multigrid<double> mg;
+    Mixed mix, mix2;   // FP32 hierarchies of the two chains (mixed precision only)
     double total_mass = 0.0;
     int shift = 0;
     int stage = ST_CREATED;
@@ -160,6 +170,8 @@ qumond_status qumond_destroy(qumond_ctx *ctx)
         (void)hipStreamDestroy(ctx->s2);
     }
     ctx->mg.release();
+    ctx->mix.mg.release();
+    ctx->mix2.mg.release();
     for (void *p : ctx->owned) (void)hipFree(p);
     if (ctx->h_count) (void)hipHostFree(ctx->h_count);
     delete ctx;
@@ -197,7 +209,12 @@ qumond_status qumond_create(const qumond_config *cfg, void *hip_stream, qumond_c
         (e = c->alloc((void **)&c->dep_scratch, qm::deposit_scratch_bytes(cfg->nbox))) != hipSuccess ||
         (e = c->alloc((void **)&c->d_count, sizeof(unsigned long long))) != hipSuccess ||
         (e = hipHostMalloc((void **)&c->h_count, sizeof(unsigned long long), hipHostMallocDefault)) != hipSuccess ||
-        (e = c->mg.init(c->n, cfg->npre, cfg->npost, c->s)) != hipSuccess) {
+        (e = c->mg.init(c->n, cfg->npre, cfg->npost, c->s)) != hipSuccess ||
+        (cfg->precision == QUMOND_MIXED &&
+         ((e = c->mix.mg.init(c->n, cfg->npre, cfg->npost, c->s)) != hipSuccess ||
+          (e = c->alloc((void **)&c->mix.a[0], c->N * sizeof(float))) != hipSuccess ||
+          (e = c->alloc((void **)&c->mix.a[1], c->N * sizeof(float))) != hipSuccess ||
+          (e = c->alloc((void **)&c->mix.r, c->N * sizeof(float))) != hipSuccess))) {
         qumond_status r = hip_fail(e, "qumond_create: allocation");
         qumond_destroy(c);
         return r;
@@ -252,7 +269,9 @@ qumond_status qumond_profile_read(qumond_ctx *ctx, qumond_kernel_stats *out)
 
 int64_t qumond_device_bytes(const qumond_ctx *ctx)
 {
-    return ctx ? ctx->bytes + (int64_t)ctx->mg.bytes + (int64_t)ctx->mg2.bytes : 0;
+    return ctx ? ctx->bytes + (int64_t)ctx->mg.bytes + (int64_t)ctx->mg2.bytes + (int64_t)ctx->mix.mg.bytes +
+                     (int64_t)ctx->mix2.mg.bytes
+               : 0;
 }
 
 static int fixed_shift_for(double total_mass)
@@ -318,6 +337,7 @@ struct Chain {
     qm::Multigrid<double> *mg;
     hipStream_t s;
     double *scratch;
+    Mixed *mix;
 };
 
 static void info_clear(qumond_solve_info *info, int nbox)
@@ -344,18 +364,45 @@ static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int 
         qm::launch_bc_from_coarse(ctx->n, uc, u, ch.scratch, ch.s);
     }
     ch.mg->bind(B.L, u, ch.scratch, f);
-    ch.mg->fmg(c.ncycle_fmg);
-    double rr = 0.0;
-    hipError_t e = ch.mg->relres(rr);
-    if (e != hipSuccess) return hip_fail(e, "solve: FMG");
-    const double rr0 = rr;
+    double rr = 0.0, rr0 = 0.0;
     int extra = 0;
-    while (c.tol_rel > 0.0 && rr > c.tol_rel && extra < c.max_vcycles) {
-        ch.mg->finest_cycle();
-        ++extra;
-        if ((e = ch.mg->relres(rr)) != hipSuccess) return hip_fail(e, "solve: V-cycle");
+    hipError_t e;
+    if (c.precision == QUMOND_MIXED) {
+        // FP32 FMG seeds the FP64 iterate ...
+        Mixed &X = *ch.mix;
+        qm::launch_narrow(f, X.r, ctx->N, ch.s);
+        qm::launch_narrow_boundary(ctx->n, u, X.a[0], X.a[1], ch.s);
+        X.mg.bind(B.L, X.a[0], X.a[1], X.r);
+        X.mg.fmg(c.ncycle_fmg);
+        qm::launch_widen_interior(ctx->n, X.mg.result(), u, ch.s);
+        if ((e = ch.mg->relres(rr)) != hipSuccess) return hip_fail(e, "solve: FP32 FMG");
+        rr0 = rr;
+        // ... then FP64 residual correction with FP32 V-cycles (zero boundary values)
+        const double nint = (double)(ctx->n - 2) * (ctx->n - 2) * (ctx->n - 2);
+        while (c.tol_rel > 0.0 && rr > c.tol_rel && extra < c.max_vcycles) {
+            const double rms = std::sqrt(ch.mg->last_r2 / nint);
+            const double scale = rms > 0.0 && std::isfinite(rms) ? rms : 1.0;
+            qm::launch_resid_to_f32(ctx->n, B.h, 1.0 / scale, f, u, X.r, ch.s);
+            qm::launch_fill<float>(X.a[0], ctx->N, 0.0f, ch.s);
+            qm::launch_fill<float>(X.a[1], ctx->N, 0.0f, ch.s);
+            X.mg.bind(B.L, X.a[0], X.a[1], X.r);
+            X.mg.finest_cycle();
+            qm::launch_correct(ctx->n, scale, X.mg.result(), u, ch.s);
+            ++extra;
+            if ((e = ch.mg->relres(rr)) != hipSuccess) return hip_fail(e, "solve: refinement");
+        }
+        if (info) info->refine_iters[b] = extra;
+    } else {
+        ch.mg->fmg(c.ncycle_fmg);
+        if ((e = ch.mg->relres(rr)) != hipSuccess) return hip_fail(e, "solve: FMG");
+        rr0 = rr;
+        while (c.tol_rel > 0.0 && rr > c.tol_rel && extra < c.max_vcycles) {
+            ch.mg->finest_cycle();
+            ++extra;
+            if ((e = ch.mg->relres(rr)) != hipSuccess) return hip_fail(e, "solve: V-cycle");
+        }
+        ch.mg->finish();
     }
-    ch.mg->finish();
     ok = !(c.tol_rel > 0.0 && !(rr <= c.tol_rel));
     if (info) {
         info->vcycles[b] = extra;
@@ -371,7 +418,7 @@ static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int 
 static qumond_status solve_chain(qumond_ctx *ctx, bool mond, qumond_solve_info *info)
 {
     info_clear(info, ctx->cfg.nbox);
-    const Chain ch{&ctx->mg, ctx->s, ctx->scratch};
+    const Chain ch{&ctx->mg, ctx->s, ctx->scratch, &ctx->mix};
     bool all_ok = true;
     for (int b = 0; b < ctx->cfg.nbox; ++b) {
         bool ok = true;
@@ -430,6 +477,12 @@ static qumond_status ensure_chain2(qumond_ctx *ctx)
     if ((e = ctx->mg2.init(ctx->n, ctx->cfg.npre, ctx->cfg.npost, ctx->s2)) != hipSuccess ||
         (e = ctx->alloc((void **)&ctx->scratch2, ctx->N * sizeof(double))) != hipSuccess)
         return hip_fail(e, "qumond_solve: allocation");
+    if (ctx->cfg.precision == QUMOND_MIXED &&
+        ((e = ctx->mix2.mg.init(ctx->n, ctx->cfg.npre, ctx->cfg.npost, ctx->s2)) != hipSuccess ||
+         (e = ctx->alloc((void **)&ctx->mix2.a[0], ctx->N * sizeof(float))) != hipSuccess ||
+         (e = ctx->alloc((void **)&ctx->mix2.a[1], ctx->N * sizeof(float))) != hipSuccess ||
+         (e = ctx->alloc((void **)&ctx->mix2.r, ctx->N * sizeof(float))) != hipSuccess))
+        return hip_fail(e, "qumond_solve: allocation");
     for (int b = 0; b < ctx->cfg.nbox; ++b)
         if ((e = hipEventCreateWithFlags(&ctx->ev_newton[b], hipEventDisableTiming)) != hipSuccess)
             return hip_fail(e, "qumond_solve: event");
@@ -460,7 +513,7 @@ qumond_status qumond_solve(qumond_ctx *ctx, qumond_solve_info *info_newton, qumo
     std::string err_m;
     bool ok_m = true;
     std::thread worker([&]() {
-        const Chain ch{&ctx->mg2, ctx->s2, ctx->scratch2};
+        const Chain ch{&ctx->mg2, ctx->s2, ctx->scratch2, &ctx->mix2};
         for (int b = 0; b < nbox; ++b) {
             {
                 std::unique_lock<std::mutex> lk(mu);
@@ -483,7 +536,7 @@ qumond_status qumond_solve(qumond_ctx *ctx, qumond_solve_info *info_newton, qumo
             ok_m = ok_m && ok;
         }
     });
-    const Chain ch{&ctx->mg, ctx->s, ctx->scratch};
+    const Chain ch{&ctx->mg, ctx->s, ctx->scratch, &ctx->mix};
     bool ok_n = true;
     qumond_status st_n = QUMOND_OK;
     for (int b = 0; b < nbox; ++b) {

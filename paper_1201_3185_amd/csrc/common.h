@@ -87,6 +87,13 @@ template <typename T> void launch_resid_norms(int n, double h, const T *f, const
                                              hipStream_t s);
 constexpr int kNormBlocks = 512;
 
+// mixed precision (FP64 refinement around FP32 multigrid)
+void launch_narrow(const double *src, float *dst, size_t count, hipStream_t s);
+void launch_narrow_boundary(int n, const double *src, float *d0, float *d1, hipStream_t s);
+void launch_widen_interior(int n, const float *src, double *dst, hipStream_t s);
+void launch_resid_to_f32(int n, double h, double inv_s, const double *f, const double *u, float *r, hipStream_t s);
+void launch_correct(int n, double scale, const float *e, double *u, hipStream_t s);
+
 // ---- bc_kernels.hip
 // mode 0 zero, 1 Newtonian monopole -GM/r, 2 QUMOND monopole.
 void launch_bc_outer(int n, double L, int mode, double GM, double a0, double *u0, double *u1, hipStream_t s);

@@ -901,6 +901,101 @@ void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial
     hipLaunchKernelGGL(norms_final_k, dim3(1), dim3(256), 0, s, partial, kNormBlocks, out);
 }
 
+// ------------------------------------------------- mixed-precision helpers
+//
+// FP64 residual-correction refinement around FP32 multigrid: the FP64 iterate
+// is corrected by s e where e solves A e = r / s in FP32 (zero Dirichlet
+// values) and s is the RMS of the FP64 residual r = f - A u.
+
+__global__ void narrow_k(const double *__restrict__ src, float *__restrict__ dst, size_t count)
+{
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < count; t += (size_t)gridDim.x * blockDim.x)
+        dst[t] = (float)src[t];
+}
+
+__global__ void narrow_boundary_k(int n, const double *__restrict__ src, float *__restrict__ d0, float *__restrict__ d1)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 6 * n * n) return;
+    int i, j, k;
+    face_node(n, t, i, j, k);
+    const size_t p = id3(n, i, j, k);
+    const float v = (float)src[p];
+    d0[p] = v;
+    if (d1) d1[p] = v;
+}
+
+// u64 interior = (double) u32
+__global__ void widen_interior_k(int n, const float *__restrict__ src, double *__restrict__ dst)
+{
+    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = 1 + blockIdx.z * blockDim.z + threadIdx.z;
+    if (i > n - 2 || j > n - 2 || k > n - 2) return;
+    const size_t p = id3(n, i, j, k);
+    dst[p] = (double)src[p];
+}
+
+// r32 = (f - A_h u) / s in FP64, rounded to FP32, at interior nodes; 0 on the boundary
+__global__ void resid_to_f32_k(int n, double ih2, double inv_s, const double *__restrict__ f, const double *__restrict__ u,
+                               float *__restrict__ r)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (i >= n || j >= n || k >= n) return;
+    const size_t p = id3(n, i, j, k);
+    if (i == 0 || j == 0 || k == 0 || i == n - 1 || j == n - 1 || k == n - 1) {
+        r[p] = 0.0f;
+        return;
+    }
+    const size_t sy = (size_t)n, sz = (size_t)n * n;
+    const double lap = (u[p - 1] + u[p + 1] + u[p - sy] + u[p + sy] + u[p - sz] + u[p + sz] - 6.0 * u[p]) * ih2;
+    r[p] = (float)((f[p] - lap) * inv_s);
+}
+
+// u64 += s e32 at interior nodes
+__global__ void correct_k(int n, double s, const float *__restrict__ e, double *__restrict__ u)
+{
+    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = 1 + blockIdx.z * blockDim.z + threadIdx.z;
+    if (i > n - 2 || j > n - 2 || k > n - 2) return;
+    const size_t p = id3(n, i, j, k);
+    u[p] += s * (double)e[p];
+}
+
+void launch_narrow(const double *src, float *dst, size_t count, hipStream_t s)
+{
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(narrow_k, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, count);
+}
+
+void launch_narrow_boundary(int n, const double *src, float *d0, float *d1, hipStream_t s)
+{
+    const int cnt = 6 * n * n;
+    hipLaunchKernelGGL(narrow_boundary_k, dim3((cnt + 255) / 256), dim3(256), 0, s, n, src, d0, d1);
+}
+
+void launch_widen_interior(int n, const float *src, double *dst, hipStream_t s)
+{
+    dim3 blk(64, 2, 2);
+    hipLaunchKernelGGL(widen_interior_k, grid3(n - 2, blk), blk, 0, s, n, src, dst);
+}
+
+void launch_resid_to_f32(int n, double h, double inv_s, const double *f, const double *u, float *r, hipStream_t s)
+{
+    dim3 blk(64, 2, 2);
+    hipLaunchKernelGGL(resid_to_f32_k, grid3(n, blk), blk, 0, s, n, 1.0 / (h * h), inv_s, f, u, r);
+}
+
+void launch_correct(int n, double scale, const float *e, double *u, hipStream_t s)
+{
+    dim3 blk(64, 2, 2);
+    hipLaunchKernelGGL(correct_k, grid3(n - 2, blk), blk, 0, s, n, scale, e, u);
+}
+
 // -------------------------------------------------------- instantiations
 #define QM_INST(T)                                                                                              \
     template void launch_rbgs<T>(int, double, const T *, const T *, T *, hipStream_t);                         \

@@ -77,6 +77,7 @@ struct Multigrid {
     std::vector<void *> owned;
     SmootherProfile prof;
     bool fused = true;   // two sweeps per launch where possible
+    double last_r2 = 0.0;  // sum of squared residuals of the last relres()
 
     hipError_t alloc(void **p, size_t b)
     {
@@ -231,11 +232,14 @@ struct Multigrid {
         if (e != hipSuccess) return e;
         // ||f - A u|| / ||f||; a source-free box is measured against the
         // boundary-value contribution instead, and if that is 0 the residual is absolute.
+        last_r2 = host_norms[0];
         const double rn = std::sqrt(host_norms[0]), fn = std::sqrt(host_norms[1]), bn = std::sqrt(host_norms[2]);
         const double den = fn > 0.0 ? fn : bn;
         out = den > 0.0 ? rn / den : rn;
         return hipSuccess;
     }
+
+    T *result() { return lv[J].u[lv[J].cur]; }
 
     // Leave the result in u[0] of the finest level.
     void finish()
