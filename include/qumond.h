@@ -77,6 +77,10 @@ typedef enum {
 } qumond_field;
 
 typedef enum { QUMOND_GUESS_NONE = 0, QUMOND_GUESS_F64 = 1, QUMOND_GUESS_F32 = 2, QUMOND_GUESS_BF16 = 3 } qumond_guess_kind;
+/* OR-ed into guess_kind: never fall back to FMG (for measuring plain V-cycles
+ * from a given start); the solve then stops after ncycle_fmg + max_vcycles
+ * cycles at the latest. */
+#define QUMOND_GUESS_NO_FALLBACK 16
 
 typedef struct qumond_config {
     int32_t n;                          /* points per side, 2^J + 1, 5 <= n <= 1025 */

@@ -26,6 +26,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "qumond_oracle.c")
+_SRC_UNET = os.path.join(_HERE, "unet_oracle.c")
 _SO = os.path.join(_HERE, "_qumond_oracle.so")
 
 # Units: kpc, Msun, km/s.  G in kpc (km/s)^2 / Msun; a0 = 3.6 (km/s)^2/pc (Eq. 2).
@@ -35,11 +36,12 @@ A0_KPC = 3600.0
 
 def build(force: bool = False) -> str:
     """Compile the oracle shared object with gcc (no FMA contraction)."""
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_SO) or any(os.path.getmtime(_SO) < os.path.getmtime(f) for f in (_SRC, _SRC_UNET))
+    if force or stale:
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(
             ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c99",
-             "-D_DEFAULT_SOURCE", _SRC, "-o", tmp, "-lm"])
+             "-D_DEFAULT_SOURCE", _SRC, _SRC_UNET, "-o", tmp, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -73,6 +75,11 @@ def lib():
             "orc_vcycles": (d, [i, d, vp, vp, i, i, i]),
             "orc_mond_source": (None, [i, d, d, vp, vp]),
             "orc_gather": (None, [i, i, vp, vp, i64, vp, vp, vp, d, d, d, d, i, vp, vp, vp, vp]),
+            "orc_conv3d_fwd": (None, [i, i, vp, i, vp, vp, i, i, vp]),
+            "orc_conv3d_dgrad": (None, [i, i, i, vp, i, vp, vp]),
+            "orc_conv3d_wgrad": (None, [i, i, vp, i, vp, i, vp]),
+            "orc_upsample": (None, [i, i, vp, vp]),
+            "orc_upsample_adj": (None, [i, i, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -289,3 +296,51 @@ def run_pipeline(cfg: OracleConfig, x, y, z, m, total_mass: float) -> OracleResu
     res.S = [mond_source(p, Lb, cfg.a0) for p, Lb in zip(res.phin, cfg.box_side)]
     res.phi, res.info_mond = solve_chain(cfg, res.S, True, total_mass)
     return res
+
+
+# ------------------------------------------------------- network layers (O2)
+
+def conv3d_fwd(x, w, b=None, stride=1, relu=False):
+    """x: [n^3, cin] channel-last, w: [cout, 27, cin]; returns [n_out^3, cout]."""
+    x, w = _f64(x), _f64(w)
+    cout, _, cin = w.shape
+    nin = round(x.shape[0] ** (1 / 3))
+    nout = (nin - 1) // stride + 1
+    y = np.zeros((nout ** 3, cout))
+    bb = _f64(b) if b is not None else None
+    lib().orc_conv3d_fwd(nin, cin, _p(x), cout, _p(w), _p(bb) if bb is not None else None, stride, int(relu), _p(y))
+    return y
+
+
+def conv3d_dgrad(w, dy, nin, stride=1):
+    w, dy = _f64(w), _f64(dy)
+    cout, _, cin = w.shape
+    dx = np.zeros((nin ** 3, cin))
+    lib().orc_conv3d_dgrad(nin, cin, cout, _p(w), stride, _p(dy), _p(dx))
+    return dx
+
+
+def conv3d_wgrad(x, dy, cout, stride=1):
+    x, dy = _f64(x), _f64(dy)
+    nin = round(x.shape[0] ** (1 / 3))
+    cin = x.shape[1]
+    dw = np.zeros((cout, 27, cin))
+    lib().orc_conv3d_wgrad(nin, cin, _p(x), cout, _p(dy), stride, _p(dw))
+    return dw
+
+
+def upsample(xc, nc):
+    xc = _f64(xc)
+    ch = xc.shape[1]
+    nf = 2 * nc - 1
+    xf = np.zeros((nf ** 3, ch))
+    lib().orc_upsample(nc, ch, _p(xc), _p(xf))
+    return xf
+
+
+def upsample_adj(gf, nc):
+    gf = _f64(gf)
+    ch = gf.shape[1]
+    gc = np.zeros((nc ** 3, ch))
+    lib().orc_upsample_adj(nc, ch, _p(gf), _p(gc))
+    return gc

@@ -349,7 +349,8 @@ static void info_clear(qumond_solve_info *info, int nbox)
 
 // One box of one potential: Dirichlet values (outer value for box 0, the
 // coarser box's solution otherwise), FMG, then V-cycles under the stopping test.
-static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int b, qumond_solve_info *info, bool &ok)
+static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int b, qumond_solve_info *info, bool &ok,
+                               const void *guess = nullptr, int guess_kind = 0)
 {
     const qumond_config &c = ctx->cfg;
     const double GM = c.G * ctx->total_mass;
@@ -367,6 +368,50 @@ static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int 
     double rr = 0.0, rr0 = 0.0;
     int extra = 0;
     hipError_t e;
+    if (guess) {
+        // Seeded solve: V-cycles from the guess's interior.  The guess is
+        // rejected (FMG from zero instead) if it is not finite, if its relative
+        // residual exceeds 1, or if it needs more cycles than FMG plus max_vcycles.
+        const bool no_fallback = (guess_kind & QUMOND_GUESS_NO_FALLBACK) != 0;
+        const int kind = guess_kind & 3;
+        const size_t esz = kind == QUMOND_GUESS_F64 ? 8 : (kind == QUMOND_GUESS_F32 ? 4 : 2);
+        qm::launch_guess_interior(ctx->n, (const char *)guess + (size_t)b * ctx->N * esz, kind, u, ch.s);
+        if ((e = ch.mg->relres(rr)) != hipSuccess) return hip_fail(e, "solve: guess");
+        rr0 = rr;
+        bool accept = no_fallback || (std::isfinite(rr) && rr <= 1.0);
+        const int budget = c.ncycle_fmg + c.max_vcycles;
+        while (accept && c.tol_rel > 0.0 && rr > c.tol_rel && extra < budget) {
+            ch.mg->finest_cycle();
+            ++extra;
+            if ((e = ch.mg->relres(rr)) != hipSuccess) return hip_fail(e, "solve: V-cycle");
+            if (!std::isfinite(rr) && !no_fallback) accept = false;
+        }
+        if (no_fallback || (accept && !(c.tol_rel > 0.0 && rr > c.tol_rel))) {
+            ch.mg->finish();
+            ok = !(c.tol_rel > 0.0 && !(rr <= c.tol_rel));
+            if (info) {
+                info->vcycles[b] = extra;
+                info->relres0[b] = rr0;
+                info->relres[b] = rr;
+                info->converged[b] = ok ? 1 : 0;
+            }
+            if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "solve: launch");
+            return QUMOND_OK;
+        }
+        // fallback: FMG from zero with the same Dirichlet values
+        ch.mg->finish();
+        if (info) info->used_fallback = 1;
+        qm::launch_fill<double>(u, ctx->N, 0.0, ch.s);
+        if (b == 0) {
+            const int mode = c.outer_bc == QUMOND_BC_ZERO ? 0 : (mond ? 2 : 1);
+            qm::launch_bc_outer(ctx->n, B.L, mode, GM, c.a0, u, ch.scratch, ch.s);
+        } else {
+            const double *uc = mond ? ctx->box[b - 1].phi : ctx->box[b - 1].phin;
+            qm::launch_bc_from_coarse(ctx->n, uc, u, ch.scratch, ch.s);
+        }
+        ch.mg->bind(B.L, u, ch.scratch, f);
+        extra = 0;
+    }
     if (c.precision == QUMOND_MIXED) {
         // FP32 FMG seeds the FP64 iterate ...
         Mixed &X = *ch.mix;
@@ -415,14 +460,15 @@ static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int 
 }
 
 // FMG chain over the boxes for one of the two potentials.
-static qumond_status solve_chain(qumond_ctx *ctx, bool mond, qumond_solve_info *info)
+static qumond_status solve_chain(qumond_ctx *ctx, bool mond, qumond_solve_info *info, const void *guess = nullptr,
+                                 int guess_kind = 0)
 {
     info_clear(info, ctx->cfg.nbox);
     const Chain ch{&ctx->mg, ctx->s, ctx->scratch, &ctx->mix};
     bool all_ok = true;
     for (int b = 0; b < ctx->cfg.nbox; ++b) {
         bool ok = true;
-        qumond_status st = solve_box(ctx, ch, mond, b, info, ok);
+        qumond_status st = solve_box(ctx, ch, mond, b, info, ok, guess, guess_kind);
         if (st != QUMOND_OK) return st;
         all_ok = all_ok && ok;
     }
@@ -455,11 +501,11 @@ qumond_status qumond_solve_mond(qumond_ctx *ctx, const void *guess, int32_t gues
 {
     if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
     if (ctx->stage < ST_SOURCE) return fail(QUMOND_ERR_STATE, "qumond_solve_mond before qumond_mond_source");
-    if (guess_kind < QUMOND_GUESS_NONE || guess_kind > QUMOND_GUESS_BF16)
+    const int kind = guess_kind & ~QUMOND_GUESS_NO_FALLBACK;
+    if (kind < QUMOND_GUESS_NONE || kind > QUMOND_GUESS_BF16 || (guess_kind & ~(QUMOND_GUESS_NO_FALLBACK | 3)))
         return fail(QUMOND_ERR_INVALID, "unknown guess_kind");
-    if (guess_kind != QUMOND_GUESS_NONE && !guess) return fail(QUMOND_ERR_INVALID, "guess is NULL");
-    if (guess_kind != QUMOND_GUESS_NONE) return fail(QUMOND_ERR_INVALID, "initial guesses are not supported yet");
-    qumond_status st = solve_chain(ctx, true, info);
+    if (kind != QUMOND_GUESS_NONE && !guess) return fail(QUMOND_ERR_INVALID, "guess is NULL");
+    qumond_status st = solve_chain(ctx, true, info, kind == QUMOND_GUESS_NONE ? nullptr : guess, guess_kind);
     if (st == QUMOND_OK || st == QUMOND_ERR_NOT_CONVERGED) ctx->stage = ST_MOND;
     return st;
 }

@@ -94,6 +94,9 @@ void launch_widen_interior(int n, const float *src, double *dst, hipStream_t s);
 void launch_resid_to_f32(int n, double h, double inv_s, const double *f, const double *u, float *r, hipStream_t s);
 void launch_correct(int n, double scale, const float *e, double *u, hipStream_t s);
 
+// interior of u from an initial guess (kind 1: double, 2: float, 3: bf16)
+void launch_guess_interior(int n, const void *g, int kind, double *u, hipStream_t s);
+
 // ---- bc_kernels.hip
 // mode 0 zero, 1 Newtonian monopole -GM/r, 2 QUMOND monopole.
 void launch_bc_outer(int n, double L, int mode, double GM, double a0, double *u0, double *u1, hipStream_t s);

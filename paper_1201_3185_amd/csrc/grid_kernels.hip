@@ -996,6 +996,37 @@ void launch_correct(int n, double scale, const float *e, double *u, hipStream_t 
     hipLaunchKernelGGL(correct_k, grid3(n - 2, blk), blk, 0, s, n, scale, e, u);
 }
 
+// Interior of u (FP64) from an initial guess of storage type T (boundary kept).
+template <typename T>
+__global__ void guess_interior_k(int n, const T *__restrict__ g, double *__restrict__ u)
+{
+    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = 1 + blockIdx.z * blockDim.z + threadIdx.z;
+    if (i > n - 2 || j > n - 2 || k > n - 2) return;
+    const size_t p = id3(n, i, j, k);
+    u[p] = (double)(float)g[p];
+}
+
+template <>
+__global__ void guess_interior_k<double>(int n, const double *__restrict__ g, double *__restrict__ u)
+{
+    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = 1 + blockIdx.z * blockDim.z + threadIdx.z;
+    if (i > n - 2 || j > n - 2 || k > n - 2) return;
+    const size_t p = id3(n, i, j, k);
+    u[p] = g[p];
+}
+
+void launch_guess_interior(int n, const void *g, int kind, double *u, hipStream_t s)
+{
+    dim3 blk(64, 2, 2);
+    if (kind == 1) hipLaunchKernelGGL(guess_interior_k<double>, grid3(n - 2, blk), blk, 0, s, n, (const double *)g, u);
+    else if (kind == 2) hipLaunchKernelGGL(guess_interior_k<float>, grid3(n - 2, blk), blk, 0, s, n, (const float *)g, u);
+    else hipLaunchKernelGGL(guess_interior_k<__bf16>, grid3(n - 2, blk), blk, 0, s, n, (const __bf16 *)g, u);
+}
+
 // -------------------------------------------------------- instantiations
 #define QM_INST(T)                                                                                              \
     template void launch_rbgs<T>(int, double, const T *, const T *, T *, hipStream_t);                         \

@@ -25,6 +25,7 @@ QUMOND_FP64, QUMOND_MIXED = 0, 1
 QUMOND_BC_ZERO, QUMOND_BC_MONOPOLE = 0, 1
 FIELD_RHO_FIXED, FIELD_RHS, FIELD_PHI_N, FIELD_SOURCE, FIELD_PHI = range(5)
 GUESS_NONE, GUESS_F64, GUESS_F32, GUESS_BF16 = range(4)
+GUESS_NO_FALLBACK = 16
 
 
 class qumond_config(ctypes.Structure):
@@ -87,6 +88,18 @@ _SIGNATURES = {
     "qumond_k_fmg": (_I32, [_I32, _D, _P, _P, _I32, _I32, _I32, _I32, _D, ctypes.POINTER(_D),
                             ctypes.POINTER(_I32), _P]),
     "qumond_k_vcycles": (_I32, [_I32, _D, _P, _P, _I32, _I32, _I32, ctypes.POINTER(_D), _P]),
+    "qumond_unet_create": (_I32, [_I32, ctypes.c_uint64, _P, ctypes.POINTER(_P)]),
+    "qumond_unet_destroy": (_I32, [_P]),
+    "qumond_unet_param_count": (_I64, [_P]),
+    "qumond_unet_get_params": (_I32, [_P, _P]),
+    "qumond_unet_set_params": (_I32, [_P, _P]),
+    "qumond_unet_get_grads": (_I32, [_P, _P]),
+    "qumond_unet_prepare_sample": (_I32, [_P, _P, _P, _P, _D, _D, _D, _P, _P]),
+    "qumond_unet_train_step": (_I32, [_P, _P, _P, ctypes.c_float, ctypes.POINTER(_D)]),
+    "qumond_unet_infer": (_I32, [_P, _P, _P, _D, _D, _D, _P]),
+    "qumond_k_conv3d_fwd": (_I32, [_I32, _I32, _P, _I32, _P, _P, _I32, _I32, _P, _P]),
+    "qumond_k_conv3d_dgrad": (_I32, [_I32, _I32, _I32, _P, _I32, _P, _P, _P]),
+    "qumond_k_conv3d_wgrad": (_I32, [_I32, _I32, _P, _I32, _P, _I32, _P, _P]),
     "qumond_tune_set": (_I32, [_I32, _I32, _I32, _I32]),
     "qumond_tune_get": (_I32, [_I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "qumond_tune_set_fused": (_I32, [_I32, _I32, _I32, _I32]),
@@ -240,13 +253,16 @@ class Context:
     def mond_source(self):
         check(lib().qumond_mond_source(self._h), "qumond_mond_source")
 
-    def solve_mond(self, guess: Optional[torch.Tensor] = None, allow_not_converged: bool = False) -> dict:
+    def solve_mond(self, guess: Optional[torch.Tensor] = None, allow_not_converged: bool = False,
+                   no_fallback: bool = False) -> dict:
         info = qumond_solve_info()
         kind = GUESS_NONE
         if guess is not None:
             kind = {torch.float64: GUESS_F64, torch.float32: GUESS_F32, torch.bfloat16: GUESS_BF16}[guess.dtype]
             if guess.numel() != self.nbox * self.n ** 3:
                 raise ValueError("guess must hold nbox * n^3 values")
+            if no_fallback:
+                kind |= GUESS_NO_FALLBACK
         check(lib().qumond_solve_mond(self._h, _ptr(guess), kind, ctypes.byref(info)), "qumond_solve_mond",
               allow=(QUMOND_ERR_NOT_CONVERGED,) if allow_not_converged else ())
         return info.as_dict()
@@ -400,3 +416,95 @@ def autotune(n_max=513, both=True, reps=5, json_path=None):
 
 def tune_load(json_path):
     check(lib().qumond_tune_load(json_path.encode()), "qumond_tune_load")
+
+
+# ------------------------------------------------------------------ U-Net
+
+class UNet:
+    """The learned initial guess (include/qumond_unet.h): BF16 MFMA 3D U-Net."""
+
+    def __init__(self, n: int = 129, seed: int = 1201, stream: Optional[torch.cuda.Stream] = None):
+        self.n = n
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        check(lib().qumond_unet_create(int(n), ctypes.c_uint64(seed), ctypes.c_void_p(self.stream.cuda_stream),
+                                       ctypes.byref(h)), "qumond_unet_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().qumond_unet_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def param_count(self) -> int:
+        return int(lib().qumond_unet_param_count(self._h))
+
+    def get_params(self):
+        import numpy as np
+        out = np.zeros(self.param_count, dtype=np.float32)
+        check(lib().qumond_unet_get_params(self._h, out.ctypes.data_as(ctypes.c_void_p)), "qumond_unet_get_params")
+        return out
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.param_count:
+            raise ValueError("parameter count mismatch")
+        check(lib().qumond_unet_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p)), "qumond_unet_set_params")
+
+    def get_grads(self):
+        import numpy as np
+        out = np.zeros(self.param_count, dtype=np.float32)
+        check(lib().qumond_unet_get_grads(self._h, out.ctypes.data_as(ctypes.c_void_p)), "qumond_unet_get_grads")
+        return out
+
+    def prepare_sample(self, phin, S, phi, h, c_phin, c_out, x=None, t=None):
+        N = self.n ** 3
+        x = torch.empty(N * 2, dtype=torch.bfloat16, device="cuda") if x is None else x
+        t = torch.empty(N, dtype=torch.float32, device="cuda") if t is None else t
+        check(lib().qumond_unet_prepare_sample(self._h, _ptr(phin), _ptr(S), _ptr(phi), float(h), float(c_phin),
+                                               float(c_out), _ptr(x), _ptr(t)), "qumond_unet_prepare_sample")
+        return x, t
+
+    def train_step(self, x, target, lr: float = 1e-3, want_loss: bool = True):
+        loss = ctypes.c_double(0.0)
+        check(lib().qumond_unet_train_step(self._h, _ptr(x), _ptr(target), ctypes.c_float(lr),
+                                           ctypes.byref(loss) if want_loss else None), "qumond_unet_train_step")
+        return float(loss.value) if want_loss else None
+
+    def infer(self, phin, S, h, c_phin, c_out, out: Optional[torch.Tensor] = None):
+        if out is None:
+            out = torch.empty(self.n ** 3, dtype=torch.float64, device="cuda")
+        check(lib().qumond_unet_infer(self._h, _ptr(phin), _ptr(S), float(h), float(c_phin), float(c_out),
+                                      _ptr(out)), "qumond_unet_infer")
+        return out
+
+
+def k_conv3d_fwd(x, n_in, cin, w, cout, bias=None, stride=1, relu=False):
+    n_out = (n_in + 1) // 2 if stride == 2 else n_in
+    y = torch.empty(n_out ** 3 * cout, dtype=torch.bfloat16, device="cuda")
+    check(lib().qumond_k_conv3d_fwd(n_in, cin, _ptr(x), cout, _ptr(w), _ptr(bias), stride, int(relu), _ptr(y), _s()),
+          "qumond_k_conv3d_fwd")
+    return y
+
+
+def k_conv3d_dgrad(n_in, cin, cout, w, dy, stride=1):
+    dx = torch.empty(n_in ** 3 * cin, dtype=torch.bfloat16, device="cuda")
+    check(lib().qumond_k_conv3d_dgrad(n_in, cin, cout, _ptr(w), stride, _ptr(dy), _ptr(dx), _s()),
+          "qumond_k_conv3d_dgrad")
+    return dx
+
+
+def k_conv3d_wgrad(n_in, cin, x, cout, dy, stride=1):
+    kpad = (27 * cin + 31) // 32 * 32
+    dw = torch.empty(cout * kpad, dtype=torch.float32, device="cuda")
+    check(lib().qumond_k_conv3d_wgrad(n_in, cin, _ptr(x), cout, _ptr(dy), stride, _ptr(dw), _s()),
+          "qumond_k_conv3d_wgrad")
+    return dw

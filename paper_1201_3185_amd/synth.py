@@ -16,6 +16,7 @@ All draws use NumPy's PCG64 with seed 31851201 + 100 * config + realisation.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -131,3 +132,42 @@ def fit_grid(count: int = 64, config: int = 4, n_choices=(129, 257)) -> list:
                               dist=float(v[r, 3]), n_particles=int(round(np.exp(v[r, 4]))),
                               n_grid=int(grids[r]), seed=seed_for(config, r + 1)))
     return out
+
+
+# ------------------------------------------------ device-side realisations
+
+def _exp_radii_torch(u, Rd):
+    """Invert 1 - (1 + x) e^-x = u by safeguarded Newton steps (x = R/Rd)."""
+    import torch
+    lo = torch.zeros_like(u)
+    hi = torch.full_like(u, 60.0)
+    x = torch.sqrt(2.0 * u).clamp(max=50.0)
+    for _ in range(40):
+        F = 1.0 - (1.0 + x) * torch.exp(-x) - u
+        lo = torch.where(F < 0, x, lo)
+        hi = torch.where(F >= 0, x, hi)
+        dF = x * torch.exp(-x)
+        xn = x - F / torch.clamp(dF, min=1e-300)
+        bad = (xn <= lo) | (xn >= hi) | ~torch.isfinite(xn)
+        x = torch.where(bad, 0.5 * (lo + hi), xn)
+    return Rd * x
+
+
+def two_component_disk_torch(n, seed, Md=5e10, Rd=3.0, zd=0.3, Mg=1e10, Rg=6.0, zg=0.15, device="cuda"):
+    """The two-component disk of two_component_disk, drawn on the GPU with
+    torch's Philox generator (a different random stream, same distributions);
+    returns (x, y, z, m) float64 device tensors."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    ns = n // 2
+    parts = []
+    for cnt, R0, M, z0 in ((ns, Rd, Md, zd), (n - ns, Rg, Mg, zg)):
+        u = torch.rand(cnt, generator=gen, device=device, dtype=torch.float64)
+        R = _exp_radii_torch(u, R0)
+        phi = 2.0 * math.pi * torch.rand(cnt, generator=gen, device=device, dtype=torch.float64)
+        w = torch.rand(cnt, generator=gen, device=device, dtype=torch.float64).clamp(1e-300, 1.0 - 1e-16)
+        z = z0 * torch.atanh(2.0 * w - 1.0) if z0 > 0 else torch.zeros_like(w)
+        parts.append((R * torch.cos(phi), R * torch.sin(phi), z, torch.full((cnt,), M / cnt, dtype=torch.float64,
+                                                                           device=device)))
+    return tuple(torch.cat([p[i] for p in parts]).contiguous() for i in range(4))

@@ -1,0 +1,288 @@
+"""The learned initial guess on the GPU: network kernels against the O2 oracle,
+whole-network gradients, training, the seeded QUMOND solve with its FMG
+fallback, and what the trained network gains.
+
+Layer tolerances: operands are rounded to BF16 on both sides, the oracle
+accumulates in FP64 and the kernels in FP32 (MFMA); a BF16 output carries a
+rounding of at most 2^-8 of its value, so outputs are compared to
+0.45% of their value plus 1e-4 of the largest; FP32 weight gradients to 1e-4 of
+the largest entry.  The whole-network gradients are compared per layer in the
+L2 norm at 3%, since each side rounds the BF16 intermediates it stores and a
+rounding can flip where the FP32 and FP64 sums straddle a BF16 boundary.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1201_3185_amd import learned
+from paper_1201_3185_amd import qumond as Q
+from paper_1201_3185_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+CKPT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1201_3185_amd", "weights",
+                    "unet129.npy")
+
+
+def bf16(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16)
+
+
+def bf16_round(a):
+    return bf16(a).float().numpy().astype(np.float64)
+
+
+def kpad_of(cin):
+    return (27 * cin + 31) // 32 * 32
+
+
+def pack_w(w):
+    """[cout][27][cin] -> [cout][kpad] with kk = tap cin + ci."""
+    cout, _, cin = w.shape
+    out = np.zeros((cout, kpad_of(cin)))
+    out[:, :27 * cin] = w.reshape(cout, 27 * cin)
+    return out
+
+
+def check_bf16(got, ref):
+    tol = 0.0045 * np.abs(ref) + 1e-4 * np.abs(ref).max()
+    assert np.all(np.abs(got - ref) <= tol), np.abs(got - ref).max()
+
+
+CASES = [(9, 8, 16, 1, False), (9, 16, 32, 2, True), (17, 32, 64, 1, True), (9, 48, 16, 1, True),
+         (9, 96, 32, 1, False), (9, 128, 64, 1, True), (17, 64, 64, 2, True), (5, 8, 16, 2, False)]
+
+
+@pytest.mark.parametrize("n,cin,cout,stride,relu", CASES)
+def test_conv3d_forward(n, cin, cout, stride, relu):
+    rng = np.random.default_rng(n * 1000 + cin + cout + stride)
+    x = bf16_round(rng.standard_normal((n ** 3, cin)))
+    w = bf16_round(rng.standard_normal((cout, 27, cin)) / np.sqrt(27 * cin))
+    b = rng.standard_normal(cout).astype(np.float32).astype(np.float64)
+    ref = O.conv3d_fwd(x, w, b, stride=stride, relu=relu)
+    y = Q.k_conv3d_fwd(bf16(x).cuda(), n, cin, bf16(pack_w(w)).cuda(), cout,
+                       bias=torch.from_numpy(b.astype(np.float32)).cuda(), stride=stride, relu=relu)
+    got = y.float().cpu().numpy().astype(np.float64).reshape(ref.shape)
+    check_bf16(got, ref)
+
+
+@pytest.mark.parametrize("n,cin,cout,stride", [(9, 16, 16, 1), (9, 16, 32, 2), (9, 48, 16, 1), (9, 96, 32, 1),
+                                               (9, 128, 64, 1), (17, 64, 64, 2), (9, 32, 64, 2)])
+def test_conv3d_input_gradient(n, cin, cout, stride):
+    rng = np.random.default_rng(7 * n + cin + cout)
+    nout = (n - 1) // stride + 1
+    w = bf16_round(rng.standard_normal((cout, 27, cin)) / np.sqrt(27 * cin))
+    dy = bf16_round(rng.standard_normal((nout ** 3, cout)))
+    ref = O.conv3d_dgrad(w, dy, n, stride)
+    dx = Q.k_conv3d_dgrad(n, cin, cout, bf16(pack_w(w)).cuda(), bf16(dy).cuda(), stride)
+    check_bf16(dx.float().cpu().numpy().astype(np.float64).reshape(ref.shape), ref)
+
+
+@pytest.mark.parametrize("n,cin,cout,stride", [(9, 8, 16, 1), (9, 16, 32, 2), (17, 32, 64, 1), (9, 48, 16, 1),
+                                               (17, 128, 64, 1), (17, 64, 64, 2)])
+def test_conv3d_weight_gradient(n, cin, cout, stride):
+    rng = np.random.default_rng(11 * n + cin + cout)
+    nout = (n - 1) // stride + 1
+    x = bf16_round(rng.standard_normal((n ** 3, cin)))
+    dy = bf16_round(rng.standard_normal((nout ** 3, cout)))
+    ref = pack_w(O.conv3d_wgrad(x, dy, cout, stride))
+    dw = Q.k_conv3d_wgrad(n, cin, bf16(x).cuda(), cout, bf16(dy).cuda(), stride).cpu().numpy().reshape(ref.shape)
+    assert np.abs(dw - ref).max() <= 1e-4 * np.abs(ref).max()
+    assert np.all(dw[:, 27 * cin:] == 0)
+
+
+# ----------------------------------------------------------- whole network
+
+LAYERS = [(8, 16, 1, 2), (16, 16, 1, 16), (16, 32, 2, 16), (32, 32, 1, 32), (32, 64, 2, 32), (64, 64, 1, 64),
+          (64, 64, 2, 64), (64, 64, 1, 64), (128, 64, 1, 128), (96, 32, 1, 96), (48, 16, 1, 48)]
+
+
+def unpack(params):
+    out, off = [], 0
+    for cin, cout, _, _ in LAYERS:
+        kp = kpad_of(cin)
+        W = params[off:off + cout * kp].reshape(cout, kp)[:, :27 * cin].reshape(cout, 27, cin).astype(np.float64)
+        off += cout * kp
+        b = params[off:off + cout].astype(np.float64)
+        off += cout
+        out.append((W, b))
+    head = params[off:off + 17].astype(np.float64)
+    return out, head
+
+
+def pack_grads(gw, gb, ghead):
+    parts = []
+    for (cin, cout, _, _), W, b in zip(LAYERS, gw, gb):
+        parts.append(pack_w(W).ravel())
+        parts.append(b)
+    parts.append(ghead)
+    return np.concatenate(parts)
+
+
+def oracle_net_grads(params, x8, target, n):
+    """The U-Net's forward and backward composed from O2 layers, rounding to
+    BF16 where the network stores BF16 tensors."""
+    L, head = unpack(params)
+    r = bf16_round
+    ns = [n, (n + 1) // 2, (n + 3) // 4, (n + 7) // 8]
+    act = {}
+    W = [r(w) for w, _ in L]
+    B = [b for _, b in L]
+
+    def conv(l, x, stride):
+        return r(O.conv3d_fwd(x, W[l], B[l], stride=stride, relu=True))
+
+    act["a0"] = conv(0, x8, 1)
+    act["s0"] = conv(1, act["a0"], 1)
+    act["a1"] = conv(2, act["s0"], 2)
+    act["s1"] = conv(3, act["a1"], 1)
+    act["a2"] = conv(4, act["s1"], 2)
+    act["s2"] = conv(5, act["a2"], 1)
+    act["a3"] = conv(6, act["s2"], 2)
+    act["b3"] = conv(7, act["a3"], 1)
+    act["c2"] = np.concatenate([r(O.upsample(act["b3"], ns[3])), act["s2"]], axis=1)
+    act["d2"] = conv(8, act["c2"], 1)
+    act["c1"] = np.concatenate([r(O.upsample(act["d2"], ns[2])), act["s1"]], axis=1)
+    act["d1"] = conv(9, act["c1"], 1)
+    act["c0"] = np.concatenate([r(O.upsample(act["d1"], ns[1])), act["s0"]], axis=1)
+    act["d0"] = conv(10, act["c0"], 1)
+    yh = act["d0"] @ head[:16] + head[16]
+    k, j, i = np.meshgrid(*(np.arange(n),) * 3, indexing="ij")
+    inner = ((i > 0) & (j > 0) & (k > 0) & (i < n - 1) & (j < n - 1) & (k < n - 1)).ravel()
+    nint = (n - 2) ** 3
+    dyh = np.where(inner, 2.0 * (yh - target) / nint, 0.0).astype(np.float32).astype(np.float64)
+    ghead = np.concatenate([act["d0"].T @ dyh, [dyh.sum()]])
+    gw = [None] * 11
+    gb = [None] * 11
+
+    def back(l, xin, yout, g, stride, want_dx=True):
+        g = np.where(yout > 0, g, 0.0)
+        gw[l] = O.conv3d_wgrad(xin, g, W[l].shape[0], stride)
+        gb[l] = g.sum(axis=0)
+        return r(O.conv3d_dgrad(W[l], g, round(xin.shape[0] ** (1 / 3)), stride)) if want_dx else None
+
+    gd0 = r(np.outer(dyh, head[:16]))
+    gc0 = back(10, act["c0"], act["d0"], gd0, 1)
+    gd1 = r(O.upsample_adj(gc0[:, :32], ns[1]))
+    gc1 = back(9, act["c1"], act["d1"], gd1, 1)
+    gd2 = r(O.upsample_adj(gc1[:, :64], ns[2]))
+    gc2 = back(8, act["c2"], act["d2"], gd2, 1)
+    gb3 = r(O.upsample_adj(gc2[:, :64], ns[3]))
+    ga3 = back(7, act["a3"], act["b3"], gb3, 1)
+    gs2 = r(back(6, act["s2"], act["a3"], ga3, 2) + gc2[:, 64:])
+    ga2 = back(5, act["a2"], act["s2"], gs2, 1)
+    gs1 = r(back(4, act["s1"], act["a2"], ga2, 2) + gc1[:, 64:])
+    ga1 = back(3, act["a1"], act["s1"], gs1, 1)
+    gs0 = r(back(2, act["s0"], act["a1"], ga1, 2) + gc0[:, 32:])
+    ga0 = back(1, act["a0"], act["s0"], gs0, 1)
+    back(0, x8, act["a0"], ga0, 1, want_dx=False)
+    return gw, gb, ghead, yh
+
+
+def smooth_sample(n, seed):
+    rng = np.random.default_rng(seed)
+    k, j, i = np.meshgrid(*(np.linspace(-1, 1, n),) * 3, indexing="ij")
+    r2 = i ** 2 + j ** 2 + (3 * k) ** 2
+    a, b = rng.uniform(0.5, 1.5, 2)
+    phin = -a / np.sqrt(r2 + 0.1)
+    S = b * np.exp(-4 * r2)
+    phi = -a * 1.3 / np.sqrt(r2 + 0.2) - 0.3 * b * np.exp(-r2)
+    return phin, S, phi
+
+
+def test_network_gradients_match_oracle_composition():
+    n = 17
+    net = Q.UNet(n, seed=5)
+    params = net.get_params()
+    phin, S, phi = smooth_sample(n, 1)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    h = 2.0 / (n - 1)
+    x2, t = net.prepare_sample(dev(phin), dev(S), dev(phi), h, 1.0, 1.0)
+    loss = net.train_step(x2, t, lr=1e-12)
+    g = net.get_grads()
+    x8 = np.zeros((n ** 3, 8))
+    x8[:, :2] = x2.float().cpu().numpy().reshape(-1, 2)
+    gw, gb, ghead, yh = oracle_net_grads(params, x8, t.cpu().numpy().astype(np.float64), n)
+    ref = pack_grads(gw, gb, ghead)
+    tgt = t.cpu().numpy().astype(np.float64)
+    inner = np.zeros((n, n, n), bool)
+    inner[1:-1, 1:-1, 1:-1] = True
+    assert loss == pytest.approx(((yh - tgt) ** 2)[inner.ravel()].mean(), rel=2e-2)
+    off = 0
+    for l, (cin, cout, _, _) in enumerate(LAYERS):
+        size = cout * kpad_of(cin)
+        a, b = g[off:off + size], ref[off:off + size]
+        assert np.linalg.norm(a - b) <= 3e-2 * np.linalg.norm(b), (l, np.linalg.norm(a - b) / np.linalg.norm(b))
+        off += size + cout
+    assert np.allclose(g[off:], ref[off:], rtol=3e-2, atol=1e-3 * np.abs(ref[off:]).max())
+
+
+def test_training_reduces_loss():
+    n = 17
+    net = Q.UNet(n, seed=9)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    samples = [net.prepare_sample(*(dev(a) for a in smooth_sample(n, s)), 2.0 / (n - 1), 1.0, 1.0) for s in range(4)]
+    first = [net.train_step(x, t, lr=2e-3) for x, t in samples]
+    for _ in range(40):
+        for x, t in samples:
+            net.train_step(x, t, lr=2e-3, want_loss=False)
+    last = [net.train_step(x, t, lr=2e-3) for x, t in samples]
+    assert np.mean(last) < 0.2 * np.mean(first)
+    # checkpoint round trip
+    p = net.get_params()
+    net2 = Q.UNet(n, seed=123)
+    net2.set_params(p)
+    assert np.array_equal(net2.get_params(), p)
+
+
+# ------------------------------------------------------- seeded solve paths
+
+def _ctx_with_source(n=33, L=120.0, seed=3):
+    p = synth.two_component_disk(100000, seed)
+    ctx = Q.Context(Q.Config(n=n, box_side=[L], tol_rel=1e-10))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    ctx.deposit(dev(p.x), dev(p.y), dev(p.z), dev(p.m), p.total_mass)
+    ctx.solve_newton()
+    ctx.mond_source()
+    return ctx
+
+
+def test_seeded_solve_with_exact_and_poor_guesses():
+    ctx = _ctx_with_source()
+    info = ctx.solve_mond()
+    phi = ctx.get_field(0, Q.FIELD_PHI).clone()
+    # the converged solution as its own guess: no cycle needed
+    info2 = ctx.solve_mond(guess=phi)
+    assert info2["vcycles"] == [0] and info2["used_fallback"] == 0 and info2["relres"][0] <= 1e-10
+    for dt in (torch.float32, torch.bfloat16):
+        i3 = ctx.solve_mond(guess=phi.to(dt))
+        assert i3["converged"] == [1] and i3["used_fallback"] == 0
+    # a non-finite guess falls back to FMG and reproduces the plain result bit for bit
+    bad = phi.clone()
+    bad[len(bad) // 2] = float("nan")
+    i4 = ctx.solve_mond(guess=bad)
+    assert i4["used_fallback"] == 1 and i4["vcycles"] == info["vcycles"]
+    assert torch.equal(ctx.get_field(0, Q.FIELD_PHI), phi)
+    # noise far from the solution (relative residual above 1) also falls back
+    noisy = phi + 1e3 * torch.randn_like(phi)
+    i5 = ctx.solve_mond(guess=noisy)
+    assert i5["used_fallback"] == 1 and i5["relres"][0] <= 1e-10
+    # without the fallback, V-cycles from a zero interior still converge
+    i6 = ctx.solve_mond(guess=torch.zeros_like(phi), no_fallback=True, allow_not_converged=True)
+    assert i6["used_fallback"] == 0 and i6["relres"][0] <= 1e-10 and i6["vcycles"][0] > info["vcycles"][0]
+
+
+@pytest.mark.skipif(not os.path.exists(CKPT), reason="no trained checkpoint (paper_1201_3185_amd/train_unet.py)")
+def test_trained_network_gain():
+    """On held-out disks the trained prediction starts far closer to the
+    solution than a zero interior or Phi_N, and needs fewer V-cycles to 1e-6."""
+    net = Q.UNet(129, seed=0)
+    net.set_params(np.load(CKPT))
+    g = learned.gain(net, learned.disk_set(4, config=6))
+    assert g["learned"]["relres0"] < 0.1 * g["zero"]["relres0"]
+    assert g["learned"]["relres0"] < g["newton"]["relres0"]
+    assert g["learned"]["vcycles"] < g["zero"]["vcycles"]
+    assert g["learned"]["max_relres"] <= 1e-6 and g["learned"]["fallbacks"] == 0
