@@ -168,8 +168,8 @@ qumond_status qumond_mond_source(qumond_ctx *ctx);
  * optional): nbox * n^3 values of type guess_kind, box after box, whose
  * interior seeds the finest level instead of FMG; the guess is rejected in
  * favour of FMG from zero (info->used_fallback = 1) when it is not finite,
- * when its relative residual exceeds 1, or when the V-cycles it needs exceed
- * the cycles FMG would have used plus max_vcycles.  Synchronises. */
+ * when the relative residual after its first V-cycle exceeds 1, or when it
+ * needs more than ncycle_fmg + max_vcycles V-cycles.  Synchronises. */
 qumond_status qumond_solve_mond(qumond_ctx *ctx, const void *guess, int32_t guess_kind, qumond_solve_info *info);
 
 /* Steps 2-4 in one call with the two chains overlapped: the Newtonian solve

@@ -370,21 +370,23 @@ static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int 
     hipError_t e;
     if (guess) {
         // Seeded solve: V-cycles from the guess's interior.  The guess is
-        // rejected (FMG from zero instead) if it is not finite, if its relative
-        // residual exceeds 1, or if it needs more cycles than FMG plus max_vcycles.
+        // rejected (FMG from zero instead) if it is not finite, if the relative
+        // residual after its first V-cycle exceeds 1 (the first smoothing removes
+        // the guess's high-frequency error, so the raw residual of the guess
+        // says little), or if it needs more cycles than FMG plus max_vcycles.
         const bool no_fallback = (guess_kind & QUMOND_GUESS_NO_FALLBACK) != 0;
         const int kind = guess_kind & 3;
         const size_t esz = kind == QUMOND_GUESS_F64 ? 8 : (kind == QUMOND_GUESS_F32 ? 4 : 2);
         qm::launch_guess_interior(ctx->n, (const char *)guess + (size_t)b * ctx->N * esz, kind, u, ch.s);
         if ((e = ch.mg->relres(rr)) != hipSuccess) return hip_fail(e, "solve: guess");
         rr0 = rr;
-        bool accept = no_fallback || (std::isfinite(rr) && rr <= 1.0);
+        bool accept = no_fallback || std::isfinite(rr);
         const int budget = c.ncycle_fmg + c.max_vcycles;
         while (accept && c.tol_rel > 0.0 && rr > c.tol_rel && extra < budget) {
             ch.mg->finest_cycle();
             ++extra;
             if ((e = ch.mg->relres(rr)) != hipSuccess) return hip_fail(e, "solve: V-cycle");
-            if (!std::isfinite(rr) && !no_fallback) accept = false;
+            if (!no_fallback && (!std::isfinite(rr) || (extra == 1 && rr > 1.0))) accept = false;
         }
         if (no_fallback || (accept && !(c.tol_rel > 0.0 && rr > c.tol_rel))) {
             ch.mg->finish();
