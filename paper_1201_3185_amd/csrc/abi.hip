@@ -41,6 +41,7 @@ struct Mixed {
     qm::Multigrid<float> mg;
     float *a[2] = {nullptr, nullptr};
     float *r = nullptr;
+    double *sc = nullptr;   // refinement scale s and 1/s (device)
 };
 
 struct Box {
@@ -88,6 +89,16 @@ struct qumond_ctx {
         return e;
     }
 };
+
+// Deposit scale 2^s with s = 62 - ceil(log2 M) - 1, so that the integer sum of
+// all corner shares stays below 2^62 (also used by the batched solver).
+int qm_fixed_shift_for(double total_mass)
+{
+    int e;
+    const double mant = std::frexp(total_mass, &e);
+    const int ceil_log2 = (mant == 0.5) ? e - 1 : e;
+    return 62 - ceil_log2 - 1;
+}
 
 extern "C" {
 
@@ -214,7 +225,8 @@ qumond_status qumond_create(const qumond_config *cfg, void *hip_stream, qumond_c
          ((e = c->mix.mg.init(c->n, cfg->npre, cfg->npost, c->s)) != hipSuccess ||
           (e = c->alloc((void **)&c->mix.a[0], c->N * sizeof(float))) != hipSuccess ||
           (e = c->alloc((void **)&c->mix.a[1], c->N * sizeof(float))) != hipSuccess ||
-          (e = c->alloc((void **)&c->mix.r, c->N * sizeof(float))) != hipSuccess))) {
+          (e = c->alloc((void **)&c->mix.r, c->N * sizeof(float))) != hipSuccess ||
+          (e = c->alloc((void **)&c->mix.sc, 2 * sizeof(double))) != hipSuccess))) {
         qumond_status r = hip_fail(e, "qumond_create: allocation");
         qumond_destroy(c);
         return r;
@@ -274,13 +286,6 @@ int64_t qumond_device_bytes(const qumond_ctx *ctx)
                : 0;
 }
 
-static int fixed_shift_for(double total_mass)
-{
-    int e;
-    const double mant = std::frexp(total_mass, &e);
-    const int ceil_log2 = (mant == 0.5) ? e - 1 : e;
-    return 62 - ceil_log2 - 1;
-}
 
 qumond_status qumond_deposit(qumond_ctx *ctx, const double *x, const double *y, const double *z, const double *m,
                              int64_t np, double total_mass, int64_t *n_outside)
@@ -290,7 +295,7 @@ qumond_status qumond_deposit(qumond_ctx *ctx, const double *x, const double *y, 
     if (np > 0 && (!x || !y || !z || !m)) return fail(QUMOND_ERR_INVALID, "particle arrays must not be NULL");
     if (!(total_mass > 0.0) || !std::isfinite(total_mass))
         return fail(QUMOND_ERR_INVALID, "total_mass must be finite and positive");
-    const int shift = ctx->cfg.fixed_shift ? ctx->cfg.fixed_shift : fixed_shift_for(total_mass);
+    const int shift = ctx->cfg.fixed_shift ? ctx->cfg.fixed_shift : qm_fixed_shift_for(total_mass);
     if (std::ldexp(total_mass, shift) >= 9.2e18) return fail(QUMOND_ERR_RANGE, "fixed_shift overflows 64 bits");
     ctx->shift = shift;
     ctx->total_mass = total_mass;
@@ -424,17 +429,16 @@ static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int 
         qm::launch_widen_interior(ctx->n, X.mg.result(), u, ch.s);
         if ((e = ch.mg->relres(rr)) != hipSuccess) return hip_fail(e, "solve: FP32 FMG");
         rr0 = rr;
-        // ... then FP64 residual correction with FP32 V-cycles (zero boundary values)
-        const double nint = (double)(ctx->n - 2) * (ctx->n - 2) * (ctx->n - 2);
+        // ... then FP64 residual correction with FP32 V-cycles (zero boundary
+        // values); the scale comes from the residual norms already on the device.
         while (c.tol_rel > 0.0 && rr > c.tol_rel && extra < c.max_vcycles) {
-            const double rms = std::sqrt(ch.mg->last_r2 / nint);
-            const double scale = rms > 0.0 && std::isfinite(rms) ? rms : 1.0;
-            qm::launch_resid_to_f32(ctx->n, B.h, 1.0 / scale, f, u, X.r, ch.s);
+            qm::launch_mixed_scale(ctx->n, ch.mg->norms, X.sc, ch.s);
+            qm::launch_resid_to_f32(ctx->n, B.h, X.sc, f, u, X.r, ch.s);
             qm::launch_fill<float>(X.a[0], ctx->N, 0.0f, ch.s);
             qm::launch_fill<float>(X.a[1], ctx->N, 0.0f, ch.s);
             X.mg.bind(B.L, X.a[0], X.a[1], X.r);
             X.mg.finest_cycle();
-            qm::launch_correct(ctx->n, scale, X.mg.result(), u, ch.s);
+            qm::launch_correct(ctx->n, X.sc, X.mg.result(), u, ch.s);
             ++extra;
             if ((e = ch.mg->relres(rr)) != hipSuccess) return hip_fail(e, "solve: refinement");
         }
@@ -529,7 +533,8 @@ static qumond_status ensure_chain2(qumond_ctx *ctx)
         ((e = ctx->mix2.mg.init(ctx->n, ctx->cfg.npre, ctx->cfg.npost, ctx->s2)) != hipSuccess ||
          (e = ctx->alloc((void **)&ctx->mix2.a[0], ctx->N * sizeof(float))) != hipSuccess ||
          (e = ctx->alloc((void **)&ctx->mix2.a[1], ctx->N * sizeof(float))) != hipSuccess ||
-         (e = ctx->alloc((void **)&ctx->mix2.r, ctx->N * sizeof(float))) != hipSuccess))
+         (e = ctx->alloc((void **)&ctx->mix2.r, ctx->N * sizeof(float))) != hipSuccess ||
+         (e = ctx->alloc((void **)&ctx->mix2.sc, 2 * sizeof(double))) != hipSuccess))
         return hip_fail(e, "qumond_solve: allocation");
     for (int b = 0; b < ctx->cfg.nbox; ++b)
         if ((e = hipEventCreateWithFlags(&ctx->ev_newton[b], hipEventDisableTiming)) != hipSuccess)

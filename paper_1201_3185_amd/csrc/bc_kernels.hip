@@ -29,12 +29,8 @@ __device__ __forceinline__ void bface_node(int n, int t, int &i, int &j, int &k)
     }
 }
 
-__global__ void bc_outer_k(int n, double L, int mode, double GM, double a0, double *__restrict__ u0, double *__restrict__ u1)
+__device__ __forceinline__ double bc_outer_value(int n, double L, int mode, double GM, double a0, int i, int j, int k)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 6 * n * n) return;
-    int i, j, k;
-    bface_node(n, t, i, j, k);
     const double h = L / (double)(n - 1);
     const double x = -0.5 * L + i * h, y = -0.5 * L + j * h, z = -0.5 * L + k * h;
     const double r = sqrt(x * x + y * y + z * z);
@@ -44,15 +40,44 @@ __global__ void bc_outer_k(int n, double L, int mode, double GM, double a0, doub
     } else if (mode == 2) {
         v = -GM / (2.0 * r) - sqrt(GM) * sqrt(GM + 4.0 * a0 * r * r) / (2.0 * r) + sqrt(GM * a0) * asinh(2.0 * r * sqrt(a0 / GM));
     }
+    return v;
+}
+
+__global__ void bc_outer_k(int n, double L, int mode, double GM, double a0, double *__restrict__ u0, double *__restrict__ u1)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 6 * n * n) return;
+    int i, j, k;
+    bface_node(n, t, i, j, k);
+    const double v = bc_outer_value(n, L, mode, GM, a0, i, j, k);
     const size_t p = id3(n, i, j, k);
     u0[p] = v;
     if (u1) u1[p] = v;
+}
+
+// problem blockIdx.y of a batch, GM = G M_p
+__global__ void bc_outer_batch_k(int n, double L, int mode, double G, double a0, const BatchProblem *__restrict__ prob,
+                                 double *__restrict__ u0)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 6 * n * n) return;
+    int i, j, k;
+    bface_node(n, t, i, j, k);
+    const double GM = G * prob[blockIdx.y].mass;
+    u0[id3(n, i, j, k) + blockIdx.y * (size_t)n * n * n] = bc_outer_value(n, L, mode, GM, a0, i, j, k);
 }
 
 void launch_bc_outer(int n, double L, int mode, double GM, double a0, double *u0, double *u1, hipStream_t s)
 {
     const int cnt = 6 * n * n;
     hipLaunchKernelGGL(bc_outer_k, dim3((cnt + 255) / 256), dim3(256), 0, s, n, L, mode, GM, a0, u0, u1);
+}
+
+void launch_bc_outer_batch(int n, double L, int mode, double G, double a0, const BatchProblem *prob, double *u0,
+                           int nb, hipStream_t s)
+{
+    const int cnt = 6 * n * n;
+    hipLaunchKernelGGL(bc_outer_batch_k, dim3((cnt + 255) / 256, nb), dim3(256), 0, s, n, L, mode, G, a0, prob, u0);
 }
 
 __global__ void bc_from_coarse_k(int n, const double *__restrict__ uc, double *__restrict__ u0, double *__restrict__ u1)

@@ -47,6 +47,19 @@ struct GatherArgs {
     int mond;
 };
 
+// One problem of a batch as its kernels read it from device memory, so that a
+// captured graph stays valid when the inputs change: particle arrays (device,
+// caller-owned), count, total mass and the fixed-point scale 2^shift.
+struct BatchProblem {
+    const double *x, *y, *z, *m;
+    long long np;
+    double mass;
+    double scale;
+    int shift;
+    int pad;
+};
+constexpr int kBatchDepositBlocks = 64;   // deposit workgroups per problem
+
 // ---- grid_kernels.hip (templated on the storage type: double or float)
 // Smoother launch shape: tile variant (0: 32x8, 1: 64x4, 2: 64x8, 3: 128x4,
 // 4: 32x16 columns) and the number of z planes one workgroup marches through.
@@ -55,44 +68,55 @@ struct SmootherShape {
     int kchunk;
 };
 constexpr int kSmootherVariants = 5;
-template <typename T> void launch_rbgs(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s);
+// Every grid launcher takes nb, the number of problems stored back to back
+// (problem p of a level with n points per side at offset p n^3); nb = 1 is the
+// single-problem case.
+template <typename T> void launch_rbgs(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s, int nb = 1);
 template <typename T> void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, SmootherShape sh,
-                                            hipStream_t s);
+                                            hipStream_t s, int nb = 1);
 template <typename T> SmootherShape &rbgs_shape(int n);   // the table entry used for n
 // Two sweeps in one launch (variants 0: 32x8, 1: 64x4); with uc != NULL the
 // correction u += P uc (uc on the next coarser level) is applied first.
 template <typename T> void launch_rbgs2(int n, double h, const T *f, const T *uin, T *uout, const T *uc,
-                                       hipStream_t s);
+                                       hipStream_t s, int nb = 1);
+template <typename T> void launch_rbgs2_shape(int n, double h, const T *f, const T *uin, T *uout, const T *uc,
+                                             SmootherShape sh, hipStream_t s, int nb = 1);
 template <typename T> SmootherShape &rbgs2_shape(int n);
 // Whether the multigrid uses the fused kernel on a level of n points per side
 // (set by the autotuner from measured times; n <= 65 by default).
 template <typename T> int &use_fused(int n);
 template <typename T> void launch_residual_restrict(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1,
-                                                   hipStream_t s);
-template <typename T> void launch_restrict(int nf, const T *src, T *dst, hipStream_t s);
-template <typename T> void launch_prolong_add(int nc, const T *uc, T *uf, hipStream_t s);
-template <typename T> void launch_interp(int nc, const T *uc, T *uf, hipStream_t s);
-template <typename T> void launch_inject_boundary(int nfine, const T *ufine, int nl, T *u0, T *u1, hipStream_t s);
+                                                   hipStream_t s, int nb = 1);
+template <typename T> void launch_restrict(int nf, const T *src, T *dst, hipStream_t s, int nb = 1);
+template <typename T> void launch_prolong_add(int nc, const T *uc, T *uf, hipStream_t s, int nb = 1);
+template <typename T> void launch_interp(int nc, const T *uc, T *uf, hipStream_t s, int nb = 1);
+template <typename T> void launch_inject_boundary(int nfine, const T *ufine, int nl, T *u0, T *u1, hipStream_t s,
+                                                 int nb = 1);
 template <typename T> void launch_fill(T *p, size_t count, T v, hipStream_t s);
 template <typename T> void launch_boundary_copy(int n, const T *src, T *dst, hipStream_t s);
-// Coarse tail: all levels with n <= 17 inside one workgroup's LDS.  mode 0: one
-// V-cycle of the top level (correction, zero boundary); mode 1: FMG from 3^3 up to
-// the top level with ncycle V-cycles per level (boundary of u = Dirichlet values).
+// Coarse tail: all levels with n <= 17 inside one workgroup's LDS (one
+// workgroup per problem).  mode 0: one V-cycle of the top level (correction,
+// zero boundary); mode 1: FMG from 3^3 up to the top level with ncycle V-cycles
+// per level (boundary of u = Dirichlet values).
 template <typename T> void launch_coarse_tail(int ltop, double L, const T *f, T *u, int npre, int npost, int ncycle,
-                                             int mode, int nrep, hipStream_t s);
+                                             int mode, int nrep, hipStream_t s, int nb = 1);
 // Sums over interior nodes of (f - A_h u)^2, f^2 and of the squared boundary-value
-// contribution: per-block partials (3 per block), then one block in fixed order,
-// into out[0..2] (device doubles).
+// contribution: per-block partials (3 per block, kNormBlocks blocks per
+// problem), then one block per problem in fixed order, into out[3p..3p+2]
+// (device doubles).
 template <typename T> void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial, double *out,
-                                             hipStream_t s);
+                                             hipStream_t s, int nb = 1);
 constexpr int kNormBlocks = 512;
 
-// mixed precision (FP64 refinement around FP32 multigrid)
+// mixed precision (FP64 refinement around FP32 multigrid); sc holds s and 1/s
+// per problem, written by launch_mixed_scale from the residual norms.
 void launch_narrow(const double *src, float *dst, size_t count, hipStream_t s);
-void launch_narrow_boundary(int n, const double *src, float *d0, float *d1, hipStream_t s);
-void launch_widen_interior(int n, const float *src, double *dst, hipStream_t s);
-void launch_resid_to_f32(int n, double h, double inv_s, const double *f, const double *u, float *r, hipStream_t s);
-void launch_correct(int n, double scale, const float *e, double *u, hipStream_t s);
+void launch_narrow_boundary(int n, const double *src, float *d0, float *d1, hipStream_t s, int nb = 1);
+void launch_widen_interior(int n, const float *src, double *dst, hipStream_t s, int nb = 1);
+void launch_mixed_scale(int n, const double *norms, double *sc, hipStream_t s, int nb = 1);
+void launch_resid_to_f32(int n, double h, const double *sc, const double *f, const double *u, float *r, hipStream_t s,
+                         int nb = 1);
+void launch_correct(int n, const double *sc, const float *e, double *u, hipStream_t s, int nb = 1);
 
 // interior of u from an initial guess (kind 1: double, 2: float, 3: bf16)
 void launch_guess_interior(int n, const void *g, int kind, double *u, hipStream_t s);
@@ -100,6 +124,9 @@ void launch_guess_interior(int n, const void *g, int kind, double *u, hipStream_
 // ---- bc_kernels.hip
 // mode 0 zero, 1 Newtonian monopole -GM/r, 2 QUMOND monopole.
 void launch_bc_outer(int n, double L, int mode, double GM, double a0, double *u0, double *u1, hipStream_t s);
+// The same for nb problems (back to back), GM = G * prob[p].mass.
+void launch_bc_outer_batch(int n, double L, int mode, double G, double a0, const BatchProblem *prob, double *u0,
+                           int nb, hipStream_t s);
 void launch_bc_from_coarse(int n, const double *uc, double *u0, double *u1, hipStream_t s);
 
 // ---- particle_kernels.hip
@@ -111,8 +138,21 @@ void launch_rhs_from_q(int n, double h, double four_pi_G, int shift, const long 
 void launch_gather(const GatherArgs &a, const double *x, const double *y, const double *z, int64_t np, double *ax,
                    double *ay, double *az, uint8_t *box_used, hipStream_t s);
 void launch_rotation_curve(const GatherArgs &a, const double *R, int nR, int naz, double *vc2, hipStream_t s);
+// Batches of single-box problems (one box of side L, n points per side):
+// q must be zeroed; scratch holds deposit_batch_scratch_bytes(nb) bytes;
+// inside[p] counts the particles of problem p deposited (must be zeroed).
+size_t deposit_batch_scratch_bytes(int nb);
+void launch_deposit_batch(int n, double L, const BatchProblem *prob, long long maxnp, unsigned long long *q,
+                          unsigned long long *scratch, unsigned long long *inside, int nb, hipStream_t s);
+void launch_rhs_batch(int n, double h, double four_pi_G, const BatchProblem *prob, const long long *q, double *f, int nb,
+                      hipStream_t s);
+// vc2[p nR + r]: Eq. 4 at radius R[r] from the potential of problem p (monopole
+// force G prob[p].mass beyond the box; mond selects the QUMOND monopole).
+void launch_rotation_curve_batch(int n, double L, double frac, double G, double a0, int mond,
+                                 const BatchProblem *prob, const double *phi, const double *R, int nR, int naz,
+                                 double *vc2, int nb, hipStream_t s);
 
 // ---- source_kernel.hip
-void launch_mond_source(int n, double h, double a0, const double *phin, double *S, hipStream_t s);
+void launch_mond_source(int n, double h, double a0, const double *phin, double *S, hipStream_t s, int nb = 1);
 
 }  // namespace qm

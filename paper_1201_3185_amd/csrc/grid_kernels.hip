@@ -12,6 +12,11 @@
 // plain red pass followed by a black pass, with u read once and written once
 // (24 bytes per point in FP64).  Reading u_in and writing u_out avoids any
 // race between tiles; the driver alternates two buffers.
+//
+// Batches.  Every grid kernel can sweep the same level of nb independent
+// problems stored back to back (problem p of a level with n points per side
+// starts at p n^3): the problem index is the slowest part of the block index,
+// so one launch covers the whole batch, and nb = 1 is the single-problem case.
 #include "common.h"
 
 namespace qm {
@@ -36,7 +41,7 @@ __device__ __forceinline__ T prolong_at(int nc, const T *__restrict__ uc, int i,
 
 template <typename T, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY)
-rbgs_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2, int kchunk)
+rbgs_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2, int kchunk, int nzc)
 {
     constexpr int PX = TX + 4, PY = TY + 4, NS = 5, NT = TX * TY;
     constexpr int PL = PX * PY;                  // values of one LDS plane (tile + two-node ring)
@@ -47,10 +52,14 @@ rbgs_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict
     const T sixth = T(1) / T(6);
     const int tid = threadIdx.x;
     const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
-    const int kb = 1 + blockIdx.z * kchunk;
+    const int pb = blockIdx.z / nzc;
+    const int kb = 1 + (blockIdx.z - pb * nzc) * kchunk;
     if (kb > n - 2) return;
     const int ke = min(kb + kchunk - 1, n - 2);
     const size_t nn = (size_t)n * n;
+    uin += (size_t)pb * nn * n;
+    uout += (size_t)pb * nn * n;
+    f += (size_t)pb * nn * n;
 
     // plane offsets of this thread's share of a plane load
     int goff[NL];
@@ -168,11 +177,12 @@ rbgs_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict
 }
 
 template <typename T, int TX, int TY>
-static void rbgs_launch(int n, double h, const T *f, const T *uin, T *uout, int kchunk, hipStream_t s)
+static void rbgs_launch(int n, double h, const T *f, const T *uin, T *uout, int kchunk, int nb, hipStream_t s)
 {
     const int m = n - 2;
-    dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, (m + kchunk - 1) / kchunk);
-    hipLaunchKernelGGL((rbgs_zmarch<T, TX, TY>), grid, dim3(TX * TY), 0, s, uin, uout, f, n, T(h * h), kchunk);
+    const int nzc = (m + kchunk - 1) / kchunk;
+    dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, nzc * nb);
+    hipLaunchKernelGGL((rbgs_zmarch<T, TX, TY>), grid, dim3(TX * TY), 0, s, uin, uout, f, n, T(h * h), kchunk, nzc);
 }
 
 // ----------------------------------------------------- two fused sweeps
@@ -190,7 +200,7 @@ static void rbgs_launch(int n, double h, const T *f, const T *uin, T *uout, int 
 template <typename T, int TX, int TY, bool PROLONG>
 __global__ void __launch_bounds__(TX *TY)
 rbgs2_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2, int kchunk,
-             const T *__restrict__ uc, int nc)
+             const T *__restrict__ uc, int nc, int nzc)
 {
     constexpr int R = 4;                         // ring of the LDS planes
     constexpr int PX = TX + 2 * R, PY = TY + 2 * R, NT = TX * TY;
@@ -203,10 +213,15 @@ rbgs2_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
     const T sixth = T(1) / T(6);
     const int tid = threadIdx.x;
     const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
-    const int kb = 1 + blockIdx.z * kchunk;
+    const int pb = blockIdx.z / nzc;
+    const int kb = 1 + (blockIdx.z - pb * nzc) * kchunk;
     if (kb > n - 2) return;
     const int ke = min(kb + kchunk - 1, n - 2);
     const size_t nn = (size_t)n * n;
+    uin += (size_t)pb * nn * n;
+    uout += (size_t)pb * nn * n;
+    f += (size_t)pb * nn * n;
+    if (PROLONG) uc += (size_t)pb * nc * nc * nc;
 
     int goff[NL], gi[NL], gj[NL];
 #pragma unroll
@@ -313,27 +328,35 @@ rbgs2_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
 }
 
 template <typename T, int TX, int TY>
-static void rbgs2_launch(int n, double h, const T *f, const T *uin, T *uout, int kchunk, const T *uc, hipStream_t s)
+static void rbgs2_launch(int n, double h, const T *f, const T *uin, T *uout, int kchunk, const T *uc, int nb,
+                         hipStream_t s)
 {
     const int m = n - 2;
-    dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, (m + kchunk - 1) / kchunk);
+    const int nzc = (m + kchunk - 1) / kchunk;
+    dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, nzc * nb);
     if (uc)
         hipLaunchKernelGGL((rbgs2_zmarch<T, TX, TY, true>), grid, dim3(TX * TY), 0, s, uin, uout, f, n, T(h * h), kchunk,
-                           uc, (n + 1) / 2);
+                           uc, (n + 1) / 2, nzc);
     else
         hipLaunchKernelGGL((rbgs2_zmarch<T, TX, TY, false>), grid, dim3(TX * TY), 0, s, uin, uout, f, n, T(h * h),
-                           kchunk, uc, (n + 1) / 2);
+                           kchunk, uc, (n + 1) / 2, nzc);
 }
 
 template <typename T>
-void launch_rbgs2(int n, double h, const T *f, const T *uin, T *uout, const T *uc, hipStream_t s)
+void launch_rbgs2_shape(int n, double h, const T *f, const T *uin, T *uout, const T *uc, SmootherShape sh, hipStream_t s,
+                        int nb)
 {
-    const SmootherShape sh = rbgs2_shape<T>(n);
     const int kc = sh.kchunk > 0 ? sh.kchunk : n;
     switch (sh.variant) {
-    case 0: rbgs2_launch<T, 32, 8>(n, h, f, uin, uout, kc, uc, s); break;
-    default: rbgs2_launch<T, 64, 4>(n, h, f, uin, uout, kc, uc, s); break;
+    case 0: rbgs2_launch<T, 32, 8>(n, h, f, uin, uout, kc, uc, nb, s); break;
+    default: rbgs2_launch<T, 64, 4>(n, h, f, uin, uout, kc, uc, nb, s); break;
     }
+}
+
+template <typename T>
+void launch_rbgs2(int n, double h, const T *f, const T *uin, T *uout, const T *uc, hipStream_t s, int nb)
+{
+    launch_rbgs2_shape<T>(n, h, f, uin, uout, uc, rbgs2_shape<T>(n), s, nb);
 }
 
 // Launch shapes of the smoother: tile variant and z-chunk per level size.
@@ -396,22 +419,22 @@ SmootherShape &rbgs_shape(int n)
 }
 
 template <typename T>
-void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, SmootherShape sh, hipStream_t s)
+void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, SmootherShape sh, hipStream_t s, int nb)
 {
     const int kc = sh.kchunk > 0 ? sh.kchunk : n;
     switch (sh.variant) {
-    case 0: rbgs_launch<T, 32, 8>(n, h, f, uin, uout, kc, s); break;
-    case 2: rbgs_launch<T, 64, 8>(n, h, f, uin, uout, kc, s); break;
-    case 3: rbgs_launch<T, 128, 4>(n, h, f, uin, uout, kc, s); break;
-    case 4: rbgs_launch<T, 32, 16>(n, h, f, uin, uout, kc, s); break;
-    default: rbgs_launch<T, 64, 4>(n, h, f, uin, uout, kc, s); break;
+    case 0: rbgs_launch<T, 32, 8>(n, h, f, uin, uout, kc, nb, s); break;
+    case 2: rbgs_launch<T, 64, 8>(n, h, f, uin, uout, kc, nb, s); break;
+    case 3: rbgs_launch<T, 128, 4>(n, h, f, uin, uout, kc, nb, s); break;
+    case 4: rbgs_launch<T, 32, 16>(n, h, f, uin, uout, kc, nb, s); break;
+    default: rbgs_launch<T, 64, 4>(n, h, f, uin, uout, kc, nb, s); break;
     }
 }
 
 template <typename T>
-void launch_rbgs(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s)
+void launch_rbgs(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s, int nb)
 {
-    launch_rbgs_shape<T>(n, h, f, uin, uout, rbgs_shape<T>(n), s);
+    launch_rbgs_shape<T>(n, h, f, uin, uout, rbgs_shape<T>(n), s, nb);
 }
 
 // ------------------------------------------------- residual and restriction
@@ -421,13 +444,20 @@ void launch_rbgs(int n, double h, const T *f, const T *uin, T *uout, hipStream_t
 // coarse correction (uc0 everywhere, uc1 on the boundary).
 template <typename T>
 __global__ void residual_restrict_k(int nf, T ih2, const T *__restrict__ f, const T *__restrict__ u, T *__restrict__ fc,
-                                    T *__restrict__ uc0, T *__restrict__ uc1)
+                                    T *__restrict__ uc0, T *__restrict__ uc1, int zb)
 {
     const int nc = (nf + 1) / 2;
+    const int pb = blockIdx.z / zb;
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int J = blockIdx.y * blockDim.y + threadIdx.y;
-    const int K = blockIdx.z * blockDim.z + threadIdx.z;
+    const int K = (blockIdx.z - pb * zb) * blockDim.z + threadIdx.z;
     if (I >= nc || J >= nc || K >= nc) return;
+    const size_t Nf = (size_t)nf * nf * nf, Nc = (size_t)nc * nc * nc;
+    f += pb * Nf;
+    u += pb * Nf;
+    fc += pb * Nc;
+    uc0 += pb * Nc;
+    if (uc1) uc1 += pb * Nc;
     const size_t C = id3(nc, I, J, K);
     const bool bnd = I == 0 || J == 0 || K == 0 || I == nc - 1 || J == nc - 1 || K == nc - 1;
     uc0[C] = T(0);
@@ -450,13 +480,16 @@ __global__ void residual_restrict_k(int nf, T ih2, const T *__restrict__ f, cons
 }
 
 template <typename T>
-__global__ void restrict_k(int nf, const T *__restrict__ src, T *__restrict__ dst)
+__global__ void restrict_k(int nf, const T *__restrict__ src, T *__restrict__ dst, int zb)
 {
     const int nc = (nf + 1) / 2;
+    const int pb = blockIdx.z / zb;
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int J = blockIdx.y * blockDim.y + threadIdx.y;
-    const int K = blockIdx.z * blockDim.z + threadIdx.z;
+    const int K = (blockIdx.z - pb * zb) * blockDim.z + threadIdx.z;
     if (I >= nc || J >= nc || K >= nc) return;
+    src += pb * (size_t)nf * nf * nf;
+    dst += pb * (size_t)nc * nc * nc;
     const size_t C = id3(nc, I, J, K);
     if (I == 0 || J == 0 || K == 0 || I == nc - 1 || J == nc - 1 || K == nc - 1) {
         dst[C] = T(0);
@@ -471,37 +504,46 @@ __global__ void restrict_k(int nf, const T *__restrict__ src, T *__restrict__ ds
     dst[C] = acc;
 }
 
-static dim3 grid3(int m, dim3 blk)
+// Grid over an m^3 block of nodes for nb problems; zb = blocks per problem along z.
+static dim3 grid3(int m, dim3 blk, int nb, int &zb)
 {
-    return dim3((m + blk.x - 1) / blk.x, (m + blk.y - 1) / blk.y, (m + blk.z - 1) / blk.z);
+    zb = (m + blk.z - 1) / blk.z;
+    return dim3((m + blk.x - 1) / blk.x, (m + blk.y - 1) / blk.y, zb * nb);
 }
 
 template <typename T>
-void launch_residual_restrict(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1, hipStream_t s)
+void launch_residual_restrict(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1, hipStream_t s, int nb)
 {
     const int nc = (nf + 1) / 2;
     dim3 blk(16, 4, 4);
-    hipLaunchKernelGGL(residual_restrict_k<T>, grid3(nc, blk), blk, 0, s, nf, T(1.0 / (h * h)), f, u, fc, uc0, uc1);
+    int zb;
+    const dim3 g = grid3(nc, blk, nb, zb);
+    hipLaunchKernelGGL(residual_restrict_k<T>, g, blk, 0, s, nf, T(1.0 / (h * h)), f, u, fc, uc0, uc1, zb);
 }
 
 template <typename T>
-void launch_restrict(int nf, const T *src, T *dst, hipStream_t s)
+void launch_restrict(int nf, const T *src, T *dst, hipStream_t s, int nb)
 {
     const int nc = (nf + 1) / 2;
     dim3 blk(16, 4, 4);
-    hipLaunchKernelGGL(restrict_k<T>, grid3(nc, blk), blk, 0, s, nf, src, dst);
+    int zb;
+    const dim3 g = grid3(nc, blk, nb, zb);
+    hipLaunchKernelGGL(restrict_k<T>, g, blk, 0, s, nf, src, dst, zb);
 }
 
 // ------------------------------------------------------------- prolongation
 
 template <typename T, bool ADD>
-__global__ void prolong_k(int nc, const T *__restrict__ uc, T *__restrict__ uf)
+__global__ void prolong_k(int nc, const T *__restrict__ uc, T *__restrict__ uf, int zb)
 {
     const int nf = 2 * nc - 1;
+    const int pb = blockIdx.z / zb;
     const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
     const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = 1 + blockIdx.z * blockDim.z + threadIdx.z;
+    const int k = 1 + (blockIdx.z - pb * zb) * blockDim.z + threadIdx.z;
     if (i > nf - 2 || j > nf - 2 || k > nf - 2) return;
+    uc += pb * (size_t)nc * nc * nc;
+    uf += pb * (size_t)nf * nf * nf;
     const size_t p = id3(nf, i, j, k);
     const T v = prolong_at(nc, uc, i, j, k);
     if (ADD) uf[p] += v;
@@ -509,19 +551,23 @@ __global__ void prolong_k(int nc, const T *__restrict__ uc, T *__restrict__ uf)
 }
 
 template <typename T>
-void launch_prolong_add(int nc, const T *uc, T *uf, hipStream_t s)
+void launch_prolong_add(int nc, const T *uc, T *uf, hipStream_t s, int nb)
 {
     const int nf = 2 * nc - 1;
     dim3 blk(64, 2, 2);
-    hipLaunchKernelGGL((prolong_k<T, true>), grid3(nf - 2, blk), blk, 0, s, nc, uc, uf);
+    int zb;
+    const dim3 g = grid3(nf - 2, blk, nb, zb);
+    hipLaunchKernelGGL((prolong_k<T, true>), g, blk, 0, s, nc, uc, uf, zb);
 }
 
 template <typename T>
-void launch_interp(int nc, const T *uc, T *uf, hipStream_t s)
+void launch_interp(int nc, const T *uc, T *uf, hipStream_t s, int nb)
 {
     const int nf = 2 * nc - 1;
     dim3 blk(64, 2, 2);
-    hipLaunchKernelGGL((prolong_k<T, false>), grid3(nf - 2, blk), blk, 0, s, nc, uc, uf);
+    int zb;
+    const dim3 g = grid3(nf - 2, blk, nb, zb);
+    hipLaunchKernelGGL((prolong_k<T, false>), g, blk, 0, s, nc, uc, uf, zb);
 }
 
 // ------------------------------------------------------- boundary helpers
@@ -548,6 +594,10 @@ __global__ void inject_boundary_k(int nfine, const T *__restrict__ ufine, int nl
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 6 * nl * nl) return;
+    const size_t Nl = (size_t)nl * nl * nl;
+    ufine += blockIdx.y * (size_t)nfine * nfine * nfine;
+    u0 += blockIdx.y * Nl;
+    if (u1) u1 += blockIdx.y * Nl;
     int i, j, k;
     face_node(nl, t, i, j, k);
     const int st = (nfine - 1) / (nl - 1);
@@ -557,10 +607,10 @@ __global__ void inject_boundary_k(int nfine, const T *__restrict__ ufine, int nl
 }
 
 template <typename T>
-void launch_inject_boundary(int nfine, const T *ufine, int nl, T *u0, T *u1, hipStream_t s)
+void launch_inject_boundary(int nfine, const T *ufine, int nl, T *u0, T *u1, hipStream_t s, int nb)
 {
     const int cnt = 6 * nl * nl;
-    hipLaunchKernelGGL(inject_boundary_k<T>, dim3((cnt + 255) / 256), dim3(256), 0, s, nfine, ufine, nl, u0, u1);
+    hipLaunchKernelGGL(inject_boundary_k<T>, dim3((cnt + 255) / 256, nb), dim3(256), 0, s, nfine, ufine, nl, u0, u1);
 }
 
 template <typename T>
@@ -779,6 +829,8 @@ coarse_tail_k(int top, T L, const T *__restrict__ fg, T *__restrict__ ug, int np
     __shared__ T Rs[kTailTopN * kTailTopN * kTailTopN];
     TailLDS<T> t{U, F, Rs, L, npre, npost};
     const int n = t.nl(top), cnt = n * n * n;
+    fg += (size_t)blockIdx.x * cnt;
+    ug += (size_t)blockIdx.x * cnt;
     constexpr int PER = (kTailTopN * kTailTopN * kTailTopN + kTailThreads - 1) / kTailThreads;
     T ru[PER], rf[PER];
 #pragma unroll
@@ -814,9 +866,9 @@ coarse_tail_k(int top, T L, const T *__restrict__ fg, T *__restrict__ ug, int np
 
 template <typename T>
 void launch_coarse_tail(int ltop, double L, const T *f, T *u, int npre, int npost, int ncycle, int mode, int nrep,
-                        hipStream_t s)
+                        hipStream_t s, int nb)
 {
-    hipLaunchKernelGGL(coarse_tail_k<T>, dim3(1), dim3(kTailThreads), 0, s, ltop, T(L), f, u, npre, npost, ncycle,
+    hipLaunchKernelGGL(coarse_tail_k<T>, dim3(nb), dim3(kTailThreads), 0, s, ltop, T(L), f, u, npre, npost, ncycle,
                        mode, nrep);
 }
 
@@ -853,6 +905,9 @@ resid_norms_partial_k(int n, double ih2, const T *__restrict__ f, const T *__res
     const int m = n - 2;
     const size_t cnt = (size_t)m * m * m;
     const size_t sy = (size_t)n, sz = (size_t)n * n;
+    f += blockIdx.y * sz * n;
+    u += blockIdx.y * sz * n;
+    partial += blockIdx.y * 3 * (size_t)gridDim.x;
     double sr = 0.0, sf = 0.0, sb = 0.0;
     for (size_t t = blockIdx.x * (size_t)256 + threadIdx.x; t < cnt; t += (size_t)gridDim.x * 256) {
         const int i = 1 + (int)(t % m), j = 1 + (int)((t / m) % m), k = 1 + (int)(t / ((size_t)m * m));
@@ -880,6 +935,8 @@ resid_norms_partial_k(int n, double ih2, const T *__restrict__ f, const T *__res
 __global__ void __launch_bounds__(256) norms_final_k(const double *__restrict__ partial, int nb, double *__restrict__ out)
 {
     __shared__ double sh[768];
+    partial += blockIdx.x * 3 * (size_t)nb;
+    out += 3 * blockIdx.x;
     double a = 0.0, b = 0.0, c = 0.0;
     for (int t = threadIdx.x; t < nb; t += 256) {
         a += partial[3 * t];
@@ -895,17 +952,20 @@ __global__ void __launch_bounds__(256) norms_final_k(const double *__restrict__ 
 }
 
 template <typename T>
-void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial, double *out, hipStream_t s)
+void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial, double *out, hipStream_t s, int nb)
 {
-    hipLaunchKernelGGL(resid_norms_partial_k<T>, dim3(kNormBlocks), dim3(256), 0, s, n, 1.0 / (h * h), f, u, partial);
-    hipLaunchKernelGGL(norms_final_k, dim3(1), dim3(256), 0, s, partial, kNormBlocks, out);
+    hipLaunchKernelGGL(resid_norms_partial_k<T>, dim3(kNormBlocks, nb), dim3(256), 0, s, n, 1.0 / (h * h), f, u,
+                       partial);
+    hipLaunchKernelGGL(norms_final_k, dim3(nb), dim3(256), 0, s, partial, kNormBlocks, out);
 }
 
 // ------------------------------------------------- mixed-precision helpers
 //
 // FP64 residual-correction refinement around FP32 multigrid: the FP64 iterate
 // is corrected by s e where e solves A e = r / s in FP32 (zero Dirichlet
-// values) and s is the RMS of the FP64 residual r = f - A u.
+// values) and s is the RMS of the FP64 residual r = f - A u over the interior
+// (1 if that is 0 or not finite).  s and 1/s are computed on the device from
+// the residual norms, so no host round trip sits between the steps.
 
 __global__ void narrow_k(const double *__restrict__ src, float *__restrict__ dst, size_t count)
 {
@@ -919,32 +979,47 @@ __global__ void narrow_boundary_k(int n, const double *__restrict__ src, float *
     if (t >= 6 * n * n) return;
     int i, j, k;
     face_node(n, t, i, j, k);
-    const size_t p = id3(n, i, j, k);
+    const size_t p = id3(n, i, j, k) + blockIdx.y * (size_t)n * n * n;
     const float v = (float)src[p];
     d0[p] = v;
     if (d1) d1[p] = v;
 }
 
 // u64 interior = (double) u32
-__global__ void widen_interior_k(int n, const float *__restrict__ src, double *__restrict__ dst)
+__global__ void widen_interior_k(int n, const float *__restrict__ src, double *__restrict__ dst, int zb)
 {
+    const int pb = blockIdx.z / zb;
     const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
     const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = 1 + blockIdx.z * blockDim.z + threadIdx.z;
+    const int k = 1 + (blockIdx.z - pb * zb) * blockDim.z + threadIdx.z;
     if (i > n - 2 || j > n - 2 || k > n - 2) return;
-    const size_t p = id3(n, i, j, k);
+    const size_t p = id3(n, i, j, k) + pb * (size_t)n * n * n;
     dst[p] = (double)src[p];
 }
 
-// r32 = (f - A_h u) / s in FP64, rounded to FP32, at interior nodes; 0 on the boundary
-__global__ void resid_to_f32_k(int n, double ih2, double inv_s, const double *__restrict__ f, const double *__restrict__ u,
-                               float *__restrict__ r)
+// sc[2p] = s, sc[2p+1] = 1/s for problem p from its residual norms (3 per problem)
+__global__ void mixed_scale_k(int n, int nb, const double *__restrict__ norms, double *__restrict__ sc)
 {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nb) return;
+    const double nint = (double)(n - 2) * (double)(n - 2) * (double)(n - 2);
+    const double rms = sqrt(norms[3 * p] / nint);
+    const double s = (rms > 0.0 && isfinite(rms)) ? rms : 1.0;
+    sc[2 * p] = s;
+    sc[2 * p + 1] = 1.0 / s;
+}
+
+// r32 = (f - A_h u) / s in FP64, rounded to FP32, at interior nodes; 0 on the boundary
+__global__ void resid_to_f32_k(int n, double ih2, const double *__restrict__ sc, const double *__restrict__ f,
+                               const double *__restrict__ u, float *__restrict__ r, int zb)
+{
+    const int pb = blockIdx.z / zb;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    const int k = (blockIdx.z - pb * zb) * blockDim.z + threadIdx.z;
     if (i >= n || j >= n || k >= n) return;
-    const size_t p = id3(n, i, j, k);
+    const double inv_s = sc[2 * pb + 1];
+    const size_t p = id3(n, i, j, k) + pb * (size_t)n * n * n;
     if (i == 0 || j == 0 || k == 0 || i == n - 1 || j == n - 1 || k == n - 1) {
         r[p] = 0.0f;
         return;
@@ -955,14 +1030,15 @@ __global__ void resid_to_f32_k(int n, double ih2, double inv_s, const double *__
 }
 
 // u64 += s e32 at interior nodes
-__global__ void correct_k(int n, double s, const float *__restrict__ e, double *__restrict__ u)
+__global__ void correct_k(int n, const double *__restrict__ sc, const float *__restrict__ e, double *__restrict__ u, int zb)
 {
+    const int pb = blockIdx.z / zb;
     const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
     const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = 1 + blockIdx.z * blockDim.z + threadIdx.z;
+    const int k = 1 + (blockIdx.z - pb * zb) * blockDim.z + threadIdx.z;
     if (i > n - 2 || j > n - 2 || k > n - 2) return;
-    const size_t p = id3(n, i, j, k);
-    u[p] += s * (double)e[p];
+    const size_t p = id3(n, i, j, k) + pb * (size_t)n * n * n;
+    u[p] += sc[2 * pb] * (double)e[p];
 }
 
 void launch_narrow(const double *src, float *dst, size_t count, hipStream_t s)
@@ -972,28 +1048,40 @@ void launch_narrow(const double *src, float *dst, size_t count, hipStream_t s)
     hipLaunchKernelGGL(narrow_k, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, count);
 }
 
-void launch_narrow_boundary(int n, const double *src, float *d0, float *d1, hipStream_t s)
+void launch_narrow_boundary(int n, const double *src, float *d0, float *d1, hipStream_t s, int nb)
 {
     const int cnt = 6 * n * n;
-    hipLaunchKernelGGL(narrow_boundary_k, dim3((cnt + 255) / 256), dim3(256), 0, s, n, src, d0, d1);
+    hipLaunchKernelGGL(narrow_boundary_k, dim3((cnt + 255) / 256, nb), dim3(256), 0, s, n, src, d0, d1);
 }
 
-void launch_widen_interior(int n, const float *src, double *dst, hipStream_t s)
+void launch_widen_interior(int n, const float *src, double *dst, hipStream_t s, int nb)
 {
     dim3 blk(64, 2, 2);
-    hipLaunchKernelGGL(widen_interior_k, grid3(n - 2, blk), blk, 0, s, n, src, dst);
+    int zb;
+    const dim3 g = grid3(n - 2, blk, nb, zb);
+    hipLaunchKernelGGL(widen_interior_k, g, blk, 0, s, n, src, dst, zb);
 }
 
-void launch_resid_to_f32(int n, double h, double inv_s, const double *f, const double *u, float *r, hipStream_t s)
+void launch_mixed_scale(int n, const double *norms, double *sc, hipStream_t s, int nb)
 {
-    dim3 blk(64, 2, 2);
-    hipLaunchKernelGGL(resid_to_f32_k, grid3(n, blk), blk, 0, s, n, 1.0 / (h * h), inv_s, f, u, r);
+    hipLaunchKernelGGL(mixed_scale_k, dim3((nb + 63) / 64), dim3(64), 0, s, n, nb, norms, sc);
 }
 
-void launch_correct(int n, double scale, const float *e, double *u, hipStream_t s)
+void launch_resid_to_f32(int n, double h, const double *sc, const double *f, const double *u, float *r, hipStream_t s,
+                         int nb)
 {
     dim3 blk(64, 2, 2);
-    hipLaunchKernelGGL(correct_k, grid3(n - 2, blk), blk, 0, s, n, scale, e, u);
+    int zb;
+    const dim3 g = grid3(n, blk, nb, zb);
+    hipLaunchKernelGGL(resid_to_f32_k, g, blk, 0, s, n, 1.0 / (h * h), sc, f, u, r, zb);
+}
+
+void launch_correct(int n, const double *sc, const float *e, double *u, hipStream_t s, int nb)
+{
+    dim3 blk(64, 2, 2);
+    int zb;
+    const dim3 g = grid3(n - 2, blk, nb, zb);
+    hipLaunchKernelGGL(correct_k, g, blk, 0, s, n, sc, e, u, zb);
 }
 
 // Interior of u (FP64) from an initial guess of storage type T (boundary kept).
@@ -1022,28 +1110,33 @@ __global__ void guess_interior_k<double>(int n, const double *__restrict__ g, do
 void launch_guess_interior(int n, const void *g, int kind, double *u, hipStream_t s)
 {
     dim3 blk(64, 2, 2);
-    if (kind == 1) hipLaunchKernelGGL(guess_interior_k<double>, grid3(n - 2, blk), blk, 0, s, n, (const double *)g, u);
-    else if (kind == 2) hipLaunchKernelGGL(guess_interior_k<float>, grid3(n - 2, blk), blk, 0, s, n, (const float *)g, u);
-    else hipLaunchKernelGGL(guess_interior_k<__bf16>, grid3(n - 2, blk), blk, 0, s, n, (const __bf16 *)g, u);
+    int zb;
+    const dim3 gr = grid3(n - 2, blk, 1, zb);
+    if (kind == 1) hipLaunchKernelGGL(guess_interior_k<double>, gr, blk, 0, s, n, (const double *)g, u);
+    else if (kind == 2) hipLaunchKernelGGL(guess_interior_k<float>, gr, blk, 0, s, n, (const float *)g, u);
+    else hipLaunchKernelGGL(guess_interior_k<__bf16>, gr, blk, 0, s, n, (const __bf16 *)g, u);
 }
 
 // -------------------------------------------------------- instantiations
 #define QM_INST(T)                                                                                              \
-    template void launch_rbgs<T>(int, double, const T *, const T *, T *, hipStream_t);                         \
-    template void launch_rbgs_shape<T>(int, double, const T *, const T *, T *, SmootherShape, hipStream_t);     \
+    template void launch_rbgs<T>(int, double, const T *, const T *, T *, hipStream_t, int);                    \
+    template void launch_rbgs_shape<T>(int, double, const T *, const T *, T *, SmootherShape, hipStream_t, int);\
     template SmootherShape &rbgs_shape<T>(int);                                                                 \
     template SmootherShape &rbgs2_shape<T>(int);                                                                \
     template int &use_fused<T>(int);                                                                            \
-    template void launch_rbgs2<T>(int, double, const T *, const T *, T *, const T *, hipStream_t);             \
-    template void launch_residual_restrict<T>(int, double, const T *, const T *, T *, T *, T *, hipStream_t);  \
-    template void launch_restrict<T>(int, const T *, T *, hipStream_t);                                        \
-    template void launch_prolong_add<T>(int, const T *, T *, hipStream_t);                                     \
-    template void launch_interp<T>(int, const T *, T *, hipStream_t);                                          \
-    template void launch_inject_boundary<T>(int, const T *, int, T *, T *, hipStream_t);                       \
+    template void launch_rbgs2<T>(int, double, const T *, const T *, T *, const T *, hipStream_t, int);        \
+    template void launch_rbgs2_shape<T>(int, double, const T *, const T *, T *, const T *, SmootherShape,        \
+                                        hipStream_t, int);                                                      \
+    template void launch_residual_restrict<T>(int, double, const T *, const T *, T *, T *, T *, hipStream_t,    \
+                                              int);                                                             \
+    template void launch_restrict<T>(int, const T *, T *, hipStream_t, int);                                   \
+    template void launch_prolong_add<T>(int, const T *, T *, hipStream_t, int);                                \
+    template void launch_interp<T>(int, const T *, T *, hipStream_t, int);                                     \
+    template void launch_inject_boundary<T>(int, const T *, int, T *, T *, hipStream_t, int);                  \
     template void launch_fill<T>(T *, size_t, T, hipStream_t);                                                 \
     template void launch_boundary_copy<T>(int, const T *, T *, hipStream_t);                                   \
-    template void launch_coarse_tail<T>(int, double, const T *, T *, int, int, int, int, int, hipStream_t);    \
-    template void launch_resid_norms<T>(int, double, const T *, const T *, double *, double *, hipStream_t);
+    template void launch_coarse_tail<T>(int, double, const T *, T *, int, int, int, int, int, hipStream_t, int);\
+    template void launch_resid_norms<T>(int, double, const T *, const T *, double *, double *, hipStream_t, int);
 QM_INST(double)
 QM_INST(float)
 #undef QM_INST

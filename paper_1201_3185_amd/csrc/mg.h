@@ -8,6 +8,9 @@
 // Every level keeps two buffers for u because the smoother works out of place;
 // `cur` says which one holds the iterate.  Both buffers carry the level's
 // boundary values (Dirichlet values on FMG levels, zero on correction levels).
+//
+// A hierarchy can hold nb problems of the same size back to back on every
+// level; each launch then covers all of them.
 #pragma once
 #include <cmath>
 #include <vector>
@@ -64,9 +67,19 @@ struct SmootherProfile {
     }
 };
 
+// Smoother launch shapes chosen for one hierarchy (indexed by level), used in
+// place of the library-wide tables when set.
+struct LevelShapes {
+    SmootherShape single[11];
+    SmootherShape fused[11];
+    int use_fused[11];
+};
+
 template <typename T>
 struct Multigrid {
     int J = 0, lt = 0;
+    int nb = 1;                          // problems per level
+    const LevelShapes *shapes = nullptr;
     double L = 0.0;
     int npre = 2, npost = 2;
     std::vector<Level<T>> lv;  // index = level, n = 2^l + 1
@@ -89,9 +102,11 @@ struct Multigrid {
         return e;
     }
 
-    // Allocate the coarse levels lt..J-1 for a finest grid of n points per side.
-    hipError_t init(int n, int npre_, int npost_, hipStream_t stream)
+    // Allocate the coarse levels lt..J-1 for a finest grid of n points per side
+    // (nb problems per level).
+    hipError_t init(int n, int npre_, int npost_, hipStream_t stream, int nb_ = 1)
     {
+        nb = nb_;
         J = log2_exact(n - 1);
         lt = J < kTailLevel ? J : kTailLevel;
         npre = npre_;
@@ -100,16 +115,17 @@ struct Multigrid {
         lv.assign(J + 1, Level<T>());
         for (int l = 1; l <= J; ++l) lv[l].n = (1 << l) + 1;
         for (int l = lt; l < J; ++l) {
-            const size_t N = (size_t)lv[l].n * lv[l].n * lv[l].n;
+            const size_t N = (size_t)lv[l].n * lv[l].n * lv[l].n * nb;
             hipError_t e;
             if ((e = alloc((void **)&lv[l].u[0], N * sizeof(T))) != hipSuccess) return e;
             if ((e = alloc((void **)&lv[l].u[1], N * sizeof(T))) != hipSuccess) return e;
             if ((e = alloc((void **)&lv[l].f, N * sizeof(T))) != hipSuccess) return e;
         }
         hipError_t e;
-        if ((e = alloc((void **)&partial, 3 * kNormBlocks * sizeof(double))) != hipSuccess) return e;
-        if ((e = alloc((void **)&norms, 3 * sizeof(double))) != hipSuccess) return e;
-        if ((e = hipHostMalloc((void **)&host_norms, 3 * sizeof(double), hipHostMallocDefault)) != hipSuccess) return e;
+        if ((e = alloc((void **)&partial, 3 * (size_t)kNormBlocks * nb * sizeof(double))) != hipSuccess) return e;
+        if ((e = alloc((void **)&norms, 3 * (size_t)nb * sizeof(double))) != hipSuccess) return e;
+        if ((e = hipHostMalloc((void **)&host_norms, 3 * (size_t)nb * sizeof(double), hipHostMallocDefault)) != hipSuccess)
+            return e;
         return hipSuccess;
     }
 
@@ -154,18 +170,21 @@ struct Multigrid {
         Level<T> &v = lv[l];
         const double pts = (double)v.n * v.n * v.n;
         if (uc && ns < 2) {
-            launch_prolong_add<T>(lv[l - 1].n, uc, v.u[v.cur], s);
+            launch_prolong_add<T>(lv[l - 1].n, uc, v.u[v.cur], s, nb);
             uc = nullptr;
         }
+        const bool fuse = fused && (shapes ? shapes->use_fused[l] != 0 : use_fused<T>(v.n) != 0);
         while (ns > 0) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
-            time_begin(&e0, &e1, 3.0 * sizeof(T) * pts);
-            if (ns >= 2 && fused && use_fused<T>(v.n)) {
-                launch_rbgs2<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], uc, s);
+            time_begin(&e0, &e1, 3.0 * sizeof(T) * pts * nb);
+            if (ns >= 2 && fuse) {
+                const SmootherShape sh = shapes ? shapes->fused[l] : rbgs2_shape<T>(v.n);
+                launch_rbgs2_shape<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], uc, sh, s, nb);
                 ns -= 2;
             } else {
-                if (uc) launch_prolong_add<T>(lv[l - 1].n, uc, v.u[v.cur], s);
-                launch_rbgs<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], s);
+                if (uc) launch_prolong_add<T>(lv[l - 1].n, uc, v.u[v.cur], s, nb);
+                const SmootherShape sh = shapes ? shapes->single[l] : rbgs_shape<T>(v.n);
+                launch_rbgs_shape<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], sh, s, nb);
                 ns -= 1;
             }
             uc = nullptr;
@@ -180,8 +199,8 @@ struct Multigrid {
         Level<T> &v = lv[l];
         smooth(l, npre);
         Level<T> &c = lv[l - 1];
-        launch_residual_restrict<T>(v.n, v.h, v.f, v.u[v.cur], c.f, c.u[c.cur], c.u[1 - c.cur], s);
-        if (l - 1 == lt) launch_coarse_tail<T>(lt, L, c.f, c.u[c.cur], npre, npost, 1, 0, 1, s);
+        launch_residual_restrict<T>(v.n, v.h, v.f, v.u[v.cur], c.f, c.u[c.cur], c.u[1 - c.cur], s, nb);
+        if (l - 1 == lt) launch_coarse_tail<T>(lt, L, c.f, c.u[c.cur], npre, npost, 1, 0, 1, s, nb);
         else vcycle(l - 1);
         smooth(l, npost, c.u[c.cur]);
     }
@@ -190,7 +209,7 @@ struct Multigrid {
     void finest_cycle(int nrep = 1)
     {
         if (J <= lt) {
-            launch_coarse_tail<T>(J, L, lv[J].f, lv[J].u[lv[J].cur], npre, npost, 1, 0, nrep, s);
+            launch_coarse_tail<T>(J, L, lv[J].f, lv[J].u[lv[J].cur], npre, npost, 1, 0, nrep, s, nb);
             return;
         }
         for (int r = 0; r < nrep; ++r) vcycle(J);
@@ -202,27 +221,34 @@ struct Multigrid {
     {
         Level<T> &F = lv[J];
         if (J <= lt) {
-            launch_coarse_tail<T>(J, L, F.f, F.u[F.cur], npre, npost, ncycle, 1, 1, s);
+            launch_coarse_tail<T>(J, L, F.f, F.u[F.cur], npre, npost, ncycle, 1, 1, s, nb);
             return;
         }
-        for (int l = J - 1; l >= lt; --l) launch_restrict<T>(lv[l + 1].n, lv[l + 1].f, lv[l].f, s);
-        for (int l = lt; l < J; ++l) launch_inject_boundary<T>(F.n, F.u[F.cur], lv[l].n, lv[l].u[0], lv[l].u[1], s);
+        for (int l = J - 1; l >= lt; --l) launch_restrict<T>(lv[l + 1].n, lv[l + 1].f, lv[l].f, s, nb);
+        for (int l = lt; l < J; ++l)
+            launch_inject_boundary<T>(F.n, F.u[F.cur], lv[l].n, lv[l].u[0], lv[l].u[1], s, nb);
         Level<T> &t = lv[lt];
-        launch_coarse_tail<T>(lt, L, t.f, t.u[t.cur], npre, npost, ncycle, 1, 1, s);
+        launch_coarse_tail<T>(lt, L, t.f, t.u[t.cur], npre, npost, ncycle, 1, 1, s, nb);
         for (int l = lt + 1; l <= J; ++l) {
             Level<T> &c = lv[l - 1];
-            launch_interp<T>(c.n, c.u[c.cur], lv[l].u[lv[l].cur], s);
+            launch_interp<T>(c.n, c.u[c.cur], lv[l].u[lv[l].cur], s, nb);
             for (int k = 0; k < ncycle; ++k) vcycle(l);
         }
+    }
+
+    // Residual norms of the finest level of every problem into norms (device).
+    void device_norms()
+    {
+        Level<T> &F = lv[J];
+        launch_resid_norms<T>(F.n, F.h, F.f, F.u[F.cur], partial, norms, s, nb);
     }
 
     // Enqueue the residual norms of the finest level into host_norms (needs a
     // stream synchronisation before reading).
     void enqueue_norms()
     {
-        Level<T> &F = lv[J];
-        launch_resid_norms<T>(F.n, F.h, F.f, F.u[F.cur], partial, norms, s);
-        (void)hipMemcpyAsync(host_norms, norms, 3 * sizeof(double), hipMemcpyDeviceToHost, s);
+        device_norms();
+        (void)hipMemcpyAsync(host_norms, norms, 3 * (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, s);
     }
 
     hipError_t relres(double &out)
@@ -246,7 +272,7 @@ struct Multigrid {
     {
         Level<T> &F = lv[J];
         if (F.cur == 1) {
-            (void)hipMemcpyAsync(F.u[0], F.u[1], (size_t)F.n * F.n * F.n * sizeof(T), hipMemcpyDeviceToDevice, s);
+            (void)hipMemcpyAsync(F.u[0], F.u[1], (size_t)F.n * F.n * F.n * nb * sizeof(T), hipMemcpyDeviceToDevice, s);
             F.cur = 0;
         }
     }

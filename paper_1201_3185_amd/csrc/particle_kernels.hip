@@ -117,6 +117,93 @@ void launch_deposit(const DepositArgs &a, const double *x, const double *y, cons
     hipLaunchKernelGGL(deposit_reduce_k, dim3((kWin + 255) / 256, a.nbox), dim3(256), 0, s, a, (int)blocks);
 }
 
+// Batched single-box deposit: workgroup (g, p) takes a contiguous share of
+// problem p's particles, with the same LDS window, scratch slabs and integer
+// adds as above; problem p's grid starts at q + p n^3.
+__global__ void __launch_bounds__(kDepositThreads)
+deposit_batch_k(int n, BoxGeom g, int wx, int wy, int wz, const BatchProblem *__restrict__ prob,
+                unsigned long long *__restrict__ qall, unsigned long long *__restrict__ scratch,
+                unsigned long long *__restrict__ inside)
+{
+#pragma clang fp contract(off)
+    __shared__ unsigned long long W[kWin];
+    __shared__ unsigned int cnt_sh;
+    const int pb = blockIdx.y;
+    const BatchProblem P = prob[pb];
+    const int64_t per_block = (P.np + kBatchDepositBlocks - 1) / kBatchDepositBlocks;
+    const int64_t p0 = (int64_t)blockIdx.x * per_block;
+    const int64_t p1 = min((int64_t)P.np, p0 + per_block);
+    unsigned long long *q = qall + (size_t)pb * n * n * n;
+    if (threadIdx.x == 0) cnt_sh = 0;
+    for (int e = threadIdx.x; e < kWin; e += kDepositThreads) W[e] = 0ULL;
+    __syncthreads();
+    unsigned int in0 = 0;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += kDepositThreads) {
+        int ic[3];
+        double w[3][2];
+        if (!cic_cell(g, n, P.x[p], P.y[p], P.z[p], ic, w)) continue;
+        ++in0;
+        const double pm = P.m[p];
+        const int lx = ic[0] - wx, ly = ic[1] - wy, lz = ic[2] - wz;
+        const bool inwin = lx >= 0 && lx < kWinX - 1 && ly >= 0 && ly < kWinY - 1 && lz >= 0 && lz < kWinZ - 1;
+        for (int c = 0; c < 2; ++c)
+            for (int bb = 0; bb < 2; ++bb)
+                for (int a = 0; a < 2; ++a) {
+                    const double wt = (w[0][a] * w[1][bb]) * w[2][c];
+                    const unsigned long long qv = (unsigned long long)__double2ll_rn((wt * pm) * P.scale);
+                    if (inwin) atomicAdd(&W[(lx + a) + kWinX * ((ly + bb) + kWinY * (lz + c))], qv);
+                    else atomicAdd(q + id3(n, ic[0] + a, ic[1] + bb, ic[2] + c), qv);
+                }
+    }
+    __syncthreads();
+    unsigned long long *slab = scratch + ((size_t)pb * kBatchDepositBlocks + blockIdx.x) * kWin;
+    for (int e = threadIdx.x; e < kWin; e += kDepositThreads) slab[e] = W[e];
+    atomicAdd(&cnt_sh, in0);
+    __syncthreads();
+    if (threadIdx.x == 0 && cnt_sh) atomicAdd(inside + pb, (unsigned long long)cnt_sh);
+}
+
+__global__ void __launch_bounds__(256)
+deposit_batch_reduce_k(int n, int wx, int wy, int wz, unsigned long long *__restrict__ qall,
+                       const unsigned long long *__restrict__ scratch)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int pb = blockIdx.y;
+    if (e >= kWin) return;
+    const int li = e % kWinX, lj = (e / kWinX) % kWinY, lk = e / (kWinX * kWinY);
+    const int i = wx + li, j = wy + lj, k = wz + lk;
+    if (i >= n || j >= n || k >= n) return;
+    unsigned long long s = 0ULL;
+    for (int g = 0; g < kBatchDepositBlocks; ++g) s += scratch[((size_t)pb * kBatchDepositBlocks + g) * kWin + e];
+    if (s) qall[(size_t)pb * n * n * n + id3(n, i, j, k)] += s;
+}
+
+size_t deposit_batch_scratch_bytes(int nb)
+{
+    return (size_t)nb * kBatchDepositBlocks * kWin * sizeof(unsigned long long);
+}
+
+void launch_deposit_batch(int n, double L, const BatchProblem *prob, long long maxnp, unsigned long long *q,
+                          unsigned long long *scratch, unsigned long long *inside, int nb, hipStream_t s)
+{
+    (void)maxnp;
+    BoxGeom g;
+    g.L = L;
+    g.xmin = -0.5 * L;
+    g.inv_h = (double)(n - 1) / L;
+    g.h = L / (double)(n - 1);
+    const int win[3] = {kWinX, kWinY, kWinZ};
+    int w0[3];
+    for (int d = 0; d < 3; ++d) {
+        const int o = (n - 1) / 2 - win[d] / 2;
+        w0[d] = o < 0 ? 0 : o;
+    }
+    hipLaunchKernelGGL(deposit_batch_k, dim3(kBatchDepositBlocks, nb), dim3(kDepositThreads), 0, s, n, g, w0[0], w0[1],
+                       w0[2], prob, q, scratch, inside);
+    hipLaunchKernelGGL(deposit_batch_reduce_k, dim3((kWin + 255) / 256, nb), dim3(256), 0, s, n, w0[0], w0[1], w0[2], q,
+                       scratch);
+}
+
 __global__ void rhs_from_q_k(size_t count, double inv_h3, double four_pi_G, int shift, const long long *__restrict__ q,
                              double *__restrict__ f)
 {
@@ -135,6 +222,29 @@ void launch_rhs_from_q(int n, double h, double four_pi_G, int shift, const long 
                        shift, q, f);
 }
 
+// Problem blockIdx.y; q and f may alias (each element is read before it is written).
+__global__ void rhs_batch_k(size_t count, double inv_h3, double four_pi_G, const BatchProblem *__restrict__ prob,
+                            const long long *q, double *f)
+{
+    const int shift = prob[blockIdx.y].shift;
+    q += blockIdx.y * count;
+    f += blockIdx.y * count;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < count; t += (size_t)gridDim.x * blockDim.x) {
+        const double rho = ldexp((double)q[t], -shift) * inv_h3;
+        f[t] = four_pi_G * rho;
+    }
+}
+
+void launch_rhs_batch(int n, double h, double four_pi_G, const BatchProblem *prob, const long long *q, double *f, int nb,
+                      hipStream_t s)
+{
+    const size_t count = (size_t)n * n * n;
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(rhs_batch_k, dim3((unsigned)blocks, nb), dim3(256), 0, s, count, 1.0 / (h * h * h), four_pi_G,
+                       prob, q, f);
+}
+
 // ------------------------------------------------------------------- gather
 
 // -d Phi / d x_d at node (i,j,k): central difference inside, one-sided second
@@ -151,35 +261,33 @@ __device__ __forceinline__ double node_accel(const double *__restrict__ P, int n
     return -g * inv2h;
 }
 
-__device__ int gather_point(const GatherArgs &A, double px, double py, double pz, double acc[3])
+// Point-mass force (QUMOND: nu(g_N/a0) g_N) for points outside every box.
+__device__ __forceinline__ void monopole_accel(double GM, double a0, int mond, double px, double py, double pz,
+                                               double acc[3])
 {
-    const double R = sqrt(px * px + py * py), az = fabs(pz);
-    int sel = -1;
-    for (int b = A.nbox - 1; b >= 0; --b)
-        if (R < A.frac * A.box[b].L && az < A.frac * A.box[b].L) { sel = b; break; }
-    const double top = (double)(A.n - 1);
-    if (sel < 0) {
-        for (int b = 0; b < A.nbox; ++b) {
-            const double ux = (px - A.box[b].xmin) * A.box[b].inv_h, uy = (py - A.box[b].xmin) * A.box[b].inv_h,
-                         uz = (pz - A.box[b].xmin) * A.box[b].inv_h;
-            if (ux >= 0.0 && ux < top && uy >= 0.0 && uy < top && uz >= 0.0 && uz < top) { sel = b; break; }
-        }
+    const double r = sqrt(px * px + py * py + pz * pz);
+    double g = 0.0;
+    if (r > 0.0) {
+        const double gN = GM / (r * r);
+        g = (mond && a0 > 0.0) ? (0.5 + 0.5 * sqrt(1.0 + 4.0 * a0 / gN)) * gN : gN;
+        g /= r;
     }
-    if (sel < 0) {
-        const double r = sqrt(px * px + py * py + pz * pz);
-        double g = 0.0;
-        if (r > 0.0) {
-            const double gN = A.GM / (r * r);
-            g = (A.mond && A.a0 > 0.0) ? (0.5 + 0.5 * sqrt(1.0 + 4.0 * A.a0 / gN)) * gN : gN;
-            g /= r;
-        }
-        acc[0] = -g * px;
-        acc[1] = -g * py;
-        acc[2] = -g * pz;
-        return 255;
-    }
-    const BoxGeom G = A.box[sel];
-    const int n = A.n;
+    acc[0] = -g * px;
+    acc[1] = -g * py;
+    acc[2] = -g * pz;
+}
+
+__device__ __forceinline__ bool in_box(const BoxGeom &G, int n, double px, double py, double pz)
+{
+    const double top = (double)(n - 1);
+    const double ux = (px - G.xmin) * G.inv_h, uy = (py - G.xmin) * G.inv_h, uz = (pz - G.xmin) * G.inv_h;
+    return ux >= 0.0 && ux < top && uy >= 0.0 && uy < top && uz >= 0.0 && uz < top;
+}
+
+// Cloud-in-cell interpolation of the nodal accelerations of box G.
+__device__ void box_accel(const BoxGeom &G, int n, const double *__restrict__ P, double px, double py, double pz,
+                          double acc[3])
+{
     const double u[3] = {(px - G.xmin) * G.inv_h, (py - G.xmin) * G.inv_h, (pz - G.xmin) * G.inv_h};
     int ic[3];
     double w[3][2];
@@ -191,7 +299,6 @@ __device__ int gather_point(const GatherArgs &A, double px, double py, double pz
         w[d][1] = fr;
     }
     const double inv2h = 0.5 * G.inv_h;
-    const double *P = A.phi[sel];
     acc[0] = acc[1] = acc[2] = 0.0;
     for (int c = 0; c < 2; ++c)
         for (int b = 0; b < 2; ++b)
@@ -199,6 +306,23 @@ __device__ int gather_point(const GatherArgs &A, double px, double py, double pz
                 const double wt = (w[0][a] * w[1][b]) * w[2][c];
                 for (int d = 0; d < 3; ++d) acc[d] += wt * node_accel(P, n, inv2h, ic[0] + a, ic[1] + b, ic[2] + c, d);
             }
+}
+
+__device__ int gather_point(const GatherArgs &A, double px, double py, double pz, double acc[3])
+{
+    const double R = sqrt(px * px + py * py), az = fabs(pz);
+    int sel = -1;
+    for (int b = A.nbox - 1; b >= 0; --b)
+        if (R < A.frac * A.box[b].L && az < A.frac * A.box[b].L) { sel = b; break; }
+    if (sel < 0) {
+        for (int b = 0; b < A.nbox; ++b)
+            if (in_box(A.box[b], A.n, px, py, pz)) { sel = b; break; }
+    }
+    if (sel < 0) {
+        monopole_accel(A.GM, A.a0, A.mond, px, py, pz, acc);
+        return 255;
+    }
+    box_accel(A.box[sel], A.n, A.phi[sel], px, py, pz, acc);
     return sel;
 }
 
@@ -252,6 +376,51 @@ void launch_rotation_curve(const GatherArgs &a, const double *R, int nR, int naz
 {
     if (nR <= 0) return;
     hipLaunchKernelGGL(rotation_curve_k, dim3(nR), dim3(256), 0, s, a, R, naz, vc2);
+}
+
+// Batched single-box curves: workgroup (r, p), same sampling and order as rotation_curve_k.
+__global__ void __launch_bounds__(256)
+rotation_curve_batch_k(int n, BoxGeom G, double frac, double Gc, double a0, int mond,
+                       const BatchProblem *__restrict__ prob, const double *__restrict__ phi, const double *__restrict__ R,
+                       int nR, int naz, double *__restrict__ vc2)
+{
+    __shared__ double sh[256];
+    const int pb = blockIdx.y;
+    const double *P = phi + (size_t)pb * n * n * n;
+    const double GM = Gc * prob[pb].mass;
+    const double r = R[blockIdx.x];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < naz; k += 256) {
+        const double ph = 2.0 * M_PI * (double)k / (double)naz;
+        const double px = r * cos(ph), py = r * sin(ph);
+        double acc[3];
+        // the box-choice rule of gather_point with one box
+        const double Rp = sqrt(px * px + py * py);
+        if ((Rp < frac * G.L && 0.0 < frac * G.L) || in_box(G, n, px, py, 0.0)) box_accel(G, n, P, px, py, 0.0, acc);
+        else monopole_accel(GM, a0, mond, px, py, 0.0, acc);
+        s += -(px * acc[0] + py * acc[1]);
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) vc2[(size_t)pb * nR + blockIdx.x] = sh[0] / (double)naz;
+}
+
+void launch_rotation_curve_batch(int n, double L, double frac, double G, double a0, int mond,
+                                 const BatchProblem *prob, const double *phi, const double *R, int nR, int naz,
+                                 double *vc2, int nb, hipStream_t s)
+{
+    if (nR <= 0 || nb <= 0) return;
+    BoxGeom g;
+    g.L = L;
+    g.xmin = -0.5 * L;
+    g.inv_h = (double)(n - 1) / L;
+    g.h = L / (double)(n - 1);
+    hipLaunchKernelGGL(rotation_curve_batch_k, dim3(nR, nb), dim3(256), 0, s, n, g, frac, G, a0, mond, prob, phi, R, nR,
+                       naz, vc2);
 }
 
 }  // namespace qm

@@ -5,6 +5,7 @@
 // component the mean of the central differences at p and q, flux
 // F = nu(|g|/a0) g_n = g_n (1 + sqrt(1 + 4 a0/|g|)) / 2 (0 where |g| = 0, the
 // limit of nu g), and S(p) = sum_d (F(p + e_d/2) - F(p - e_d/2)) / h.
+// Batches of problems stored back to back are covered by the z block index.
 #include "common.h"
 
 namespace qm {
@@ -21,12 +22,15 @@ __device__ __forceinline__ double face_flux(const double *__restrict__ P, size_t
 }
 
 __global__ void __launch_bounds__(256)
-mond_source_k(int n, double ih, double a0, const double *__restrict__ P, double *__restrict__ S)
+mond_source_k(int n, double ih, double a0, const double *__restrict__ P, double *__restrict__ S, int zb)
 {
+    const int pb = blockIdx.z / zb;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    const int k = (blockIdx.z - pb * zb) * blockDim.z + threadIdx.z;
     if (i >= n || j >= n || k >= n) return;
+    P += pb * (size_t)n * n * n;
+    S += pb * (size_t)n * n * n;
     const size_t p = id3(n, i, j, k);
     if (i == 0 || j == 0 || k == 0 || i == n - 1 || j == n - 1 || k == n - 1) {
         S[p] = 0.0;
@@ -39,11 +43,12 @@ mond_source_k(int n, double ih, double a0, const double *__restrict__ P, double 
     S[p] = s * ih;
 }
 
-void launch_mond_source(int n, double h, double a0, const double *phin, double *S, hipStream_t s)
+void launch_mond_source(int n, double h, double a0, const double *phin, double *S, hipStream_t s, int nb)
 {
     dim3 blk(64, 2, 2);
-    dim3 grid((n + 63) / 64, (n + 1) / 2, (n + 1) / 2);
-    hipLaunchKernelGGL(mond_source_k, grid, blk, 0, s, n, 1.0 / h, a0, phin, S);
+    const int zb = (n + 1) / 2;
+    dim3 grid((n + 63) / 64, (n + 1) / 2, zb * nb);
+    hipLaunchKernelGGL(mond_source_k, grid, blk, 0, s, n, 1.0 / h, a0, phin, S, zb);
 }
 
 }  // namespace qm

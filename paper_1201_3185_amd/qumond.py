@@ -1,4 +1,5 @@
-"""Thin ctypes binding of libqumond.so (include/qumond.h, include/qumond_kernels.h).
+"""Thin ctypes binding of libqumond.so (include/qumond.h, qumond_kernels.h,
+qumond_tune.h, qumond_unet.h, qumond_batch.h).
 
 Argument marshalling only: torch tensors supply device memory and the HIP
 stream (``torch.cuda.current_stream()``); every step of the solve runs in the
@@ -50,6 +51,23 @@ class qumond_solve_info(ctypes.Structure):
         return {"vcycles": list(self.vcycles[:nb]), "converged": list(self.converged[:nb]),
                 "refine_iters": list(self.refine_iters[:nb]), "relres0": list(self.relres0[:nb]),
                 "relres": list(self.relres[:nb]), "used_fallback": int(self.used_fallback)}
+
+
+class qumond_batch_config(ctypes.Structure):
+    _fields_ = [
+        ("nprob", ctypes.c_int32), ("box_side", ctypes.c_double), ("G", ctypes.c_double), ("a0", ctypes.c_double),
+        ("npre", ctypes.c_int32), ("npost", ctypes.c_int32), ("ncycle_fmg", ctypes.c_int32),
+        ("refine_iters", ctypes.c_int32), ("max_extra", ctypes.c_int32), ("tol_rel", ctypes.c_double),
+        ("gather_frac", ctypes.c_double), ("naz", ctypes.c_int32), ("autotune", ctypes.c_int32),
+    ]
+
+
+class qumond_batch_problem_info(ctypes.Structure):
+    _fields_ = [
+        ("relres_newton", ctypes.c_double), ("relres_mond", ctypes.c_double), ("steps_newton", ctypes.c_int32),
+        ("steps_mond", ctypes.c_int32), ("converged", ctypes.c_int32), ("redone", ctypes.c_int32),
+        ("n_inside", ctypes.c_int64),
+    ]
 
 
 class qumond_kernel_stats(ctypes.Structure):
@@ -107,6 +125,16 @@ _SIGNATURES = {
     "qumond_k_rbgs_sweep_shape": (_I32, [_I32, _D, _P, _P, _P, _I32, _I32, _P]),
     "qumond_autotune": (_I32, [_I32, _I32, _I32, ctypes.c_char_p, ctypes.POINTER(_D), _P]),
     "qumond_tune_load": (_I32, [ctypes.c_char_p]),
+    "qumond_batch_default_config": (None, [ctypes.POINTER(qumond_batch_config)]),
+    "qumond_batch_validate": (_I32, [ctypes.POINTER(qumond_batch_config), _P, _P, _I32]),
+    "qumond_batch_create": (_I32, [ctypes.POINTER(qumond_batch_config), _P, _P, _I32, _P, ctypes.POINTER(_P)]),
+    "qumond_batch_destroy": (_I32, [_P]),
+    "qumond_batch_set_particles": (_I32, [_P, _I32, _P, _P, _P, _P, _I64, _D]),
+    "qumond_batch_run": (_I32, [_P, _I32, _P]),
+    "qumond_batch_rotation_curves": (_I32, [_P, _I32, _P]),
+    "qumond_batch_get_field": (_I32, [_P, _I32, _I32, _P]),
+    "qumond_batch_describe": (_I32, [_P, ctypes.c_char_p, _I64]),
+    "qumond_batch_device_bytes": (_I64, [_P]),
 }
 
 _lib = None
@@ -508,3 +536,117 @@ def k_conv3d_wgrad(n_in, cin, x, cout, dy, stride=1):
     check(lib().qumond_k_conv3d_wgrad(n_in, cin, _ptr(x), cout, _ptr(dy), stride, _ptr(dw), _s()),
           "qumond_k_conv3d_wgrad")
     return dw
+
+
+# ------------------------------------------------------------- batches
+
+@dataclass
+class BatchConfig:
+    """Mirror of qumond_batch_config (defaults from qumond_batch_default_config)."""
+    box_side: float = 120.0
+    G: float = 4.300917270e-6
+    a0: float = 3600.0
+    npre: int = 2
+    npost: int = 2
+    ncycle_fmg: int = 2
+    refine_iters: int = 4
+    max_extra: int = 20
+    tol_rel: float = 1e-6
+    gather_frac: float = 0.2
+    naz: int = 16
+    autotune: bool = False
+
+    def to_c(self, nprob: int) -> qumond_batch_config:
+        c = qumond_batch_config()
+        lib().qumond_batch_default_config(ctypes.byref(c))
+        c.nprob = int(nprob)
+        for k in ("box_side", "G", "a0", "tol_rel", "gather_frac"):
+            setattr(c, k, float(getattr(self, k)))
+        for k in ("npre", "npost", "ncycle_fmg", "refine_iters", "max_extra", "naz"):
+            setattr(c, k, int(getattr(self, k)))
+        c.autotune = int(bool(self.autotune))
+        return c
+
+
+def batch_validate(cfg: BatchConfig, n_per_problem, R) -> int:
+    ns = (ctypes.c_int32 * len(n_per_problem))(*[int(v) for v in n_per_problem])
+    rr = (ctypes.c_double * max(1, len(R)))(*[float(v) for v in R])
+    c = cfg.to_c(len(n_per_problem))
+    return int(lib().qumond_batch_validate(ctypes.byref(c), ns, rr if len(R) else None, len(R)))
+
+
+class Batch:
+    """Many single-box disks solved together (include/qumond_batch.h)."""
+
+    def __init__(self, cfg: BatchConfig, n_per_problem, R, stream: Optional[torch.cuda.Stream] = None):
+        self.cfg = cfg
+        self.n_of = [int(v) for v in n_per_problem]
+        self.nprob = len(self.n_of)
+        self.R = [float(v) for v in R]
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        ns = (ctypes.c_int32 * self.nprob)(*self.n_of)
+        rr = (ctypes.c_double * len(self.R))(*self.R)
+        self._c = cfg.to_c(self.nprob)
+        h = ctypes.c_void_p()
+        check(lib().qumond_batch_create(ctypes.byref(self._c), ns, rr, len(self.R),
+                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+              "qumond_batch_create")
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().qumond_batch_destroy(self._h)
+            self._h = None
+        self._keep = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def device_bytes(self) -> int:
+        return int(lib().qumond_batch_device_bytes(self._h))
+
+    def set_particles(self, p: int, x, y, z, m, total_mass: Optional[float] = None):
+        np_ = x.numel()
+        for t, nm in ((x, "x"), (y, "y"), (z, "z"), (m, "m")):
+            _f64(t, nm)
+            if t.numel() != np_:
+                raise ValueError("particle arrays differ in length")
+        if total_mass is None:
+            total_mass = float(m.sum().item())
+        check(lib().qumond_batch_set_particles(self._h, int(p), _ptr(x), _ptr(y), _ptr(z), _ptr(m), np_,
+                                               float(total_mass)), "qumond_batch_set_particles")
+        self._keep[int(p)] = (x, y, z, m)   # the batch reads them at every run
+
+    def run(self, use_graph: bool = True, allow_not_converged: bool = False) -> List[dict]:
+        info = (qumond_batch_problem_info * self.nprob)()
+        check(lib().qumond_batch_run(self._h, int(bool(use_graph)), info), "qumond_batch_run",
+              allow=(QUMOND_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+        return [{k: getattr(i, k) for k, _ in qumond_batch_problem_info._fields_} for i in info]
+
+    def rotation_curves(self, mond: bool = True) -> torch.Tensor:
+        out = torch.empty((self.nprob, len(self.R)), dtype=torch.float64, device="cuda")
+        check(lib().qumond_batch_rotation_curves(self._h, int(bool(mond)), _ptr(out)), "qumond_batch_rotation_curves")
+        return out
+
+    def get_field(self, p: int, fld: int) -> torch.Tensor:
+        n = self.n_of[p]
+        out = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+        check(lib().qumond_batch_get_field(self._h, int(p), int(fld), _ptr(out)), "qumond_batch_get_field")
+        return out
+
+    def describe(self) -> dict:
+        import json
+        buf = ctypes.create_string_buffer(1 << 16)
+        check(lib().qumond_batch_describe(self._h, buf, len(buf)), "qumond_batch_describe")
+        return json.loads(buf.value.decode())

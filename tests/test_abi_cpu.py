@@ -83,3 +83,47 @@ def test_null_handles_and_arguments(Q):
     assert L.qumond_k_rbgs_sweep(64, 1.0, None, None, None, None) == Q.QUMOND_ERR_INVALID
     assert L.qumond_k_fmg(33, 1.0, None, None, 2, 2, 6, 0, 0.0, None, None, None) == Q.QUMOND_ERR_INVALID
     assert L.qumond_status_string(Q.QUMOND_ERR_STATE) == b"call out of order"
+
+
+# ------------------------------------------------------------ batches
+
+def _batch_args(Q, cfg, ns, R):
+    c = cfg.to_c(len(ns))
+    return c, (ctypes.c_int32 * len(ns))(*ns), (ctypes.c_double * max(1, len(R)))(*R)
+
+
+def test_batch_defaults(Q):
+    c = Q.qumond_batch_config()
+    Q.lib().qumond_batch_default_config(ctypes.byref(c))
+    assert (c.npre, c.npost, c.ncycle_fmg, c.refine_iters, c.naz) == (2, 2, 2, 4, 16)
+    assert c.tol_rel == 1e-6 and c.box_side == 120.0 and c.a0 == 3600.0
+    assert Q.batch_validate(Q.BatchConfig(), [129, 257, 129], [1.0, 2.0]) == Q.QUMOND_OK
+
+
+@pytest.mark.parametrize("ns,R,change", [
+    ([130], [1.0], {}), ([9], [1.0], {}), ([2049], [1.0], {}), ([129], [], {}), ([129], [-1.0], {}),
+    ([129], [float("nan")], {}), ([257] * 600, [1.0], {}), ([129], [1.0], dict(box_side=0.0)),
+    ([129], [1.0], dict(G=-1.0)), ([129], [1.0], dict(npre=0, npost=0)), ([129], [1.0], dict(ncycle_fmg=0)),
+    ([129], [1.0], dict(refine_iters=-1)), ([129], [1.0], dict(max_extra=-1)), ([129], [1.0], dict(tol_rel=-1.0)),
+    ([129], [1.0], dict(gather_frac=0.6)), ([129], [1.0], dict(naz=0)),
+])
+def test_batch_invalid_rejected_without_gpu(Q, ns, R, change):
+    cfg = Q.BatchConfig(**change)
+    c, nn, rr = _batch_args(Q, cfg, ns, R)
+    assert Q.lib().qumond_batch_validate(ctypes.byref(c), nn, rr if R else None, len(R)) == Q.QUMOND_ERR_INVALID
+    h = ctypes.c_void_p()
+    assert Q.lib().qumond_batch_create(ctypes.byref(c), nn, rr if R else None, len(R), None,
+                                       ctypes.byref(h)) == Q.QUMOND_ERR_INVALID
+    assert not h.value and len(Q.lib().qumond_last_error()) > 0
+
+
+def test_batch_null_handles(Q):
+    L = Q.lib()
+    assert L.qumond_batch_destroy(None) == Q.QUMOND_OK
+    assert L.qumond_batch_run(None, 1, None) == Q.QUMOND_ERR_INVALID
+    assert L.qumond_batch_set_particles(None, 0, None, None, None, None, 0, 1.0) == Q.QUMOND_ERR_INVALID
+    assert L.qumond_batch_rotation_curves(None, 1, None) == Q.QUMOND_ERR_INVALID
+    assert L.qumond_batch_get_field(None, 0, Q.FIELD_PHI, None) == Q.QUMOND_ERR_INVALID
+    assert L.qumond_batch_device_bytes(None) == 0
+    c = Q.BatchConfig().to_c(1)
+    assert L.qumond_batch_validate(ctypes.byref(c), None, None, 0) == Q.QUMOND_ERR_INVALID

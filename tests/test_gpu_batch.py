@@ -1,0 +1,245 @@
+"""Batched solves of many disks (include/qumond_batch.h) through the C ABI.
+
+* Every problem of a batch equals, bit for bit, the single-problem context
+  (one box, mixed precision, the same FP32 FMG cycles and refinement steps):
+  the same kernels with the same arithmetic, whatever the smoother shapes
+  (also after the per-batch autotuner has changed them).
+* The captured graph, replayed several times with other GPU work and host
+  synchronisations in between, reproduces the direct launches bit for bit.
+* Against the FP64 oracle: the deposit's right-hand side to rounding, the
+  residual of the batch's potentials under the oracle's own operator below
+  the tolerance, and the potentials close to the oracle's FP64 FMG solution.
+* The tail check: with no refinement steps in the graph every problem is
+  brought to tolerance afterwards (and its QUMOND part redone).
+* The batched fit's workload: 64 disks of 129^3 and 257^3, sampled problems
+  checked against the single-problem context and the oracle's residual.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1201_3185_amd import qumond as Q
+from paper_1201_3185_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+L_BOX = 120.0
+R_CURVE = [0.5 * k for k in range(1, 41)]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def small_disks(ns, count_scale=1.0, seed0=900):
+    """Two-component disks with the fit's parameter ranges, fewer particles."""
+    params = synth.fit_grid(len(ns), config=4, n_choices=(129,))
+    out = []
+    for r, dp in enumerate(params):
+        dp.n_particles = int(20000 * count_scale) + 1000 * r
+        dp.seed = seed0 + r
+        p = dp.particles()
+        out.append(p)
+    return out
+
+
+def make_batch(ns, parts, **kw):
+    cfg = Q.BatchConfig(box_side=L_BOX, **kw)
+    b = Q.Batch(cfg, ns, R_CURVE)
+    for i, p in enumerate(parts):
+        b.set_particles(i, dev(p.x), dev(p.y), dev(p.z), dev(p.m), p.total_mass)
+    return b
+
+
+def solo(n, p, K, ncycle=2, mass=None):
+    cfg = Q.Config(n=n, box_side=[L_BOX], precision=Q.QUMOND_MIXED, ncycle_fmg=ncycle, tol_rel=1e-300,
+                   max_vcycles=K)
+    ctx = Q.Context(cfg)
+    ctx.deposit(dev(p.x), dev(p.y), dev(p.z), dev(p.m), p.total_mass if mass is None else mass)
+    ctx.solve_newton(allow_not_converged=True)
+    ctx.mond_source()
+    ctx.solve_mond(allow_not_converged=True)
+    Rt = dev(R_CURVE)
+    out = {k: ctx.get_field(0, f).cpu().numpy() for k, f in
+           (("f", Q.FIELD_RHS), ("phin", Q.FIELD_PHI_N), ("S", Q.FIELD_SOURCE), ("phi", Q.FIELD_PHI))}
+    out["vc2_n"] = ctx.rotation_curve(Rt, 16, 0).cpu().numpy()
+    out["vc2_m"] = ctx.rotation_curve(Rt, 16, 1).cpu().numpy()
+    ctx.close()
+    return out
+
+
+def batch_fields(b, p):
+    return {k: b.get_field(p, f).cpu().numpy() for k, f in
+            (("f", Q.FIELD_RHS), ("phin", Q.FIELD_PHI_N), ("S", Q.FIELD_SOURCE), ("phi", Q.FIELD_PHI))}
+
+
+NS_MIXED = [33, 65, 33, 17, 65]
+
+
+@pytest.fixture(scope="module")
+def mixed_batch():
+    parts = small_disks(NS_MIXED)
+    b = make_batch(NS_MIXED, parts, refine_iters=4, max_extra=0)
+    info = b.run(use_graph=False, allow_not_converged=True)
+    return parts, b, info
+
+
+@pytest.mark.parametrize("p", range(len(NS_MIXED)))
+def test_batch_equals_single_problem_bitwise(mixed_batch, p):
+    parts, b, info = mixed_batch
+    ref = solo(NS_MIXED[p], parts[p], 4)
+    got = batch_fields(b, p)
+    for k in ("f", "phin", "S", "phi"):
+        assert np.array_equal(got[k], ref[k]), f"{k} differs for problem {p} (n={NS_MIXED[p]})"
+    assert np.array_equal(b.rotation_curves(False).cpu().numpy()[p], ref["vc2_n"])
+    assert np.array_equal(b.rotation_curves(True).cpu().numpy()[p], ref["vc2_m"])
+    assert info[p]["n_inside"] == parts[p].n
+    assert info[p]["steps_newton"] == 4 and info[p]["steps_mond"] == 4
+
+
+def test_graph_replays_equal_direct_launches(mixed_batch):
+    parts, b, _ = mixed_batch
+    ref = [batch_fields(b, p) for p in range(len(NS_MIXED))]
+    ref_vc = b.rotation_curves(True).cpu().numpy()
+    for rep in range(3):
+        # other work on the device and host synchronisations between replays
+        junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        (junk * 2.0).sum().item()
+        torch.cuda.synchronize()
+        b.run(use_graph=True, allow_not_converged=True)
+        torch.cuda.synchronize()
+        for p in range(len(NS_MIXED)):
+            got = batch_fields(b, p)
+            for k in ("f", "phin", "S", "phi"):
+                assert np.array_equal(got[k], ref[p][k]), f"replay {rep}: {k} differs for problem {p}"
+        assert np.array_equal(b.rotation_curves(True).cpu().numpy(), ref_vc)
+    assert b.describe()["graph_nodes"] > 50
+
+
+def test_replay_picks_up_new_particles(mixed_batch):
+    parts, b, _ = mixed_batch
+    b.run(use_graph=True, allow_not_converged=True)
+    # new particles for problem 1 (same buffers' shapes, new arrays): no new capture needed
+    p_new = synth.two_component_disk(15000, 4242)
+    b.set_particles(1, dev(p_new.x), dev(p_new.y), dev(p_new.z), dev(p_new.m), p_new.total_mass)
+    b.run(use_graph=True, allow_not_converged=True)
+    ref = solo(NS_MIXED[1], p_new, 4)
+    assert np.array_equal(b.get_field(1, Q.FIELD_PHI).cpu().numpy(), ref["phi"])
+    b.set_particles(1, dev(parts[1].x), dev(parts[1].y), dev(parts[1].z), dev(parts[1].m), parts[1].total_mass)
+
+
+def test_autotuned_shapes_keep_results_bitwise():
+    ns = [65, 65, 33]
+    parts = small_disks(ns, seed0=700)
+    b0 = make_batch(ns, parts, refine_iters=3, max_extra=0)
+    b0.run(use_graph=False, allow_not_converged=True)
+    b1 = make_batch(ns, parts, refine_iters=3, max_extra=0, autotune=True)
+    b1.run(use_graph=True, allow_not_converged=True)
+    d = b1.describe()
+    assert d["tuned"] == 1 and all(c["shapes"] for c in d["classes"])
+    for p in range(len(ns)):
+        assert np.array_equal(b0.get_field(p, Q.FIELD_PHI).cpu().numpy(), b1.get_field(p, Q.FIELD_PHI).cpu().numpy())
+
+
+def test_batch_against_oracle():
+    ns = [33, 65]
+    parts = small_disks(ns, seed0=500)
+    b = make_batch(ns, parts, refine_iters=4, max_extra=20, tol_rel=1e-6)
+    info = b.run(use_graph=True)
+    for p, n in enumerate(ns):
+        assert info[p]["converged"] == 1
+        oc = O.OracleConfig(n=n, box_side=[L_BOX], tol_rel=1e-10)
+        o = O.run_pipeline(oc, parts[p].x, parts[p].y, parts[p].z, parts[p].m, parts[p].total_mass)
+        g = batch_fields(b, p)
+        h = L_BOX / (n - 1)
+        assert rel(g["f"], o.f[0]) <= 1e-15
+        for u, f in ((g["phin"], o.f[0]), (g["phi"], g["S"])):
+            r = O.residual(f, u, h)
+            rr = np.sqrt((r ** 2).sum() / (f[1:-1, 1:-1, 1:-1] ** 2).sum())
+            assert rr <= 1e-6
+        # the source from the batch's Phi_N under the oracle's Eq. 2 discretisation
+        assert rel(g["S"], O.mond_source(g["phin"], L_BOX)) <= 1e-12
+        assert rel(g["phin"], o.phin[0]) <= 1e-5
+        assert rel(g["phi"], o.phi[0]) <= 1e-5
+
+
+def test_tail_check_converges_every_problem():
+    ns = [33, 33, 65]
+    parts = small_disks(ns, seed0=300)
+    b = make_batch(ns, parts, refine_iters=0, max_extra=30, tol_rel=1e-7)
+    info = b.run(use_graph=True)
+    for p in range(len(ns)):
+        assert info[p]["converged"] == 1
+        assert info[p]["steps_newton"] > 0 and info[p]["redone"] == 1
+        assert info[p]["relres_newton"] <= 1e-7 and info[p]["relres_mond"] <= 1e-7
+    # the same problems with refinement inside the graph agree to the tolerance
+    b2 = make_batch(ns, parts, refine_iters=5, max_extra=30, tol_rel=1e-7)
+    b2.run(use_graph=True)
+    for p in range(len(ns)):
+        assert rel(b.get_field(p, Q.FIELD_PHI).cpu().numpy(), b2.get_field(p, Q.FIELD_PHI).cpu().numpy()) <= 1e-5
+
+
+def test_empty_problem_and_particles_outside():
+    ns = [17, 17]
+    far = synth.Particles(np.array([500.0]), np.array([0.0]), np.array([0.0]), np.array([1e10]))
+    empty = synth.Particles(np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0))
+    b = Q.Batch(Q.BatchConfig(box_side=L_BOX, max_extra=0), ns, R_CURVE)
+    b.set_particles(0, dev(far.x), dev(far.y), dev(far.z), dev(far.m), 1e10)
+    z = torch.zeros(0, dtype=torch.float64, device="cuda")
+    b.set_particles(1, z, z, z, z, 1e10)
+    info = b.run(use_graph=True, allow_not_converged=True)
+    assert info[0]["n_inside"] == 0 and info[1]["n_inside"] == 0
+    for p, parts in ((0, far), (1, empty)):
+        assert np.all(b.get_field(p, Q.FIELD_RHS).cpu().numpy() == 0.0)
+        ref = solo(17, parts, 4, mass=1e10)
+        assert np.array_equal(b.get_field(p, Q.FIELD_PHI).cpu().numpy(), ref["phi"])
+        # matter-free: Phi_N is the harmonic extension of -GM/r, close to -GM/r inside
+        assert np.isfinite(info[p]["relres_newton"])
+
+
+def test_run_before_particles_is_a_state_error():
+    b = Q.Batch(Q.BatchConfig(box_side=L_BOX), [17, 33], R_CURVE)
+    x = dev([0.0])
+    b.set_particles(0, x, x, x, dev([1e9]), 1e9)
+    with pytest.raises(Q.QumondError) as e:
+        b.run()
+    assert e.value.status == Q.QUMOND_ERR_STATE
+
+
+@pytest.mark.slow
+def test_fit_workload_64_disks():
+    params = synth.fit_grid(64, config=4)
+    ns = [dp.n_grid for dp in params]
+    assert 20 <= sum(1 for n in ns if n == 257) <= 44
+    b = Q.Batch(Q.BatchConfig(box_side=L_BOX, autotune=True), ns, R_CURVE)
+    keep = []
+    for i, dp in enumerate(params):
+        d = dp.dist
+        x, y, zz, m = synth.two_component_disk_torch(dp.n_particles, dp.seed, Md=dp.ml * 5e10 * d * d, Rd=3.0 * d,
+                                                     zd=dp.z_star, Mg=1e10 * d * d, Rg=6.0 * d, zg=dp.z_gas)
+        b.set_particles(i, x, y, zz, m, float(m.sum().item()))
+        keep.append((x, y, zz, m))
+    info = b.run(use_graph=True)
+    assert all(i["converged"] == 1 for i in info)
+    assert all(i["relres_mond"] <= 1e-6 and i["relres_newton"] <= 1e-6 for i in info)
+    # sampled problems: one of each size, against the single-problem context and the oracle's residual
+    for n in (129, 257):
+        p = ns.index(n)
+        x, y, zz, m = keep[p]
+        parts = synth.Particles(x.cpu().numpy(), y.cpu().numpy(), zz.cpu().numpy(), m.cpu().numpy())
+        ref = solo(n, parts, 4)
+        got = batch_fields(b, p)
+        if info[p]["steps_newton"] == 4 and info[p]["steps_mond"] == 4:
+            for k in ("f", "phin", "S", "phi"):
+                assert np.array_equal(got[k], ref[k])
+        h = L_BOX / (n - 1)
+        q, inside = O.cic_deposit(n, L_BOX, parts.x, parts.y, parts.z, parts.m, O.fixed_shift(float(m.sum().item())))
+        f_o = O.rhs_from_q(n, L_BOX, q, O.fixed_shift(float(m.sum().item())))
+        assert rel(got["f"], f_o) <= 1e-15 and inside == info[p]["n_inside"]
+        r = O.residual(f_o, got["phin"], h)
+        assert np.sqrt((r ** 2).sum() / (f_o[1:-1, 1:-1, 1:-1] ** 2).sum()) <= 1e-6
