@@ -107,6 +107,59 @@ def mixed_vs_fp64(Q, synth, torch, np, dev, reps=3):
     return out
 
 
+def batched_fit(Q, synth, torch, np, reps=3, refine_iters=4):
+    """The batched rotation-curve fit: 64 two-component disks on the seeded
+    parameter grid (M/L 0.3-1.2, z* 0.1-0.6 kpc, z_g 0.05-0.5 kpc, distance
+    +-20%, 2e5-2e6 particles), grids 129^3 or 257^3 in a 120 kpc box, mixed
+    precision to 1e-6, one captured hipGraph per run (plus the tail check),
+    smoother shapes autotuned on the batch's own grids.  Particles are drawn
+    on the GPU and resident before timing."""
+    params = synth.fit_grid(64, config=4)
+    ns = [dp.n_grid for dp in params]
+    R = [0.5 * k for k in range(1, 61)]
+    b = Q.Batch(Q.BatchConfig(box_side=120.0, refine_iters=refine_iters, tol_rel=1e-6, autotune=True), ns, R)
+    keep, npart = [], 0
+    for i, dp in enumerate(params):
+        d = dp.dist
+        x, y, z, m = synth.two_component_disk_torch(dp.n_particles, dp.seed, Md=dp.ml * 5e10 * d * d, Rd=3.0 * d,
+                                                    zd=dp.z_star, Mg=1e10 * d * d, Rg=6.0 * d, zg=dp.z_gas)
+        b.set_particles(i, x, y, z, m, float(m.sum().item()))
+        keep.append((x, y, z, m))
+        npart += dp.n_particles
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = b.run(use_graph=True)            # autotune + capture + first replay (setup)
+    t_setup = (time.perf_counter() - t0) * 1e3
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = b.run(use_graph=True)
+        times.append((time.perf_counter() - t0) * 1e3)
+    t0 = time.perf_counter()
+    b.run(use_graph=False)
+    t_eager = (time.perf_counter() - t0) * 1e3
+    pts = sum(n ** 3 for n in ns)
+    ms = float(np.median(times))
+    d = b.describe()
+    out = {"workload": "64 two-component disks (seeded fit grid), 129^3/257^3 boxes of 120 kpc, mixed precision "
+                       f"({refine_iters} FP64 refinement steps in the graph, tail to 1e-6)",
+           "problems": 64, "n_257": ns.count(257), "n_129": ns.count(129), "grid_pts": pts, "particles": npart,
+           "ms_per_run": ms, "grid_pts_per_s": pts / (ms * 1e-3), "particles_per_s": npart / (ms * 1e-3),
+           "ms_eager": t_eager, "ms_first_run_with_tune_and_capture": t_setup, "graph_nodes": d["graph_nodes"],
+           "converged": int(sum(i["converged"] for i in info)),
+           "max_relres_newton": max(i["relres_newton"] for i in info),
+           "max_relres_mond": max(i["relres_mond"] for i in info),
+           "tail_steps": int(sum(i["steps_newton"] + i["steps_mond"] - 2 * refine_iters for i in info)),
+           "device_gb": d["device_bytes"] / 1e9, "shapes": d["classes"]}
+    log(f"batched fit: {ms:.1f} ms per run of 64 disks ({pts / (ms * 1e-3):.3g} grid-pts/s), "
+        f"eager {t_eager:.1f} ms, {out['converged']}/64 converged")
+    b.close()
+    del keep
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +168,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile-pass", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the 513^3 FP64-vs-mixed comparison")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-disk batched fit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a design "
@@ -182,6 +236,10 @@ def main():
     if not args.no_mixed:
         mixed = mixed_vs_fp64(Q, synth, torch, np, dev)
 
+    batch = None
+    if not args.no_batch:
+        batch = batched_fit(Q, synth, torch, np)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -207,6 +265,7 @@ def main():
         "vcycles_after_fmg": {"newton": infos["newton"]["vcycles"], "mond": infos["mond"]["vcycles"]},
         "smoother_shapes": shapes,
         "mixed_vs_fp64_513": mixed,
+        "batched_fit_64": batch,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

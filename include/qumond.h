@@ -166,10 +166,12 @@ qumond_status qumond_mond_source(qumond_ctx *ctx);
  * configured Dirichlet value (zero, or the QUMOND monopole of total_mass),
  * inner boxes from the next coarser box's converged Phi.  guess (device,
  * optional): nbox * n^3 values of type guess_kind, box after box, whose
- * interior seeds the finest level instead of FMG; the guess is rejected in
- * favour of FMG from zero (info->used_fallback = 1) when it is not finite,
- * when the relative residual after its first V-cycle exceeds 1, or when it
- * needs more than ncycle_fmg + max_vcycles V-cycles.  Synchronises. */
+ * interior seeds the finest level instead of FMG, followed by V-cycles (with
+ * QUMOND_MIXED: FP64 refinement steps, each one FP32 V-cycle, as after the
+ * FP32 FMG); the guess is rejected in favour of FMG from zero
+ * (info->used_fallback = 1) when it is not finite, when the relative
+ * residual after its first cycle exceeds 1, or when it needs more than
+ * ncycle_fmg + max_vcycles cycles.  Synchronises. */
 qumond_status qumond_solve_mond(qumond_ctx *ctx, const void *guess, int32_t guess_kind, qumond_solve_info *info);
 
 /* Steps 2-4 in one call with the two chains overlapped: the Newtonian solve

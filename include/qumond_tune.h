@@ -22,13 +22,15 @@
 extern "C" {
 #endif
 
-/* variant: 0 = 32x8, 1 = 64x4, 2 = 64x8, 3 = 128x4, 4 = 32x16 columns per
- * workgroup; kchunk: z planes per workgroup (0 = all).  fp32 selects the
- * table of the single-precision smoother. */
+/* variant: z-march over 0 = 32x8, 1 = 64x4, 2 = 64x8, 3 = 128x4, 4 = 32x16
+ * columns per workgroup, or 5 = 8^3 bricks held whole in LDS (small levels);
+ * kchunk: z planes per workgroup (0 = all; ignored by bricks).  fp32 selects
+ * the table of the single-precision smoother. */
 qumond_status qumond_tune_set(int32_t n, int32_t fp32, int32_t variant, int32_t kchunk);
 qumond_status qumond_tune_get(int32_t n, int32_t fp32, int32_t *variant, int32_t *kchunk);
 
-/* The same for the fused two-sweep smoother (variant 0 = 32x8, 1 = 64x4). */
+/* The same for the fused two-sweep smoother (variant 0 = 32x8, 1 = 64x4
+ * z-march, 2 = 8^3 bricks). */
 qumond_status qumond_tune_set_fused(int32_t n, int32_t fp32, int32_t variant, int32_t kchunk);
 qumond_status qumond_tune_get_fused(int32_t n, int32_t fp32, int32_t *variant, int32_t *kchunk);
 

@@ -13,8 +13,13 @@
  * and Adam state FP32.
  *
  * Scaling (chosen by the caller from quantities known before the solve):
- * input channel 0 = Phi_N / c_phin, channel 1 = h^2 S / c_out, output
- * Phi = c_out * prediction.  All arrays are device pointers except where
+ * the network sees and predicts departures from the potentials of a
+ * softened point mass of the box's total mass M, B_N = -GM / r_s and
+ * B_Q = the QUMOND monopole of qumond.h at r_s, r_s = sqrt(r^2 + soft^2) (r
+ * from the box centre), which carry the mass-dependent part of Phi that the
+ * scaled fields alone would hide: input channel 0 = (Phi_N - B_N) / c_phin,
+ * channel 1 = h^2 S / c_out, output Phi = B_Q + c_out * prediction.  GM = 0
+ * turns the baselines off.  All arrays are device pointers except where
  * marked host; calls are asynchronous on the net's stream unless they return
  * a host value.
  */
@@ -43,18 +48,21 @@ qumond_status qumond_unet_set_params(qumond_unet *net, const float *host);
 qumond_status qumond_unet_get_grads(qumond_unet *net, float *host);
 
 /* One training sample from the method's fields: x (n^3 x 2 BF16, the two
- * input channels) and target (n^3 FP32, Phi / c_out). */
+ * input channels) and target (n^3 FP32, (Phi - B_Q) / c_out).  GM (>= 0),
+ * a0 (>= 0) and soft (kpc, > 0) define the baselines; the box side is
+ * h (n - 1). */
 qumond_status qumond_unet_prepare_sample(qumond_unet *net, const double *phin, const double *S, const double *phi,
-                                         double h, double c_phin, double c_out, void *x, float *target);
+                                         double h, double c_phin, double c_out, double GM, double a0, double soft,
+                                         void *x, float *target);
 
 /* One Adam step (learning rate lr) on the mean squared error over interior
  * nodes between the prediction for x and target; loss (host, optional;
  * synchronises) gets the loss before the step. */
 qumond_status qumond_unet_train_step(qumond_unet *net, const void *x, const float *target, float lr, double *loss);
 
-/* Prediction for (Phi_N, S): guess = c_out * network output (n^3 FP64). */
+/* Prediction for (Phi_N, S): guess = B_Q + c_out * network output (n^3 FP64). */
 qumond_status qumond_unet_infer(qumond_unet *net, const double *phin, const double *S, double h, double c_phin,
-                                double c_out, double *guess);
+                                double c_out, double GM, double a0, double soft, double *guess);
 
 /* Single-layer entry points (BF16 channel-last tensors with slot width equal
  * to the channel count; weights [cout][kpad], kpad = 27 cin rounded up to 32;

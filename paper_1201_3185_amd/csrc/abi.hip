@@ -373,12 +373,27 @@ static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int 
     double rr = 0.0, rr0 = 0.0;
     int extra = 0;
     hipError_t e;
+    // One FP64 residual-correction step of the mixed solve: the FP64 residual
+    // scaled by its RMS (from the norms of the last relres), one FP32 V-cycle
+    // on it with zero boundary values, the scaled correction added in FP64.
+    auto refine_step = [&]() {
+        Mixed &X = *ch.mix;
+        qm::launch_mixed_scale(ctx->n, ch.mg->norms, X.sc, ch.s);
+        qm::launch_resid_to_f32(ctx->n, B.h, X.sc, f, u, X.r, ch.s);
+        qm::launch_fill<float>(X.a[0], ctx->N, 0.0f, ch.s);
+        qm::launch_fill<float>(X.a[1], ctx->N, 0.0f, ch.s);
+        X.mg.bind(B.L, X.a[0], X.a[1], X.r);
+        X.mg.finest_cycle();
+        qm::launch_correct(ctx->n, X.sc, X.mg.result(), u, ch.s);
+    };
+    const bool mixed = c.precision == QUMOND_MIXED;
     if (guess) {
-        // Seeded solve: V-cycles from the guess's interior.  The guess is
-        // rejected (FMG from zero instead) if it is not finite, if the relative
-        // residual after its first V-cycle exceeds 1 (the first smoothing removes
-        // the guess's high-frequency error, so the raw residual of the guess
-        // says little), or if it needs more cycles than FMG plus max_vcycles.
+        // Seeded solve: V-cycles from the guess's interior (in mixed precision,
+        // refinement steps with FP32 V-cycles).  The guess is rejected (FMG
+        // from zero instead) if it is not finite, if the relative residual
+        // after its first V-cycle exceeds 1 (the first smoothing removes the
+        // guess's high-frequency error, so the raw residual of the guess says
+        // little), or if it needs more cycles than FMG plus max_vcycles.
         const bool no_fallback = (guess_kind & QUMOND_GUESS_NO_FALLBACK) != 0;
         const int kind = guess_kind & 3;
         const size_t esz = kind == QUMOND_GUESS_F64 ? 8 : (kind == QUMOND_GUESS_F32 ? 4 : 2);
@@ -388,7 +403,8 @@ static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int 
         bool accept = no_fallback || std::isfinite(rr);
         const int budget = c.ncycle_fmg + c.max_vcycles;
         while (accept && c.tol_rel > 0.0 && rr > c.tol_rel && extra < budget) {
-            ch.mg->finest_cycle();
+            if (mixed) refine_step();
+            else ch.mg->finest_cycle();
             ++extra;
             if ((e = ch.mg->relres(rr)) != hipSuccess) return hip_fail(e, "solve: V-cycle");
             if (!no_fallback && (!std::isfinite(rr) || (extra == 1 && rr > 1.0))) accept = false;
@@ -397,6 +413,7 @@ static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int 
             ch.mg->finish();
             ok = !(c.tol_rel > 0.0 && !(rr <= c.tol_rel));
             if (info) {
+                if (mixed) info->refine_iters[b] = extra;
                 info->vcycles[b] = extra;
                 info->relres0[b] = rr0;
                 info->relres[b] = rr;
@@ -419,7 +436,7 @@ static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int 
         ch.mg->bind(B.L, u, ch.scratch, f);
         extra = 0;
     }
-    if (c.precision == QUMOND_MIXED) {
+    if (mixed) {
         // FP32 FMG seeds the FP64 iterate ...
         Mixed &X = *ch.mix;
         qm::launch_narrow(f, X.r, ctx->N, ch.s);
@@ -432,13 +449,7 @@ static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int 
         // ... then FP64 residual correction with FP32 V-cycles (zero boundary
         // values); the scale comes from the residual norms already on the device.
         while (c.tol_rel > 0.0 && rr > c.tol_rel && extra < c.max_vcycles) {
-            qm::launch_mixed_scale(ctx->n, ch.mg->norms, X.sc, ch.s);
-            qm::launch_resid_to_f32(ctx->n, B.h, X.sc, f, u, X.r, ch.s);
-            qm::launch_fill<float>(X.a[0], ctx->N, 0.0f, ch.s);
-            qm::launch_fill<float>(X.a[1], ctx->N, 0.0f, ch.s);
-            X.mg.bind(B.L, X.a[0], X.a[1], X.r);
-            X.mg.finest_cycle();
-            qm::launch_correct(ctx->n, X.sc, X.mg.result(), u, ch.s);
+            refine_step();
             ++extra;
             if ((e = ch.mg->relres(rr)) != hipSuccess) return hip_fail(e, "solve: refinement");
         }

@@ -29,11 +29,8 @@ __device__ __forceinline__ void bface_node(int n, int t, int &i, int &j, int &k)
     }
 }
 
-__device__ __forceinline__ double bc_outer_value(int n, double L, int mode, double GM, double a0, int i, int j, int k)
+__device__ __forceinline__ double monopole_value(int mode, double GM, double a0, double r)
 {
-    const double h = L / (double)(n - 1);
-    const double x = -0.5 * L + i * h, y = -0.5 * L + j * h, z = -0.5 * L + k * h;
-    const double r = sqrt(x * x + y * y + z * z);
     double v = 0.0;
     if (mode == 1) {
         v = -GM / r;
@@ -41,6 +38,33 @@ __device__ __forceinline__ double bc_outer_value(int n, double L, int mode, doub
         v = -GM / (2.0 * r) - sqrt(GM) * sqrt(GM + 4.0 * a0 * r * r) / (2.0 * r) + sqrt(GM * a0) * asinh(2.0 * r * sqrt(a0 / GM));
     }
     return v;
+}
+
+__device__ __forceinline__ double bc_outer_value(int n, double L, int mode, double GM, double a0, int i, int j, int k)
+{
+    const double h = L / (double)(n - 1);
+    const double x = -0.5 * L + i * h, y = -0.5 * L + j * h, z = -0.5 * L + k * h;
+    return monopole_value(mode, GM, a0, sqrt(x * x + y * y + z * z));
+}
+
+// The monopole potential at every node with r softened to sqrt(r^2 + soft^2)
+// (finite at the centre); GM = 0 gives zero.
+__global__ void monopole_field_k(int n, double L, int mode, double GM, double a0, double soft2, double *__restrict__ out)
+{
+    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t N = (size_t)n * n * n;
+    if (t >= N) return;
+    const int i = (int)(t % n), j = (int)((t / n) % n), k = (int)(t / ((size_t)n * n));
+    const double h = L / (double)(n - 1);
+    const double x = -0.5 * L + i * h, y = -0.5 * L + j * h, z = -0.5 * L + k * h;
+    out[t] = GM > 0.0 ? monopole_value(mode, GM, a0, sqrt(x * x + y * y + z * z + soft2)) : 0.0;
+}
+
+void launch_monopole_field(int n, double L, int mode, double GM, double a0, double soft, double *out, hipStream_t s)
+{
+    const size_t N = (size_t)n * n * n;
+    hipLaunchKernelGGL(monopole_field_k, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, n, L, mode, GM, a0,
+                       soft * soft, out);
 }
 
 __global__ void bc_outer_k(int n, double L, int mode, double GM, double a0, double *__restrict__ u0, double *__restrict__ u1)

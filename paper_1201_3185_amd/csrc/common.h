@@ -61,13 +61,15 @@ struct BatchProblem {
 constexpr int kBatchDepositBlocks = 64;   // deposit workgroups per problem
 
 // ---- grid_kernels.hip (templated on the storage type: double or float)
-// Smoother launch shape: tile variant (0: 32x8, 1: 64x4, 2: 64x8, 3: 128x4,
-// 4: 32x16 columns) and the number of z planes one workgroup marches through.
+// Smoother launch shape: tile variant (z-march over 0: 32x8, 1: 64x4, 2: 64x8,
+// 3: 128x4, 4: 32x16 columns; 5: 8^3 bricks) and the number of z planes one
+// workgroup marches through (ignored by bricks).
 struct SmootherShape {
     int variant;
     int kchunk;
 };
-constexpr int kSmootherVariants = 5;
+constexpr int kSmootherVariants = 6;
+constexpr int kFusedVariants = 3;   // two sweeps: 0: 32x8, 1: 64x4 z-march, 2: 8^3 bricks
 // Every grid launcher takes nb, the number of problems stored back to back
 // (problem p of a level with n points per side at offset p n^3); nb = 1 is the
 // single-problem case.
@@ -75,8 +77,9 @@ template <typename T> void launch_rbgs(int n, double h, const T *f, const T *uin
 template <typename T> void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, SmootherShape sh,
                                             hipStream_t s, int nb = 1);
 template <typename T> SmootherShape &rbgs_shape(int n);   // the table entry used for n
-// Two sweeps in one launch (variants 0: 32x8, 1: 64x4); with uc != NULL the
-// correction u += P uc (uc on the next coarser level) is applied first.
+// Two sweeps in one launch (variants 0: 32x8, 1: 64x4 z-march, 2: 8^3 bricks);
+// with uc != NULL the correction u += P uc (uc on the next coarser level) is
+// applied first.
 template <typename T> void launch_rbgs2(int n, double h, const T *f, const T *uin, T *uout, const T *uc,
                                        hipStream_t s, int nb = 1);
 template <typename T> void launch_rbgs2_shape(int n, double h, const T *f, const T *uin, T *uout, const T *uc,
@@ -124,6 +127,8 @@ void launch_guess_interior(int n, const void *g, int kind, double *u, hipStream_
 // ---- bc_kernels.hip
 // mode 0 zero, 1 Newtonian monopole -GM/r, 2 QUMOND monopole.
 void launch_bc_outer(int n, double L, int mode, double GM, double a0, double *u0, double *u1, hipStream_t s);
+// Mode 1 or 2 at every node with r -> sqrt(r^2 + soft^2) (n^3 doubles).
+void launch_monopole_field(int n, double L, int mode, double GM, double a0, double soft, double *out, hipStream_t s);
 // The same for nb problems (back to back), GM = G * prob[p].mass.
 void launch_bc_outer_batch(int n, double L, int mode, double G, double a0, const BatchProblem *prob, double *u0,
                            int nb, hipStream_t s);

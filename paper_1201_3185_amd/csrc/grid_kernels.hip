@@ -185,6 +185,98 @@ static void rbgs_launch(int n, double h, const T *f, const T *uin, T *uout, int 
     hipLaunchKernelGGL((rbgs_zmarch<T, TX, TY>), grid, dim3(TX * TY), 0, s, uin, uout, f, n, T(h * h), kchunk, nzc);
 }
 
+// ------------------------------------------------------ brick smoother
+//
+// For small levels, where a z-march spends most of its time filling its
+// pipeline, each workgroup owns a B^3 brick of interior nodes, loads u on the
+// brick plus a 2S-node ring (with the correction u += P uc added on load under
+// PROLONG) and f on the brick plus a (2S-1)-node ring into LDS once, runs the
+// 2S colour passes of S red-black sweeps on regions one node narrower each
+// time, and stores the brick.  Ring values are recomputed by every brick that
+// loads them, from the same inputs, so the stored brick equals S sequential
+// sweeps; the node update is the same expression as in rbgs_zmarch, so the
+// results agree bit for bit.
+template <typename T, int B, int S, bool PROLONG>
+__global__ void __launch_bounds__(256)
+rbgs_brick(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2,
+           const T *__restrict__ uc, int nc, int nbx)
+{
+    constexpr int R = 2 * S, E = B + 2 * R, FE = E - 2, NT = 256;
+    __shared__ T U[E * E * E];
+    __shared__ T F[FE * FE * FE];
+    const T sixth = T(1) / T(6);
+    const int tid = threadIdx.x;
+    int bid = blockIdx.x;
+    const int bx = bid % nbx;
+    bid /= nbx;
+    const int by = bid % nbx;
+    bid /= nbx;
+    const int bz = bid % nbx;
+    const int pb = bid / nbx;
+    const size_t N = (size_t)n * n * n;
+    uin += pb * N;
+    uout += pb * N;
+    f += pb * N;
+    if (PROLONG) uc += pb * (size_t)nc * nc * nc;
+    const int i0 = 1 + bx * B - R, j0 = 1 + by * B - R, k0 = 1 + bz * B - R;   // global node of U[0]
+    for (int t = tid; t < E * E * E; t += NT) {
+        const int a = t % E, b = (t / E) % E, c = t / (E * E);
+        const int i = i0 + a, j = j0 + b, k = k0 + c;
+        T x = T(0);
+        if (i >= 0 && i < n && j >= 0 && j < n && k >= 0 && k < n) {
+            x = uin[id3(n, i, j, k)];
+            if (PROLONG && i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2 && k >= 1 && k <= n - 2)
+                x += prolong_at(nc, uc, i, j, k);
+        }
+        U[t] = x;
+    }
+    for (int t = tid; t < FE * FE * FE; t += NT) {
+        const int a = t % FE, b = (t / FE) % FE, c = t / (FE * FE);
+        const int i = i0 + 1 + a, j = j0 + 1 + b, k = k0 + 1 + c;
+        F[t] = (i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2 && k >= 1 && k <= n - 2) ? f[id3(n, i, j, k)] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < 2 * S; ++st) {
+        const int colour = st & 1;           // red ((i+j+k) even) first
+        const int r = R - 1 - st;            // ring of this pass
+        const int W = B + 2 * r, o = R - r;  // region edge and its start in U
+        const int hw = (W + 1) / 2;
+        for (int t = tid; t < hw * W * W; t += NT) {
+            const int q = t % hw, b = o + (t / hw) % W, c = o + t / (hw * W);
+            const int j = j0 + b, k = k0 + c;
+            const int ia = i0 + o;
+            const int a = o + (((ia + j + k) & 1) == colour ? 0 : 1) + 2 * q;
+            const int i = i0 + a;
+            if (a >= o + W || i < 1 || i > n - 2 || j < 1 || j > n - 2 || k < 1 || k > n - 2) continue;
+            const int p = a + E * (b + E * c);
+            const T sum = U[p - 1] + U[p + 1] + U[p - E] + U[p + E] + U[p - E * E] + U[p + E * E];
+            U[p] = (sum - h2 * F[(a - 1) + FE * ((b - 1) + FE * (c - 1))]) * sixth;
+        }
+        __syncthreads();
+    }
+    for (int t = tid; t < B * B * B; t += NT) {
+        const int a = R + t % B, b = R + (t / B) % B, c = R + t / (B * B);
+        const int i = i0 + a, j = j0 + b, k = k0 + c;
+        if (i > n - 2 || j > n - 2 || k > n - 2) continue;
+        uout[id3(n, i, j, k)] = U[a + E * (b + E * c)];
+    }
+}
+
+template <typename T, int S>
+static void brick_launch(int n, double h, const T *f, const T *uin, T *uout, const T *uc, int nb, hipStream_t s)
+{
+    constexpr int B = 8;
+    const int nbx = (n - 2 + B - 1) / B;
+    const dim3 grid((unsigned)((size_t)nbx * nbx * nbx * nb));
+    if (uc)
+        hipLaunchKernelGGL((rbgs_brick<T, B, S, true>), grid, dim3(256), 0, s, uin, uout, f, n, T(h * h), uc,
+                           (n + 1) / 2, nbx);
+    else
+        hipLaunchKernelGGL((rbgs_brick<T, B, S, false>), grid, dim3(256), 0, s, uin, uout, f, n, T(h * h), uc,
+                           (n + 1) / 2, nbx);
+}
+
 // ----------------------------------------------------- two fused sweeps
 //
 // Two red-black sweeps (A then B) in one pass: four stages one z plane
@@ -349,6 +441,7 @@ void launch_rbgs2_shape(int n, double h, const T *f, const T *uin, T *uout, cons
     const int kc = sh.kchunk > 0 ? sh.kchunk : n;
     switch (sh.variant) {
     case 0: rbgs2_launch<T, 32, 8>(n, h, f, uin, uout, kc, uc, nb, s); break;
+    case 2: brick_launch<T, 2>(n, h, f, uin, uout, uc, nb, s); break;
     default: rbgs2_launch<T, 64, 4>(n, h, f, uin, uout, kc, uc, nb, s); break;
     }
 }
@@ -427,6 +520,7 @@ void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, Smoot
     case 2: rbgs_launch<T, 64, 8>(n, h, f, uin, uout, kc, nb, s); break;
     case 3: rbgs_launch<T, 128, 4>(n, h, f, uin, uout, kc, nb, s); break;
     case 4: rbgs_launch<T, 32, 16>(n, h, f, uin, uout, kc, nb, s); break;
+    case 5: brick_launch<T, 1>(n, h, f, uin, uout, nullptr, nb, s); break;
     default: rbgs_launch<T, 64, 4>(n, h, f, uin, uout, kc, nb, s); break;
     }
 }

@@ -246,11 +246,15 @@ void launch_rhs_batch(int n, double h, double four_pi_G, const BatchProblem *pro
 }
 
 // ------------------------------------------------------------------- gather
+//
+// The gather arithmetic is written out with contraction off, so that every
+// kernel that inlines it (forces, curves, batched curves) rounds the same way.
 
 // -d Phi / d x_d at node (i,j,k): central difference inside, one-sided second
 // order on the faces.
 __device__ __forceinline__ double node_accel(const double *__restrict__ P, int n, double inv2h, int i, int j, int k, int d)
 {
+#pragma clang fp contract(off)
     const size_t st = d == 0 ? 1 : (d == 1 ? (size_t)n : (size_t)n * n);
     const int c = d == 0 ? i : (d == 1 ? j : k);
     const size_t p = id3(n, i, j, k);
@@ -265,6 +269,7 @@ __device__ __forceinline__ double node_accel(const double *__restrict__ P, int n
 __device__ __forceinline__ void monopole_accel(double GM, double a0, int mond, double px, double py, double pz,
                                                double acc[3])
 {
+#pragma clang fp contract(off)
     const double r = sqrt(px * px + py * py + pz * pz);
     double g = 0.0;
     if (r > 0.0) {
@@ -288,6 +293,7 @@ __device__ __forceinline__ bool in_box(const BoxGeom &G, int n, double px, doubl
 __device__ void box_accel(const BoxGeom &G, int n, const double *__restrict__ P, double px, double py, double pz,
                           double acc[3])
 {
+#pragma clang fp contract(off)
     const double u[3] = {(px - G.xmin) * G.inv_h, (py - G.xmin) * G.inv_h, (pz - G.xmin) * G.inv_h};
     int ic[3];
     double w[3][2];
@@ -310,6 +316,7 @@ __device__ void box_accel(const BoxGeom &G, int n, const double *__restrict__ P,
 
 __device__ int gather_point(const GatherArgs &A, double px, double py, double pz, double acc[3])
 {
+#pragma clang fp contract(off)
     const double R = sqrt(px * px + py * py), az = fabs(pz);
     int sel = -1;
     for (int b = A.nbox - 1; b >= 0; --b)
@@ -353,6 +360,7 @@ void launch_gather(const GatherArgs &a, const double *x, const double *y, const 
 __global__ void __launch_bounds__(256)
 rotation_curve_k(GatherArgs A, const double *__restrict__ R, int naz, double *__restrict__ vc2)
 {
+#pragma clang fp contract(off)
     __shared__ double sh[256];
     const double r = R[blockIdx.x];
     double s = 0.0;
@@ -384,6 +392,7 @@ rotation_curve_batch_k(int n, BoxGeom G, double frac, double Gc, double a0, int 
                        const BatchProblem *__restrict__ prob, const double *__restrict__ phi, const double *__restrict__ R,
                        int nR, int naz, double *__restrict__ vc2)
 {
+#pragma clang fp contract(off)
     __shared__ double sh[256];
     const int pb = blockIdx.y;
     const double *P = phi + (size_t)pb * n * n * n;

@@ -53,10 +53,12 @@ qumond_status tune_one(int n, int reps, hipStream_t s, double &best_us, bool fus
             qm::launch_rbgs_shape<T>(n, h, f, a, b, sh, s);
         }
     };
-    const int nvar = fused ? 2 : qm::kSmootherVariants;
+    const int nvar = fused ? qm::kFusedVariants : qm::kSmootherVariants;
+    const int brick = fused ? 2 : 5;
     for (int v = 0; v < nvar; ++v)
         for (int kc : kChunks) {
             if (kc != 0 && kc >= n - 2) continue;
+            if (v == brick && kc != 0) continue;   // bricks have no z-chunk
             const qm::SmootherShape sh{v, kc};
             std::vector<float> t;
             run(u0, u1, sh);   // warm-up
@@ -115,7 +117,8 @@ qumond_status qumond_tune_get(int32_t n, int32_t fp32, int32_t *variant, int32_t
 
 qumond_status qumond_tune_set_fused(int32_t n, int32_t fp32, int32_t variant, int32_t kchunk)
 {
-    if (!good_n(n) || variant < 0 || variant > 1 || kchunk < 0) return tfail("qumond_tune_set_fused: bad argument");
+    if (!good_n(n) || variant < 0 || variant >= qm::kFusedVariants || kchunk < 0)
+        return tfail("qumond_tune_set_fused: bad argument");
     qm::SmootherShape sh{variant, kchunk};
     if (fp32) qm::rbgs2_shape<float>(n) = sh;
     else qm::rbgs2_shape<double>(n) = sh;

@@ -32,11 +32,13 @@ void launch_head_bwd(const float *dyh, Tensor x, int c, const float *w, Tensor d
 void launch_mse(const float *yh, const float *tg, int n, float *dy, double *partial, double *loss, hipStream_t s);
 void launch_adam(float *w, float *m, float *v, const float *g, int count, float lr, int step, __bf16 *wb, hipStream_t s);
 void launch_to_bf16(const float *src, __bf16 *dst, int count, hipStream_t s);
-void launch_prep_input(int n, const double *phin, const double *S, double inv_cn, double h2_cs, Tensor x,
-                       hipStream_t s);
+// channel 0 = (phin - base) inv_cn, channel 1 = S h2_cs
+void launch_prep_input(int n, const double *phin, const double *base, const double *S, double inv_cn, double h2_cs,
+                       Tensor x, hipStream_t s);
 void launch_expand_input(const __bf16 *xc, Tensor x, hipStream_t s);
-void launch_scale_out(const float *in, int count, double a, double *out, hipStream_t s);
-void launch_scale_in(const double *in, int count, double a, float *out, hipStream_t s);
+// out = a in + base;  target = a (in - base)
+void launch_scale_out(const float *in, int count, double a, const double *base, double *out, hipStream_t s);
+void launch_scale_in(const double *in, const double *base, int count, double a, float *out, hipStream_t s);
 
 inline int kpad_of(int cin) { return (27 * cin + 31) / 32 * 32; }
 

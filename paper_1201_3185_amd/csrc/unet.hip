@@ -45,6 +45,7 @@ struct qumond_unet {
     Tensor gd0, gc0, gd1, gc1, gd2, gc2, gb3, ga3, gs2, ga2, gs1, ga1, gs0, ga0, dil;
     float *yhat = nullptr, *dyhat = nullptr, *partial = nullptr;
     double *lpartial = nullptr, *loss = nullptr, *host_loss = nullptr;
+    double *base_n = nullptr, *base_q = nullptr;   // point-mass baselines (n^3 each)
     int step = 0;
     std::vector<void *> owned;
     hipError_t err = hipSuccess;
@@ -293,6 +294,8 @@ qumond_status qumond_unet_create(int32_t n, uint64_t seed, void *hip_stream, qum
     u->dil = u->tensor(n0, 32);
     const size_t N0 = (size_t)n0 * n0 * n0;
     u->yhat = (float *)u->alloc(N0 * 4);
+    u->base_n = (double *)u->alloc(N0 * 8);
+    u->base_q = (double *)u->alloc(N0 * 8);
     u->dyhat = (float *)u->alloc(N0 * 4);
     // wgrad partials: nsplit x cout x kpad <= max(4096 tiles x 256, cout x kpad); bias/head partials are smaller
     u->partial = (float *)u->alloc((size_t)2 * 1024 * 1024 * 4);
@@ -380,18 +383,34 @@ qumond_status qumond_unet_set_params(qumond_unet *u, const float *host)
     return check_hip("qumond_unet_set_params");
 }
 
-qumond_status qumond_unet_prepare_sample(qumond_unet *u, const double *phin, const double *S, const double *phi,
-                                         double h, double c_phin, double c_out, void *x, float *target)
+static bool baseline_ok(double GM, double a0, double soft)
 {
-    if (!u || !phin || !S || !phi || !x || !target || !(h > 0) || !(c_phin > 0) || !(c_out > 0))
+    return GM >= 0.0 && std::isfinite(GM) && a0 >= 0.0 && std::isfinite(a0) && soft > 0.0 && std::isfinite(soft);
+}
+
+static void baselines(qumond_unet *u, double h, double GM, double a0, double soft)
+{
+    const int n = u->n[0];
+    const double L = h * (double)(n - 1);
+    qm::launch_monopole_field(n, L, 1, GM, a0, soft, u->base_n, u->s);
+    qm::launch_monopole_field(n, L, 2, GM, a0, soft, u->base_q, u->s);
+}
+
+qumond_status qumond_unet_prepare_sample(qumond_unet *u, const double *phin, const double *S, const double *phi,
+                                         double h, double c_phin, double c_out, double GM, double a0, double soft,
+                                         void *x, float *target)
+{
+    if (!u || !phin || !S || !phi || !x || !target || !(h > 0) || !(c_phin > 0) || !(c_out > 0) ||
+        !baseline_ok(GM, a0, soft))
         return ufail(QUMOND_ERR_INVALID, "qumond_unet_prepare_sample: bad argument");
     const int n = u->n[0];
     Tensor t;
     t.p = (__bf16 *)x;
     t.n = n;
     t.cs = 2;
-    qm::launch_prep_input(n, phin, S, 1.0 / c_phin, h * h / c_out, t, u->s);
-    qm::launch_scale_in(phi, n * n * n, 1.0 / c_out, target, u->s);
+    baselines(u, h, GM, a0, soft);
+    qm::launch_prep_input(n, phin, u->base_n, S, 1.0 / c_phin, h * h / c_out, t, u->s);
+    qm::launch_scale_in(phi, u->base_q, n * n * n, 1.0 / c_out, target, u->s);
     return check_hip("qumond_unet_prepare_sample");
 }
 
@@ -413,14 +432,15 @@ qumond_status qumond_unet_train_step(qumond_unet *u, const void *x, const float 
 }
 
 qumond_status qumond_unet_infer(qumond_unet *u, const double *phin, const double *S, double h, double c_phin,
-                                double c_out, double *guess)
+                                double c_out, double GM, double a0, double soft, double *guess)
 {
-    if (!u || !phin || !S || !guess || !(h > 0) || !(c_phin > 0) || !(c_out > 0))
+    if (!u || !phin || !S || !guess || !(h > 0) || !(c_phin > 0) || !(c_out > 0) || !baseline_ok(GM, a0, soft))
         return ufail(QUMOND_ERR_INVALID, "qumond_unet_infer: bad argument");
     const int n = u->n[0];
-    qm::launch_prep_input(n, phin, S, 1.0 / c_phin, h * h / c_out, u->x0, u->s);
+    baselines(u, h, GM, a0, soft);
+    qm::launch_prep_input(n, phin, u->base_n, S, 1.0 / c_phin, h * h / c_out, u->x0, u->s);
     forward(u);
-    qm::launch_scale_out(u->yhat, n * n * n, c_out, guess, u->s);
+    qm::launch_scale_out(u->yhat, n * n * n, c_out, u->base_q, guess, u->s);
     return check_hip("qumond_unet_infer");
 }
 

@@ -33,7 +33,13 @@ __device__ __forceinline__ void decode3(int v, int n, int &i, int &j, int &k)
 // ------------------------------------------------------------ convolution
 
 // y[v, co] = act(bias[co] + sum_{tap, ci} x[s v + d(tap), ci] W[co, tap cin + ci])
-template <int NB>
+//
+// Each wave computes RB blocks of 16 consecutive output voxels for all cout
+// = 16 NB channels: per K-chunk it loads RB activation fragments and NB weight
+// fragments and issues RB x NB MFMAs, and it loads the next chunk's fragments
+// before the current chunk's MFMAs.  Every output is accumulated over the
+// K-chunks in the same order whatever RB is.
+template <int NB, int RB>
 __global__ void __launch_bounds__(256)
 conv3d_fwd_k(Tensor x, int cin, const __bf16 *__restrict__ wt, int kpad, const float *__restrict__ bias, Tensor y,
              int stride, int relu)
@@ -41,30 +47,65 @@ conv3d_fwd_k(Tensor x, int cin, const __bf16 *__restrict__ wt, int kpad, const f
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nout = y.n, nin = x.n;
     const int Nout = nout * nout * nout;
-    const int v0 = (blockIdx.x * 4 + wave) * 16;
+    const int v0 = (blockIdx.x * 4 + wave) * 16 * RB;
     if (v0 >= Nout) return;
     const int g = lane >> 4, r16 = lane & 15;
-    const int va = v0 + r16;
-    int io = 0, jo = 0, ko = 0;
-    if (va < Nout) decode3(va, nout, io, jo, ko);
-    const int bi = stride * io, bj = stride * jo, bk = stride * ko;
-    f32x4 acc[NB];
+    int bi[RB], bj[RB], bk[RB];
+    bool ok[RB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int rb = 0; rb < RB; ++rb) {
+        const int va = v0 + 16 * rb + r16;
+        int io = 0, jo = 0, ko = 0;
+        ok[rb] = va < Nout;
+        if (ok[rb]) decode3(va, nout, io, jo, ko);
+        bi[rb] = stride * io;
+        bj[rb] = stride * jo;
+        bk[rb] = stride * ko;
+    }
     const int kreal = 27 * cin;
-    for (int kc = 0; kc < kpad; kc += 32) {
-        const int kk0 = kc + 8 * g;
-        bf16x8 a = {};
-        if (kk0 < kreal && va < Nout) {
-            const int tap = kk0 / cin, c0 = kk0 - tap * cin;
-            const int i = bi + tap % 3 - 1, j = bj + (tap / 3) % 3 - 1, k = bk + tap / 9 - 1;
-            if (i >= 0 && i < nin && j >= 0 && j < nin && k >= 0 && k < nin)
-                a = *reinterpret_cast<const bf16x8 *>(x.p + (size_t)(i + nin * (j + nin * k)) * x.cs + c0);
+    const size_t xcs = (size_t)x.cs;
+    // K index of this lane's fragment in the current chunk, as (tap, channel)
+    int kk0 = 8 * g, tap = kk0 / cin, c0 = kk0 - tap * cin;
+    auto load = [&](bf16x8 *a, bf16x8 *w) {
+        const bool live = kk0 < kreal;
+        const int di = tap % 3 - 1, dj = (tap / 3) % 3 - 1, dk = tap / 9 - 1;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            bf16x8 t = {};
+            const int i = bi[rb] + di, j = bj[rb] + dj, k = bk[rb] + dk;
+            if (live && ok[rb] && i >= 0 && i < nin && j >= 0 && j < nin && k >= 0 && k < nin)
+                t = *reinterpret_cast<const bf16x8 *>(x.p + (size_t)(i + nin * (j + nin * k)) * xcs + c0);
+            a[rb] = t;
         }
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const bf16x8 w = *reinterpret_cast<const bf16x8 *>(wt + (size_t)(b * 16 + r16) * kpad + kk0);
-            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w, acc[b], 0, 0, 0);
+        for (int b = 0; b < NB; ++b)
+            w[b] = *reinterpret_cast<const bf16x8 *>(wt + (size_t)(b * 16 + r16) * kpad + kk0);
+        kk0 += 32;
+        c0 += 32;
+        while (c0 >= cin) {
+            c0 -= cin;
+            ++tap;
+        }
+    };
+    f32x4 acc[RB][NB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[rb][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 a[RB], w[NB];
+    load(a, w);
+    for (int kc = 0; kc < kpad; kc += 32) {
+        bf16x8 an[RB], wn[NB];
+        if (kc + 32 < kpad) load(an, wn);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[rb][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], w[b], acc[rb][b], 0, 0, 0);
+        if (kc + 32 < kpad) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) a[rb] = an[rb];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) w[b] = wn[b];
         }
     }
 #pragma unroll
@@ -72,28 +113,46 @@ conv3d_fwd_k(Tensor x, int cin, const __bf16 *__restrict__ wt, int kpad, const f
         const int co = b * 16 + r16;
         const float bb = bias ? bias[co] : 0.f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int v = v0 + 4 * g + r;
-            if (v >= Nout) continue;
-            float val = acc[b][r] + bb;
-            if (relu) val = val > 0.f ? val : 0.f;
-            y.p[(size_t)v * y.cs + co] = (__bf16)val;
-        }
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int v = v0 + 16 * rb + 4 * g + r;
+                if (v >= Nout) continue;
+                float val = acc[rb][b][r] + bb;
+                if (relu) val = val > 0.f ? val : 0.f;
+                y.p[(size_t)v * y.cs + co] = (__bf16)val;
+            }
+    }
+}
+
+template <int NB>
+static void conv_fwd_nb(Tensor x, int cin, const __bf16 *wt, int kpad, const float *bias, Tensor y, int stride,
+                        int relu, hipStream_t s)
+{
+    const int Nout = y.n * y.n * y.n;
+    // RB row blocks per wave while the grid keeps at least ~1024 workgroups
+    if (Nout >= 1024 * 256 && NB <= 4) {
+        hipLaunchKernelGGL((conv3d_fwd_k<NB, 4>), dim3((Nout + 255) / 256), dim3(256), 0, s, x, cin, wt, kpad, bias, y,
+                           stride, relu);
+    } else if (Nout >= 1024 * 128) {
+        hipLaunchKernelGGL((conv3d_fwd_k<NB, 2>), dim3((Nout + 127) / 128), dim3(256), 0, s, x, cin, wt, kpad, bias, y,
+                           stride, relu);
+    } else {
+        hipLaunchKernelGGL((conv3d_fwd_k<NB, 1>), dim3((Nout + 63) / 64), dim3(256), 0, s, x, cin, wt, kpad, bias, y,
+                           stride, relu);
     }
 }
 
 void launch_conv3d_fwd(Tensor x, int cin, const __bf16 *wt, int kpad, int cout, const float *bias, Tensor y,
                        int stride, int relu, hipStream_t s)
 {
-    const int Nout = y.n * y.n * y.n;
-    const int blocks = (Nout + 63) / 64;
     switch (cout / 16) {
-    case 1: hipLaunchKernelGGL(conv3d_fwd_k<1>, dim3(blocks), dim3(256), 0, s, x, cin, wt, kpad, bias, y, stride, relu); break;
-    case 2: hipLaunchKernelGGL(conv3d_fwd_k<2>, dim3(blocks), dim3(256), 0, s, x, cin, wt, kpad, bias, y, stride, relu); break;
-    case 3: hipLaunchKernelGGL(conv3d_fwd_k<3>, dim3(blocks), dim3(256), 0, s, x, cin, wt, kpad, bias, y, stride, relu); break;
-    case 4: hipLaunchKernelGGL(conv3d_fwd_k<4>, dim3(blocks), dim3(256), 0, s, x, cin, wt, kpad, bias, y, stride, relu); break;
-    case 6: hipLaunchKernelGGL(conv3d_fwd_k<6>, dim3(blocks), dim3(256), 0, s, x, cin, wt, kpad, bias, y, stride, relu); break;
-    case 8: hipLaunchKernelGGL(conv3d_fwd_k<8>, dim3(blocks), dim3(256), 0, s, x, cin, wt, kpad, bias, y, stride, relu); break;
+    case 1: conv_fwd_nb<1>(x, cin, wt, kpad, bias, y, stride, relu, s); break;
+    case 2: conv_fwd_nb<2>(x, cin, wt, kpad, bias, y, stride, relu, s); break;
+    case 3: conv_fwd_nb<3>(x, cin, wt, kpad, bias, y, stride, relu, s); break;
+    case 4: conv_fwd_nb<4>(x, cin, wt, kpad, bias, y, stride, relu, s); break;
+    case 6: conv_fwd_nb<6>(x, cin, wt, kpad, bias, y, stride, relu, s); break;
+    case 8: conv_fwd_nb<8>(x, cin, wt, kpad, bias, y, stride, relu, s); break;
     default: break;   // rejected by the caller
     }
 }
@@ -477,13 +536,13 @@ void launch_to_bf16(const float *src, __bf16 *dst, int count, hipStream_t s)
 
 // Network input: channel 0 = Phi_N / cn, channel 1 = h^2 S / cs, further channels
 // of the slot (if any) = 0.
-__global__ void prep_input_k(int n, const double *__restrict__ phin, const double *__restrict__ S, double inv_cn,
-                             double h2_cs, Tensor x)
+__global__ void prep_input_k(int n, const double *__restrict__ phin, const double *__restrict__ base,
+                             const double *__restrict__ S, double inv_cn, double h2_cs, Tensor x)
 {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n * n * n) return;
     __bf16 *p = x.p + (size_t)v * x.cs;
-    p[0] = (__bf16)(float)(phin[v] * inv_cn);
+    p[0] = (__bf16)(float)((phin[v] - base[v]) * inv_cn);
     p[1] = (__bf16)(float)(S[v] * h2_cs);
     for (int c = 2; c < x.cs; ++c) p[c] = (__bf16)0.f;
 }
@@ -505,34 +564,37 @@ void launch_expand_input(const __bf16 *xc, Tensor x, hipStream_t s)
     hipLaunchKernelGGL(expand_input_k, dim3((N + 255) / 256), dim3(256), 0, s, xc, x);
 }
 
-void launch_prep_input(int n, const double *phin, const double *S, double inv_cn, double h2_cs, Tensor x, hipStream_t s)
+void launch_prep_input(int n, const double *phin, const double *base, const double *S, double inv_cn, double h2_cs,
+                       Tensor x, hipStream_t s)
 {
     const int N = n * n * n;
-    hipLaunchKernelGGL(prep_input_k, dim3((N + 255) / 256), dim3(256), 0, s, n, phin, S, inv_cn, h2_cs, x);
+    hipLaunchKernelGGL(prep_input_k, dim3((N + 255) / 256), dim3(256), 0, s, n, phin, base, S, inv_cn, h2_cs, x);
 }
 
-// out[v] = a * in[v] (FP32 -> FP64)
-__global__ void scale_out_k(const float *__restrict__ in, int count, double a, double *__restrict__ out)
+// out[v] = a * in[v] + base[v] (FP32 -> FP64)
+__global__ void scale_out_k(const float *__restrict__ in, int count, double a, const double *__restrict__ base,
+                            double *__restrict__ out)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < count) out[t] = a * (double)in[t];
+    if (t < count) out[t] = a * (double)in[t] + base[t];
 }
 
-void launch_scale_out(const float *in, int count, double a, double *out, hipStream_t s)
+void launch_scale_out(const float *in, int count, double a, const double *base, double *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(scale_out_k, dim3((count + 255) / 256), dim3(256), 0, s, in, count, a, out);
+    hipLaunchKernelGGL(scale_out_k, dim3((count + 255) / 256), dim3(256), 0, s, in, count, a, base, out);
 }
 
-// out[v] = (float)(a * in[v]) (FP64 -> FP32 target)
-__global__ void scale_in_k(const double *__restrict__ in, int count, double a, float *__restrict__ out)
+// out[v] = (float)(a * (in[v] - base[v])) (FP64 -> FP32 target)
+__global__ void scale_in_k(const double *__restrict__ in, const double *__restrict__ base, int count, double a,
+                           float *__restrict__ out)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < count) out[t] = (float)(a * in[t]);
+    if (t < count) out[t] = (float)(a * (in[t] - base[t]));
 }
 
-void launch_scale_in(const double *in, int count, double a, float *out, hipStream_t s)
+void launch_scale_in(const double *in, const double *base, int count, double a, float *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(scale_in_k, dim3((count + 255) / 256), dim3(256), 0, s, in, count, a, out);
+    hipLaunchKernelGGL(scale_in_k, dim3((count + 255) / 256), dim3(256), 0, s, in, base, count, a, out);
 }
 
 }  // namespace qm

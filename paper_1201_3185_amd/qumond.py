@@ -112,9 +112,9 @@ _SIGNATURES = {
     "qumond_unet_get_params": (_I32, [_P, _P]),
     "qumond_unet_set_params": (_I32, [_P, _P]),
     "qumond_unet_get_grads": (_I32, [_P, _P]),
-    "qumond_unet_prepare_sample": (_I32, [_P, _P, _P, _P, _D, _D, _D, _P, _P]),
+    "qumond_unet_prepare_sample": (_I32, [_P, _P, _P, _P, _D, _D, _D, _D, _D, _D, _P, _P]),
     "qumond_unet_train_step": (_I32, [_P, _P, _P, ctypes.c_float, ctypes.POINTER(_D)]),
-    "qumond_unet_infer": (_I32, [_P, _P, _P, _D, _D, _D, _P]),
+    "qumond_unet_infer": (_I32, [_P, _P, _P, _D, _D, _D, _D, _D, _D, _P]),
     "qumond_k_conv3d_fwd": (_I32, [_I32, _I32, _P, _I32, _P, _P, _I32, _I32, _P, _P]),
     "qumond_k_conv3d_dgrad": (_I32, [_I32, _I32, _I32, _P, _I32, _P, _P, _P]),
     "qumond_k_conv3d_wgrad": (_I32, [_I32, _I32, _P, _I32, _P, _I32, _P, _P]),
@@ -406,7 +406,8 @@ def k_vcycles(f, u, L, ncyc, npre=2, npost=2):
 
 # ------------------------------------------------------------------ tuning
 
-SMOOTHER_VARIANTS = {0: (32, 8), 1: (64, 4), 2: (64, 8), 3: (128, 4), 4: (32, 16)}
+SMOOTHER_VARIANTS = {0: (32, 8), 1: (64, 4), 2: (64, 8), 3: (128, 4), 4: (32, 16), 5: "brick8"}
+FUSED_VARIANTS = {0: (32, 8), 1: (64, 4), 2: "brick8"}
 
 
 def tune_set(n, variant, kchunk, fp32=False):
@@ -493,12 +494,13 @@ class UNet:
         check(lib().qumond_unet_get_grads(self._h, out.ctypes.data_as(ctypes.c_void_p)), "qumond_unet_get_grads")
         return out
 
-    def prepare_sample(self, phin, S, phi, h, c_phin, c_out, x=None, t=None):
+    def prepare_sample(self, phin, S, phi, h, c_phin, c_out, x=None, t=None, GM=0.0, a0=3600.0, soft=1.0):
         N = self.n ** 3
         x = torch.empty(N * 2, dtype=torch.bfloat16, device="cuda") if x is None else x
         t = torch.empty(N, dtype=torch.float32, device="cuda") if t is None else t
         check(lib().qumond_unet_prepare_sample(self._h, _ptr(phin), _ptr(S), _ptr(phi), float(h), float(c_phin),
-                                               float(c_out), _ptr(x), _ptr(t)), "qumond_unet_prepare_sample")
+                                               float(c_out), float(GM), float(a0), float(soft), _ptr(x), _ptr(t)),
+              "qumond_unet_prepare_sample")
         return x, t
 
     def train_step(self, x, target, lr: float = 1e-3, want_loss: bool = True):
@@ -507,11 +509,11 @@ class UNet:
                                            ctypes.byref(loss) if want_loss else None), "qumond_unet_train_step")
         return float(loss.value) if want_loss else None
 
-    def infer(self, phin, S, h, c_phin, c_out, out: Optional[torch.Tensor] = None):
+    def infer(self, phin, S, h, c_phin, c_out, out: Optional[torch.Tensor] = None, GM=0.0, a0=3600.0, soft=1.0):
         if out is None:
             out = torch.empty(self.n ** 3, dtype=torch.float64, device="cuda")
         check(lib().qumond_unet_infer(self._h, _ptr(phin), _ptr(S), float(h), float(c_phin), float(c_out),
-                                      _ptr(out)), "qumond_unet_infer")
+                                      float(GM), float(a0), float(soft), _ptr(out)), "qumond_unet_infer")
         return out
 
 

@@ -225,7 +225,7 @@ def test_vcycles(n):
     assert rel(host(d), ref) < 1e-12
 
 
-@pytest.mark.parametrize("n", [33, 129])
+@pytest.mark.parametrize("n", [5, 17, 33, 65, 129])
 def test_every_smoother_shape_is_bitwise_identical(n):
     """Launch shapes change only the schedule: each node's update is the same
     sum in the same order, so every shape gives the same bits."""
@@ -242,6 +242,44 @@ def test_every_smoother_shape_is_bitwise_identical(n):
             out = dev(u)
             Q.k_rbgs_sweep_shape(fd, ud, out, h, v, kc)
             assert np.array_equal(host(out), ref), (v, kc)
+
+
+@pytest.mark.parametrize("n", [5, 17, 33, 65, 129])
+def test_every_fused_shape_is_bitwise_identical(n):
+    """The fused two-sweep smoother in every shape (z-march tiles and 8^3
+    bricks, ragged at the far faces) equals two single sweeps bit for bit, and
+    with a coarse correction equals prolong-add then two sweeps."""
+    L = 5.0
+    h = L / (n - 1)
+    f, u = rand_state(n, 1700 + n)
+    fd = dev(f)
+    a, b, c = dev(u), dev(u), dev(u)
+    Q.k_rbgs_sweep(fd, a, b, h)
+    Q.k_rbgs_sweep(fd, b, c, h)
+    two = host(c)
+    nc = (n + 1) // 2
+    uc = np.random.default_rng(n).standard_normal((nc, nc, nc))
+    uc[0, :, :] = uc[-1, :, :] = uc[:, 0, :] = uc[:, -1, :] = uc[:, :, 0] = uc[:, :, -1] = 0.0
+    ucd = dev(uc)
+    pa = dev(u)
+    Q.k_prolong_add(ucd, pa)
+    b2, c2 = dev(u), dev(u)
+    Q.k_rbgs_sweep(fd, pa, b2, h)
+    Q.k_rbgs_sweep(fd, b2, c2, h)
+    two_p = host(c2)
+    before = Q.tune_get_fused(n)
+    try:
+        for v in Q.FUSED_VARIANTS:
+            for kc in ((0,) if v == 2 else (4, 16, 0)):
+                Q.tune_set_fused(n, v, kc)
+                out = dev(u)
+                Q.k_rbgs_double_sweep(fd, dev(u), out, h)
+                assert np.array_equal(host(out), two), (v, kc)
+                out = dev(u)
+                Q.k_rbgs_double_sweep(fd, dev(u), out, h, uc=ucd)
+                assert np.array_equal(host(out), two_p), (v, kc, "prolong")
+    finally:
+        Q.tune_set_fused(n, *before)
 
 
 def test_autotune_installs_a_table(tmp_path):

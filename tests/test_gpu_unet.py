@@ -290,3 +290,33 @@ def test_trained_network_gain():
     assert g["learned"]["fallbacks"] == 0 and g["learned"]["max_relres"] <= 1e-6
     assert g["learned"]["vcycles"] < g["zero"]["vcycles"]
     assert g["learned"]["vcycles"] < g["newton"]["vcycles"]
+
+
+def test_point_mass_baselines():
+    """The network's input and target are departures from the softened
+    point-mass potentials of the box's mass (the oracle's closed forms at
+    r_s = sqrt(r^2 + soft^2)), and inference adds the QUMOND one back."""
+    n, L, M, soft = 17, 40.0, 3e10, 2.5
+    h = L / (n - 1)
+    net = Q.UNet(n, seed=3)
+    rng = np.random.default_rng(8)
+    phin, S, phi = (rng.standard_normal((n, n, n)) * 1e3 for _ in range(3))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    c_phin, c_out = 2e3, 5e3
+    GM = O.G_KPC * M
+    x2, t = net.prepare_sample(dev(phin), dev(S), dev(phi), h, c_phin, c_out, GM=GM, a0=O.A0_KPC, soft=soft)
+    ax = -0.5 * L + h * np.arange(n)
+    zz, yy, xx = np.meshgrid(ax, ax, ax, indexing="ij")
+    rs = np.sqrt(xx ** 2 + yy ** 2 + zz ** 2 + soft ** 2)
+    bn = O.phi_point_newton(rs, M=M)
+    bq = O.phi_point_mond(rs, M=M)
+    x2 = x2.float().cpu().numpy().reshape(n, n, n, 2)
+    ref0 = ((phin - bn) / c_phin).astype(np.float32)
+    assert np.abs(x2[..., 0] - ref0).max() <= 1e-2 * np.abs(ref0).max()   # BF16 rounding
+    ref_t = (phi - bq) / c_out
+    assert np.abs(t.cpu().numpy().reshape(n, n, n) - ref_t).max() <= 1e-6 * np.abs(ref_t).max()
+    g1 = net.infer(dev(phin), dev(S), h, c_phin, c_out, GM=GM, a0=O.A0_KPC, soft=soft).cpu().numpy()
+    # the same prediction without baselines but with the input shifted by B_N
+    # (the two inputs may differ in a last bit, hence BF16-level agreement)
+    g0 = net.infer(dev(phin - bn), dev(S), h, c_phin, c_out).cpu().numpy()
+    assert np.abs((g1 - g0).reshape(n, n, n) - bq).max() <= 1e-2 * c_out < 1e-2 * np.abs(bq).max()
