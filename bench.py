@@ -20,6 +20,10 @@ of its launches divided by their summed durations, from hipEvents recorded by
 the library around each launch on the solve's stream during a second pass of
 the same K steps.  cpu_baseline times the CPU oracle (single thread) on one
 full step of the same workload.
+
+Further legs (same JSON line, not the headline value): the 513^3 disk to 1e-6
+in FP64 and in mixed precision; the batched fit (64 disks of 129^3/257^3 in one
+captured graph); the learned initial guess on held-out 129^3 disks.
 """
 import argparse
 import hashlib
@@ -160,6 +164,29 @@ def batched_fit(Q, synth, torch, np, reps=3, refine_iters=4):
     return out
 
 
+def learned_leg(Q, torch, np, count=8):
+    """Wall time and V-cycles of the QUMOND solve to 1e-6 on held-out disks
+    (seed family 6, 129^3, 120 kpc) for the plain FP64 FMG, FP64 V-cycles from
+    zero / Phi_N / the trained network's prediction, the mixed FMG and the
+    network's prediction followed by mixed-precision refinement; inference
+    time is included where the prediction is used."""
+    from paper_1201_3185_amd import learned
+    ckpt = os.path.join(HERE, "paper_1201_3185_amd", "weights", "unet129.npy")
+    if not os.path.exists(ckpt):
+        return None
+    net = Q.UNet(129, seed=0)
+    net.set_params(np.load(ckpt))
+    g = learned.gain(net, learned.disk_set(count, config=6))
+    g["workload"] = (f"{count} held-out two-component disks (fit parameter ranges), one 129^3 box of 120 kpc, "
+                     "QUMOND solve to 1e-6 from the same Phi_N and source")
+    g["speedup_vs_fmg"] = {k: g["fmg"]["ms"] / g[k]["ms"] for k in learned.VARIANTS}
+    log("learned guess: " + ", ".join(f"{k} {g[k]['ms']:.2f} ms" for k in learned.VARIANTS) +
+        f", inference {g['infer_ms']:.2f} ms")
+    net = None
+    torch.cuda.empty_cache()
+    return g
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +196,10 @@ def main():
     ap.add_argument("--no-profile-pass", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the 513^3 FP64-vs-mixed comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-disk batched fit")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess comparison")
+    ap.add_argument("--save-tune", default=None, help="write the autotuned smoother table to this JSON file")
+    ap.add_argument("--tune-table", default=None, help="load the smoother table from this JSON file instead of "
+                                                       "autotuning (to replay the same launches under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a design "
@@ -188,8 +219,12 @@ def main():
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     x, y, z, m = dev(p.x), dev(p.y), dev(p.z), dev(p.m)
     M = p.total_mass
-    log("autotuning smoother launch shapes (setup, not timed)")
-    tuned = Q.autotune(n_max=n, both=False, reps=5)
+    if args.tune_table:
+        log(f"loading smoother launch shapes from {args.tune_table}")
+        Q.tune_load(args.tune_table)
+    else:
+        log("autotuning smoother launch shapes (setup, not timed)")
+        Q.autotune(n_max=n, both=False, reps=5, json_path=args.save_tune)
     shapes = {str(k): {"single": Q.tune_get(k), "fused": Q.tune_get_fused(k)} for k in (33, 65, 129)}
     cfg = Q.Config(n=n, box_side=sides, tol_rel=1e-10)
     ctx = Q.Context(cfg)
@@ -240,6 +275,10 @@ def main():
     if not args.no_batch:
         batch = batched_fit(Q, synth, torch, np)
 
+    learned_out = None
+    if not args.no_learned:
+        learned_out = learned_leg(Q, torch, np)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -266,6 +305,7 @@ def main():
         "smoother_shapes": shapes,
         "mixed_vs_fp64_513": mixed,
         "batched_fit_64": batch,
+        "learned_guess_129": learned_out,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -605,14 +605,85 @@ static dim3 grid3(int m, dim3 blk, int nb, int &zb)
     return dim3((m + blk.x - 1) / blk.x, (m + blk.y - 1) / blk.y, zb * nb);
 }
 
+// The same result with the fine block staged in LDS: a workgroup owns an
+// 8 x 8 x 4 block of coarse nodes, loads u on the fine nodes it needs plus a
+// one-node ring and f on those nodes once, forms the fine residuals in LDS,
+// and restricts them; each residual and each coarse sum is the same
+// expression in the same order as in residual_restrict_k.
+template <typename T>
+__global__ void __launch_bounds__(256)
+residual_restrict_tile_k(int nf, T ih2, const T *__restrict__ f, const T *__restrict__ u, T *__restrict__ fc,
+                         T *__restrict__ uc0, T *__restrict__ uc1, int tx, int ty, int tz)
+{
+    constexpr int CX = 8, CY = 8, CZ = 4;
+    constexpr int RX = 2 * CX + 1, RY = 2 * CY + 1, RZ = 2 * CZ + 1;   // fine residual region
+    constexpr int UX = RX + 2, UY = RY + 2, UZ = RZ + 2;               // u region (one-node ring)
+    __shared__ T Us[UX * UY * UZ];
+    __shared__ T Rs[RX * RY * RZ];
+    const int nc = (nf + 1) / 2;
+    int bid = blockIdx.x;
+    const int bx = bid % tx;
+    bid /= tx;
+    const int by = bid % ty;
+    bid /= ty;
+    const int bz = bid % tz;
+    const int pb = bid / tz;
+    const size_t Nf = (size_t)nf * nf * nf, Nc = (size_t)nc * nc * nc;
+    f += pb * Nf;
+    u += pb * Nf;
+    fc += pb * Nc;
+    uc0 += pb * Nc;
+    if (uc1) uc1 += pb * Nc;
+    const int I0 = bx * CX, J0 = by * CY, K0 = bz * CZ;         // first coarse node of the block
+    const int fi0 = 2 * I0 - 1, fj0 = 2 * J0 - 1, fk0 = 2 * K0 - 1;   // first fine node of the residual region
+    for (int t = threadIdx.x; t < UX * UY * UZ; t += 256) {
+        const int a = t % UX, b = (t / UX) % UY, c = t / (UX * UY);
+        const int i = fi0 - 1 + a, j = fj0 - 1 + b, k = fk0 - 1 + c;
+        Us[t] = (i >= 0 && i < nf && j >= 0 && j < nf && k >= 0 && k < nf) ? u[id3(nf, i, j, k)] : T(0);
+    }
+    for (int t = threadIdx.x; t < RX * RY * RZ; t += 256) {
+        const int a = t % RX, b = (t / RX) % RY, c = t / (RX * RY);
+        const int i = fi0 + a, j = fj0 + b, k = fk0 + c;
+        Rs[t] = (i >= 1 && i < nf - 1 && j >= 1 && j < nf - 1 && k >= 1 && k < nf - 1) ? f[id3(nf, i, j, k)] : T(0);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < RX * RY * RZ; t += 256) {
+        const int a = t % RX, b = (t / RX) % RY, c = t / (RX * RY);
+        const int i = fi0 + a, j = fj0 + b, k = fk0 + c;
+        if (!(i >= 1 && i < nf - 1 && j >= 1 && j < nf - 1 && k >= 1 && k < nf - 1)) continue;
+        const int q = (a + 1) + UX * ((b + 1) + UY * (c + 1));
+        const T lap = (Us[q - 1] + Us[q + 1] + Us[q - UX] + Us[q + UX] + Us[q - UX * UY] + Us[q + UX * UY] -
+                       T(6) * Us[q]) * ih2;
+        Rs[t] = Rs[t] - lap;
+    }
+    __syncthreads();
+    const int li = threadIdx.x % CX, lj = (threadIdx.x / CX) % CY, lk = threadIdx.x / (CX * CY);
+    const int I = I0 + li, J = J0 + lj, K = K0 + lk;
+    if (I >= nc || J >= nc || K >= nc) return;
+    const size_t C = id3(nc, I, J, K);
+    uc0[C] = T(0);
+    if (I == 0 || J == 0 || K == 0 || I == nc - 1 || J == nc - 1 || K == nc - 1) {
+        if (uc1) uc1[C] = T(0);
+        fc[C] = T(0);
+        return;
+    }
+    const T w[3] = {T(0.25), T(0.5), T(0.25)};
+    T acc = T(0);
+    for (int c = -1; c <= 1; ++c)
+        for (int b = -1; b <= 1; ++b)
+            for (int a = -1; a <= 1; ++a)
+                acc += (w[a + 1] * w[b + 1] * w[c + 1]) * Rs[(2 * li + 1 + a) + RX * ((2 * lj + 1 + b) + RY * (2 * lk + 1 + c))];
+    fc[C] = acc;
+}
+
 template <typename T>
 void launch_residual_restrict(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1, hipStream_t s, int nb)
 {
     const int nc = (nf + 1) / 2;
-    dim3 blk(16, 4, 4);
-    int zb;
-    const dim3 g = grid3(nc, blk, nb, zb);
-    hipLaunchKernelGGL(residual_restrict_k<T>, g, blk, 0, s, nf, T(1.0 / (h * h)), f, u, fc, uc0, uc1, zb);
+    const int tx = (nc + 7) / 8, ty = (nc + 7) / 8, tz = (nc + 3) / 4;
+    const dim3 g((unsigned)((size_t)tx * ty * tz * nb));
+    hipLaunchKernelGGL(residual_restrict_tile_k<T>, g, dim3(256), 0, s, nf, T(1.0 / (h * h)), f, u, fc, uc0, uc1, tx, ty,
+                       tz);
 }
 
 template <typename T>
@@ -776,6 +847,7 @@ struct TailLDS {
         const int tx = threadIdx.x & 7, ty = (threadIdx.x >> 3) & 15, tz = threadIdx.x >> 7;
         const int j = 1 + ty;
         if (j <= m) {
+#pragma unroll 2
             for (int k = 1 + tz; k <= m; k += 8) {
                 const int i = 1 + 2 * tx + ((colour + 1 + j + k) & 1);
                 if (i > m) continue;
@@ -817,6 +889,7 @@ struct TailLDS {
         const int li = threadIdx.x & 15, lj = (threadIdx.x >> 4) & 15, lk = threadIdx.x >> 8;
         if (li < m && lj < m) {
             const int i = 1 + li, j = 1 + lj;
+#pragma unroll 4
             for (int k = 1 + lk; k <= m; k += 4) {
                 const int p = i + n * (j + n * k);
                 R[p] = ff[p] - (uu[p - 1] + uu[p + 1] + uu[p - n] + uu[p + n] + uu[p - n * n] + uu[p + n * n] -
@@ -877,6 +950,7 @@ struct TailLDS {
         const int li = threadIdx.x & 15, lj = (threadIdx.x >> 4) & 15, lk = threadIdx.x >> 8;
         if (li < m && lj < m) {
             const int i = 1 + li, j = 1 + lj;
+#pragma unroll 4
             for (int k = 1 + lk; k <= m; k += 4) {
                 const T v = prolong_at(nc, uc, i, j, k);
                 const int p = i + n * (j + n * k);

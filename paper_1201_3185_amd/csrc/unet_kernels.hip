@@ -179,24 +179,32 @@ void launch_dgrad_weights(const __bf16 *wt, int cin, int cout, int kpad, __bf16 
     hipLaunchKernelGGL(dgrad_weights_k, dim3((cnt + 255) / 256), dim3(256), 0, s, wt, cin, cout, kpad, wd, kpad_d);
 }
 
-// Zero-insertion of a stride-2 output gradient onto the input grid.
+// Zero-insertion of a stride-2 output gradient onto the input grid; one
+// thread per (voxel, group of 8 channels), 16-byte accesses.
 __global__ void dilate_k(Tensor src, Tensor dst, int c)
 {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nf = dst.n, N = nf * nf * nf;
-    if (v >= N) return;
+    const int g8 = c / 8;
+    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const int nf = dst.n;
+    const size_t N = (size_t)nf * nf * nf;
+    if (t >= N * g8) return;
+    const int v = (int)(t / g8), grp = (int)(t - (size_t)v * g8);
     int i, j, k;
     decode3(v, nf, i, j, k);
     const bool even = !((i | j | k) & 1);
     const int nc = src.n;
-    const size_t vc = even ? (size_t)((i >> 1) + nc * ((j >> 1) + nc * (k >> 1))) : 0;
-    for (int ch = 0; ch < c; ++ch) dst.p[(size_t)v * dst.cs + ch] = even ? src.p[vc * src.cs + ch] : (__bf16)0.f;
+    bf16x8 val = {};
+    if (even) {
+        const size_t vc = (size_t)((i >> 1) + nc * ((j >> 1) + nc * (k >> 1)));
+        val = *reinterpret_cast<const bf16x8 *>(src.p + vc * src.cs + 8 * grp);
+    }
+    *reinterpret_cast<bf16x8 *>(dst.p + (size_t)v * dst.cs + 8 * grp) = val;
 }
 
 void launch_dilate(Tensor src, Tensor dst, int c, hipStream_t s)
 {
-    const int N = dst.n * dst.n * dst.n;
-    hipLaunchKernelGGL(dilate_k, dim3((N + 255) / 256), dim3(256), 0, s, src, dst, c);
+    const size_t cnt = (size_t)dst.n * dst.n * dst.n * (c / 8);
+    hipLaunchKernelGGL(dilate_k, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, src, dst, c);
 }
 
 // Weight gradient: partial[split, co, kk] = sum over the split's output voxels
@@ -284,25 +292,40 @@ void launch_wgrad(Tensor x, int cin, Tensor dy, int cout, int kpad, int stride, 
     hipLaunchKernelGGL(split_reduce_k, dim3((cnt + 255) / 256), dim3(256), 0, s, partial, nsplit, cnt, dw);
 }
 
-// bias gradient: partial[split, c] = sum over the split's voxels of dy[v, c]
-__global__ void bgrad_k(Tensor dy, int c, int nsplit, int per, float *__restrict__ partial)
+// Splits of a voxel range for the fixed-order reductions below: at most
+// kMaxSplit workgroups, each over a contiguous range.
+static int reduce_splits(int N)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= c * nsplit) return;
-    const int split = t / c, ch = t - split * c;
+    int ns = (N + 2047) / 2048;
+    return ns < 1 ? 1 : (ns > kMaxSplit ? kMaxSplit : ns);
+}
+
+// bias gradient: partial[split, c] = sum over the split's voxels of dy[v, c].
+// Workgroup = split; thread t sums channel t % c over voxels t / c + q (256 / c)
+// (c divides 256), then the c sums are combined in a fixed order.
+__global__ void __launch_bounds__(256) bgrad_k(Tensor dy, int c, int per, float *__restrict__ partial)
+{
+    __shared__ float sh[256];
     const int N = dy.n * dy.n * dy.n;
-    const int vb = split * per, ve = min(N, vb + per);
+    const int vb = blockIdx.x * per, ve = min(N, vb + per);
+    const int ch = threadIdx.x % c, lanes = 256 / c, l = threadIdx.x / c;
     float s = 0.f;
-    for (int v = vb; v < ve; ++v) s += (float)dy.p[(size_t)v * dy.cs + ch];
-    partial[(size_t)split * c + ch] = s;
+    for (int v = vb + l; v < ve; v += lanes) s += (float)dy.p[(size_t)v * dy.cs + ch];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if ((int)threadIdx.x < c) {
+        float t = 0.f;
+        for (int q = 0; q < lanes; ++q) t += sh[q * c + threadIdx.x];
+        partial[(size_t)blockIdx.x * c + threadIdx.x] = t;
+    }
 }
 
 void launch_bgrad(Tensor dy, int c, float *partial, float *db, hipStream_t s)
 {
     const int N = dy.n * dy.n * dy.n;
-    const int nsplit = N < 4096 ? 1 : (N / 4096 < kMaxSplit ? N / 4096 : kMaxSplit);
+    const int nsplit = reduce_splits(N);
     const int per = (N + nsplit - 1) / nsplit;
-    hipLaunchKernelGGL(bgrad_k, dim3((c * nsplit + 255) / 256), dim3(256), 0, s, dy, c, nsplit, per, partial);
+    hipLaunchKernelGGL(bgrad_k, dim3(nsplit), dim3(256), 0, s, dy, c, per, partial);
     hipLaunchKernelGGL(split_reduce_k, dim3((c + 255) / 256), dim3(256), 0, s, partial, nsplit, c, db);
 }
 
@@ -341,67 +364,84 @@ void launch_add(Tensor dst, Tensor src, int c, hipStream_t s)
     hipLaunchKernelGGL(add_k, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, dst, src, c);
 }
 
-// Trilinear 2x up-sampling of vertex-centred grids (n_fine = 2 n_coarse - 1).
+// Trilinear 2x up-sampling of vertex-centred grids (n_fine = 2 n_coarse - 1);
+// one thread per (fine voxel, group of 8 channels).
 __global__ void upsample_k(Tensor src, Tensor dst, int c)
 {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nf = dst.n, nc = src.n, N = nf * nf * nf;
-    if (v >= N) return;
+    const int g8 = c / 8;
+    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const int nf = dst.n, nc = src.n;
+    const size_t N = (size_t)nf * nf * nf;
+    if (t >= N * g8) return;
+    const int v = (int)(t / g8), grp = (int)(t - (size_t)v * g8);
     int i, j, k;
     decode3(v, nf, i, j, k);
     const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
     const float wi = (i & 1) ? 0.5f : 1.f, wj = (j & 1) ? 0.5f : 1.f, wk = (k & 1) ? 0.5f : 1.f;
     const float wi1 = (i & 1) ? 0.5f : 0.f, wj1 = (j & 1) ? 0.5f : 0.f, wk1 = (k & 1) ? 0.5f : 0.f;
-    auto at = [&](int a, int b, int cc, int ch) { return (float)src.p[(size_t)(a + nc * (b + nc * cc)) * src.cs + ch]; };
-    for (int ch = 0; ch < c; ++ch) {
-        const float x00 = wi * at(i0, j0, k0, ch) + wi1 * at(i1, j0, k0, ch);
-        const float x10 = wi * at(i0, j1, k0, ch) + wi1 * at(i1, j1, k0, ch);
-        const float x01 = wi * at(i0, j0, k1, ch) + wi1 * at(i1, j0, k1, ch);
-        const float x11 = wi * at(i0, j1, k1, ch) + wi1 * at(i1, j1, k1, ch);
-        const float val = wk * (wj * x00 + wj1 * x10) + wk1 * (wj * x01 + wj1 * x11);
-        dst.p[(size_t)v * dst.cs + ch] = (__bf16)val;
+    auto at = [&](int a, int b, int cc) {
+        return *reinterpret_cast<const bf16x8 *>(src.p + (size_t)(a + nc * (b + nc * cc)) * src.cs + 8 * grp);
+    };
+    const bf16x8 a000 = at(i0, j0, k0), a100 = at(i1, j0, k0), a010 = at(i0, j1, k0), a110 = at(i1, j1, k0);
+    const bf16x8 a001 = at(i0, j0, k1), a101 = at(i1, j0, k1), a011 = at(i0, j1, k1), a111 = at(i1, j1, k1);
+    bf16x8 out;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const float x00 = wi * (float)a000[e] + wi1 * (float)a100[e];
+        const float x10 = wi * (float)a010[e] + wi1 * (float)a110[e];
+        const float x01 = wi * (float)a001[e] + wi1 * (float)a101[e];
+        const float x11 = wi * (float)a011[e] + wi1 * (float)a111[e];
+        out[e] = (__bf16)(wk * (wj * x00 + wj1 * x10) + wk1 * (wj * x01 + wj1 * x11));
     }
+    *reinterpret_cast<bf16x8 *>(dst.p + (size_t)v * dst.cs + 8 * grp) = out;
 }
 
 void launch_upsample(Tensor src, Tensor dst, int c, hipStream_t s)
 {
-    const int N = dst.n * dst.n * dst.n;
-    hipLaunchKernelGGL(upsample_k, dim3((N + 255) / 256), dim3(256), 0, s, src, dst, c);
+    const size_t cnt = (size_t)dst.n * dst.n * dst.n * (c / 8);
+    hipLaunchKernelGGL(upsample_k, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, src, dst, c);
 }
 
 // Adjoint of upsample_k: coarse node I gathers w g(2I + d) over d in {-1,0,1}^3,
 // w = product over axes of (1 if d = 0 else 1/2).
+// one thread per (coarse voxel, group of 8 channels)
 __global__ void upsample_adj_k(Tensor gf, Tensor gc, int c)
 {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nc = gc.n, nf = gf.n, N = nc * nc * nc;
-    if (v >= N) return;
+    const int g8 = c / 8;
+    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const int nc = gc.n, nf = gf.n;
+    const size_t N = (size_t)nc * nc * nc;
+    if (t >= N * g8) return;
+    const int v = (int)(t / g8), grp = (int)(t - (size_t)v * g8);
     int I, J, K;
     decode3(v, nc, I, J, K);
-    for (int ch = 0; ch < c; ++ch) {
-        float s = 0.f;
-        for (int dz = -1; dz <= 1; ++dz) {
-            const int k = 2 * K + dz;
-            if (k < 0 || k >= nf) continue;
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int j = 2 * J + dy;
-                if (j < 0 || j >= nf) continue;
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int i = 2 * I + dx;
-                    if (i < 0 || i >= nf) continue;
-                    const float w = (dx ? 0.5f : 1.f) * (dy ? 0.5f : 1.f) * (dz ? 0.5f : 1.f);
-                    s += w * (float)gf.p[(size_t)(i + nf * (j + nf * k)) * gf.cs + ch];
-                }
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int k = 2 * K + dz;
+        if (k < 0 || k >= nf) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int j = 2 * J + dy;
+            if (j < 0 || j >= nf) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int i = 2 * I + dx;
+                if (i < 0 || i >= nf) continue;
+                const float w = (dx ? 0.5f : 1.f) * (dy ? 0.5f : 1.f) * (dz ? 0.5f : 1.f);
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(gf.p + (size_t)(i + nf * (j + nf * k)) * gf.cs + 8 * grp);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) s[e] += w * (float)a[e];
             }
         }
-        gc.p[(size_t)v * gc.cs + ch] = (__bf16)s;
     }
+    bf16x8 out;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[e] = (__bf16)s[e];
+    *reinterpret_cast<bf16x8 *>(gc.p + (size_t)v * gc.cs + 8 * grp) = out;
 }
 
 void launch_upsample_adj(Tensor gf, Tensor gc, int c, hipStream_t s)
 {
-    const int N = gc.n * gc.n * gc.n;
-    hipLaunchKernelGGL(upsample_adj_k, dim3((N + 255) / 256), dim3(256), 0, s, gf, gc, c);
+    const size_t cnt = (size_t)gc.n * gc.n * gc.n * (c / 8);
+    hipLaunchKernelGGL(upsample_adj_k, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, gf, gc, c);
 }
 
 // ------------------------------------------------------------- head, loss
@@ -432,17 +472,33 @@ __global__ void head_bwd_x_k(const float *__restrict__ dyh, int c, const float *
     for (int ch = 0; ch < c; ++ch) dx.p[(size_t)v * dx.cs + ch] = (__bf16)(dyh[v] * w[ch]);
 }
 
-// partial[split, c] = sum dy[v] x[v, c] (c < C), partial[split, C] = sum dy[v]
-__global__ void head_bwd_w_k(const float *__restrict__ dyh, Tensor x, int c, int nsplit, int per, float *__restrict__ partial)
+// partial[split, c] = sum dy[v] x[v, c] (c < C), partial[split, C] = sum dy[v];
+// workgroup = split, fixed-order combination as in bgrad_k (C divides 256).
+__global__ void __launch_bounds__(256)
+head_bwd_w_k(const float *__restrict__ dyh, Tensor x, int c, int per, float *__restrict__ partial)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (c + 1) * nsplit) return;
-    const int split = t / (c + 1), ch = t - split * (c + 1);
+    __shared__ float sh[256], sb[256];
     const int N = x.n * x.n * x.n;
-    const int vb = split * per, ve = min(N, vb + per);
-    float s = 0.f;
-    for (int v = vb; v < ve; ++v) s += dyh[v] * (ch < c ? (float)x.p[(size_t)v * x.cs + ch] : 1.f);
-    partial[(size_t)split * (c + 1) + ch] = s;
+    const int vb = blockIdx.x * per, ve = min(N, vb + per);
+    const int ch = threadIdx.x % c, lanes = 256 / c, l = threadIdx.x / c;
+    float s = 0.f, sbias = 0.f;
+    for (int v = vb + l; v < ve; v += lanes) {
+        const float d = dyh[v];
+        s += d * (float)x.p[(size_t)v * x.cs + ch];
+        sbias += d;
+    }
+    sh[threadIdx.x] = s;
+    sb[threadIdx.x] = sbias;
+    __syncthreads();
+    if ((int)threadIdx.x < c) {
+        float t = 0.f;
+        for (int q = 0; q < lanes; ++q) t += sh[q * c + threadIdx.x];
+        partial[(size_t)blockIdx.x * (c + 1) + threadIdx.x] = t;
+    } else if ((int)threadIdx.x == c) {
+        float t = 0.f;
+        for (int q = 0; q < lanes; ++q) t += sb[q * c];   // channel-0 threads saw every voxel once
+        partial[(size_t)blockIdx.x * (c + 1) + c] = t;
+    }
 }
 
 void launch_head_bwd(const float *dyh, Tensor x, int c, const float *w, Tensor dx, float *partial, float *dwb,
@@ -450,10 +506,9 @@ void launch_head_bwd(const float *dyh, Tensor x, int c, const float *w, Tensor d
 {
     const int N = x.n * x.n * x.n;
     hipLaunchKernelGGL(head_bwd_x_k, dim3((N + 255) / 256), dim3(256), 0, s, dyh, c, w, dx);
-    const int nsplit = N < 4096 ? 1 : (N / 4096 < kMaxSplit ? N / 4096 : kMaxSplit);
+    const int nsplit = reduce_splits(N);
     const int per = (N + nsplit - 1) / nsplit;
-    hipLaunchKernelGGL(head_bwd_w_k, dim3(((c + 1) * nsplit + 255) / 256), dim3(256), 0, s, dyh, x, c, nsplit, per,
-                       partial);
+    hipLaunchKernelGGL(head_bwd_w_k, dim3(nsplit), dim3(256), 0, s, dyh, x, c, per, partial);
     hipLaunchKernelGGL(split_reduce_k, dim3(1), dim3(256), 0, s, partial, nsplit, c + 1, dwb);
 }
 
