@@ -34,6 +34,12 @@ qumond_status qumond_tune_get(int32_t n, int32_t fp32, int32_t *variant, int32_t
 qumond_status qumond_tune_set_fused(int32_t n, int32_t fp32, int32_t variant, int32_t kchunk);
 qumond_status qumond_tune_get_fused(int32_t n, int32_t fp32, int32_t *variant, int32_t *kchunk);
 
+/* Residual restriction kernel for a fine level of n points: variant 0 = one
+ * thread per coarse node gathering its 27 fine residuals, 1 = LDS tile of the
+ * fine block (identical results; the autotuner picks the faster). */
+qumond_status qumond_tune_set_rr(int32_t n, int32_t fp32, int32_t variant);
+qumond_status qumond_tune_get_rr(int32_t n, int32_t fp32, int32_t *variant);
+
 /* One smoother sweep with an explicit shape (see qumond_k_rbgs_sweep). */
 qumond_status qumond_k_rbgs_sweep_shape(int32_t n, double h, const double *f, const double *u_in, double *u_out,
                                         int32_t variant, int32_t kchunk, void *stream);

@@ -90,6 +90,12 @@ template <typename T> SmootherShape &rbgs2_shape(int n);
 template <typename T> int &use_fused(int n);
 template <typename T> void launch_residual_restrict(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1,
                                                    hipStream_t s, int nb = 1);
+// The two implementations of the residual restriction (0: per-node gather,
+// 1: LDS tile; identical results) and the table entry that selects one per
+// fine level size (set by the autotuner).
+template <typename T> void launch_residual_restrict_variant(int nf, double h, const T *f, const T *u, T *fc, T *uc0,
+                                                           T *uc1, int variant, hipStream_t s, int nb = 1);
+template <typename T> int &rr_variant(int nf);
 template <typename T> void launch_restrict(int nf, const T *src, T *dst, hipStream_t s, int nb = 1);
 template <typename T> void launch_prolong_add(int nc, const T *uc, T *uf, hipStream_t s, int nb = 1);
 template <typename T> void launch_interp(int nc, const T *uc, T *uf, hipStream_t s, int nb = 1);

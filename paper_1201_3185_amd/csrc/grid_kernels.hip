@@ -37,6 +37,17 @@ __device__ __forceinline__ T prolong_at(int nc, const T *__restrict__ uc, int i,
     return wka * (wja * xa + wjb * xb) + wkb * (wja * xc + wjb * xd);
 }
 
+// Workgroups are dispatched to the 8 XCDs round robin (hardware id w runs on
+// XCD w mod 8), and each XCD has its own L2.  xcd_tile gives hardware id w the
+// tile (w mod 8) * (nblk / 8) + w / 8, so that each XCD works through one
+// contiguous range of tiles and neighbouring tiles share their halos in one
+// L2; ids beyond the last multiple of 8 keep their own tile.
+__device__ __forceinline__ unsigned xcd_tile(unsigned w, unsigned nblk)
+{
+    const unsigned full = nblk & ~7u;
+    return w < full ? (w & 7u) * (full >> 3) + (w >> 3) : w;
+}
+
 // ------------------------------------------------------------------ smoother
 
 template <typename T, int TX, int TY>
@@ -51,9 +62,12 @@ rbgs_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict
     __shared__ T pl[NS][PL];
     const T sixth = T(1) / T(6);
     const int tid = threadIdx.x;
-    const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
-    const int pb = blockIdx.z / nzc;
-    const int kb = 1 + (blockIdx.z - pb * nzc) * kchunk;
+    const unsigned tl = xcd_tile(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                 gridDim.x * gridDim.y * gridDim.z);
+    const int bx = tl % gridDim.x, by = (tl / gridDim.x) % gridDim.y, bzz = tl / (gridDim.x * gridDim.y);
+    const int i0 = 1 + bx * TX, j0 = 1 + by * TY;
+    const int pb = bzz / nzc;
+    const int kb = 1 + (bzz - pb * nzc) * kchunk;
     if (kb > n - 2) return;
     const int ke = min(kb + kchunk - 1, n - 2);
     const size_t nn = (size_t)n * n;
@@ -206,7 +220,7 @@ rbgs_brick(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict_
     __shared__ T F[FE * FE * FE];
     const T sixth = T(1) / T(6);
     const int tid = threadIdx.x;
-    int bid = blockIdx.x;
+    int bid = (int)xcd_tile(blockIdx.x, gridDim.x);
     const int bx = bid % nbx;
     bid /= nbx;
     const int by = bid % nbx;
@@ -304,9 +318,12 @@ rbgs2_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
     __shared__ T fp[NF][FL];
     const T sixth = T(1) / T(6);
     const int tid = threadIdx.x;
-    const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
-    const int pb = blockIdx.z / nzc;
-    const int kb = 1 + (blockIdx.z - pb * nzc) * kchunk;
+    const unsigned tl = xcd_tile(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                 gridDim.x * gridDim.y * gridDim.z);
+    const int bx = tl % gridDim.x, by = (tl / gridDim.x) % gridDim.y, bzz = tl / (gridDim.x * gridDim.y);
+    const int i0 = 1 + bx * TX, j0 = 1 + by * TY;
+    const int pb = bzz / nzc;
+    const int kb = 1 + (bzz - pb * nzc) * kchunk;
     if (kb > n - 2) return;
     const int ke = min(kb + kchunk - 1, n - 2);
     const size_t nn = (size_t)n * n;
@@ -621,7 +638,7 @@ residual_restrict_tile_k(int nf, T ih2, const T *__restrict__ f, const T *__rest
     __shared__ T Us[UX * UY * UZ];
     __shared__ T Rs[RX * RY * RZ];
     const int nc = (nf + 1) / 2;
-    int bid = blockIdx.x;
+    int bid = (int)xcd_tile(blockIdx.x, gridDim.x);
     const int bx = bid % tx;
     bid /= tx;
     const int by = bid % ty;
@@ -676,14 +693,40 @@ residual_restrict_tile_k(int nf, T ih2, const T *__restrict__ f, const T *__rest
     fc[C] = acc;
 }
 
+// Which residual-restriction kernel a fine level of n points uses (0: per-node
+// gather, 1: LDS tile), per precision; set by the autotuner, tile by default.
+static int g_rr_variant[2][11] = {{1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1}, {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1}};
+
 template <typename T>
-void launch_residual_restrict(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1, hipStream_t s, int nb)
+int &rr_variant(int nf)
+{
+    int J = 0;
+    while ((1 << J) < nf - 1) ++J;
+    return g_rr_variant[sizeof(T) == 4 ? 1 : 0][J > 10 ? 10 : J];
+}
+
+template <typename T>
+void launch_residual_restrict_variant(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1, int variant,
+                                      hipStream_t s, int nb)
 {
     const int nc = (nf + 1) / 2;
+    if (variant == 0) {
+        dim3 blk(16, 4, 4);
+        int zb;
+        const dim3 g = grid3(nc, blk, nb, zb);
+        hipLaunchKernelGGL(residual_restrict_k<T>, g, blk, 0, s, nf, T(1.0 / (h * h)), f, u, fc, uc0, uc1, zb);
+        return;
+    }
     const int tx = (nc + 7) / 8, ty = (nc + 7) / 8, tz = (nc + 3) / 4;
     const dim3 g((unsigned)((size_t)tx * ty * tz * nb));
     hipLaunchKernelGGL(residual_restrict_tile_k<T>, g, dim3(256), 0, s, nf, T(1.0 / (h * h)), f, u, fc, uc0, uc1, tx, ty,
                        tz);
+}
+
+template <typename T>
+void launch_residual_restrict(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1, hipStream_t s, int nb)
+{
+    launch_residual_restrict_variant<T>(nf, h, f, u, fc, uc0, uc1, rr_variant<T>(nf), s, nb);
 }
 
 template <typename T>
@@ -1297,6 +1340,9 @@ void launch_guess_interior(int n, const void *g, int kind, double *u, hipStream_
                                         hipStream_t, int);                                                      \
     template void launch_residual_restrict<T>(int, double, const T *, const T *, T *, T *, T *, hipStream_t,    \
                                               int);                                                             \
+    template void launch_residual_restrict_variant<T>(int, double, const T *, const T *, T *, T *, T *, int,     \
+                                                      hipStream_t, int);                                        \
+    template int &rr_variant<T>(int);                                                                           \
     template void launch_restrict<T>(int, const T *, T *, hipStream_t, int);                                   \
     template void launch_prolong_add<T>(int, const T *, T *, hipStream_t, int);                                \
     template void launch_interp<T>(int, const T *, T *, hipStream_t, int);                                     \

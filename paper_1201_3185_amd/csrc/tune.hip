@@ -92,6 +92,61 @@ qumond_status tune_one(int n, int reps, hipStream_t s, double &best_us, bool fus
     return QUMOND_OK;
 }
 
+// Time both residual-restriction kernels on a fine level of n points and
+// install the faster one.
+template <typename T>
+qumond_status tune_rr(int n, int reps, hipStream_t s, double us[2])
+{
+    const int nc = (n + 1) / 2;
+    const size_t N = (size_t)n * n * n, Nc = (size_t)nc * nc * nc;
+    T *f = nullptr, *u = nullptr, *fc = nullptr, *c0 = nullptr, *c1 = nullptr;
+    if (hipMalloc((void **)&f, N * sizeof(T)) != hipSuccess || hipMalloc((void **)&u, N * sizeof(T)) != hipSuccess ||
+        hipMalloc((void **)&fc, Nc * sizeof(T)) != hipSuccess || hipMalloc((void **)&c0, Nc * sizeof(T)) != hipSuccess ||
+        hipMalloc((void **)&c1, Nc * sizeof(T)) != hipSuccess) {
+        (void)hipFree(f);
+        (void)hipFree(u);
+        (void)hipFree(fc);
+        (void)hipFree(c0);
+        qm_set_last_error("qumond_autotune: allocation failed");
+        return QUMOND_ERR_OOM;
+    }
+    qm::launch_fill<T>(f, N, T(1), s);
+    qm::launch_fill<T>(u, N, T(0.5), s);
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const double h = 1.0 / (n - 1);
+    for (int v = 0; v < 2; ++v) {
+        qm::launch_residual_restrict_variant<T>(n, h, f, u, fc, c0, c1, v, s);
+        std::vector<float> t;
+        for (int r = 0; r < reps; ++r) {
+            (void)hipEventRecord(e0, s);
+            qm::launch_residual_restrict_variant<T>(n, h, f, u, fc, c0, c1, v, s);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            t.push_back(ms);
+        }
+        std::sort(t.begin(), t.end());
+        us[v] = 1e3 * t[t.size() / 2];
+    }
+    qm::rr_variant<T>(n) = us[1] < us[0] ? 1 : 0;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(f);
+    (void)hipFree(u);
+    (void)hipFree(fc);
+    (void)hipFree(c0);
+    (void)hipFree(c1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        qm_set_last_error(hipGetErrorString(e));
+        return QUMOND_ERR_HIP;
+    }
+    return QUMOND_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -131,6 +186,21 @@ qumond_status qumond_tune_get_fused(int32_t n, int32_t fp32, int32_t *variant, i
     const qm::SmootherShape sh = fp32 ? qm::rbgs2_shape<float>(n) : qm::rbgs2_shape<double>(n);
     *variant = sh.variant;
     *kchunk = sh.kchunk;
+    return QUMOND_OK;
+}
+
+qumond_status qumond_tune_set_rr(int32_t n, int32_t fp32, int32_t variant)
+{
+    if (!good_n(n) || (variant != 0 && variant != 1)) return tfail("qumond_tune_set_rr: bad argument");
+    if (fp32) qm::rr_variant<float>(n) = variant;
+    else qm::rr_variant<double>(n) = variant;
+    return QUMOND_OK;
+}
+
+qumond_status qumond_tune_get_rr(int32_t n, int32_t fp32, int32_t *variant)
+{
+    if (!good_n(n) || !variant) return tfail("qumond_tune_get_rr: bad argument");
+    *variant = fp32 ? qm::rr_variant<float>(n) : qm::rr_variant<double>(n);
     return QUMOND_OK;
 }
 
@@ -180,8 +250,15 @@ qumond_status qumond_autotune(int32_t n_max, int32_t both, int32_t reps, const c
             const int fuse = us_pair[1] < 2.0 * us_pair[0] ? 1 : 0;
             if (prec) qm::use_fused<float>(n) = fuse;
             else qm::use_fused<double>(n) = fuse;
-            char buf[96];
-            std::snprintf(buf, sizeof buf, ", {\"n\": %d, \"fp32\": %d, \"use_fused\": %d}", n, prec, fuse);
+            double rr_us[2] = {0.0, 0.0};
+            const qumond_status st = prec ? tune_rr<float>(n, reps, s, rr_us) : tune_rr<double>(n, reps, s, rr_us);
+            if (st != QUMOND_OK) return st;
+            const int rrv = prec ? qm::rr_variant<float>(n) : qm::rr_variant<double>(n);
+            char buf[200];
+            std::snprintf(buf, sizeof buf,
+                          ", {\"n\": %d, \"fp32\": %d, \"use_fused\": %d}, {\"n\": %d, \"fp32\": %d, \"rr\": %d, "
+                          "\"rr_us\": [%.3f, %.3f]}",
+                          n, prec, fuse, n, prec, rrv, rr_us[0], rr_us[1]);
             js += buf;
         }
     }
@@ -225,6 +302,15 @@ qumond_status qumond_tune_load(const char *json_path)
             good_n(n)) {
             if (fp32) qm::use_fused<float>(n) = fuse ? 1 : 0;
             else qm::use_fused<double>(n) = fuse ? 1 : 0;
+        }
+        ++pos;
+    }
+    pos = 0;
+    while ((pos = txt.find("{\"n\":", pos)) != std::string::npos) {
+        int n = 0, fp32 = 0, rrv = 0;
+        if (std::sscanf(txt.c_str() + pos, "{\"n\": %d, \"fp32\": %d, \"rr\": %d", &n, &fp32, &rrv) == 3 && good_n(n)) {
+            if (fp32) qm::rr_variant<float>(n) = rrv ? 1 : 0;
+            else qm::rr_variant<double>(n) = rrv ? 1 : 0;
         }
         ++pos;
     }

@@ -125,11 +125,109 @@ conv3d_fwd_k(Tensor x, int cin, const __bf16 *__restrict__ wt, int kpad, const f
     }
 }
 
+// Stride-1 convolution with the input tile in LDS: a workgroup computes a
+// 16 x 4 x 4 block of output voxels (each wave 4 x-rows of 16 voxels, one
+// MFMA row block each) for all cout = 16 NB channels.  The input channels are
+// taken in chunks of up to 32; for each chunk the 18 x 6 x 6 input voxels
+// (block plus a one-voxel ring) are staged in LDS once and every one of the
+// 27 taps reads its activation fragments from there.  Within a chunk of cc
+// channels the K-steps of 32 cover 32 / cc taps at a time (cc = 8, 16 or 32),
+// in the same (tap, channel) order as conv3d_fwd_k.
+constexpr int kTileX = 16, kTileY = 4, kTileZ = 4;
+constexpr int kInX = kTileX + 2, kInY = kTileY + 2, kInZ = kTileZ + 2, kInV = kInX * kInY * kInZ;
+constexpr int kChunk = 32, kPitch = kChunk + 8;   // bf16 per staged voxel (padded against bank conflicts)
+
+template <int NB>
+__global__ void __launch_bounds__(256)
+conv3d_fwd_lds_k(Tensor x, int cin, const __bf16 *__restrict__ wt, int kpad, const float *__restrict__ bias, Tensor y,
+                 int relu, int tx, int ty)
+{
+    constexpr int RB = 4;
+    __shared__ __bf16 tile[kInV * kPitch];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const int n = y.n;   // = x.n (stride 1)
+    int bid = blockIdx.x;
+    const int bx = bid % tx;
+    bid /= tx;
+    const int by = bid % ty;
+    const int bz = bid / ty;
+    const int X0 = bx * kTileX, Y0 = by * kTileY, Z0 = bz * kTileZ;
+    const size_t xcs = (size_t)x.cs;
+    f32x4 acc[RB][NB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[rb][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // this lane's rows: wave w, row block rb -> output row (y, z) = (rb, w) of the block, x = r16
+    for (int cb = 0; cb < cin; cb += kChunk) {
+        const int cc = min(kChunk, cin - cb);     // 8, 16 or 32 (cin is a multiple of 8; chunks of 32 then the rest)
+        const int g8 = cc / 8;
+        __syncthreads();
+        for (int t = threadIdx.x; t < kInV * g8; t += 256) {
+            const int v = t / g8, q = t - v * g8;
+            const int a = v % kInX, b = (v / kInX) % kInY, c = v / (kInX * kInY);
+            const int i = X0 - 1 + a, j = Y0 - 1 + b, k = Z0 - 1 + c;
+            bf16x8 val = {};
+            if (i >= 0 && i < n && j >= 0 && j < n && k >= 0 && k < n)
+                val = *reinterpret_cast<const bf16x8 *>(x.p + (size_t)(i + n * (j + n * k)) * xcs + cb + 8 * q);
+            *reinterpret_cast<bf16x8 *>(tile + v * kPitch + 8 * q) = val;
+        }
+        __syncthreads();
+        const int steps = (27 * cc + 31) / 32;
+        for (int st = 0; st < steps; ++st) {
+            const int kl = 32 * st + 8 * g;        // local K index of this lane's fragment
+            const int tap = kl / cc, cl = kl - tap * cc;
+            const bool live = tap < 27;
+            const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;   // offsets + 1
+            bf16x8 a[RB], w[NB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const int v = (r16 + dx) + kInX * ((rb + dy) + kInY * (wave + dz));
+                a[rb] = live ? *reinterpret_cast<const bf16x8 *>(tile + v * kPitch + cl) : bf16x8{};
+            }
+            const int kw = live ? tap * cin + cb + cl : 0;
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                w[b] = live ? *reinterpret_cast<const bf16x8 *>(wt + (size_t)(b * 16 + r16) * kpad + kw) : bf16x8{};
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    acc[rb][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], w[b], acc[rb][b], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int co = b * 16 + r16;
+        const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            const int j = Y0 + rb, k = Z0 + wave;
+            if (j >= n || k >= n) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = X0 + 4 * g + r;
+                if (i >= n) continue;
+                float val = acc[rb][b][r] + bb;
+                if (relu) val = val > 0.f ? val : 0.f;
+                y.p[(size_t)(i + n * (j + n * k)) * y.cs + co] = (__bf16)val;
+            }
+        }
+    }
+}
+
 template <int NB>
 static void conv_fwd_nb(Tensor x, int cin, const __bf16 *wt, int kpad, const float *bias, Tensor y, int stride,
                         int relu, hipStream_t s)
 {
     const int Nout = y.n * y.n * y.n;
+    if (stride == 1 && NB <= 4 && (cin % 32 == 0 || cin == 8 || cin == 16 || cin == 48)) {
+        const int tx = (y.n + kTileX - 1) / kTileX, ty = (y.n + kTileY - 1) / kTileY, tz = (y.n + kTileZ - 1) / kTileZ;
+        hipLaunchKernelGGL((conv3d_fwd_lds_k<NB <= 4 ? NB : 4>), dim3((unsigned)(tx * ty * tz)), dim3(256), 0, s, x,
+                           cin, wt, kpad, bias, y, relu, tx, ty);
+        return;
+    }
     // RB row blocks per wave while the grid keeps at least ~1024 workgroups
     if (Nout >= 1024 * 256 && NB <= 4) {
         hipLaunchKernelGGL((conv3d_fwd_k<NB, 4>), dim3((Nout + 255) / 256), dim3(256), 0, s, x, cin, wt, kpad, bias, y,

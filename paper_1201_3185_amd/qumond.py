@@ -125,6 +125,8 @@ _SIGNATURES = {
     "qumond_k_rbgs_sweep_shape": (_I32, [_I32, _D, _P, _P, _P, _I32, _I32, _P]),
     "qumond_autotune": (_I32, [_I32, _I32, _I32, ctypes.c_char_p, ctypes.POINTER(_D), _P]),
     "qumond_tune_load": (_I32, [ctypes.c_char_p]),
+    "qumond_tune_set_rr": (_I32, [_I32, _I32, _I32]),
+    "qumond_tune_get_rr": (_I32, [_I32, _I32, ctypes.POINTER(_I32)]),
     "qumond_batch_default_config": (None, [ctypes.POINTER(qumond_batch_config)]),
     "qumond_batch_validate": (_I32, [ctypes.POINTER(qumond_batch_config), _P, _P, _I32]),
     "qumond_batch_create": (_I32, [ctypes.POINTER(qumond_batch_config), _P, _P, _I32, _P, ctypes.POINTER(_P)]),
@@ -441,6 +443,16 @@ def autotune(n_max=513, both=True, reps=5, json_path=None):
     check(lib().qumond_autotune(int(n_max), int(bool(both)), int(reps), json_path.encode() if json_path else None,
                                 best, _s()), "qumond_autotune")
     return {(1 << J) + 1: best[J] for J in range(5, 11) if best[J] > 0}
+
+
+def tune_set_rr(n, variant, fp32=False):
+    check(lib().qumond_tune_set_rr(int(n), int(bool(fp32)), int(variant)), "qumond_tune_set_rr")
+
+
+def tune_get_rr(n, fp32=False):
+    v = ctypes.c_int32()
+    check(lib().qumond_tune_get_rr(int(n), int(bool(fp32)), ctypes.byref(v)), "qumond_tune_get_rr")
+    return v.value
 
 
 def tune_load(json_path):

@@ -91,6 +91,27 @@ def test_residual_restrict(n):
         assert np.all(u1[1:-1, 1:-1, 1:-1] == 9.0)
 
 
+@pytest.mark.parametrize("n", [9, 17, 33, 65, 129])
+def test_residual_restrict_variants_bitwise(n):
+    """The gather and the LDS-tile residual restriction give the same bits."""
+    L = 3.0
+    h = L / (n - 1)
+    f, u = rand_state(n, 400 + n)
+    nc = (n + 1) // 2
+    before = Q.tune_get_rr(n)
+    outs = []
+    try:
+        for v in (0, 1):
+            Q.tune_set_rr(n, v)
+            fc, uc0, uc1 = (dev(np.full((nc,) * 3, 3.0)) for _ in range(3))
+            Q.k_residual_restrict(dev(f), dev(u), h, fc, uc0, uc1)
+            outs.append((host(fc), host(uc0), host(uc1)))
+    finally:
+        Q.tune_set_rr(n, before)
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("n", SIZES)
 def test_restrict(n):
     src = rand_state(n, 300 + n)[0]
