@@ -263,7 +263,7 @@ def main():
         tr = smoother_traffic(per_launch)
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
-                "kernel": "red-black smoother launches, all levels (fused two-sweep rbgs2_zmarch; 24 B/pt per launch)", "launches_per_step": st["launches"] // args.steps,
+                "kernel": "red-black smoother launches, all levels (z-march and brick kernels, one or two sweeps per launch; 24 B/pt per launch)", "launches_per_step": st["launches"] // args.steps,
                 "avg_launch_us": round(avg_ms * 1e3, 3), "alg_bytes_per_launch": per_launch}
         log(f"smoother: {st['launches']} launches, avg {avg_ms * 1e3:.2f} us, {achieved:.1f} GB/s algorithmic")
 
