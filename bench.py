@@ -111,7 +111,7 @@ def mixed_vs_fp64(Q, synth, torch, np, dev, reps=3):
     return out
 
 
-def batched_fit(Q, synth, torch, np, reps=3, refine_iters=4):
+def batched_fit(Q, synth, torch, np, reps=3, refine_iters=3):
     """The batched rotation-curve fit: 64 two-component disks on the seeded
     parameter grid (M/L 0.3-1.2, z* 0.1-0.6 kpc, z_g 0.05-0.5 kpc, distance
     +-20%, 2e5-2e6 particles), grids 129^3 or 257^3 in a 120 kpc box, mixed

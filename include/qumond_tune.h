@@ -40,9 +40,11 @@ qumond_status qumond_tune_get_fused(int32_t n, int32_t fp32, int32_t *variant, i
 qumond_status qumond_tune_set_rr(int32_t n, int32_t fp32, int32_t variant);
 qumond_status qumond_tune_get_rr(int32_t n, int32_t fp32, int32_t *variant);
 
-/* One smoother sweep with an explicit shape (see qumond_k_rbgs_sweep). */
+/* One smoother sweep with an explicit shape (see qumond_k_rbgs_sweep); with
+ * uc != NULL (device, ((n+1)/2)^3 doubles) the correction u += P uc is applied
+ * to u_in's interior first, in the same launch. */
 qumond_status qumond_k_rbgs_sweep_shape(int32_t n, double h, const double *f, const double *u_in, double *u_out,
-                                        int32_t variant, int32_t kchunk, void *stream);
+                                        int32_t variant, int32_t kchunk, const double *uc, void *stream);
 
 /* Time all shapes of both smoother kernels for n = 33, 65, ..., n_max (and
  * both precisions if both != 0), install the fastest; json_path (host

@@ -301,11 +301,37 @@ hipError_t tune_class(qumond_batch *B, Class &C, int reps)
                 }
         }
         C.shapes.use_fused[l] = best[1] < 2.0 * best[0] ? 1 : 0;
-        char buf[256];
+        // residual restriction from this level: both kernels on the batch's own grids
+        double rr_us[2] = {0.0, 0.0};
+        {
+            // levels lt..J-1 are allocated and l - 1 >= lt here
+            float *fc = C.mg.lv[l - 1].f, *c0 = C.mg.lv[l - 1].u[0], *c1 = C.mg.lv[l - 1].u[1];
+            {
+                for (int v = 0; v < 2; ++v) {
+                    qm::launch_residual_restrict_variant<float>(n, h, f, u0, fc, c0, c1, v, s, C.P);
+                    std::vector<float> t;
+                    for (int r = 0; r < reps; ++r) {
+                        (void)hipEventRecord(e0, s);
+                        qm::launch_residual_restrict_variant<float>(n, h, f, u0, fc, c0, c1, v, s, C.P);
+                        (void)hipEventRecord(e1, s);
+                        if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+                        float ms = 0.f;
+                        (void)hipEventElapsedTime(&ms, e0, e1);
+                        t.push_back(ms);
+                    }
+                    std::sort(t.begin(), t.end());
+                    rr_us[v] = 1e3 * t[t.size() / 2];
+                }
+                C.shapes.rr[l] = rr_us[1] < rr_us[0] ? 1 : 0;
+            }
+        }
+        char buf[320];
         std::snprintf(buf, sizeof buf,
-                      "%s{\"n\": %d, \"single\": [%d, %d, %.2f], \"fused\": [%d, %d, %.2f], \"use_fused\": %d}",
+                      "%s{\"n\": %d, \"single\": [%d, %d, %.2f], \"fused\": [%d, %d, %.2f], \"use_fused\": %d, "
+                      "\"rr\": [%d, %.2f, %.2f]}",
                       first ? "" : ", ", n, C.shapes.single[l].variant, C.shapes.single[l].kchunk, best[0],
-                      C.shapes.fused[l].variant, C.shapes.fused[l].kchunk, best[1], C.shapes.use_fused[l]);
+                      C.shapes.fused[l].variant, C.shapes.fused[l].kchunk, best[1], C.shapes.use_fused[l],
+                      C.shapes.rr[l], rr_us[0], rr_us[1]);
         js += buf;
         first = false;
     }
@@ -475,6 +501,7 @@ qumond_status qumond_batch_create(const qumond_batch_config *cfg, const int32_t 
             C.shapes.single[l] = qm::rbgs_shape<float>(nl < 5 ? 5 : nl);
             C.shapes.fused[l] = qm::rbgs2_shape<float>(nl < 5 ? 5 : nl);
             C.shapes.use_fused[l] = qm::use_fused<float>(nl < 5 ? 5 : nl);
+            C.shapes.rr[l] = qm::rr_variant<float>(nl < 5 ? 5 : nl);
         }
         C.mg.shapes = &C.shapes;
         // the solver's buffers start defined (a solve reads only what it wrote)

@@ -73,9 +73,12 @@ constexpr int kFusedVariants = 3;   // two sweeps: 0: 32x8, 1: 64x4 z-march, 2: 
 // Every grid launcher takes nb, the number of problems stored back to back
 // (problem p of a level with n points per side at offset p n^3); nb = 1 is the
 // single-problem case.
-template <typename T> void launch_rbgs(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s, int nb = 1);
+// One sweep; with uc != NULL the correction u += P uc (uc on the next coarser
+// level) is applied first, in the same launch.
+template <typename T> void launch_rbgs(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s, int nb = 1,
+                                      const T *uc = nullptr);
 template <typename T> void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, SmootherShape sh,
-                                            hipStream_t s, int nb = 1);
+                                            hipStream_t s, int nb = 1, const T *uc = nullptr);
 template <typename T> SmootherShape &rbgs_shape(int n);   // the table entry used for n
 // Two sweeps in one launch (variants 0: 32x8, 1: 64x4 z-march, 2: 8^3 bricks);
 // with uc != NULL the correction u += P uc (uc on the next coarser level) is

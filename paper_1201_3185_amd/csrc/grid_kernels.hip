@@ -50,9 +50,13 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned w, unsigned nblk)
 
 // ------------------------------------------------------------------ smoother
 
-template <typename T, int TX, int TY>
+// With PROLONG the coarse-grid correction u += P uc is applied to every
+// interior node as its plane is loaded (the first post-smoothing sweep of a
+// V-cycle), with the same expression as prolong_k.
+template <typename T, int TX, int TY, bool PROLONG>
 __global__ void __launch_bounds__(TX *TY)
-rbgs_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2, int kchunk, int nzc)
+rbgs_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2, int kchunk, int nzc,
+            const T *__restrict__ uc, int nc)
 {
     constexpr int PX = TX + 4, PY = TY + 4, NS = 5, NT = TX * TY;
     constexpr int PL = PX * PY;                  // values of one LDS plane (tile + two-node ring)
@@ -74,16 +78,23 @@ rbgs_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict
     uin += (size_t)pb * nn * n;
     uout += (size_t)pb * nn * n;
     f += (size_t)pb * nn * n;
+    if (PROLONG) uc += (size_t)pb * nc * nc * nc;
 
-    // plane offsets of this thread's share of a plane load
-    int goff[NL];
+    // plane offsets of this thread's share of a plane load (and, for the
+    // correction, whether the node is interior in x and y)
+    int goff[NL], gij[NL];
 #pragma unroll
     for (int r = 0; r < NL; ++r) {
         const int t = tid + r * NT;
         const int a = t % PX, b = t / PX;
         const int i = i0 - 2 + a, j = j0 - 2 + b;
         goff[r] = (t < PL && i >= 0 && i < n && j >= 0 && j < n) ? i + n * j : -1;
+        gij[r] = (goff[r] >= 0 && i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2) ? (i | (j << 16)) : -1;
     }
+    auto corrected = [&](T x, int r, int k) {
+        if (PROLONG && k >= 1 && k <= n - 2 && gij[r] >= 0) x += prolong_at(nc, uc, gij[r] & 0xffff, gij[r] >> 16, k);
+        return x;
+    };
     // this thread's red node (tile + ring): row b_r, column depends on the plane's parity
     const int b_r = 1 + tid / HALF, j_r = j0 - 2 + b_r, q_r = tid % HALF;
     const bool red_thread = tid < HALF * (TY + 2) && j_r >= 1 && j_r <= n - 2;
@@ -99,14 +110,14 @@ rbgs_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict
 #pragma unroll
         for (int r = 0; r < NL; ++r) {
             const int t = tid + r * NT;
-            if (t < PL) P[t] = goff[r] >= 0 ? src[goff[r]] : T(0);
+            if (t < PL) P[t] = goff[r] >= 0 ? corrected(src[goff[r]], r, k) : T(0);
         }
     };
     T v[NL];
     auto prefetch = [&](int k) {
         const T *src = uin + (size_t)k * nn;
 #pragma unroll
-        for (int r = 0; r < NL; ++r) v[r] = goff[r] >= 0 ? src[goff[r]] : T(0);
+        for (int r = 0; r < NL; ++r) v[r] = goff[r] >= 0 ? corrected(src[goff[r]], r, k) : T(0);
     };
     auto commit = [&](int k) {
         T *P = pl[k % NS];
@@ -191,12 +202,18 @@ rbgs_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict
 }
 
 template <typename T, int TX, int TY>
-static void rbgs_launch(int n, double h, const T *f, const T *uin, T *uout, int kchunk, int nb, hipStream_t s)
+static void rbgs_launch(int n, double h, const T *f, const T *uin, T *uout, int kchunk, int nb, const T *uc,
+                        hipStream_t s)
 {
     const int m = n - 2;
     const int nzc = (m + kchunk - 1) / kchunk;
     dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, nzc * nb);
-    hipLaunchKernelGGL((rbgs_zmarch<T, TX, TY>), grid, dim3(TX * TY), 0, s, uin, uout, f, n, T(h * h), kchunk, nzc);
+    if (uc)
+        hipLaunchKernelGGL((rbgs_zmarch<T, TX, TY, true>), grid, dim3(TX * TY), 0, s, uin, uout, f, n, T(h * h), kchunk,
+                           nzc, uc, (n + 1) / 2);
+    else
+        hipLaunchKernelGGL((rbgs_zmarch<T, TX, TY, false>), grid, dim3(TX * TY), 0, s, uin, uout, f, n, T(h * h),
+                           kchunk, nzc, uc, (n + 1) / 2);
 }
 
 // ------------------------------------------------------ brick smoother
@@ -529,23 +546,24 @@ SmootherShape &rbgs_shape(int n)
 }
 
 template <typename T>
-void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, SmootherShape sh, hipStream_t s, int nb)
+void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, SmootherShape sh, hipStream_t s, int nb,
+                       const T *uc)
 {
     const int kc = sh.kchunk > 0 ? sh.kchunk : n;
     switch (sh.variant) {
-    case 0: rbgs_launch<T, 32, 8>(n, h, f, uin, uout, kc, nb, s); break;
-    case 2: rbgs_launch<T, 64, 8>(n, h, f, uin, uout, kc, nb, s); break;
-    case 3: rbgs_launch<T, 128, 4>(n, h, f, uin, uout, kc, nb, s); break;
-    case 4: rbgs_launch<T, 32, 16>(n, h, f, uin, uout, kc, nb, s); break;
-    case 5: brick_launch<T, 1>(n, h, f, uin, uout, nullptr, nb, s); break;
-    default: rbgs_launch<T, 64, 4>(n, h, f, uin, uout, kc, nb, s); break;
+    case 0: rbgs_launch<T, 32, 8>(n, h, f, uin, uout, kc, nb, uc, s); break;
+    case 2: rbgs_launch<T, 64, 8>(n, h, f, uin, uout, kc, nb, uc, s); break;
+    case 3: rbgs_launch<T, 128, 4>(n, h, f, uin, uout, kc, nb, uc, s); break;
+    case 4: rbgs_launch<T, 32, 16>(n, h, f, uin, uout, kc, nb, uc, s); break;
+    case 5: brick_launch<T, 1>(n, h, f, uin, uout, uc, nb, s); break;
+    default: rbgs_launch<T, 64, 4>(n, h, f, uin, uout, kc, nb, uc, s); break;
     }
 }
 
 template <typename T>
-void launch_rbgs(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s, int nb)
+void launch_rbgs(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s, int nb, const T *uc)
 {
-    launch_rbgs_shape<T>(n, h, f, uin, uout, rbgs_shape<T>(n), s, nb);
+    launch_rbgs_shape<T>(n, h, f, uin, uout, rbgs_shape<T>(n), s, nb, uc);
 }
 
 // ------------------------------------------------- residual and restriction
@@ -694,8 +712,9 @@ residual_restrict_tile_k(int nf, T ih2, const T *__restrict__ f, const T *__rest
 }
 
 // Which residual-restriction kernel a fine level of n points uses (0: per-node
-// gather, 1: LDS tile), per precision; set by the autotuner, tile by default.
-static int g_rr_variant[2][11] = {{1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1}, {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1}};
+// gather, 1: LDS tile), per precision; set by the autotuner, gather by default
+// (the faster of the two in the measurements so far).
+static int g_rr_variant[2][11] = {{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
 
 template <typename T>
 int &rr_variant(int nf)
@@ -1113,15 +1132,16 @@ __global__ void __launch_bounds__(256)
 resid_norms_partial_k(int n, double ih2, const T *__restrict__ f, const T *__restrict__ u, double *__restrict__ partial)
 {
     __shared__ double sh[768];
-    const int m = n - 2;
-    const size_t cnt = (size_t)m * m * m;
+    const unsigned m = (unsigned)(n - 2);
+    const unsigned cnt = m * m * m;   // < 2^31 for n <= 1025
     const size_t sy = (size_t)n, sz = (size_t)n * n;
     f += blockIdx.y * sz * n;
     u += blockIdx.y * sz * n;
     partial += blockIdx.y * 3 * (size_t)gridDim.x;
     double sr = 0.0, sf = 0.0, sb = 0.0;
-    for (size_t t = blockIdx.x * (size_t)256 + threadIdx.x; t < cnt; t += (size_t)gridDim.x * 256) {
-        const int i = 1 + (int)(t % m), j = 1 + (int)((t / m) % m), k = 1 + (int)(t / ((size_t)m * m));
+    for (unsigned t = blockIdx.x * 256u + threadIdx.x; t < cnt; t += gridDim.x * 256u) {
+        const unsigned tq = t / m;
+        const int i = 1 + (int)(t - tq * m), j = 1 + (int)(tq % m), k = 1 + (int)(tq / m);
         const size_t p = id3(n, i, j, k);
         const double um = u[p - 1], up = u[p + 1], vm = u[p - sy], vp = u[p + sy], wm = u[p - sz], wp = u[p + sz];
         const double lap = (um + up + vm + vp + wm + wp - 6.0 * (double)u[p]) * ih2;
@@ -1330,8 +1350,9 @@ void launch_guess_interior(int n, const void *g, int kind, double *u, hipStream_
 
 // -------------------------------------------------------- instantiations
 #define QM_INST(T)                                                                                              \
-    template void launch_rbgs<T>(int, double, const T *, const T *, T *, hipStream_t, int);                    \
-    template void launch_rbgs_shape<T>(int, double, const T *, const T *, T *, SmootherShape, hipStream_t, int);\
+    template void launch_rbgs<T>(int, double, const T *, const T *, T *, hipStream_t, int, const T *);         \
+    template void launch_rbgs_shape<T>(int, double, const T *, const T *, T *, SmootherShape, hipStream_t, int,  \
+                                       const T *);                                                              \
     template SmootherShape &rbgs_shape<T>(int);                                                                 \
     template SmootherShape &rbgs2_shape<T>(int);                                                                \
     template int &use_fused<T>(int);                                                                            \

@@ -73,6 +73,7 @@ struct LevelShapes {
     SmootherShape single[11];
     SmootherShape fused[11];
     int use_fused[11];
+    int rr[11];   // residual-restriction kernel of fine level l
 };
 
 template <typename T>
@@ -169,7 +170,7 @@ struct Multigrid {
     {
         Level<T> &v = lv[l];
         const double pts = (double)v.n * v.n * v.n;
-        if (uc && ns < 2) {
+        if (uc && ns == 0) {
             launch_prolong_add<T>(lv[l - 1].n, uc, v.u[v.cur], s, nb);
             uc = nullptr;
         }
@@ -182,9 +183,8 @@ struct Multigrid {
                 launch_rbgs2_shape<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], uc, sh, s, nb);
                 ns -= 2;
             } else {
-                if (uc) launch_prolong_add<T>(lv[l - 1].n, uc, v.u[v.cur], s, nb);
                 const SmootherShape sh = shapes ? shapes->single[l] : rbgs_shape<T>(v.n);
-                launch_rbgs_shape<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], sh, s, nb);
+                launch_rbgs_shape<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], sh, s, nb, uc);
                 ns -= 1;
             }
             uc = nullptr;
@@ -199,7 +199,11 @@ struct Multigrid {
         Level<T> &v = lv[l];
         smooth(l, npre);
         Level<T> &c = lv[l - 1];
-        launch_residual_restrict<T>(v.n, v.h, v.f, v.u[v.cur], c.f, c.u[c.cur], c.u[1 - c.cur], s, nb);
+        if (shapes)
+            launch_residual_restrict_variant<T>(v.n, v.h, v.f, v.u[v.cur], c.f, c.u[c.cur], c.u[1 - c.cur],
+                                                shapes->rr[l], s, nb);
+        else
+            launch_residual_restrict<T>(v.n, v.h, v.f, v.u[v.cur], c.f, c.u[c.cur], c.u[1 - c.cur], s, nb);
         if (l - 1 == lt) launch_coarse_tail<T>(lt, L, c.f, c.u[c.cur], npre, npost, 1, 0, 1, s, nb);
         else vcycle(l - 1);
         smooth(l, npost, c.u[c.cur]);

@@ -175,12 +175,12 @@ conv3d_fwd_lds_k(Tensor x, int cin, const __bf16 *__restrict__ wt, int kpad, con
         }
         __syncthreads();
         const int steps = (27 * cc + 31) / 32;
-        for (int st = 0; st < steps; ++st) {
+        // fragments of K-step st (activations from the tile, weights from global)
+        auto frags = [&](int st, bf16x8 *a, bf16x8 *w) {
             const int kl = 32 * st + 8 * g;        // local K index of this lane's fragment
             const int tap = kl / cc, cl = kl - tap * cc;
             const bool live = tap < 27;
             const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;   // offsets + 1
-            bf16x8 a[RB], w[NB];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
                 const int v = (r16 + dx) + kInX * ((rb + dy) + kInY * (wave + dz));
@@ -190,11 +190,23 @@ conv3d_fwd_lds_k(Tensor x, int cin, const __bf16 *__restrict__ wt, int kpad, con
 #pragma unroll
             for (int b = 0; b < NB; ++b)
                 w[b] = live ? *reinterpret_cast<const bf16x8 *>(wt + (size_t)(b * 16 + r16) * kpad + kw) : bf16x8{};
+        };
+        bf16x8 a[RB], w[NB];
+        frags(0, a, w);
+        for (int st = 0; st < steps; ++st) {
+            bf16x8 an[RB], wn[NB];
+            if (st + 1 < steps) frags(st + 1, an, wn);   // in flight during this step's MFMAs
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
                     acc[rb][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], w[b], acc[rb][b], 0, 0, 0);
+            if (st + 1 < steps) {
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) a[rb] = an[rb];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) w[b] = wn[b];
+            }
         }
     }
 #pragma unroll
@@ -544,14 +556,18 @@ void launch_upsample_adj(Tensor gf, Tensor gc, int c, hipStream_t s)
 
 // ------------------------------------------------------------- head, loss
 
-// yhat[v] = b + sum_c w[c] x[v, c]
+// yhat[v] = b + sum_c w[c] x[v, c] (c a multiple of 8; 16-byte loads, same order)
 __global__ void head_fwd_k(Tensor x, int c, const float *__restrict__ w, const float *__restrict__ b, float *__restrict__ yh)
 {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     const int N = x.n * x.n * x.n;
     if (v >= N) return;
     float s = b[0];
-    for (int ch = 0; ch < c; ++ch) s += w[ch] * (float)x.p[(size_t)v * x.cs + ch];
+    for (int c8 = 0; c8 < c; c8 += 8) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(x.p + (size_t)v * x.cs + c8);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s += w[c8 + e] * (float)a[e];
+    }
     yh[v] = s;
 }
 
@@ -561,13 +577,19 @@ void launch_head_fwd(Tensor x, int c, const float *w, const float *b, float *yh,
     hipLaunchKernelGGL(head_fwd_k, dim3((N + 255) / 256), dim3(256), 0, s, x, c, w, b, yh);
 }
 
-// dx[v, c] = dy[v] w[c]
+// dx[v, c] = dy[v] w[c] (c a multiple of 8; 16-byte stores)
 __global__ void head_bwd_x_k(const float *__restrict__ dyh, int c, const float *__restrict__ w, Tensor dx)
 {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     const int N = dx.n * dx.n * dx.n;
     if (v >= N) return;
-    for (int ch = 0; ch < c; ++ch) dx.p[(size_t)v * dx.cs + ch] = (__bf16)(dyh[v] * w[ch]);
+    const float d = dyh[v];
+    for (int c8 = 0; c8 < c; c8 += 8) {
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = (__bf16)(d * w[c8 + e]);
+        *reinterpret_cast<bf16x8 *>(dx.p + (size_t)v * dx.cs + c8) = o;
+    }
 }
 
 // partial[split, c] = sum dy[v] x[v, c] (c < C), partial[split, C] = sum dy[v];

@@ -122,7 +122,7 @@ _SIGNATURES = {
     "qumond_tune_get": (_I32, [_I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "qumond_tune_set_fused": (_I32, [_I32, _I32, _I32, _I32]),
     "qumond_tune_get_fused": (_I32, [_I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
-    "qumond_k_rbgs_sweep_shape": (_I32, [_I32, _D, _P, _P, _P, _I32, _I32, _P]),
+    "qumond_k_rbgs_sweep_shape": (_I32, [_I32, _D, _P, _P, _P, _I32, _I32, _P, _P]),
     "qumond_autotune": (_I32, [_I32, _I32, _I32, ctypes.c_char_p, ctypes.POINTER(_D), _P]),
     "qumond_tune_load": (_I32, [ctypes.c_char_p]),
     "qumond_tune_set_rr": (_I32, [_I32, _I32, _I32]),
@@ -433,9 +433,9 @@ def tune_get_fused(n, fp32=False):
     return int(v.value), int(k.value)
 
 
-def k_rbgs_sweep_shape(f, u_in, u_out, h, variant, kchunk):
+def k_rbgs_sweep_shape(f, u_in, u_out, h, variant, kchunk, uc=None):
     check(lib().qumond_k_rbgs_sweep_shape(u_in.shape[0], float(h), _ptr(f), _ptr(u_in), _ptr(u_out), int(variant),
-                                          int(kchunk), _s()), "qumond_k_rbgs_sweep_shape")
+                                          int(kchunk), _ptr(uc), _s()), "qumond_k_rbgs_sweep_shape")
 
 
 def autotune(n_max=513, both=True, reps=5, json_path=None):

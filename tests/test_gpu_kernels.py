@@ -266,6 +266,29 @@ def test_every_smoother_shape_is_bitwise_identical(n):
 
 
 @pytest.mark.parametrize("n", [5, 17, 33, 65, 129])
+def test_single_sweep_with_correction_is_bitwise_identical(n):
+    """A single sweep that applies the coarse correction on load equals
+    prolong-add followed by a sweep, bit for bit, in every shape."""
+    L = 4.5
+    h = L / (n - 1)
+    f, u = rand_state(n, 1900 + n)
+    nc = (n + 1) // 2
+    uc = np.random.default_rng(n + 3).standard_normal((nc, nc, nc))
+    uc[0, :, :] = uc[-1, :, :] = uc[:, 0, :] = uc[:, -1, :] = uc[:, :, 0] = uc[:, :, -1] = 0.0
+    fd, ucd = dev(f), dev(uc)
+    pa = dev(u)
+    Q.k_prolong_add(ucd, pa)
+    ref = dev(u)
+    Q.k_rbgs_sweep(fd, pa, ref, h)
+    ref = host(ref)
+    for v in Q.SMOOTHER_VARIANTS:
+        for kc in ((0,) if v == 5 else (4, 16, 0)):
+            out = dev(u)
+            Q.k_rbgs_sweep_shape(fd, dev(u), out, h, v, kc, uc=ucd)
+            assert np.array_equal(host(out), ref), (v, kc)
+
+
+@pytest.mark.parametrize("n", [5, 17, 33, 65, 129])
 def test_every_fused_shape_is_bitwise_identical(n):
     """The fused two-sweep smoother in every shape (z-march tiles and 8^3
     bricks, ragged at the far faces) equals two single sweeps bit for bit, and
