@@ -13,6 +13,11 @@
 // (24 bytes per point in FP64).  Reading u_in and writing u_out avoids any
 // race between tiles; the driver alternates two buffers.
 //
+// Rounding.  The stencil kernels evaluate every node update, residual and
+// transfer with floating-point contraction off, so that the result does not
+// depend on which kernel (tile shape, fused or single sweep, gather or tile
+// restriction) computes it.
+//
 // Batches.  Every grid kernel can sweep the same level of nb independent
 // problems stored back to back (problem p of a level with n points per side
 // starts at p n^3): the problem index is the slowest part of the block index,
@@ -26,6 +31,7 @@ namespace qm {
 template <typename T>
 __device__ __forceinline__ T prolong_at(int nc, const T *__restrict__ uc, int i, int j, int k)
 {
+#pragma clang fp contract(off)
     const int ia = i >> 1, ib = (i + 1) >> 1, ja = j >> 1, jb = (j + 1) >> 1, ka = k >> 1, kb = (k + 1) >> 1;
     const T wia = (i & 1) ? T(0.5) : T(1), wib = (i & 1) ? T(0.5) : T(0);
     const T wja = (j & 1) ? T(0.5) : T(1), wjb = (j & 1) ? T(0.5) : T(0);
@@ -58,6 +64,7 @@ __global__ void __launch_bounds__(TX *TY)
 rbgs_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2, int kchunk, int nzc,
             const T *__restrict__ uc, int nc)
 {
+#pragma clang fp contract(off)
     constexpr int PX = TX + 4, PY = TY + 4, NS = 5, NT = TX * TY;
     constexpr int PL = PX * PY;                  // values of one LDS plane (tile + two-node ring)
     constexpr int NL = (PL + NT - 1) / NT;       // plane values loaded per thread
@@ -232,6 +239,7 @@ __global__ void __launch_bounds__(256)
 rbgs_brick(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2,
            const T *__restrict__ uc, int nc, int nbx)
 {
+#pragma clang fp contract(off)
     constexpr int R = 2 * S, E = B + 2 * R, FE = E - 2, NT = 256;
     __shared__ T U[E * E * E];
     __shared__ T F[FE * FE * FE];
@@ -325,6 +333,7 @@ __global__ void __launch_bounds__(TX *TY)
 rbgs2_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2, int kchunk,
              const T *__restrict__ uc, int nc, int nzc)
 {
+#pragma clang fp contract(off)
     constexpr int R = 4;                         // ring of the LDS planes
     constexpr int PX = TX + 2 * R, PY = TY + 2 * R, NT = TX * TY;
     constexpr int PL = PX * PY;
@@ -575,6 +584,7 @@ template <typename T>
 __global__ void residual_restrict_k(int nf, T ih2, const T *__restrict__ f, const T *__restrict__ u, T *__restrict__ fc,
                                     T *__restrict__ uc0, T *__restrict__ uc1, int zb)
 {
+#pragma clang fp contract(off)
     const int nc = (nf + 1) / 2;
     const int pb = blockIdx.z / zb;
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
@@ -611,6 +621,7 @@ __global__ void residual_restrict_k(int nf, T ih2, const T *__restrict__ f, cons
 template <typename T>
 __global__ void restrict_k(int nf, const T *__restrict__ src, T *__restrict__ dst, int zb)
 {
+#pragma clang fp contract(off)
     const int nc = (nf + 1) / 2;
     const int pb = blockIdx.z / zb;
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
@@ -650,6 +661,7 @@ __global__ void __launch_bounds__(256)
 residual_restrict_tile_k(int nf, T ih2, const T *__restrict__ f, const T *__restrict__ u, T *__restrict__ fc,
                          T *__restrict__ uc0, T *__restrict__ uc1, int tx, int ty, int tz)
 {
+#pragma clang fp contract(off)
     constexpr int CX = 8, CY = 8, CZ = 4;
     constexpr int RX = 2 * CX + 1, RY = 2 * CY + 1, RZ = 2 * CZ + 1;   // fine residual region
     constexpr int UX = RX + 2, UY = RY + 2, UZ = RZ + 2;               // u region (one-node ring)
@@ -890,49 +902,63 @@ constexpr int kTailTopN = (1 << kTailTop) + 1;
 
 // Lanes of the 1024-thread workgroup cover a 16 x 16 x 4 brick of nodes (i, j
 // from the lane, k strided by 4); colour passes use 8 x 16 x 8 with two nodes of
-// one colour per row pair.
+// one colour per row pair.  Every level is a compile-time template argument, so
+// all node indexing folds to constants.
 template <typename T>
 struct TailLDS {
     T *U, *F, *R;
     T L;
     int npre, npost;
-    __device__ static int nl(int l) { return (1 << l) + 1; }
-    __device__ T *u(int l) const { return U + tail_off(l); }
-    __device__ T *fr(int l) const { return F + tail_off(l); }
+    T *h2, *ih2;   // in LDS: h^2 and 1/h^2 per level, h = L / (n - 1)
 
-    __device__ void gs(int l, int colour) const
+    __device__ void init_h() const   // by one thread, before the first barrier
     {
-        const int n = nl(l), m = n - 2;
-        const T h = L / T(n - 1), h2 = h * h, sixth = T(1) / T(6);
-        T *uu = u(l);
-        const T *ff = fr(l);
+        for (int l = 1; l <= kTailTop; ++l) {
+            const T h = L / T((1 << l));
+            h2[l] = h * h;
+            ih2[l] = T(1) / (h * h);
+        }
+    }
+    template <int LV> __device__ T *u() const { return U + tail_off(LV); }
+    template <int LV> __device__ T *fr() const { return F + tail_off(LV); }
+
+    template <int LV>
+    __device__ void gs(int colour) const
+    {
+#pragma clang fp contract(off)
+        constexpr int n = (1 << LV) + 1, m = n - 2;
+        const T hh = h2[LV], sixth = T(1) / T(6);
+        T *uu = u<LV>();
+        const T *ff = fr<LV>();
         const int tx = threadIdx.x & 7, ty = (threadIdx.x >> 3) & 15, tz = threadIdx.x >> 7;
         const int j = 1 + ty;
         if (j <= m) {
-#pragma unroll 2
+#pragma unroll
             for (int k = 1 + tz; k <= m; k += 8) {
                 const int i = 1 + 2 * tx + ((colour + 1 + j + k) & 1);
                 if (i > m) continue;
                 const int p = i + n * (j + n * k);
                 const T s = uu[p - 1] + uu[p + 1] + uu[p - n] + uu[p + n] + uu[p - n * n] + uu[p + n * n];
-                uu[p] = (s - h2 * ff[p]) * sixth;
+                uu[p] = (s - hh * ff[p]) * sixth;
             }
         }
         __syncthreads();
     }
-    __device__ void sweeps(int l, int ns) const
+    template <int LV>
+    __device__ void sweeps(int ns) const
     {
         for (int s = 0; s < ns; ++s) {
-            gs(l, 0);
-            gs(l, 1);
+            gs<LV>(0);
+            gs<LV>(1);
         }
     }
     // exact solve of the single interior node of the 3^3 level, in FP64
     __device__ void exact() const
     {
+#pragma clang fp contract(off)
         if (threadIdx.x == 0) {
-            T *uu = u(1);
-            const T *ff = fr(1);
+            T *uu = u<1>();
+            const T *ff = fr<1>();
             const double h = double(L) / 2.0;
             const int p = 13;
             const double s = double(uu[p - 1]) + double(uu[p + 1]) + double(uu[p - 3]) + double(uu[p + 3]) +
@@ -941,26 +967,27 @@ struct TailLDS {
         }
         __syncthreads();
     }
-    // fc = FW(f - A u) on level l-1 and uc = 0: the residual of level l is staged in R
-    __device__ void resid_restrict(int l) const
+    // fc = FW(f - A u) on level LV-1 and uc = 0: the residual of level LV is staged in R
+    template <int LV>
+    __device__ void resid_restrict() const
     {
-        const int n = nl(l), m = n - 2, nc = nl(l - 1);
-        const T h = L / T(n - 1), ih2 = T(1) / (h * h);
-        const T *uu = u(l);
-        const T *ff = fr(l);
+#pragma clang fp contract(off)
+        constexpr int n = (1 << LV) + 1, m = n - 2, nc = (1 << (LV - 1)) + 1;
+        const T ih = ih2[LV];
+        const T *uu = u<LV>();
+        const T *ff = fr<LV>();
         const int li = threadIdx.x & 15, lj = (threadIdx.x >> 4) & 15, lk = threadIdx.x >> 8;
         if (li < m && lj < m) {
             const int i = 1 + li, j = 1 + lj;
-#pragma unroll 4
             for (int k = 1 + lk; k <= m; k += 4) {
                 const int p = i + n * (j + n * k);
                 R[p] = ff[p] - (uu[p - 1] + uu[p + 1] + uu[p - n] + uu[p + n] + uu[p - n * n] + uu[p + n * n] -
-                                T(6) * uu[p]) * ih2;
+                                T(6) * uu[p]) * ih;
             }
         }
         __syncthreads();
-        T *fc = fr(l - 1);
-        T *uc = u(l - 1);
+        T *fc = fr<LV - 1>();
+        T *uc = u<LV - 1>();
         const T w[3] = {T(0.25), T(0.5), T(0.25)};
         if (li < nc && lj < nc) {
             for (int K = lk; K < nc; K += 4) {
@@ -980,11 +1007,13 @@ struct TailLDS {
         }
         __syncthreads();
     }
-    __device__ void restrict_f(int l) const   // f_{l-1} = FW(f_l)
+    template <int LV>
+    __device__ void restrict_f() const   // f_{LV-1} = FW(f_LV)
     {
-        const int n = nl(l), nc = nl(l - 1);
-        const T *ff = fr(l);
-        T *fc = fr(l - 1);
+#pragma clang fp contract(off)
+        constexpr int n = (1 << LV) + 1, nc = (1 << (LV - 1)) + 1;
+        const T *ff = fr<LV>();
+        T *fc = fr<LV - 1>();
         const T w[3] = {T(0.25), T(0.5), T(0.25)};
         const int li = threadIdx.x & 15, lj = (threadIdx.x >> 4) & 15, lk = threadIdx.x >> 8;
         if (li < nc && lj < nc) {
@@ -1004,15 +1033,15 @@ struct TailLDS {
         }
         __syncthreads();
     }
-    __device__ void prolong(int lc, bool add) const   // level lc -> lc+1 interior
+    template <int LC>
+    __device__ void prolong(bool add) const   // level LC -> LC+1 interior
     {
-        const int nc = nl(lc), n = nl(lc + 1), m = n - 2;
-        const T *uc = u(lc);
-        T *uf = u(lc + 1);
+        constexpr int nc = (1 << LC) + 1, n = (1 << (LC + 1)) + 1, m = n - 2;
+        const T *uc = u<LC>();
+        T *uf = u<LC + 1>();
         const int li = threadIdx.x & 15, lj = (threadIdx.x >> 4) & 15, lk = threadIdx.x >> 8;
         if (li < m && lj < m) {
             const int i = 1 + li, j = 1 + lj;
-#pragma unroll 4
             for (int k = 1 + lk; k <= m; k += 4) {
                 const T v = prolong_at(nc, uc, i, j, k);
                 const int p = i + n * (j + n * k);
@@ -1021,11 +1050,12 @@ struct TailLDS {
         }
         __syncthreads();
     }
-    __device__ void inject(int l, int top) const   // boundary of level l from level top, interior 0
+    template <int LV, int TOP>
+    __device__ void inject() const   // boundary of level LV from level TOP, interior 0
     {
-        const int n = nl(l), nt = nl(top), st = (nt - 1) / (n - 1);
-        T *uu = u(l);
-        const T *ut = u(top);
+        constexpr int n = (1 << LV) + 1, nt = (1 << TOP) + 1, st = (nt - 1) / (n - 1);
+        T *uu = u<LV>();
+        const T *ut = u<TOP>();
         const int li = threadIdx.x & 15, lj = (threadIdx.x >> 4) & 15, lk = threadIdx.x >> 8;
         if (li < n && lj < n) {
             for (int k = lk; k < n; k += 4) {
@@ -1035,16 +1065,66 @@ struct TailLDS {
         }
         __syncthreads();
     }
-    __device__ void vcycle(int top) const
+    template <int LV>
+    __device__ void down() const
     {
-        for (int l = top; l >= 2; --l) {
-            sweeps(l, npre);
-            resid_restrict(l);
+        if constexpr (LV >= 2) {
+            sweeps<LV>(npre);
+            resid_restrict<LV>();
+            down<LV - 1>();
         }
+    }
+    template <int LV, int TOP>
+    __device__ void up() const
+    {
+        if constexpr (LV <= TOP) {
+            prolong<LV - 1>(true);
+            sweeps<LV>(npost);
+            up<LV + 1, TOP>();
+        }
+    }
+    template <int TOP>
+    __device__ void vcycle() const
+    {
+        down<TOP>();
         exact();
-        for (int l = 2; l <= top; ++l) {
-            prolong(l - 1, true);
-            sweeps(l, npost);
+        up<2, TOP>();
+    }
+    template <int LV, int TOP>
+    __device__ void restrict_all() const   // f of TOP-1 .. 1 from TOP
+    {
+        if constexpr (LV >= 2) {
+            restrict_f<LV>();
+            restrict_all<LV - 1, TOP>();
+        }
+    }
+    template <int LV, int TOP>
+    __device__ void inject_all() const
+    {
+        if constexpr (LV < TOP) {
+            inject<LV, TOP>();
+            inject_all<LV + 1, TOP>();
+        }
+    }
+    template <int LV, int TOP>
+    __device__ void fmg_up(int ncycle) const
+    {
+        if constexpr (LV <= TOP) {
+            prolong<LV - 1>(false);
+            for (int c = 0; c < ncycle; ++c) vcycle<LV>();
+            fmg_up<LV + 1, TOP>(ncycle);
+        }
+    }
+    template <int TOP>
+    __device__ void run(int mode, int ncycle, int nrep) const
+    {
+        if (mode == 1) {
+            restrict_all<TOP, TOP>();
+            inject_all<1, TOP>();
+            exact();
+            fmg_up<2, TOP>(ncycle);
+        } else {
+            for (int r = 0; r < nrep; ++r) vcycle<TOP>();
         }
     }
 };
@@ -1057,41 +1137,25 @@ coarse_tail_k(int top, T L, const T *__restrict__ fg, T *__restrict__ ug, int np
     __shared__ T U[kTailSize];
     __shared__ T F[kTailSize];
     __shared__ T Rs[kTailTopN * kTailTopN * kTailTopN];
-    TailLDS<T> t{U, F, Rs, L, npre, npost};
-    const int n = t.nl(top), cnt = n * n * n;
+    __shared__ T hs[2][kTailTop + 1];
+    TailLDS<T> t{U, F, Rs, L, npre, npost, hs[0], hs[1]};
+    if (threadIdx.x == 0) t.init_h();
+    const int n = (1 << top) + 1, cnt = n * n * n;
     fg += (size_t)blockIdx.x * cnt;
     ug += (size_t)blockIdx.x * cnt;
-    constexpr int PER = (kTailTopN * kTailTopN * kTailTopN + kTailThreads - 1) / kTailThreads;
-    T ru[PER], rf[PER];
-#pragma unroll
-    for (int r = 0; r < PER; ++r) {
-        const int p = threadIdx.x + r * kTailThreads;
-        if (p < cnt) {
-            ru[r] = ug[p];
-            rf[r] = fg[p];
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < PER; ++r) {
-        const int p = threadIdx.x + r * kTailThreads;
-        if (p < cnt) {
-            t.u(top)[p] = ru[r];
-            t.fr(top)[p] = rf[r];
-        }
+    T *utop = U + tail_off(top), *ftop = F + tail_off(top);
+    for (int p = threadIdx.x; p < cnt; p += kTailThreads) {
+        utop[p] = ug[p];
+        ftop[p] = fg[p];
     }
     __syncthreads();
-    if (mode == 1) {
-        for (int l = top - 1; l >= 1; --l) t.restrict_f(l + 1);
-        for (int l = 1; l < top; ++l) t.inject(l, top);
-        t.exact();
-        for (int l = 2; l <= top; ++l) {
-            t.prolong(l - 1, false);
-            for (int c = 0; c < ncycle; ++c) t.vcycle(l);
-        }
-    } else {
-        for (int r = 0; r < nrep; ++r) t.vcycle(top);
+    switch (top) {
+    case 1: t.template run<1>(mode, ncycle, nrep); break;
+    case 2: t.template run<2>(mode, ncycle, nrep); break;
+    case 3: t.template run<3>(mode, ncycle, nrep); break;
+    default: t.template run<4>(mode, ncycle, nrep); break;
     }
-    for (int p = threadIdx.x; p < cnt; p += blockDim.x) ug[p] = t.u(top)[p];
+    for (int p = threadIdx.x; p < cnt; p += blockDim.x) ug[p] = utop[p];
 }
 
 template <typename T>

@@ -135,7 +135,7 @@ def test_replay_picks_up_new_particles(mixed_batch):
 
 
 def test_autotuned_shapes_keep_results_bitwise():
-    ns = [65, 65, 33]
+    ns = [129, 65, 65, 33]
     parts = small_disks(ns, seed0=700)
     b0 = make_batch(ns, parts, refine_iters=3, max_extra=0)
     b0.run(use_graph=False, allow_not_converged=True)
@@ -223,24 +223,25 @@ def test_fit_workload_64_disks():
         d = dp.dist
         x, y, zz, m = synth.two_component_disk_torch(dp.n_particles, dp.seed, Md=dp.ml * 5e10 * d * d, Rd=3.0 * d,
                                                      zd=dp.z_star, Mg=1e10 * d * d, Rg=6.0 * d, zg=dp.z_gas)
-        b.set_particles(i, x, y, zz, m, float(m.sum().item()))
-        keep.append((x, y, zz, m))
+        M = float(m.sum().item())
+        b.set_particles(i, x, y, zz, m, M)
+        keep.append((x, y, zz, m, M))
     info = b.run(use_graph=True)
     assert all(i["converged"] == 1 for i in info)
     assert all(i["relres_mond"] <= 1e-6 and i["relres_newton"] <= 1e-6 for i in info)
     # sampled problems: one of each size, against the single-problem context and the oracle's residual
     for n in (129, 257):
         p = ns.index(n)
-        x, y, zz, m = keep[p]
+        x, y, zz, m, M = keep[p]
         parts = synth.Particles(x.cpu().numpy(), y.cpu().numpy(), zz.cpu().numpy(), m.cpu().numpy())
-        ref = solo(n, parts, 4)
+        ref = solo(n, parts, 4, mass=M)   # the same total mass the batch was given
         got = batch_fields(b, p)
         if info[p]["steps_newton"] == 4 and info[p]["steps_mond"] == 4:
             for k in ("f", "phin", "S", "phi"):
                 assert np.array_equal(got[k], ref[k])
         h = L_BOX / (n - 1)
-        q, inside = O.cic_deposit(n, L_BOX, parts.x, parts.y, parts.z, parts.m, O.fixed_shift(float(m.sum().item())))
-        f_o = O.rhs_from_q(n, L_BOX, q, O.fixed_shift(float(m.sum().item())))
+        q, inside = O.cic_deposit(n, L_BOX, parts.x, parts.y, parts.z, parts.m, O.fixed_shift(M))
+        f_o = O.rhs_from_q(n, L_BOX, q, O.fixed_shift(M))
         assert rel(got["f"], f_o) <= 1e-15 and inside == info[p]["n_inside"]
         r = O.residual(f_o, got["phin"], h)
         assert np.sqrt((r ** 2).sum() / (f_o[1:-1, 1:-1, 1:-1] ** 2).sum()) <= 1e-6
