@@ -164,6 +164,50 @@ def batched_fit(Q, synth, torch, np, reps=3, refine_iters=3):
     return out
 
 
+def kuzmin_paper_mode(Q, synth, torch, np, dev):
+    """The paper's accuracy experiment (Sec. 3.1): stratified Kuzmin disks,
+    nested 257^3 boxes halving from 2^10 times the finest box, zero outer
+    potential, box choice R < L/5; largest relative error of the midplane
+    circular speed against the closed-form curves, and the wall time of
+    deposit + both solves."""
+    G, a0 = 4.300917270e-6, 3600.0
+
+    def vc2_newton(R, a, M):   # Sec. 3.1: |g_N,R| = G M R (R^2 + a^2)^-3/2 in the midplane
+        return G * M * R * R * (R * R + a * a) ** -1.5
+
+    def vc2_qumond(R, a, M):   # Sec. 3.1: nu(|g_N,r| / a0) |g_N,R| with |g_N,r| = G M / (R^2 + a^2)
+        y = G * M / (R * R + a * a) / a0
+        return (0.5 + 0.5 * np.sqrt(1.0 + 4.0 / y)) * vc2_newton(R, a, M)
+
+    out = {}
+    for name, a, M, finest, nbox in (("a1.5kpc_M1e10_boxes4096to4kpc", 1.5, 1e10, 4.0, 11),
+                                     ("a150pc_M1e9_boxes4096to0.5kpc", 0.15, 1e9, 0.5, 14)):
+        p = synth.kuzmin_disk_stratified(20_000_000, a, M)
+        sides = [finest * 2 ** k for k in range(nbox - 1, -1, -1)]
+        ctx = Q.Context(Q.Config(n=257, box_side=sides, outer_bc=Q.QUMOND_BC_ZERO, tol_rel=1e-10))
+        x, y, z, m = dev(p.x), dev(p.y), dev(p.z), dev(p.m)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.deposit(x, y, z, m, M, count_outside=False)
+        ctx.solve()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        R = np.geomspace(0.03, 30.0, 48)
+        rec = {"boxes": nbox, "n": 257, "particles": 20_000_000, "ms": ms}
+        for which, fn, tag in ((0, vc2_newton, "newton"), (1, vc2_qumond, "qumond")):
+            vc2 = ctx.rotation_curve(dev(R), 64, which).cpu().numpy()
+            err = np.abs(np.sqrt(vc2 / fn(R, a, M)) - 1.0)
+            for r0 in (0.05, 0.3, 1.0):
+                rec[f"{tag}_max_err_R_ge_{r0}kpc"] = float(err[R >= r0].max())
+        out[name] = rec
+        ctx.close()
+        del ctx, x, y, z, m
+        torch.cuda.empty_cache()
+    log("Kuzmin paper mode: " + ", ".join(f"{k}: qumond {v['qumond_max_err_R_ge_0.3kpc']:.1e} (R>=0.3), "
+                                          f"{v['qumond_max_err_R_ge_1.0kpc']:.1e} (R>=1)" for k, v in out.items()))
+    return out
+
+
 def learned_leg(Q, torch, np, count=8):
     """Wall time and V-cycles of the QUMOND solve to 1e-6 on held-out disks
     (seed family 6, 129^3, 120 kpc) for the plain FP64 FMG, FP64 V-cycles from
@@ -197,6 +241,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the 513^3 FP64-vs-mixed comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-disk batched fit")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess comparison")
+    ap.add_argument("--no-kuzmin", action="store_true", help="skip the paper-mode Kuzmin accuracy run")
     ap.add_argument("--save-tune", default=None, help="write the autotuned smoother table to this JSON file")
     ap.add_argument("--tune-table", default=None, help="load the smoother table from this JSON file instead of "
                                                        "autotuning (to replay the same launches under a profiler)")
@@ -275,6 +320,10 @@ def main():
     if not args.no_batch:
         batch = batched_fit(Q, synth, torch, np)
 
+    kuz = None
+    if not args.no_kuzmin:
+        kuz = kuzmin_paper_mode(Q, synth, torch, np, dev)
+
     learned_out = None
     if not args.no_learned:
         learned_out = learned_leg(Q, torch, np)
@@ -306,6 +355,7 @@ def main():
         "mixed_vs_fp64_513": mixed,
         "batched_fit_64": batch,
         "learned_guess_129": learned_out,
+        "kuzmin_paper_mode_257": kuz,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

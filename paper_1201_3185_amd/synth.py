@@ -65,6 +65,18 @@ def kuzmin_disk(n: int, a: float, M: float, seed: int) -> Particles:
     return Particles(x, y, z, m)
 
 
+def kuzmin_disk_stratified(n: int, a: float, M: float) -> Particles:
+    """The Kuzmin disk with its inverse-CDF radii taken at the stratified mass
+    fractions f = (i + 1/2) / n and azimuths from the golden-ratio sequence:
+    the same distribution as kuzmin_disk with far less sampling noise, for
+    measuring the solver's own accuracy."""
+    i = np.arange(n, dtype=np.float64)
+    f = (i + 0.5) / n
+    R = a * np.sqrt((1.0 - f) ** -2 - 1.0)
+    phi = 2.0 * np.pi * np.mod(i * 0.6180339887498949, 1.0)
+    return Particles(R * np.cos(phi), R * np.sin(phi), np.zeros(n), np.full(n, M / n))
+
+
 def _exp_radii(rng: np.random.Generator, n: int, Rd: float) -> np.ndarray:
     u = rng.random(n)
     # 1 - (1 + x) e^-x = u  <=>  x = -1 - W_{-1}(-(1 - u)/e)
