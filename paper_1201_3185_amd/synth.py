@@ -77,6 +77,36 @@ def kuzmin_disk_stratified(n: int, a: float, M: float) -> Particles:
     return Particles(R * np.cos(phi), R * np.sin(phi), np.zeros(n), np.full(n, M / n))
 
 
+def _radical_inverse(i: np.ndarray, base: int) -> np.ndarray:
+    """Van der Corput sequence in the given base (low-discrepancy points in [0, 1))."""
+    out = np.zeros(i.shape, dtype=np.float64)
+    f = 1.0 / base
+    k = i.astype(np.int64).copy()
+    while np.any(k > 0):
+        out += f * (k % base)
+        k //= base
+        f /= base
+    return out
+
+
+def exponential_disk_stratified(n: int, Rd: float, M: float, z0: float) -> Particles:
+    """Exponential disk with sech^2(z/z0) heights (razor thin for z0 = 0) from
+    stratified mass fractions (i + 1/2) / n, golden-ratio azimuths and base-3
+    van der Corput height fractions: the distribution of exponential_disk with
+    far less sampling noise."""
+    i = np.arange(n, dtype=np.float64)
+    f = (i + 0.5) / n
+    w = lambertw(-(1.0 - f) / np.e, k=-1).real
+    R = Rd * (-1.0 - w)
+    phi = 2.0 * np.pi * np.mod(i * 0.6180339887498949, 1.0)
+    if z0 > 0.0:
+        u = np.clip(_radical_inverse(np.arange(1, n + 1), 3), 1e-300, 1.0 - 1e-16)
+        z = z0 * np.arctanh(2.0 * u - 1.0)
+    else:
+        z = np.zeros(n)
+    return Particles(R * np.cos(phi), R * np.sin(phi), z, np.full(n, M / n))
+
+
 def _exp_radii(rng: np.random.Generator, n: int, Rd: float) -> np.ndarray:
     u = rng.random(n)
     # 1 - (1 + x) e^-x = u  <=>  x = -1 - W_{-1}(-(1 - u)/e)
