@@ -232,6 +232,43 @@ def vc2_from_acc(x, y, ax, ay, nR, naz=16):
     return (-(x * ax + y * ay)).reshape(nR, naz).mean(axis=1)
 
 
+# ------------------------------------------------------------ diagnostics
+
+def algebraic_field(ax, ay, az, a0=A0_KPC):
+    """Eq. 3, the algebraic MOND relation: g = nu(|g_N| / a0) g_N, point by
+    point, from Newtonian accelerations (g_N = 0 stays 0)."""
+    ax, ay, az = _f64(ax), _f64(ay), _f64(az)
+    if a0 <= 0.0:                      # nu -> 1: the Newtonian field
+        return ax.copy(), ay.copy(), az.copy()
+    g = np.sqrt(ax * ax + ay * ay + az * az)
+    k = np.zeros_like(g)
+    pos = g > 0.0
+    k[pos] = nu(g[pos] / a0)
+    return k * ax, k * ay, k * az
+
+
+def sigma_z_points(R, z, naz=16):
+    """Sample points of the Eq. 5 diagnostic: for each radius, naz azimuths
+    phi_k = 2 pi k / naz at height +z, then the same azimuths at -z."""
+    R = np.asarray(R, dtype=np.float64)
+    phi = 2.0 * np.pi * np.arange(naz) / naz
+    x = np.concatenate([R[:, None] * np.cos(phi)[None, :]] * 2, axis=1).ravel()
+    y = np.concatenate([R[:, None] * np.sin(phi)[None, :]] * 2, axis=1).ravel()
+    zz = np.concatenate([np.full((len(R), naz), z), np.full((len(R), naz), -z)], axis=1).ravel()
+    return x, y, zz
+
+
+def sigma_z2_from_az(zs, az, z0, nR, naz=16):
+    """Eq. 5 for stars whose density falls off as sech^2(z / z0) at every
+    radius: rho / d_z rho = -z0 / (2 tanh(z / z0)), so
+    sigma_z^2 = -(d Phi / dz) rho / d_z rho = (d Phi / dz) z0 / (2 tanh(z / z0))
+              = -a_z z0 / (2 tanh(z / z0)),
+    averaged over the 2 naz sample points of each radius (sigma_z_points)."""
+    zs, az = _f64(zs), _f64(az)
+    s2 = -az * z0 / (2.0 * np.tanh(zs / z0))
+    return s2.reshape(nR, 2 * naz).mean(axis=1)
+
+
 # ------------------------------------------------------------ the pipeline
 
 @dataclass
