@@ -77,6 +77,14 @@ typedef enum {
 } qumond_field;
 
 typedef enum { QUMOND_GUESS_NONE = 0, QUMOND_GUESS_F64 = 1, QUMOND_GUESS_F32 = 2, QUMOND_GUESS_BF16 = 3 } qumond_guess_kind;
+/* Field choice ("which") of qumond_gather_forces, qumond_rotation_curve and
+ * qumond_sigma_z. */
+enum {
+    QUMOND_WHICH_NEWTON = 0,     /* -grad Phi_N (Eq. 1) */
+    QUMOND_WHICH_QUMOND = 1,     /* -grad Phi (Eq. 2) */
+    QUMOND_WHICH_ALGEBRAIC = 2   /* Eq. 3: nu(|g_N| / a0) g_N at the point, g_N from Phi_N */
+};
+
 /* OR-ed into guess_kind: never fall back to FMG (for measuring plain V-cycles
  * from a given start); the solve then stops after ncycle_fmg + max_vcycles
  * cycles at the latest. */
@@ -184,22 +192,40 @@ qumond_status qumond_solve_mond(qumond_ctx *ctx, const void *guess, int32_t gues
  * after all of it.  Either info (host) may be NULL.  Synchronises. */
 qumond_status qumond_solve(qumond_ctx *ctx, qumond_solve_info *info_newton, qumond_solve_info *info_mond);
 
-/* Accelerations -grad Phi (which = 0: Phi_N, 1: Phi) at np points.  Gravity
+/* Accelerations at np points: -grad Phi_N (which = QUMOND_WHICH_NEWTON),
+ * -grad Phi (QUMOND_WHICH_QUMOND) or the algebraic MOND field of Eq. 3
+ * (QUMOND_WHICH_ALGEBRAIC: the Newtonian acceleration g_N at the point times
+ * nu(|g_N| / a0), the relation Sec. 1 compares QUMOND with).  Gravity
  * at nodes by central differences (one-sided second order on box faces),
  * weighted to the point with the cloud-in-cell weights.  Box choice (Sec. 3.1):
  * the finest box with sqrt(x^2+y^2) < gather_frac L_b and |z| < gather_frac L_b;
  * otherwise the outermost box that contains the point; otherwise the monopole
- * of total_mass (Newtonian, or QUMOND with nu(g_N/a0) for which = 1).
- * box_used (device, optional) receives the box index, 255 for the monopole. */
+ * of total_mass (Newtonian, or QUMOND with nu(g_N/a0) for the other two).
+ * box_used (device, optional) receives the box index, 255 for the monopole.
+ * QUMOND_ERR_STATE before the solve the field needs. */
 qumond_status qumond_gather_forces(qumond_ctx *ctx, const double *x, const double *y, const double *z,
                                    int64_t np, int32_t which, double *ax, double *ay, double *az,
                                    uint8_t *box_used);
 
 /* Eq. 4: v_c^2(R) = R dPhi/dR at z = 0, averaged over naz azimuths
  * phi_k = 2 pi k / naz, for the nR radii R (device) into vc2 (device).
- * which as for qumond_gather_forces.  1 <= naz <= 1024. */
+ * which as for qumond_gather_forces (QUMOND_WHICH_ALGEBRAIC gives the
+ * algebraic MOND curve of Eq. 3).  1 <= naz <= 1024. */
 qumond_status qumond_rotation_curve(qumond_ctx *ctx, const double *R, int32_t nR, int32_t naz, int32_t which,
                                     double *vc2);
+
+/* Eq. 5 (Sec. 5), the vertical velocity dispersion of an isothermal stellar
+ * disk, sigma_z^2 = -(dPhi/dz) rho_* / (d rho_* / dz), for stars whose density
+ * falls off as sech^2(z / z0) at every radius (the vertical profile of the
+ * disk models, scale height z0 > 0), so rho_* / (d rho_* / dz) =
+ * -z0 / (2 tanh(z / z0)) and sigma_z^2 = -a_z z0 / (2 tanh(z / z0)).  a_z is
+ * the gathered vertical acceleration of field `which` (as for
+ * qumond_gather_forces) at height z > 0 (kpc) above and below the plane;
+ * sig2[r] (device, (km/s)^2) is the mean over the 2 naz points
+ * (R[r] cos phi_k, R[r] sin phi_k, +-z), phi_k = 2 pi k / naz, 1 <= naz <= 1024.
+ * R (device) holds nR >= 0 radii.  Asynchronous on the context's stream. */
+qumond_status qumond_sigma_z(qumond_ctx *ctx, const double *R, int32_t nR, int32_t naz, double z, double z0,
+                             int32_t which, double *sig2);
 
 /* Copy one n^3 field of box b to dst (device; int64 for RHO_FIXED, double
  * otherwise).  Asynchronous. */

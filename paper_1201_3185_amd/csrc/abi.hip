@@ -642,23 +642,34 @@ static qm::GatherArgs gather_args(const qumond_ctx *ctx, int which)
         a.box[b].xmin = -0.5 * B.L;
         a.box[b].inv_h = (double)(ctx->n - 1) / B.L;
         a.box[b].h = B.h;
-        a.phi[b] = which ? B.phi : B.phin;
+        a.phi[b] = which == QUMOND_WHICH_QUMOND ? B.phi : B.phin;
     }
     a.frac = ctx->cfg.gather_frac;
     a.GM = ctx->cfg.G * ctx->total_mass;
     a.a0 = ctx->cfg.a0;
-    a.mond = which;
+    a.mond = which == QUMOND_WHICH_QUMOND;
+    a.alg = which == QUMOND_WHICH_ALGEBRAIC;
     return a;
+}
+
+// The field choice of the gather-type calls and the stage it needs.
+static qumond_status check_which(const qumond_ctx *ctx, int which)
+{
+    if (which != QUMOND_WHICH_NEWTON && which != QUMOND_WHICH_QUMOND && which != QUMOND_WHICH_ALGEBRAIC)
+        return fail(QUMOND_ERR_INVALID, "which must be 0 (Newton), 1 (QUMOND) or 2 (algebraic MOND)");
+    if (ctx->stage < (which == QUMOND_WHICH_QUMOND ? ST_MOND : ST_NEWTON))
+        return fail(QUMOND_ERR_STATE, "potential not solved yet");
+    return QUMOND_OK;
 }
 
 qumond_status qumond_gather_forces(qumond_ctx *ctx, const double *x, const double *y, const double *z, int64_t np,
                                    int32_t which, double *ax, double *ay, double *az, uint8_t *box_used)
 {
     if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
-    if (which != 0 && which != 1) return fail(QUMOND_ERR_INVALID, "which must be 0 (Newton) or 1 (QUMOND)");
     if (np < 0) return fail(QUMOND_ERR_INVALID, "np must be >= 0");
     if (np > 0 && (!x || !y || !z || !ax || !ay || !az)) return fail(QUMOND_ERR_INVALID, "array is NULL");
-    if (ctx->stage < (which ? ST_MOND : ST_NEWTON)) return fail(QUMOND_ERR_STATE, "potential not solved yet");
+    qumond_status st = check_which(ctx, which);
+    if (st != QUMOND_OK) return st;
     qm::launch_gather(gather_args(ctx, which), x, y, z, np, ax, ay, az, box_used, ctx->s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "qumond_gather_forces: launch");
@@ -669,13 +680,29 @@ qumond_status qumond_rotation_curve(qumond_ctx *ctx, const double *R, int32_t nR
                                     double *vc2)
 {
     if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
-    if (which != 0 && which != 1) return fail(QUMOND_ERR_INVALID, "which must be 0 or 1");
     if (nR < 0 || naz < 1 || naz > 1024) return fail(QUMOND_ERR_INVALID, "need nR >= 0 and 1 <= naz <= 1024");
     if (nR > 0 && (!R || !vc2)) return fail(QUMOND_ERR_INVALID, "array is NULL");
-    if (ctx->stage < (which ? ST_MOND : ST_NEWTON)) return fail(QUMOND_ERR_STATE, "potential not solved yet");
+    qumond_status st = check_which(ctx, which);
+    if (st != QUMOND_OK) return st;
     qm::launch_rotation_curve(gather_args(ctx, which), R, nR, naz, vc2, ctx->s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "qumond_rotation_curve: launch");
+    return QUMOND_OK;
+}
+
+qumond_status qumond_sigma_z(qumond_ctx *ctx, const double *R, int32_t nR, int32_t naz, double z, double z0,
+                             int32_t which, double *sig2)
+{
+    if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
+    if (nR < 0 || naz < 1 || naz > 1024) return fail(QUMOND_ERR_INVALID, "need nR >= 0 and 1 <= naz <= 1024");
+    if (!(z > 0.0) || !(z0 > 0.0) || !std::isfinite(z) || !std::isfinite(z0))
+        return fail(QUMOND_ERR_INVALID, "need finite z > 0 and z0 > 0");
+    if (nR > 0 && (!R || !sig2)) return fail(QUMOND_ERR_INVALID, "array is NULL");
+    qumond_status st = check_which(ctx, which);
+    if (st != QUMOND_OK) return st;
+    qm::launch_sigma_z(gather_args(ctx, which), R, nR, naz, z, z0, sig2, ctx->s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "qumond_sigma_z: launch");
     return QUMOND_OK;
 }
 

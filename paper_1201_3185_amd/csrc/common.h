@@ -44,7 +44,8 @@ struct GatherArgs {
     BoxGeom box[kMaxBox];
     const double *phi[kMaxBox];
     double frac, GM, a0;
-    int mond;
+    int mond;  // monopole of points outside every box: 0 Newtonian, 1 QUMOND
+    int alg;   // 1: Eq. 3 applied to the gathered (Newtonian) field
 };
 
 // One problem of a batch as its kernels read it from device memory, so that a
@@ -152,6 +153,8 @@ void launch_rhs_from_q(int n, double h, double four_pi_G, int shift, const long 
 void launch_gather(const GatherArgs &a, const double *x, const double *y, const double *z, int64_t np, double *ax,
                    double *ay, double *az, uint8_t *box_used, hipStream_t s);
 void launch_rotation_curve(const GatherArgs &a, const double *R, int nR, int naz, double *vc2, hipStream_t s);
+void launch_sigma_z(const GatherArgs &a, const double *R, int nR, int naz, double z, double z0, double *sig2,
+                    hipStream_t s);
 // Batches of single-box problems (one box of side L, n points per side):
 // q must be zeroed; scratch holds deposit_batch_scratch_bytes(nb) bytes;
 // inside[p] counts the particles of problem p deposited (must be zeroed).

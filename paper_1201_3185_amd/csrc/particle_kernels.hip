@@ -314,6 +314,19 @@ __device__ void box_accel(const BoxGeom &G, int n, const double *__restrict__ P,
             }
 }
 
+// Eq. 3, the algebraic MOND relation: g = nu(|g_N| / a0) g_N at the point.
+__device__ __forceinline__ void algebraic_mond(double a0, double acc[3])
+{
+#pragma clang fp contract(off)
+    const double g = sqrt(acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2]);
+    if (g > 0.0 && a0 > 0.0) {
+        const double k = 0.5 + 0.5 * sqrt(1.0 + 4.0 * a0 / g);
+        acc[0] *= k;
+        acc[1] *= k;
+        acc[2] *= k;
+    }
+}
+
 __device__ int gather_point(const GatherArgs &A, double px, double py, double pz, double acc[3])
 {
 #pragma clang fp contract(off)
@@ -325,12 +338,10 @@ __device__ int gather_point(const GatherArgs &A, double px, double py, double pz
         for (int b = 0; b < A.nbox; ++b)
             if (in_box(A.box[b], A.n, px, py, pz)) { sel = b; break; }
     }
-    if (sel < 0) {
-        monopole_accel(A.GM, A.a0, A.mond, px, py, pz, acc);
-        return 255;
-    }
-    box_accel(A.box[sel], A.n, A.phi[sel], px, py, pz, acc);
-    return sel;
+    if (sel < 0) monopole_accel(A.GM, A.a0, A.mond, px, py, pz, acc);
+    else box_accel(A.box[sel], A.n, A.phi[sel], px, py, pz, acc);
+    if (A.alg) algebraic_mond(A.a0, acc);
+    return sel < 0 ? 255 : sel;
 }
 
 __global__ void __launch_bounds__(256)
@@ -384,6 +395,43 @@ void launch_rotation_curve(const GatherArgs &a, const double *R, int nR, int naz
 {
     if (nR <= 0) return;
     hipLaunchKernelGGL(rotation_curve_k, dim3(nR), dim3(256), 0, s, a, R, naz, vc2);
+}
+
+// Eq. 5 for stars with a sech^2(z / z0) vertical profile at every radius:
+// rho / d_z rho = -z0 / (2 tanh(z / z0)), so sigma_z^2 = -a_z z0 / (2 tanh(z / z0)).
+// One workgroup per radius; samples k < naz at (R cos phi_k, R sin phi_k, +z),
+// k >= naz at the same azimuths and -z, averaged in a fixed order.
+__global__ void __launch_bounds__(256)
+sigma_z_k(GatherArgs A, const double *__restrict__ R, int naz, double z, double z0, double *__restrict__ sig2)
+{
+#pragma clang fp contract(off)
+    __shared__ double sh[256];
+    const double r = R[blockIdx.x];
+    const double c = z0 / (2.0 * tanh(z / z0));
+    double s = 0.0;
+    for (int k = threadIdx.x; k < 2 * naz; k += 256) {
+        const bool up = k < naz;
+        const int ka = up ? k : k - naz;
+        const double phi = 2.0 * M_PI * (double)ka / (double)naz;
+        const double px = r * cos(phi), py = r * sin(phi);
+        double acc[3];
+        gather_point(A, px, py, up ? z : -z, acc);
+        s += up ? -acc[2] * c : acc[2] * c;  // tanh is odd
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sig2[blockIdx.x] = sh[0] / (double)(2 * naz);
+}
+
+void launch_sigma_z(const GatherArgs &a, const double *R, int nR, int naz, double z, double z0, double *sig2,
+                    hipStream_t s)
+{
+    if (nR <= 0) return;
+    hipLaunchKernelGGL(sigma_z_k, dim3(nR), dim3(256), 0, s, a, R, naz, z, z0, sig2);
 }
 
 // Batched single-box curves: workgroup (r, p), same sampling and order as rotation_curve_k.

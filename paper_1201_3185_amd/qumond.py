@@ -27,6 +27,7 @@ QUMOND_BC_ZERO, QUMOND_BC_MONOPOLE = 0, 1
 FIELD_RHO_FIXED, FIELD_RHS, FIELD_PHI_N, FIELD_SOURCE, FIELD_PHI = range(5)
 GUESS_NONE, GUESS_F64, GUESS_F32, GUESS_BF16 = range(4)
 GUESS_NO_FALLBACK = 16
+WHICH_NEWTON, WHICH_QUMOND, WHICH_ALGEBRAIC = range(3)
 
 
 class qumond_config(ctypes.Structure):
@@ -87,6 +88,7 @@ _SIGNATURES = {
     "qumond_solve_mond": (_I32, [_P, _P, _I32, ctypes.POINTER(qumond_solve_info)]),
     "qumond_gather_forces": (_I32, [_P, _P, _P, _P, _I64, _I32, _P, _P, _P, _P]),
     "qumond_rotation_curve": (_I32, [_P, _P, _I32, _I32, _I32, _P]),
+    "qumond_sigma_z": (_I32, [_P, _P, _I32, _I32, _D, _D, _I32, _P]),
     "qumond_get_field": (_I32, [_P, _I32, _I32, _P]),
     "qumond_set_field": (_I32, [_P, _I32, _I32, _P]),
     "qumond_device_bytes": (_I64, [_P]),
@@ -322,6 +324,15 @@ class Context:
         check(lib().qumond_rotation_curve(self._h, _ptr(R), R.numel(), int(naz), int(which), _ptr(vc2)),
               "qumond_rotation_curve")
         return vc2
+
+    def sigma_z(self, R: torch.Tensor, z: float, z0: float, naz: int = 16, which: int = 1) -> torch.Tensor:
+        """Eq. 5: sigma_z^2 (km/s)^2 at the radii R for a sech^2(z/z0) stellar
+        disk, from the vertical acceleration at heights +-z."""
+        _f64(R, "R")
+        s2 = torch.empty_like(R)
+        check(lib().qumond_sigma_z(self._h, _ptr(R), R.numel(), int(naz), float(z), float(z0), int(which),
+                                   _ptr(s2)), "qumond_sigma_z")
+        return s2
 
     def get_field(self, box: int, fld: int) -> torch.Tensor:
         dt = torch.int64 if fld == FIELD_RHO_FIXED else torch.float64
