@@ -56,6 +56,7 @@ def lib():
         d, i, i64, vp = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
         sig = {
             "orc_nu": (d, [d]),
+            "orc_nu_n": (d, [d, d]),
             "orc_fixed_shift": (i, [d]),
             "orc_cic_deposit": (i64, [i, d, i64, vp, vp, vp, vp, i, vp]),
             "orc_rhs_from_q": (None, [i, d, d, i, vp, vp]),
@@ -74,7 +75,9 @@ def lib():
             "orc_fmg": (i, [i, d, vp, vp, i, i, i, i, d, vp, vp]),
             "orc_vcycles": (d, [i, d, vp, vp, i, i, i]),
             "orc_mond_source": (None, [i, d, d, vp, vp]),
+            "orc_mond_source_nu": (None, [i, d, d, d, vp, vp]),
             "orc_gather": (None, [i, i, vp, vp, i64, vp, vp, vp, d, d, d, d, i, vp, vp, vp, vp]),
+            "orc_gather_nu": (None, [i, i, vp, vp, i64, vp, vp, vp, d, d, d, d, i, d, vp, vp, vp, vp]),
             "orc_conv3d_fwd": (None, [i, i, vp, i, vp, vp, i, i, vp]),
             "orc_conv3d_dgrad": (None, [i, i, i, vp, i, vp, vp]),
             "orc_conv3d_wgrad": (None, [i, i, vp, i, vp, i, vp]),
@@ -99,9 +102,47 @@ def _f64(a) -> np.ndarray:
 
 # ---------------------------------------------------------------- pointwise
 
-def nu(y):
-    """Eq. 2 interpolating function, elementwise."""
-    return np.vectorize(lib().orc_nu, otypes=[np.float64])(np.asarray(y, dtype=np.float64))
+def nu(y, nu_n=1.0):
+    """Eq. 2 interpolating function, elementwise; nu_n != 1 selects the
+    n-family member [(1 + sqrt(1 + 4 y^-n)) / 2]^(1/n) (Sec. 2 allows other
+    forms of nu; n = 1 is Eq. 2's)."""
+    if nu_n == 1.0:
+        return np.vectorize(lib().orc_nu, otypes=[np.float64])(np.asarray(y, dtype=np.float64))
+    return np.vectorize(lambda v: lib().orc_nu_n(v, float(nu_n)), otypes=[np.float64])(np.asarray(y, dtype=np.float64))
+
+
+def _nu_minus_one_at(s, nu_n):
+    """nu_n(1/s^2) - 1 without cancellation: with w = s^(2n),
+    nu^n = 1 + q, q = 2 w / (1 + sqrt(1 + 4 w)), so nu - 1 = expm1(log1p(q) / n)."""
+    w = s ** (2.0 * nu_n)
+    q = 2.0 * w / (1.0 + math.sqrt(1.0 + 4.0 * w))
+    return math.expm1(math.log1p(q) / nu_n)
+
+
+def point_mond_integral(t, nu_n):
+    """I(t) = int_0^t (nu_n(1/s^2) - 1) / s^2 ds (scipy quad on geometric
+    pieces), the dimensionless part of the point-mass QUMOND potential."""
+    from scipy import integrate
+    f = lambda s: _nu_minus_one_at(s, nu_n) / (s * s) if s > 0.0 else (1.0 if nu_n == 1.0 else 0.0)
+    edges = [0.0] + [e for e in (1e-3 * 4.0 ** k for k in range(40)) if e < t] + [t]
+    total = 0.0
+    for a, b in zip(edges[:-1], edges[1:]):
+        val, _ = integrate.quad(f, a, b, epsabs=0.0, epsrel=1e-13, limit=200)
+        total += val
+    return total
+
+
+def phi_point_mond_family(r, G=G_KPC, M=1.0, a0=A0_KPC, nu_n=1.0):
+    """Point-mass QUMOND potential for the n-family: the radial integral of
+    nu_n(g_N/a0) g_N fixed to tend to -GM/r at small r, i.e.
+    -GM/r + sqrt(G M a0) I(r / r_M), r_M = sqrt(G M / a0)."""
+    GM = G * M
+    r = np.asarray(r, dtype=np.float64)
+    if a0 <= 0.0 or GM <= 0.0:
+        return -GM / r
+    rm = math.sqrt(GM / a0)
+    out = np.array([-GM / rr + math.sqrt(GM * a0) * point_mond_integral(rr / rm, nu_n) for rr in r.ravel()])
+    return out.reshape(r.shape)
 
 
 def fixed_shift(total_mass: float) -> int:
@@ -133,10 +174,22 @@ def rhs_from_q(n, L, q, shift, G=G_KPC):
     return f
 
 
-def bc_outer(u, L, mode, G=G_KPC, a0=A0_KPC, M=0.0):
-    """mode 0 zero, 1 Newtonian monopole, 2 QUMOND monopole (boundary nodes only)."""
+def bc_outer(u, L, mode, G=G_KPC, a0=A0_KPC, M=0.0, nu_n=1.0):
+    """mode 0 zero, 1 Newtonian monopole, 2 QUMOND monopole (boundary nodes only).
+    For nu_n != 1 the QUMOND monopole is the quadrature of phi_point_mond_family,
+    once per distinct radius."""
     n = u.shape[0]
-    lib().orc_bc_outer(n, float(L), int(mode), float(G), float(a0), float(M), _p(u))
+    if mode != 2 or nu_n == 1.0:
+        lib().orc_bc_outer(n, float(L), int(mode), float(G), float(a0), float(M), _p(u))
+        return u
+    h = L / (n - 1)
+    c = -0.5 * L + h * np.arange(n)
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    bnd = np.zeros((n, n, n), dtype=bool)
+    bnd[0], bnd[-1], bnd[:, 0], bnd[:, -1], bnd[:, :, 0], bnd[:, :, -1] = (True,) * 6
+    r = np.sqrt(X[bnd] ** 2 + Y[bnd] ** 2 + Z[bnd] ** 2)
+    ru, inv = np.unique(r, return_inverse=True)
+    u[bnd] = phi_point_mond_family(ru, G, M, a0, nu_n)[inv]
     return u
 
 
@@ -194,14 +247,14 @@ def vcycles(f, u, L, ncyc, npre=2, npost=2):
     return float(lib().orc_vcycles(u.shape[0], float(L), _p(_f64(f)), _p(u), npre, npost, ncyc))
 
 
-def mond_source(phin, L, a0=A0_KPC):
+def mond_source(phin, L, a0=A0_KPC, nu_n=1.0):
     phin = _f64(phin)
     S = np.zeros_like(phin)
-    lib().orc_mond_source(phin.shape[0], float(L), float(a0), _p(phin), _p(S))
+    lib().orc_mond_source_nu(phin.shape[0], float(L), float(a0), float(nu_n), _p(phin), _p(S))
     return S
 
 
-def gather(phis, Ls, x, y, z, frac=0.2, G=G_KPC, a0=A0_KPC, M=0.0, mond=True):
+def gather(phis, Ls, x, y, z, frac=0.2, G=G_KPC, a0=A0_KPC, M=0.0, mond=True, nu_n=1.0):
     """Accelerations (ax, ay, az) and the box index used (255 = monopole)."""
     n = phis[0].shape[0]
     nbox = len(phis)
@@ -212,9 +265,9 @@ def gather(phis, Ls, x, y, z, frac=0.2, G=G_KPC, a0=A0_KPC, M=0.0, mond=True):
     np_ = len(x)
     ax, ay, az = np.zeros(np_), np.zeros(np_), np.zeros(np_)
     used = np.zeros(np_, dtype=np.uint8)
-    lib().orc_gather(nbox, n, _p(Ls_a), ctypes.cast(ptrs, ctypes.c_void_p), np_, _p(x), _p(y), _p(z),
-                     float(frac), float(G), float(a0), float(M), int(bool(mond)),
-                     _p(ax), _p(ay), _p(az), _p(used))
+    lib().orc_gather_nu(nbox, n, _p(Ls_a), ctypes.cast(ptrs, ctypes.c_void_p), np_, _p(x), _p(y), _p(z),
+                        float(frac), float(G), float(a0), float(M), int(bool(mond)), float(nu_n),
+                        _p(ax), _p(ay), _p(az), _p(used))
     return ax, ay, az, used
 
 
@@ -234,7 +287,7 @@ def vc2_from_acc(x, y, ax, ay, nR, naz=16):
 
 # ------------------------------------------------------------ diagnostics
 
-def algebraic_field(ax, ay, az, a0=A0_KPC):
+def algebraic_field(ax, ay, az, a0=A0_KPC, nu_n=1.0):
     """Eq. 3, the algebraic MOND relation: g = nu(|g_N| / a0) g_N, point by
     point, from Newtonian accelerations (g_N = 0 stays 0)."""
     ax, ay, az = _f64(ax), _f64(ay), _f64(az)
@@ -243,7 +296,7 @@ def algebraic_field(ax, ay, az, a0=A0_KPC):
     g = np.sqrt(ax * ax + ay * ay + az * az)
     k = np.zeros_like(g)
     pos = g > 0.0
-    k[pos] = nu(g[pos] / a0)
+    k[pos] = nu(g[pos] / a0, nu_n)
     return k * ax, k * ay, k * az
 
 
@@ -285,6 +338,7 @@ class OracleConfig:
     outer_bc: int = 1             # 0 zero, 1 monopole
     gather_frac: float = 0.2
     fixed_shift: int = 0          # 0 = from the total mass
+    nu_n: float = 1.0             # interpolating function: 1 = Eq. 2's nu, else the n-family
 
 
 @dataclass
@@ -308,7 +362,7 @@ def solve_chain(cfg: OracleConfig, rhs: list, mond: bool, M: float):
         u = np.zeros((cfg.n,) * 3)
         if b == 0:
             mode = 0 if cfg.outer_bc == 0 else (2 if mond else 1)
-            bc_outer(u, Lb, mode, cfg.G, cfg.a0, M)
+            bc_outer(u, Lb, mode, cfg.G, cfg.a0, M, cfg.nu_n)
         else:
             bc_from_coarse(out[b - 1], cfg.box_side[b - 1], u, Lb)
         st, rr, ex = fmg(rhs[b], u, Lb, cfg.npre, cfg.npost, cfg.ncycle_fmg, cfg.max_vcycles, cfg.tol_rel)
@@ -330,7 +384,7 @@ def run_pipeline(cfg: OracleConfig, x, y, z, m, total_mass: float) -> OracleResu
         res.f.append(rhs_from_q(cfg.n, Lb, q, shift, cfg.G))
     res.n_outside = len(np.asarray(x)) - inside_outer
     res.phin, res.info_newton = solve_chain(cfg, res.f, False, total_mass)
-    res.S = [mond_source(p, Lb, cfg.a0) for p, Lb in zip(res.phin, cfg.box_side)]
+    res.S = [mond_source(p, Lb, cfg.a0, cfg.nu_n) for p, Lb in zip(res.phin, cfg.box_side)]
     res.phi, res.info_mond = solve_chain(cfg, res.S, True, total_mass)
     return res
 

@@ -46,6 +46,15 @@
 /* Eq. 2: nu(y) = 1/2 + 1/2 sqrt(1 + 4/y), y = |grad Phi_N| / a0. */
 double orc_nu(double y) { return 0.5 + 0.5 * sqrt(1.0 + 4.0 / y); }
 
+/* Other forms of nu (Sec. 2 notes that nu could take another form): the
+ * n-family nu_n(y) = [(1 + sqrt(1 + 4 y^-n)) / 2]^(1/n), whose n = 1 member
+ * is Eq. 2's nu (evaluated by orc_nu) and n = 2 the "standard" function. */
+double orc_nu_n(double y, double nn)
+{
+    if (nn == 1.0) return orc_nu(y);
+    return pow(0.5 * (1.0 + sqrt(1.0 + 4.0 * pow(y, -nn))), 1.0 / nn);
+}
+
 /* --------------------------------------------------------------- deposit */
 
 /* Fixed-point scale exponent s such that the integer grid can hold the total
@@ -478,7 +487,7 @@ double orc_vcycles(int n, double L, const double *f, double *u, int npre, int np
  * normal gradient (Phi_q - Phi_p)/h, transverse components averaged over the
  * four nodes beside the face, F = nu(|g|/a0) g_n, and F = 0 where |g| = 0
  * (the limit of nu(|g|/a0) g as |g| -> 0). */
-static double face_flux(int n, double h, double a0, const double *P, int i, int j, int k, int d)
+static double face_flux(int n, double h, double a0, double nn, const double *P, int i, int j, int k, int d)
 {
     int e[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
     int qi = i + e[d][0], qj = j + e[d][1], qk = k + e[d][2];
@@ -494,12 +503,13 @@ static double face_flux(int n, double h, double a0, const double *P, int i, int 
     }
     double g = sqrt(g2);
     if (g == 0.0) return 0.0;
+    if (nn != 1.0) return gn * orc_nu_n(g / a0, nn);
     return 0.5 * gn * (1.0 + sqrt(1.0 + 4.0 * a0 / g));
 }
 
 /* Eq. 2 source: S_p = sum_d (F_{p+e_d/2} - F_{p-e_d/2}) / h at interior
- * nodes, 0 on the boundary. */
-void orc_mond_source(int n, double L, double a0, const double *phin, double *S)
+ * nodes, 0 on the boundary; nu from the n-family (nn = 1: Eq. 2's nu). */
+void orc_mond_source_nu(int n, double L, double a0, double nn, const double *phin, double *S)
 {
     const double h = L / (double)(n - 1);
     for (int k = 0; k < n; k++)
@@ -508,11 +518,16 @@ void orc_mond_source(int n, double L, double a0, const double *phin, double *S)
                 size_t c = ID3(n, i, j, k);
                 if (on_boundary(n, i, j, k)) { S[c] = 0.0; continue; }
                 double s = 0.0;
-                s += face_flux(n, h, a0, phin, i, j, k, 0) - face_flux(n, h, a0, phin, i - 1, j, k, 0);
-                s += face_flux(n, h, a0, phin, i, j, k, 1) - face_flux(n, h, a0, phin, i, j - 1, k, 1);
-                s += face_flux(n, h, a0, phin, i, j, k, 2) - face_flux(n, h, a0, phin, i, j, k - 1, 2);
+                s += face_flux(n, h, a0, nn, phin, i, j, k, 0) - face_flux(n, h, a0, nn, phin, i - 1, j, k, 0);
+                s += face_flux(n, h, a0, nn, phin, i, j, k, 1) - face_flux(n, h, a0, nn, phin, i, j - 1, k, 1);
+                s += face_flux(n, h, a0, nn, phin, i, j, k, 2) - face_flux(n, h, a0, nn, phin, i, j, k - 1, 2);
                 S[c] = s / h;
             }
+}
+
+void orc_mond_source(int n, double L, double a0, const double *phin, double *S)
+{
+    orc_mond_source_nu(n, L, a0, 1.0, phin, S);
 }
 
 /* ---------------------------------------------------------------- gather */
@@ -547,10 +562,10 @@ static double node_grad(int n, double h, const double *P, int i, int j, int k, i
  * monopole of mass M (Newtonian for mond == 0, QUMOND otherwise).  Inside the
  * chosen box the node gravities of the 8 CIC corners are weighted with the
  * CIC weights.  box_used gets the box index, 255 for the monopole. */
-void orc_gather(int nbox, int n, const double *Ls, const double *const *phis, int64_t np,
-                const double *x, const double *y, const double *z, double frac, double G,
-                double a0, double M, int mond, double *ax, double *ay, double *az,
-                uint8_t *box_used)
+void orc_gather_nu(int nbox, int n, const double *Ls, const double *const *phis, int64_t np,
+                   const double *x, const double *y, const double *z, double frac, double G,
+                   double a0, double M, int mond, double nn, double *ax, double *ay, double *az,
+                   uint8_t *box_used)
 {
     for (int64_t p = 0; p < np; p++) {
         double R = sqrt(x[p] * x[p] + y[p] * y[p]);
@@ -572,7 +587,7 @@ void orc_gather(int nbox, int n, const double *Ls, const double *const *phis, in
             double g = 0.0;
             if (r > 0.0) {
                 double gN = G * M / (r * r);
-                g = (mond && a0 > 0.0) ? orc_nu(gN / a0) * gN : gN;
+                g = (mond && a0 > 0.0) ? orc_nu_n(gN / a0, nn) * gN : gN;
                 g /= r;
             }
             ax[p] = -g * x[p];
@@ -606,4 +621,12 @@ void orc_gather(int nbox, int n, const double *Ls, const double *const *phis, in
         ay[p] = acc[1];
         az[p] = acc[2];
     }
+}
+
+void orc_gather(int nbox, int n, const double *Ls, const double *const *phis, int64_t np,
+                const double *x, const double *y, const double *z, double frac, double G,
+                double a0, double M, int mond, double *ax, double *ay, double *az,
+                uint8_t *box_used)
+{
+    orc_gather_nu(nbox, n, Ls, phis, np, x, y, z, frac, G, a0, M, mond, 1.0, ax, ay, az, box_used);
 }

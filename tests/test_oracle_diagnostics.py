@@ -126,3 +126,83 @@ def test_sigma_z_kuzmin_second_order():
         errs.append(np.max(np.abs(_sigma(phi, L, R, z, z0, frac=0.4) / exact - 1.0)))
     assert errs[1] < 0.02
     assert errs[0] / errs[1] > 3.0
+
+
+# ------------------------------------------------------------ other nu forms
+
+@pytest.mark.parametrize("nn", [1.0, 2.0, 3.0])
+def test_nu_family_inverts_its_mu(nn):
+    # the n-family is the inverse of mu_n(x) = x / (1 + x^n)^(1/n): y = x mu_n(x) <=> nu_n(y) = 1 / mu_n(x)
+    x = np.logspace(-4, 4, 61)
+    y = x * x / (1.0 + x ** nn) ** (1.0 / nn)
+    assert np.allclose(O.nu(y, nn), (1.0 + x ** nn) ** (1.0 / nn) / x, rtol=1e-11, atol=0)
+
+
+def test_nu_family_n1_is_eq2_nu():
+    y = np.logspace(-6, 6, 25)
+    assert np.array_equal(O.nu(y, 1.0), O.nu(y))
+    assert np.allclose(np.vectorize(lambda v: O.lib().orc_nu_n(v, 1.0))(y), O.nu(y), rtol=0, atol=0)
+
+
+def test_point_potential_family_n1_is_closed_form():
+    r = np.geomspace(0.05, 5000.0, 23)
+    for M in (1e6, 1e10, 3e11):
+        closed = A.phi_point_mond_closed(r, O.G_KPC, M, O.A0_KPC)
+        assert np.allclose(O.phi_point_mond_family(r, O.G_KPC, M, O.A0_KPC, 1.0), closed, rtol=1e-12)
+
+
+@pytest.mark.parametrize("nn", [2.0, 4.0])
+def test_point_potential_family_derivative_and_limits(nn):
+    G, M, a0 = O.G_KPC, 2e10, O.A0_KPC
+    r = np.array([0.3, 2.0, 4.7, 20.0, 300.0])
+    d = 1e-3 * r
+    phi = lambda s: O.phi_point_mond_family(s, G, M, a0, nn)
+    dphi = (-phi(r + 2 * d) + 8 * phi(r + d) - 8 * phi(r - d) + phi(r - 2 * d)) / (12 * d)
+    gN = G * M / (r * r)
+    assert np.allclose(dphi, O.nu(gN / a0, nn) * gN, rtol=1e-8)
+    # -GM/r at small r, logarithmic with slope sqrt(G M a0) far out
+    assert phi(np.array([1e-4]))[0] == pytest.approx(-G * M / 1e-4, rel=1e-6)
+    far = phi(np.array([1e5, 1e6]))
+    assert (far[1] - far[0]) / np.log(10.0) == pytest.approx(np.sqrt(G * M * a0), rel=1e-4)
+
+
+def test_source_family_converges_at_second_order():
+    G, M, b, nn = O.G_KPC, 1e10, 2.0, 2.0
+    L = 20.0
+    c0 = np.array([0.11, -0.07, 0.05])
+
+    def div(rr):                     # analytic (1/r^2) d/dr [r^2 nu_2(g/a0) g] for the Plummer Phi_N
+        def flux(q):
+            g = G * M * q / (q * q + b * b) ** 1.5
+            nu2 = np.sqrt(0.5 * (1.0 + np.sqrt(1.0 + 4.0 * (O.A0_KPC / g) ** 2)))
+            return q * q * nu2 * g
+        d = 1e-4 * rr
+        return (flux(rr + d) - flux(rr - d)) / (2 * d) / (rr * rr)
+
+    errs = []
+    for n in (33, 65):
+        X, Y, Z = node_coords(n, L)
+        r = np.sqrt((X - c0[0]) ** 2 + (Y - c0[1]) ** 2 + (Z - c0[2]) ** 2)
+        S = O.mond_source(-G * M / np.sqrt(r * r + b * b), L, nu_n=nn)
+        shell = (r > 3.0) & (r < 7.0)
+        ex = div(r[shell])
+        errs.append(np.abs(S[shell] - ex).max() / np.abs(ex).max())
+    assert errs[0] < 0.05
+    assert 3.3 < errs[0] / errs[1] < 4.7
+
+
+def test_bc_outer_family_values():
+    n, L, M = 9, 40.0, 5e10
+    u = np.zeros((n,) * 3)
+    O.bc_outer(u, L, 2, M=M, nu_n=2.0)
+    X, Y, Z = node_coords(n, L)
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    bmask = np.zeros_like(u, dtype=bool)
+    bmask[0], bmask[-1], bmask[:, 0], bmask[:, -1], bmask[:, :, 0], bmask[:, :, -1] = (True,) * 6
+    ref = O.phi_point_mond_family(r[bmask], O.G_KPC, M, O.A0_KPC, 2.0)
+    assert np.allclose(u[bmask], ref, rtol=1e-14)
+    assert np.all(u[~bmask] == 0)
+    # n = 1 through the same call is the closed form of the C oracle
+    u1 = np.zeros((n,) * 3)
+    O.bc_outer(u1, L, 2, M=M, nu_n=1.0)
+    assert np.allclose(u1[bmask], A.phi_point_mond_closed(r[bmask], O.G_KPC, M, O.A0_KPC), rtol=1e-13)
