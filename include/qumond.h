@@ -105,6 +105,11 @@ typedef struct qumond_config {
     double gather_frac;                 /* box choice: finest box with R, |z| < gather_frac * L_b, in (0, 0.5) */
     int32_t fixed_shift;                /* deposit scale exponent s (q = rint(w m 2^s)); 0 = from total mass */
     int32_t use_graphs;                 /* 1: replay the fixed FMG schedule from captured HIP graphs */
+    double nu_n;                        /* interpolating function (Sec. 2 allows other forms of nu): 1 = Eq. 2's
+                                           nu(y) = 1/2 + 1/2 sqrt(1 + 4/y) (default); otherwise, 1 < nu_n <= 10,
+                                           the n-family nu_n(y) = [(1 + sqrt(1 + 4 y^-n)) / 2]^(1/n) (2: the
+                                           "standard" nu), used by the Eq. 2 source, the QUMOND monopole
+                                           boundary and force, and Eq. 3 */
 } qumond_config;
 
 typedef struct qumond_solve_info {
@@ -121,7 +126,8 @@ typedef struct qumond_ctx qumond_ctx;
 
 /* Fill *cfg with the paper's defaults for a single box of side 100 kpc and
  * n = 65: 2+2 sweeps and 6 V-cycles per FMG level (Sec. 2, Sec. 3.2),
- * monopole outer boundary, tol_rel 1e-10, gather_frac 0.2 (Sec. 3.1). */
+ * monopole outer boundary, tol_rel 1e-10, gather_frac 0.2 (Sec. 3.1), Eq. 2's
+ * nu (nu_n = 1). */
 void qumond_default_config(qumond_config *cfg);
 
 /* Check a configuration without touching the GPU.  Returns QUMOND_OK or

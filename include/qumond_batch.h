@@ -57,6 +57,7 @@ typedef struct {
     double gather_frac;   /* box choice of Eq. 4 points, default 0.2 (as qumond_config) */
     int32_t naz;          /* azimuths per radius of the curve, default 16 */
     int32_t autotune;     /* 1: time smoother shapes on the batch's own grids at the first run */
+    double nu_n;          /* interpolating function, as qumond_config.nu_n (default 1: Eq. 2's nu) */
 } qumond_batch_config;
 
 typedef struct {

@@ -7,10 +7,12 @@
 #include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <string>
 #include <thread>
+#include <vector>
 
 #include "../../include/qumond.h"
 #include "common.h"
@@ -76,6 +78,7 @@ struct qumond_ctx {
     double *scratch2 = nullptr;
     hipEvent_t ev_newton[QUMOND_MAX_BOX] = {};
     hipEvent_t ev_done = nullptr;
+    qm::NuFn nu;                         // interpolating function (+ device table for nu_n != 1)
     std::vector<void *> owned;
     int64_t bytes = 0;
 
@@ -89,6 +92,22 @@ struct qumond_ctx {
         return e;
     }
 };
+
+// The point-mass integral table of the n-family member cfg.nu_n (none for 1).
+static hipError_t qm_make_nu(double nu_n, qm::NuFn &nu, const std::function<hipError_t(void **, size_t)> &alloc)
+{
+    nu.n = nu_n;
+    nu.tab = nullptr;
+    if (nu_n == 1.0) return hipSuccess;
+    std::vector<double> tab(2 * (size_t)qm::kNuTab);
+    qm::build_nu_table(nu_n, tab.data());
+    double *d = nullptr;
+    hipError_t e = alloc((void **)&d, tab.size() * sizeof(double));
+    if (e != hipSuccess) return e;
+    if ((e = hipMemcpy(d, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) return e;
+    nu.tab = d;
+    return hipSuccess;
+}
 
 // Deposit scale 2^s with s = 62 - ceil(log2 M) - 1, so that the integer sum of
 // all corner shares stays below 2^62 (also used by the batched solver).
@@ -121,6 +140,7 @@ void qumond_default_config(qumond_config *cfg)
     cfg->gather_frac = 0.2;
     cfg->fixed_shift = 0;
     cfg->use_graphs = 0;
+    cfg->nu_n = 1.0;
 }
 
 qumond_status qumond_validate_config(const qumond_config *c)
@@ -149,6 +169,7 @@ qumond_status qumond_validate_config(const qumond_config *c)
     if (!(c->gather_frac > 0.0 && c->gather_frac < 0.5))
         return fail(QUMOND_ERR_INVALID, "gather_frac must be in (0, 0.5)");
     if (c->fixed_shift < 0 || c->fixed_shift > 120) return fail(QUMOND_ERR_INVALID, "fixed_shift must be in 0..120");
+    if (!(c->nu_n >= 1.0 && c->nu_n <= 10.0)) return fail(QUMOND_ERR_INVALID, "nu_n must be in [1, 10]");
     return QUMOND_OK;
 }
 
@@ -228,6 +249,11 @@ qumond_status qumond_create(const qumond_config *cfg, void *hip_stream, qumond_c
           (e = c->alloc((void **)&c->mix.r, c->N * sizeof(float))) != hipSuccess ||
           (e = c->alloc((void **)&c->mix.sc, 2 * sizeof(double))) != hipSuccess))) {
         qumond_status r = hip_fail(e, "qumond_create: allocation");
+        qumond_destroy(c);
+        return r;
+    }
+    if ((e = qm_make_nu(cfg->nu_n, c->nu, [c](void **p, size_t b) { return c->alloc(p, b); })) != hipSuccess) {
+        qumond_status r = hip_fail(e, "qumond_create: nu table");
         qumond_destroy(c);
         return r;
     }
@@ -364,7 +390,7 @@ static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int 
     double *f = mond ? B.S : B.f;
     if (b == 0) {
         const int mode = c.outer_bc == QUMOND_BC_ZERO ? 0 : (mond ? 2 : 1);
-        qm::launch_bc_outer(ctx->n, B.L, mode, GM, c.a0, u, ch.scratch, ch.s);
+        qm::launch_bc_outer(ctx->n, B.L, mode, GM, c.a0, u, ch.scratch, ch.s, ctx->nu);
     } else {
         const double *uc = mond ? ctx->box[b - 1].phi : ctx->box[b - 1].phin;
         qm::launch_bc_from_coarse(ctx->n, uc, u, ch.scratch, ch.s);
@@ -428,7 +454,7 @@ static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int 
         qm::launch_fill<double>(u, ctx->N, 0.0, ch.s);
         if (b == 0) {
             const int mode = c.outer_bc == QUMOND_BC_ZERO ? 0 : (mond ? 2 : 1);
-            qm::launch_bc_outer(ctx->n, B.L, mode, GM, c.a0, u, ch.scratch, ch.s);
+            qm::launch_bc_outer(ctx->n, B.L, mode, GM, c.a0, u, ch.scratch, ch.s, ctx->nu);
         } else {
             const double *uc = mond ? ctx->box[b - 1].phi : ctx->box[b - 1].phin;
             qm::launch_bc_from_coarse(ctx->n, uc, u, ch.scratch, ch.s);
@@ -507,7 +533,8 @@ qumond_status qumond_mond_source(qumond_ctx *ctx)
     if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
     if (ctx->stage < ST_NEWTON) return fail(QUMOND_ERR_STATE, "qumond_mond_source before qumond_solve_newton");
     for (int b = 0; b < ctx->cfg.nbox; ++b)
-        qm::launch_mond_source(ctx->n, ctx->box[b].h, ctx->cfg.a0, ctx->box[b].phin, ctx->box[b].S, ctx->s);
+        qm::launch_mond_source(ctx->n, ctx->box[b].h, ctx->cfg.a0, ctx->box[b].phin, ctx->box[b].S, ctx->s, 1,
+                              ctx->cfg.nu_n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "qumond_mond_source: launch");
     ctx->stage = ST_SOURCE;
@@ -590,7 +617,8 @@ qumond_status qumond_solve(qumond_ctx *ctx, qumond_solve_info *info_newton, qumo
                 err_m = g_last_error;
                 return;
             }
-            qm::launch_mond_source(ctx->n, ctx->box[b].h, ctx->cfg.a0, ctx->box[b].phin, ctx->box[b].S, ctx->s2);
+            qm::launch_mond_source(ctx->n, ctx->box[b].h, ctx->cfg.a0, ctx->box[b].phin, ctx->box[b].S, ctx->s2, 1,
+                                  ctx->cfg.nu_n);
             bool ok = true;
             st_m = solve_box(ctx, ch, true, b, info_mond, ok);
             if (st_m != QUMOND_OK) {
@@ -649,6 +677,7 @@ static qm::GatherArgs gather_args(const qumond_ctx *ctx, int which)
     a.a0 = ctx->cfg.a0;
     a.mond = which == QUMOND_WHICH_QUMOND;
     a.alg = which == QUMOND_WHICH_ALGEBRAIC;
+    a.nun = ctx->cfg.nu_n;
     return a;
 }
 

@@ -85,6 +85,7 @@ struct qumond_batch {
     std::vector<int> has_particles;
     double *R = nullptr;
     int nR = 0;
+    qm::NuFn nu;                  // interpolating function (+ device table for nu_n != 1)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     size_t graph_nodes = 0;
@@ -146,7 +147,7 @@ void enqueue_solve(const qumond_batch *B, Class &C, qm::Multigrid<float> &mg, bo
     double *u = (mond ? C.phi : C.phin) + (size_t)p0 * C.N;
     const double *f = (mond ? C.S : C.f) + (size_t)p0 * C.N;
     const size_t cnt = (size_t)nb * C.N;
-    qm::launch_bc_outer_batch(C.n, c.box_side, mond ? 2 : 1, c.G, c.a0, C.prob + p0, u, nb, s);
+    qm::launch_bc_outer_batch(C.n, c.box_side, mond ? 2 : 1, c.G, c.a0, C.prob + p0, u, nb, s, B->nu);
     qm::launch_narrow(f, C.r, cnt, s);
     qm::launch_narrow_boundary(C.n, u, C.a[0], C.a[1], s, nb);
     mg.bind(c.box_side, C.a[0], C.a[1], C.r);
@@ -172,7 +173,7 @@ void enqueue_curves(const qumond_batch *B, Class &C, int p0, int nb, int which, 
         if (which >= 0 && w != which) continue;
         qm::launch_rotation_curve_batch(C.n, c.box_side, c.gather_frac, c.G, c.a0, w, C.prob + p0,
                                         (w ? C.phi : C.phin) + (size_t)p0 * C.N, B->R, B->nR, c.naz,
-                                        C.vc2[w] + (size_t)p0 * B->nR, nb, s);
+                                        C.vc2[w] + (size_t)p0 * B->nR, nb, s, c.nu_n);
     }
 }
 
@@ -185,7 +186,7 @@ void enqueue_class(const qumond_batch *B, Class &C, hipStream_t s)
     qm::launch_deposit_batch(C.n, c.box_side, C.prob, 0, (unsigned long long *)C.q, C.dep, C.inside, C.P, s);
     qm::launch_rhs_batch(C.n, C.h, 4.0 * M_PI * c.G, C.prob, C.q, C.f, C.P, s);
     enqueue_solve(B, C, C.mg, false, 0, C.P, K_of(B), s);
-    qm::launch_mond_source(C.n, C.h, c.a0, C.phin, C.S, s, C.P);
+    qm::launch_mond_source(C.n, C.h, c.a0, C.phin, C.S, s, C.P, c.nu_n);
     enqueue_solve(B, C, C.mg, true, 0, C.P, K_of(B), s);
     enqueue_curves(B, C, 0, C.P, -1, s);
     (void)hipMemcpyAsync(C.hinside, C.inside, (size_t)C.P * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
@@ -379,6 +380,7 @@ void qumond_batch_default_config(qumond_batch_config *cfg)
     cfg->gather_frac = 0.2;
     cfg->naz = 16;
     cfg->autotune = 0;
+    cfg->nu_n = 1.0;
 }
 
 qumond_status qumond_batch_validate(const qumond_batch_config *c, const int32_t *n_per_problem, const double *R,
@@ -401,6 +403,7 @@ qumond_status qumond_batch_validate(const qumond_batch_config *c, const int32_t 
         return bfail(QUMOND_ERR_INVALID, "gather_frac must be in (0, 0.5)");
     if (c->naz < 1 || c->naz > 1024) return bfail(QUMOND_ERR_INVALID, "naz must be in 1..1024");
     if (c->autotune != 0 && c->autotune != 1) return bfail(QUMOND_ERR_INVALID, "autotune must be 0 or 1");
+    if (!(c->nu_n >= 1.0 && c->nu_n <= 10.0)) return bfail(QUMOND_ERR_INVALID, "nu_n must be in [1, 10]");
     if (nR < 1 || nR > 4096 || !R) return bfail(QUMOND_ERR_INVALID, "need 1 <= nR <= 4096 radii");
     for (int i = 0; i < nR; ++i)
         if (!(R[i] >= 0.0) || !std::isfinite(R[i])) return bfail(QUMOND_ERR_INVALID, "radii must be finite and >= 0");
@@ -465,6 +468,15 @@ qumond_status qumond_batch_create(const qumond_batch_config *cfg, const int32_t 
     BCHK(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
     BCHK(B->alloc((void **)&B->R, (size_t)nR * sizeof(double)));
     BCHK(hipMemcpy(B->R, R, (size_t)nR * sizeof(double), hipMemcpyHostToDevice));
+    B->nu.n = cfg->nu_n;
+    if (cfg->nu_n != 1.0) {
+        std::vector<double> tab(2 * (size_t)qm::kNuTab);
+        qm::build_nu_table(cfg->nu_n, tab.data());
+        double *d = nullptr;
+        BCHK(B->alloc((void **)&d, tab.size() * sizeof(double)));
+        BCHK(hipMemcpy(d, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+        B->nu.tab = d;
+    }
     for (auto &cp : B->cls) {
         Class &C = *cp;
         const size_t PN = (size_t)C.P * C.N;
@@ -621,7 +633,8 @@ qumond_status qumond_batch_run(qumond_batch *b, int32_t use_graph, qumond_batch_
                 if (sn > 0) {
                     // the QUMOND part depends on Phi_N: redo it for this problem
                     qm::Multigrid<float> mg = single_view(C);
-                    qm::launch_mond_source(C.n, C.h, b->cfg.a0, C.phin + (size_t)sl * C.N, C.S + (size_t)sl * C.N, C.s, 1);
+                    qm::launch_mond_source(C.n, C.h, b->cfg.a0, C.phin + (size_t)sl * C.N, C.S + (size_t)sl * C.N, C.s, 1,
+                                           b->cfg.nu_n);
                     enqueue_solve(b, C, mg, true, sl, 1, K, C.s);
                     enqueue_curves(b, C, sl, 1, -1, C.s);
                     double *hm = C.hhist + (((size_t)1 * (K + 1) + K) * C.P + sl) * 3;

@@ -15,6 +15,51 @@ __host__ __device__ __forceinline__ size_t id3(int n, int i, int j, int k)
     return (size_t)i + (size_t)n * ((size_t)j + (size_t)n * (size_t)k);
 }
 
+// ------------------------------------------------------------ nu
+// The interpolating function.  n == 1 is Eq. 2's nu(y) = 1/2 + 1/2 sqrt(1 + 4/y),
+// evaluated by the closed expressions in each kernel; any other n is the
+// n-family nu_n(y) = [(1 + sqrt(1 + 4 y^-n)) / 2]^(1/n) (n = 2: the "standard"
+// function).  The point-mass QUMOND potential for n != 1 is
+// -GM/r + sqrt(G M a0) I(r / r_M), r_M = sqrt(G M / a0), with the universal
+// I(t) = int_0^t (nu_n(1/s^2) - 1) / s^2 ds tabulated at u = ln t on a uniform
+// grid (values and exact slopes dI/du, cubic Hermite in between).
+constexpr int kNuTab = 10241;
+constexpr double kNuU0 = -20.0, kNuDu = 1.0 / 256.0;
+
+struct NuFn {
+    double n = 1.0;
+    const double *tab = nullptr;  // device, [kNuTab][2] = {I, dI/du}; only for n != 1
+};
+
+__host__ __device__ inline double nu_family(double y, double n)
+{
+    return pow(0.5 * (1.0 + sqrt(1.0 + 4.0 * pow(y, -n))), 1.0 / n);
+}
+
+// I(t) from the table; below the table the leading term t^(2n-1) / (n (2n-1)),
+// above it the end slope continued (I grows like ln t there).
+__device__ inline double nu_point_integral(const NuFn &nu, double t)
+{
+#pragma clang fp contract(off)
+    const double u = log(t);
+    const double n = nu.n;
+    if (u <= kNuU0) return pow(t, 2.0 * n - 1.0) / (n * (2.0 * n - 1.0));
+    const double x = (u - kNuU0) / kNuDu;
+    int k = (int)x;
+    if (k >= kNuTab - 1) {
+        const double *e = nu.tab + 2 * (kNuTab - 1);
+        return e[0] + e[1] * (u - (kNuU0 + (kNuTab - 1) * kNuDu));
+    }
+    const double s = x - (double)k;
+    const double *a = nu.tab + 2 * k;
+    const double s2 = s * s, s3 = s2 * s;
+    return (2.0 * s3 - 3.0 * s2 + 1.0) * a[0] + (s3 - 2.0 * s2 + s) * kNuDu * a[1] + (3.0 * s2 - 2.0 * s3) * a[2] +
+           (s3 - s2) * kNuDu * a[3];
+}
+
+// Host: fills tab[kNuTab][2] for the n-family member n (n >= 1).
+void build_nu_table(double n, double *tab);
+
 // Geometry of one box as the particle kernels see it.
 struct BoxGeom {
     double L;       // side, kpc
@@ -46,6 +91,7 @@ struct GatherArgs {
     double frac, GM, a0;
     int mond;  // monopole of points outside every box: 0 Newtonian, 1 QUMOND
     int alg;   // 1: Eq. 3 applied to the gathered (Newtonian) field
+    double nun;  // interpolating function (NuFn::n)
 };
 
 // One problem of a batch as its kernels read it from device memory, so that a
@@ -136,12 +182,13 @@ void launch_guess_interior(int n, const void *g, int kind, double *u, hipStream_
 
 // ---- bc_kernels.hip
 // mode 0 zero, 1 Newtonian monopole -GM/r, 2 QUMOND monopole.
-void launch_bc_outer(int n, double L, int mode, double GM, double a0, double *u0, double *u1, hipStream_t s);
+void launch_bc_outer(int n, double L, int mode, double GM, double a0, double *u0, double *u1, hipStream_t s,
+                     const NuFn &nu = NuFn());
 // Mode 1 or 2 at every node with r -> sqrt(r^2 + soft^2) (n^3 doubles).
 void launch_monopole_field(int n, double L, int mode, double GM, double a0, double soft, double *out, hipStream_t s);
 // The same for nb problems (back to back), GM = G * prob[p].mass.
 void launch_bc_outer_batch(int n, double L, int mode, double G, double a0, const BatchProblem *prob, double *u0,
-                           int nb, hipStream_t s);
+                           int nb, hipStream_t s, const NuFn &nu = NuFn());
 void launch_bc_from_coarse(int n, const double *uc, double *u0, double *u1, hipStream_t s);
 
 // ---- particle_kernels.hip
@@ -167,9 +214,10 @@ void launch_rhs_batch(int n, double h, double four_pi_G, const BatchProblem *pro
 // force G prob[p].mass beyond the box; mond selects the QUMOND monopole).
 void launch_rotation_curve_batch(int n, double L, double frac, double G, double a0, int mond,
                                  const BatchProblem *prob, const double *phi, const double *R, int nR, int naz,
-                                 double *vc2, int nb, hipStream_t s);
+                                 double *vc2, int nb, hipStream_t s, double nun = 1.0);
 
 // ---- source_kernel.hip
-void launch_mond_source(int n, double h, double a0, const double *phin, double *S, hipStream_t s, int nb = 1);
+void launch_mond_source(int n, double h, double a0, const double *phin, double *S, hipStream_t s, int nb = 1,
+                        double nun = 1.0);
 
 }  // namespace qm

@@ -265,16 +265,23 @@ __device__ __forceinline__ double node_accel(const double *__restrict__ P, int n
     return -g * inv2h;
 }
 
+// nu(y) with y = g / a0 (g > 0, a0 > 0): Eq. 2's function for nun == 1, else the n-family.
+__device__ __forceinline__ double nu_of_g(double g, double a0, double nun)
+{
+#pragma clang fp contract(off)
+    return nun == 1.0 ? 0.5 + 0.5 * sqrt(1.0 + 4.0 * a0 / g) : nu_family(g / a0, nun);
+}
+
 // Point-mass force (QUMOND: nu(g_N/a0) g_N) for points outside every box.
-__device__ __forceinline__ void monopole_accel(double GM, double a0, int mond, double px, double py, double pz,
-                                               double acc[3])
+__device__ __forceinline__ void monopole_accel(double GM, double a0, int mond, double nun, double px, double py,
+                                               double pz, double acc[3])
 {
 #pragma clang fp contract(off)
     const double r = sqrt(px * px + py * py + pz * pz);
     double g = 0.0;
     if (r > 0.0) {
         const double gN = GM / (r * r);
-        g = (mond && a0 > 0.0) ? (0.5 + 0.5 * sqrt(1.0 + 4.0 * a0 / gN)) * gN : gN;
+        g = (mond && a0 > 0.0 && gN > 0.0) ? nu_of_g(gN, a0, nun) * gN : gN;
         g /= r;
     }
     acc[0] = -g * px;
@@ -315,12 +322,12 @@ __device__ void box_accel(const BoxGeom &G, int n, const double *__restrict__ P,
 }
 
 // Eq. 3, the algebraic MOND relation: g = nu(|g_N| / a0) g_N at the point.
-__device__ __forceinline__ void algebraic_mond(double a0, double acc[3])
+__device__ __forceinline__ void algebraic_mond(double a0, double nun, double acc[3])
 {
 #pragma clang fp contract(off)
     const double g = sqrt(acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2]);
     if (g > 0.0 && a0 > 0.0) {
-        const double k = 0.5 + 0.5 * sqrt(1.0 + 4.0 * a0 / g);
+        const double k = nu_of_g(g, a0, nun);
         acc[0] *= k;
         acc[1] *= k;
         acc[2] *= k;
@@ -338,9 +345,9 @@ __device__ int gather_point(const GatherArgs &A, double px, double py, double pz
         for (int b = 0; b < A.nbox; ++b)
             if (in_box(A.box[b], A.n, px, py, pz)) { sel = b; break; }
     }
-    if (sel < 0) monopole_accel(A.GM, A.a0, A.mond, px, py, pz, acc);
+    if (sel < 0) monopole_accel(A.GM, A.a0, A.mond, A.nun, px, py, pz, acc);
     else box_accel(A.box[sel], A.n, A.phi[sel], px, py, pz, acc);
-    if (A.alg) algebraic_mond(A.a0, acc);
+    if (A.alg) algebraic_mond(A.a0, A.nun, acc);
     return sel < 0 ? 255 : sel;
 }
 
@@ -436,7 +443,7 @@ void launch_sigma_z(const GatherArgs &a, const double *R, int nR, int naz, doubl
 
 // Batched single-box curves: workgroup (r, p), same sampling and order as rotation_curve_k.
 __global__ void __launch_bounds__(256)
-rotation_curve_batch_k(int n, BoxGeom G, double frac, double Gc, double a0, int mond,
+rotation_curve_batch_k(int n, BoxGeom G, double frac, double Gc, double a0, int mond, double nun,
                        const BatchProblem *__restrict__ prob, const double *__restrict__ phi, const double *__restrict__ R,
                        int nR, int naz, double *__restrict__ vc2)
 {
@@ -454,7 +461,7 @@ rotation_curve_batch_k(int n, BoxGeom G, double frac, double Gc, double a0, int 
         // the box-choice rule of gather_point with one box
         const double Rp = sqrt(px * px + py * py);
         if ((Rp < frac * G.L && 0.0 < frac * G.L) || in_box(G, n, px, py, 0.0)) box_accel(G, n, P, px, py, 0.0, acc);
-        else monopole_accel(GM, a0, mond, px, py, 0.0, acc);
+        else monopole_accel(GM, a0, mond, nun, px, py, 0.0, acc);
         s += -(px * acc[0] + py * acc[1]);
     }
     sh[threadIdx.x] = s;
@@ -468,7 +475,7 @@ rotation_curve_batch_k(int n, BoxGeom G, double frac, double Gc, double a0, int 
 
 void launch_rotation_curve_batch(int n, double L, double frac, double G, double a0, int mond,
                                  const BatchProblem *prob, const double *phi, const double *R, int nR, int naz,
-                                 double *vc2, int nb, hipStream_t s)
+                                 double *vc2, int nb, hipStream_t s, double nun)
 {
     if (nR <= 0 || nb <= 0) return;
     BoxGeom g;
@@ -476,8 +483,8 @@ void launch_rotation_curve_batch(int n, double L, double frac, double G, double 
     g.xmin = -0.5 * L;
     g.inv_h = (double)(n - 1) / L;
     g.h = L / (double)(n - 1);
-    hipLaunchKernelGGL(rotation_curve_batch_k, dim3(nR, nb), dim3(256), 0, s, n, g, frac, G, a0, mond, prob, phi, R, nR,
-                       naz, vc2);
+    hipLaunchKernelGGL(rotation_curve_batch_k, dim3(nR, nb), dim3(256), 0, s, n, g, frac, G, a0, mond, nun, prob, phi,
+                       R, nR, naz, vc2);
 }
 
 }  // namespace qm

@@ -48,12 +48,14 @@ class CurveBatch:
     run of one batch of single-box problems (n^3 grid, box_side kpc)."""
 
     def __init__(self, size: int = 64, n: int = 129, box_side: float = 120.0, r_max: float = 36.0, dr: float = 0.1,
-                 n_particles: int = 500_000, refine_iters: int = 3):
+                 n_particles: int = 500_000, refine_iters: int = 3, nu_n: float = 1.0, a0: float = 3600.0):
+        """nu_n and a0 choose the MOND interpolating function (1: Eq. 2's nu,
+        else the n-family) and acceleration constant of every model."""
         self.size = size
         self.n_particles = n_particles
         self.R = np.arange(dr, r_max + 0.5 * dr, dr)
-        self.batch = Q.Batch(Q.BatchConfig(box_side=box_side, refine_iters=refine_iters, autotune=True),
-                             [n] * size, self.R)
+        self.batch = Q.Batch(Q.BatchConfig(box_side=box_side, refine_iters=refine_iters, autotune=True, nu_n=nu_n,
+                                           a0=a0), [n] * size, self.R)
         self.seconds = 0.0
         self.runs = 0
 

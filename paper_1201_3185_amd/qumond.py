@@ -36,7 +36,7 @@ class qumond_config(ctypes.Structure):
         ("G", ctypes.c_double), ("a0", ctypes.c_double), ("npre", ctypes.c_int32), ("npost", ctypes.c_int32),
         ("ncycle_fmg", ctypes.c_int32), ("max_vcycles", ctypes.c_int32), ("tol_rel", ctypes.c_double),
         ("precision", ctypes.c_int32), ("outer_bc", ctypes.c_int32), ("gather_frac", ctypes.c_double),
-        ("fixed_shift", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
+        ("fixed_shift", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("nu_n", ctypes.c_double),
     ]
 
 
@@ -60,6 +60,7 @@ class qumond_batch_config(ctypes.Structure):
         ("npre", ctypes.c_int32), ("npost", ctypes.c_int32), ("ncycle_fmg", ctypes.c_int32),
         ("refine_iters", ctypes.c_int32), ("max_extra", ctypes.c_int32), ("tol_rel", ctypes.c_double),
         ("gather_frac", ctypes.c_double), ("naz", ctypes.c_int32), ("autotune", ctypes.c_int32),
+        ("nu_n", ctypes.c_double),
     ]
 
 
@@ -192,6 +193,7 @@ class Config:
     gather_frac: float = 0.2
     fixed_shift: int = 0
     use_graphs: int = 0
+    nu_n: float = 1.0            # 1: Eq. 2's nu; else the n-family member (2: the standard nu)
 
     def to_c(self) -> qumond_config:
         c = qumond_config()
@@ -202,6 +204,7 @@ class Config:
         c.ncycle_fmg, c.max_vcycles, c.tol_rel = self.ncycle_fmg, self.max_vcycles, self.tol_rel
         c.precision, c.outer_bc, c.gather_frac = self.precision, self.outer_bc, self.gather_frac
         c.fixed_shift, c.use_graphs = self.fixed_shift, self.use_graphs
+        c.nu_n = float(self.nu_n)
         return c
 
 
@@ -580,6 +583,7 @@ class BatchConfig:
     gather_frac: float = 0.2
     naz: int = 16
     autotune: bool = False
+    nu_n: float = 1.0
 
     def to_c(self, nprob: int) -> qumond_batch_config:
         c = qumond_batch_config()
@@ -590,6 +594,7 @@ class BatchConfig:
         for k in ("npre", "npost", "ncycle_fmg", "refine_iters", "max_extra", "naz"):
             setattr(c, k, int(getattr(self, k)))
         c.autotune = int(bool(self.autotune))
+        c.nu_n = float(self.nu_n)
         return c
 
 

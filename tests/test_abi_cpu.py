@@ -54,7 +54,8 @@ def test_default_config_is_the_papers(Q):
     dict(n=64), dict(n=3), dict(n=2049), dict(box_side=[]), dict(box_side=[100.0, 60.0]),
     dict(box_side=[-1.0]), dict(G=0.0), dict(a0=-1.0), dict(npre=0, npost=0), dict(npre=9),
     dict(ncycle_fmg=0), dict(max_vcycles=-1), dict(tol_rel=-1e-3), dict(precision=7), dict(outer_bc=3),
-    dict(gather_frac=0.5), dict(gather_frac=0.0), dict(fixed_shift=-2),
+    dict(gather_frac=0.5), dict(gather_frac=0.0), dict(fixed_shift=-2), dict(nu_n=0.5), dict(nu_n=10.5),
+    dict(nu_n=float("nan")),
 ])
 def test_invalid_configs_rejected_without_gpu(Q, change):
     cfg = Q.Config(**change)
@@ -70,6 +71,10 @@ def test_valid_nested_configs(Q):
     assert Q.validate_config(Q.Config(n=129, box_side=[400.0, 200.0, 100.0, 50.0])) == Q.QUMOND_OK
     assert Q.validate_config(Q.Config(n=5, box_side=[1.0])) == Q.QUMOND_OK
     assert Q.validate_config(Q.Config(n=513, box_side=[120.0], precision=Q.QUMOND_MIXED)) == Q.QUMOND_OK
+    assert Q.validate_config(Q.Config(nu_n=2.0)) == Q.QUMOND_OK
+    c = Q.qumond_config()
+    Q.lib().qumond_default_config(ctypes.byref(c))
+    assert c.nu_n == 1.0
 
 
 def test_null_handles_and_arguments(Q):
@@ -105,7 +110,7 @@ def test_batch_defaults(Q):
     ([129], [float("nan")], {}), ([257] * 600, [1.0], {}), ([129], [1.0], dict(box_side=0.0)),
     ([129], [1.0], dict(G=-1.0)), ([129], [1.0], dict(npre=0, npost=0)), ([129], [1.0], dict(ncycle_fmg=0)),
     ([129], [1.0], dict(refine_iters=-1)), ([129], [1.0], dict(max_extra=-1)), ([129], [1.0], dict(tol_rel=-1.0)),
-    ([129], [1.0], dict(gather_frac=0.6)), ([129], [1.0], dict(naz=0)),
+    ([129], [1.0], dict(gather_frac=0.6)), ([129], [1.0], dict(naz=0)), ([129], [1.0], dict(nu_n=0.9)),
 ])
 def test_batch_invalid_rejected_without_gpu(Q, ns, R, change):
     cfg = Q.BatchConfig(**change)

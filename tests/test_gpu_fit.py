@@ -63,3 +63,14 @@ def test_truth_scores_best(search):
                 fit.Params(0.8, 1.0, 0.3, 0.15)):
         assert table[off] > c_truth + 3.0, off
     assert table[fit.Params(1.0, 1.0, 0.6, 0.15)] > c_truth
+
+
+def test_standard_nu_needs_more_mass(search):
+    cb, best, c_best, table = search
+    cb2 = fit.CurveBatch(size=32, n=129, box_side=120.0, n_particles=400_000, nu_n=2.0)
+    v_obs, sig = fit.observe(cb, TRUTH, R_OBS)
+    axes = {"dist": [1.0], "ml": [0.9, 1.0, 1.1, 1.2, 1.3, 1.4, 1.5], "z_star": [0.3], "z_gas": [0.15]}
+    best2, c2, _ = fit.grid_search(cb2, axes, R_OBS, v_obs, sig)
+    print(f"standard nu: best {best2} chi2/n {c2:.3f}")
+    assert best2.ml > 1.0
+    cb2.close()
