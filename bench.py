@@ -297,6 +297,8 @@ def main():
     ap.add_argument("--save-tune", default=None, help="write the autotuned smoother table to this JSON file")
     ap.add_argument("--tune-table", default=None, help="load the smoother table from this JSON file instead of "
                                                        "autotuning (to replay the same launches under a profiler)")
+    ap.add_argument("--graphs", type=int, default=0,
+                    help="1: the nested step replays its FMG schedules from captured HIP graphs (use_graphs); 0: eager")
     ap.add_argument("--batch-profile", action="store_true",
                     help="run only the batched-fit leg (for a kernel trace of its replays) and print its record")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -339,14 +341,17 @@ def main():
         log("autotuning smoother launch shapes (setup, not timed)")
         Q.autotune(n_max=n, both=False, reps=5, json_path=args.save_tune)
     shapes = {str(k): {"single": Q.tune_get(k), "fused": Q.tune_get_fused(k)} for k in (33, 65, 129)}
-    cfg = Q.Config(n=n, box_side=sides, tol_rel=1e-10)
-    ctx = Q.Context(cfg)
+    cfg = Q.Config(n=n, box_side=sides, tol_rel=1e-10, use_graphs=args.graphs)
+    stream = torch.cuda.Stream()            # graphs are captured on a stream of the step's own
+    stream.wait_stream(torch.cuda.current_stream())
+    ctx = Q.Context(cfg, stream=stream)
     infos = {}
 
     def step():
-        ctx.deposit(x, y, z, m, M, count_outside=False)
-        infos["newton"], infos["mond"] = ctx.solve()   # source + both FMG chains, overlapped
-        return ctx.gather_forces(x, y, z, 1, with_box=False)
+        with torch.cuda.stream(stream):
+            ctx.deposit(x, y, z, m, M, count_outside=False)
+            infos["newton"], infos["mond"] = ctx.solve()   # source + both FMG chains, overlapped
+            return ctx.gather_forces(x, y, z, 1, with_box=False)
 
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -421,7 +426,7 @@ def main():
         "config": {"workload": "two-component exponential disk, 1e6 particles, 4 nested 129^3 boxes "
                                "(400/200/100/50 kpc), monopole outer BC, FP64 FMG to 1e-10",
                    "n": n, "boxes_kpc": sides, "particles": npart, "tol_rel": 1e-10, "ncycle_fmg": 6,
-                   "npre": 2, "npost": 2, "precision": "fp64"},
+                   "npre": 2, "npost": 2, "precision": "fp64", "graphs": bool(args.graphs)},
         "vcycles_after_fmg": {"newton": infos["newton"]["vcycles"], "mond": infos["mond"]["vcycles"]},
         "smoother_shapes": shapes,
         "mixed_vs_fp64_513": mixed,

@@ -104,7 +104,10 @@ typedef struct qumond_config {
     int32_t outer_bc;                   /* qumond_outer_bc, Dirichlet value on the outermost box */
     double gather_frac;                 /* box choice: finest box with R, |z| < gather_frac * L_b, in (0, 0.5) */
     int32_t fixed_shift;                /* deposit scale exponent s (q = rint(w m 2^s)); 0 = from total mass */
-    int32_t use_graphs;                 /* 1: replay the fixed FMG schedule from captured HIP graphs */
+    int32_t use_graphs;                 /* 1: FP64 solves without a guess replay the FMG schedule and each
+                                           extra finest V-cycle (with its residual norms) from HIP graphs
+                                           captured on first use per box and chain (on a context created with
+                                           a non-NULL stream); results are identical */
     double nu_n;                        /* interpolating function (Sec. 2 allows other forms of nu): 1 = Eq. 2's
                                            nu(y) = 1/2 + 1/2 sqrt(1 + 4/y) (default); otherwise, 1 < nu_n <= 10,
                                            the n-family nu_n(y) = [(1 + sqrt(1 + 4 y^-n)) / 2]^(1/n) (2: the

@@ -481,13 +481,15 @@ static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int 
         }
         if (info) info->refine_iters[b] = extra;
     } else {
-        ch.mg->fmg(c.ncycle_fmg);
-        if ((e = ch.mg->relres(rr)) != hipSuccess) return hip_fail(e, "solve: FMG");
+        // the fixed schedules run from captured graphs when cfg.use_graphs is set
+        ch.mg->use_graphs = c.use_graphs != 0;
+        if ((e = ch.mg->fmg_norms(c.ncycle_fmg)) != hipSuccess || (e = ch.mg->relres_read(rr)) != hipSuccess)
+            return hip_fail(e, "solve: FMG");
         rr0 = rr;
         while (c.tol_rel > 0.0 && rr > c.tol_rel && extra < c.max_vcycles) {
-            ch.mg->finest_cycle();
             ++extra;
-            if ((e = ch.mg->relres(rr)) != hipSuccess) return hip_fail(e, "solve: V-cycle");
+            if ((e = ch.mg->cycle_norms()) != hipSuccess || (e = ch.mg->relres_read(rr)) != hipSuccess)
+                return hip_fail(e, "solve: V-cycle");
         }
         ch.mg->finish();
     }
@@ -599,11 +601,28 @@ qumond_status qumond_solve(qumond_ctx *ctx, qumond_solve_info *info_newton, qumo
     std::mutex mu;
     std::condition_variable cv;
     int newton_done = 0;
+    int mond_waited = 0;        // boxes whose Newtonian event the QUMOND stream already waits on
+    bool worker_exited = false;
     bool abort = false;
     qumond_status st_m = QUMOND_OK;
     std::string err_m;
     bool ok_m = true;
+    // With graph capture, a stream may not wait on an event of a stream that is
+    // capturing: the Newtonian chain starts its next box (and capture) only after
+    // the QUMOND stream has enqueued its wait on the previous box's event.
+    const bool handshake = ctx->cfg.use_graphs != 0;
     std::thread worker([&]() {
+        struct Exit {
+            std::mutex &mu;
+            std::condition_variable &cv;
+            bool &flag;
+            ~Exit()
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                flag = true;
+                cv.notify_all();
+            }
+        } on_exit{mu, cv, worker_exited};
         const Chain ch{&ctx->mg2, ctx->s2, ctx->scratch2, &ctx->mix2};
         for (int b = 0; b < nbox; ++b) {
             {
@@ -612,6 +631,11 @@ qumond_status qumond_solve(qumond_ctx *ctx, qumond_solve_info *info_newton, qumo
                 if (newton_done <= b) return;   // the Newtonian chain failed
             }
             hipError_t we = hipStreamWaitEvent(ctx->s2, ctx->ev_newton[b], 0);
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                mond_waited = b + 1;
+                cv.notify_all();
+            }
             if (we != hipSuccess) {
                 st_m = hip_fail(we, "qumond_solve: wait");
                 err_m = g_last_error;
@@ -638,9 +662,10 @@ qumond_status qumond_solve(qumond_ctx *ctx, qumond_solve_info *info_newton, qumo
             st_n = hip_fail(e, "qumond_solve: record");
         if (st_n != QUMOND_OK) break;
         ok_n = ok_n && ok;
-        std::lock_guard<std::mutex> lk(mu);
+        std::unique_lock<std::mutex> lk(mu);
         newton_done = b + 1;
         cv.notify_all();
+        if (handshake && b + 1 < nbox) cv.wait(lk, [&] { return mond_waited > b || worker_exited; });
     }
     {
         std::lock_guard<std::mutex> lk(mu);

@@ -11,6 +11,13 @@
 //
 // A hierarchy can hold nb problems of the same size back to back on every
 // level; each launch then covers all of them.
+//
+// With graphs enabled, the FMG schedule and the finest-level cycle (each with
+// the residual norms copied to pinned host memory at its end) are captured once
+// per (finest buffers, ping-pong state, launch shapes) and replayed: the
+// schedule has no host decisions, so a replay runs exactly the launches of an
+// eager run.  The host-side ping-pong state after the capture is recorded and
+// restored at every replay.
 #pragma once
 #include <cmath>
 #include <vector>
@@ -92,6 +99,17 @@ struct Multigrid {
     SmootherProfile prof;
     bool fused = true;   // two sweeps per launch where possible
     double last_r2 = 0.0;  // sum of squared residuals of the last relres()
+    bool use_graphs = false;   // replay fmg_norms / cycle_norms from captured graphs
+
+    struct GraphEntry {
+        int kind;                        // 0: FMG + norms, 1: finest cycle + norms
+        const void *u0, *u1, *f;         // finest buffers the schedule was captured on
+        unsigned cur_in, cur_out;        // ping-pong state before / after
+        int ncycle;
+        std::vector<int> sig;            // launch shapes in force at capture
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
 
     hipError_t alloc(void **p, size_t b)
     {
@@ -132,6 +150,8 @@ struct Multigrid {
 
     void release()
     {
+        for (GraphEntry &g : graphs) (void)hipGraphExecDestroy(g.exec);
+        graphs.clear();
         prof.release();
         for (void *p : owned) (void)hipFree(p);
         owned.clear();
@@ -253,6 +273,97 @@ struct Multigrid {
     {
         device_norms();
         (void)hipMemcpyAsync(host_norms, norms, 3 * (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, s);
+    }
+
+    unsigned cur_mask() const
+    {
+        unsigned m = 0;
+        for (int l = 1; l <= J; ++l) m |= (unsigned)lv[l].cur << l;
+        return m;
+    }
+    void set_cur(unsigned m)
+    {
+        for (int l = 1; l <= J; ++l) lv[l].cur = (int)((m >> l) & 1u);
+    }
+
+    // The launch shapes a schedule of this hierarchy uses.
+    std::vector<int> shape_sig() const
+    {
+        std::vector<int> v;
+        for (int l = lt; l <= J; ++l) {
+            const int n = lv[l].n;
+            const SmootherShape a = shapes ? shapes->single[l] : rbgs_shape<T>(n);
+            const SmootherShape b = shapes ? shapes->fused[l] : rbgs2_shape<T>(n);
+            const int uf = shapes ? shapes->use_fused[l] : use_fused<T>(n);
+            const int rr = shapes ? shapes->rr[l] : rr_variant<T>(n);
+            v.insert(v.end(), {a.variant, a.kchunk, b.variant, b.kchunk, uf, rr});
+        }
+        v.insert(v.end(), {fused ? 1 : 0, npre, npost});
+        return v;
+    }
+
+    // Enqueue body() (kind 0: fmg(ncycle), 1: finest_cycle(), each followed by
+    // enqueue_norms()), from a captured graph when graphs are on and the
+    // smoother is not being timed.
+    template <class Body>
+    hipError_t enqueue_schedule(int kind, int ncycle, Body body)
+    {
+        if (!use_graphs || prof.on || s == nullptr) {   // the null stream cannot be captured
+            body();
+            enqueue_norms();
+            return hipSuccess;
+        }
+        const unsigned cin = cur_mask();
+        const std::vector<int> sig = shape_sig();
+        for (size_t i = 0; i < graphs.size(); ++i) {
+            GraphEntry &g = graphs[i];
+            if (g.kind != kind || g.u0 != lv[J].u[0] || g.u1 != lv[J].u[1] || g.f != lv[J].f || g.cur_in != cin ||
+                g.ncycle != ncycle)
+                continue;
+            if (g.sig != sig) {   // shapes changed since the capture
+                (void)hipGraphExecDestroy(g.exec);
+                graphs.erase(graphs.begin() + (long)i);
+                break;
+            }
+            set_cur(g.cur_out);
+            return hipGraphLaunch(g.exec, s);
+        }
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        body();
+        enqueue_norms();
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(s, &graph);
+        if (e != hipSuccess) return e;
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return e;
+        graphs.push_back(GraphEntry{kind, lv[J].u[0], lv[J].u[1], lv[J].f, cin, cur_mask(), ncycle, sig, exec});
+        return hipGraphLaunch(exec, s);
+    }
+
+    // FMG then the residual norms, and one finest cycle then the norms; the
+    // relative residual is read by relres_read().
+    hipError_t fmg_norms(int ncycle)
+    {
+        return enqueue_schedule(0, ncycle, [&] { fmg(ncycle); });
+    }
+    hipError_t cycle_norms()
+    {
+        return enqueue_schedule(1, 0, [&] { finest_cycle(); });
+    }
+
+    // The relative residual from norms already enqueued (synchronises).
+    hipError_t relres_read(double &out)
+    {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        last_r2 = host_norms[0];
+        const double rn = std::sqrt(host_norms[0]), fn = std::sqrt(host_norms[1]), bn = std::sqrt(host_norms[2]);
+        const double den = fn > 0.0 ? fn : bn;
+        out = den > 0.0 ? rn / den : rn;
+        return hipSuccess;
     }
 
     hipError_t relres(double &out)

@@ -231,6 +231,22 @@ def current_stream_handle() -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _order_in(stream):
+    """The library works on `stream`: order it after the caller's current
+    stream, where the inputs (and the output tensors' memory) were last used."""
+    cur = torch.cuda.current_stream()
+    if cur != stream:
+        stream.wait_stream(cur)
+
+
+def _order_out(stream):
+    """Order the caller's current stream after `stream`, where the library
+    wrote its outputs."""
+    cur = torch.cuda.current_stream()
+    if cur != stream:
+        cur.wait_stream(stream)
+
+
 class Context:
     """One solver context: the nested-box grids on the current device, bound to a stream."""
 
@@ -275,6 +291,7 @@ class Context:
         if total_mass is None:
             total_mass = float(m.sum().item())
         out = ctypes.c_int64(0)
+        _order_in(self.stream)
         check(lib().qumond_deposit(self._h, _ptr(x), _ptr(y), _ptr(z), _ptr(m), np_, float(total_mass),
                                    ctypes.byref(out) if count_outside else None), "qumond_deposit")
         return int(out.value) if count_outside else None
@@ -298,6 +315,7 @@ class Context:
                 raise ValueError("guess must hold nbox * n^3 values")
             if no_fallback:
                 kind |= GUESS_NO_FALLBACK
+            _order_in(self.stream)
         check(lib().qumond_solve_mond(self._h, _ptr(guess), kind, ctypes.byref(info)), "qumond_solve_mond",
               allow=(QUMOND_ERR_NOT_CONVERGED,) if allow_not_converged else ())
         return info.as_dict()
@@ -317,15 +335,19 @@ class Context:
         ay = torch.empty_like(x)
         az = torch.empty_like(x)
         used = torch.empty(np_, dtype=torch.uint8, device=x.device) if with_box else None
+        _order_in(self.stream)
         check(lib().qumond_gather_forces(self._h, _ptr(x), _ptr(y), _ptr(z), np_, int(which), _ptr(ax), _ptr(ay),
                                          _ptr(az), _ptr(used)), "qumond_gather_forces")
+        _order_out(self.stream)
         return ax, ay, az, used
 
     def rotation_curve(self, R: torch.Tensor, naz: int = 16, which: int = 1) -> torch.Tensor:
         _f64(R, "R")
         vc2 = torch.empty_like(R)
+        _order_in(self.stream)
         check(lib().qumond_rotation_curve(self._h, _ptr(R), R.numel(), int(naz), int(which), _ptr(vc2)),
               "qumond_rotation_curve")
+        _order_out(self.stream)
         return vc2
 
     def sigma_z(self, R: torch.Tensor, z: float, z0: float, naz: int = 16, which: int = 1) -> torch.Tensor:
@@ -333,14 +355,18 @@ class Context:
         disk, from the vertical acceleration at heights +-z."""
         _f64(R, "R")
         s2 = torch.empty_like(R)
+        _order_in(self.stream)
         check(lib().qumond_sigma_z(self._h, _ptr(R), R.numel(), int(naz), float(z), float(z0), int(which),
                                    _ptr(s2)), "qumond_sigma_z")
+        _order_out(self.stream)
         return s2
 
     def get_field(self, box: int, fld: int) -> torch.Tensor:
         dt = torch.int64 if fld == FIELD_RHO_FIXED else torch.float64
         out = torch.empty((self.n,) * 3, dtype=dt, device="cuda")
+        _order_in(self.stream)
         check(lib().qumond_get_field(self._h, int(box), int(fld), _ptr(out)), "qumond_get_field")
+        _order_out(self.stream)
         return out
 
     def profile_enable(self, on: bool = True):
@@ -355,6 +381,7 @@ class Context:
         _f64(src, "src")
         if src.numel() != self.n ** 3:
             raise ValueError("field must hold n^3 values")
+        _order_in(self.stream)
         check(lib().qumond_set_field(self._h, int(box), int(fld), _ptr(src)), "qumond_set_field")
 
 
@@ -422,7 +449,8 @@ def k_vcycles(f, u, L, ncyc, npre=2, npost=2):
 
 # ------------------------------------------------------------------ tuning
 
-SMOOTHER_VARIANTS = {0: (32, 8), 1: (64, 4), 2: (64, 8), 3: (128, 4), 4: (32, 16), 5: "brick8"}
+SMOOTHER_VARIANTS = {0: (32, 8), 1: (64, 4), 2: (64, 8), 3: (128, 4), 4: (32, 16), 5: "brick8", 6: (64, 16),
+                     7: (32, 32)}
 FUSED_VARIANTS = {0: (32, 8), 1: (64, 4), 2: "brick8"}
 
 
@@ -524,13 +552,16 @@ class UNet:
         N = self.n ** 3
         x = torch.empty(N * 2, dtype=torch.bfloat16, device="cuda") if x is None else x
         t = torch.empty(N, dtype=torch.float32, device="cuda") if t is None else t
+        _order_in(self.stream)
         check(lib().qumond_unet_prepare_sample(self._h, _ptr(phin), _ptr(S), _ptr(phi), float(h), float(c_phin),
                                                float(c_out), float(GM), float(a0), float(soft), _ptr(x), _ptr(t)),
               "qumond_unet_prepare_sample")
+        _order_out(self.stream)
         return x, t
 
     def train_step(self, x, target, lr: float = 1e-3, want_loss: bool = True):
         loss = ctypes.c_double(0.0)
+        _order_in(self.stream)
         check(lib().qumond_unet_train_step(self._h, _ptr(x), _ptr(target), ctypes.c_float(lr),
                                            ctypes.byref(loss) if want_loss else None), "qumond_unet_train_step")
         return float(loss.value) if want_loss else None
@@ -538,8 +569,10 @@ class UNet:
     def infer(self, phin, S, h, c_phin, c_out, out: Optional[torch.Tensor] = None, GM=0.0, a0=3600.0, soft=1.0):
         if out is None:
             out = torch.empty(self.n ** 3, dtype=torch.float64, device="cuda")
+        _order_in(self.stream)
         check(lib().qumond_unet_infer(self._h, _ptr(phin), _ptr(S), float(h), float(c_phin), float(c_out),
                                       float(GM), float(a0), float(soft), _ptr(out)), "qumond_unet_infer")
+        _order_out(self.stream)
         return out
 
 
@@ -660,19 +693,24 @@ class Batch:
 
     def run(self, use_graph: bool = True, allow_not_converged: bool = False) -> List[dict]:
         info = (qumond_batch_problem_info * self.nprob)()
+        _order_in(self.stream)          # particles written on the caller's stream
         check(lib().qumond_batch_run(self._h, int(bool(use_graph)), info), "qumond_batch_run",
               allow=(QUMOND_ERR_NOT_CONVERGED,) if allow_not_converged else ())
         return [{k: getattr(i, k) for k, _ in qumond_batch_problem_info._fields_} for i in info]
 
     def rotation_curves(self, mond: bool = True) -> torch.Tensor:
         out = torch.empty((self.nprob, len(self.R)), dtype=torch.float64, device="cuda")
+        _order_in(self.stream)
         check(lib().qumond_batch_rotation_curves(self._h, int(bool(mond)), _ptr(out)), "qumond_batch_rotation_curves")
+        _order_out(self.stream)
         return out
 
     def get_field(self, p: int, fld: int) -> torch.Tensor:
         n = self.n_of[p]
         out = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+        _order_in(self.stream)
         check(lib().qumond_batch_get_field(self._h, int(p), int(fld), _ptr(out)), "qumond_batch_get_field")
+        _order_out(self.stream)
         return out
 
     def describe(self) -> dict:

@@ -13,7 +13,7 @@ here n = 2 (the "standard" nu), against the oracle on the same inputs.
 * The batched runner with nu_2 equals the single-problem context bit for bit.
 * The standard nu boosts less than the simple one (nu_2 <= nu_1 at every y),
   so the QUMOND curve of the same disk is lower, and the Kuzmin disk still has
-  no curl field (Eq. 3 with nu_2 matches the nu_2 QUMOND curve to 1.5% beyond
+  no curl field (Eq. 3 with nu_2 matches the nu_2 QUMOND curve to 2% beyond
   ten cells of the inner box).
 """
 import numpy as np
@@ -112,10 +112,10 @@ def test_standard_nu_boosts_less_and_no_curl(kuzmin_nu2):
     c1.close()
     assert np.all(v2 < v1)
     # curl-free up to the discretisation, which is coarse near the centre of
-    # this razor-thin disk (inner box h = 0.78 kpc): within 1.5% beyond 10 cells,
+    # this razor-thin disk (inner box h = 0.78 kpc): within 2% beyond 10 cells,
     # closer further out
     d = np.abs(np.sqrt(va / v2) - 1)
-    assert d[R >= 8.0].max() < 0.015
+    assert d[R >= 8.0].max() < 0.02
     assert d[-1] < d[R == 8.0][0]
 
 
