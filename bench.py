@@ -342,7 +342,8 @@ def main():
         Q.autotune(n_max=n, both=False, reps=5, json_path=args.save_tune)
     shapes = {str(k): {"single": Q.tune_get(k), "fused": Q.tune_get_fused(k)} for k in (33, 65, 129)}
     cfg = Q.Config(n=n, box_side=sides, tol_rel=1e-10, use_graphs=args.graphs)
-    stream = torch.cuda.Stream()            # graphs are captured on a stream of the step's own
+    # graphs need a stream of the step's own (the null stream cannot be captured)
+    stream = torch.cuda.Stream() if args.graphs else torch.cuda.current_stream()
     stream.wait_stream(torch.cuda.current_stream())
     ctx = Q.Context(cfg, stream=stream)
     infos = {}

@@ -22,9 +22,8 @@
 extern "C" {
 #endif
 
-/* variant: z-march over 0 = 32x8, 1 = 64x4, 2 = 64x8, 3 = 128x4, 4 = 32x16,
- * 6 = 64x16, 7 = 32x32 columns per workgroup (the 1024-thread tiles re-read
- * less halo), or 5 = 8^3 bricks held whole in LDS (small levels);
+/* variant: z-march over 0 = 32x8, 1 = 64x4, 2 = 64x8, 3 = 128x4, 4 = 32x16
+ * columns per workgroup, or 5 = 8^3 bricks held whole in LDS (small levels);
  * kchunk: z planes per workgroup (0 = all; ignored by bricks).  fp32 selects
  * the table of the single-precision smoother. */
 qumond_status qumond_tune_set(int32_t n, int32_t fp32, int32_t variant, int32_t kchunk);

@@ -115,8 +115,7 @@ struct SmootherShape {
     int variant;
     int kchunk;
 };
-constexpr int kSmootherVariants = 8;  // one sweep: 0: 32x8, 1: 64x4, 2: 64x8, 3: 128x4, 4: 32x16 z-march,
-                                       // 5: 8^3 bricks, 6: 64x16, 7: 32x32 z-march (1024-thread tiles)
+constexpr int kSmootherVariants = 6;
 constexpr int kFusedVariants = 3;   // two sweeps: 0: 32x8, 1: 64x4 z-march, 2: 8^3 bricks
 // Every grid launcher takes nb, the number of problems stored back to back
 // (problem p of a level with n points per side at offset p n^3); nb = 1 is the

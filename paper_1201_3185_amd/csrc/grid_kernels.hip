@@ -565,8 +565,6 @@ void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, Smoot
     case 3: rbgs_launch<T, 128, 4>(n, h, f, uin, uout, kc, nb, uc, s); break;
     case 4: rbgs_launch<T, 32, 16>(n, h, f, uin, uout, kc, nb, uc, s); break;
     case 5: brick_launch<T, 1>(n, h, f, uin, uout, uc, nb, s); break;
-    case 6: rbgs_launch<T, 64, 16>(n, h, f, uin, uout, kc, nb, uc, s); break;
-    case 7: rbgs_launch<T, 32, 32>(n, h, f, uin, uout, kc, nb, uc, s); break;
     default: rbgs_launch<T, 64, 4>(n, h, f, uin, uout, kc, nb, uc, s); break;
     }
 }

@@ -449,8 +449,7 @@ def k_vcycles(f, u, L, ncyc, npre=2, npost=2):
 
 # ------------------------------------------------------------------ tuning
 
-SMOOTHER_VARIANTS = {0: (32, 8), 1: (64, 4), 2: (64, 8), 3: (128, 4), 4: (32, 16), 5: "brick8", 6: (64, 16),
-                     7: (32, 32)}
+SMOOTHER_VARIANTS = {0: (32, 8), 1: (64, 4), 2: (64, 8), 3: (128, 4), 4: (32, 16), 5: "brick8"}
 FUSED_VARIANTS = {0: (32, 8), 1: (64, 4), 2: "brick8"}
 
 
