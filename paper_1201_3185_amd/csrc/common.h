@@ -160,12 +160,12 @@ template <typename T> void launch_boundary_copy(int n, const T *src, T *dst, hip
 template <typename T> void launch_coarse_tail(int ltop, double L, const T *f, T *u, int npre, int npost, int ncycle,
                                              int mode, int nrep, hipStream_t s, int nb = 1);
 // Sums over interior nodes of (f - A_h u)^2, f^2 and of the squared boundary-value
-// contribution: per-block partials (3 per block, kNormBlocks blocks per
+// contribution: per-block partials (3 per block, up to kNormBlocks blocks per
 // problem), then one block per problem in fixed order, into out[3p..3p+2]
 // (device doubles).
 template <typename T> void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial, double *out,
                                              hipStream_t s, int nb = 1);
-constexpr int kNormBlocks = 512;
+constexpr int kNormBlocks = 2048;
 
 // mixed precision (FP64 refinement around FP32 multigrid); sc holds s and 1/s
 // per problem, written by launch_mixed_scale from the residual norms.

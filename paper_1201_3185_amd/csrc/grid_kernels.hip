@@ -22,6 +22,8 @@
 // problems stored back to back (problem p of a level with n points per side
 // starts at p n^3): the problem index is the slowest part of the block index,
 // so one launch covers the whole batch, and nb = 1 is the single-problem case.
+#include <algorithm>
+
 #include "common.h"
 
 namespace qm {
@@ -1190,33 +1192,41 @@ __device__ __forceinline__ void block_sum3(double *sh, double &a, double &b, dou
 
 // Per-block partial sums over interior nodes of (f - A_h u)^2, f^2 and the
 // squared boundary-value contribution (sum of boundary neighbours / h^2),
-// which scales the stopping test of a source-free box.
+// which scales the stopping test of a source-free box.  A workgroup is 4 rows
+// of 64 lanes: each lane row walks x along one interior (j, k) row (coalesced),
+// the workgroups stride over the rows; the summation order depends only on n
+// and the block count, so the norms are reproducible bit for bit.
 template <typename T>
 __global__ void __launch_bounds__(256)
 resid_norms_partial_k(int n, double ih2, const T *__restrict__ f, const T *__restrict__ u, double *__restrict__ partial)
 {
     __shared__ double sh[768];
-    const unsigned m = (unsigned)(n - 2);
-    const unsigned cnt = m * m * m;   // < 2^31 for n <= 1025
+    const int m = n - 2;
+    const unsigned rows = (unsigned)m * (unsigned)m;
     const size_t sy = (size_t)n, sz = (size_t)n * n;
     f += blockIdx.y * sz * n;
     u += blockIdx.y * sz * n;
     partial += blockIdx.y * 3 * (size_t)gridDim.x;
+    const int lane = threadIdx.x & 63, ty = threadIdx.x >> 6;
     double sr = 0.0, sf = 0.0, sb = 0.0;
-    for (unsigned t = blockIdx.x * 256u + threadIdx.x; t < cnt; t += gridDim.x * 256u) {
-        const unsigned tq = t / m;
-        const int i = 1 + (int)(t - tq * m), j = 1 + (int)(tq % m), k = 1 + (int)(tq / m);
-        const size_t p = id3(n, i, j, k);
-        const double um = u[p - 1], up = u[p + 1], vm = u[p - sy], vp = u[p + sy], wm = u[p - sz], wp = u[p + sz];
-        const double lap = (um + up + vm + vp + wm + wp - 6.0 * (double)u[p]) * ih2;
-        const double fv = (double)f[p];
-        const double r = fv - lap;
-        sr += r * r;
-        sf += fv * fv;
-        if (i == 1 || j == 1 || k == 1 || i == n - 2 || j == n - 2 || k == n - 2) {
-            const double b = ((i == 1 ? um : 0.0) + (i == n - 2 ? up : 0.0) + (j == 1 ? vm : 0.0) +
-                              (j == n - 2 ? vp : 0.0) + (k == 1 ? wm : 0.0) + (k == n - 2 ? wp : 0.0)) * ih2;
-            sb += b * b;
+    for (unsigned r = blockIdx.x * 4u + (unsigned)ty; r < rows; r += gridDim.x * 4u) {
+        const unsigned kq = r / (unsigned)m;              // one division per row
+        const int j = 1 + (int)(r - kq * (unsigned)m), k = 1 + (int)kq;
+        const bool jk_edge = j == 1 || k == 1 || j == n - 2 || k == n - 2;
+        const size_t row = id3(n, 0, j, k);
+        for (int i = 1 + lane; i <= n - 2; i += 64) {
+            const size_t p = row + (size_t)i;
+            const double um = u[p - 1], up = u[p + 1], vm = u[p - sy], vp = u[p + sy], wm = u[p - sz], wp = u[p + sz];
+            const double lap = (um + up + vm + vp + wm + wp - 6.0 * (double)u[p]) * ih2;
+            const double fv = (double)f[p];
+            const double res = fv - lap;
+            sr += res * res;
+            sf += fv * fv;
+            if (jk_edge || i == 1 || i == n - 2) {
+                const double b = ((i == 1 ? um : 0.0) + (i == n - 2 ? up : 0.0) + (j == 1 ? vm : 0.0) +
+                                  (j == n - 2 ? vp : 0.0) + (k == 1 ? wm : 0.0) + (k == n - 2 ? wp : 0.0)) * ih2;
+                sb += b * b;
+            }
         }
     }
     block_sum3<256>(sh, sr, sf, sb);
@@ -1249,9 +1259,11 @@ __global__ void __launch_bounds__(256) norms_final_k(const double *__restrict__ 
 template <typename T>
 void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial, double *out, hipStream_t s, int nb)
 {
-    hipLaunchKernelGGL(resid_norms_partial_k<T>, dim3(kNormBlocks, nb), dim3(256), 0, s, n, 1.0 / (h * h), f, u,
-                       partial);
-    hipLaunchKernelGGL(norms_final_k, dim3(nb), dim3(256), 0, s, partial, kNormBlocks, out);
+    // about 8 four-row groups per workgroup, at most kNormBlocks workgroups per problem
+    const long long rows = (long long)(n - 2) * (n - 2);
+    const int blocks = (int)std::min<long long>(kNormBlocks, std::max<long long>(1, (rows + 31) / 32));
+    hipLaunchKernelGGL(resid_norms_partial_k<T>, dim3(blocks, nb), dim3(256), 0, s, n, 1.0 / (h * h), f, u, partial);
+    hipLaunchKernelGGL(norms_final_k, dim3(nb), dim3(256), 0, s, partial, blocks, out);
 }
 
 // ------------------------------------------------- mixed-precision helpers

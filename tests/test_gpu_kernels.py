@@ -180,7 +180,7 @@ def test_bc_from_coarse(n):
     assert rel(host(d), ref) < 1e-15
 
 
-@pytest.mark.parametrize("n", [5, 33, 129])
+@pytest.mark.parametrize("n", [5, 33, 65, 129, 257])
 def test_resid_norms(n):
     L = 2.0
     h = L / (n - 1)
