@@ -725,9 +725,153 @@ residual_restrict_tile_k(int nf, T ih2, const T *__restrict__ f, const T *__rest
     fc[C] = acc;
 }
 
+// Residual and restriction marching in z: a workgroup owns CX x CY coarse
+// columns and a chunk of kc interior coarse planes.  For coarse plane K it
+// loads u planes 2K+1 and 2K+2 into a ring of four LDS planes, forms the fine
+// residuals of planes 2K and 2K+1 once each into a ring of three (plane 2K-1
+// is kept from the step before), then restricts planes 2K-1..2K+1 to plane K.
+// Every fine residual is formed once, with the expression and summation order
+// of residual_restrict_k, so the two kernels give identical results.
+template <typename T, int CX, int CY>
+__global__ void __launch_bounds__(256)
+residual_restrict_zmarch_k(int nf, T ih2, const T *__restrict__ f, const T *__restrict__ u, T *__restrict__ fc,
+                           T *__restrict__ uc0, T *__restrict__ uc1, int tx, int ty, int tzc, int kc)
+{
+#pragma clang fp contract(off)
+    constexpr int NT = 256;
+    constexpr int RX = 2 * CX + 1, RY = 2 * CY + 1, RP = RX * RY;   // fine residual region of a plane
+    constexpr int UX = RX + 2, UY = RY + 2, UP = UX * UY;           // u region (one-node ring)
+    constexpr int NU = (UP + NT - 1) / NT, NR = (RP + NT - 1) / NT;
+    static_assert(CX * CY <= NT, "one coarse node per thread");
+    __shared__ T Us[4][UP];
+    __shared__ T Rs[3][RP];
+    const int nc = (nf + 1) / 2;
+    int bid = (int)xcd_tile(blockIdx.x, gridDim.x);
+    const int bx = bid % tx;
+    bid /= tx;
+    const int by = bid % ty;
+    bid /= ty;
+    const int bz = bid % tzc;
+    const int pb = bid / tzc;
+    const size_t Nf = (size_t)nf * nf * nf, Nc = (size_t)nc * nc * nc;
+    const size_t sy = (size_t)nf, sz = (size_t)nf * nf;
+    f += pb * Nf;
+    u += pb * Nf;
+    fc += pb * Nc;
+    uc0 += pb * Nc;
+    if (uc1) uc1 += pb * Nc;
+    const int tid = threadIdx.x;
+    const int I0 = bx * CX, J0 = by * CY;
+    const int fi0 = 2 * I0 - 1, fj0 = 2 * J0 - 1;   // origin of the fine residual region
+    // this thread's share of a u plane and of a residual plane
+    int uoff[NU], foff[NR], rq[NR];
+#pragma unroll
+    for (int r = 0; r < NU; ++r) {
+        const int t = tid + r * NT;
+        const int a = t % UX, b = t / UX;
+        const int i = fi0 - 1 + a, j = fj0 - 1 + b;
+        uoff[r] = (t < UP && i >= 0 && i < nf && j >= 0 && j < nf) ? i + nf * j : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int t = tid + r * NT;
+        const int a = t % RX, b = t / RX;
+        const int i = fi0 + a, j = fj0 + b;
+        foff[r] = (t < RP && i >= 1 && i <= nf - 2 && j >= 1 && j <= nf - 2) ? i + nf * j : -1;
+        rq[r] = (a + 1) + UX * (b + 1);
+    }
+    // this thread's coarse node
+    const int ci = tid % CX, cj = tid / CX;
+    const int I = I0 + ci, J = J0 + cj;
+    const bool c_thread = tid < CX * CY && I < nc && J < nc;
+    const bool c_inner = c_thread && I >= 1 && I <= nc - 2 && J >= 1 && J <= nc - 2;
+    const int Kb = 1 + bz * kc, Ke = min(Kb + kc - 1, nc - 2);
+
+    auto zero_node = [&](int K) {
+        const size_t C = id3(nc, I, J, K);
+        uc0[C] = T(0);
+        if (uc1) uc1[C] = T(0);
+        fc[C] = T(0);
+    };
+    if (c_thread && bz == 0) zero_node(0);
+    if (c_thread && bz == tzc - 1) zero_node(nc - 1);
+
+    auto load_u = [&](int p) {
+        T *U = Us[p & 3];
+        const T *src = u + (size_t)p * sz;
+#pragma unroll
+        for (int r = 0; r < NU; ++r) {
+            const int t = tid + r * NT;
+            if (t < UP) U[t] = uoff[r] >= 0 ? src[uoff[r]] : T(0);
+        }
+    };
+    auto load_f = [&](int p, T *fv) {
+        const T *src = f + (size_t)p * sz;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) fv[r] = foff[r] >= 0 ? src[foff[r]] : T(0);
+    };
+    auto resid = [&](int p, const T *fv) {
+        const T *U = Us[p & 3];
+        const T *Um = Us[(p - 1) & 3];
+        const T *Up = Us[(p + 1) & 3];
+        T *Rp = Rs[p % 3];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int t = tid + r * NT;
+            if (t >= RP) continue;
+            if (foff[r] < 0) {
+                Rp[t] = T(0);
+                continue;
+            }
+            const int q = rq[r];
+            const T lap = (U[q - 1] + U[q + 1] + U[q - UX] + U[q + UX] + Um[q] + Up[q] - T(6) * U[q]) * ih2;
+            Rp[t] = fv[r] - lap;
+        }
+    };
+    auto restrict_plane = [&](int K) {
+        if (!c_thread) return;
+        if (!c_inner) {
+            zero_node(K);
+            return;
+        }
+        const T w[3] = {T(0.25), T(0.5), T(0.25)};
+        T acc = T(0);
+        for (int c = -1; c <= 1; ++c) {
+            const T *Rp = Rs[(2 * K + c) % 3];
+            for (int b = -1; b <= 1; ++b)
+                for (int a = -1; a <= 1; ++a)
+                    acc += (w[a + 1] * w[b + 1] * w[c + 1]) * Rp[(2 * ci + 1 + a) + RX * (2 * cj + 1 + b)];
+        }
+        const size_t C = id3(nc, I, J, K);
+        uc0[C] = T(0);
+        fc[C] = acc;
+    };
+
+    T fa[NR], fb[NR];
+    // warm-up: u planes 2Kb-2..2Kb and the residual of plane 2Kb-1
+    load_u(2 * Kb - 2);
+    load_u(2 * Kb - 1);
+    load_u(2 * Kb);
+    load_f(2 * Kb - 1, fa);
+    __syncthreads();
+    resid(2 * Kb - 1, fa);
+    __syncthreads();
+    for (int K = Kb; K <= Ke; ++K) {
+        load_u(2 * K + 1);   // slots of planes 2K-3 and 2K-2, last read before the previous barrier
+        load_u(2 * K + 2);
+        load_f(2 * K, fa);
+        load_f(2 * K + 1, fb);
+        __syncthreads();
+        resid(2 * K, fa);
+        resid(2 * K + 1, fb);
+        __syncthreads();
+        restrict_plane(K);
+    }
+}
+
 // Which residual-restriction kernel a fine level of n points uses (0: per-node
-// gather, 1: LDS tile), per precision; set by the autotuner, gather by default
-// (the faster of the two in the measurements so far).
+// gather, 1: LDS tile, 2: z-march), per precision; set by the autotuner, gather
+// by default.
 static int g_rr_variant[2][11] = {{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
 
 template <typename T>
@@ -748,6 +892,15 @@ void launch_residual_restrict_variant(int nf, double h, const T *f, const T *u, 
         int zb;
         const dim3 g = grid3(nc, blk, nb, zb);
         hipLaunchKernelGGL(residual_restrict_k<T>, g, blk, 0, s, nf, T(1.0 / (h * h)), f, u, fc, uc0, uc1, zb);
+        return;
+    }
+    if (variant == 2) {
+        constexpr int CX = 16, CY = 8;
+        const int kc = nc >= 129 ? 16 : 8;
+        const int tx = (nc + CX - 1) / CX, ty = (nc + CY - 1) / CY, tzc = (nc - 2 + kc - 1) / kc;
+        const dim3 g((unsigned)((size_t)tx * ty * tzc * nb));
+        hipLaunchKernelGGL((residual_restrict_zmarch_k<T, CX, CY>), g, dim3(256), 0, s, nf, T(1.0 / (h * h)), f, u, fc,
+                           uc0, uc1, tx, ty, tzc, kc);
         return;
     }
     const int tx = (nc + 7) / 8, ty = (nc + 7) / 8, tz = (nc + 3) / 4;

@@ -147,6 +147,31 @@ def test_autotuned_shapes_keep_results_bitwise():
         assert np.array_equal(b0.get_field(p, Q.FIELD_PHI).cpu().numpy(), b1.get_field(p, Q.FIELD_PHI).cpu().numpy())
 
 
+def test_zmarch_residual_restriction_over_stacked_problems():
+    """Every residual restriction of a batch forced to the z-march kernel (one
+    launch over the stacked problems of a class) gives the bits of the gather
+    kernel."""
+    ns = [65, 65, 33, 129, 33]
+    parts = small_disks(ns, seed0=900)
+    levels = (33, 65, 129)
+    saved = {(n, fp): Q.tune_get_rr(n, fp32=fp) for n in levels for fp in (False, True)}
+    try:
+        fields = []
+        for v in (0, 2):
+            for n in levels:
+                for fp in (False, True):
+                    Q.tune_set_rr(n, v, fp32=fp)
+            b = make_batch(ns, parts, refine_iters=3, max_extra=0)
+            b.run(use_graph=v == 2, allow_not_converged=True)
+            fields.append([b.get_field(p, Q.FIELD_PHI).cpu().numpy() for p in range(len(ns))])
+            b.close()
+        for p in range(len(ns)):
+            assert np.array_equal(fields[0][p], fields[1][p]), p
+    finally:
+        for (n, fp), v in saved.items():
+            Q.tune_set_rr(n, v, fp32=fp)
+
+
 def test_batch_against_oracle():
     ns = [33, 65]
     parts = small_disks(ns, seed0=500)
