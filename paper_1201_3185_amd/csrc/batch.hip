@@ -303,12 +303,12 @@ hipError_t tune_class(qumond_batch *B, Class &C, int reps)
         }
         C.shapes.use_fused[l] = best[1] < 2.0 * best[0] ? 1 : 0;
         // residual restriction from this level: both kernels on the batch's own grids
-        double rr_us[3] = {0.0, 0.0, 0.0};
+        double rr_us[qm::kRrVariants] = {};
         {
             // levels lt..J-1 are allocated and l - 1 >= lt here
             float *fc = C.mg.lv[l - 1].f, *c0 = C.mg.lv[l - 1].u[0], *c1 = C.mg.lv[l - 1].u[1];
             {
-                for (int v = 0; v < 3; ++v) {
+                for (int v = 0; v < qm::kRrVariants; ++v) {
                     qm::launch_residual_restrict_variant<float>(n, h, f, u0, fc, c0, c1, v, s, C.P);
                     std::vector<float> t;
                     for (int r = 0; r < reps; ++r) {
@@ -324,7 +324,7 @@ hipError_t tune_class(qumond_batch *B, Class &C, int reps)
                     rr_us[v] = 1e3 * t[t.size() / 2];
                 }
                 int best = 0;
-                for (int v = 1; v < 3; ++v)
+                for (int v = 1; v < qm::kRrVariants; ++v)
                     if (rr_us[v] < rr_us[best]) best = v;
                 C.shapes.rr[l] = best;
             }
@@ -332,10 +332,10 @@ hipError_t tune_class(qumond_batch *B, Class &C, int reps)
         char buf[320];
         std::snprintf(buf, sizeof buf,
                       "%s{\"n\": %d, \"single\": [%d, %d, %.2f], \"fused\": [%d, %d, %.2f], \"use_fused\": %d, "
-                      "\"rr\": [%d, %.2f, %.2f, %.2f]}",
+                      "\"rr\": [%d, %.2f, %.2f, %.2f, %.2f, %.2f]}",
                       first ? "" : ", ", n, C.shapes.single[l].variant, C.shapes.single[l].kchunk, best[0],
                       C.shapes.fused[l].variant, C.shapes.fused[l].kchunk, best[1], C.shapes.use_fused[l],
-                      C.shapes.rr[l], rr_us[0], rr_us[1], rr_us[2]);
+                      C.shapes.rr[l], rr_us[0], rr_us[1], rr_us[2], rr_us[3], rr_us[4]);
         js += buf;
         first = false;
     }

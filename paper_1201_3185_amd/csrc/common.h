@@ -116,6 +116,7 @@ struct SmootherShape {
     int kchunk;
 };
 constexpr int kSmootherVariants = 6;
+constexpr int kRrVariants = 5;   // residual restriction: gather, LDS tile, z-march with 4/8/16-plane chunks
 constexpr int kFusedVariants = 3;   // two sweeps: 0: 32x8, 1: 64x4 z-march, 2: 8^3 bricks
 // Every grid launcher takes nb, the number of problems stored back to back
 // (problem p of a level with n points per side at offset p n^3); nb = 1 is the

@@ -870,8 +870,8 @@ residual_restrict_zmarch_k(int nf, T ih2, const T *__restrict__ f, const T *__re
 }
 
 // Which residual-restriction kernel a fine level of n points uses (0: per-node
-// gather, 1: LDS tile, 2: z-march), per precision; set by the autotuner, gather
-// by default.
+// gather, 1: LDS tile, 2/3/4: z-march over chunks of 4/8/16 coarse planes), per
+// precision; set by the autotuner, gather by default.
 static int g_rr_variant[2][11] = {{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
 
 template <typename T>
@@ -894,9 +894,9 @@ void launch_residual_restrict_variant(int nf, double h, const T *f, const T *u, 
         hipLaunchKernelGGL(residual_restrict_k<T>, g, blk, 0, s, nf, T(1.0 / (h * h)), f, u, fc, uc0, uc1, zb);
         return;
     }
-    if (variant == 2) {
+    if (variant >= 2) {   // z-march with chunks of 4, 8 or 16 coarse planes
         constexpr int CX = 16, CY = 8;
-        const int kc = nc >= 129 ? 16 : 8;
+        const int kc = variant == 2 ? 4 : (variant == 3 ? 8 : 16);
         const int tx = (nc + CX - 1) / CX, ty = (nc + CY - 1) / CY, tzc = (nc - 2 + kc - 1) / kc;
         const dim3 g((unsigned)((size_t)tx * ty * tzc * nb));
         hipLaunchKernelGGL((residual_restrict_zmarch_k<T, CX, CY>), g, dim3(256), 0, s, nf, T(1.0 / (h * h)), f, u, fc,

@@ -95,7 +95,7 @@ qumond_status tune_one(int n, int reps, hipStream_t s, double &best_us, bool fus
 // Time both residual-restriction kernels on a fine level of n points and
 // install the faster one.
 template <typename T>
-qumond_status tune_rr(int n, int reps, hipStream_t s, double us[3])
+qumond_status tune_rr(int n, int reps, hipStream_t s, double us[qm::kRrVariants])
 {
     const int nc = (n + 1) / 2;
     const size_t N = (size_t)n * n * n, Nc = (size_t)nc * nc * nc;
@@ -117,7 +117,7 @@ qumond_status tune_rr(int n, int reps, hipStream_t s, double us[3])
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     const double h = 1.0 / (n - 1);
-    for (int v = 0; v < 3; ++v) {
+    for (int v = 0; v < qm::kRrVariants; ++v) {
         qm::launch_residual_restrict_variant<T>(n, h, f, u, fc, c0, c1, v, s);
         std::vector<float> t;
         for (int r = 0; r < reps; ++r) {
@@ -133,7 +133,7 @@ qumond_status tune_rr(int n, int reps, hipStream_t s, double us[3])
         us[v] = 1e3 * t[t.size() / 2];
     }
     int best = 0;
-    for (int v = 1; v < 3; ++v)
+    for (int v = 1; v < qm::kRrVariants; ++v)
         if (us[v] < us[best]) best = v;
     qm::rr_variant<T>(n) = best;
     (void)hipEventDestroy(e0);
@@ -195,7 +195,7 @@ qumond_status qumond_tune_get_fused(int32_t n, int32_t fp32, int32_t *variant, i
 
 qumond_status qumond_tune_set_rr(int32_t n, int32_t fp32, int32_t variant)
 {
-    if (!good_n(n) || variant < 0 || variant > 2) return tfail("qumond_tune_set_rr: bad argument");
+    if (!good_n(n) || variant < 0 || variant >= qm::kRrVariants) return tfail("qumond_tune_set_rr: bad argument");
     if (fp32) qm::rr_variant<float>(n) = variant;
     else qm::rr_variant<double>(n) = variant;
     return QUMOND_OK;
@@ -254,15 +254,15 @@ qumond_status qumond_autotune(int32_t n_max, int32_t both, int32_t reps, const c
             const int fuse = us_pair[1] < 2.0 * us_pair[0] ? 1 : 0;
             if (prec) qm::use_fused<float>(n) = fuse;
             else qm::use_fused<double>(n) = fuse;
-            double rr_us[3] = {0.0, 0.0, 0.0};
+            double rr_us[qm::kRrVariants] = {};
             const qumond_status st = prec ? tune_rr<float>(n, reps, s, rr_us) : tune_rr<double>(n, reps, s, rr_us);
             if (st != QUMOND_OK) return st;
             const int rrv = prec ? qm::rr_variant<float>(n) : qm::rr_variant<double>(n);
-            char buf[200];
+            char buf[320];
             std::snprintf(buf, sizeof buf,
                           ", {\"n\": %d, \"fp32\": %d, \"use_fused\": %d}, {\"n\": %d, \"fp32\": %d, \"rr\": %d, "
-                          "\"rr_us\": [%.3f, %.3f, %.3f]}",
-                          n, prec, fuse, n, prec, rrv, rr_us[0], rr_us[1], rr_us[2]);
+                          "\"rr_us\": [%.3f, %.3f, %.3f, %.3f, %.3f]}",
+                          n, prec, fuse, n, prec, rrv, rr_us[0], rr_us[1], rr_us[2], rr_us[3], rr_us[4]);
             js += buf;
         }
     }
@@ -313,7 +313,7 @@ qumond_status qumond_tune_load(const char *json_path)
     while ((pos = txt.find("{\"n\":", pos)) != std::string::npos) {
         int n = 0, fp32 = 0, rrv = 0;
         if (std::sscanf(txt.c_str() + pos, "{\"n\": %d, \"fp32\": %d, \"rr\": %d", &n, &fp32, &rrv) == 3 && good_n(n)) {
-            const int v = rrv >= 0 && rrv <= 2 ? rrv : 0;
+            const int v = rrv >= 0 && rrv < qm::kRrVariants ? rrv : 0;
             if (fp32) qm::rr_variant<float>(n) = v;
             else qm::rr_variant<double>(n) = v;
         }
