@@ -306,8 +306,8 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a design "
-              "described in DESIGN.md and is not run.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): this build has no multi-GPU path; "
+              "sharding the boxes or the batch over GPUs is a design that is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

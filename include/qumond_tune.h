@@ -41,6 +41,15 @@ qumond_status qumond_tune_get_fused(int32_t n, int32_t fp32, int32_t *variant, i
 qumond_status qumond_tune_set_rr(int32_t n, int32_t fp32, int32_t variant);
 qumond_status qumond_tune_get_rr(int32_t n, int32_t fp32, int32_t *variant);
 
+/* Coarse-grid correction of a level of n points (the u += P uc step of a
+ * V-cycle before post-smoothing): split = 0 applies it inside the first
+ * post-smoothing launch as each plane of u is loaded, split = 1 runs it as its
+ * own prolong-add launch first (identical results; the autotuner times both in
+ * the level's smoother form and keeps the faster).  Errors: n not 2^J + 1 in
+ * 5..1025 or split outside {0, 1} -> QUMOND_ERR_INVALID. */
+qumond_status qumond_tune_set_split(int32_t n, int32_t fp32, int32_t split);
+qumond_status qumond_tune_get_split(int32_t n, int32_t fp32, int32_t *split);
+
 /* One smoother sweep with an explicit shape (see qumond_k_rbgs_sweep); with
  * uc != NULL (device, ((n+1)/2)^3 doubles) the correction u += P uc is applied
  * to u_in's interior first, in the same launch. */
@@ -52,7 +61,9 @@ qumond_status qumond_k_rbgs_sweep_shape(int32_t n, double h, const double *f, co
  * string, optional) receives the table.  best_us (host, optional, 11 entries)
  * gets the FP64 time of one fused two-sweep launch indexed by log2(n-1).
  * For each size it also records whether the multigrid should use the fused
- * launch (faster than two single sweeps) or single sweeps. */
+ * launch (faster than two single sweeps) or single sweeps, the fastest
+ * residual-restriction kernel, and whether the coarse-grid correction runs as
+ * its own launch (timed with two post-smoothing sweeps). */
 qumond_status qumond_autotune(int32_t n_max, int32_t both, int32_t reps, const char *json_path, double *best_us,
                               void *stream);
 qumond_status qumond_tune_load(const char *json_path);

@@ -329,13 +329,48 @@ hipError_t tune_class(qumond_batch *B, Class &C, int reps)
                 C.shapes.rr[l] = best;
             }
         }
-        char buf[320];
+        // the first post-smoothing launch with the coarse-grid correction inside
+        // it, against a prolong-add launch and the same launch without it
+        double sp_us[2] = {};
+        {
+            const int nc = (n + 1) / 2;
+            const float *uc = C.mg.lv[l - 1].u[0];
+            const bool fz = C.shapes.use_fused[l] != 0 && C.mg.npost >= 2;
+            for (int sp = 0; sp < 2; ++sp) {
+                auto run = [&](int r) {
+                    float *a = (r & 1) ? u1 : u0, *b = (r & 1) ? u0 : u1;
+                    const float *c = uc;
+                    if (sp) {
+                        qm::launch_prolong_add<float>(nc, uc, a, s, C.P);
+                        c = nullptr;
+                    }
+                    if (fz) qm::launch_rbgs2_shape<float>(n, h, f, a, b, c, C.shapes.fused[l], s, C.P);
+                    else qm::launch_rbgs_shape<float>(n, h, f, a, b, C.shapes.single[l], s, C.P, c);
+                };
+                run(0);
+                std::vector<float> t;
+                for (int r = 0; r < reps; ++r) {
+                    (void)hipEventRecord(e0, s);
+                    run(r);
+                    (void)hipEventRecord(e1, s);
+                    if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    t.push_back(ms);
+                }
+                std::sort(t.begin(), t.end());
+                sp_us[sp] = 1e3 * t[t.size() / 2];
+            }
+            C.shapes.split[l] = sp_us[1] < sp_us[0] ? 1 : 0;
+        }
+        char buf[400];
         std::snprintf(buf, sizeof buf,
                       "%s{\"n\": %d, \"single\": [%d, %d, %.2f], \"fused\": [%d, %d, %.2f], \"use_fused\": %d, "
-                      "\"rr\": [%d, %.2f, %.2f, %.2f, %.2f, %.2f]}",
+                      "\"rr\": [%d, %.2f, %.2f, %.2f, %.2f, %.2f], \"split_prolong\": [%d, %.2f, %.2f]}",
                       first ? "" : ", ", n, C.shapes.single[l].variant, C.shapes.single[l].kchunk, best[0],
                       C.shapes.fused[l].variant, C.shapes.fused[l].kchunk, best[1], C.shapes.use_fused[l],
-                      C.shapes.rr[l], rr_us[0], rr_us[1], rr_us[2], rr_us[3], rr_us[4]);
+                      C.shapes.rr[l], rr_us[0], rr_us[1], rr_us[2], rr_us[3], rr_us[4], C.shapes.split[l], sp_us[0],
+                      sp_us[1]);
         js += buf;
         first = false;
     }
@@ -517,6 +552,7 @@ qumond_status qumond_batch_create(const qumond_batch_config *cfg, const int32_t 
             C.shapes.fused[l] = qm::rbgs2_shape<float>(nl < 5 ? 5 : nl);
             C.shapes.use_fused[l] = qm::use_fused<float>(nl < 5 ? 5 : nl);
             C.shapes.rr[l] = qm::rr_variant<float>(nl < 5 ? 5 : nl);
+            C.shapes.split[l] = qm::split_prolong<float>(nl < 5 ? 5 : nl);
         }
         C.mg.shapes = &C.shapes;
         // the solver's buffers start defined (a solve reads only what it wrote)

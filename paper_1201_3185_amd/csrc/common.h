@@ -139,6 +139,10 @@ template <typename T> SmootherShape &rbgs2_shape(int n);
 // Whether the multigrid uses the fused kernel on a level of n points per side
 // (set by the autotuner from measured times; n <= 65 by default).
 template <typename T> int &use_fused(int n);
+// Whether the coarse-grid correction of a level of n points is its own
+// prolong-add launch (1) or is folded into the first post-smoothing launch (0);
+// identical results, chosen by the autotuner from measured times.
+template <typename T> int &split_prolong(int n);
 template <typename T> void launch_residual_restrict(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1,
                                                    hipStream_t s, int nb = 1);
 // The two implementations of the residual restriction (0: per-node gather,

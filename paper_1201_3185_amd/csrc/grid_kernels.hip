@@ -527,6 +527,20 @@ int &use_fused(int n)
     return g_use_fused[sizeof(T) == 4 ? 1 : 0][J > 10 ? 10 : J];
 }
 
+// Whether the coarse-grid correction of a level of n points runs as its own
+// prolong-add launch before the post-smoothing (1) or is applied inside the
+// first post-smoothing launch as planes are loaded (0, the default); both give
+// the same values bit for bit.  Set by the autotuner per precision.
+static int g_split_prolong[2][11] = {{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+
+template <typename T>
+int &split_prolong(int n)
+{
+    int J = 0;
+    while ((1 << J) < n - 1) ++J;
+    return g_split_prolong[sizeof(T) == 4 ? 1 : 0][J > 10 ? 10 : J];
+}
+
 template <typename T>
 SmootherShape &rbgs2_shape(int n)
 {
@@ -927,41 +941,67 @@ void launch_restrict(int nf, const T *src, T *dst, hipStream_t s, int nb)
 
 // ------------------------------------------------------------- prolongation
 
+// One thread per pair of fine nodes along x, i = 2q + 1 (between coarse
+// nodes q and q + 1) and i = 2q + 2 (on coarse node q + 1): both read the same
+// two coarse values per (j, k) row, so a pair takes 8 coarse loads instead of
+// 16.  Each fine value is the expression of prolong_at with its weights, in the
+// same order, so the result equals prolong_at's bit for bit.
 template <typename T, bool ADD>
-__global__ void prolong_k(int nc, const T *__restrict__ uc, T *__restrict__ uf, int zb)
+__global__ void __launch_bounds__(256) prolong_k(int nc, const T *__restrict__ uc, T *__restrict__ uf, int zb)
 {
+#pragma clang fp contract(off)
     const int nf = 2 * nc - 1;
     const int pb = blockIdx.z / zb;
-    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
     const int k = 1 + (blockIdx.z - pb * zb) * blockDim.z + threadIdx.z;
-    if (i > nf - 2 || j > nf - 2 || k > nf - 2) return;
+    if (q > nc - 2 || j > nf - 2 || k > nf - 2) return;
     uc += pb * (size_t)nc * nc * nc;
     uf += pb * (size_t)nf * nf * nf;
-    const size_t p = id3(nf, i, j, k);
-    const T v = prolong_at(nc, uc, i, j, k);
-    if (ADD) uf[p] += v;
-    else uf[p] = v;
+    const int ja = j >> 1, jb = (j + 1) >> 1, ka = k >> 1, kb = (k + 1) >> 1;
+    const T wja = (j & 1) ? T(0.5) : T(1), wjb = (j & 1) ? T(0.5) : T(0);
+    const T wka = (k & 1) ? T(0.5) : T(1), wkb = (k & 1) ? T(0.5) : T(0);
+    const T a0 = uc[id3(nc, q, ja, ka)], a1 = uc[id3(nc, q + 1, ja, ka)];
+    const T b0 = uc[id3(nc, q, jb, ka)], b1 = uc[id3(nc, q + 1, jb, ka)];
+    const T c0 = uc[id3(nc, q, ja, kb)], c1 = uc[id3(nc, q + 1, ja, kb)];
+    const T d0 = uc[id3(nc, q, jb, kb)], d1 = uc[id3(nc, q + 1, jb, kb)];
+    const T h = T(0.5), one = T(1), zero = T(0);
+    const size_t p = id3(nf, 2 * q + 1, j, k);
+    {   // odd i: weights 1/2, 1/2 between coarse q and q + 1
+        const T xa = h * a0 + h * a1, xb = h * b0 + h * b1, xc = h * c0 + h * c1, xd = h * d0 + h * d1;
+        const T v = wka * (wja * xa + wjb * xb) + wkb * (wja * xc + wjb * xd);
+        if (ADD) uf[p] += v;
+        else uf[p] = v;
+    }
+    if (2 * q + 2 <= nf - 2) {   // even i: coarse q + 1 with weights 1, 0
+        const T xa = one * a1 + zero * a1, xb = one * b1 + zero * b1, xc = one * c1 + zero * c1,
+                xd = one * d1 + zero * d1;
+        const T v = wka * (wja * xa + wjb * xb) + wkb * (wja * xc + wjb * xd);
+        if (ADD) uf[p + 1] += v;
+        else uf[p + 1] = v;
+    }
+}
+
+template <typename T, bool ADD>
+static void launch_prolong(int nc, const T *uc, T *uf, hipStream_t s, int nb)
+{
+    const int nf = 2 * nc - 1;
+    const dim3 blk(64, 2, 2);
+    const int zb = (nf - 2 + 1) / 2;
+    const dim3 g((unsigned)((nc - 1 + 63) / 64), (unsigned)((nf - 2 + 1) / 2), (unsigned)(zb * nb));
+    hipLaunchKernelGGL((prolong_k<T, ADD>), g, blk, 0, s, nc, uc, uf, zb);
 }
 
 template <typename T>
 void launch_prolong_add(int nc, const T *uc, T *uf, hipStream_t s, int nb)
 {
-    const int nf = 2 * nc - 1;
-    dim3 blk(64, 2, 2);
-    int zb;
-    const dim3 g = grid3(nf - 2, blk, nb, zb);
-    hipLaunchKernelGGL((prolong_k<T, true>), g, blk, 0, s, nc, uc, uf, zb);
+    launch_prolong<T, true>(nc, uc, uf, s, nb);
 }
 
 template <typename T>
 void launch_interp(int nc, const T *uc, T *uf, hipStream_t s, int nb)
 {
-    const int nf = 2 * nc - 1;
-    dim3 blk(64, 2, 2);
-    int zb;
-    const dim3 g = grid3(nf - 2, blk, nb, zb);
-    hipLaunchKernelGGL((prolong_k<T, false>), g, blk, 0, s, nc, uc, uf, zb);
+    launch_prolong<T, false>(nc, uc, uf, s, nb);
 }
 
 // ------------------------------------------------------- boundary helpers
@@ -1585,6 +1625,7 @@ void launch_guess_interior(int n, const void *g, int kind, double *u, hipStream_
     template SmootherShape &rbgs_shape<T>(int);                                                                 \
     template SmootherShape &rbgs2_shape<T>(int);                                                                \
     template int &use_fused<T>(int);                                                                            \
+    template int &split_prolong<T>(int);                                                                        \
     template void launch_rbgs2<T>(int, double, const T *, const T *, T *, const T *, hipStream_t, int);        \
     template void launch_rbgs2_shape<T>(int, double, const T *, const T *, T *, const T *, SmootherShape,        \
                                         hipStream_t, int);                                                      \

@@ -81,6 +81,7 @@ struct LevelShapes {
     SmootherShape fused[11];
     int use_fused[11];
     int rr[11];   // residual-restriction kernel of fine level l
+    int split[11];   // coarse-grid correction of level l as its own launch
 };
 
 template <typename T>
@@ -185,12 +186,14 @@ struct Multigrid {
     }
 
     // ns red-black sweeps on level l; pairs of sweeps run as one fused launch.
-    // With uc != NULL the correction u += P uc is applied before the first sweep.
+    // With uc != NULL the correction u += P uc is applied before the first
+    // sweep: inside its launch, or by a prolong-add launch of its own where
+    // the level's table entry asks for that (or when ns == 0).
     void smooth(int l, int ns, const T *uc = nullptr)
     {
         Level<T> &v = lv[l];
         const double pts = (double)v.n * v.n * v.n;
-        if (uc && ns == 0) {
+        if (uc && (ns == 0 || (shapes ? shapes->split[l] : split_prolong<T>(v.n)) != 0)) {
             launch_prolong_add<T>(lv[l - 1].n, uc, v.u[v.cur], s, nb);
             uc = nullptr;
         }
@@ -296,7 +299,8 @@ struct Multigrid {
             const SmootherShape b = shapes ? shapes->fused[l] : rbgs2_shape<T>(n);
             const int uf = shapes ? shapes->use_fused[l] : use_fused<T>(n);
             const int rr = shapes ? shapes->rr[l] : rr_variant<T>(n);
-            v.insert(v.end(), {a.variant, a.kchunk, b.variant, b.kchunk, uf, rr});
+            const int sp = shapes ? shapes->split[l] : split_prolong<T>(n);
+            v.insert(v.end(), {a.variant, a.kchunk, b.variant, b.kchunk, uf, rr, sp});
         }
         v.insert(v.end(), {fused ? 1 : 0, npre, npost});
         return v;

@@ -151,6 +151,74 @@ qumond_status tune_rr(int n, int reps, hipStream_t s, double us[qm::kRrVariants]
     return QUMOND_OK;
 }
 
+// Time the first post-smoothing launch of a level of n points with the
+// coarse-grid correction applied inside it (us[0]) against a prolong-add
+// launch followed by the same smoother launch without it (us[1]), in the
+// smoother form the tables choose for that level, and install the faster.
+template <typename T>
+qumond_status tune_split(int n, int reps, hipStream_t s, double us[2])
+{
+    const int nc = (n + 1) / 2;
+    const size_t N = (size_t)n * n * n, Nc = (size_t)nc * nc * nc;
+    T *f = nullptr, *u0 = nullptr, *u1 = nullptr, *uc = nullptr;
+    if (hipMalloc((void **)&f, N * sizeof(T)) != hipSuccess || hipMalloc((void **)&u0, N * sizeof(T)) != hipSuccess ||
+        hipMalloc((void **)&u1, N * sizeof(T)) != hipSuccess || hipMalloc((void **)&uc, Nc * sizeof(T)) != hipSuccess) {
+        (void)hipFree(f);
+        (void)hipFree(u0);
+        (void)hipFree(u1);
+        (void)hipFree(uc);
+        qm_set_last_error("qumond_autotune: allocation failed");
+        return QUMOND_ERR_OOM;
+    }
+    qm::launch_fill<T>(f, N, T(1), s);
+    qm::launch_fill<T>(u0, N, T(0.5), s);
+    qm::launch_fill<T>(u1, N, T(0.5), s);
+    qm::launch_fill<T>(uc, Nc, T(0.001), s);
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const double h = 1.0 / (n - 1);
+    const bool fz = qm::use_fused<T>(n) != 0;
+    for (int sp = 0; sp < 2; ++sp) {
+        auto run = [&](int r) {
+            T *a = (r & 1) ? u1 : u0, *b = (r & 1) ? u0 : u1;
+            const T *c = uc;
+            if (sp) {
+                qm::launch_prolong_add<T>(nc, uc, a, s);
+                c = nullptr;
+            }
+            if (fz) qm::launch_rbgs2<T>(n, h, f, a, b, c, s);
+            else qm::launch_rbgs<T>(n, h, f, a, b, s, 1, c);
+        };
+        run(0);
+        std::vector<float> t;
+        for (int r = 0; r < reps; ++r) {
+            (void)hipEventRecord(e0, s);
+            run(r);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            t.push_back(ms);
+        }
+        std::sort(t.begin(), t.end());
+        us[sp] = 1e3 * t[t.size() / 2];
+    }
+    qm::split_prolong<T>(n) = us[1] < us[0] ? 1 : 0;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(f);
+    (void)hipFree(u0);
+    (void)hipFree(u1);
+    (void)hipFree(uc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        qm_set_last_error(hipGetErrorString(e));
+        return QUMOND_ERR_HIP;
+    }
+    return QUMOND_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -208,6 +276,21 @@ qumond_status qumond_tune_get_rr(int32_t n, int32_t fp32, int32_t *variant)
     return QUMOND_OK;
 }
 
+qumond_status qumond_tune_set_split(int32_t n, int32_t fp32, int32_t split)
+{
+    if (!good_n(n) || split < 0 || split > 1) return tfail("qumond_tune_set_split: bad argument");
+    if (fp32) qm::split_prolong<float>(n) = split;
+    else qm::split_prolong<double>(n) = split;
+    return QUMOND_OK;
+}
+
+qumond_status qumond_tune_get_split(int32_t n, int32_t fp32, int32_t *split)
+{
+    if (!good_n(n) || !split) return tfail("qumond_tune_get_split: bad argument");
+    *split = fp32 ? qm::split_prolong<float>(n) : qm::split_prolong<double>(n);
+    return QUMOND_OK;
+}
+
 qumond_status qumond_k_rbgs_sweep_shape(int32_t n, double h, const double *f, const double *u_in, double *u_out,
                                         int32_t variant, int32_t kchunk, const double *uc, void *stream)
 {
@@ -258,11 +341,17 @@ qumond_status qumond_autotune(int32_t n_max, int32_t both, int32_t reps, const c
             const qumond_status st = prec ? tune_rr<float>(n, reps, s, rr_us) : tune_rr<double>(n, reps, s, rr_us);
             if (st != QUMOND_OK) return st;
             const int rrv = prec ? qm::rr_variant<float>(n) : qm::rr_variant<double>(n);
-            char buf[320];
+            double sp_us[2] = {};
+            const qumond_status st2 = prec ? tune_split<float>(n, reps, s, sp_us) : tune_split<double>(n, reps, s, sp_us);
+            if (st2 != QUMOND_OK) return st2;
+            const int spv = prec ? qm::split_prolong<float>(n) : qm::split_prolong<double>(n);
+            char buf[400];
             std::snprintf(buf, sizeof buf,
                           ", {\"n\": %d, \"fp32\": %d, \"use_fused\": %d}, {\"n\": %d, \"fp32\": %d, \"rr\": %d, "
-                          "\"rr_us\": [%.3f, %.3f, %.3f, %.3f, %.3f]}",
-                          n, prec, fuse, n, prec, rrv, rr_us[0], rr_us[1], rr_us[2], rr_us[3], rr_us[4]);
+                          "\"rr_us\": [%.3f, %.3f, %.3f, %.3f, %.3f]}, {\"n\": %d, \"fp32\": %d, \"split_prolong\": %d, "
+                          "\"us\": [%.3f, %.3f]}",
+                          n, prec, fuse, n, prec, rrv, rr_us[0], rr_us[1], rr_us[2], rr_us[3], rr_us[4], n, prec, spv,
+                          sp_us[0], sp_us[1]);
             js += buf;
         }
     }
@@ -316,6 +405,16 @@ qumond_status qumond_tune_load(const char *json_path)
             const int v = rrv >= 0 && rrv < qm::kRrVariants ? rrv : 0;
             if (fp32) qm::rr_variant<float>(n) = v;
             else qm::rr_variant<double>(n) = v;
+        }
+        ++pos;
+    }
+    pos = 0;
+    while ((pos = txt.find("{\"n\":", pos)) != std::string::npos) {
+        int n = 0, fp32 = 0, sp = 0;
+        if (std::sscanf(txt.c_str() + pos, "{\"n\": %d, \"fp32\": %d, \"split_prolong\": %d", &n, &fp32, &sp) == 3 &&
+            good_n(n)) {
+            if (fp32) qm::split_prolong<float>(n) = sp ? 1 : 0;
+            else qm::split_prolong<double>(n) = sp ? 1 : 0;
         }
         ++pos;
     }

@@ -130,6 +130,8 @@ _SIGNATURES = {
     "qumond_tune_load": (_I32, [ctypes.c_char_p]),
     "qumond_tune_set_rr": (_I32, [_I32, _I32, _I32]),
     "qumond_tune_get_rr": (_I32, [_I32, _I32, ctypes.POINTER(_I32)]),
+    "qumond_tune_set_split": (_I32, [_I32, _I32, _I32]),
+    "qumond_tune_get_split": (_I32, [_I32, _I32, ctypes.POINTER(_I32)]),
     "qumond_batch_default_config": (None, [ctypes.POINTER(qumond_batch_config)]),
     "qumond_batch_validate": (_I32, [ctypes.POINTER(qumond_batch_config), _P, _P, _I32]),
     "qumond_batch_create": (_I32, [ctypes.POINTER(qumond_batch_config), _P, _P, _I32, _P, ctypes.POINTER(_P)]),
@@ -493,6 +495,16 @@ def tune_set_rr(n, variant, fp32=False):
 def tune_get_rr(n, fp32=False):
     v = ctypes.c_int32()
     check(lib().qumond_tune_get_rr(int(n), int(bool(fp32)), ctypes.byref(v)), "qumond_tune_get_rr")
+    return v.value
+
+
+def tune_set_split(n, split, fp32=False):
+    check(lib().qumond_tune_set_split(int(n), int(bool(fp32)), int(split)), "qumond_tune_set_split")
+
+
+def tune_get_split(n, fp32=False):
+    v = ctypes.c_int32()
+    check(lib().qumond_tune_get_split(int(n), int(bool(fp32)), ctypes.byref(v)), "qumond_tune_get_split")
     return v.value
 
 

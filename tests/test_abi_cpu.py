@@ -90,6 +90,18 @@ def test_null_handles_and_arguments(Q):
     assert L.qumond_status_string(Q.QUMOND_ERR_STATE) == b"call out of order"
 
 
+def test_split_prolong_table_without_gpu(Q):
+    for n in (33, 129):
+        before = Q.tune_get_split(n)
+        Q.tune_set_split(n, 1 - before)
+        assert Q.tune_get_split(n) == 1 - before and Q.tune_get_split(n, fp32=True) in (0, 1)
+        Q.tune_set_split(n, before)
+    L = Q.lib()
+    assert L.qumond_tune_set_split(33, 0, 2) == Q.QUMOND_ERR_INVALID
+    assert L.qumond_tune_set_split(34, 0, 1) == Q.QUMOND_ERR_INVALID
+    assert L.qumond_tune_get_split(33, 0, None) == Q.QUMOND_ERR_INVALID
+
+
 # ------------------------------------------------------------ batches
 
 def _batch_args(Q, cfg, ns, R):

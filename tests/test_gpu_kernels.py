@@ -337,6 +337,8 @@ def test_autotune_installs_a_table(tmp_path):
     Q.tune_set(65, *before)
     Q.tune_load(str(tmp_path / "t.json"))
     assert Q.tune_get(65) in [(v, k) for v in Q.SMOOTHER_VARIANTS for k in (4, 8, 16, 32, 64, 128, 0)]
+    assert '"split_prolong"' in txt and all(Q.tune_get_split(n, fp32=fp) in (0, 1) for n in (33, 65)
+                                            for fp in (False, True))
 
 
 @pytest.mark.parametrize("n", [5, 9, 17, 33, 65, 129, 257])
