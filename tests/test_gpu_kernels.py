@@ -223,6 +223,26 @@ def test_fmg_fixed_schedule(n):
     assert rel(host(d), ref) < 1e-12
 
 
+@pytest.mark.parametrize("n", [5, 9, 17])
+def test_coarse_tail_repeatable(n):
+    """The single-workgroup coarse tail gives the same bits on every run, for
+    FMG and for V-cycles, and matches the oracle."""
+    L = 7.0
+    f, u = _bc_problem(n, L, 800 + n)
+    outs = []
+    for _ in range(3):
+        d = dev(u)
+        Q.k_fmg(dev(f), d, L, ncycle=3, max_extra=0, tol=0.0)
+        Q.k_vcycles(dev(f), d, L, 2)
+        outs.append(host(d))
+    ref = u.copy()
+    O.fmg(f, ref, L, ncycle=3, max_extra=0, tol=0.0)
+    O.vcycles(f, ref, L, 2)
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    assert rel(outs[0], ref) < 1e-12
+
+
 @pytest.mark.parametrize("n", [17, 65])
 def test_fmg_tolerance_stop_same_cycles(n):
     L = 1.0
