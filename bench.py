@@ -54,12 +54,14 @@ def smoother_traffic(per_launch_alg_bytes):
     return rec.get("bytes_per_launch")
 
 
-def mixed_vs_fp64(Q, synth, torch, np, dev, reps=3):
+def mixed_vs_fp64(Q, synth, torch, np, dev, reps=3, profile=False):
     """The metric's second part on the 513^3 workload (two-component disk,
     1e7 particles, 120 kpc box, monopole boundary): wall time of deposit +
     both solves (to 1e-6 FP64 relative residual) + gather, plain FP64 against
     FP32 multigrid with FP64 refinement, and the 513^3 smoother's HBM roofline
-    from the FP64 run's smoother launches."""
+    from the FP64 run's smoother launches.  With profile=True only the mixed
+    case runs, its timed repetitions between two 0.5 s host pauses (for a
+    kernel trace of them)."""
     n, L = 513, 120.0
     log("513^3 workload: 1e7 particles")
     p = synth.two_component_disk(10_000_000, synth.seed_for(3))
@@ -69,12 +71,14 @@ def mixed_vs_fp64(Q, synth, torch, np, dev, reps=3):
     Q.autotune(n_max=n, both=True, reps=3)
     # plain: the paper's 6 V-cycles per FMG level in FP64; same short schedule in FP64
     # for comparison; mixed: 2 FP32 cycles per FMG level, then FP64 refinement
-    for name, prec, ncyc in (("fp64", Q.QUMOND_FP64, 6), ("fp64_2cyc", Q.QUMOND_FP64, 2),
-                             ("mixed", Q.QUMOND_MIXED, 2)):
+    cases = (("fp64", Q.QUMOND_FP64, 6), ("fp64_2cyc", Q.QUMOND_FP64, 2), ("mixed", Q.QUMOND_MIXED, 2))
+    for name, prec, ncyc in (cases[2:] if profile else cases):
         ctx = Q.Context(Q.Config(n=n, box_side=[L], precision=prec, tol_rel=1e-6, ncycle_fmg=ncyc))
         times = []
         for r in range(reps + 1):
             torch.cuda.synchronize()
+            if profile and r == 1:
+                time.sleep(0.5)
             t0 = time.perf_counter()
             ctx.deposit(x, y, z, m, p.total_mass, count_outside=False)
             i_n, i_m = ctx.solve()
@@ -82,6 +86,8 @@ def mixed_vs_fp64(Q, synth, torch, np, dev, reps=3):
             torch.cuda.synchronize()
             if r:
                 times.append((time.perf_counter() - t0) * 1e3)
+        if profile:
+            time.sleep(0.5)
         rec = {"ms": float(np.median(times)), "ncycle_fmg": ncyc,
                "relres_newton": i_n["relres"][0], "relres_mond": i_m["relres"][0],
                "cycles_newton": i_n["vcycles"][0], "cycles_mond": i_m["vcycles"][0]}
@@ -101,6 +107,9 @@ def mixed_vs_fp64(Q, synth, torch, np, dev, reps=3):
         ctx.close()
         del ctx
         torch.cuda.empty_cache()
+    if profile:
+        log(f"513^3 mixed: {out['mixed']['ms']:.1f} ms per run")
+        return out
     out["mixed_err_vs_fp64"] = float(np.abs(fields["mixed"] - fields["fp64"]).max() / np.abs(fields["fp64"]).max())
     out["mixed_err_vs_fp64_2cyc"] = float(np.abs(fields["mixed"] - fields["fp64_2cyc"]).max() /
                                           np.abs(fields["fp64_2cyc"]).max())
@@ -301,6 +310,9 @@ def main():
                     help="1: the nested step replays its FMG schedules from captured HIP graphs (use_graphs); 0: eager")
     ap.add_argument("--batch-profile", action="store_true",
                     help="run only the batched-fit leg (for a kernel trace of its replays) and print its record")
+    ap.add_argument("--mixed-profile", action="store_true",
+                    help="run only the 513^3 mixed-precision case (timed runs between host pauses) and print its "
+                         "record")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device three times (the known-size kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -327,6 +339,10 @@ def main():
         return
     if args.batch_profile:
         print(json.dumps(batched_fit(Q, synth, torch, np, reps=2)), flush=True)
+        return
+    if args.mixed_profile:
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        print(json.dumps(mixed_vs_fp64(Q, synth, torch, np, dev, reps=2, profile=True)), flush=True)
         return
     n, sides, npart = 129, [400.0, 200.0, 100.0, 50.0], 1_000_000
     log(f"generating {npart} particles")

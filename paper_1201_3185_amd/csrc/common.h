@@ -109,13 +109,14 @@ constexpr int kBatchDepositBlocks = 64;   // deposit workgroups per problem
 
 // ---- grid_kernels.hip (templated on the storage type: double or float)
 // Smoother launch shape: tile variant (z-march over 0: 32x8, 1: 64x4, 2: 64x8,
-// 3: 128x4, 4: 32x16 columns; 5: 8^3 bricks) and the number of z planes one
+// 3: 128x4, 4: 32x16 columns; 5: 8^3 bricks; 6: 64x8, 7: 64x16, 8: 128x8
+// columns with one thread per x-pair of nodes) and the number of z planes one
 // workgroup marches through (ignored by bricks).
 struct SmootherShape {
     int variant;
     int kchunk;
 };
-constexpr int kSmootherVariants = 6;
+constexpr int kSmootherVariants = 9;
 constexpr int kRrVariants = 5;   // residual restriction: gather, LDS tile, z-march with 4/8/16-plane chunks
 constexpr int kFusedVariants = 3;   // two sweeps: 0: 32x8, 1: 64x4 z-march, 2: 8^3 bricks
 // Every grid launcher takes nb, the number of problems stored back to back

@@ -210,6 +210,201 @@ rbgs_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict
     }
 }
 
+// The same sweep with half the threads: each thread owns an x-pair of tile
+// nodes (columns 2q and 2q + 1 of its row), one red and one black on every
+// plane, so the black pass keeps every lane busy (rbgs_zmarch leaves the
+// lanes on red tile nodes idle there) and a plane needs half the thread
+// iterations per node between its two barriers.  The red pass covers the
+// tile plus a one-node ring (up to two red nodes per thread).  Node updates,
+// their order within a plane and the plane pipeline are those of
+// rbgs_zmarch, so the results agree bit for bit.
+template <typename T, int TX, int TY, bool PROLONG>
+__global__ void __launch_bounds__(TX *TY / 2)
+rbgs_zmarch_pair(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2, int kchunk,
+                 int nzc, const T *__restrict__ uc, int nc)
+{
+#pragma clang fp contract(off)
+    static_assert(TX % 2 == 0, "x-pairs");
+    constexpr int PX = TX + 4, PY = TY + 4, NS = 5, NT = TX * TY / 2;
+    constexpr int PL = PX * PY;
+    constexpr int NL = (PL + NT - 1) / NT;
+    constexpr int HALF = (TX + 2) / 2;            // red nodes per row of tile + one-node ring
+    constexpr int NRED = HALF * (TY + 2);
+    constexpr int RI = (NRED + NT - 1) / NT;      // red nodes per thread
+    constexpr int HX = TX / 2;                    // pairs per tile row
+    __shared__ T pl[NS][PL];
+    const T sixth = T(1) / T(6);
+    const int tid = threadIdx.x;
+    const unsigned tl = xcd_tile(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                 gridDim.x * gridDim.y * gridDim.z);
+    const int bx = tl % gridDim.x, by = (tl / gridDim.x) % gridDim.y, bzz = tl / (gridDim.x * gridDim.y);
+    const int i0 = 1 + bx * TX, j0 = 1 + by * TY;
+    const int pb = bzz / nzc;
+    const int kb = 1 + (bzz - pb * nzc) * kchunk;
+    if (kb > n - 2) return;
+    const int ke = min(kb + kchunk - 1, n - 2);
+    const size_t nn = (size_t)n * n;
+    uin += (size_t)pb * nn * n;
+    uout += (size_t)pb * nn * n;
+    f += (size_t)pb * nn * n;
+    if (PROLONG) uc += (size_t)pb * nc * nc * nc;
+
+    int goff[NL], gij[NL];
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+        const int t = tid + r * NT;
+        const int a = t % PX, b = t / PX;
+        const int i = i0 - 2 + a, j = j0 - 2 + b;
+        goff[r] = (t < PL && i >= 0 && i < n && j >= 0 && j < n) ? i + n * j : -1;
+        gij[r] = (goff[r] >= 0 && i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2) ? (i | (j << 16)) : -1;
+    }
+    auto corrected = [&](T x, int r, int k) {
+        if (PROLONG && k >= 1 && k <= n - 2 && gij[r] >= 0) x += prolong_at(nc, uc, gij[r] & 0xffff, gij[r] >> 16, k);
+        return x;
+    };
+    // this thread's red nodes (tile + ring): row br[r], column from the plane's parity
+    int br[RI], jr[RI], qr[RI];
+    bool rv[RI];
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+        const int t = tid + r * NT;
+        br[r] = 1 + t / HALF;
+        jr[r] = j0 - 2 + br[r];
+        qr[r] = t % HALF;
+        rv[r] = t < NRED && jr[r] >= 1 && jr[r] <= n - 2;
+    }
+    auto red_a = [&](int r, int k) { return ((((i0 - 1) + jr[r] + k) & 1) ? 2 : 1) + 2 * qr[r]; };
+    // this thread's pair of tile nodes: columns lo, lo + 1 of row bb
+    const int bb = 2 + tid / HX, lo = 2 + 2 * (tid % HX);
+    const int jb = j0 - 2 + bb, ilo = i0 - 2 + lo;
+    const bool row_ok = jb <= n - 2;
+    auto black_a = [&](int k) { return ((ilo + jb + k) & 1) ? lo : lo + 1; };
+
+    auto load_now = [&](int k) {
+        T *P = pl[k % NS];
+        const T *src = uin + (size_t)k * nn;
+#pragma unroll
+        for (int r = 0; r < NL; ++r) {
+            const int t = tid + r * NT;
+            if (t < PL) P[t] = goff[r] >= 0 ? corrected(src[goff[r]], r, k) : T(0);
+        }
+    };
+    T v[NL];
+    auto prefetch = [&](int k) {
+        const T *src = uin + (size_t)k * nn;
+#pragma unroll
+        for (int r = 0; r < NL; ++r) v[r] = goff[r] >= 0 ? corrected(src[goff[r]], r, k) : T(0);
+    };
+    auto commit = [&](int k) {
+        T *P = pl[k % NS];
+#pragma unroll
+        for (int r = 0; r < NL; ++r) {
+            const int t = tid + r * NT;
+            if (t < PL) P[t] = v[r];
+        }
+    };
+    auto f_red = [&](int k, T *fr) {
+#pragma unroll
+        for (int r = 0; r < RI; ++r) {
+            const int i = i0 - 2 + red_a(r, k);
+            fr[r] = (rv[r] && i >= 1 && i <= n - 2) ? f[(size_t)k * nn + i + (size_t)n * jr[r]] : T(0);
+        }
+    };
+    auto f_black = [&](int k) {
+        const int i = i0 - 2 + black_a(k);
+        return (row_ok && i <= n - 2) ? f[(size_t)k * nn + i + (size_t)n * jb] : T(0);
+    };
+    auto red = [&](int k, const T *fr) {
+        T *P = pl[k % NS];
+        const T *Pm = pl[(k - 1) % NS];
+        const T *Pp = pl[(k + 1) % NS];
+#pragma unroll
+        for (int r = 0; r < RI; ++r) {
+            const int a = red_a(r, k), i = i0 - 2 + a;
+            if (!rv[r] || i < 1 || i > n - 2) continue;
+            const int c = br[r] * PX + a;
+            const T s = P[c - 1] + P[c + 1] + P[c - PX] + P[c + PX] + Pm[c] + Pp[c];
+            P[c] = (s - h2 * fr[r]) * sixth;
+        }
+    };
+    auto black_store = [&](int k, T fv) {
+        if (!row_ok) return;
+        const T *P = pl[k % NS];
+        const T *Pm = pl[(k - 1) % NS];
+        const T *Pp = pl[(k + 1) % NS];
+        const int ab = black_a(k), ar = ab == lo ? lo + 1 : lo;
+        const int ib = i0 - 2 + ab, ir = i0 - 2 + ar;
+        T *dst = uout + (size_t)k * nn + (size_t)n * jb;
+        if (ib <= n - 2) {
+            const int c = bb * PX + ab;
+            const T s = P[c - 1] + P[c + 1] + P[c - PX] + P[c + PX] + Pm[c] + Pp[c];
+            dst[ib] = (s - h2 * fv) * sixth;
+        }
+        if (ir <= n - 2) dst[ir] = P[bb * PX + ar];
+    };
+
+    // warm-up: planes kb-2..kb+2 and red of kb-1..kb+1
+    if (kb >= 2) load_now(kb - 2);
+    load_now(kb - 1);
+    load_now(kb);
+    load_now(kb + 1);
+    if (kb + 2 <= n - 1) load_now(kb + 2);
+    T fr0[RI], fr1[RI], fr2[RI];
+#pragma unroll
+    for (int r = 0; r < RI; ++r) fr0[r] = fr2[r] = T(0);
+    if (kb - 1 >= 1) f_red(kb - 1, fr0);
+    f_red(kb, fr1);
+    if (kb + 1 <= n - 2) f_red(kb + 1, fr2);
+    __syncthreads();
+    if (kb - 1 >= 1) red(kb - 1, fr0);
+    red(kb, fr1);
+    if (kb + 1 <= n - 2) red(kb + 1, fr2);
+    __syncthreads();
+
+    auto need_red = [&](int k) { return (k + 2 <= n - 2) && (k + 2 <= ke + 1); };  // red(k+2) in iteration k
+    T fr_next[RI], fr[RI];
+#pragma unroll
+    for (int r = 0; r < RI; ++r) fr_next[r] = T(0);
+    T fb_next = f_black(kb);
+    if (need_red(kb)) {
+        prefetch(kb + 3);
+        f_red(kb + 2, fr_next);
+    }
+    for (int k = kb; k <= ke; ++k) {
+        const bool more = need_red(k);
+        if (more) commit(k + 3);
+        const T fb = fb_next;
+#pragma unroll
+        for (int r = 0; r < RI; ++r) fr[r] = fr_next[r];
+        if (k + 1 <= ke) {
+            fb_next = f_black(k + 1);
+            if (need_red(k + 1)) {
+                prefetch(k + 4);
+                f_red(k + 3, fr_next);
+            }
+        }
+        black_store(k, fb);
+        __syncthreads();
+        if (more) red(k + 2, fr);
+        __syncthreads();
+    }
+}
+
+template <typename T, int TX, int TY>
+static void rbgs_pair_launch(int n, double h, const T *f, const T *uin, T *uout, int kchunk, int nb, const T *uc,
+                             hipStream_t s)
+{
+    const int m = n - 2;
+    const int nzc = (m + kchunk - 1) / kchunk;
+    dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, nzc * nb);
+    if (uc)
+        hipLaunchKernelGGL((rbgs_zmarch_pair<T, TX, TY, true>), grid, dim3(TX * TY / 2), 0, s, uin, uout, f, n,
+                           T(h * h), kchunk, nzc, uc, (n + 1) / 2);
+    else
+        hipLaunchKernelGGL((rbgs_zmarch_pair<T, TX, TY, false>), grid, dim3(TX * TY / 2), 0, s, uin, uout, f, n,
+                           T(h * h), kchunk, nzc, uc, (n + 1) / 2);
+}
+
 template <typename T, int TX, int TY>
 static void rbgs_launch(int n, double h, const T *f, const T *uin, T *uout, int kchunk, int nb, const T *uc,
                         hipStream_t s)
@@ -581,6 +776,9 @@ void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, Smoot
     case 3: rbgs_launch<T, 128, 4>(n, h, f, uin, uout, kc, nb, uc, s); break;
     case 4: rbgs_launch<T, 32, 16>(n, h, f, uin, uout, kc, nb, uc, s); break;
     case 5: brick_launch<T, 1>(n, h, f, uin, uout, uc, nb, s); break;
+    case 6: rbgs_pair_launch<T, 64, 8>(n, h, f, uin, uout, kc, nb, uc, s); break;
+    case 7: rbgs_pair_launch<T, 64, 16>(n, h, f, uin, uout, kc, nb, uc, s); break;
+    case 8: rbgs_pair_launch<T, 128, 8>(n, h, f, uin, uout, kc, nb, uc, s); break;
     default: rbgs_launch<T, 64, 4>(n, h, f, uin, uout, kc, nb, uc, s); break;
     }
 }
