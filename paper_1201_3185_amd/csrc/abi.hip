@@ -43,7 +43,9 @@ struct Mixed {
     qm::Multigrid<float> mg;
     float *a[2] = {nullptr, nullptr};
     float *r = nullptr;
-    double *sc = nullptr;   // refinement scale s and 1/s (device)
+    double *sc = nullptr;   // two slots of the refinement scale s and 1/s (device)
+    int cur = 0;            // slot of the scale r was formed with
+    bool fresh = false;     // r holds the scaled residual of the current iterate
 };
 
 struct Box {
@@ -247,7 +249,7 @@ qumond_status qumond_create(const qumond_config *cfg, void *hip_stream, qumond_c
           (e = c->alloc((void **)&c->mix.a[0], c->N * sizeof(float))) != hipSuccess ||
           (e = c->alloc((void **)&c->mix.a[1], c->N * sizeof(float))) != hipSuccess ||
           (e = c->alloc((void **)&c->mix.r, c->N * sizeof(float))) != hipSuccess ||
-          (e = c->alloc((void **)&c->mix.sc, 2 * sizeof(double))) != hipSuccess))) {
+          (e = c->alloc((void **)&c->mix.sc, 4 * sizeof(double))) != hipSuccess))) {
         qumond_status r = hip_fail(e, "qumond_create: allocation");
         qumond_destroy(c);
         return r;
@@ -396,21 +398,34 @@ static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int 
         qm::launch_bc_from_coarse(ctx->n, uc, u, ch.scratch, ch.s);
     }
     ch.mg->bind(B.L, u, ch.scratch, f);
+    ch.mg->set_r32(nullptr, nullptr);
+    ch.mix->fresh = false;
     double rr = 0.0, rr0 = 0.0;
     int extra = 0;
     hipError_t e;
     // One FP64 residual-correction step of the mixed solve: the FP64 residual
     // scaled by its RMS (from the norms of the last relres), one FP32 V-cycle
     // on it with zero boundary values, the scaled correction added in FP64.
+    // The norms pass that follows a step (the relres() of the loop) also forms
+    // the next step's right-hand side, scaled by the power of two from the
+    // norms before the step's correction (any power of two gives the same
+    // corrected iterate), so only the first step forms it separately.
     auto refine_step = [&]() {
         Mixed &X = *ch.mix;
-        qm::launch_mixed_scale(ctx->n, ch.mg->norms, X.sc, ch.s);
-        qm::launch_resid_to_f32(ctx->n, B.h, X.sc, f, u, X.r, ch.s);
+        double *sc = X.sc + 2 * X.cur;
+        if (!X.fresh) {
+            qm::launch_mixed_scale(ctx->n, ch.mg->norms, sc, ch.s);
+            qm::launch_resid_to_f32(ctx->n, B.h, sc, f, u, X.r, ch.s);
+        }
         qm::launch_fill<float>(X.a[0], ctx->N, 0.0f, ch.s);
         qm::launch_fill<float>(X.a[1], ctx->N, 0.0f, ch.s);
         X.mg.bind(B.L, X.a[0], X.a[1], X.r);
         X.mg.finest_cycle();
-        qm::launch_correct(ctx->n, X.sc, X.mg.result(), u, ch.s);
+        qm::launch_correct(ctx->n, sc, X.mg.result(), u, ch.s);
+        X.cur ^= 1;
+        qm::launch_mixed_scale(ctx->n, ch.mg->norms, X.sc + 2 * X.cur, ch.s);
+        ch.mg->set_r32(X.sc + 2 * X.cur, X.r);
+        X.fresh = true;
     };
     const bool mixed = c.precision == QUMOND_MIXED;
     if (guess) {
@@ -574,7 +589,7 @@ static qumond_status ensure_chain2(qumond_ctx *ctx)
          (e = ctx->alloc((void **)&ctx->mix2.a[0], ctx->N * sizeof(float))) != hipSuccess ||
          (e = ctx->alloc((void **)&ctx->mix2.a[1], ctx->N * sizeof(float))) != hipSuccess ||
          (e = ctx->alloc((void **)&ctx->mix2.r, ctx->N * sizeof(float))) != hipSuccess ||
-         (e = ctx->alloc((void **)&ctx->mix2.sc, 2 * sizeof(double))) != hipSuccess))
+         (e = ctx->alloc((void **)&ctx->mix2.sc, 4 * sizeof(double))) != hipSuccess))
         return hip_fail(e, "qumond_solve: allocation");
     for (int b = 0; b < ctx->cfg.nbox; ++b)
         if ((e = hipEventCreateWithFlags(&ctx->ev_newton[b], hipEventDisableTiming)) != hipSuccess)

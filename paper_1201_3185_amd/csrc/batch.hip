@@ -154,15 +154,23 @@ void enqueue_solve(const qumond_batch *B, Class &C, qm::Multigrid<float> &mg, bo
     mg.fmg(c.ncycle_fmg);
     qm::launch_widen_interior(C.n, mg.result(), u, s, nb);
     qm::launch_resid_norms<double>(C.n, C.h, f, u, C.partial, hist_slot(B, C, mond, 0, p0), s, nb);
+    // Scales in two slots of 2 nb doubles: step k corrects with the scale its
+    // right-hand side was formed with, and its norms pass forms the next
+    // right-hand side with the power of two from the norms before its correction.
+    double *const scs[2] = {C.sc, C.sc + 2 * (size_t)C.P};
     for (int k = 1; k <= K; ++k) {
-        qm::launch_mixed_scale(C.n, hist_slot(B, C, mond, k - 1, p0), C.sc, s, nb);
-        qm::launch_resid_to_f32(C.n, C.h, C.sc, f, u, C.r, s, nb);
+        double *cur = scs[(k - 1) & 1], *next = scs[k & 1];
+        if (k == 1) {
+            qm::launch_mixed_scale(C.n, hist_slot(B, C, mond, 0, p0), cur, s, nb);
+            qm::launch_resid_to_f32(C.n, C.h, cur, f, u, C.r, s, nb);
+        }
         qm::launch_fill<float>(C.a[0], cnt, 0.0f, s);
         qm::launch_fill<float>(C.a[1], cnt, 0.0f, s);
         mg.bind(c.box_side, C.a[0], C.a[1], C.r);
         mg.finest_cycle();
-        qm::launch_correct(C.n, C.sc, mg.result(), u, s, nb);
-        qm::launch_resid_norms<double>(C.n, C.h, f, u, C.partial, hist_slot(B, C, mond, k, p0), s, nb);
+        qm::launch_correct(C.n, cur, mg.result(), u, s, nb);
+        qm::launch_mixed_scale(C.n, hist_slot(B, C, mond, k - 1, p0), next, s, nb);
+        qm::launch_resid_norms_r32(C.n, C.h, f, u, C.partial, hist_slot(B, C, mond, k, p0), next, C.r, s, nb);
     }
 }
 
@@ -536,7 +544,7 @@ qumond_status qumond_batch_create(const qumond_batch_config *cfg, const int32_t 
         const size_t nh = (size_t)2 * (K + 1) * C.P * 3;
         BCHK(B->alloc((void **)&C.hist, nh * sizeof(double)));
         BCHK(B->alloc_host((void **)&C.hhist, nh * sizeof(double)));
-        BCHK(B->alloc((void **)&C.sc, (size_t)C.P * 2 * sizeof(double)));
+        BCHK(B->alloc((void **)&C.sc, (size_t)C.P * 4 * sizeof(double)));
         BCHK(B->alloc((void **)&C.dep, qm::deposit_batch_scratch_bytes(C.P)));
         BCHK(B->alloc((void **)&C.inside, (size_t)C.P * sizeof(unsigned long long)));
         BCHK(B->alloc_host((void **)&C.hinside, (size_t)C.P * sizeof(unsigned long long)));

@@ -179,6 +179,10 @@ void launch_narrow(const double *src, float *dst, size_t count, hipStream_t s);
 void launch_narrow_boundary(int n, const double *src, float *d0, float *d1, hipStream_t s, int nb = 1);
 void launch_widen_interior(int n, const float *src, double *dst, hipStream_t s, int nb = 1);
 void launch_mixed_scale(int n, const double *norms, double *sc, hipStream_t s, int nb = 1);
+// The residual norms (as launch_resid_norms) and, in the same pass, the
+// residual times 1/s (sc per problem) rounded to FP32 at interior nodes.
+void launch_resid_norms_r32(int n, double h, const double *f, const double *u, double *partial, double *out,
+                            const double *sc, float *r32, hipStream_t s, int nb = 1);
 void launch_resid_to_f32(int n, double h, const double *sc, const double *f, const double *u, float *r, hipStream_t s,
                          int nb = 1);
 void launch_correct(int n, const double *sc, const float *e, double *u, hipStream_t s, int nb = 1);

@@ -1586,10 +1586,14 @@ __device__ __forceinline__ void block_sum3(double *sh, double &a, double &b, dou
 // which scales the stopping test of a source-free box.  A workgroup is 4 rows
 // of 64 lanes: each lane row walks x along one interior (j, k) row (coalesced),
 // the workgroups stride over the rows; the summation order depends only on n
-// and the block count, so the norms are reproducible bit for bit.
-template <typename T>
+// and the block count, so the norms are reproducible bit for bit.  With R32
+// the pass also writes the residual times 1/s (sc[2p + 1]) rounded to FP32 at
+// every interior node, the right-hand side of the next refinement step of a
+// mixed solve (the value resid_to_f32_k forms, saving that pass).
+template <typename T, bool R32>
 __global__ void __launch_bounds__(256)
-resid_norms_partial_k(int n, double ih2, const T *__restrict__ f, const T *__restrict__ u, double *__restrict__ partial)
+resid_norms_partial_k(int n, double ih2, const T *__restrict__ f, const T *__restrict__ u, double *__restrict__ partial,
+                      const double *__restrict__ sc, float *__restrict__ r32)
 {
     __shared__ double sh[768];
     const int m = n - 2;
@@ -1598,6 +1602,11 @@ resid_norms_partial_k(int n, double ih2, const T *__restrict__ f, const T *__res
     f += blockIdx.y * sz * n;
     u += blockIdx.y * sz * n;
     partial += blockIdx.y * 3 * (size_t)gridDim.x;
+    double inv_s = 0.0;
+    if (R32) {
+        r32 += blockIdx.y * sz * n;
+        inv_s = sc[2 * blockIdx.y + 1];
+    }
     const int lane = threadIdx.x & 63, ty = threadIdx.x >> 6;
     double sr = 0.0, sf = 0.0, sb = 0.0;
     for (unsigned r = blockIdx.x * 4u + (unsigned)ty; r < rows; r += gridDim.x * 4u) {
@@ -1611,6 +1620,7 @@ resid_norms_partial_k(int n, double ih2, const T *__restrict__ f, const T *__res
             const double lap = (um + up + vm + vp + wm + wp - 6.0 * (double)u[p]) * ih2;
             const double fv = (double)f[p];
             const double res = fv - lap;
+            if (R32) r32[p] = (float)(res * inv_s);
             sr += res * res;
             sf += fv * fv;
             if (jk_edge || i == 1 || i == n - 2) {
@@ -1653,7 +1663,18 @@ void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial
     // about 8 four-row groups per workgroup, at most kNormBlocks workgroups per problem
     const long long rows = (long long)(n - 2) * (n - 2);
     const int blocks = (int)std::min<long long>(kNormBlocks, std::max<long long>(1, (rows + 31) / 32));
-    hipLaunchKernelGGL(resid_norms_partial_k<T>, dim3(blocks, nb), dim3(256), 0, s, n, 1.0 / (h * h), f, u, partial);
+    hipLaunchKernelGGL((resid_norms_partial_k<T, false>), dim3(blocks, nb), dim3(256), 0, s, n, 1.0 / (h * h), f, u,
+                       partial, nullptr, nullptr);
+    hipLaunchKernelGGL(norms_final_k, dim3(nb), dim3(256), 0, s, partial, blocks, out);
+}
+
+void launch_resid_norms_r32(int n, double h, const double *f, const double *u, double *partial, double *out,
+                            const double *sc, float *r32, hipStream_t s, int nb)
+{
+    const long long rows = (long long)(n - 2) * (n - 2);
+    const int blocks = (int)std::min<long long>(kNormBlocks, std::max<long long>(1, (rows + 31) / 32));
+    hipLaunchKernelGGL((resid_norms_partial_k<double, true>), dim3(blocks, nb), dim3(256), 0, s, n, 1.0 / (h * h), f,
+                       u, partial, sc, r32);
     hipLaunchKernelGGL(norms_final_k, dim3(nb), dim3(256), 0, s, partial, blocks, out);
 }
 
@@ -1661,9 +1682,15 @@ void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial
 //
 // FP64 residual-correction refinement around FP32 multigrid: the FP64 iterate
 // is corrected by s e where e solves A e = r / s in FP32 (zero Dirichlet
-// values) and s is the RMS of the FP64 residual r = f - A u over the interior
-// (1 if that is 0 or not finite).  s and 1/s are computed on the device from
-// the residual norms, so no host round trip sits between the steps.
+// values) and s is the power of two at or below the RMS of the FP64 residual
+// r = f - A u over the interior (1 if that is 0 or not finite).  Scaling by a
+// power of two is exact, and every FP32 multigrid operation commutes with it,
+// so the corrected iterate does not depend on which power of two scales a
+// step (values far from the FP32 subnormal range): a step may take its scale
+// from the norms before the previous correction, which lets the norms pass
+// of one step write the next step's scaled residual.  s and 1/s are computed
+// on the device from the residual norms, so no host round trip sits between
+// the steps.
 
 __global__ void narrow_k(const double *__restrict__ src, float *__restrict__ dst, size_t count)
 {
@@ -1702,9 +1729,9 @@ __global__ void mixed_scale_k(int n, int nb, const double *__restrict__ norms, d
     if (p >= nb) return;
     const double nint = (double)(n - 2) * (double)(n - 2) * (double)(n - 2);
     const double rms = sqrt(norms[3 * p] / nint);
-    const double s = (rms > 0.0 && isfinite(rms)) ? rms : 1.0;
-    sc[2 * p] = s;
-    sc[2 * p + 1] = 1.0 / s;
+    const int e = (rms > 0.0 && isfinite(rms)) ? ilogb(rms) : 0;
+    sc[2 * p] = ldexp(1.0, e);
+    sc[2 * p + 1] = ldexp(1.0, -e);
 }
 
 // r32 = (f - A_h u) / s in FP64, rounded to FP32, at interior nodes; 0 on the boundary

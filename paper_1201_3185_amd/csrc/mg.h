@@ -101,6 +101,8 @@ struct Multigrid {
     bool fused = true;   // two sweeps per launch where possible
     double last_r2 = 0.0;  // sum of squared residuals of the last relres()
     bool use_graphs = false;   // replay fmg_norms / cycle_norms from captured graphs
+    const double *r32_sc = nullptr;   // set_r32: the next norms pass also writes r32_out
+    float *r32_out = nullptr;
 
     struct GraphEntry {
         int kind;                        // 0: FMG + norms, 1: finest cycle + norms
@@ -263,11 +265,26 @@ struct Multigrid {
         }
     }
 
-    // Residual norms of the finest level of every problem into norms (device).
+    // Residual norms of the finest level of every problem into norms (device);
+    // after set_r32 the next norms pass (once) also writes the residual times
+    // 1/s, rounded to FP32, to r32 (FP64 hierarchies only).
     void device_norms()
     {
         Level<T> &F = lv[J];
+        if constexpr (sizeof(T) == 8) {
+            if (r32_out) {
+                launch_resid_norms_r32(F.n, F.h, F.f, F.u[F.cur], partial, norms, r32_sc, r32_out, s, nb);
+                r32_sc = nullptr;
+                r32_out = nullptr;
+                return;
+            }
+        }
         launch_resid_norms<T>(F.n, F.h, F.f, F.u[F.cur], partial, norms, s, nb);
+    }
+    void set_r32(const double *sc, float *r)
+    {
+        r32_sc = sc;
+        r32_out = r;
     }
 
     // Enqueue the residual norms of the finest level into host_norms (needs a

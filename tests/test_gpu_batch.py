@@ -173,6 +173,29 @@ def test_zmarch_residual_restriction_over_stacked_problems():
             Q.tune_set_rr(n, v, fp32=fp)
 
 
+def test_power_of_two_scales_give_the_same_iterate():
+    """Refinement scales are powers of two, so the corrected iterate does not
+    depend on which one scales a step: the context forms each step's FP32
+    right-hand side in the norms pass of the step before (scale from the norms
+    before that step's correction), the batch's tail steps form it separately
+    from the current norms, and both reach the same bits after the same
+    number of steps."""
+    n = 65
+    p = small_disks([n], seed0=1200)[0]
+    b = make_batch([n], [p], refine_iters=1, tol_rel=1e-9, max_extra=30)
+    info = b.run(use_graph=True)[0]
+    assert info["converged"] == 1 and info["steps_newton"] > 2 and info["steps_mond"] > 2
+    ctx = Q.Context(Q.Config(n=n, box_side=[L_BOX], precision=Q.QUMOND_MIXED, ncycle_fmg=2, tol_rel=1e-9,
+                             max_vcycles=31))
+    ctx.deposit(dev(p.x), dev(p.y), dev(p.z), dev(p.m), p.total_mass)
+    i_n, i_m = ctx.solve()
+    assert i_n["refine_iters"][0] == info["steps_newton"] and i_m["refine_iters"][0] == info["steps_mond"]
+    for fld in (Q.FIELD_PHI_N, Q.FIELD_PHI):
+        assert np.array_equal(b.get_field(0, fld).cpu().numpy(), ctx.get_field(0, fld).cpu().numpy())
+    ctx.close()
+    b.close()
+
+
 def test_batch_against_oracle():
     ns = [33, 65]
     parts = small_disks(ns, seed0=500)
