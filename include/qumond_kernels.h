@@ -26,6 +26,15 @@ extern "C" {
 qumond_status qumond_k_rbgs_sweep(int32_t n, double h, const double *f, const double *u_in, double *u_out,
                                   void *stream);
 
+/* The sweep of qumond_k_rbgs_sweep from a zero iterate with zero boundary
+ * values, without an input array: writes the interior of u_out (n^3 doubles,
+ * device; its boundary nodes must already hold zeros) -- bit for bit the
+ * result of qumond_k_rbgs_sweep on a zero-filled u_in, with red nodes at
+ * (0 - h^2 f)/6.  The first smoothing sweep of a correction V-cycle (Sec. 2's
+ * multigrid, in this build's mixed-precision refinement).  Errors: n not
+ * 2^J + 1 in 5..1025, h <= 0 or a NULL pointer -> QUMOND_ERR_INVALID. */
+qumond_status qumond_k_rbgs_sweep_from_zero(int32_t n, double h, const double *f, double *u_out, void *stream);
+
 /* Two sweeps in one launch (same result, bit for bit, as two calls of
  * qumond_k_rbgs_sweep).  uc (optional): a coarse grid of (n+1)/2 points per side
  * whose trilinear prolongation is added to u_in's interior first, as the

@@ -54,7 +54,8 @@ qumond_status qumond_tune_get_split(int32_t n, int32_t fp32, int32_t *split);
 
 /* One smoother sweep with an explicit shape (see qumond_k_rbgs_sweep); with
  * uc != NULL (device, ((n+1)/2)^3 doubles) the correction u += P uc is applied
- * to u_in's interior first, in the same launch. */
+ * to u_in's interior first, in the same launch.  u_in == NULL stands for a zero
+ * iterate (boundary included), read from nowhere. */
 qumond_status qumond_k_rbgs_sweep_shape(int32_t n, double h, const double *f, const double *u_in, double *u_out,
                                         int32_t variant, int32_t kchunk, const double *uc, void *stream);
 

@@ -417,9 +417,14 @@ static qumond_status solve_box(qumond_ctx *ctx, const Chain &ch, bool mond, int 
             qm::launch_mixed_scale(ctx->n, ch.mg->norms, sc, ch.s);
             qm::launch_resid_to_f32(ctx->n, B.h, sc, f, u, X.r, ch.s);
         }
-        qm::launch_fill<float>(X.a[0], ctx->N, 0.0f, ch.s);
-        qm::launch_fill<float>(X.a[1], ctx->N, 0.0f, ch.s);
+        // zero correction iterate: the buffers are cleared on the first step of
+        // a solve; later steps' first sweeps read no iterate
         X.mg.bind(B.L, X.a[0], X.a[1], X.r);
+        if (!X.fresh || !X.mg.zero_start_ok()) {
+            qm::launch_fill<float>(X.a[0], ctx->N, 0.0f, ch.s);
+            qm::launch_fill<float>(X.a[1], ctx->N, 0.0f, ch.s);
+        }
+        X.mg.zero_start = X.mg.zero_start_ok();
         X.mg.finest_cycle();
         qm::launch_correct(ctx->n, sc, X.mg.result(), u, ch.s);
         X.cur ^= 1;

@@ -164,9 +164,14 @@ void enqueue_solve(const qumond_batch *B, Class &C, qm::Multigrid<float> &mg, bo
             qm::launch_mixed_scale(C.n, hist_slot(B, C, mond, 0, p0), cur, s, nb);
             qm::launch_resid_to_f32(C.n, C.h, cur, f, u, C.r, s, nb);
         }
-        qm::launch_fill<float>(C.a[0], cnt, 0.0f, s);
-        qm::launch_fill<float>(C.a[1], cnt, 0.0f, s);
+        // zero correction iterate: the buffers (boundaries left by the FMG) are
+        // cleared once; later steps' first sweeps read no iterate
         mg.bind(c.box_side, C.a[0], C.a[1], C.r);
+        if (k == 1 || !mg.zero_start_ok()) {
+            qm::launch_fill<float>(C.a[0], cnt, 0.0f, s);
+            qm::launch_fill<float>(C.a[1], cnt, 0.0f, s);
+        }
+        mg.zero_start = mg.zero_start_ok();
         mg.finest_cycle();
         qm::launch_correct(C.n, cur, mg.result(), u, s, nb);
         qm::launch_mixed_scale(C.n, hist_slot(B, C, mond, k - 1, p0), next, s, nb);
@@ -232,9 +237,12 @@ hipError_t tail_steps(qumond_batch *B, Class &C, bool mond, int p, const double 
     while (rr > c.tol_rel && steps < c.max_extra) {
         qm::launch_mixed_scale(C.n, last, C.sc1, s, 1);
         qm::launch_resid_to_f32(C.n, C.h, C.sc1, f, u, C.r, s, 1);
-        qm::launch_fill<float>(C.a[0], C.N, 0.0f, s);
-        qm::launch_fill<float>(C.a[1], C.N, 0.0f, s);
         mg.bind(c.box_side, C.a[0], C.a[1], C.r);
+        if (steps == 0 || !mg.zero_start_ok()) {
+            qm::launch_fill<float>(C.a[0], C.N, 0.0f, s);
+            qm::launch_fill<float>(C.a[1], C.N, 0.0f, s);
+        }
+        mg.zero_start = mg.zero_start_ok();
         mg.finest_cycle();
         qm::launch_correct(C.n, C.sc1, mg.result(), u, s, 1);
         qm::launch_resid_norms<double>(C.n, C.h, f, u, C.partial, C.norms1, s, 1);

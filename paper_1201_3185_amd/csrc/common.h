@@ -123,7 +123,9 @@ constexpr int kFusedVariants = 3;   // two sweeps: 0: 32x8, 1: 64x4 z-march, 2: 
 // (problem p of a level with n points per side at offset p n^3); nb = 1 is the
 // single-problem case.
 // One sweep; with uc != NULL the correction u += P uc (uc on the next coarser
-// level) is applied first, in the same launch.
+// level) is applied first, in the same launch.  A null uin stands for a zero
+// iterate (boundary included) in the single-sweep kernels (z-march, pair
+// z-march, brick), which then read no iterate at all.
 template <typename T> void launch_rbgs(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s, int nb = 1,
                                       const T *uc = nullptr);
 template <typename T> void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, SmootherShape sh,

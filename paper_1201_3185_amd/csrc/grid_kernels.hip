@@ -113,20 +113,21 @@ rbgs_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict
     const int i_b = i0 - 2 + a_b, j_b = j0 - 2 + b_b;
     const bool tile_thread = i_b <= n - 2 && j_b <= n - 2;
 
+    // a null uin is a zero iterate (boundary included), read from nowhere
     auto load_now = [&](int k) {
         T *P = pl[k % NS];
-        const T *src = uin + (size_t)k * nn;
+        const T *src = uin ? uin + (size_t)k * nn : nullptr;
 #pragma unroll
         for (int r = 0; r < NL; ++r) {
             const int t = tid + r * NT;
-            if (t < PL) P[t] = goff[r] >= 0 ? corrected(src[goff[r]], r, k) : T(0);
+            if (t < PL) P[t] = goff[r] >= 0 ? corrected(src ? src[goff[r]] : T(0), r, k) : T(0);
         }
     };
     T v[NL];
     auto prefetch = [&](int k) {
-        const T *src = uin + (size_t)k * nn;
+        const T *src = uin ? uin + (size_t)k * nn : nullptr;
 #pragma unroll
-        for (int r = 0; r < NL; ++r) v[r] = goff[r] >= 0 ? corrected(src[goff[r]], r, k) : T(0);
+        for (int r = 0; r < NL; ++r) v[r] = goff[r] >= 0 ? corrected(src ? src[goff[r]] : T(0), r, k) : T(0);
     };
     auto commit = [&](int k) {
         T *P = pl[k % NS];
@@ -280,20 +281,21 @@ rbgs_zmarch_pair(const T *__restrict__ uin, T *__restrict__ uout, const T *__res
     const bool row_ok = jb <= n - 2;
     auto black_a = [&](int k) { return ((ilo + jb + k) & 1) ? lo : lo + 1; };
 
+    // a null uin is a zero iterate (boundary included), read from nowhere
     auto load_now = [&](int k) {
         T *P = pl[k % NS];
-        const T *src = uin + (size_t)k * nn;
+        const T *src = uin ? uin + (size_t)k * nn : nullptr;
 #pragma unroll
         for (int r = 0; r < NL; ++r) {
             const int t = tid + r * NT;
-            if (t < PL) P[t] = goff[r] >= 0 ? corrected(src[goff[r]], r, k) : T(0);
+            if (t < PL) P[t] = goff[r] >= 0 ? corrected(src ? src[goff[r]] : T(0), r, k) : T(0);
         }
     };
     T v[NL];
     auto prefetch = [&](int k) {
-        const T *src = uin + (size_t)k * nn;
+        const T *src = uin ? uin + (size_t)k * nn : nullptr;
 #pragma unroll
-        for (int r = 0; r < NL; ++r) v[r] = goff[r] >= 0 ? corrected(src[goff[r]], r, k) : T(0);
+        for (int r = 0; r < NL; ++r) v[r] = goff[r] >= 0 ? corrected(src ? src[goff[r]] : T(0), r, k) : T(0);
     };
     auto commit = [&](int k) {
         T *P = pl[k % NS];
@@ -460,7 +462,7 @@ rbgs_brick(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict_
         const int i = i0 + a, j = j0 + b, k = k0 + c;
         T x = T(0);
         if (i >= 0 && i < n && j >= 0 && j < n && k >= 0 && k < n) {
-            x = uin[id3(n, i, j, k)];
+            x = uin ? uin[id3(n, i, j, k)] : T(0);   // a null uin is a zero iterate
             if (PROLONG && i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2 && k >= 1 && k <= n - 2)
                 x += prolong_at(nc, uc, i, j, k);
         }

@@ -35,6 +35,13 @@ qumond_status qumond_k_rbgs_sweep(int32_t n, double h, const double *f, const do
     return kcheck("qumond_k_rbgs_sweep");
 }
 
+qumond_status qumond_k_rbgs_sweep_from_zero(int32_t n, double h, const double *f, double *u_out, void *stream)
+{
+    if (!good_n(n) || !(h > 0.0) || !f || !u_out) return kfail("qumond_k_rbgs_sweep_from_zero: bad argument");
+    qm::launch_rbgs<double>(n, h, f, nullptr, u_out, (hipStream_t)stream);
+    return kcheck("qumond_k_rbgs_sweep_from_zero");
+}
+
 qumond_status qumond_k_rbgs_double_sweep(int32_t n, double h, const double *f, const double *u_in, double *u_out,
                                          const double *uc, void *stream)
 {

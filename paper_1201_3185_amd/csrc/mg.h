@@ -102,6 +102,12 @@ struct Multigrid {
     double last_r2 = 0.0;  // sum of squared residuals of the last relres()
     bool use_graphs = false;   // replay fmg_norms / cycle_norms from captured graphs
     const double *r32_sc = nullptr;   // set_r32: the next norms pass also writes r32_out
+    // set by a caller whose finest iterate is zero before a finest_cycle():
+    // its first sweep reads no iterate (the smoother's null input), so the
+    // caller need not fill the interiors again; both ping-pong buffers'
+    // boundaries must hold zeros.  Valid where zero_start_ok().
+    bool zero_start = false;
+    bool zero_start_ok() const { return J > lt && npre > 0; }
     float *r32_out = nullptr;
 
     struct GraphEntry {
@@ -195,6 +201,13 @@ struct Multigrid {
     {
         Level<T> &v = lv[l];
         const double pts = (double)v.n * v.n * v.n;
+        if (zero_start && l == J && ns > 0 && !uc) {   // the iterate is zero: first sweep without reading it
+            const SmootherShape sh = shapes ? shapes->single[l] : rbgs_shape<T>(v.n);
+            launch_rbgs_shape<T>(v.n, v.h, v.f, nullptr, v.u[1 - v.cur], sh, s, nb);
+            v.cur ^= 1;
+            --ns;
+            zero_start = false;
+        }
         if (uc && (ns == 0 || (shapes ? shapes->split[l] : split_prolong<T>(v.n)) != 0)) {
             launch_prolong_add<T>(lv[l - 1].n, uc, v.u[v.cur], s, nb);
             uc = nullptr;
@@ -238,10 +251,12 @@ struct Multigrid {
     void finest_cycle(int nrep = 1)
     {
         if (J <= lt) {
+            zero_start = false;
             launch_coarse_tail<T>(J, L, lv[J].f, lv[J].u[lv[J].cur], npre, npost, 1, 0, nrep, s, nb);
             return;
         }
         for (int r = 0; r < nrep; ++r) vcycle(J);
+        zero_start = false;
     }
 
     // FMG with ncycle V-cycles per level.  The finest u's boundary holds the

@@ -294,7 +294,7 @@ qumond_status qumond_tune_get_split(int32_t n, int32_t fp32, int32_t *split)
 qumond_status qumond_k_rbgs_sweep_shape(int32_t n, double h, const double *f, const double *u_in, double *u_out,
                                         int32_t variant, int32_t kchunk, const double *uc, void *stream)
 {
-    if (!good_n(n) || !(h > 0.0) || !f || !u_in || !u_out || u_in == u_out || variant < 0 ||
+    if (!good_n(n) || !(h > 0.0) || !f || !u_out || u_in == u_out || variant < 0 ||
         variant >= qm::kSmootherVariants || kchunk < 0)
         return tfail("qumond_k_rbgs_sweep_shape: bad argument");
     qm::launch_rbgs_shape<double>(n, h, f, u_in, u_out, qm::SmootherShape{variant, kchunk}, (hipStream_t)stream, 1, uc);

@@ -98,6 +98,7 @@ _SIGNATURES = {
     "qumond_status_string": (ctypes.c_char_p, [_I32]),
     "qumond_last_error": (ctypes.c_char_p, []),
     "qumond_k_rbgs_sweep": (_I32, [_I32, _D, _P, _P, _P, _P]),
+    "qumond_k_rbgs_sweep_from_zero": (_I32, [_I32, _D, _P, _P, _P]),
     "qumond_k_rbgs_double_sweep": (_I32, [_I32, _D, _P, _P, _P, _P, _P]),
     "qumond_k_residual_restrict": (_I32, [_I32, _D, _P, _P, _P, _P, _P, _P]),
     "qumond_k_restrict": (_I32, [_I32, _P, _P, _P]),
@@ -393,6 +394,12 @@ def _s(stream=None):
     return ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
 
 
+def k_rbgs_sweep_from_zero(f, u_out, h):
+    n = u_out.shape[0]
+    check(lib().qumond_k_rbgs_sweep_from_zero(n, float(h), _ptr(f), _ptr(u_out), _s()),
+          "qumond_k_rbgs_sweep_from_zero")
+
+
 def k_rbgs_sweep(f, u_in, u_out, h):
     n = u_in.shape[0]
     check(lib().qumond_k_rbgs_sweep(n, float(h), _ptr(f), _ptr(u_in), _ptr(u_out), _s()), "qumond_k_rbgs_sweep")
@@ -478,7 +485,7 @@ def tune_get_fused(n, fp32=False):
 
 
 def k_rbgs_sweep_shape(f, u_in, u_out, h, variant, kchunk, uc=None):
-    check(lib().qumond_k_rbgs_sweep_shape(u_in.shape[0], float(h), _ptr(f), _ptr(u_in), _ptr(u_out), int(variant),
+    check(lib().qumond_k_rbgs_sweep_shape(u_out.shape[0], float(h), _ptr(f), _ptr(u_in), _ptr(u_out), int(variant),
                                           int(kchunk), _ptr(uc), _s()), "qumond_k_rbgs_sweep_shape")
 
 

@@ -86,6 +86,8 @@ def test_null_handles_and_arguments(Q):
     assert L.qumond_solve_mond(None, None, 0, None) == Q.QUMOND_ERR_INVALID
     assert L.qumond_gather_forces(None, None, None, None, 0, 0, None, None, None, None) == Q.QUMOND_ERR_INVALID
     assert L.qumond_k_rbgs_sweep(64, 1.0, None, None, None, None) == Q.QUMOND_ERR_INVALID
+    assert L.qumond_k_rbgs_sweep_from_zero(33, 1.0, None, None, None) == Q.QUMOND_ERR_INVALID
+    assert L.qumond_k_rbgs_sweep_from_zero(34, 1.0, None, None, None) == Q.QUMOND_ERR_INVALID
     assert L.qumond_k_fmg(33, 1.0, None, None, 2, 2, 6, 0, 0.0, None, None, None) == Q.QUMOND_ERR_INVALID
     assert L.qumond_status_string(Q.QUMOND_ERR_STATE) == b"call out of order"
 

@@ -287,6 +287,32 @@ def test_every_smoother_shape_is_bitwise_identical(n):
             assert np.array_equal(host(out), ref), (v, kc)
 
 
+@pytest.mark.parametrize("n", [5, 9, 17, 33, 65, 129, 257])
+def test_sweep_from_zero_is_bitwise_identical(n):
+    """A sweep from a zero iterate that reads no iterate (null input) equals
+    the sweep of a zero-filled iterate, in every single-sweep shape; only the
+    interior of the output is written."""
+    L = 3.5
+    h = L / (n - 1)
+    f = rand_state(n, 2100 + n)[0]
+    fd = dev(f)
+    ref = dev(np.zeros((n, n, n)))
+    Q.k_rbgs_sweep(fd, dev(np.zeros((n, n, n))), ref, h)
+    ref = host(ref)
+    assert rel(ref, O.rbgs_sweep(f, np.zeros((n, n, n)), h)) < 1e-14
+    start = np.full((n, n, n), 7.0)
+    start[1:-1, 1:-1, 1:-1] = -3.0
+    start[0] = start[-1] = start[:, 0] = start[:, -1] = start[:, :, 0] = start[:, :, -1] = 0.0
+    out = dev(start)
+    Q.k_rbgs_sweep_from_zero(fd, out, h)
+    assert np.array_equal(host(out), ref)
+    for v in Q.SMOOTHER_VARIANTS:
+        for kc in ((0,) if v == 5 else (4, 16, 0)):
+            out = dev(start)
+            Q.k_rbgs_sweep_shape(fd, None, out, h, v, kc)
+            assert np.array_equal(host(out), ref), (v, kc)
+
+
 @pytest.mark.parametrize("n", [5, 17, 33, 65, 129])
 def test_single_sweep_with_correction_is_bitwise_identical(n):
     """A single sweep that applies the coarse correction on load equals
