@@ -259,7 +259,7 @@ hipError_t tail_steps(qumond_batch *B, Class &C, bool mond, int p, const double 
 
 // ------------------------------------------------------------ autotuner
 
-const int kTuneChunks[] = {4, 8, 16, 32, 64, 0};
+const int kTuneChunks[] = {2, 4, 8, 16, 32, 64, 0};
 
 hipError_t tune_class(qumond_batch *B, Class &C, int reps)
 {
@@ -289,6 +289,7 @@ hipError_t tune_class(qumond_batch *B, Class &C, int reps)
                 for (int kc : kTuneChunks) {
                     if (kc != 0 && kc >= n - 2) continue;
                     if (v == brick && kc != 0) continue;
+                    if (fz && kc != 0 && kc < 4) continue;   // the two-sweep march needs 4-plane chunks
                     const int nzc = kc ? (n - 2 + kc - 1) / kc : 1;
                     if (nzc > zmax) continue;
                     const qm::SmootherShape sh{v, kc};

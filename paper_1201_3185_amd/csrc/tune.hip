@@ -21,7 +21,7 @@ qumond_status tfail(const std::string &m)
 
 bool good_n(int n) { return n >= 5 && n <= 1025 && qm::log2_exact(n - 1) >= 2; }
 
-const int kChunks[] = {4, 8, 16, 32, 64, 128, 0};
+const int kChunks[] = {2, 4, 8, 16, 32, 64, 128, 0};
 
 template <typename T>
 qumond_status tune_one(int n, int reps, hipStream_t s, double &best_us, bool fused)
@@ -59,6 +59,7 @@ qumond_status tune_one(int n, int reps, hipStream_t s, double &best_us, bool fus
         for (int kc : kChunks) {
             if (kc != 0 && kc >= n - 2) continue;
             if (v == brick && kc != 0) continue;   // bricks have no z-chunk
+            if (fused && kc != 0 && kc < 4) continue;   // the two-sweep march needs 4-plane chunks
             const qm::SmootherShape sh{v, kc};
             std::vector<float> t;
             run(u0, u1, sh);   // warm-up

@@ -281,7 +281,7 @@ def test_every_smoother_shape_is_bitwise_identical(n):
     ref = host(ref)
     assert rel(ref, O.rbgs_sweep(f, u.copy(), h)) < 1e-14
     for v in Q.SMOOTHER_VARIANTS:
-        for kc in (4, 16, 0):
+        for kc in (2, 4, 16, 0):
             out = dev(u)
             Q.k_rbgs_sweep_shape(fd, ud, out, h, v, kc)
             assert np.array_equal(host(out), ref), (v, kc)
@@ -307,7 +307,7 @@ def test_sweep_from_zero_is_bitwise_identical(n):
     Q.k_rbgs_sweep_from_zero(fd, out, h)
     assert np.array_equal(host(out), ref)
     for v in Q.SMOOTHER_VARIANTS:
-        for kc in ((0,) if v == 5 else (4, 16, 0)):
+        for kc in ((0,) if v == 5 else (2, 4, 16, 0)):
             out = dev(start)
             Q.k_rbgs_sweep_shape(fd, None, out, h, v, kc)
             assert np.array_equal(host(out), ref), (v, kc)
@@ -330,7 +330,7 @@ def test_single_sweep_with_correction_is_bitwise_identical(n):
     Q.k_rbgs_sweep(fd, pa, ref, h)
     ref = host(ref)
     for v in Q.SMOOTHER_VARIANTS:
-        for kc in ((0,) if v == 5 else (4, 16, 0)):
+        for kc in ((0,) if v == 5 else (2, 4, 16, 0)):
             out = dev(u)
             Q.k_rbgs_sweep_shape(fd, dev(u), out, h, v, kc, uc=ucd)
             assert np.array_equal(host(out), ref), (v, kc)
@@ -382,7 +382,7 @@ def test_autotune_installs_a_table(tmp_path):
     assert '"n": 65' in txt
     Q.tune_set(65, *before)
     Q.tune_load(str(tmp_path / "t.json"))
-    assert Q.tune_get(65) in [(v, k) for v in Q.SMOOTHER_VARIANTS for k in (4, 8, 16, 32, 64, 128, 0)]
+    assert Q.tune_get(65) in [(v, k) for v in Q.SMOOTHER_VARIANTS for k in (2, 4, 8, 16, 32, 64, 128, 0)]
     assert '"split_prolong"' in txt and all(Q.tune_get_split(n, fp32=fp) in (0, 1) for n in (33, 65)
                                             for fp in (False, True))
 
