@@ -284,11 +284,10 @@ hipError_t tune_class(qumond_batch *B, Class &C, int reps)
         double best[2] = {1e30, 1e30};
         for (int fz = 0; fz < 2; ++fz) {
             const int nvar = fz ? qm::kFusedVariants : qm::kSmootherVariants;
-            const int brick = fz ? 2 : 5;
             for (int v = 0; v < nvar; ++v)
                 for (int kc : kTuneChunks) {
                     if (kc != 0 && kc >= n - 2) continue;
-                    if (v == brick && kc != 0) continue;
+                    if (qm::is_brick_variant(v, fz != 0) && kc != 0) continue;
                     if (fz && kc != 0 && kc < 4) continue;   // the two-sweep march needs 4-plane chunks
                     const int nzc = kc ? (n - 2 + kc - 1) / kc : 1;
                     if (nzc > zmax) continue;

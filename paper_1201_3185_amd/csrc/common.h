@@ -110,15 +110,17 @@ constexpr int kBatchDepositBlocks = 64;   // deposit workgroups per problem
 // ---- grid_kernels.hip (templated on the storage type: double or float)
 // Smoother launch shape: tile variant (z-march over 0: 32x8, 1: 64x4, 2: 64x8,
 // 3: 128x4, 4: 32x16 columns; 5: 8^3 bricks; 6: 64x8, 7: 64x16, 8: 128x8
-// columns with one thread per x-pair of nodes) and the number of z planes one
-// workgroup marches through (ignored by bricks).
+// columns with one thread per x-pair of nodes; 9: 4^3, 10: 6^3 bricks) and the
+// number of z planes one workgroup marches through (ignored by bricks).
 struct SmootherShape {
     int variant;
     int kchunk;
 };
-constexpr int kSmootherVariants = 9;
+constexpr int kSmootherVariants = 11;
 constexpr int kRrVariants = 5;   // residual restriction: gather, LDS tile, z-march with 4/8/16-plane chunks
-constexpr int kFusedVariants = 3;   // two sweeps: 0: 32x8, 1: 64x4 z-march, 2: 8^3 bricks
+// bricks hold their whole block in LDS and take no z-chunk
+inline bool is_brick_variant(int v, bool fused) { return fused ? (v >= 2 && v <= 4) : (v == 5 || v >= 9); }
+constexpr int kFusedVariants = 5;   // two sweeps: 0: 32x8, 1: 64x4 z-march, 2: 8^3, 3: 4^3, 4: 6^3 bricks
 // Every grid launcher takes nb, the number of problems stored back to back
 // (problem p of a level with n points per side at offset p n^3); nb = 1 is the
 // single-problem case.

@@ -501,10 +501,9 @@ rbgs_brick(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict_
     }
 }
 
-template <typename T, int S>
+template <typename T, int S, int B = 8>
 static void brick_launch(int n, double h, const T *f, const T *uin, T *uout, const T *uc, int nb, hipStream_t s)
 {
-    constexpr int B = 8;
     const int nbx = (n - 2 + B - 1) / B;
     const dim3 grid((unsigned)((size_t)nbx * nbx * nbx * nb));
     if (uc)
@@ -684,6 +683,8 @@ void launch_rbgs2_shape(int n, double h, const T *f, const T *uin, T *uout, cons
     switch (sh.variant) {
     case 0: rbgs2_launch<T, 32, 8>(n, h, f, uin, uout, kc, uc, nb, s); break;
     case 2: brick_launch<T, 2>(n, h, f, uin, uout, uc, nb, s); break;
+    case 3: brick_launch<T, 2, 4>(n, h, f, uin, uout, uc, nb, s); break;
+    case 4: brick_launch<T, 2, 6>(n, h, f, uin, uout, uc, nb, s); break;
     default: rbgs2_launch<T, 64, 4>(n, h, f, uin, uout, kc, uc, nb, s); break;
     }
 }
@@ -781,6 +782,8 @@ void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, Smoot
     case 6: rbgs_pair_launch<T, 64, 8>(n, h, f, uin, uout, kc, nb, uc, s); break;
     case 7: rbgs_pair_launch<T, 64, 16>(n, h, f, uin, uout, kc, nb, uc, s); break;
     case 8: rbgs_pair_launch<T, 128, 8>(n, h, f, uin, uout, kc, nb, uc, s); break;
+    case 9: brick_launch<T, 1, 4>(n, h, f, uin, uout, uc, nb, s); break;
+    case 10: brick_launch<T, 1, 6>(n, h, f, uin, uout, uc, nb, s); break;
     default: rbgs_launch<T, 64, 4>(n, h, f, uin, uout, kc, nb, uc, s); break;
     }
 }

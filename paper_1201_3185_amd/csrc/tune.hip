@@ -54,11 +54,10 @@ qumond_status tune_one(int n, int reps, hipStream_t s, double &best_us, bool fus
         }
     };
     const int nvar = fused ? qm::kFusedVariants : qm::kSmootherVariants;
-    const int brick = fused ? 2 : 5;
     for (int v = 0; v < nvar; ++v)
         for (int kc : kChunks) {
             if (kc != 0 && kc >= n - 2) continue;
-            if (v == brick && kc != 0) continue;   // bricks have no z-chunk
+            if (qm::is_brick_variant(v, fused) && kc != 0) continue;   // bricks have no z-chunk
             if (fused && kc != 0 && kc < 4) continue;   // the two-sweep march needs 4-plane chunks
             const qm::SmootherShape sh{v, kc};
             std::vector<float> t;
