@@ -117,7 +117,8 @@ struct SmootherShape {
     int kchunk;
 };
 constexpr int kSmootherVariants = 11;
-constexpr int kRrVariants = 5;   // residual restriction: gather, LDS tile, z-march with 4/8/16-plane chunks
+constexpr int kRrVariants = 7;   // residual restriction: gather, 8x8x4 LDS tile, z-march with 4/8/16-plane chunks,
+                                 // 4x4x4 and 4x4x2 LDS tiles
 // bricks hold their whole block in LDS and take no z-chunk
 inline bool is_brick_variant(int v, bool fused) { return fused ? (v >= 2 && v <= 4) : (v == 5 || v >= 9); }
 constexpr int kFusedVariants = 5;   // two sweeps: 0: 32x8, 1: 64x4 z-march, 2: 8^3, 3: 4^3, 4: 6^3 bricks

@@ -870,18 +870,19 @@ static dim3 grid3(int m, dim3 blk, int nb, int &zb)
     return dim3((m + blk.x - 1) / blk.x, (m + blk.y - 1) / blk.y, zb * nb);
 }
 
-// The same result with the fine block staged in LDS: a workgroup owns an
-// 8 x 8 x 4 block of coarse nodes, loads u on the fine nodes it needs plus a
+// The same result with the fine block staged in LDS: a workgroup owns a
+// CX x CY x CZ block of coarse nodes (8 x 8 x 4, or 4 x 4 x 4 and 4 x 4 x 2 for
+// more workgroups on small levels), loads u on the fine nodes it needs plus a
 // one-node ring and f on those nodes once, forms the fine residuals in LDS,
 // and restricts them; each residual and each coarse sum is the same
 // expression in the same order as in residual_restrict_k.
-template <typename T>
+template <typename T, int CX, int CY, int CZ>
 __global__ void __launch_bounds__(256)
 residual_restrict_tile_k(int nf, T ih2, const T *__restrict__ f, const T *__restrict__ u, T *__restrict__ fc,
                          T *__restrict__ uc0, T *__restrict__ uc1, int tx, int ty, int tz)
 {
 #pragma clang fp contract(off)
-    constexpr int CX = 8, CY = 8, CZ = 4;
+    static_assert(CX * CY * CZ <= 256, "one coarse node per thread");
     constexpr int RX = 2 * CX + 1, RY = 2 * CY + 1, RZ = 2 * CZ + 1;   // fine residual region
     constexpr int UX = RX + 2, UY = RY + 2, UZ = RZ + 2;               // u region (one-node ring)
     __shared__ T Us[UX * UY * UZ];
@@ -923,6 +924,7 @@ residual_restrict_tile_k(int nf, T ih2, const T *__restrict__ f, const T *__rest
         Rs[t] = Rs[t] - lap;
     }
     __syncthreads();
+    if ((int)threadIdx.x >= CX * CY * CZ) return;
     const int li = threadIdx.x % CX, lj = (threadIdx.x / CX) % CY, lk = threadIdx.x / (CX * CY);
     const int I = I0 + li, J = J0 + lj, K = K0 + lk;
     if (I >= nc || J >= nc || K >= nc) return;
@@ -1087,7 +1089,8 @@ residual_restrict_zmarch_k(int nf, T ih2, const T *__restrict__ f, const T *__re
 }
 
 // Which residual-restriction kernel a fine level of n points uses (0: per-node
-// gather, 1: LDS tile, 2/3/4: z-march over chunks of 4/8/16 coarse planes), per
+// gather, 1: 8x8x4 LDS tile, 2/3/4: z-march over chunks of 4/8/16 coarse planes,
+// 5: 4x4x4, 6: 4x4x2 LDS tiles), per
 // precision; set by the autotuner, gather by default.
 static int g_rr_variant[2][11] = {{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
 
@@ -1111,7 +1114,7 @@ void launch_residual_restrict_variant(int nf, double h, const T *f, const T *u, 
         hipLaunchKernelGGL(residual_restrict_k<T>, g, blk, 0, s, nf, T(1.0 / (h * h)), f, u, fc, uc0, uc1, zb);
         return;
     }
-    if (variant >= 2) {   // z-march with chunks of 4, 8 or 16 coarse planes
+    if (variant >= 2 && variant <= 4) {   // z-march with chunks of 4, 8 or 16 coarse planes
         constexpr int CX = 16, CY = 8;
         const int kc = variant == 2 ? 4 : (variant == 3 ? 8 : 16);
         const int tx = (nc + CX - 1) / CX, ty = (nc + CY - 1) / CY, tzc = (nc - 2 + kc - 1) / kc;
@@ -1120,10 +1123,24 @@ void launch_residual_restrict_variant(int nf, double h, const T *f, const T *u, 
                            uc0, uc1, tx, ty, tzc, kc);
         return;
     }
+    if (variant == 5) {   // 4 x 4 x 4 coarse tiles
+        const int tx = (nc + 3) / 4, ty = (nc + 3) / 4, tz = (nc + 3) / 4;
+        const dim3 g((unsigned)((size_t)tx * ty * tz * nb));
+        hipLaunchKernelGGL((residual_restrict_tile_k<T, 4, 4, 4>), g, dim3(256), 0, s, nf, T(1.0 / (h * h)), f, u, fc,
+                           uc0, uc1, tx, ty, tz);
+        return;
+    }
+    if (variant == 6) {   // 4 x 4 x 2 coarse tiles
+        const int tx = (nc + 3) / 4, ty = (nc + 3) / 4, tz = (nc + 1) / 2;
+        const dim3 g((unsigned)((size_t)tx * ty * tz * nb));
+        hipLaunchKernelGGL((residual_restrict_tile_k<T, 4, 4, 2>), g, dim3(256), 0, s, nf, T(1.0 / (h * h)), f, u, fc,
+                           uc0, uc1, tx, ty, tz);
+        return;
+    }
     const int tx = (nc + 7) / 8, ty = (nc + 7) / 8, tz = (nc + 3) / 4;
     const dim3 g((unsigned)((size_t)tx * ty * tz * nb));
-    hipLaunchKernelGGL(residual_restrict_tile_k<T>, g, dim3(256), 0, s, nf, T(1.0 / (h * h)), f, u, fc, uc0, uc1, tx, ty,
-                       tz);
+    hipLaunchKernelGGL((residual_restrict_tile_k<T, 8, 8, 4>), g, dim3(256), 0, s, nf, T(1.0 / (h * h)), f, u, fc, uc0,
+                       uc1, tx, ty, tz);
 }
 
 template <typename T>

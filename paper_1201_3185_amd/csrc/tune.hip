@@ -348,9 +348,9 @@ qumond_status qumond_autotune(int32_t n_max, int32_t both, int32_t reps, const c
             char buf[400];
             std::snprintf(buf, sizeof buf,
                           ", {\"n\": %d, \"fp32\": %d, \"use_fused\": %d}, {\"n\": %d, \"fp32\": %d, \"rr\": %d, "
-                          "\"rr_us\": [%.3f, %.3f, %.3f, %.3f, %.3f]}, {\"n\": %d, \"fp32\": %d, \"split_prolong\": %d, "
+                          "\"rr_us\": [%.3f, %.3f, %.3f, %.3f, %.3f, %.3f, %.3f]}, {\"n\": %d, \"fp32\": %d, \"split_prolong\": %d, "
                           "\"us\": [%.3f, %.3f]}",
-                          n, prec, fuse, n, prec, rrv, rr_us[0], rr_us[1], rr_us[2], rr_us[3], rr_us[4], n, prec, spv,
+                          n, prec, fuse, n, prec, rrv, rr_us[0], rr_us[1], rr_us[2], rr_us[3], rr_us[4], rr_us[5], rr_us[6], n, prec, spv,
                           sp_us[0], sp_us[1]);
             js += buf;
         }

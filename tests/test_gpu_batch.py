@@ -148,16 +148,16 @@ def test_autotuned_shapes_keep_results_bitwise():
 
 
 def test_zmarch_residual_restriction_over_stacked_problems():
-    """Every residual restriction of a batch forced to the z-march kernel (one
-    launch over the stacked problems of a class) gives the bits of the gather
-    kernel."""
+    """Every residual restriction of a batch forced to the z-march or the
+    4x4x4 / 4x4x2 LDS-tile kernels (one launch over the stacked problems of a class)
+    gives the bits of the gather kernel."""
     ns = [65, 65, 33, 129, 33]
     parts = small_disks(ns, seed0=900)
     levels = (33, 65, 129)
     saved = {(n, fp): Q.tune_get_rr(n, fp32=fp) for n in levels for fp in (False, True)}
     try:
         fields = []
-        for v in (0, 2, 4):
+        for v in (0, 2, 4, 5, 6):
             for n in levels:
                 for fp in (False, True):
                     Q.tune_set_rr(n, v, fp32=fp)
@@ -166,7 +166,7 @@ def test_zmarch_residual_restriction_over_stacked_problems():
             fields.append([b.get_field(p, Q.FIELD_PHI).cpu().numpy() for p in range(len(ns))])
             b.close()
         for p in range(len(ns)):
-            for v in (1, 2):
+            for v in (1, 2, 3, 4):
                 assert np.array_equal(fields[0][p], fields[v][p]), (p, v)
     finally:
         for (n, fp), v in saved.items():
