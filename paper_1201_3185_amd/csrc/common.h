@@ -110,17 +110,18 @@ constexpr int kBatchDepositBlocks = 64;   // deposit workgroups per problem
 // ---- grid_kernels.hip (templated on the storage type: double or float)
 // Smoother launch shape: tile variant (z-march over 0: 32x8, 1: 64x4, 2: 64x8,
 // 3: 128x4, 4: 32x16 columns; 5: 8^3 bricks; 6: 64x8, 7: 64x16, 8: 128x8
-// columns with one thread per x-pair of nodes; 9: 4^3, 10: 6^3 bricks) and the
-// number of z planes one workgroup marches through (ignored by bricks).
+// columns with one thread per x-pair of nodes; 9: 4^3, 10: 6^3 bricks; 11: 32x16,
+// 12: 32x8 pair columns) and the number of z planes one workgroup marches
+// through (ignored by bricks).
 struct SmootherShape {
     int variant;
     int kchunk;
 };
-constexpr int kSmootherVariants = 11;
+constexpr int kSmootherVariants = 13;
 constexpr int kRrVariants = 7;   // residual restriction: gather, 8x8x4 LDS tile, z-march with 4/8/16-plane chunks,
                                  // 4x4x4 and 4x4x2 LDS tiles
 // bricks hold their whole block in LDS and take no z-chunk
-inline bool is_brick_variant(int v, bool fused) { return fused ? (v >= 2 && v <= 4) : (v == 5 || v >= 9); }
+inline bool is_brick_variant(int v, bool fused) { return fused ? (v >= 2 && v <= 4) : (v == 5 || v == 9 || v == 10); }
 constexpr int kFusedVariants = 5;   // two sweeps: 0: 32x8, 1: 64x4 z-march, 2: 8^3, 3: 4^3, 4: 6^3 bricks
 // Every grid launcher takes nb, the number of problems stored back to back
 // (problem p of a level with n points per side at offset p n^3); nb = 1 is the
@@ -166,8 +167,9 @@ template <typename T> void launch_fill(T *p, size_t count, T v, hipStream_t s);
 template <typename T> void launch_boundary_copy(int n, const T *src, T *dst, hipStream_t s);
 // Coarse tail: all levels with n <= 17 inside one workgroup's LDS (one
 // workgroup per problem).  mode 0: one V-cycle of the top level (correction,
-// zero boundary); mode 1: FMG from 3^3 up to the top level with ncycle V-cycles
-// per level (boundary of u = Dirichlet values).
+// zero boundary); mode 2: the same from an iterate that is zero everywhere,
+// which is then not read; mode 1: FMG from 3^3 up to the top level with ncycle
+// V-cycles per level (boundary of u = Dirichlet values).
 template <typename T> void launch_coarse_tail(int ltop, double L, const T *f, T *u, int npre, int npost, int ncycle,
                                              int mode, int nrep, hipStream_t s, int nb = 1);
 // Sums over interior nodes of (f - A_h u)^2, f^2 and of the squared boundary-value

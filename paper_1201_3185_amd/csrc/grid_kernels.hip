@@ -784,6 +784,8 @@ void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, Smoot
     case 8: rbgs_pair_launch<T, 128, 8>(n, h, f, uin, uout, kc, nb, uc, s); break;
     case 9: brick_launch<T, 1, 4>(n, h, f, uin, uout, uc, nb, s); break;
     case 10: brick_launch<T, 1, 6>(n, h, f, uin, uout, uc, nb, s); break;
+    case 11: rbgs_pair_launch<T, 32, 16>(n, h, f, uin, uout, kc, nb, uc, s); break;
+    case 12: rbgs_pair_launch<T, 32, 8>(n, h, f, uin, uout, kc, nb, uc, s); break;
     default: rbgs_launch<T, 64, 4>(n, h, f, uin, uout, kc, nb, uc, s); break;
     }
 }
@@ -1559,16 +1561,18 @@ coarse_tail_k(int top, T L, const T *__restrict__ fg, T *__restrict__ ug, int np
     fg += (size_t)blockIdx.x * cnt;
     ug += (size_t)blockIdx.x * cnt;
     T *utop = U + tail_off(top), *ftop = F + tail_off(top);
+    const bool uzero = mode == 2;   // a correction V-cycle whose iterate is known to be zero: not read
     for (int p = threadIdx.x; p < cnt; p += kTailThreads) {
-        utop[p] = ug[p];
+        utop[p] = uzero ? T(0) : ug[p];
         ftop[p] = fg[p];
     }
     __syncthreads();
+    const int md = mode == 1 ? 1 : 0;
     switch (top) {
-    case 1: t.template run<1>(mode, ncycle, nrep); break;
-    case 2: t.template run<2>(mode, ncycle, nrep); break;
-    case 3: t.template run<3>(mode, ncycle, nrep); break;
-    default: t.template run<4>(mode, ncycle, nrep); break;
+    case 1: t.template run<1>(md, ncycle, nrep); break;
+    case 2: t.template run<2>(md, ncycle, nrep); break;
+    case 3: t.template run<3>(md, ncycle, nrep); break;
+    default: t.template run<4>(md, ncycle, nrep); break;
     }
     for (int p = threadIdx.x; p < cnt; p += blockDim.x) ug[p] = utop[p];
 }

@@ -242,7 +242,8 @@ struct Multigrid {
                                                 shapes->rr[l], s, nb);
         else
             launch_residual_restrict<T>(v.n, v.h, v.f, v.u[v.cur], c.f, c.u[c.cur], c.u[1 - c.cur], s, nb);
-        if (l - 1 == lt) launch_coarse_tail<T>(lt, L, c.f, c.u[c.cur], npre, npost, 1, 0, 1, s, nb);
+        // the restriction zeroed the correction: the tail need not read it
+        if (l - 1 == lt) launch_coarse_tail<T>(lt, L, c.f, c.u[c.cur], npre, npost, 1, 2, 1, s, nb);
         else vcycle(l - 1);
         smooth(l, npost, c.u[c.cur]);
     }
