@@ -176,8 +176,9 @@ template <typename T> void launch_coarse_tail(int ltop, double L, const T *f, T 
 // contribution: per-block partials (3 per block, up to kNormBlocks blocks per
 // problem), then one block per problem in fixed order, into out[3p..3p+2]
 // (device doubles).
+// hout (optional): device-mapped pinned host memory that also receives the sums.
 template <typename T> void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial, double *out,
-                                             hipStream_t s, int nb = 1);
+                                             hipStream_t s, int nb = 1, double *hout = nullptr);
 constexpr int kNormBlocks = 2048;
 
 // mixed precision (FP64 refinement around FP32 multigrid); sc holds s and 1/s
@@ -189,7 +190,7 @@ void launch_mixed_scale(int n, const double *norms, double *sc, hipStream_t s, i
 // The residual norms (as launch_resid_norms) and, in the same pass, the
 // residual times 1/s (sc per problem) rounded to FP32 at interior nodes.
 void launch_resid_norms_r32(int n, double h, const double *f, const double *u, double *partial, double *out,
-                            const double *sc, float *r32, hipStream_t s, int nb = 1);
+                            const double *sc, float *r32, hipStream_t s, int nb = 1, double *hout = nullptr);
 void launch_resid_to_f32(int n, double h, const double *sc, const double *f, const double *u, float *r, hipStream_t s,
                          int nb = 1);
 void launch_correct(int n, const double *sc, const float *e, double *u, hipStream_t s, int nb = 1);

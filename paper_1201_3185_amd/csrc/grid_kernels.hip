@@ -1664,7 +1664,10 @@ resid_norms_partial_k(int n, double ih2, const T *__restrict__ f, const T *__res
     }
 }
 
-__global__ void __launch_bounds__(256) norms_final_k(const double *__restrict__ partial, int nb, double *__restrict__ out)
+// hout (optional): the same three sums per problem, written straight into
+// pinned host memory (its device-mapped address), so no copy launch follows.
+__global__ void __launch_bounds__(256) norms_final_k(const double *__restrict__ partial, int nb, double *__restrict__ out,
+                                                     double *__restrict__ hout)
 {
     __shared__ double sh[768];
     partial += blockIdx.x * 3 * (size_t)nb;
@@ -1680,28 +1683,36 @@ __global__ void __launch_bounds__(256) norms_final_k(const double *__restrict__ 
         out[0] = a;
         out[1] = b;
         out[2] = c;
+        if (hout) {
+            hout += 3 * blockIdx.x;
+            hout[0] = a;
+            hout[1] = b;
+            hout[2] = c;
+            __threadfence_system();
+        }
     }
 }
 
 template <typename T>
-void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial, double *out, hipStream_t s, int nb)
+void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial, double *out, hipStream_t s, int nb,
+                        double *hout)
 {
     // about 8 four-row groups per workgroup, at most kNormBlocks workgroups per problem
     const long long rows = (long long)(n - 2) * (n - 2);
     const int blocks = (int)std::min<long long>(kNormBlocks, std::max<long long>(1, (rows + 31) / 32));
     hipLaunchKernelGGL((resid_norms_partial_k<T, false>), dim3(blocks, nb), dim3(256), 0, s, n, 1.0 / (h * h), f, u,
                        partial, nullptr, nullptr);
-    hipLaunchKernelGGL(norms_final_k, dim3(nb), dim3(256), 0, s, partial, blocks, out);
+    hipLaunchKernelGGL(norms_final_k, dim3(nb), dim3(256), 0, s, partial, blocks, out, hout);
 }
 
 void launch_resid_norms_r32(int n, double h, const double *f, const double *u, double *partial, double *out,
-                            const double *sc, float *r32, hipStream_t s, int nb)
+                            const double *sc, float *r32, hipStream_t s, int nb, double *hout)
 {
     const long long rows = (long long)(n - 2) * (n - 2);
     const int blocks = (int)std::min<long long>(kNormBlocks, std::max<long long>(1, (rows + 31) / 32));
     hipLaunchKernelGGL((resid_norms_partial_k<double, true>), dim3(blocks, nb), dim3(256), 0, s, n, 1.0 / (h * h), f,
                        u, partial, sc, r32);
-    hipLaunchKernelGGL(norms_final_k, dim3(nb), dim3(256), 0, s, partial, blocks, out);
+    hipLaunchKernelGGL(norms_final_k, dim3(nb), dim3(256), 0, s, partial, blocks, out, hout);
 }
 
 // ------------------------------------------------- mixed-precision helpers
@@ -1892,7 +1903,8 @@ void launch_guess_interior(int n, const void *g, int kind, double *u, hipStream_
     template void launch_fill<T>(T *, size_t, T, hipStream_t);                                                 \
     template void launch_boundary_copy<T>(int, const T *, T *, hipStream_t);                                   \
     template void launch_coarse_tail<T>(int, double, const T *, T *, int, int, int, int, int, hipStream_t, int);\
-    template void launch_resid_norms<T>(int, double, const T *, const T *, double *, double *, hipStream_t, int);
+    template void launch_resid_norms<T>(int, double, const T *, const T *, double *, double *, hipStream_t, int,    \
+                                        double *);
 QM_INST(double)
 QM_INST(float)
 #undef QM_INST

@@ -93,7 +93,8 @@ struct Multigrid {
     int npre = 2, npost = 2;
     std::vector<Level<T>> lv;  // index = level, n = 2^l + 1
     double *partial = nullptr, *norms = nullptr;
-    double *host_norms = nullptr;  // pinned, 3 doubles
+    double *host_norms = nullptr;  // pinned, 3 doubles per problem
+    double *host_norms_dev = nullptr;   // its device-mapped address (null: copied instead)
     hipStream_t s = nullptr;
     size_t bytes = 0;
     std::vector<void *> owned;
@@ -154,6 +155,11 @@ struct Multigrid {
         if ((e = alloc((void **)&norms, 3 * (size_t)nb * sizeof(double))) != hipSuccess) return e;
         if ((e = hipHostMalloc((void **)&host_norms, 3 * (size_t)nb * sizeof(double), hipHostMallocDefault)) != hipSuccess)
             return e;
+        // kernels write the norms into the pinned buffer directly where it is mapped
+        if (hipHostGetDevicePointer((void **)&host_norms_dev, host_norms, 0) != hipSuccess) {
+            host_norms_dev = nullptr;
+            (void)hipGetLastError();   // not mapped: copy instead, and leave no error behind
+        }
         return hipSuccess;
     }
 
@@ -166,6 +172,7 @@ struct Multigrid {
         owned.clear();
         if (host_norms) (void)hipHostFree(host_norms);
         host_norms = nullptr;
+        host_norms_dev = nullptr;
         bytes = 0;
     }
 
@@ -284,18 +291,18 @@ struct Multigrid {
     // Residual norms of the finest level of every problem into norms (device);
     // after set_r32 the next norms pass (once) also writes the residual times
     // 1/s, rounded to FP32, to r32 (FP64 hierarchies only).
-    void device_norms()
+    void device_norms(double *hout = nullptr)
     {
         Level<T> &F = lv[J];
         if constexpr (sizeof(T) == 8) {
             if (r32_out) {
-                launch_resid_norms_r32(F.n, F.h, F.f, F.u[F.cur], partial, norms, r32_sc, r32_out, s, nb);
+                launch_resid_norms_r32(F.n, F.h, F.f, F.u[F.cur], partial, norms, r32_sc, r32_out, s, nb, hout);
                 r32_sc = nullptr;
                 r32_out = nullptr;
                 return;
             }
         }
-        launch_resid_norms<T>(F.n, F.h, F.f, F.u[F.cur], partial, norms, s, nb);
+        launch_resid_norms<T>(F.n, F.h, F.f, F.u[F.cur], partial, norms, s, nb, hout);
     }
     void set_r32(const double *sc, float *r)
     {
@@ -307,6 +314,10 @@ struct Multigrid {
     // stream synchronisation before reading).
     void enqueue_norms()
     {
+        if (host_norms_dev) {   // the norms kernel writes the pinned copy itself
+            device_norms(host_norms_dev);
+            return;
+        }
         device_norms();
         (void)hipMemcpyAsync(host_norms, norms, 3 * (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, s);
     }
