@@ -71,7 +71,7 @@ struct BoxGeom {
 // LDS window of the deposit: every workgroup accumulates the corners that fall
 // in a kWinX x kWinY x kWinZ block of nodes around each box's centre (where a
 // galaxy's mass concentrates) in LDS, and writes it to its own scratch slab.
-constexpr int kWinX = 32, kWinY = 32, kWinZ = 8, kWin = kWinX * kWinY * kWinZ;
+constexpr int kWinX = 48, kWinY = 48, kWinZ = 8, kWin = kWinX * kWinY * kWinZ;
 constexpr int kDepositThreads = 1024;
 constexpr int kDepositMaxBlocks = 256;
 
