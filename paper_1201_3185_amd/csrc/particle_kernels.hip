@@ -98,8 +98,19 @@ deposit_reduce_k(DepositArgs A, int nblocks)
     const int li = e % kWinX, lj = (e / kWinX) % kWinY, lk = e / (kWinX * kWinY);
     const int i = A.w0[b][0] + li, j = A.w0[b][1] + lj, k = A.w0[b][2] + lk;
     if (i >= A.n || j >= A.n || k >= A.n) return;
-    unsigned long long s = 0ULL;
-    for (int g = 0; g < nblocks; ++g) s += A.scratch[((size_t)g * A.nbox + b) * kWin + e];
+    // four independent integer sums keep four slab loads in flight (any order gives the same sum)
+    unsigned long long s0 = 0ULL, s1 = 0ULL, s2 = 0ULL, s3 = 0ULL;
+    const size_t st = (size_t)A.nbox * kWin;
+    const unsigned long long *src = A.scratch + (size_t)b * kWin + e;
+    int g = 0;
+    for (; g + 4 <= nblocks; g += 4) {
+        s0 += src[(size_t)g * st];
+        s1 += src[(size_t)(g + 1) * st];
+        s2 += src[(size_t)(g + 2) * st];
+        s3 += src[(size_t)(g + 3) * st];
+    }
+    for (; g < nblocks; ++g) s0 += src[(size_t)g * st];
+    const unsigned long long s = (s0 + s1) + (s2 + s3);
     if (s) A.q[b][id3(A.n, i, j, k)] += s;
 }
 
