@@ -457,21 +457,43 @@ rbgs_brick(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict_
     f += pb * N;
     if (PROLONG) uc += pb * (size_t)nc * nc * nc;
     const int i0 = 1 + bx * B - R, j0 = 1 + by * B - R, k0 = 1 + bz * B - R;   // global node of U[0]
-    for (int t = tid; t < E * E * E; t += NT) {
+    // Every lane issues all of its global loads before its first LDS store, so
+    // their latencies overlap: addresses are clamped into the grid (always in
+    // bounds) and nodes outside it are replaced by zero afterwards.
+    constexpr int NU = (E * E * E + NT - 1) / NT, NF = (FE * FE * FE + NT - 1) / NT;
+    T xu[NU], xf[NF];
+#pragma unroll
+    for (int r = 0; r < NU; ++r) {
+        const int t = min(tid + r * NT, E * E * E - 1);
         const int a = t % E, b = (t / E) % E, c = t / (E * E);
         const int i = i0 + a, j = j0 + b, k = k0 + c;
-        T x = T(0);
-        if (i >= 0 && i < n && j >= 0 && j < n && k >= 0 && k < n) {
-            x = uin ? uin[id3(n, i, j, k)] : T(0);   // a null uin is a zero iterate
-            if (PROLONG && i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2 && k >= 1 && k <= n - 2)
-                x += prolong_at(nc, uc, i, j, k);
-        }
-        U[t] = x;
+        const bool in = i >= 0 && i < n && j >= 0 && j < n && k >= 0 && k < n;
+        const T x = uin ? uin[id3(n, min(max(i, 0), n - 1), min(max(j, 0), n - 1), min(max(k, 0), n - 1))]
+                        : T(0);   // a null uin is a zero iterate
+        xu[r] = in ? x : T(0);
     }
-    for (int t = tid; t < FE * FE * FE; t += NT) {
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+        const int t = min(tid + r * NT, FE * FE * FE - 1);
         const int a = t % FE, b = (t / FE) % FE, c = t / (FE * FE);
         const int i = i0 + 1 + a, j = j0 + 1 + b, k = k0 + 1 + c;
-        F[t] = (i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2 && k >= 1 && k <= n - 2) ? f[id3(n, i, j, k)] : T(0);
+        const bool inner = i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2 && k >= 1 && k <= n - 2;
+        const T x = f[id3(n, min(max(i, 1), n - 2), min(max(j, 1), n - 2), min(max(k, 1), n - 2))];
+        xf[r] = inner ? x : T(0);
+    }
+#pragma unroll
+    for (int r = 0; r < NU; ++r)
+        if (tid + r * NT < E * E * E) U[tid + r * NT] = xu[r];
+#pragma unroll
+    for (int r = 0; r < NF; ++r)
+        if (tid + r * NT < FE * FE * FE) F[tid + r * NT] = xf[r];
+    if (PROLONG) {   // u += P uc on interior nodes: each lane updates the entries it stored
+        for (int t = tid; t < E * E * E; t += NT) {
+            const int a = t % E, b = (t / E) % E, c = t / (E * E);
+            const int i = i0 + a, j = j0 + b, k = k0 + c;
+            if (i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2 && k >= 1 && k <= n - 2)
+                U[t] = U[t] + prolong_at(nc, uc, i, j, k);
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -1562,9 +1584,22 @@ coarse_tail_k(int top, T L, const T *__restrict__ fg, T *__restrict__ ug, int np
     ug += (size_t)blockIdx.x * cnt;
     T *utop = U + tail_off(top), *ftop = F + tail_off(top);
     const bool uzero = mode == 2;   // a correction V-cycle whose iterate is known to be zero: not read
-    for (int p = threadIdx.x; p < cnt; p += kTailThreads) {
-        utop[p] = uzero ? T(0) : ug[p];
-        ftop[p] = fg[p];
+    // all global loads of a lane first, then its LDS stores (overlapped latency)
+    constexpr int NL = (kTailTopN * kTailTopN * kTailTopN + kTailThreads - 1) / kTailThreads;
+    T xu[NL], xf[NL];
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+        const int p = min((int)threadIdx.x + r * kTailThreads, cnt - 1);
+        xu[r] = uzero ? T(0) : ug[p];
+        xf[r] = fg[p];
+    }
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+        const int p = threadIdx.x + r * kTailThreads;
+        if (p < cnt) {
+            utop[p] = xu[r];
+            ftop[p] = xf[r];
+        }
     }
     __syncthreads();
     const int md = mode == 1 ? 1 : 0;
