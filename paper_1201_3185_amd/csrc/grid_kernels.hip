@@ -927,16 +927,34 @@ residual_restrict_tile_k(int nf, T ih2, const T *__restrict__ f, const T *__rest
     if (uc1) uc1 += pb * Nc;
     const int I0 = bx * CX, J0 = by * CY, K0 = bz * CZ;         // first coarse node of the block
     const int fi0 = 2 * I0 - 1, fj0 = 2 * J0 - 1, fk0 = 2 * K0 - 1;   // first fine node of the residual region
-    for (int t = threadIdx.x; t < UX * UY * UZ; t += 256) {
+    // All of a lane's global loads go out before its first LDS store (clamped,
+    // always in-bounds addresses; nodes outside the grid are zeroed after the load).
+    constexpr int NU = (UX * UY * UZ + 255) / 256, NR = (RX * RY * RZ + 255) / 256;
+    T xu[NU], xr[NR];
+#pragma unroll
+    for (int r = 0; r < NU; ++r) {
+        const int t = min((int)threadIdx.x + r * 256, UX * UY * UZ - 1);
         const int a = t % UX, b = (t / UX) % UY, c = t / (UX * UY);
         const int i = fi0 - 1 + a, j = fj0 - 1 + b, k = fk0 - 1 + c;
-        Us[t] = (i >= 0 && i < nf && j >= 0 && j < nf && k >= 0 && k < nf) ? u[id3(nf, i, j, k)] : T(0);
+        const bool in = i >= 0 && i < nf && j >= 0 && j < nf && k >= 0 && k < nf;
+        const T x = u[id3(nf, min(max(i, 0), nf - 1), min(max(j, 0), nf - 1), min(max(k, 0), nf - 1))];
+        xu[r] = in ? x : T(0);
     }
-    for (int t = threadIdx.x; t < RX * RY * RZ; t += 256) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int t = min((int)threadIdx.x + r * 256, RX * RY * RZ - 1);
         const int a = t % RX, b = (t / RX) % RY, c = t / (RX * RY);
         const int i = fi0 + a, j = fj0 + b, k = fk0 + c;
-        Rs[t] = (i >= 1 && i < nf - 1 && j >= 1 && j < nf - 1 && k >= 1 && k < nf - 1) ? f[id3(nf, i, j, k)] : T(0);
+        const bool in = i >= 1 && i < nf - 1 && j >= 1 && j < nf - 1 && k >= 1 && k < nf - 1;
+        const T x = f[id3(nf, min(max(i, 1), nf - 2), min(max(j, 1), nf - 2), min(max(k, 1), nf - 2))];
+        xr[r] = in ? x : T(0);
     }
+#pragma unroll
+    for (int r = 0; r < NU; ++r)
+        if ((int)threadIdx.x + r * 256 < UX * UY * UZ) Us[threadIdx.x + r * 256] = xu[r];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        if ((int)threadIdx.x + r * 256 < RX * RY * RZ) Rs[threadIdx.x + r * 256] = xr[r];
     __syncthreads();
     for (int t = threadIdx.x; t < RX * RY * RZ; t += 256) {
         const int a = t % RX, b = (t / RX) % RY, c = t / (RX * RY);
