@@ -346,11 +346,37 @@ rbgs_zmarch_pair(const T *__restrict__ uin, T *__restrict__ uout, const T *__res
     };
 
     // warm-up: planes kb-2..kb+2 and red of kb-1..kb+1
-    if (kb >= 2) load_now(kb - 2);
-    load_now(kb - 1);
-    load_now(kb);
-    load_now(kb + 1);
-    if (kb + 2 <= n - 1) load_now(kb + 2);
+    if constexpr (!PROLONG) {
+        // all five planes' loads in flight before the first LDS store (plane and
+        // in-plane offsets clamped into the grid; out-of-grid planes not stored)
+        T w[5][NL];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const T *src = uin ? uin + (size_t)min(max(kb - 2 + q, 0), n - 1) * nn : nullptr;
+#pragma unroll
+            for (int r = 0; r < NL; ++r) {
+                const T x = src ? src[max(goff[r], 0)] : T(0);
+                w[q][r] = goff[r] >= 0 ? x : T(0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const int k = kb - 2 + q;
+            if (k < 0 || k > n - 1) continue;
+            T *P = pl[k % NS];
+#pragma unroll
+            for (int r = 0; r < NL; ++r) {
+                const int t = tid + r * NT;
+                if (t < PL) P[t] = w[q][r];
+            }
+        }
+    } else {
+        if (kb >= 2) load_now(kb - 2);
+        load_now(kb - 1);
+        load_now(kb);
+        load_now(kb + 1);
+        if (kb + 2 <= n - 1) load_now(kb + 2);
+    }
     T fr0[RI], fr1[RI], fr2[RI];
 #pragma unroll
     for (int r = 0; r < RI; ++r) fr0[r] = fr2[r] = T(0);
