@@ -61,6 +61,15 @@ qumond_status qumond_tune_get_split(int32_t n, int32_t fp32, int32_t *split);
 qumond_status qumond_k_rbgs_sweep_shape(int32_t n, double h, const double *f, const double *u_in, double *u_out,
                                         int32_t variant, int32_t kchunk, const double *uc, void *stream);
 
+/* One sweep of nb problems stored back to back (problem p's n^3 grid at
+ * offset p n^3 of f, u_in and u_out, device doubles), all in one launch with
+ * an explicit shape, as the batched runner sweeps a level of a size class.
+ * u_in == NULL stands for a zero iterate of every problem.  Errors: n not
+ * 2^J + 1 in 5..1025, nb outside 1..4096, h <= 0, a NULL f or u_out,
+ * u_in == u_out, or a variant outside the table -> QUMOND_ERR_INVALID. */
+qumond_status qumond_k_rbgs_sweep_stacked(int32_t n, int32_t nb, double h, const double *f, const double *u_in,
+                                          double *u_out, int32_t variant, int32_t kchunk, void *stream);
+
 /* Time all shapes of both smoother kernels for n = 33, 65, ..., n_max (and
  * both precisions if both != 0), install the fastest; json_path (host
  * string, optional) receives the table.  best_us (host, optional, 11 entries)

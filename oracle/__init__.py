@@ -4,9 +4,10 @@ TEST INFRASTRUCTURE ONLY: the plain FP64 judge of the HIP library.  It shares no
 code with the product package and may be imported only by the test suite, the
 smoke check and the benchmark's CPU-baseline leg.
 
-The arithmetic lives in ``qumond_oracle.c`` (single-threaded, ``gcc -O2
--ffp-contract=off``); this module builds it on demand, declares its C
-signatures, and chains the steps in the order of Sec. 2:
+The arithmetic lives in ``qumond_oracle.c`` (``gcc -O2 -ffp-contract=off``,
+one thread unless ``set_threads`` asks for more; the node-parallel loops give
+the same bits at any thread count); this module builds it on demand, declares
+its C signatures, and chains the steps in the order of Sec. 2:
 
     step 1  CIC density per box           (cic_deposit, rhs_from_q)
     step 2  Newtonian FMG, box by box     (fmg, outer BC, BC from coarser box)
@@ -40,7 +41,7 @@ def build(force: bool = False) -> str:
     if force or stale:
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c99",
+            ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c99",
              "-D_DEFAULT_SOURCE", _SRC, _SRC_UNET, "-o", tmp, "-lm"])
         os.replace(tmp, _SO)
     return _SO
@@ -55,6 +56,8 @@ def lib():
         L = ctypes.CDLL(build())
         d, i, i64, vp = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
         sig = {
+            "orc_set_threads": (None, [i]),
+            "orc_get_threads": (i, []),
             "orc_nu": (d, [d]),
             "orc_nu_n": (d, [d, d]),
             "orc_fixed_shift": (i, [d]),
@@ -90,6 +93,15 @@ def lib():
             fn.argtypes = args
         _lib = L
     return _lib
+
+
+def set_threads(t: int) -> int:
+    """Threads of the oracle's node-parallel loops (colour passes, residual,
+    transfers, source, gather); the deposit and every sum stay serial, so the
+    results do not depend on the count.  Returns the previous count."""
+    prev = lib().orc_get_threads()
+    lib().orc_set_threads(int(t))
+    return prev
 
 
 def _p(a: np.ndarray):

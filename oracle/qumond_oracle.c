@@ -8,8 +8,16 @@
  * and only the test suite, the smoke check and the benchmark's CPU-baseline
  * leg may load it.  The product path never calls into it.
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, so the
- * CIC weights are the same IEEE products the paper's recipe defines).
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (no FMA
+ * contraction, so the CIC weights are the same IEEE products the paper's
+ * recipe defines).
+ *
+ * Threads.  One thread unless orc_set_threads says otherwise.  Only loops
+ * whose iterations write distinct nodes and read nothing another iteration
+ * writes are split over threads (a colour pass of red-black Gauss-Seidel,
+ * the residual, restriction, prolongation, interpolation, the Eq. 2 source
+ * and the per-point gather), so every result is the same bit for bit at any
+ * thread count; the deposit and every sum stay serial in their fixed order.
  *
  * What each routine follows:
  *   cic_*            Sec. 2, "cloud-in-cell technique" for the density (step 1),
@@ -40,6 +48,12 @@
 #include <string.h>
 
 #define ID3(n, i, j, k) ((size_t)(i) + (size_t)(n) * ((size_t)(j) + (size_t)(n) * (size_t)(k)))
+
+/* Threads of the node-parallel loops (see the header note). */
+static int orc_threads = 1;
+void orc_set_threads(int t) { orc_threads = t < 1 ? 1 : t; }
+int orc_get_threads(void) { return orc_threads; }
+#define ORC_PAR _Pragma("omp parallel for num_threads(orc_threads) schedule(static)")
 
 /* ------------------------------------------------------------------ nu */
 
@@ -210,6 +224,7 @@ void orc_bc_from_coarse(int n, double Lc, const double *uc, double Lf, double *u
 void orc_rbgs_colour(int n, double h, const double *f, double *u, int colour)
 {
     const double h2 = h * h;
+    ORC_PAR
     for (int k = 1; k < n - 1; k++)
         for (int j = 1; j < n - 1; j++)
             for (int i = 1; i < n - 1; i++) {
@@ -231,6 +246,7 @@ void orc_rbgs_sweep(int n, double h, const double *f, double *u)
 void orc_residual(int n, double h, const double *f, const double *u, double *r)
 {
     const double ih2 = 1.0 / (h * h);
+    ORC_PAR
     for (int k = 0; k < n; k++)
         for (int j = 0; j < n; j++)
             for (int i = 0; i < n; i++) {
@@ -262,6 +278,7 @@ void orc_restrict_fw(int nf, const double *rf, double *fc)
 {
     const int nc = (nf + 1) / 2;
     static const double w[3] = {0.25, 0.5, 0.25};
+    ORC_PAR
     for (int K = 0; K < nc; K++)
         for (int J = 0; J < nc; J++)
             for (int I = 0; I < nc; I++) {
@@ -303,6 +320,7 @@ static double prolong_value(int nc, const double *uc, int i, int j, int k)
 void orc_prolong_add(int nc, const double *uc, double *uf)
 {
     const int nf = 2 * nc - 1;
+    ORC_PAR
     for (int k = 1; k < nf - 1; k++)
         for (int j = 1; j < nf - 1; j++)
             for (int i = 1; i < nf - 1; i++) uf[ID3(nf, i, j, k)] += prolong_value(nc, uc, i, j, k);
@@ -312,6 +330,7 @@ void orc_prolong_add(int nc, const double *uc, double *uf)
 void orc_interp(int nc, const double *uc, double *uf)
 {
     const int nf = 2 * nc - 1;
+    ORC_PAR
     for (int k = 1; k < nf - 1; k++)
         for (int j = 1; j < nf - 1; j++)
             for (int i = 1; i < nf - 1; i++) uf[ID3(nf, i, j, k)] = prolong_value(nc, uc, i, j, k);
@@ -512,6 +531,7 @@ static double face_flux(int n, double h, double a0, double nn, const double *P, 
 void orc_mond_source_nu(int n, double L, double a0, double nn, const double *phin, double *S)
 {
     const double h = L / (double)(n - 1);
+    ORC_PAR
     for (int k = 0; k < n; k++)
         for (int j = 0; j < n; j++)
             for (int i = 0; i < n; i++) {
@@ -567,6 +587,7 @@ void orc_gather_nu(int nbox, int n, const double *Ls, const double *const *phis,
                    double a0, double M, int mond, double nn, double *ax, double *ay, double *az,
                    uint8_t *box_used)
 {
+    ORC_PAR
     for (int64_t p = 0; p < np; p++) {
         double R = sqrt(x[p] * x[p] + y[p] * y[p]);
         double az_abs = fabs(z[p]);

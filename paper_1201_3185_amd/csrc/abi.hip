@@ -278,8 +278,12 @@ qumond_status qumond_create(const qumond_config *cfg, void *hip_stream, qumond_c
 qumond_status qumond_profile_enable(qumond_ctx *ctx, int32_t on)
 {
     if (!ctx) return fail(QUMOND_ERR_INVALID, "ctx is NULL");
-    ctx->mg.prof.on = on != 0;
-    ctx->mg2.prof.on = on != 0;
+    if (on < 0 || (on > 1 && (on < 5 || qm::log2_exact(on - 1) < 2)))
+        return fail(QUMOND_ERR_INVALID, "qumond_profile_enable: on must be 0, 1 or a level size 2^J + 1 >= 5");
+    for (qm::SmootherProfile *p : {&ctx->mg.prof, &ctx->mg2.prof}) {
+        p->on = on != 0;
+        p->only_n = on > 1 ? on : 0;
+    }
     return QUMOND_OK;
 }
 

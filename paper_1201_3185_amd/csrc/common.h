@@ -15,6 +15,17 @@ __host__ __device__ __forceinline__ size_t id3(int n, int i, int j, int k)
     return (size_t)i + (size_t)n * ((size_t)j + (size_t)n * (size_t)k);
 }
 
+// Workgroups are dispatched to the 8 XCDs round robin (hardware id w runs on
+// XCD w mod 8), and each XCD has its own L2.  xcd_tile gives hardware id w the
+// tile (w mod 8) * (nblk / 8) + w / 8, so that each XCD works through one
+// contiguous range of tiles and neighbouring tiles share their halos in one
+// L2; ids beyond the last multiple of 8 keep their own tile.
+__device__ __forceinline__ unsigned xcd_tile(unsigned w, unsigned nblk)
+{
+    const unsigned full = nblk & ~7u;
+    return w < full ? (w & 7u) * (full >> 3) + (w >> 3) : w;
+}
+
 // ------------------------------------------------------------ nu
 // The interpolating function.  n == 1 is Eq. 2's nu(y) = 1/2 + 1/2 sqrt(1 + 4/y),
 // evaluated by the closed expressions in each kernel; any other n is the

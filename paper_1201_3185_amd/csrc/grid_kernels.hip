@@ -45,17 +45,6 @@ __device__ __forceinline__ T prolong_at(int nc, const T *__restrict__ uc, int i,
     return wka * (wja * xa + wjb * xb) + wkb * (wja * xc + wjb * xd);
 }
 
-// Workgroups are dispatched to the 8 XCDs round robin (hardware id w runs on
-// XCD w mod 8), and each XCD has its own L2.  xcd_tile gives hardware id w the
-// tile (w mod 8) * (nblk / 8) + w / 8, so that each XCD works through one
-// contiguous range of tiles and neighbouring tiles share their halos in one
-// L2; ids beyond the last multiple of 8 keep their own tile.
-__device__ __forceinline__ unsigned xcd_tile(unsigned w, unsigned nblk)
-{
-    const unsigned full = nblk & ~7u;
-    return w < full ? (w & 7u) * (full >> 3) + (w >> 3) : w;
-}
-
 // ------------------------------------------------------------------ smoother
 
 // With PROLONG the coarse-grid correction u += P uc is applied to every
@@ -84,7 +73,8 @@ rbgs_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict
     if (kb > n - 2) return;
     const int ke = min(kb + kchunk - 1, n - 2);
     const size_t nn = (size_t)n * n;
-    uin += (size_t)pb * nn * n;
+    // a null uin (zero iterate) stays null: only a real array is offset
+    if (uin) uin += (size_t)pb * nn * n;
     uout += (size_t)pb * nn * n;
     f += (size_t)pb * nn * n;
     if (PROLONG) uc += (size_t)pb * nc * nc * nc;
@@ -245,7 +235,8 @@ rbgs_zmarch_pair(const T *__restrict__ uin, T *__restrict__ uout, const T *__res
     if (kb > n - 2) return;
     const int ke = min(kb + kchunk - 1, n - 2);
     const size_t nn = (size_t)n * n;
-    uin += (size_t)pb * nn * n;
+    // a null uin (zero iterate) stays null: only a real array is offset
+    if (uin) uin += (size_t)pb * nn * n;
     uout += (size_t)pb * nn * n;
     f += (size_t)pb * nn * n;
     if (PROLONG) uc += (size_t)pb * nc * nc * nc;
@@ -478,7 +469,7 @@ rbgs_brick(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict_
     const int bz = bid % nbx;
     const int pb = bid / nbx;
     const size_t N = (size_t)n * n * n;
-    uin += pb * N;
+    if (uin) uin += pb * N;   // a null uin (zero iterate) stays null
     uout += pb * N;
     f += pb * N;
     if (PROLONG) uc += pb * (size_t)nc * nc * nc;
@@ -599,7 +590,8 @@ rbgs2_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
     if (kb > n - 2) return;
     const int ke = min(kb + kchunk - 1, n - 2);
     const size_t nn = (size_t)n * n;
-    uin += (size_t)pb * nn * n;
+    // a null uin (zero iterate) stays null: only a real array is offset
+    if (uin) uin += (size_t)pb * nn * n;
     uout += (size_t)pb * nn * n;
     f += (size_t)pb * nn * n;
     if (PROLONG) uc += (size_t)pb * nc * nc * nc;

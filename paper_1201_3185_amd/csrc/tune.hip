@@ -306,6 +306,22 @@ qumond_status qumond_k_rbgs_sweep_shape(int32_t n, double h, const double *f, co
     return QUMOND_OK;
 }
 
+qumond_status qumond_k_rbgs_sweep_stacked(int32_t n, int32_t nb, double h, const double *f, const double *u_in,
+                                          double *u_out, int32_t variant, int32_t kchunk, void *stream)
+{
+    if (!good_n(n) || nb < 1 || nb > 4096 || !(h > 0.0) || !f || !u_out || u_in == u_out || variant < 0 ||
+        variant >= qm::kSmootherVariants || kchunk < 0)
+        return tfail("qumond_k_rbgs_sweep_stacked: bad argument");
+    qm::launch_rbgs_shape<double>(n, h, f, u_in, u_out, qm::SmootherShape{variant, kchunk}, (hipStream_t)stream, nb,
+                                  nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        qm_set_last_error(hipGetErrorString(e));
+        return QUMOND_ERR_HIP;
+    }
+    return QUMOND_OK;
+}
+
 qumond_status qumond_autotune(int32_t n_max, int32_t both, int32_t reps, const char *json_path, double *best_us,
                               void *stream)
 {

@@ -127,6 +127,7 @@ _SIGNATURES = {
     "qumond_tune_set_fused": (_I32, [_I32, _I32, _I32, _I32]),
     "qumond_tune_get_fused": (_I32, [_I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "qumond_k_rbgs_sweep_shape": (_I32, [_I32, _D, _P, _P, _P, _I32, _I32, _P, _P]),
+    "qumond_k_rbgs_sweep_stacked": (_I32, [_I32, _I32, _D, _P, _P, _P, _I32, _I32, _P]),
     "qumond_autotune": (_I32, [_I32, _I32, _I32, ctypes.c_char_p, ctypes.POINTER(_D), _P]),
     "qumond_tune_load": (_I32, [ctypes.c_char_p]),
     "qumond_tune_set_rr": (_I32, [_I32, _I32, _I32]),
@@ -285,14 +286,15 @@ class Context:
     def device_bytes(self) -> int:
         return int(lib().qumond_device_bytes(self._h))
 
-    def deposit(self, x, y, z, m, total_mass: Optional[float] = None, count_outside: bool = True):
+    def deposit(self, x, y, z, m, total_mass: float, count_outside: bool = True):
+        """Step 1.  total_mass (Msun) is the mass of all particles, also those
+        outside every box: the caller states it (it sets the monopole boundary
+        value and the fixed-point scale)."""
         np_ = x.numel()
         for t, nm in ((x, "x"), (y, "y"), (z, "z"), (m, "m")):
             _f64(t, nm)
             if t.numel() != np_:
                 raise ValueError("particle arrays differ in length")
-        if total_mass is None:
-            total_mass = float(m.sum().item())
         out = ctypes.c_int64(0)
         _order_in(self.stream)
         check(lib().qumond_deposit(self._h, _ptr(x), _ptr(y), _ptr(z), _ptr(m), np_, float(total_mass),
@@ -372,8 +374,11 @@ class Context:
         _order_out(self.stream)
         return out
 
-    def profile_enable(self, on: bool = True):
-        check(lib().qumond_profile_enable(self._h, int(bool(on))), "qumond_profile_enable")
+    def profile_enable(self, on: bool = True, level_n: int = 0):
+        """Time smoother launches with hipEvents: all levels, or with level_n
+        only the levels of level_n points per side."""
+        v = 0 if not on else (int(level_n) if level_n else 1)
+        check(lib().qumond_profile_enable(self._h, v), "qumond_profile_enable")
 
     def profile_read(self) -> dict:
         st = qumond_kernel_stats()
@@ -488,6 +493,14 @@ def tune_get_fused(n, fp32=False):
 def k_rbgs_sweep_shape(f, u_in, u_out, h, variant, kchunk, uc=None):
     check(lib().qumond_k_rbgs_sweep_shape(u_out.shape[0], float(h), _ptr(f), _ptr(u_in), _ptr(u_out), int(variant),
                                           int(kchunk), _ptr(uc), _s()), "qumond_k_rbgs_sweep_shape")
+
+
+def k_rbgs_sweep_stacked(f, u_in, u_out, h, variant, kchunk):
+    """One sweep of the nb problems of u_out ([nb, n, n, n]) in one launch;
+    u_in None = zero iterates."""
+    nb, n = u_out.shape[0], u_out.shape[1]
+    check(lib().qumond_k_rbgs_sweep_stacked(n, nb, float(h), _ptr(f), _ptr(u_in), _ptr(u_out), int(variant),
+                                            int(kchunk), _s()), "qumond_k_rbgs_sweep_stacked")
 
 
 def autotune(n_max=513, both=True, reps=5, json_path=None):
@@ -699,14 +712,13 @@ class Batch:
     def device_bytes(self) -> int:
         return int(lib().qumond_batch_device_bytes(self._h))
 
-    def set_particles(self, p: int, x, y, z, m, total_mass: Optional[float] = None):
+    def set_particles(self, p: int, x, y, z, m, total_mass: float):
+        """Particles of problem p; total_mass (Msun, > 0) as for deposit."""
         np_ = x.numel()
         for t, nm in ((x, "x"), (y, "y"), (z, "z"), (m, "m")):
             _f64(t, nm)
             if t.numel() != np_:
                 raise ValueError("particle arrays differ in length")
-        if total_mass is None:
-            total_mass = float(m.sum().item())
         check(lib().qumond_batch_set_particles(self._h, int(p), _ptr(x), _ptr(y), _ptr(z), _ptr(m), np_,
                                                float(total_mass)), "qumond_batch_set_particles")
         self._keep[int(p)] = (x, y, z, m)   # the batch reads them at every run

@@ -313,6 +313,43 @@ def test_sweep_from_zero_is_bitwise_identical(n):
             assert np.array_equal(host(out), ref), (v, kc)
 
 
+@pytest.mark.parametrize("n", [5, 17, 33, 65])
+def test_stacked_sweeps_are_bitwise_single_problem_sweeps(n):
+    """Three problems stored back to back and swept in one launch (as the
+    batched runner sweeps a size class), from a zero iterate (no input array)
+    and from given iterates, give every problem the bits of its own
+    single-problem sweep, in every single-sweep shape: a problem's offset is
+    applied only to arrays that exist."""
+    nb, L = 3, 2.5
+    h = L / (n - 1)
+    rng = np.random.default_rng(3300 + n)
+    f = rng.standard_normal((nb, n, n, n))
+    u = rng.standard_normal((nb, n, n, n))
+    u[:, 0] = u[:, -1] = u[:, :, 0] = u[:, :, -1] = u[:, :, :, 0] = u[:, :, :, -1] = 0.0
+    fd, ud = dev(f), dev(u)
+    ref_zero, ref_u = [], []
+    for p in range(nb):
+        o = dev(np.zeros((n, n, n)))
+        Q.k_rbgs_sweep_from_zero(dev(f[p]), o, h)
+        ref_zero.append(host(o))
+        o = dev(u[p])
+        Q.k_rbgs_sweep(dev(f[p]), dev(u[p]), o, h)
+        ref_u.append(host(o))
+    start = np.full((nb, n, n, n), 5.0)
+    start[:, 0] = start[:, -1] = start[:, :, 0] = start[:, :, -1] = start[:, :, :, 0] = start[:, :, :, -1] = 0.0
+    for v in Q.SMOOTHER_VARIANTS:
+        for kc in ((0,) if v in (5, 9, 10) else (2, 16, 0)):
+            out = dev(start)
+            Q.k_rbgs_sweep_stacked(fd, None, out, h, v, kc)
+            got = host(out)
+            out2 = dev(u)
+            Q.k_rbgs_sweep_stacked(fd, ud, out2, h, v, kc)
+            got2 = host(out2)
+            for p in range(nb):
+                assert np.array_equal(got[p], ref_zero[p]), (v, kc, p)
+                assert np.array_equal(got2[p], ref_u[p]), (v, kc, p)
+
+
 @pytest.mark.parametrize("n", [5, 17, 33, 65, 129])
 def test_single_sweep_with_correction_is_bitwise_identical(n):
     """A single sweep that applies the coarse correction on load equals

@@ -8,10 +8,8 @@ difference of Phi_N), give up to a few times the residual.  So a solve
 stopped at a 1e-6 residual is held to 2e-6, and the 1e-6 field bar is checked
 on solves refined to a 1e-7 residual; refining further to 1e-10 reaches the
 FP64 result to 1e-9, so there is no FP32 accuracy floor.
-At the full size of the 513^3, 1e7-particle workload the oracle's FP64 FMG
-would take minutes, so the comparison there is with the GPU's own FP64 path
-(itself pinned to the oracle at the smaller sizes) and with the relative FP64
-residual recomputed independently in NumPy.
+The full-size 513^3, 1e7-particle workload is compared with the oracle in
+test_gpu_config3_513.py.
 """
 import numpy as np
 import pytest
@@ -108,35 +106,3 @@ def test_mixed_257_against_oracle():
     ctx, i_n, i_m = gpu_run(cfg, p, overlapped=True)
     assert rel(ctx.get_field(0, Q.FIELD_PHI_N).cpu().numpy(), o.phin[0]) <= 1e-6
     assert rel(ctx.get_field(0, Q.FIELD_PHI).cpu().numpy(), o.phi[0]) <= 1e-6
-
-
-@pytest.mark.slow
-def test_config3_full_size_513():
-    """513^3 box of 120 kpc, 1e7 particles: mixed to 1e-6 against FP64 to 1e-10."""
-    p = synth.two_component_disk(10_000_000, synth.seed_for(3))
-    base = dict(n=513, box_side=[120.0])
-    c64, n64, m64 = gpu_run(Q.Config(**base, tol_rel=1e-10), p, overlapped=True)
-    phin64 = c64.get_field(0, Q.FIELD_PHI_N).cpu().numpy()
-    phi64 = c64.get_field(0, Q.FIELD_PHI).cpu().numpy()
-    q64 = c64.get_field(0, Q.FIELD_RHO_FIXED).cpu().numpy()
-    c64.close()
-    del c64
-    torch.cuda.empty_cache()
-    cmx, nmx, mmx = gpu_run(Q.Config(**base, precision=Q.QUMOND_MIXED, tol_rel=1e-7), p, overlapped=True)
-    assert np.array_equal(cmx.get_field(0, Q.FIELD_RHO_FIXED).cpu().numpy(), q64)
-    phin = cmx.get_field(0, Q.FIELD_PHI_N).cpu().numpy()
-    phi = cmx.get_field(0, Q.FIELD_PHI).cpu().numpy()
-    assert rel(phin, phin64) <= 1e-6
-    assert rel(phi, phi64) <= 1e-6
-    f = cmx.get_field(0, Q.FIELD_RHS).cpu().numpy()
-    assert relres_numpy(f, phin, 120.0 / 512) <= 1.01e-7
-    S = cmx.get_field(0, Q.FIELD_SOURCE).cpu().numpy()
-    assert relres_numpy(S, phi, 120.0 / 512) <= 1.01e-7
-    # mass conservation of the fixed-point deposit at full size (particles inside the box)
-    s = O.fixed_shift(p.total_mass)
-    u = lambda c: (c + 60.0) * (512.0 / 120.0)
-    ins = np.ones(p.n, bool)
-    for c in (p.x, p.y, p.z):
-        ins &= (u(c) >= 0) & (u(c) < 512)
-    m_in = p.m[ins].sum() * 2.0 ** s
-    assert abs(int(q64.sum()) - m_in) <= 4 * p.n + 1e-12 * m_in

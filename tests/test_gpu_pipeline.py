@@ -194,7 +194,7 @@ def test_call_order_state_machine():
     with pytest.raises(Q.QumondError) as e:
         ctx.gather_forces(x, x, x, 0)
     assert e.value.status == Q.QUMOND_ERR_STATE
-    ctx.deposit(x, x, x, dev([1e9]))
+    ctx.deposit(x, x, x, dev([1e9]), 1e9)
     with pytest.raises(Q.QumondError) as e:
         ctx.mond_source()
     assert e.value.status == Q.QUMOND_ERR_STATE
@@ -212,7 +212,7 @@ def test_not_converged_reports_best_iterate():
     p = synth.kuzmin_disk(20000, 3.0, 1e10, 4321)
     cfg = Q.Config(n=33, box_side=[100.0], ncycle_fmg=1, max_vcycles=1, tol_rel=1e-14)
     ctx = Q.Context(cfg)
-    ctx.deposit(dev(p.x), dev(p.y), dev(p.z), dev(p.m))
+    ctx.deposit(dev(p.x), dev(p.y), dev(p.z), dev(p.m), p.total_mass)
     with pytest.raises(Q.QumondError) as e:
         ctx.solve_newton()
     assert e.value.status == Q.QUMOND_ERR_NOT_CONVERGED
