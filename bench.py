@@ -4,119 +4,241 @@
 One step is one pass of the whole path over one synthetic galaxy already
 resident in HBM: CIC deposit -> Newtonian FMG -> Eq. 2 source -> QUMOND FMG ->
 force gather at every particle, all through the C ABI of libqumond.so
-(qumond_deposit, qumond_solve -- which overlaps the QUMOND chain of box b with
-the Newtonian solve of box b+1 -- and qumond_gather_forces).
+(qumond_deposit, qumond_solve -- the source and both FMG solves, the QUMOND
+chain on a second stream -- and qumond_gather_forces).
 
-Workload: two-component exponential disk (stars Md = 5e10 Msun, Rd = 3 kpc,
-sech^2 height 0.3 kpc; gas Mg = 1e10 Msun, Rg = 6 kpc, height 0.15 kpc),
-1e6 particles, four nested 129^3 boxes of 400/200/100/50 kpc with a monopole
-outer boundary, 2+2 red-black sweeps and 6 V-cycles per FMG level, both solves
-to 1e-10 relative residual, in FP64.
+Headline workload (the largest single-GPU configuration): two-component
+exponential disk (stars Md = 5e10 Msun, Rd = 3 kpc, sech^2 height 0.3 kpc; gas
+Mg = 1e10 Msun, Rg = 6 kpc, height 0.15 kpc), 1e7 particles, one 513^3 box of
+120 kpc with a monopole outer boundary, 2+2 red-black sweeps and 6 V-cycles per
+FMG level, both solves to a 1e-10 relative residual, plain FP64.
 
-value = grid points of all boxes / wall time of one step (host syncs of the
-stopping tests included).  The roofline object reports the red-black
-smoother (the dominant kernel): algorithmic bytes (read u, read f, write u)
-of its launches divided by their summed durations, from hipEvents recorded by
-the library around each launch on the solve's stream during a second pass of
-the same K steps.  cpu_baseline times the CPU oracle (single thread) on one
-full step of the same workload.
+value = 513^3 grid points / wall time of one step (host syncs of the stopping
+tests included).  The roofline object reports the red-black smoother on the
+finest (513^3) level, the dominant kernel: algorithmic bytes (read u, read f,
+write u: 24 B per node) of those launches over their average duration, from
+hipEvents the library records around each of them, on the stream it runs on,
+during the timed steps.  cpu_baseline runs the CPU oracle on the full headline
+workload (its node-parallel loops on the stated number of host threads), and
+its potentials are the reference for every error figure of the 513^3 legs.
 
 Further legs (same JSON line, not the headline value): the 513^3 disk to 1e-6
-in FP64 and in mixed precision; the batched fit (64 disks of 129^3/257^3 in one
-captured graph); the learned initial guess on held-out 129^3 disks.
+in FP64 (the paper's schedule and a 2-cycle one) and in mixed precision; the
+nested 129^3 step (four boxes); the batched fit (64 disks of 129^3/257^3 in one
+captured graph); the learned initial guess on held-out 129^3 disks; the paper's
+Kuzmin and exponential-disk experiments.
 """
 import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 METRIC = "QUMOND solve grid-pts/s & wall time to 1e-6 rel residual: plain FP64 vs mixed+learned"
 HBM_PEAK_GBS = 8000.0
+LAUNCH_TABLE = os.path.join(HERE, "paper_1201_3185_amd", "launch_shapes_mi355x.json")
+N3, L3, NP3 = 513, 120.0, 10_000_000
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def smoother_traffic(per_launch_alg_bytes):
-    """HBM traffic per smoother launch from committed rocprofv3 counter runs,
-    valid only while the kernel source is unchanged (null otherwise)."""
+def rel(a, b):
+    import numpy as np
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def host_cpu():
+    """CPU model and logical core count of this host (from /proc/cpuinfo)."""
+    model, cores = platform.processor() or "unknown", os.cpu_count() or 1
+    try:
+        with open("/proc/cpuinfo") as fh:
+            lines = fh.read().splitlines()
+        names = [ln.split(":", 1)[1].strip() for ln in lines if ln.startswith("model name")]
+        if names:
+            model, cores = names[0], len(names)
+    except OSError:
+        pass
+    return model, cores
+
+
+def smoother_traffic(key):
+    """HBM traffic per launch of the finest-level smoother from the committed
+    rocprofv3 counter runs (copy-calibrated FETCH_SIZE + WRITE_SIZE), valid only
+    while the kernel source is unchanged (null otherwise)."""
     path = os.path.join(HERE, "profiles", "smoother_traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
+    rec = json.load(open(path)).get(key)
+    if not rec:
+        return None
     src = open(os.path.join(HERE, "paper_1201_3185_amd", "csrc", "grid_kernels.hip"), "rb").read()
     if rec.get("grid_kernels_sha256") != hashlib.sha256(src).hexdigest():
         return None
     return rec.get("bytes_per_launch")
 
 
-def mixed_vs_fp64(Q, synth, torch, np, dev, reps=3, profile=False):
-    """The metric's second part on the 513^3 workload (two-component disk,
-    1e7 particles, 120 kpc box, monopole boundary): wall time of deposit +
-    both solves (to 1e-6 FP64 relative residual) + gather, plain FP64 against
-    FP32 multigrid with FP64 refinement, and the 513^3 smoother's HBM roofline
-    from the FP64 run's smoother launches.  With profile=True only the mixed
-    case runs, its timed repetitions between two 0.5 s host pauses (for a
-    kernel trace of them)."""
-    n, L = 513, 120.0
-    log("513^3 workload: 1e7 particles")
-    p = synth.two_component_disk(10_000_000, synth.seed_for(3))
-    x, y, z, m = dev(p.x), dev(p.y), dev(p.z), dev(p.m)
+def load_shapes(Q, args, n_max):
+    if args.autotune or not os.path.exists(args.tune_table):
+        log(f"autotuning launch shapes up to {n_max}^3 (setup, not timed)")
+        Q.autotune(n_max=n_max, both=True, reps=5, json_path=args.save_tune)
+        return "autotuned on this GPU"
+    Q.tune_load(args.tune_table)
+    return os.path.relpath(args.tune_table, HERE)
+
+
+class Oracle513:
+    """The CPU oracle on the headline workload: timed, and kept as the
+    reference potentials of the 513^3 legs."""
+
+    def __init__(self, p, threads):
+        import oracle as O
+        self.threads = threads
+        prev = O.set_threads(threads)
+        try:
+            c0 = time.perf_counter()
+            r = O.run_pipeline(O.OracleConfig(n=N3, box_side=[L3], tol_rel=1e-10), p.x, p.y, p.z, p.m, p.total_mass)
+            c1 = time.perf_counter()
+            O.gather(r.phi, [L3], p.x, p.y, p.z, M=p.total_mass, mond=True)
+            c2 = time.perf_counter()
+        finally:
+            O.set_threads(prev)
+        self.seconds = c2 - c0
+        self.gather_seconds = c2 - c1
+        self.phin, self.phi = r.phin[0], r.phi[0]
+        self.cycles = (r.info_newton[0][2], r.info_mond[0][2])
+
+
+def headline(Q, torch, np, x, y, z, m, M, steps, warmup, orc):
+    """The 513^3 FP64 step to 1e-10: timed steps with the finest-level
+    smoother's launches bracketed by hipEvents, then one step with events
+    between its phases (deposit, solves, gather)."""
+    ctx = Q.Context(Q.Config(n=N3, box_side=[L3], tol_rel=1e-10), stream=torch.cuda.current_stream())
+    infos = {}
+
+    def step():
+        ctx.deposit(x, y, z, m, M, count_outside=False)
+        infos["newton"], infos["mond"] = ctx.solve()
+        ctx.gather_forces(x, y, z, 1, with_box=False)
+
+    log(f"513^3 FP64: warmup {warmup}")
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile_enable(True, level_n=N3)
+    log(f"513^3 FP64: timing {steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    st = ctx.profile_read()
+    ctx.profile_enable(False)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    ctx.deposit(x, y, z, m, M, count_outside=False)
+    ev[1].record()
+    ctx.solve()
+    ev[2].record()
+    ctx.gather_forces(x, y, z, 1, with_box=False)
+    ev[3].record()
+    torch.cuda.synchronize()
+    phase = [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+    npart = x.numel()
+    rec = {"ms": ms, "relres_newton": infos["newton"]["relres"][0], "relres_mond": infos["mond"]["relres"][0],
+           "vcycles_after_fmg": [infos["newton"]["vcycles"][0], infos["mond"]["vcycles"][0]],
+           "phases_ms": {"deposit": phase[0], "solves": phase[1], "gather": phase[2]},
+           "deposit_particles_per_s": npart / (phase[0] * 1e-3), "gather_particles_per_s": npart / (phase[2] * 1e-3)}
+    if orc is not None:
+        rec["err_vs_oracle"] = {"phi_n": rel(ctx.get_field(0, Q.FIELD_PHI_N).cpu().numpy(), orc.phin),
+                                "phi": rel(ctx.get_field(0, Q.FIELD_PHI).cpu().numpy(), orc.phi)}
+        rec["oracle_vcycles_after_fmg"] = list(orc.cycles)
+    ctx.close()
+    torch.cuda.empty_cache()
+    return rec, st
+
+
+def to_1e6_513(Q, torch, np, x, y, z, m, M, orc, reps=3):
+    """The metric's second part on the 513^3 workload: wall time of deposit +
+    both solves to a 1e-6 FP64 relative residual + gather, for plain FP64 with
+    the paper's 6 cycles per FMG level, plain FP64 with 2 cycles per level (a
+    plain baseline that does no more than the target needs) and mixed
+    precision (FP32 multigrid, FP64 refinement); each with its error against
+    the oracle's FP64 potentials."""
     out = {"workload": "two-component disk, 1e7 particles, one 513^3 box of 120 kpc, solves to 1e-6"}
-    fields = {}
-    Q.autotune(n_max=n, both=True, reps=3)
-    # plain: the paper's 6 V-cycles per FMG level in FP64; same short schedule in FP64
-    # for comparison; mixed: 2 FP32 cycles per FMG level, then FP64 refinement
-    cases = (("fp64", Q.QUMOND_FP64, 6), ("fp64_2cyc", Q.QUMOND_FP64, 2), ("mixed", Q.QUMOND_MIXED, 2))
-    for name, prec, ncyc in (cases[2:] if profile else cases):
-        ctx = Q.Context(Q.Config(n=n, box_side=[L], precision=prec, tol_rel=1e-6, ncycle_fmg=ncyc))
+    for name, prec, ncyc in (("fp64", Q.QUMOND_FP64, 6), ("fp64_2cyc", Q.QUMOND_FP64, 2),
+                             ("mixed", Q.QUMOND_MIXED, 2)):
+        ctx = Q.Context(Q.Config(n=N3, box_side=[L3], precision=prec, tol_rel=1e-6, ncycle_fmg=ncyc))
         times = []
         for r in range(reps + 1):
             torch.cuda.synchronize()
-            if profile and r == 1:
-                time.sleep(0.5)
             t0 = time.perf_counter()
-            ctx.deposit(x, y, z, m, p.total_mass, count_outside=False)
+            ctx.deposit(x, y, z, m, M, count_outside=False)
             i_n, i_m = ctx.solve()
             ctx.gather_forces(x, y, z, 1, with_box=False)
             torch.cuda.synchronize()
             if r:
                 times.append((time.perf_counter() - t0) * 1e3)
-        if profile:
-            time.sleep(0.5)
         rec = {"ms": float(np.median(times)), "ncycle_fmg": ncyc,
                "relres_newton": i_n["relres"][0], "relres_mond": i_m["relres"][0],
                "cycles_newton": i_n["vcycles"][0], "cycles_mond": i_m["vcycles"][0]}
-        if name == "fp64":
-            ctx.profile_enable(True)
-            ctx.deposit(x, y, z, m, p.total_mass, count_outside=False)
-            ctx.solve()
-            st = ctx.profile_read()
-            ctx.profile_enable(False)
-            gbs = st["alg_bytes"] / (st["total_ms"] * 1e-3) / 1e9
-            rec["smoother_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                                        "launches": st["launches"],
-                                        "avg_launch_us": round(1e3 * st["total_ms"] / max(st["launches"], 1), 2)}
-        fields[name] = ctx.get_field(0, Q.FIELD_PHI).cpu().numpy()
+        if orc is not None:
+            rec["err_vs_oracle"] = {"phi_n": rel(ctx.get_field(0, Q.FIELD_PHI_N).cpu().numpy(), orc.phin),
+                                    "phi": rel(ctx.get_field(0, Q.FIELD_PHI).cpu().numpy(), orc.phi)}
         out[name] = rec
         ctx.close()
         del ctx
         torch.cuda.empty_cache()
-    if profile:
-        log(f"513^3 mixed: {out['mixed']['ms']:.1f} ms per run")
-        return out
-    out["mixed_err_vs_fp64"] = float(np.abs(fields["mixed"] - fields["fp64"]).max() / np.abs(fields["fp64"]).max())
-    out["mixed_err_vs_fp64_2cyc"] = float(np.abs(fields["mixed"] - fields["fp64_2cyc"]).max() /
-                                          np.abs(fields["fp64_2cyc"]).max())
-    out["speedup_mixed"] = out["fp64"]["ms"] / out["mixed"]["ms"]
-    out["speedup_mixed_same_schedule"] = out["fp64_2cyc"]["ms"] / out["mixed"]["ms"]
-    log(f"513^3: fp64 {out['fp64']['ms']:.1f} ms, mixed {out['mixed']['ms']:.1f} ms, "
-        f"err {out['mixed_err_vs_fp64']:.2e}")
+    out["speedup_mixed_vs_fp64"] = out["fp64"]["ms"] / out["mixed"]["ms"]
+    out["speedup_mixed_vs_fp64_2cyc"] = out["fp64_2cyc"]["ms"] / out["mixed"]["ms"]
+    log(f"513^3 to 1e-6: fp64 {out['fp64']['ms']:.1f} ms, fp64 2-cycle {out['fp64_2cyc']['ms']:.1f} ms, "
+        f"mixed {out['mixed']['ms']:.1f} ms")
+    return out
+
+
+def nested_129(Q, synth, torch, np, steps, warmup):
+    """The nested 129^3 step: the same disk with 1e6 particles in four 129^3
+    boxes of 400/200/100/50 kpc, FP64 to 1e-10; smoother launches of all
+    levels timed with hipEvents in a second pass of the same steps."""
+    n, sides = 129, [400.0, 200.0, 100.0, 50.0]
+    p = synth.two_component_disk(1_000_000, synth.seed_for(2))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    x, y, z, m = dev(p.x), dev(p.y), dev(p.z), dev(p.m)
+    ctx = Q.Context(Q.Config(n=n, box_side=sides, tol_rel=1e-10), stream=torch.cuda.current_stream())
+
+    def step():
+        ctx.deposit(x, y, z, m, p.total_mass, count_outside=False)
+        ctx.solve()
+        ctx.gather_forces(x, y, z, 1, with_box=False)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ctx.profile_enable(True)
+    for _ in range(steps):
+        step()
+    st = ctx.profile_read()
+    ctx.profile_enable(False)
+    ctx.close()
+    avg = st["total_ms"] / max(st["launches"], 1)
+    per = st["alg_bytes"] / max(st["launches"], 1)
+    out = {"workload": "two-component disk, 1e6 particles, 4 nested 129^3 boxes (400/200/100/50 kpc), monopole "
+                       "outer BC, FP64 FMG to 1e-10",
+           "ms_per_step": ms, "grid_pts_per_s": 4 * n ** 3 / (ms * 1e-3),
+           "smoother_all_levels": {"launches_per_step": st["launches"] // steps, "avg_launch_us": avg * 1e3,
+                                   "alg_bytes_per_launch": per,
+                                   "achieved_GBs": per / (avg * 1e-3) / 1e9 if avg > 0 else None}}
+    log(f"nested 129^3 step: {ms:.2f} ms")
+    torch.cuda.empty_cache()
     return out
 
 
@@ -166,7 +288,7 @@ def batched_fit(Q, synth, torch, np, reps=3, refine_iters=3):
            "max_relres_newton": max(i["relres_newton"] for i in info),
            "max_relres_mond": max(i["relres_mond"] for i in info),
            "tail_steps": int(sum(i["steps_newton"] + i["steps_mond"] - 2 * refine_iters for i in info)),
-           "device_gb": d["device_bytes"] / 1e9, "shapes": d["classes"]}
+           "device_gb": d["device_bytes"] / 1e9}
     log(f"batched fit: {ms:.1f} ms per run of 64 disks ({pts / (ms * 1e-3):.3g} grid-pts/s), "
         f"eager {t_eager:.1f} ms, {out['converged']}/64 converged")
     b.close()
@@ -267,22 +389,43 @@ def disk_experiments(Q, synth, torch, np, dev):
     return out
 
 
-def learned_leg(Q, torch, np, count=8):
+def learned_leg(Q, torch, np, count=8, oracle_threads=1):
     """Wall time and V-cycles of the QUMOND solve to 1e-6 on held-out disks
-    (seed family 6, 129^3, 120 kpc) for the plain FP64 FMG, FP64 V-cycles from
-    zero / Phi_N / the trained network's prediction, the mixed FMG and the
-    network's prediction followed by mixed-precision refinement; inference
-    time is included where the prediction is used."""
+    (seed family 6, 129^3, 120 kpc) for the plain FP64 FMG with 6, 2 and 1
+    cycles per level, FP64 V-cycles from zero / Phi_N / the trained network's
+    prediction, the mixed FMG and the network's prediction followed by
+    mixed-precision refinement (inference time included where the prediction
+    is used); each variant's potential against the FP64 oracle's (deposit,
+    both solves to 1e-10) on the same particles, when oracle_threads > 0."""
     from paper_1201_3185_amd import learned
     ckpt = os.path.join(HERE, "paper_1201_3185_amd", "weights", "unet129.npy")
     if not os.path.exists(ckpt):
         return None
     net = Q.UNet(129, seed=0)
     net.set_params(np.load(ckpt))
-    g = learned.gain(net, learned.disk_set(count, config=6))
+    params = learned.disk_set(count, config=6)
+    judge = None
+    if oracle_threads > 0:
+        import oracle as O
+        refs = {}
+
+        def judge(i, phi):
+            if i not in refs:
+                x, y, z, m = (t.cpu().numpy() for t in learned._disk_tensors(params[i]))
+                prev = O.set_threads(oracle_threads)
+                try:
+                    o = O.run_pipeline(O.OracleConfig(n=129, box_side=[120.0], tol_rel=1e-10), x, y, z, m,
+                                       float(m.sum()))
+                finally:
+                    O.set_threads(prev)
+                refs[i] = o.phi[0]
+            return rel(phi.cpu().numpy(), refs[i])
+
+    g = learned.gain(net, params, judge=judge)
     g["workload"] = (f"{count} held-out two-component disks (fit parameter ranges), one 129^3 box of 120 kpc, "
                      "QUMOND solve to 1e-6 from the same Phi_N and source")
     g["speedup_vs_fmg"] = {k: g["fmg"]["ms"] / g[k]["ms"] for k in learned.VARIANTS}
+    g["speedup_vs_fmg2"] = {k: g["fmg2"]["ms"] / g[k]["ms"] for k in learned.VARIANTS}
     log("learned guess: " + ", ".join(f"{k} {g[k]['ms']:.2f} ms" for k in learned.VARIANTS) +
         f", inference {g['infer_ms']:.2f} ms")
     net = None
@@ -296,26 +439,30 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile-pass", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the 513^3 FP64-vs-mixed comparison")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="host threads of the oracle's node-parallel loops (0: min(16, logical cores))")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the 513^3 legs to 1e-6")
+    ap.add_argument("--no-nested", action="store_true", help="skip the nested 129^3 step")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-disk batched fit")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess comparison")
     ap.add_argument("--no-kuzmin", action="store_true", help="skip the paper-mode Kuzmin accuracy run")
     ap.add_argument("--no-disks", action="store_true",
                     help="skip the paper-mode thickness, algebraic-MOND and sigma_z experiments")
-    ap.add_argument("--save-tune", default=None, help="write the autotuned smoother table to this JSON file")
-    ap.add_argument("--tune-table", default=None, help="load the smoother table from this JSON file instead of "
-                                                       "autotuning (to replay the same launches under a profiler)")
-    ap.add_argument("--graphs", type=int, default=0,
-                    help="1: the nested step replays its FMG schedules from captured HIP graphs (use_graphs); 0: eager")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the 513^3 FP64 steps (no oracle, no other legs): the command the kernel traces and "
+                         "counter runs profile")
+    ap.add_argument("--tune-table", default=LAUNCH_TABLE,
+                    help="launch-shape table to load (default: the committed MI355X table)")
+    ap.add_argument("--autotune", action="store_true", help="autotune the launch shapes instead of loading a table")
+    ap.add_argument("--save-tune", default=None, help="with --autotune: write the table to this JSON file")
     ap.add_argument("--batch-profile", action="store_true",
                     help="run only the batched-fit leg (for a kernel trace of its replays) and print its record")
-    ap.add_argument("--mixed-profile", action="store_true",
-                    help="run only the 513^3 mixed-precision case (timed runs between host pauses) and print its "
-                         "record")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only copy 1 GiB device to device three times (the known-size kernel that scales the "
+                    help="only copy 1 GiB device to device three times (a known-size copy that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--calibrate-own", action="store_true",
+                    help="only run the library's prolong-add kernel three times on a 513^3 grid (reads 9 B and "
+                         "writes 8 B per fine node: a second, own-kernel scale for the counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): this build has no multi-GPU path; "
@@ -337,122 +484,86 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration_copy_bytes": a.numel() * 8, "copies": 3}), flush=True)
         return
+    if args.calibrate_own:
+        nc = (N3 + 1) // 2
+        uc = torch.ones((nc, nc, nc), dtype=torch.float64, device="cuda")
+        uf = torch.zeros((N3, N3, N3), dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            Q.k_prolong_add(uc, uf)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_kernel": "prolong_k<double, true>", "fine_interior_nodes": (N3 - 2) ** 3,
+                          "coarse_nodes": nc ** 3, "launches": 3}), flush=True)
+        return
     if args.batch_profile:
         print(json.dumps(batched_fit(Q, synth, torch, np, reps=2)), flush=True)
         return
-    if args.mixed_profile:
-        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-        print(json.dumps(mixed_vs_fp64(Q, synth, torch, np, dev, reps=2, profile=True)), flush=True)
-        return
-    n, sides, npart = 129, [400.0, 200.0, 100.0, 50.0], 1_000_000
-    log(f"generating {npart} particles")
-    p = synth.two_component_disk(npart, synth.seed_for(2))
+
+    shapes_from = load_shapes(Q, args, N3)
+    log(f"generating {NP3} particles")
+    p = synth.two_component_disk(NP3, synth.seed_for(3))
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     x, y, z, m = dev(p.x), dev(p.y), dev(p.z), dev(p.m)
     M = p.total_mass
-    if args.tune_table:
-        log(f"loading smoother launch shapes from {args.tune_table}")
-        Q.tune_load(args.tune_table)
-    else:
-        log("autotuning smoother launch shapes (setup, not timed)")
-        Q.autotune(n_max=n, both=False, reps=5, json_path=args.save_tune)
-    shapes = {str(k): {"single": Q.tune_get(k), "fused": Q.tune_get_fused(k)} for k in (33, 65, 129)}
-    cfg = Q.Config(n=n, box_side=sides, tol_rel=1e-10, use_graphs=args.graphs)
-    # graphs need a stream of the step's own (the null stream cannot be captured)
-    stream = torch.cuda.Stream() if args.graphs else torch.cuda.current_stream()
-    stream.wait_stream(torch.cuda.current_stream())
-    ctx = Q.Context(cfg, stream=stream)
-    infos = {}
 
-    def step():
-        with torch.cuda.stream(stream):
-            ctx.deposit(x, y, z, m, M, count_outside=False)
-            infos["newton"], infos["mond"] = ctx.solve()   # source + both FMG chains, overlapped
-            return ctx.gather_forces(x, y, z, 1, with_box=False)
+    orc, cpu = None, None
+    model, ncores = host_cpu()
+    threads = args.cpu_threads if args.cpu_threads > 0 else max(1, min(16, ncores))
+    if not args.no_cpu_baseline and not args.headline_only:
+        log(f"CPU oracle on the full 513^3 workload ({threads} threads)")
+        orc = Oracle513(p, threads)
+        cpu = {"value": N3 ** 3 / orc.seconds, "unit": "grid-pts/s", "cores": threads, "kind": "oracle",
+               "sample": f"the full headline workload (deposit of 1e7 particles, both FMG solves to 1e-10, source, "
+                         f"gather at all particles) in {orc.seconds:.1f} s; node-parallel loops on {threads} threads, "
+                         f"deposit and sums serial",
+               "cpu_model": model, "host_logical_cores": ncores}
+        log(f"oracle: {orc.seconds:.1f} s")
 
-    log(f"warmup {args.warmup}")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"timing {args.steps} steps")
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
-    pts = len(sides) * n ** 3
-    value = pts / (ms * 1e-3)
-    log(f"{ms:.3f} ms/step, {value:.4g} grid-pts/s")
+    head, st = headline(Q, torch, np, x, y, z, m, M, args.steps, args.warmup, orc)
+    ms = head["ms"]
+    value = N3 ** 3 / (ms * 1e-3)
+    avg_ms = st["total_ms"] / max(st["launches"], 1)
+    per_launch = st["alg_bytes"] / max(st["launches"], 1)
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": smoother_traffic("fp64_513"),
+            "kernel": "red-black smoother, finest (513^3) level, one sweep per launch, FP64 (24 B per node)",
+            "launches_per_step": st["launches"] // args.steps, "avg_launch_us": round(avg_ms * 1e3, 2),
+            "alg_bytes_per_launch": per_launch}
+    log(f"513^3 FP64 step {ms:.2f} ms, {value:.4g} grid-pts/s; finest smoother {st['launches']} launches, "
+        f"avg {avg_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic")
 
-    roof = None
-    if not args.no_profile_pass:
-        ctx.profile_enable(True)
-        for _ in range(args.steps):
-            step()
-        st = ctx.profile_read()
-        ctx.profile_enable(False)
-        avg_ms = st["total_ms"] / max(st["launches"], 1)
-        per_launch = st["alg_bytes"] / max(st["launches"], 1)
-        achieved = per_launch / (avg_ms * 1e-3) / 1e9
-        tr = smoother_traffic(per_launch)
-        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
-                "kernel": "red-black smoother launches, all levels (z-march and brick kernels, one or two sweeps per launch; 24 B/pt per launch)", "launches_per_step": st["launches"] // args.steps,
-                "avg_launch_us": round(avg_ms * 1e3, 3), "alg_bytes_per_launch": per_launch}
-        log(f"smoother: {st['launches']} launches, avg {avg_ms * 1e3:.2f} us, {achieved:.1f} GB/s algorithmic")
-
-    mixed = None
-    if not args.no_mixed:
-        mixed = mixed_vs_fp64(Q, synth, torch, np, dev)
-
-    batch = None
-    if not args.no_batch:
-        batch = batched_fit(Q, synth, torch, np)
-
-    kuz = None
-    if not args.no_kuzmin:
-        kuz = kuzmin_paper_mode(Q, synth, torch, np, dev)
-
-    disks = None
-    if not args.no_disks:
-        disks = disk_experiments(Q, synth, torch, np, dev)
-
-    learned_out = None
-    if not args.no_learned:
-        learned_out = learned_leg(Q, torch, np)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle as O
-        log("timing the CPU oracle on one full step")
-        oc = O.OracleConfig(n=n, box_side=sides, tol_rel=1e-10)
-        c0 = time.perf_counter()
-        res = O.run_pipeline(oc, p.x, p.y, p.z, p.m, M)
-        O.gather(res.phi, sides, p.x, p.y, p.z, M=M, mond=True)
-        c1 = time.perf_counter()
-        cpu = {"value": pts / (c1 - c0), "unit": "grid-pts/s", "cores": 1, "kind": "oracle",
-               "sample": "one full step of the same workload (deposit, both FMG solves to 1e-10, source, "
-                         f"gather of all particles) in {c1 - c0:.1f} s, single-threaded C"}
-        log(f"oracle: {c1 - c0:.2f} s")
+    legs = {}
+    if not args.headline_only:
+        if not args.no_mixed:
+            legs["to_1e-6_513"] = to_1e6_513(Q, torch, np, x, y, z, m, M, orc)
+        del x, y, z, m
+        torch.cuda.empty_cache()
+        orc_threads = threads if not args.no_cpu_baseline else 0
+        orc = None
+        if not args.no_nested:
+            legs["nested_129"] = nested_129(Q, synth, torch, np, args.steps, args.warmup)
+        if not args.no_batch:
+            legs["batched_fit_64"] = batched_fit(Q, synth, torch, np)
+        if not args.no_learned:
+            legs["learned_guess_129"] = learned_leg(Q, torch, np, oracle_threads=orc_threads)
+        if not args.no_kuzmin:
+            legs["kuzmin_paper_mode_257"] = kuzmin_paper_mode(Q, synth, torch, np, dev)
+        if not args.no_disks:
+            legs["exponential_disks_paper_mode_257"] = disk_experiments(Q, synth, torch, np, dev)
 
     out = {
         "metric": METRIC, "value": value, "unit": "grid-pts/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "two-component exponential disk, 1e6 particles, 4 nested 129^3 boxes "
-                               "(400/200/100/50 kpc), monopole outer BC, FP64 FMG to 1e-10",
-                   "n": n, "boxes_kpc": sides, "particles": npart, "tol_rel": 1e-10, "ncycle_fmg": 6,
-                   "npre": 2, "npost": 2, "precision": "fp64", "graphs": bool(args.graphs)},
-        "vcycles_after_fmg": {"newton": infos["newton"]["vcycles"], "mond": infos["mond"]["vcycles"]},
-        "smoother_shapes": shapes,
-        "mixed_vs_fp64_513": mixed,
-        "batched_fit_64": batch,
-        "learned_guess_129": learned_out,
-        "kuzmin_paper_mode_257": kuz,
-        "exponential_disks_paper_mode_257": disks,
+        "config": {"workload": "two-component exponential disk, 1e7 particles, one 513^3 box of 120 kpc, monopole "
+                               "outer BC, FP64 FMG (2+2 RB-GS, 6 V-cycles per level) to 1e-10, deposit + both "
+                               "solves + gather at all particles",
+                   "n": N3, "box_kpc": L3, "particles": NP3, "tol_rel": 1e-10, "ncycle_fmg": 6, "npre": 2,
+                   "npost": 2, "precision": "fp64", "launch_shapes": shapes_from},
+        "headline_513": head,
         "roofline": roof, "cpu_baseline": cpu,
     }
+    out.update(legs)
     print(json.dumps(out), flush=True)
 
 

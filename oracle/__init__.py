@@ -85,6 +85,7 @@ def lib():
             "orc_conv3d_dgrad": (None, [i, i, i, vp, i, vp, vp]),
             "orc_conv3d_wgrad": (None, [i, i, vp, i, vp, i, vp]),
             "orc_upsample": (None, [i, i, vp, vp]),
+            "orc_adam_step": (None, [i, vp, vp, vp, vp, d, d, d, d, i]),
             "orc_upsample_adj": (None, [i, i, vp, vp]),
         }
         for name, (res, args) in sig.items():
@@ -447,3 +448,23 @@ def upsample_adj(gf, nc):
     gc = np.zeros((nc ** 3, ch))
     lib().orc_upsample_adj(nc, ch, _p(gf), _p(gc))
     return gc
+
+
+class Adam:
+    """Adam (Kingma and Ba 2015, Algorithm 1) in FP64 on a flat parameter
+    vector: m and v start at zero, step t counts from 1."""
+
+    def __init__(self, w, lr, b1=0.9, b2=0.999, eps=1e-8):
+        self.w = _f64(w).copy()
+        self.m = np.zeros_like(self.w)
+        self.v = np.zeros_like(self.w)
+        self.lr, self.b1, self.b2, self.eps = float(lr), float(b1), float(b2), float(eps)
+        self.t = 0
+
+    def step(self, g, lr=None):
+        g = _f64(g)
+        assert g.shape == self.w.shape
+        self.t += 1
+        lib().orc_adam_step(self.w.size, _p(self.w), _p(self.m), _p(self.v), _p(g),
+                            self.lr if lr is None else float(lr), self.b1, self.b2, self.eps, self.t)
+        return self.w

@@ -11,6 +11,7 @@
  * The input and weight gradients are the adjoints of that map, written
  * directly from the definition (scatter over every output voxel and tap).
  */
+#include <math.h>
 #include <stddef.h>
 
 static int inside(int i, int j, int k, int n) { return i >= 0 && j >= 0 && k >= 0 && i < n && j < n && k < n; }
@@ -116,4 +117,31 @@ void orc_upsample_adj(int nc, int ch, const double *gf, double *gc)
                             for (int c = 0; c < ch; c++) gc[u * ch + c] += w * gf[v * ch + c];
                         }
             }
+}
+
+/*
+ * One step of Adam (Kingma and Ba, "Adam: a method for stochastic
+ * optimization", ICLR 2015, Algorithm 1) on `count` parameters, in FP64: with
+ * the gradient g of step t (t >= 1, counted from 1),
+ *   m <- b1 m + (1 - b1) g,   v <- b2 v + (1 - b2) g^2,
+ *   m_hat = m / (1 - b1^t),   v_hat = v / (1 - b2^t),
+ *   w <- w - lr m_hat / (sqrt(v_hat) + eps).
+ * m and v start at zero before step 1.
+ */
+void orc_adam_step(int count, double *w, double *m, double *v, const double *g, double lr, double b1, double b2,
+                   double eps, int t)
+{
+    double c1 = 1.0, c2 = 1.0;
+    for (int s = 0; s < t; s++) {   /* b1^t and b2^t by repeated products */
+        c1 *= b1;
+        c2 *= b2;
+    }
+    c1 = 1.0 - c1;
+    c2 = 1.0 - c2;
+    for (int i = 0; i < count; i++) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        const double mh = m[i] / c1, vh = v[i] / c2;
+        w[i] -= lr * mh / (sqrt(vh) + eps);
+    }
 }

@@ -320,3 +320,33 @@ def test_point_mass_baselines():
     # (the two inputs may differ in a last bit, hence BF16-level agreement)
     g0 = net.infer(dev(phin - bn), dev(S), h, c_phin, c_out).cpu().numpy()
     assert np.abs((g1 - g0).reshape(n, n, n) - bq).max() <= 1e-2 * c_out < 1e-2 * np.abs(bq).max()
+
+
+def test_adam_updates_match_oracle():
+    """Three training steps: each step's weight update (FP32 master weights,
+    FP32 moments) equals the oracle's FP64 Adam (Kingma and Ba, Algorithm 1)
+    fed the same gradients, to FP32 rounding: 1e-5 of the learning rate plus
+    two FP32 ulps of the weight.  Entries that never had a gradient (the
+    padding of the packed weights) stay put."""
+    n, lr = 17, 2e-3
+    net = Q.UNet(n, seed=11)
+    p0 = net.get_params()
+    net.set_params(p0)                       # moments and step count reset
+    rng = np.random.default_rng(12)
+    x = bf16(rng.standard_normal(2 * n ** 3)).cuda()
+    t = torch.from_numpy(rng.standard_normal(n ** 3).astype(np.float32)).cuda()
+    opt = O.Adam(p0.astype(np.float64), lr=lr)
+    prev_gpu, prev_ref = p0.astype(np.float64), p0.astype(np.float64)
+    touched = np.zeros(p0.size, bool)
+    for step in range(3):
+        net.train_step(x, t, lr, want_loss=False)
+        g = net.get_grads().astype(np.float64)
+        p = net.get_params().astype(np.float64)
+        ref = opt.step(g).copy()
+        d_gpu, d_ref = p - prev_gpu, ref - prev_ref
+        tol = 1e-5 * lr + 2.0 * np.spacing(np.abs(p).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(d_gpu - d_ref) <= tol), (step, np.abs(d_gpu - d_ref).max())
+        touched |= g != 0.0
+        assert np.all(d_gpu[~touched] == 0.0) and touched.sum() < touched.size
+        assert np.abs(d_ref).max() > 0.5 * lr    # the steps are real (about lr per weight)
+        prev_gpu, prev_ref = p, ref
