@@ -73,6 +73,19 @@ qumond_status qumond_k_bc_from_coarse(int32_t n, const double *uc, double *uf, v
 qumond_status qumond_k_resid_norms(int32_t n, double h, const double *f, const double *u, double *out3,
                                    void *stream);
 
+/* qumond_k_resid_norms without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and bits as
+ * qumond_k_resid_norms.  The partial sums live in a fixed 48 KiB workspace
+ * that the library holds on each device for the life of the process (its
+ * address is looked up on the first call on a device); it covers every
+ * n = 2^J + 1 up to 1025, and a larger n returns QUMOND_ERR_INVALID.  All
+ * calls on one device share that workspace: calls that overlap in time on
+ * one device (on different streams, or from different threads) race and must
+ * be serialised by the caller; calls in order on one stream are safe. */
+qumond_status qumond_k_resid_norms_noalloc(int32_t n, double h, const double *f, const double *u, double *out3,
+                                           void *stream);
+
 /* FMG solve of one box in place on u (boundary = Dirichlet values), as
  * qumond_solve_newton does per box.  relres, extra (host, optional). */
 qumond_status qumond_k_fmg(int32_t n, double L, const double *f, double *u, int32_t npre, int32_t npost,

@@ -1,6 +1,7 @@
 // Single-grid entry points (qumond_kernels.h): each runs one kernel, or one
 // FMG / V-cycle schedule, on caller-owned device grids.
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "../../include/qumond_kernels.h"
@@ -24,6 +25,50 @@ qumond_status kcheck(const char *where)
 }
 bool good_n(int n) { return n >= 5 && n <= 1025 && qm::log2_exact(n - 1) >= 2; }
 bool good_nc(int nc) { return nc >= 3 && nc <= 513 && qm::log2_exact(nc - 1) >= 1; }
+}  // namespace
+
+// Workspace of qumond_k_resid_norms_noalloc: the per-workgroup partial sums
+// (three doubles per workgroup) of one problem.  The partial pass uses at most
+// kNormBlocks workgroups for any n, so 48 KiB covers every grid up to the
+// largest the library takes (n = 1025).  Each device holds its own copy for
+// the life of the process.  Host code never uses this name as an address: the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) double scratch[3 * qm::kNormBlocks];
+
+namespace {
+constexpr int kScratchMaxN = 1025;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up on the
+// first call made on that device.
+qumond_status scratch_on_current_device(double **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        qm_set_last_error((std::string("qumond_k_resid_norms_noalloc: hipGetDevice: ") + hipGetErrorString(e)).c_str());
+        return QUMOND_ERR_HIP;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        qm_set_last_error("qumond_k_resid_norms_noalloc: device index beyond the workspace table (64 devices)");
+        return QUMOND_ERR_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            qm_set_last_error((std::string("qumond_k_resid_norms_noalloc: hipGetSymbolAddress: ") +
+                               hipGetErrorString(e)).c_str());
+            return QUMOND_ERR_HIP;
+        }
+        g_scratch_dev[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return QUMOND_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -104,6 +149,20 @@ qumond_status qumond_k_resid_norms(int32_t n, double h, const double *f, const d
     qm::launch_resid_norms<double>(n, h, f, u, partial, out2, s);
     (void)hipFreeAsync(partial, s);
     return kcheck("qumond_k_resid_norms");
+}
+
+qumond_status qumond_k_resid_norms_noalloc(int32_t n, double h, const double *f, const double *u, double *out3,
+                                           void *stream)
+{
+    if (n > kScratchMaxN)
+        return kfail("qumond_k_resid_norms_noalloc: n exceeds the workspace maximum (1025 points per side)");
+    if (!good_n(n) || !(h > 0.0) || !f || !u || !out3) return kfail("qumond_k_resid_norms_noalloc: bad argument");
+    static_assert(3 * qm::kNormBlocks * sizeof(double) == sizeof(scratch), "one problem's partial sums");
+    double *partial = nullptr;
+    const qumond_status st = scratch_on_current_device(&partial);
+    if (st != QUMOND_OK) return st;
+    qm::launch_resid_norms<double>(n, h, f, u, partial, out3, (hipStream_t)stream);
+    return kcheck("qumond_k_resid_norms_noalloc");
 }
 
 static qumond_status run_schedule(int32_t n, double L, const double *f, double *u, int32_t npre, int32_t npost,

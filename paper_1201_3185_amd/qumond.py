@@ -107,6 +107,7 @@ _SIGNATURES = {
     "qumond_k_mond_source": (_I32, [_I32, _D, _D, _P, _P, _P]),
     "qumond_k_bc_from_coarse": (_I32, [_I32, _P, _P, _P]),
     "qumond_k_resid_norms": (_I32, [_I32, _D, _P, _P, _P, _P]),
+    "qumond_k_resid_norms_noalloc": (_I32, [_I32, _D, _P, _P, _P, _P]),
     "qumond_k_fmg": (_I32, [_I32, _D, _P, _P, _I32, _I32, _I32, _I32, _D, ctypes.POINTER(_D),
                             ctypes.POINTER(_I32), _P]),
     "qumond_k_vcycles": (_I32, [_I32, _D, _P, _P, _I32, _I32, _I32, ctypes.POINTER(_D), _P]),
@@ -444,6 +445,13 @@ def k_bc_from_coarse(uc, uf):
 def k_resid_norms(f, u, h, out2):
     check(lib().qumond_k_resid_norms(u.shape[0], float(h), _ptr(f), _ptr(u), _ptr(out2), _s()),
           "qumond_k_resid_norms")
+
+
+def k_resid_norms_noalloc(f, u, h, out3):
+    """k_resid_norms without allocating: partial sums in the library's fixed
+    per-device workspace (calls overlapping on one device race)."""
+    check(lib().qumond_k_resid_norms_noalloc(u.shape[0], float(h), _ptr(f), _ptr(u), _ptr(out3), _s()),
+          "qumond_k_resid_norms_noalloc")
 
 
 def k_fmg(f, u, L, npre=2, npost=2, ncycle=6, max_extra=50, tol=1e-10):
