@@ -8,8 +8,11 @@
 // With another member of the n-family of interpolating functions (nun != 1)
 // the flux is nu_n(|g|/a0) g_n.
 //
-// Kernel design.  Every face flux costs two FP64 square roots and a division,
-// and each face borders two nodes, so the kernel computes each flux once.  A
+// Kernel design.  The face fluxes are the work: each needs |g| and
+// sqrt(1 + 4 a0/|g|), formed from the hardware reciprocal square root refined
+// by Newton-Raphson steps (a few ulp, no correctly rounded square root or
+// division), and each face borders two nodes, so the kernel computes each
+// flux once.  A
 // workgroup owns a TX x TY column tile of interior nodes and marches up a
 // chunk of z planes, holding three planes of Phi_N (k-1, k, k+1; tile plus a
 // one-node ring) in LDS.  On plane k every lane forms the +x, +y and +z face
@@ -29,6 +32,22 @@ namespace qm {
 
 namespace {
 
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton-Raphson
+// steps for f(y) = 1/y^2 - x, y <- y + y (1 - x y^2) / 2 (each step squares
+// the relative error, so two steps take any estimate within 1e-4 to a few
+// units in the last place).
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-(x * y), y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+template <bool FAMILY>
 __device__ __forceinline__ double face_flux(double pp, double pq, double t1, double t2, double ih, double a0,
                                             double nun)
 {
@@ -40,16 +59,24 @@ __device__ __forceinline__ double face_flux(double pp, double pq, double t1, dou
     const double gn = (pq - pp) * ih;
     const double g1 = t1 * (0.25 * ih);
     const double g2 = t2 * (0.25 * ih);
-    const double g = sqrt(gn * gn + g1 * g1 + g2 * g2);
-    if (!(g > 0.0)) return 0.0;
-    if (nun == 1.0) return 0.5 * gn * (1.0 + sqrt(1.0 + 4.0 * a0 / g));
-    return gn * nu_family(g / a0, nun);
+    const double G2 = gn * gn + g1 * g1 + g2 * g2;
+    if (!(G2 > 0.0)) return 0.0;
+    if (!FAMILY) {
+        // nu g_n = g_n (1 + sqrt(1 + 4 a0 / |g|)) / 2 with 1/|g| = 1/sqrt(G2)
+        // and sqrt(x) = x / sqrt(x) plus one Newton correction (x >= 1 here)
+        const double x = 1.0 + 4.0 * a0 * rsqrt_nr(G2);
+        const double y = rsqrt_nr(x);
+        double r = x * y;
+        r = fma(0.5 * y, fma(-r, r, x), r);
+        return 0.5 * gn * (1.0 + r);
+    }
+    return gn * nu_family(sqrt(G2) / a0, nun);
 }
 
 constexpr int kSrcTX = 32, kSrcTY = 8;
 static_assert(kSrcTX + kSrcTY <= 64, "the ring faces fit in the first wavefront");
 
-template <int TX, int TY>
+template <int TX, int TY, bool FAMILY>
 __global__ void __launch_bounds__(TX *TY)
 mond_source_zmarch(int n, double ih, double a0, double nun, const double *__restrict__ P, double *__restrict__ S,
                    int kchunk, int nzc)
@@ -108,15 +135,15 @@ mond_source_zmarch(int n, double ih, double a0, double nun, const double *__rest
     const int cr = tid < TY ? (tid + 1) * PX : (tid - TY + 1);
 
     auto flux_x = [&](const double *M, const double *Z, const double *Q, int q) {   // face q -> q + 1
-        return face_flux(Z[q], Z[q + 1], Z[q + PX] + Z[q + 1 + PX] - Z[q - PX] - Z[q + 1 - PX],
+        return face_flux<FAMILY>(Z[q], Z[q + 1], Z[q + PX] + Z[q + 1 + PX] - Z[q - PX] - Z[q + 1 - PX],
                          Q[q] + Q[q + 1] - M[q] - M[q + 1], ih, a0, nun);
     };
     auto flux_y = [&](const double *M, const double *Z, const double *Q, int q) {   // face q -> q + PX
-        return face_flux(Z[q], Z[q + PX], Z[q + 1] + Z[q + PX + 1] - Z[q - 1] - Z[q + PX - 1],
+        return face_flux<FAMILY>(Z[q], Z[q + PX], Z[q + 1] + Z[q + PX + 1] - Z[q - 1] - Z[q + PX - 1],
                          Q[q] + Q[q + PX] - M[q] - M[q + PX], ih, a0, nun);
     };
     auto flux_z = [&](const double *Z, const double *Q, int q) {   // face plane Z -> plane Q
-        return face_flux(Z[q], Q[q], Z[q + 1] + Q[q + 1] - Z[q - 1] - Q[q - 1],
+        return face_flux<FAMILY>(Z[q], Q[q], Z[q + 1] + Q[q + 1] - Z[q - 1] - Q[q - 1],
                          Z[q + PX] + Q[q + PX] - Z[q - PX] - Q[q - PX], ih, a0, nun);
     };
 
@@ -194,8 +221,12 @@ void launch_mond_source(int n, double h, double a0, const double *phin, double *
     const int kchunk = n >= 513 ? 32 : (n >= 257 ? 16 : (n >= 129 ? 8 : 4));
     const int nzc = (m + kchunk - 1) / kchunk;
     dim3 grid((m + kSrcTX - 1) / kSrcTX, (m + kSrcTY - 1) / kSrcTY, nzc * nb);
-    hipLaunchKernelGGL((mond_source_zmarch<kSrcTX, kSrcTY>), grid, dim3(kSrcTX * kSrcTY), 0, s, n, 1.0 / h, a0, nun,
-                       phin, S, kchunk, nzc);
+    if (nun == 1.0)
+        hipLaunchKernelGGL((mond_source_zmarch<kSrcTX, kSrcTY, false>), grid, dim3(kSrcTX * kSrcTY), 0, s, n, 1.0 / h,
+                           a0, nun, phin, S, kchunk, nzc);
+    else
+        hipLaunchKernelGGL((mond_source_zmarch<kSrcTX, kSrcTY, true>), grid, dim3(kSrcTX * kSrcTY), 0, s, n, 1.0 / h,
+                           a0, nun, phin, S, kchunk, nzc);
     hipLaunchKernelGGL(zero_faces_k, dim3((6 * n * n + 255) / 256, nb), dim3(256), 0, s, n, S);
 }
 
