@@ -249,10 +249,11 @@ qumond_status qumond_set_field(qumond_ctx *ctx, int32_t box, int32_t field, cons
 /* Timing of the red-black smoother, the solve's dominant kernel: when
  * enabled, every smoother launch of the context's FP64 solves is bracketed by
  * two hipEvents on the stream it runs on.  on = 0 disables, on = 1 records
- * every level, on = n (2^J + 1 >= 5) records only the launches on levels of
- * n points per side (n = the box's n: the finest level); any other value
- * returns QUMOND_ERR_INVALID.  The first sweep of a correction from a zero
- * iterate is not recorded.  qumond_profile_read synchronises, returns the
+ * every level, on = n (2^J + 1 >= 5) records only the plain sweeps on levels
+ * of n points per side (n = the box's n: the finest level), leaving out the
+ * sweeps that also apply the coarse-grid correction as they load u; any other
+ * value returns QUMOND_ERR_INVALID.  The first sweep of a correction from a
+ * zero iterate is not recorded.  qumond_profile_read synchronises, returns the
  * number of launches, their summed duration and their summed algorithmic
  * traffic (read u, read f, write u: 3 values per node of the level), and
  * clears the record. */

@@ -26,7 +26,10 @@ extern "C" {
  * columns per workgroup, 5 = 8^3 bricks held whole in LDS (small levels), or
  * z-march over 6 = 64x8, 7 = 64x16, 8 = 128x8 columns with one thread per
  * x-pair of nodes (half the threads per tile), 9 = 4^3, 10 = 6^3 bricks, or
- * 11 = 32x16, 12 = 32x8 pair columns; all give identical results;
+ * 11 = 32x16, 12 = 32x8 pair columns, or 13 = 64x16, 14 = 128x8, 15 = 64x32
+ * pair columns whose loads run two march steps ahead (plain sweeps; a sweep
+ * that also applies the coarse-grid correction uses the pair kernel of the
+ * same tile); all give identical results;
  * kchunk: z planes per workgroup (0 = all; ignored by bricks).  fp32 selects
  * the table of the single-precision smoother. */
 qumond_status qumond_tune_set(int32_t n, int32_t fp32, int32_t variant, int32_t kchunk);

@@ -122,13 +122,14 @@ constexpr int kBatchDepositBlocks = 64;   // deposit workgroups per problem
 // Smoother launch shape: tile variant (z-march over 0: 32x8, 1: 64x4, 2: 64x8,
 // 3: 128x4, 4: 32x16 columns; 5: 8^3 bricks; 6: 64x8, 7: 64x16, 8: 128x8
 // columns with one thread per x-pair of nodes; 9: 4^3, 10: 6^3 bricks; 11: 32x16,
-// 12: 32x8 pair columns) and the number of z planes one workgroup marches
-// through (ignored by bricks).
+// 12: 32x8 pair columns; 13: 64x16, 14: 128x8, 15: 64x32 pair columns with
+// loads two march steps ahead) and the number of z planes one workgroup
+// marches through (ignored by bricks).
 struct SmootherShape {
     int variant;
     int kchunk;
 };
-constexpr int kSmootherVariants = 13;
+constexpr int kSmootherVariants = 16;
 constexpr int kRrVariants = 7;   // residual restriction: gather, 8x8x4 LDS tile, z-march with 4/8/16-plane chunks,
                                  // 4x4x4 and 4x4x2 LDS tiles
 // bricks hold their whole block in LDS and take no z-chunk

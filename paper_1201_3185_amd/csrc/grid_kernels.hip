@@ -209,6 +209,12 @@ rbgs_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict
 // tile plus a one-node ring (up to two red nodes per thread).  Node updates,
 // their order within a plane and the plane pipeline are those of
 // rbgs_zmarch, so the results agree bit for bit.
+// With PROLONG, the coarse planes the correction u += P uc reads are staged
+// in an LDS ring of three (the tile's coarse footprint, (TX/2 + 3) x
+// (TY/2 + 3) values, loaded one march step ahead), and every plane of the
+// march takes its correction from there as it is stored to LDS: one coarse
+// load per coarse node instead of eight per fine node.  The expression is
+// prolong_at's, so the bits are those of a separate prolong-add launch.
 template <typename T, int TX, int TY, bool PROLONG>
 __global__ void __launch_bounds__(TX *TY / 2)
 rbgs_zmarch_pair(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2, int kchunk,
@@ -223,7 +229,10 @@ rbgs_zmarch_pair(const T *__restrict__ uin, T *__restrict__ uout, const T *__res
     constexpr int NRED = HALF * (TY + 2);
     constexpr int RI = (NRED + NT - 1) / NT;      // red nodes per thread
     constexpr int HX = TX / 2;                    // pairs per tile row
+    constexpr int CPX = TX / 2 + 3, CPY = TY / 2 + 3, CPL = CPX * CPY;   // coarse footprint of a plane
+    constexpr int NCL = (CPL + NT - 1) / NT;
     __shared__ T pl[NS][PL];
+    __shared__ T cpl[PROLONG ? 3 : 1][PROLONG ? CPL : 1];
     const T sixth = T(1) / T(6);
     const int tid = threadIdx.x;
     const unsigned tl = xcd_tile(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
@@ -240,6 +249,46 @@ rbgs_zmarch_pair(const T *__restrict__ uin, T *__restrict__ uout, const T *__res
     uout += (size_t)pb * nn * n;
     f += (size_t)pb * nn * n;
     if (PROLONG) uc += (size_t)pb * nc * nc * nc;
+    // coarse footprint: coarse nodes ci0 .. ci0 + CPX - 1 (and likewise in y)
+    // cover the interpolation stencils of fine nodes i0 - 2 .. i0 + TX + 1
+    const int ci0 = (i0 - 3) >> 1, cj0 = (j0 - 3) >> 1;
+    int coff[NCL];
+    T cv[NCL];
+#pragma unroll
+    for (int r = 0; r < NCL; ++r) {
+        const int t = tid + r * NT;
+        const int I = ci0 + t % CPX, J = cj0 + t / CPX;
+        coff[r] = (PROLONG && t < CPL && I >= 0 && I < nc && J >= 0 && J < nc) ? I + nc * J : -1;
+        cv[r] = T(0);
+    }
+    auto fetch_c = [&](int c) {   // coarse plane c into registers
+#pragma unroll
+        for (int r = 0; r < NCL; ++r) cv[r] = coff[r] >= 0 ? uc[(size_t)c * nc * nc + coff[r]] : T(0);
+    };
+    auto store_c = [&](int c) {   // ... and from there into its LDS slot
+        if constexpr (PROLONG) {
+            T *D = cpl[c % 3];
+#pragma unroll
+            for (int r = 0; r < NCL; ++r) {
+                const int t = tid + r * NT;
+                if (t < CPL) D[t] = cv[r];
+            }
+        }
+    };
+    // prolong_at's trilinear value from the staged coarse planes
+    auto prolong_lds = [&](int i, int j, int k) {
+        const int ia = (i >> 1) - ci0, ib = ((i + 1) >> 1) - ci0, ja = (j >> 1) - cj0, jb = ((j + 1) >> 1) - cj0;
+        const T *Ca = cpl[(k >> 1) % 3];
+        const T *Cb = cpl[((k + 1) >> 1) % 3];
+        const T wia = (i & 1) ? T(0.5) : T(1), wib = (i & 1) ? T(0.5) : T(0);
+        const T wja = (j & 1) ? T(0.5) : T(1), wjb = (j & 1) ? T(0.5) : T(0);
+        const T wka = (k & 1) ? T(0.5) : T(1), wkb = (k & 1) ? T(0.5) : T(0);
+        const T xa = wia * Ca[ia + CPX * ja] + wib * Ca[ib + CPX * ja];
+        const T xb = wia * Ca[ia + CPX * jb] + wib * Ca[ib + CPX * jb];
+        const T xc = wia * Cb[ia + CPX * ja] + wib * Cb[ib + CPX * ja];
+        const T xd = wia * Cb[ia + CPX * jb] + wib * Cb[ib + CPX * jb];
+        return wka * (wja * xa + wjb * xb) + wkb * (wja * xc + wjb * xd);
+    };
 
     int goff[NL], gij[NL];
 #pragma unroll
@@ -283,17 +332,20 @@ rbgs_zmarch_pair(const T *__restrict__ uin, T *__restrict__ uout, const T *__res
         }
     };
     T v[NL];
-    auto prefetch = [&](int k) {
+    auto prefetch = [&](int k) {   // raw values; the correction is added from LDS at commit
         const T *src = uin ? uin + (size_t)k * nn : nullptr;
 #pragma unroll
-        for (int r = 0; r < NL; ++r) v[r] = goff[r] >= 0 ? corrected(src ? src[goff[r]] : T(0), r, k) : T(0);
+        for (int r = 0; r < NL; ++r) v[r] = goff[r] >= 0 ? (src ? src[goff[r]] : T(0)) : T(0);
     };
     auto commit = [&](int k) {
         T *P = pl[k % NS];
 #pragma unroll
         for (int r = 0; r < NL; ++r) {
             const int t = tid + r * NT;
-            if (t < PL) P[t] = v[r];
+            if (t >= PL) continue;
+            T x = v[r];
+            if (PROLONG && k >= 1 && k <= n - 2 && gij[r] >= 0) x += prolong_lds(gij[r] & 0xffff, gij[r] >> 16, k);
+            P[t] = x;
         }
     };
     auto f_red = [&](int k, T *fr) {
@@ -367,6 +419,19 @@ rbgs_zmarch_pair(const T *__restrict__ uin, T *__restrict__ uout, const T *__res
         load_now(kb);
         load_now(kb + 1);
         if (kb + 2 <= n - 1) load_now(kb + 2);
+        // the coarse planes of the march's first stored plane (kb + 3), and the
+        // one the first odd step stages
+        const int ca = (kb + 3) >> 1, cb = (kb + 4) >> 1;
+        if (ca <= nc - 1) {
+            fetch_c(ca);
+            store_c(ca);
+        }
+        if (cb != ca && cb <= nc - 1) {
+            fetch_c(cb);
+            store_c(cb);
+        }
+        const int c1 = ((kb | 1) + 5) / 2;
+        if (c1 <= nc - 1) fetch_c(c1);
     }
     T fr0[RI], fr1[RI], fr2[RI];
 #pragma unroll
@@ -405,8 +470,230 @@ rbgs_zmarch_pair(const T *__restrict__ uin, T *__restrict__ uout, const T *__res
         black_store(k, fb);
         __syncthreads();
         if (more) red(k + 2, fr);
+        // an odd step stages coarse plane (k + 5) / 2, first read by the store
+        // of fine plane k + 4 in the next step, into the slot of plane
+        // (k - 1) / 2, last read three steps ago; then loads the next one
+        if (PROLONG && (k & 1)) {
+            if ((k + 5) / 2 <= nc - 1) store_c((k + 5) / 2);
+            if ((k + 7) / 2 <= nc - 1) fetch_c((k + 7) / 2);
+        }
         __syncthreads();
     }
+}
+
+// The pair sweep with its loads two march steps ahead: plane k+5 of u, the
+// red f values of plane k+4 and the black ones of plane k+2 are requested in
+// step k, so a load has two steps' time to arrive (the pair kernel gives it
+// one).  Two register sets alternate between even and odd steps (the loop is
+// unrolled by two).  Plain sweeps only (no correction on load); the plane
+// pipeline, LDS layout and node updates are the pair kernel's, so the bits
+// are too.
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY / 2)
+rbgs_zmarch_pair_deep(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2,
+                      int kchunk, int nzc)
+{
+#pragma clang fp contract(off)
+    static_assert(TX % 2 == 0, "x-pairs");
+    constexpr int PX = TX + 4, PY = TY + 4, NS = 5, NT = TX * TY / 2;
+    constexpr int PL = PX * PY;
+    constexpr int NL = (PL + NT - 1) / NT;
+    constexpr int HALF = (TX + 2) / 2;
+    constexpr int NRED = HALF * (TY + 2);
+    constexpr int RI = (NRED + NT - 1) / NT;
+    constexpr int HX = TX / 2;
+    __shared__ T pl[NS][PL];
+    const T sixth = T(1) / T(6);
+    const int tid = threadIdx.x;
+    const unsigned tl = xcd_tile(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                 gridDim.x * gridDim.y * gridDim.z);
+    const int bx = tl % gridDim.x, by = (tl / gridDim.x) % gridDim.y, bzz = tl / (gridDim.x * gridDim.y);
+    const int i0 = 1 + bx * TX, j0 = 1 + by * TY;
+    const int pb = bzz / nzc;
+    const int kb = 1 + (bzz - pb * nzc) * kchunk;
+    if (kb > n - 2) return;
+    const int ke = min(kb + kchunk - 1, n - 2);
+    const size_t nn = (size_t)n * n;
+    if (uin) uin += (size_t)pb * nn * n;   // a null uin (zero iterate) stays null
+    uout += (size_t)pb * nn * n;
+    f += (size_t)pb * nn * n;
+
+    int goff[NL];
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+        const int t = tid + r * NT;
+        const int a = t % PX, b = t / PX;
+        const int i = i0 - 2 + a, j = j0 - 2 + b;
+        goff[r] = (t < PL && i >= 0 && i < n && j >= 0 && j < n) ? i + n * j : -1;
+    }
+    int br[RI], jr[RI], qr[RI];
+    bool rv[RI];
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+        const int t = tid + r * NT;
+        br[r] = 1 + t / HALF;
+        jr[r] = j0 - 2 + br[r];
+        qr[r] = t % HALF;
+        rv[r] = t < NRED && jr[r] >= 1 && jr[r] <= n - 2;
+    }
+    auto red_a = [&](int r, int k) { return ((((i0 - 1) + jr[r] + k) & 1) ? 2 : 1) + 2 * qr[r]; };
+    const int bb = 2 + tid / HX, lo = 2 + 2 * (tid % HX);
+    const int jb = j0 - 2 + bb, ilo = i0 - 2 + lo;
+    const bool row_ok = jb <= n - 2;
+    auto black_a = [&](int k) { return ((ilo + jb + k) & 1) ? lo : lo + 1; };
+
+    auto fetch = [&](int k, T *vv) {
+        const T *src = uin ? uin + (size_t)k * nn : nullptr;
+#pragma unroll
+        for (int r = 0; r < NL; ++r) vv[r] = goff[r] >= 0 ? (src ? src[goff[r]] : T(0)) : T(0);
+    };
+    auto commit = [&](int k, const T *vv) {
+        T *P = pl[k % NS];
+#pragma unroll
+        for (int r = 0; r < NL; ++r) {
+            const int t = tid + r * NT;
+            if (t < PL) P[t] = vv[r];
+        }
+    };
+    auto f_red = [&](int k, T *fr) {
+#pragma unroll
+        for (int r = 0; r < RI; ++r) {
+            const int i = i0 - 2 + red_a(r, k);
+            fr[r] = (rv[r] && i >= 1 && i <= n - 2) ? f[(size_t)k * nn + i + (size_t)n * jr[r]] : T(0);
+        }
+    };
+    auto f_black = [&](int k) {
+        const int i = i0 - 2 + black_a(k);
+        return (row_ok && i <= n - 2) ? f[(size_t)k * nn + i + (size_t)n * jb] : T(0);
+    };
+    auto red = [&](int k, const T *fr) {
+        T *P = pl[k % NS];
+        const T *Pm = pl[(k - 1) % NS];
+        const T *Pp = pl[(k + 1) % NS];
+#pragma unroll
+        for (int r = 0; r < RI; ++r) {
+            const int a = red_a(r, k), i = i0 - 2 + a;
+            if (!rv[r] || i < 1 || i > n - 2) continue;
+            const int c = br[r] * PX + a;
+            const T s = P[c - 1] + P[c + 1] + P[c - PX] + P[c + PX] + Pm[c] + Pp[c];
+            P[c] = (s - h2 * fr[r]) * sixth;
+        }
+    };
+    auto black_store = [&](int k, T fv) {
+        if (!row_ok) return;
+        const T *P = pl[k % NS];
+        const T *Pm = pl[(k - 1) % NS];
+        const T *Pp = pl[(k + 1) % NS];
+        const int ab = black_a(k), ar = ab == lo ? lo + 1 : lo;
+        const int ib = i0 - 2 + ab, ir = i0 - 2 + ar;
+        T *dst = uout + (size_t)k * nn + (size_t)n * jb;
+        if (ib <= n - 2) {
+            const int c = bb * PX + ab;
+            const T s = P[c - 1] + P[c + 1] + P[c - PX] + P[c + PX] + Pm[c] + Pp[c];
+            dst[ib] = (s - h2 * fv) * sixth;
+        }
+        if (ir <= n - 2) dst[ir] = P[bb * PX + ar];
+    };
+
+    // warm-up: planes kb-2..kb+2 (all loads in flight before the first LDS
+    // store, offsets clamped into the grid) and red of kb-1..kb+1
+    {
+        T w[5][NL];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const T *src = uin ? uin + (size_t)min(max(kb - 2 + q, 0), n - 1) * nn : nullptr;
+#pragma unroll
+            for (int r = 0; r < NL; ++r) {
+                const T x = src ? src[max(goff[r], 0)] : T(0);
+                w[q][r] = goff[r] >= 0 ? x : T(0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const int k = kb - 2 + q;
+            if (k < 0 || k > n - 1) continue;
+            T *P = pl[k % NS];
+#pragma unroll
+            for (int r = 0; r < NL; ++r) {
+                const int t = tid + r * NT;
+                if (t < PL) P[t] = w[q][r];
+            }
+        }
+    }
+    T fr0[RI], fr1[RI], fr2[RI];
+#pragma unroll
+    for (int r = 0; r < RI; ++r) fr0[r] = fr2[r] = T(0);
+    if (kb - 1 >= 1) f_red(kb - 1, fr0);
+    f_red(kb, fr1);
+    if (kb + 1 <= n - 2) f_red(kb + 1, fr2);
+    __syncthreads();
+    if (kb - 1 >= 1) red(kb - 1, fr0);
+    red(kb, fr1);
+    if (kb + 1 <= n - 2) red(kb + 1, fr2);
+    __syncthreads();
+
+    auto need_red = [&](int k) { return (k + 2 <= n - 2) && (k + 2 <= ke + 1); };  // red(k+2) in step k
+    // two register sets: set A serves the steps of kb's parity, set B the others
+    T vA[NL], vB[NL], rA[RI], rB[RI];
+    T bA = T(0), bB = T(0);
+#pragma unroll
+    for (int r = 0; r < RI; ++r) rA[r] = rB[r] = T(0);
+    bA = f_black(kb);
+    if (need_red(kb)) {
+        fetch(kb + 3, vA);
+        f_red(kb + 2, rA);
+    }
+    if (kb + 1 <= ke) {
+        bB = f_black(kb + 1);
+        if (need_red(kb + 1)) {
+            fetch(kb + 4, vB);
+            f_red(kb + 3, rB);
+        }
+    }
+    auto step = [&](int k, T *vX, T *rX, T &bX) {
+        const bool more = need_red(k);
+        if (more) commit(k + 3, vX);
+        const T fb = bX;
+        T frc[RI];
+#pragma unroll
+        for (int r = 0; r < RI; ++r) frc[r] = rX[r];
+        if (k + 2 <= ke) {   // refill the set for step k + 2
+            bX = f_black(k + 2);
+            if (need_red(k + 2)) {
+                fetch(k + 5, vX);
+                f_red(k + 4, rX);
+            }
+        }
+        black_store(k, fb);
+        __syncthreads();
+        if (more) red(k + 2, frc);
+        __syncthreads();
+    };
+    for (int k = kb; k <= ke; k += 2) {
+        step(k, vA, rA, bA);
+        if (k + 1 <= ke) step(k + 1, vB, rB, bB);
+    }
+}
+
+template <typename T, int TX, int TY>
+static void rbgs_pair_launch(int n, double h, const T *f, const T *uin, T *uout, int kchunk, int nb, const T *uc,
+                             hipStream_t s);
+
+// The deep-prefetch pair sweep; a sweep that also applies the coarse-grid
+// correction runs the pair kernel's correcting form.
+template <typename T, int TX, int TY>
+static void rbgs_pair_deep_launch(int n, double h, const T *f, const T *uin, T *uout, int kchunk, int nb, const T *uc,
+                                  hipStream_t s)
+{
+    if (uc) {
+        rbgs_pair_launch<T, TX, TY>(n, h, f, uin, uout, kchunk, nb, uc, s);
+        return;
+    }
+    const int m = n - 2;
+    const int nzc = (m + kchunk - 1) / kchunk;
+    dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, nzc * nb);
+    hipLaunchKernelGGL((rbgs_zmarch_pair_deep<T, TX, TY>), grid, dim3(TX * TY / 2), 0, s, uin, uout, f, n, T(h * h),
+                       kchunk, nzc);
 }
 
 template <typename T, int TX, int TY>
@@ -779,11 +1066,15 @@ int &split_prolong(int n)
     return g_split_prolong[sizeof(T) == 4 ? 1 : 0][J > 10 ? 10 : J];
 }
 
+// One flag for both precisions: the defaults of the whole table are written
+// once, so an entry set for one precision is never reset by the first use of
+// the other.
+static bool g_rbgs2_init = false;
+
 template <typename T>
 SmootherShape &rbgs2_shape(int n)
 {
-    static bool init = false;
-    if (!init) {
+    if (!g_rbgs2_init) {
         for (int t = 0; t < 2; ++t)
             for (int J = 0; J <= 10; ++J) {
                 SmootherShape &sh = g_rbgs2_shape[t][J];
@@ -792,7 +1083,7 @@ SmootherShape &rbgs2_shape(int n)
                 else if (J == 7) sh = {1, 16};
                 else sh = {1, 64};
             }
-        init = true;
+        g_rbgs2_init = true;
     }
     int J = 0;
     while ((1 << J) < n - 1) ++J;
@@ -826,6 +1117,9 @@ void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, Smoot
     case 10: brick_launch<T, 1, 6>(n, h, f, uin, uout, uc, nb, s); break;
     case 11: rbgs_pair_launch<T, 32, 16>(n, h, f, uin, uout, kc, nb, uc, s); break;
     case 12: rbgs_pair_launch<T, 32, 8>(n, h, f, uin, uout, kc, nb, uc, s); break;
+    case 13: rbgs_pair_deep_launch<T, 64, 16>(n, h, f, uin, uout, kc, nb, uc, s); break;
+    case 14: rbgs_pair_deep_launch<T, 128, 8>(n, h, f, uin, uout, kc, nb, uc, s); break;
+    case 15: rbgs_pair_deep_launch<T, 64, 32>(n, h, f, uin, uout, kc, nb, uc, s); break;
     default: rbgs_launch<T, 64, 4>(n, h, f, uin, uout, kc, nb, uc, s); break;
     }
 }
@@ -1126,7 +1420,22 @@ residual_restrict_zmarch_k(int nf, T ih2, const T *__restrict__ f, const T *__re
         fc[C] = acc;
     };
 
-    T fa[NR], fb[NR];
+    // u planes 2K+1, 2K+2 and f planes 2K, 2K+1 of step K travel in registers
+    // one step ahead: their loads are in flight while step K-1 computes
+    T ua[NU], ub[NU], fa[NR], fb[NR];
+    auto fetch_u = [&](int p, T *uv) {
+        const T *src = u + (size_t)p * sz;
+#pragma unroll
+        for (int r = 0; r < NU; ++r) uv[r] = uoff[r] >= 0 ? src[uoff[r]] : T(0);
+    };
+    auto store_u = [&](int p, const T *uv) {
+        T *U = Us[p & 3];
+#pragma unroll
+        for (int r = 0; r < NU; ++r) {
+            const int t = tid + r * NT;
+            if (t < UP) U[t] = uv[r];
+        }
+    };
     // warm-up: u planes 2Kb-2..2Kb and the residual of plane 2Kb-1
     load_u(2 * Kb - 2);
     load_u(2 * Kb - 1);
@@ -1134,15 +1443,29 @@ residual_restrict_zmarch_k(int nf, T ih2, const T *__restrict__ f, const T *__re
     load_f(2 * Kb - 1, fa);
     __syncthreads();
     resid(2 * Kb - 1, fa);
+    fetch_u(2 * Kb + 1, ua);
+    fetch_u(2 * Kb + 2, ub);
+    load_f(2 * Kb, fa);
+    load_f(2 * Kb + 1, fb);
     __syncthreads();
     for (int K = Kb; K <= Ke; ++K) {
-        load_u(2 * K + 1);   // slots of planes 2K-3 and 2K-2, last read before the previous barrier
-        load_u(2 * K + 2);
-        load_f(2 * K, fa);
-        load_f(2 * K + 1, fb);
+        store_u(2 * K + 1, ua);   // slots of planes 2K-3 and 2K-2, last read before the previous barrier
+        store_u(2 * K + 2, ub);
+        T fc0[NR], fc1[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            fc0[r] = fa[r];
+            fc1[r] = fb[r];
+        }
+        if (K + 1 <= Ke) {   // the next step's planes, in flight during this one
+            fetch_u(2 * K + 3, ua);
+            fetch_u(2 * K + 4, ub);
+            load_f(2 * K + 2, fa);
+            load_f(2 * K + 3, fb);
+        }
         __syncthreads();
-        resid(2 * K, fa);
-        resid(2 * K + 1, fb);
+        resid(2 * K, fc0);
+        resid(2 * K + 1, fc1);
         __syncthreads();
         restrict_plane(K);
     }

@@ -48,7 +48,7 @@ struct Level {
 // with its algorithmic traffic: read u, read f, write u = 3 values per node.
 struct SmootherProfile {
     bool on = false;
-    int only_n = 0;   // if > 0, only the launches on levels of only_n points per side
+    int only_n = 0;   // if > 0, only the plain sweeps (no folded correction) on levels of only_n points per side
     std::vector<hipEvent_t> ev;
     std::vector<double> bytes;
     size_t used = 0;
@@ -189,9 +189,9 @@ struct Multigrid {
         for (int l = 1; l <= J; ++l) lv[l].cur = 0;
     }
 
-    void time_begin(hipEvent_t *e0, hipEvent_t *e1, double bytes, int n)
+    void time_begin(hipEvent_t *e0, hipEvent_t *e1, double bytes, int n, bool folds_correction)
     {
-        if (!prof.on || (prof.only_n > 0 && prof.only_n != n)) return;
+        if (!prof.on || (prof.only_n > 0 && (prof.only_n != n || folds_correction))) return;
         prof.record_pair(s, e0, e1);
         prof.bytes.push_back(bytes);
         (void)hipEventRecord(*e0, s);
@@ -223,7 +223,7 @@ struct Multigrid {
         const bool fuse = fused && (shapes ? shapes->use_fused[l] != 0 : use_fused<T>(v.n) != 0);
         while (ns > 0) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
-            time_begin(&e0, &e1, 3.0 * sizeof(T) * pts * nb, v.n);
+            time_begin(&e0, &e1, 3.0 * sizeof(T) * pts * nb, v.n, uc != nullptr);
             if (ns >= 2 && fuse) {
                 const SmootherShape sh = shapes ? shapes->fused[l] : rbgs2_shape<T>(v.n);
                 launch_rbgs2_shape<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], uc, sh, s, nb);

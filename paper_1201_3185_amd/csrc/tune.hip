@@ -21,7 +21,7 @@ qumond_status tfail(const std::string &m)
 
 bool good_n(int n) { return n >= 5 && n <= 1025 && qm::log2_exact(n - 1) >= 2; }
 
-const int kChunks[] = {2, 4, 8, 16, 32, 64, 128, 0};
+const int kChunks[] = {2, 4, 8, 16, 32, 64, 128, 256, 0};
 
 template <typename T>
 qumond_status tune_one(int n, int reps, hipStream_t s, double &best_us, bool fused)

@@ -146,3 +146,25 @@ def test_batch_null_handles(Q):
     assert L.qumond_batch_device_bytes(None) == 0
     c = Q.BatchConfig().to_c(1)
     assert L.qumond_batch_validate(ctypes.byref(c), None, None, 0) == Q.QUMOND_ERR_INVALID
+
+
+def test_tune_tables_keep_entries_of_both_precisions():
+    """Setting a launch shape for one precision never resets the other's
+    table (the defaults are written once for both), so the entries of a
+    loaded table survive whatever order its FP64 and FP32 rows come in.  Run
+    in a fresh process: the first use of each precision's table is the case."""
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_1201_3185_amd import qumond as Q\n"
+        "Q.tune_set_fused(33, 3, 0, fp32=False)\n"
+        "Q.tune_set(33, 9, 0, fp32=False)\n"
+        "Q.tune_set_fused(33, 4, 0, fp32=True)\n"
+        "Q.tune_set(33, 10, 0, fp32=True)\n"
+        "assert Q.tune_get_fused(33, fp32=False) == (3, 0), Q.tune_get_fused(33, fp32=False)\n"
+        "assert Q.tune_get(33, fp32=False) == (9, 0)\n"
+        "assert Q.tune_get_fused(33, fp32=True) == (4, 0)\n"
+        "assert Q.tune_get(33, fp32=True) == (10, 0)\n"
+        "print('ok')\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr

@@ -6,13 +6,15 @@
   (also after the per-batch autotuner has changed them).
 * The captured graph, replayed several times with other GPU work and host
   synchronisations in between, reproduces the direct launches bit for bit.
-* Against the FP64 oracle: the deposit's right-hand side to rounding, the
-  residual of the batch's potentials under the oracle's own operator below
-  the tolerance, and the potentials close to the oracle's FP64 FMG solution.
+* Against the FP64 oracle (33^3 to 257^3): the deposit's right-hand side to
+  rounding, the residual of the batch's potentials under the oracle's own
+  operator below the tolerance, and the potentials within 2e-6 of the
+  oracle's after a 1e-6 residual, 1e-6 after 1e-7.
 * The tail check: with no refinement steps in the graph every problem is
   brought to tolerance afterwards (and its QUMOND part redone).
-* The batched fit's workload: 64 disks of 129^3 and 257^3, sampled problems
-  checked against the single-problem context and the oracle's residual.
+* The batched fit's workload: 64 disks of 129^3 and 257^3; one problem of
+  each size bit for bit against the single-problem context with the same
+  refinement counts, and against the oracle's pipeline at the 2e-6 bar.
 """
 import numpy as np
 import pytest
@@ -196,26 +198,45 @@ def test_power_of_two_scales_give_the_same_iterate():
     b.close()
 
 
-def test_batch_against_oracle():
-    ns = [33, 65]
+@pytest.fixture(scope="module")
+def oracle_threads():
+    import os
+    prev = O.set_threads(max(1, min(16, os.cpu_count() or 1)))   # same bits at any thread count
+    yield
+    O.set_threads(prev)
+
+
+def test_batch_against_oracle(oracle_threads):
+    """Four problems of 33^3 to 257^3 against the oracle's FP64 pipeline (to
+    1e-10) on the same particles: the right-hand side to rounding, the source
+    formed by the oracle from the batch's own Phi_N to 1e-12, and the
+    potentials to the mixed-precision bars -- 2e-6 of max|Phi| when stopped at
+    a 1e-6 FP64 residual, 1e-6 when refined to 1e-7."""
+    ns = [33, 65, 129, 257]
     parts = small_disks(ns, seed0=500)
-    b = make_batch(ns, parts, refine_iters=4, max_extra=20, tol_rel=1e-6)
-    info = b.run(use_graph=True)
+    refs = []
     for p, n in enumerate(ns):
-        assert info[p]["converged"] == 1
         oc = O.OracleConfig(n=n, box_side=[L_BOX], tol_rel=1e-10)
-        o = O.run_pipeline(oc, parts[p].x, parts[p].y, parts[p].z, parts[p].m, parts[p].total_mass)
-        g = batch_fields(b, p)
-        h = L_BOX / (n - 1)
-        assert rel(g["f"], o.f[0]) <= 1e-15
-        for u, f in ((g["phin"], o.f[0]), (g["phi"], g["S"])):
-            r = O.residual(f, u, h)
-            rr = np.sqrt((r ** 2).sum() / (f[1:-1, 1:-1, 1:-1] ** 2).sum())
-            assert rr <= 1e-6
-        # the source from the batch's Phi_N under the oracle's Eq. 2 discretisation
-        assert rel(g["S"], O.mond_source(g["phin"], L_BOX)) <= 1e-12
-        assert rel(g["phin"], o.phin[0]) <= 1e-5
-        assert rel(g["phi"], o.phi[0]) <= 1e-5
+        refs.append(O.run_pipeline(oc, parts[p].x, parts[p].y, parts[p].z, parts[p].m, parts[p].total_mass))
+    for tol, bar in ((1e-6, 2e-6), (1e-7, 1e-6)):
+        b = make_batch(ns, parts, refine_iters=3, max_extra=20, tol_rel=tol)
+        info = b.run(use_graph=True)
+        for p, n in enumerate(ns):
+            o = refs[p]
+            assert info[p]["converged"] == 1
+            assert info[p]["relres_newton"] <= tol and info[p]["relres_mond"] <= tol
+            g = batch_fields(b, p)
+            h = L_BOX / (n - 1)
+            assert rel(g["f"], o.f[0]) <= 1e-15
+            for u, f in ((g["phin"], o.f[0]), (g["phi"], g["S"])):
+                r = O.residual(f, u, h)
+                rr = np.sqrt((r ** 2).sum() / (f[1:-1, 1:-1, 1:-1] ** 2).sum())
+                assert rr <= tol * 1.0001
+            # the source from the batch's Phi_N under the oracle's Eq. 2 discretisation
+            assert rel(g["S"], O.mond_source(g["phin"], L_BOX)) <= 1e-12
+            assert rel(g["phin"], o.phin[0]) <= bar, (n, tol)
+            assert rel(g["phi"], o.phi[0]) <= bar, (n, tol)
+        b.close()
 
 
 def test_tail_check_converges_every_problem():
@@ -231,7 +252,8 @@ def test_tail_check_converges_every_problem():
     b2 = make_batch(ns, parts, refine_iters=5, max_extra=30, tol_rel=1e-7)
     b2.run(use_graph=True)
     for p in range(len(ns)):
-        assert rel(b.get_field(p, Q.FIELD_PHI).cpu().numpy(), b2.get_field(p, Q.FIELD_PHI).cpu().numpy()) <= 1e-5
+        # both within 1e-6 of the converged field (the 1e-7-residual bar)
+        assert rel(b.get_field(p, Q.FIELD_PHI).cpu().numpy(), b2.get_field(p, Q.FIELD_PHI).cpu().numpy()) <= 2e-6
 
 
 def test_empty_problem_and_particles_outside():
@@ -261,8 +283,29 @@ def test_run_before_particles_is_a_state_error():
     assert e.value.status == Q.QUMOND_ERR_STATE
 
 
+def solo_steps(n, p, k_newton, k_mond, mass):
+    """The single-problem context with the batch's refinement counts of each
+    solve: the Newtonian solve with k_newton steps, then Phi_N and the source
+    handed to a second context whose QUMOND solve takes k_mond steps."""
+    mk = lambda K: Q.Context(Q.Config(n=n, box_side=[L_BOX], precision=Q.QUMOND_MIXED, ncycle_fmg=2,
+                                      tol_rel=1e-300, max_vcycles=K))
+    a = mk(k_newton)
+    a.deposit(dev(p.x), dev(p.y), dev(p.z), dev(p.m), mass)
+    a.solve_newton(allow_not_converged=True)
+    a.mond_source()
+    b = mk(k_mond)
+    b.deposit(dev(p.x), dev(p.y), dev(p.z), dev(p.m), mass)
+    b.set_field(0, Q.FIELD_PHI_N, a.get_field(0, Q.FIELD_PHI_N).reshape(-1))
+    b.set_field(0, Q.FIELD_SOURCE, a.get_field(0, Q.FIELD_SOURCE).reshape(-1))
+    b.solve_mond(allow_not_converged=True)
+    out = {k: a.get_field(0, f).cpu().numpy() for k, f in
+           (("f", Q.FIELD_RHS), ("phin", Q.FIELD_PHI_N), ("S", Q.FIELD_SOURCE))}
+    out["phi"] = b.get_field(0, Q.FIELD_PHI).cpu().numpy()
+    return out
+
+
 @pytest.mark.slow
-def test_fit_workload_64_disks():
+def test_fit_workload_64_disks(oracle_threads):
     params = synth.fit_grid(64, config=4)
     ns = [dp.n_grid for dp in params]
     assert 20 <= sum(1 for n in ns if n == 257) <= 44
@@ -278,19 +321,20 @@ def test_fit_workload_64_disks():
     info = b.run(use_graph=True)
     assert all(i["converged"] == 1 for i in info)
     assert all(i["relres_mond"] <= 1e-6 and i["relres_newton"] <= 1e-6 for i in info)
-    # sampled problems: one of each size, against the single-problem context and the oracle's residual
+    # sampled problems, one of each size: bit for bit the single-problem context
+    # with the same refinement counts, and the oracle's FP64 pipeline on the
+    # same particles (same total mass) to the 1e-6-residual bar
     for n in (129, 257):
         p = ns.index(n)
         x, y, zz, m, M = keep[p]
         parts = synth.Particles(x.cpu().numpy(), y.cpu().numpy(), zz.cpu().numpy(), m.cpu().numpy())
-        ref = solo(n, parts, 4, mass=M)   # the same total mass the batch was given
+        ref = solo_steps(n, parts, info[p]["steps_newton"], info[p]["steps_mond"], M)
         got = batch_fields(b, p)
-        if info[p]["steps_newton"] == 4 and info[p]["steps_mond"] == 4:
-            for k in ("f", "phin", "S", "phi"):
-                assert np.array_equal(got[k], ref[k])
-        h = L_BOX / (n - 1)
-        q, inside = O.cic_deposit(n, L_BOX, parts.x, parts.y, parts.z, parts.m, O.fixed_shift(M))
-        f_o = O.rhs_from_q(n, L_BOX, q, O.fixed_shift(M))
-        assert rel(got["f"], f_o) <= 1e-15 and inside == info[p]["n_inside"]
-        r = O.residual(f_o, got["phin"], h)
-        assert np.sqrt((r ** 2).sum() / (f_o[1:-1, 1:-1, 1:-1] ** 2).sum()) <= 1e-6
+        for k in ("f", "phin", "S", "phi"):
+            assert np.array_equal(got[k], ref[k]), (n, k)
+        o = O.run_pipeline(O.OracleConfig(n=n, box_side=[L_BOX], tol_rel=1e-10), parts.x, parts.y, parts.z, parts.m,
+                           M)
+        assert rel(got["f"], o.f[0]) <= 1e-15 and o.n_outside == len(parts.x) - info[p]["n_inside"]
+        assert rel(got["S"], O.mond_source(got["phin"], L_BOX)) <= 1e-12
+        assert rel(got["phin"], o.phin[0]) <= 2e-6, n
+        assert rel(got["phi"], o.phi[0]) <= 2e-6, n
