@@ -481,10 +481,17 @@ def main():
     if args.calibrate_copy:
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
+        ms = []
         for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
             b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"calibration_copy_bytes": a.numel() * 8, "copies": 3}), flush=True)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        t = min(ms)
+        print(json.dumps({"calibration_copy_bytes": a.numel() * 8, "copies": 3, "best_ms": t,
+                          "read_plus_write_GBs": 2 * a.numel() * 8 / (t * 1e-3) / 1e9}), flush=True)
         return
     if args.calibrate_own:
         nc = (N3 + 1) // 2

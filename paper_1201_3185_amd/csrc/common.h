@@ -134,7 +134,8 @@ constexpr int kRrVariants = 7;   // residual restriction: gather, 8x8x4 LDS tile
                                  // 4x4x4 and 4x4x2 LDS tiles
 // bricks hold their whole block in LDS and take no z-chunk
 inline bool is_brick_variant(int v, bool fused) { return fused ? (v >= 2 && v <= 4) : (v == 5 || v == 9 || v == 10); }
-constexpr int kFusedVariants = 5;   // two sweeps: 0: 32x8, 1: 64x4 z-march, 2: 8^3, 3: 4^3, 4: 6^3 bricks
+constexpr int kFusedVariants = 8;   // two sweeps: 0: 32x8, 1: 64x4 z-march, 2: 8^3, 3: 4^3, 4: 6^3 bricks,
+                                    // 5: 64x16, 6: 64x8, 7: 32x16 pair z-march with loads two steps ahead
 // Every grid launcher takes nb, the number of problems stored back to back
 // (problem p of a level with n points per side at offset p n^3); nb = 1 is the
 // single-problem case.

@@ -485,13 +485,21 @@ rbgs_zmarch_pair(const T *__restrict__ uin, T *__restrict__ uout, const T *__res
 // red f values of plane k+4 and the black ones of plane k+2 are requested in
 // step k, so a load has two steps' time to arrive (the pair kernel gives it
 // one).  Two register sets alternate between even and odd steps (the loop is
-// unrolled by two).  Plain sweeps only (no correction on load); the plane
-// pipeline, LDS layout and node updates are the pair kernel's, so the bits
-// are too.
-template <typename T, int TX, int TY>
+// unrolled by two).  The plane pipeline, LDS layout and node updates are the
+// pair kernel's, so the bits are too.
+// With PROLONG the coarse-grid correction u += P uc is added to every plane
+// as it is stored to LDS, from staged data in the order of prolong_at's
+// expression (x first, then y, then z): each coarse plane arrives in an LDS
+// buffer (two alternate), is interpolated along x once for the tile's fine
+// columns and coarse rows into a ring of three x-interpolated planes, and a
+// node's correction then takes four LDS values and three weighted sums.  An
+// odd step k stores coarse plane (k+7)/2, interpolates plane (k+5)/2 along x
+// (first read by the store of fine plane k+4, in step k+1) and requests plane
+// (k+9)/2.
+template <typename T, int TX, int TY, bool PROLONG>
 __global__ void __launch_bounds__(TX *TY / 2)
 rbgs_zmarch_pair_deep(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2,
-                      int kchunk, int nzc)
+                      int kchunk, int nzc, const T *__restrict__ uc, int nc)
 {
 #pragma clang fp contract(off)
     static_assert(TX % 2 == 0, "x-pairs");
@@ -502,7 +510,12 @@ rbgs_zmarch_pair_deep(const T *__restrict__ uin, T *__restrict__ uout, const T *
     constexpr int NRED = HALF * (TY + 2);
     constexpr int RI = (NRED + NT - 1) / NT;
     constexpr int HX = TX / 2;
+    constexpr int CPX = TX / 2 + 3, CPY = TY / 2 + 3, CPL = CPX * CPY;   // coarse footprint of a plane
+    constexpr int XPL = PX * CPY;                                         // x-interpolated plane
+    constexpr int NCL = (CPL + NT - 1) / NT, NXL = (XPL + NT - 1) / NT;
     __shared__ T pl[NS][PL];
+    __shared__ T craw[PROLONG ? 2 : 1][PROLONG ? CPL : 1];
+    __shared__ T xip[PROLONG ? 3 : 1][PROLONG ? XPL : 1];
     const T sixth = T(1) / T(6);
     const int tid = threadIdx.x;
     const unsigned tl = xcd_tile(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
@@ -517,14 +530,71 @@ rbgs_zmarch_pair_deep(const T *__restrict__ uin, T *__restrict__ uout, const T *
     if (uin) uin += (size_t)pb * nn * n;   // a null uin (zero iterate) stays null
     uout += (size_t)pb * nn * n;
     f += (size_t)pb * nn * n;
+    if (PROLONG) uc += (size_t)pb * nc * nc * nc;
 
-    int goff[NL];
+    // coarse footprint: coarse nodes ci0 .. ci0 + CPX - 1 (and likewise in y)
+    // cover the interpolation stencils of fine nodes i0 - 2 .. i0 + TX + 1
+    const int ci0 = (i0 - 3) >> 1, cj0 = (j0 - 3) >> 1;
+    int coff[NCL];
+    T cv[NCL];
+#pragma unroll
+    for (int r = 0; r < NCL; ++r) {
+        const int t = tid + r * NT;
+        const int I = ci0 + t % CPX, J = cj0 + t / CPX;
+        coff[r] = (PROLONG && t < CPL && I >= 0 && I < nc && J >= 0 && J < nc) ? I + nc * J : -1;
+        cv[r] = T(0);
+    }
+    auto fetch_c = [&](int c) {   // coarse plane c into registers
+#pragma unroll
+        for (int r = 0; r < NCL; ++r) cv[r] = coff[r] >= 0 ? uc[(size_t)c * nc * nc + coff[r]] : T(0);
+    };
+    auto store_c = [&](int c) {   // ... into its raw LDS buffer
+        if constexpr (PROLONG) {
+            T *D = craw[c & 1];
+#pragma unroll
+            for (int r = 0; r < NCL; ++r) {
+                const int t = tid + r * NT;
+                if (t < CPL) D[t] = cv[r];
+            }
+        }
+    };
+    auto interp_x = [&](int c) {   // raw coarse plane c -> x-interpolated plane (fine columns, coarse rows)
+        if constexpr (PROLONG) {
+            const T *C = craw[c & 1];
+            T *D = xip[c % 3];
+#pragma unroll
+            for (int r = 0; r < NXL; ++r) {
+                const int t = tid + r * NT;
+                if (t >= XPL) continue;
+                const int a = t % PX, jj = t / PX;
+                const int i = i0 - 2 + a;
+                const int ia = (i >> 1) - ci0, ib = ((i + 1) >> 1) - ci0;
+                const T wia = (i & 1) ? T(0.5) : T(1), wib = (i & 1) ? T(0.5) : T(0);
+                D[t] = wia * C[ia + CPX * jj] + wib * C[ib + CPX * jj];
+            }
+        }
+    };
+    // the correction at fine node (column a of the plane, row j, plane k):
+    // prolong_at's y and z sums over the x-interpolated planes
+    auto corr_at = [&](int a, int j, int k) {
+        const int ja = (j >> 1) - cj0, jb = ((j + 1) >> 1) - cj0;
+        const T *Xa = xip[(k >> 1) % 3];
+        const T *Xb = xip[((k + 1) >> 1) % 3];
+        const T wja = (j & 1) ? T(0.5) : T(1), wjb = (j & 1) ? T(0.5) : T(0);
+        const T wka = (k & 1) ? T(0.5) : T(1), wkb = (k & 1) ? T(0.5) : T(0);
+        const T xa = Xa[a + PX * ja], xb = Xa[a + PX * jb], xc = Xb[a + PX * ja], xd = Xb[a + PX * jb];
+        return wka * (wja * xa + wjb * xb) + wkb * (wja * xc + wjb * xd);
+    };
+
+    int goff[NL], gaj[NL];
 #pragma unroll
     for (int r = 0; r < NL; ++r) {
         const int t = tid + r * NT;
         const int a = t % PX, b = t / PX;
         const int i = i0 - 2 + a, j = j0 - 2 + b;
         goff[r] = (t < PL && i >= 0 && i < n && j >= 0 && j < n) ? i + n * j : -1;
+        // plane column and grid row of a node interior in x and y (it takes the correction), else -1
+        gaj[r] = (goff[r] >= 0 && i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2) ? (a | (j << 16)) : -1;
     }
     int br[RI], jr[RI], qr[RI];
     bool rv[RI];
@@ -549,10 +619,14 @@ rbgs_zmarch_pair_deep(const T *__restrict__ uin, T *__restrict__ uout, const T *
     };
     auto commit = [&](int k, const T *vv) {
         T *P = pl[k % NS];
+        const bool kin = k >= 1 && k <= n - 2;
 #pragma unroll
         for (int r = 0; r < NL; ++r) {
             const int t = tid + r * NT;
-            if (t < PL) P[t] = vv[r];
+            if (t >= PL) continue;
+            T x = vv[r];
+            if (PROLONG && kin && gaj[r] >= 0) x += corr_at(gaj[r] & 0xffff, gaj[r] >> 16, k);
+            P[t] = x;
         }
     };
     auto f_red = [&](int k, T *fr) {
@@ -596,7 +670,9 @@ rbgs_zmarch_pair_deep(const T *__restrict__ uin, T *__restrict__ uout, const T *
     };
 
     // warm-up: planes kb-2..kb+2 (all loads in flight before the first LDS
-    // store, offsets clamped into the grid) and red of kb-1..kb+1
+    // store, offsets clamped into the grid; with PROLONG the correction of
+    // these five planes is prolong_at from global memory) and red of
+    // kb-1..kb+1
     {
         T w[5][NL];
 #pragma unroll
@@ -616,9 +692,30 @@ rbgs_zmarch_pair_deep(const T *__restrict__ uin, T *__restrict__ uout, const T *
 #pragma unroll
             for (int r = 0; r < NL; ++r) {
                 const int t = tid + r * NT;
-                if (t < PL) P[t] = w[q][r];
+                if (t >= PL) continue;
+                T x = w[q][r];
+                if (PROLONG && k >= 1 && k <= n - 2 && gaj[r] >= 0)
+                    x += prolong_at(nc, uc, i0 - 2 + (gaj[r] & 0xffff), gaj[r] >> 16, k);
+                P[t] = x;
             }
         }
+    }
+    if constexpr (PROLONG) {
+        // x-interpolated coarse planes read by the stores of the steps before the
+        // first odd step k1, then the raw plane k1 interpolates and the one it stores
+        const int k1 = kb | 1;
+        for (int c = (kb + 3) >> 1; c <= ((k1 + 4) >> 1) && c <= nc - 1; ++c) {
+            fetch_c(c);
+            store_c(c);
+            __syncthreads();
+            interp_x(c);
+            __syncthreads();
+        }
+        if ((k1 + 5) / 2 <= nc - 1) {
+            fetch_c((k1 + 5) / 2);
+            store_c((k1 + 5) / 2);
+        }
+        if ((k1 + 7) / 2 <= nc - 1) fetch_c((k1 + 7) / 2);
     }
     T fr0[RI], fr1[RI], fr2[RI];
 #pragma unroll
@@ -667,6 +764,11 @@ rbgs_zmarch_pair_deep(const T *__restrict__ uin, T *__restrict__ uout, const T *
         black_store(k, fb);
         __syncthreads();
         if (more) red(k + 2, frc);
+        if (PROLONG && (k & 1)) {
+            if ((k + 7) / 2 <= nc - 1) store_c((k + 7) / 2);   // raw buffer of plane (k+3)/2, interpolated two steps ago
+            if ((k + 5) / 2 <= nc - 1) interp_x((k + 5) / 2);  // into the slot of plane (k-1)/2, last read in step k-3
+            if ((k + 9) / 2 <= nc - 1) fetch_c((k + 9) / 2);
+        }
         __syncthreads();
     };
     for (int k = kb; k <= ke; k += 2) {
@@ -676,24 +778,18 @@ rbgs_zmarch_pair_deep(const T *__restrict__ uin, T *__restrict__ uout, const T *
 }
 
 template <typename T, int TX, int TY>
-static void rbgs_pair_launch(int n, double h, const T *f, const T *uin, T *uout, int kchunk, int nb, const T *uc,
-                             hipStream_t s);
-
-// The deep-prefetch pair sweep; a sweep that also applies the coarse-grid
-// correction runs the pair kernel's correcting form.
-template <typename T, int TX, int TY>
 static void rbgs_pair_deep_launch(int n, double h, const T *f, const T *uin, T *uout, int kchunk, int nb, const T *uc,
                                   hipStream_t s)
 {
-    if (uc) {
-        rbgs_pair_launch<T, TX, TY>(n, h, f, uin, uout, kchunk, nb, uc, s);
-        return;
-    }
     const int m = n - 2;
     const int nzc = (m + kchunk - 1) / kchunk;
     dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, nzc * nb);
-    hipLaunchKernelGGL((rbgs_zmarch_pair_deep<T, TX, TY>), grid, dim3(TX * TY / 2), 0, s, uin, uout, f, n, T(h * h),
-                       kchunk, nzc);
+    if (uc)
+        hipLaunchKernelGGL((rbgs_zmarch_pair_deep<T, TX, TY, true>), grid, dim3(TX * TY / 2), 0, s, uin, uout, f, n,
+                           T(h * h), kchunk, nzc, uc, (n + 1) / 2);
+    else
+        hipLaunchKernelGGL((rbgs_zmarch_pair_deep<T, TX, TY, false>), grid, dim3(TX * TY / 2), 0, s, uin, uout, f, n,
+                           T(h * h), kchunk, nzc, uc, (n + 1) / 2);
 }
 
 template <typename T, int TX, int TY>
@@ -987,6 +1083,176 @@ rbgs2_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
     }
 }
 
+// The two-sweep march with one thread per pair of tile nodes and every load
+// two steps ahead (u plane k+6 and f plane k+5 are requested in step k, two
+// register sets alternating between even and odd steps), for large levels
+// where the fused launch should move u and f once for two sweeps.  Six LDS
+// planes of u (tile + four-node ring: step k reads planes k-1..k+4, and the
+// store of plane k+4 at the start of step k takes the slot of plane k-2) and
+// four of f (planes k..k+3 on the three-node ring).  The four stages, their
+// regions and every node update are those of rbgs2_zmarch, so the bits are
+// too; with PROLONG the correction u += P uc is prolong_at's, added as u is
+// loaded.
+template <typename T, int TX, int TY, bool PROLONG>
+__global__ void __launch_bounds__(TX *TY / 2)
+rbgs2_zmarch_deep(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2, int kchunk,
+                  const T *__restrict__ uc, int nc, int nzc)
+{
+#pragma clang fp contract(off)
+    constexpr int R = 4;
+    constexpr int PX = TX + 2 * R, PY = TY + 2 * R, NT = TX * TY / 2;
+    constexpr int PL = PX * PY;
+    constexpr int FX = TX + 6, FY = TY + 6, FL = FX * FY;
+    constexpr int NS = 6, NF = 4;
+    constexpr int NL = (PL + NT - 1) / NT, NFL = (FL + NT - 1) / NT;
+    __shared__ T pl[NS][PL];
+    __shared__ T fp[NF][FL];
+    const T sixth = T(1) / T(6);
+    const int tid = threadIdx.x;
+    const unsigned tl = xcd_tile(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                 gridDim.x * gridDim.y * gridDim.z);
+    const int bx = tl % gridDim.x, by = (tl / gridDim.x) % gridDim.y, bzz = tl / (gridDim.x * gridDim.y);
+    const int i0 = 1 + bx * TX, j0 = 1 + by * TY;
+    const int pb = bzz / nzc;
+    const int kb = 1 + (bzz - pb * nzc) * kchunk;
+    if (kb > n - 2) return;
+    const int ke = min(kb + kchunk - 1, n - 2);
+    const size_t nn = (size_t)n * n;
+    if (uin) uin += (size_t)pb * nn * n;   // a null uin (zero iterate) stays null
+    uout += (size_t)pb * nn * n;
+    f += (size_t)pb * nn * n;
+    if (PROLONG) uc += (size_t)pb * nc * nc * nc;
+
+    int goff[NL], gij[NL];
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+        const int t = tid + r * NT;
+        const int a = t % PX, b = t / PX;
+        const int i = i0 - R + a, j = j0 - R + b;
+        goff[r] = (t < PL && i >= 0 && i < n && j >= 0 && j < n) ? i + n * j : -1;
+        gij[r] = (goff[r] >= 0 && i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2) ? (i | (j << 16)) : -1;
+    }
+    int foff[NFL];
+#pragma unroll
+    for (int r = 0; r < NFL; ++r) {
+        const int t = tid + r * NT;
+        const int a = t % FX, b = t / FX;
+        const int i = i0 - 3 + a, j = j0 - 3 + b;
+        foff[r] = (t < FL && i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2) ? i + n * j : -1;
+    }
+    auto fetch_u = [&](int k, T *vv) {
+        const T *src = uin ? uin + (size_t)k * nn : nullptr;
+        const bool inner_plane = k >= 1 && k <= n - 2;
+#pragma unroll
+        for (int r = 0; r < NL; ++r) {
+            T x = goff[r] >= 0 ? (src ? src[goff[r]] : T(0)) : T(0);
+            if (PROLONG && inner_plane && gij[r] >= 0) x += prolong_at(nc, uc, gij[r] & 0xffff, gij[r] >> 16, k);
+            vv[r] = x;
+        }
+    };
+    auto commit_u = [&](int k, const T *vv) {
+        T *P = pl[k % NS];
+#pragma unroll
+        for (int r = 0; r < NL; ++r) {
+            const int t = tid + r * NT;
+            if (t < PL) P[t] = vv[r];
+        }
+    };
+    auto fetch_f = [&](int k, T *ww) {
+        const T *src = f + (size_t)k * nn;
+#pragma unroll
+        for (int r = 0; r < NFL; ++r) ww[r] = foff[r] >= 0 ? src[foff[r]] : T(0);
+    };
+    auto commit_f = [&](int k, const T *ww) {
+        T *F = fp[k % NF];
+#pragma unroll
+        for (int r = 0; r < NFL; ++r) {
+            const int t = tid + r * NT;
+            if (t < FL) F[t] = ww[r];
+        }
+    };
+    auto stage = [&](int k, int ring, int colour) {   // one colour of plane k on the tile plus `ring` nodes
+        T *P = pl[k % NS];
+        const T *Pm = pl[(k + NS - 1) % NS];
+        const T *Pp = pl[(k + 1) % NS];
+        const T *F = fp[k % NF];
+        const int hw = (TX + 2 * ring) / 2, rows = TY + 2 * ring, a0 = R - ring;
+        for (int t = tid; t < hw * rows; t += NT) {
+            const int b = a0 + t / hw;
+            const int j = j0 - R + b;
+            const int ia0 = i0 - R + a0;
+            const int a = a0 + (((ia0 + j + k) & 1) == colour ? 0 : 1) + 2 * (t % hw);
+            const int i = i0 - R + a;
+            if (i < 1 || i > n - 2 || j < 1 || j > n - 2) continue;
+            const int c = b * PX + a;
+            const T sum = P[c - 1] + P[c + 1] + P[c - PX] + P[c + PX] + Pm[c] + Pp[c];
+            P[c] = (sum - h2 * F[(b - 1) * FX + (a - 1)]) * sixth;
+        }
+    };
+    auto store = [&](int k) {
+        const T *P = pl[k % NS];
+        for (int t = tid; t < TX * TY; t += NT) {
+            const int a = R + t % TX, b = R + t / TX;
+            const int i = i0 - R + a, j = j0 - R + b;
+            if (i > n - 2 || j > n - 2) continue;
+            uout[(size_t)k * nn + i + (size_t)n * j] = P[b * PX + a];
+        }
+    };
+    auto in_u = [&](int k) { return k >= max(0, kb - 4) && k <= min(n - 1, ke + 4); };
+    auto in_f = [&](int k) { return k >= max(1, kb - 3) && k <= min(n - 2, ke + 3); };
+    auto in_stage = [&](int k, int lag) { return k >= max(1, kb - lag) && k <= min(n - 2, ke + lag); };
+
+    // step k stores u plane k+4 and f plane k+3 and requests u plane k+6 and
+    // f plane k+5; set A serves the steps of kb's parity
+    const int k0 = kb - 8;
+    T uA[NL], uB[NL], fA[NFL], fB[NFL];
+#pragma unroll
+    for (int r = 0; r < NL; ++r) uA[r] = uB[r] = T(0);
+#pragma unroll
+    for (int r = 0; r < NFL; ++r) fA[r] = fB[r] = T(0);
+    if (in_u(k0 + 4)) fetch_u(k0 + 4, uA);
+    if (in_f(k0 + 3)) fetch_f(k0 + 3, fA);
+    if (in_u(k0 + 5)) fetch_u(k0 + 5, uB);
+    if (in_f(k0 + 4)) fetch_f(k0 + 4, fB);
+    auto step = [&](int k, T *uX, T *fX) {
+        if (in_u(k + 4)) commit_u(k + 4, uX);
+        if (in_f(k + 3)) commit_f(k + 3, fX);
+        if (in_u(k + 6)) fetch_u(k + 6, uX);
+        if (in_f(k + 5)) fetch_f(k + 5, fX);
+        __syncthreads();
+        if (in_stage(k + 3, 3)) stage(k + 3, 3, 0);      // red, sweep A
+        __syncthreads();
+        if (in_stage(k + 2, 2)) stage(k + 2, 2, 1);      // black, sweep A
+        __syncthreads();
+        if (in_stage(k + 1, 1)) stage(k + 1, 1, 0);      // red, sweep B
+        __syncthreads();
+        if (k >= kb) {
+            stage(k, 0, 1);                              // black, sweep B
+            __syncthreads();
+            store(k);
+        }
+    };
+    for (int k = k0; k <= ke; k += 2) {
+        step(k, uA, fA);
+        if (k + 1 <= ke) step(k + 1, uB, fB);
+    }
+}
+
+template <typename T, int TX, int TY>
+static void rbgs2_deep_launch(int n, double h, const T *f, const T *uin, T *uout, int kchunk, const T *uc, int nb,
+                              hipStream_t s)
+{
+    const int m = n - 2;
+    const int nzc = (m + kchunk - 1) / kchunk;
+    dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, nzc * nb);
+    if (uc)
+        hipLaunchKernelGGL((rbgs2_zmarch_deep<T, TX, TY, true>), grid, dim3(TX * TY / 2), 0, s, uin, uout, f, n,
+                           T(h * h), kchunk, uc, (n + 1) / 2, nzc);
+    else
+        hipLaunchKernelGGL((rbgs2_zmarch_deep<T, TX, TY, false>), grid, dim3(TX * TY / 2), 0, s, uin, uout, f, n,
+                           T(h * h), kchunk, uc, (n + 1) / 2, nzc);
+}
+
 template <typename T, int TX, int TY>
 static void rbgs2_launch(int n, double h, const T *f, const T *uin, T *uout, int kchunk, const T *uc, int nb,
                          hipStream_t s)
@@ -1012,6 +1278,9 @@ void launch_rbgs2_shape(int n, double h, const T *f, const T *uin, T *uout, cons
     case 2: brick_launch<T, 2>(n, h, f, uin, uout, uc, nb, s); break;
     case 3: brick_launch<T, 2, 4>(n, h, f, uin, uout, uc, nb, s); break;
     case 4: brick_launch<T, 2, 6>(n, h, f, uin, uout, uc, nb, s); break;
+    case 5: rbgs2_deep_launch<T, 64, 16>(n, h, f, uin, uout, kc, uc, nb, s); break;
+    case 6: rbgs2_deep_launch<T, 64, 8>(n, h, f, uin, uout, kc, uc, nb, s); break;
+    case 7: rbgs2_deep_launch<T, 32, 16>(n, h, f, uin, uout, kc, uc, nb, s); break;
     default: rbgs2_launch<T, 64, 4>(n, h, f, uin, uout, kc, uc, nb, s); break;
     }
 }

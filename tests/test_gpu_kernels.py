@@ -350,7 +350,7 @@ def test_stacked_sweeps_are_bitwise_single_problem_sweeps(n):
                 assert np.array_equal(got2[p], ref_u[p]), (v, kc, p)
 
 
-@pytest.mark.parametrize("n", [5, 17, 33, 65, 129])
+@pytest.mark.parametrize("n", [5, 17, 33, 65, 129, 257])
 def test_single_sweep_with_correction_is_bitwise_identical(n):
     """A single sweep that applies the coarse correction on load equals
     prolong-add followed by a sweep, bit for bit, in every shape."""
