@@ -455,6 +455,8 @@ def main():
                     help="launch-shape table to load (default: the committed MI355X table)")
     ap.add_argument("--autotune", action="store_true", help="autotune the launch shapes instead of loading a table")
     ap.add_argument("--save-tune", default=None, help="with --autotune: write the table to this JSON file")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="only the 513^3 legs to 1e-6 (FP64 6- and 2-cycle, mixed; no oracle) and print their record")
     ap.add_argument("--nested-only", action="store_true",
                     help="only the nested 129^3 step (after loading the launch table) and print its record")
     ap.add_argument("--batch-profile", action="store_true",
@@ -517,6 +519,9 @@ def main():
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     x, y, z, m = dev(p.x), dev(p.y), dev(p.z), dev(p.m)
     M = p.total_mass
+    if args.mixed_only:
+        print(json.dumps(to_1e6_513(Q, torch, np, x, y, z, m, M, None)), flush=True)
+        return
 
     orc, cpu = None, None
     model, ncores = host_cpu()
