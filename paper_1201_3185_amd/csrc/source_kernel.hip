@@ -10,9 +10,10 @@
 //
 // Kernel design.  The face fluxes are the work: each needs |g| and
 // sqrt(1 + 4 a0/|g|), formed from the hardware reciprocal square root refined
-// by Newton-Raphson steps (a few ulp, no correctly rounded square root or
-// division), and each face borders two nodes, so the kernel computes each
-// flux once.  A
+// by one Newton-Raphson step (relative error about 4e-15, no correctly
+// rounded square root or division), with the constant factors of g and of the
+// difference folded into one scale applied to S, and each face borders two
+// nodes, so the kernel computes each flux once.  A
 // workgroup owns a TX x TY column tile of interior nodes and marches up a
 // chunk of z planes, holding three planes of Phi_N (k-1, k, k+1; tile plus a
 // one-node ring) in LDS.  On plane k every lane forms the +x, +y and +z face
@@ -32,53 +33,58 @@ namespace qm {
 
 namespace {
 
-// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton-Raphson
-// steps for f(y) = 1/y^2 - x, y <- y + y (1 - x y^2) / 2 (each step squares
-// the relative error, so two steps take any estimate within 1e-4 to a few
-// units in the last place).
+// 1/sqrt(x) for x > 0: the hardware estimate (v_rsq_f64, measured within
+// 5.3e-8 relative on gfx950) refined by one Newton-Raphson step for
+// f(y) = 1/y^2 - x, y <- y + y (1 - x y^2) / 2, which squares the relative
+// error: about 1.5 (5.3e-8)^2 = 4e-15 (the same holds for the Newton step of
+// the square root below).
 __device__ __forceinline__ double rsqrt_nr(double x)
 {
-    double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const double e = fma(-(x * y), y, 1.0);
-        y = fma(0.5 * y, e, y);
-    }
-    return y;
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-(x * y), y, 1.0);
+    return fma(0.5 * y, e, y);
 }
 
+// The flux through one face scaled by 2h (F' = 2 h F), so that
+// S(p) = (ih^2 / 2) sum_d (F'(p + e_d/2) - F'(p - e_d/2)).  With
+// d = Phi_q - Phi_p and t1, t2 the transverse sums
+// (Phi(p+e) - Phi(p-e)) + (Phi(q+e) - Phi(q-e)) along the two other axes,
+// g = ih (d, t1/4, t2/4), so |g| = ih sqrt(A) / 4 with A = 16 d^2 + t1^2 + t2^2
+// and 4 a0 / |g| = c16 / sqrt(A) with c16 = 16 a0 h; then
+// F' = 2 nu g_n / ih = d (1 + sqrt(1 + c16 / sqrt(A))).  A = 0 only where
+// d = t1 = t2 = 0, where the flux is 0 (the limit of nu g): DBL_MIN is added
+// to A, which leaves every A above 2^53 DBL_MIN unchanged after rounding,
+// keeps every step finite at A = 0 and gives 0 * finite there.
+// Contraction off: every inlined copy rounds alike, so a face computed by two
+// workgroups (a tile's ring face) has the same flux in both.
 template <bool FAMILY>
-__device__ __forceinline__ double face_flux(double pp, double pq, double t1, double t2, double ih, double a0,
-                                            double nun)
+__device__ __forceinline__ double face_flux(double pp, double pq, double t1, double t2, double h, double c16,
+                                            double a0, double nun)
 {
-    // pp, pq: Phi_N at the face's two nodes; t1, t2: the transverse sums
-    // Phi(p+e) + Phi(q+e) - Phi(p-e) - Phi(q-e) along the two other axes.
-    // Contraction off: every inlined copy rounds alike, so the two nodes of a
-    // face see the same flux.
 #pragma clang fp contract(off)
-    const double gn = (pq - pp) * ih;
-    const double g1 = t1 * (0.25 * ih);
-    const double g2 = t2 * (0.25 * ih);
-    const double G2 = gn * gn + g1 * g1 + g2 * g2;
-    if (!(G2 > 0.0)) return 0.0;
+    const double d = pq - pp;
+    const double d4 = 4.0 * d;
     if (!FAMILY) {
-        // nu g_n = g_n (1 + sqrt(1 + 4 a0 / |g|)) / 2 with 1/|g| = 1/sqrt(G2)
-        // and sqrt(x) = x / sqrt(x) plus one Newton correction (x >= 1 here)
-        const double x = 1.0 + 4.0 * a0 * rsqrt_nr(G2);
-        const double y = rsqrt_nr(x);
-        double r = x * y;
-        r = fma(0.5 * y, fma(-r, r, x), r);
-        return 0.5 * gn * (1.0 + r);
+        const double A = fma(t2, t2, fma(t1, t1, fma(d4, d4, 2.2250738585072014e-308)));
+        const double x = fma(c16, rsqrt_nr(A), 1.0);   // x >= 1
+        // sqrt(x): r0 = x rsq(x), then one Newton step for r^2 = x,
+        // r <- r0 + (x - r0^2) rsq(x) / 2 (relative error about 4e-15)
+        const double y = __builtin_amdgcn_rsq(x);
+        const double r0 = x * y;
+        const double r = fma(0.5 * y, fma(-r0, r0, x), r0);
+        return fma(d, r, d);
     }
-    return gn * nu_family(sqrt(G2) / a0, nun);
+    const double A = fma(t2, t2, fma(t1, t1, d4 * d4));
+    if (!(A > 0.0)) return 0.0;
+    return 2.0 * d * nu_family(sqrt(A) / (4.0 * h * a0), nun);
 }
 
-constexpr int kSrcTX = 32, kSrcTY = 8;
+constexpr int kSrcTX = 32, kSrcTY = 16;
 static_assert(kSrcTX + kSrcTY <= 64, "the ring faces fit in the first wavefront");
 
 template <int TX, int TY, bool FAMILY>
 __global__ void __launch_bounds__(TX *TY)
-mond_source_zmarch(int n, double ih, double a0, double nun, const double *__restrict__ P, double *__restrict__ S,
+mond_source_zmarch(int n, double h, double a0, double nun, const double *__restrict__ P, double *__restrict__ S,
                    int kchunk, int nzc)
 {
     constexpr int PX = TX + 2, PY = TY + 2, PL = PX * PY, NT = TX * TY;
@@ -96,6 +102,7 @@ mond_source_zmarch(int n, double ih, double a0, double nun, const double *__rest
     if (kb > n - 2) return;
     const int ke = min(kb + kchunk - 1, n - 2);
     const size_t nn = (size_t)n * n;
+    const double ih = 1.0 / h, c16 = 16.0 * a0 * h, sscale = 0.5 * ih * ih;
     P += (size_t)pb * nn * n;
     S += (size_t)pb * nn * n;
 
@@ -128,23 +135,24 @@ mond_source_zmarch(int n, double ih, double a0, double nun, const double *__rest
     const bool own = i <= n - 2 && j <= n - 2;
     const int c = (b + 1) * PX + (a + 1);
     // lanes 0..TY-1: the -x face of tile row tid (between ring column 0 and
-    // tile column 0); lanes TY..TY+TX-1: the -y face of tile column tid-TY;
-    // cr is the face's minus node in the plane
-    const bool ring_x = tid < TY && j0 + tid <= n - 2;
-    const bool ring_y = tid >= TY && tid < TY + TX && i0 + (tid - TY) <= n - 2;
+    // tile column 0); lanes TY..TY+TX-1: the -y face of tile column tid-TY.
+    // cr is the face's minus node in the plane, (rn, rt) its normal and
+    // in-plane transverse strides, rdst where its flux goes; both kinds take
+    // one pass of the same code.
+    const bool ring = (tid < TY && j0 + tid <= n - 2) || (tid >= TY && tid < TY + TX && i0 + (tid - TY) <= n - 2);
     const int cr = tid < TY ? (tid + 1) * PX : (tid - TY + 1);
+    const int rn = tid < TY ? 1 : PX, rt = tid < TY ? PX : 1;
+    double *rdst = tid < TY ? &fx[tid][0] : &fy[0][min(max(tid - TY, 0), TX - 1)];
 
-    auto flux_x = [&](const double *M, const double *Z, const double *Q, int q) {   // face q -> q + 1
-        return face_flux<FAMILY>(Z[q], Z[q + 1], Z[q + PX] + Z[q + 1 + PX] - Z[q - PX] - Z[q + 1 - PX],
-                         Q[q] + Q[q + 1] - M[q] - M[q + 1], ih, a0, nun);
-    };
-    auto flux_y = [&](const double *M, const double *Z, const double *Q, int q) {   // face q -> q + PX
-        return face_flux<FAMILY>(Z[q], Z[q + PX], Z[q + 1] + Z[q + PX + 1] - Z[q - 1] - Z[q + PX - 1],
-                         Q[q] + Q[q + PX] - M[q] - M[q + PX], ih, a0, nun);
-    };
-    auto flux_z = [&](const double *Z, const double *Q, int q) {   // face plane Z -> plane Q
-        return face_flux<FAMILY>(Z[q], Q[q], Z[q + 1] + Q[q + 1] - Z[q - 1] - Q[q - 1],
-                         Z[q + PX] + Q[q + PX] - Z[q - PX] - Q[q - PX], ih, a0, nun);
+    // The transverse sums are sums of central differences at the face's two
+    // nodes, each a difference of two plane values; a lane forms those of its
+    // node once per plane and carries the x and y differences of plane k+1
+    // to the next plane.  The ring faces form the same differences in the
+    // same order, so they round alike.
+    // flux through the face q -> q + sn of plane Z, st the other in-plane stride
+    auto flux_xy = [&](const double *M, const double *Z, const double *Q, int q, int sn, int st) {
+        return face_flux<FAMILY>(Z[q], Z[q + sn], (Z[q + st] - Z[q - st]) + (Z[q + sn + st] - Z[q + sn - st]),
+                                 (Q[q] - M[q]) + (Q[q + sn] - M[q + sn]), h, c16, a0, nun);
     };
 
     // warm-up: planes kb-1, kb, kb+1 (all loads in flight before the first
@@ -168,25 +176,41 @@ mond_source_zmarch(int n, double ih, double a0, double nun, const double *__rest
         }
     }
     __syncthreads();
-    double fz_lo = own ? flux_z(pl[(kb - 1) % 3], pl[kb % 3], c) : 0.0;
+    // x and y central differences of this lane's node on plane kb, and the
+    // -z flux of plane kb (the face from plane kb-1)
+    double cx = 0.0, cy = 0.0, fz_lo = 0.0;
+    if (own) {
+        const double *M = pl[(kb - 1) % 3], *Z = pl[kb % 3];
+        cx = Z[c + 1] - Z[c - 1];
+        cy = Z[c + PX] - Z[c - PX];
+        fz_lo = face_flux<FAMILY>(M[c], Z[c], (M[c + 1] - M[c - 1]) + cx, (M[c + PX] - M[c - PX]) + cy, h, c16,
+                                  a0, nun);
+    }
     if (kb + 2 <= ke + 1) fetch(kb + 2);
 
     for (int k = kb; k <= ke; ++k) {
         const double *M = pl[(k - 1) % 3], *Z = pl[k % 3], *Q = pl[(k + 1) % 3];
-        double fz_hi = 0.0;
+        double fx_hi = 0.0, fy_hi = 0.0, fz_hi = 0.0;
         if (own) {
-            fx[b][a + 1] = flux_x(M, Z, Q, c);
-            fy[b + 1][a] = flux_y(M, Z, Q, c);
-            fz_hi = flux_z(Z, Q, c);
+            const double cz = Q[c] - M[c];
+            fx_hi = face_flux<FAMILY>(Z[c], Z[c + 1], cy + (Z[c + 1 + PX] - Z[c + 1 - PX]),
+                                      cz + (Q[c + 1] - M[c + 1]), h, c16, a0, nun);
+            fy_hi = face_flux<FAMILY>(Z[c], Z[c + PX], cx + (Z[c + PX + 1] - Z[c + PX - 1]),
+                                      cz + (Q[c + PX] - M[c + PX]), h, c16, a0, nun);
+            const double qx = Q[c + 1] - Q[c - 1], qy = Q[c + PX] - Q[c - PX];
+            fz_hi = face_flux<FAMILY>(Z[c], Q[c], cx + qx, cy + qy, h, c16, a0, nun);
+            cx = qx;
+            cy = qy;
+            fx[b][a + 1] = fx_hi;
+            fy[b + 1][a] = fy_hi;
         }
-        if (ring_x) fx[tid][0] = flux_x(M, Z, Q, cr);
-        if (ring_y) fy[0][tid - TY] = flux_y(M, Z, Q, cr);
+        if (ring) *rdst = flux_xy(M, Z, Q, cr, rn, rt);
         __syncthreads();
         if (own) {
-            double s = fx[b][a + 1] - fx[b][a];
-            s += fy[b + 1][a] - fy[b][a];
+            double s = fx_hi - fx[b][a];
+            s += fy_hi - fy[b][a];
             s += fz_hi - fz_lo;
-            S[(size_t)k * nn + i + (size_t)n * j] = s * ih;
+            S[(size_t)k * nn + i + (size_t)n * j] = s * sscale;
         }
         fz_lo = fz_hi;
         if (k + 2 <= ke + 1) {   // plane k+2 replaces plane k-1, whose readers are past the barrier
@@ -222,10 +246,10 @@ void launch_mond_source(int n, double h, double a0, const double *phin, double *
     const int nzc = (m + kchunk - 1) / kchunk;
     dim3 grid((m + kSrcTX - 1) / kSrcTX, (m + kSrcTY - 1) / kSrcTY, nzc * nb);
     if (nun == 1.0)
-        hipLaunchKernelGGL((mond_source_zmarch<kSrcTX, kSrcTY, false>), grid, dim3(kSrcTX * kSrcTY), 0, s, n, 1.0 / h,
+        hipLaunchKernelGGL((mond_source_zmarch<kSrcTX, kSrcTY, false>), grid, dim3(kSrcTX * kSrcTY), 0, s, n, h,
                            a0, nun, phin, S, kchunk, nzc);
     else
-        hipLaunchKernelGGL((mond_source_zmarch<kSrcTX, kSrcTY, true>), grid, dim3(kSrcTX * kSrcTY), 0, s, n, 1.0 / h,
+        hipLaunchKernelGGL((mond_source_zmarch<kSrcTX, kSrcTY, true>), grid, dim3(kSrcTX * kSrcTY), 0, s, n, h,
                            a0, nun, phin, S, kchunk, nzc);
     hipLaunchKernelGGL(zero_faces_k, dim3((6 * n * n + 255) / 256, nb), dim3(256), 0, s, n, S);
 }
