@@ -461,6 +461,9 @@ def main():
                     help="only the nested 129^3 step (after loading the launch table) and print its record")
     ap.add_argument("--batch-profile", action="store_true",
                     help="run only the batched-fit leg (for a kernel trace of its replays) and print its record")
+    ap.add_argument("--learned-profile", action="store_true",
+                    help="run only the learned-guess leg on 4 held-out disks without the oracle (for a kernel "
+                         "trace of the U-Net inference) and print its record")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device three times (a known-size copy that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -507,6 +510,10 @@ def main():
         return
     if args.batch_profile:
         print(json.dumps(batched_fit(Q, synth, torch, np, reps=2)), flush=True)
+        return
+    if args.learned_profile:
+        load_shapes(Q, args, 129)
+        print(json.dumps(learned_leg(Q, torch, np, count=4, oracle_threads=0)), flush=True)
         return
     if args.nested_only:
         load_shapes(Q, args, 129)

@@ -2327,6 +2327,148 @@ resid_norms_partial_k(int n, double ih2, const T *__restrict__ f, const T *__res
     }
 }
 
+// The same partial sums from a z-march: a workgroup owns a 64 x 4 column tile
+// of interior nodes and a chunk of z planes, holds three planes of u (tile
+// plus a one-node ring) in LDS and loads each plane once, with the next plane
+// and the next f values in flight while a plane is summed, so u and f are
+// read from HBM about once (the row form reads the +-z neighbour rows again,
+// from other workgroups at other times).  Each lane sums its own column; the
+// order depends only on n and the launch shape, which the launcher fixes from
+// n, so the sums are reproducible bit for bit.  Same residual expression, same
+// FP32 residual with R32.
+constexpr int kNzTX = 64, kNzTY = 4;
+
+template <typename T, bool R32>
+__global__ void __launch_bounds__(kNzTX *kNzTY)
+resid_norms_zmarch_k(int n, double ih2, const T *__restrict__ f, const T *__restrict__ u,
+                     double *__restrict__ partial, const double *__restrict__ sc, float *__restrict__ r32, int kchunk,
+                     int gx, int gy)
+{
+    constexpr int TX = kNzTX, TY = kNzTY, PX = TX + 2, PY = TY + 2, PL = PX * PY, NT = TX * TY;
+    constexpr int NL = (PL + NT - 1) / NT;
+    __shared__ double pl[3][PL];
+    __shared__ double sh[3 * NT];
+    const size_t nn = (size_t)n * n;
+    f += blockIdx.y * nn * n;
+    u += blockIdx.y * nn * n;
+    partial += blockIdx.y * 3 * (size_t)gridDim.x;
+    double inv_s = 0.0;
+    if (R32) {
+        r32 += blockIdx.y * nn * n;
+        inv_s = sc[2 * blockIdx.y + 1];
+    }
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x, bx = b % gx, by = (b / gx) % gy, bz = b / (gx * gy);
+    const int i0 = 1 + bx * TX, j0 = 1 + by * TY;
+    const int kb = 1 + bz * kchunk, ke = min(kb + kchunk - 1, n - 2);
+    int goff[NL];
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+        const int t = tid + r * NT;
+        const int i = i0 - 1 + t % PX, j = j0 - 1 + t / PX;
+        goff[r] = (t < PL && i < n && j < n) ? i + n * j : -1;
+    }
+    double v[NL];
+    auto fetch = [&](int k) {
+        const T *src = u + (size_t)k * nn;
+#pragma unroll
+        for (int r = 0; r < NL; ++r) v[r] = goff[r] >= 0 ? (double)src[goff[r]] : 0.0;
+    };
+    auto commit = [&](int k) {
+        double *D = pl[k % 3];
+#pragma unroll
+        for (int r = 0; r < NL; ++r) {
+            const int t = tid + r * NT;
+            if (t < PL) D[t] = v[r];
+        }
+    };
+    const int a = tid % TX, bq = tid / TX;
+    const int i = i0 + a, j = j0 + bq;
+    const bool own = i <= n - 2 && j <= n - 2 && kb <= ke;
+    const int c = (bq + 1) * PX + (a + 1);
+    const size_t col = (size_t)i + (size_t)n * j;
+    const bool ij_edge = i == 1 || j == 1 || i == n - 2 || j == n - 2;
+    double sr = 0.0, sf = 0.0, sb = 0.0;
+    if (kb <= ke) {
+        {   // planes kb-1, kb, kb+1: all loads in flight before the first store
+            double w[3][NL];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const T *src = u + (size_t)(kb - 1 + q) * nn;
+#pragma unroll
+                for (int r = 0; r < NL; ++r) w[q][r] = goff[r] >= 0 ? (double)src[goff[r]] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                double *D = pl[(kb - 1 + q) % 3];
+#pragma unroll
+                for (int r = 0; r < NL; ++r) {
+                    const int t = tid + r * NT;
+                    if (t < PL) D[t] = w[q][r];
+                }
+            }
+        }
+        if (kb + 2 <= ke + 1) fetch(kb + 2);
+        double fv = own ? (double)f[(size_t)kb * nn + col] : 0.0;
+        __syncthreads();
+        for (int k = kb; k <= ke; ++k) {
+            const double fn = (own && k + 1 <= ke) ? (double)f[(size_t)(k + 1) * nn + col] : 0.0;
+            if (own) {
+                const double *M = pl[(k - 1) % 3], *Z = pl[k % 3], *Q = pl[(k + 1) % 3];
+                const double um = Z[c - 1], up = Z[c + 1], vm = Z[c - PX], vp = Z[c + PX], wm = M[c], wp = Q[c];
+                const double lap = (um + up + vm + vp + wm + wp - 6.0 * Z[c]) * ih2;
+                const double res = fv - lap;
+                if (R32) r32[(size_t)k * nn + col] = (float)(res * inv_s);
+                sr += res * res;
+                sf += fv * fv;
+                if (ij_edge || k == 1 || k == n - 2) {
+                    const double bv = ((i == 1 ? um : 0.0) + (i == n - 2 ? up : 0.0) + (j == 1 ? vm : 0.0) +
+                                       (j == n - 2 ? vp : 0.0) + (k == 1 ? wm : 0.0) + (k == n - 2 ? wp : 0.0)) * ih2;
+                    sb += bv * bv;
+                }
+            }
+            fv = fn;
+            __syncthreads();
+            if (k + 2 <= ke + 1) {   // plane k+2 replaces plane k-1, whose readers are past the barrier
+                commit(k + 2);
+                if (k + 3 <= ke + 1) fetch(k + 3);
+            }
+            __syncthreads();
+        }
+    }
+    block_sum3<NT>(sh, sr, sf, sb);
+    if (threadIdx.x == 0) {
+        partial[3 * blockIdx.x] = sr;
+        partial[3 * blockIdx.x + 1] = sf;
+        partial[3 * blockIdx.x + 2] = sb;
+    }
+}
+
+// Launch shape of the z-march norms for n: tiles of 64 x 4 columns and the
+// z-chunk that keeps the block count at most kNormBlocks (and the chunks at
+// least 8 planes); 0 blocks when the tiles alone exceed kNormBlocks (the row
+// form serves then).
+struct NormsShape {
+    int gx, gy, kchunk, nzc, blocks;
+};
+static NormsShape norms_shape(int n)
+{
+    NormsShape sh;
+    const int m = n - 2;
+    sh.gx = (m + kNzTX - 1) / kNzTX;
+    sh.gy = (m + kNzTY - 1) / kNzTY;
+    const int tiles = sh.gx * sh.gy;
+    if (tiles > kNormBlocks) {
+        sh.kchunk = sh.nzc = sh.blocks = 0;
+        return sh;
+    }
+    const int q = kNormBlocks / tiles;
+    sh.kchunk = std::max(8, (m + q - 1) / q);
+    sh.nzc = (m + sh.kchunk - 1) / sh.kchunk;
+    sh.blocks = tiles * sh.nzc;
+    return sh;
+}
+
 // hout (optional): the same three sums per problem, written straight into
 // pinned host memory (its device-mapped address), so no copy launch follows.
 __global__ void __launch_bounds__(256) norms_final_k(const double *__restrict__ partial, int nb, double *__restrict__ out,
@@ -2360,6 +2502,13 @@ template <typename T>
 void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial, double *out, hipStream_t s, int nb,
                         double *hout)
 {
+    const NormsShape zs = norms_shape(n);
+    if (zs.blocks > 0) {
+        hipLaunchKernelGGL((resid_norms_zmarch_k<T, false>), dim3(zs.blocks, nb), dim3(kNzTX * kNzTY), 0, s, n,
+                           1.0 / (h * h), f, u, partial, nullptr, nullptr, zs.kchunk, zs.gx, zs.gy);
+        hipLaunchKernelGGL(norms_final_k, dim3(nb), dim3(256), 0, s, partial, zs.blocks, out, hout);
+        return;
+    }
     // about 8 four-row groups per workgroup, at most kNormBlocks workgroups per problem
     const long long rows = (long long)(n - 2) * (n - 2);
     const int blocks = (int)std::min<long long>(kNormBlocks, std::max<long long>(1, (rows + 31) / 32));
@@ -2371,6 +2520,13 @@ void launch_resid_norms(int n, double h, const T *f, const T *u, double *partial
 void launch_resid_norms_r32(int n, double h, const double *f, const double *u, double *partial, double *out,
                             const double *sc, float *r32, hipStream_t s, int nb, double *hout)
 {
+    const NormsShape zs = norms_shape(n);
+    if (zs.blocks > 0) {
+        hipLaunchKernelGGL((resid_norms_zmarch_k<double, true>), dim3(zs.blocks, nb), dim3(kNzTX * kNzTY), 0, s, n,
+                           1.0 / (h * h), f, u, partial, sc, r32, zs.kchunk, zs.gx, zs.gy);
+        hipLaunchKernelGGL(norms_final_k, dim3(nb), dim3(256), 0, s, partial, zs.blocks, out, hout);
+        return;
+    }
     const long long rows = (long long)(n - 2) * (n - 2);
     const int blocks = (int)std::min<long long>(kNormBlocks, std::max<long long>(1, (rows + 31) / 32));
     hipLaunchKernelGGL((resid_norms_partial_k<double, true>), dim3(blocks, nb), dim3(256), 0, s, n, 1.0 / (h * h), f,
