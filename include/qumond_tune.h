@@ -35,6 +35,16 @@ extern "C" {
 qumond_status qumond_tune_set(int32_t n, int32_t fp32, int32_t variant, int32_t kchunk);
 qumond_status qumond_tune_get(int32_t n, int32_t fp32, int32_t *variant, int32_t *kchunk);
 
+/* Shape of the single sweep that also applies the coarse-grid correction
+ * (the first post-smoothing sweep of a level when the correction is folded
+ * into it), from the same variants and chunks as qumond_tune_set; variant -1
+ * (the default) takes the level's plain-sweep shape.  The autotuner times
+ * every shape with the correction applied; results are identical in every
+ * shape.  Errors: n not 2^J + 1 in 5..1025, variant outside -1..15 or
+ * kchunk < 0 -> QUMOND_ERR_INVALID. */
+qumond_status qumond_tune_set_corr(int32_t n, int32_t fp32, int32_t variant, int32_t kchunk);
+qumond_status qumond_tune_get_corr(int32_t n, int32_t fp32, int32_t *variant, int32_t *kchunk);
+
 /* The same for the fused two-sweep smoother (variant 0 = 32x8, 1 = 64x4
  * z-march, 2 = 8^3, 3 = 4^3, 4 = 6^3 bricks, 5 = 64x16, 6 = 64x8, 7 = 32x16
  * z-march with one thread per pair of tile nodes and loads two steps

@@ -148,6 +148,10 @@ template <typename T> void launch_rbgs(int n, double h, const T *f, const T *uin
 template <typename T> void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, SmootherShape sh,
                                             hipStream_t s, int nb = 1, const T *uc = nullptr);
 template <typename T> SmootherShape &rbgs_shape(int n);   // the table entry used for n
+// Shape of a single sweep that also applies the coarse-grid correction; a
+// variant below 0 (the default) means the level's plain-sweep shape.
+template <typename T> SmootherShape &rbgs_corr_shape(int n);
+template <typename T> SmootherShape rbgs_corr_effective(int n);
 // Two sweeps in one launch (variants 0: 32x8, 1: 64x4 z-march, 2: 8^3 bricks);
 // with uc != NULL the correction u += P uc (uc on the next coarser level) is
 // applied first.

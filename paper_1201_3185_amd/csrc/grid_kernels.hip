@@ -1368,6 +1368,27 @@ SmootherShape &rbgs_shape(int n)
     return g_rbgs_shape[sizeof(T) == 4 ? 1 : 0][J > 10 ? 10 : J];
 }
 
+// The correcting sweep's own shape per level and precision (the autotuner
+// times it with the correction applied; -1: as the plain sweep).
+static SmootherShape g_rbgs_corr_shape[2][11] = {
+    {{-1, 0}, {-1, 0}, {-1, 0}, {-1, 0}, {-1, 0}, {-1, 0}, {-1, 0}, {-1, 0}, {-1, 0}, {-1, 0}, {-1, 0}},
+    {{-1, 0}, {-1, 0}, {-1, 0}, {-1, 0}, {-1, 0}, {-1, 0}, {-1, 0}, {-1, 0}, {-1, 0}, {-1, 0}, {-1, 0}}};
+
+template <typename T>
+SmootherShape &rbgs_corr_shape(int n)
+{
+    int J = 0;
+    while ((1 << J) < n - 1) ++J;
+    return g_rbgs_corr_shape[sizeof(T) == 4 ? 1 : 0][J > 10 ? 10 : J];
+}
+
+template <typename T>
+SmootherShape rbgs_corr_effective(int n)
+{
+    const SmootherShape c = rbgs_corr_shape<T>(n);
+    return c.variant >= 0 ? c : rbgs_shape<T>(n);
+}
+
 template <typename T>
 void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, SmootherShape sh, hipStream_t s, int nb,
                        const T *uc)
@@ -1396,7 +1417,7 @@ void launch_rbgs_shape(int n, double h, const T *f, const T *uin, T *uout, Smoot
 template <typename T>
 void launch_rbgs(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s, int nb, const T *uc)
 {
-    launch_rbgs_shape<T>(n, h, f, uin, uout, rbgs_shape<T>(n), s, nb, uc);
+    launch_rbgs_shape<T>(n, h, f, uin, uout, uc ? rbgs_corr_effective<T>(n) : rbgs_shape<T>(n), s, nb, uc);
 }
 
 // ------------------------------------------------- residual and restriction
@@ -2701,6 +2722,8 @@ void launch_guess_interior(int n, const void *g, int kind, double *u, hipStream_
 // -------------------------------------------------------- instantiations
 #define QM_INST(T)                                                                                              \
     template void launch_rbgs<T>(int, double, const T *, const T *, T *, hipStream_t, int, const T *);         \
+    template SmootherShape &rbgs_corr_shape<T>(int);                                                            \
+    template SmootherShape rbgs_corr_effective<T>(int);                                                         \
     template void launch_rbgs_shape<T>(int, double, const T *, const T *, T *, SmootherShape, hipStream_t, int,  \
                                        const T *);                                                              \
     template SmootherShape &rbgs_shape<T>(int);                                                                 \

@@ -79,6 +79,7 @@ struct SmootherProfile {
 // place of the library-wide tables when set.
 struct LevelShapes {
     SmootherShape single[11];
+    SmootherShape corr[11];   // single sweep with the correction applied (variant < 0: as single)
     SmootherShape fused[11];
     int use_fused[11];
     int rr[11];   // residual-restriction kernel of fine level l
@@ -201,6 +202,15 @@ struct Multigrid {
         if (prof.on && e1) (void)hipEventRecord(e1, s);
     }
 
+    // The single-sweep shape of level l, with or without the correction.
+    SmootherShape corr_shape(int l, bool with_corr) const
+    {
+        const int n = lv[l].n;
+        if (!with_corr) return shapes ? shapes->single[l] : rbgs_shape<T>(n);
+        if (shapes) return shapes->corr[l].variant >= 0 ? shapes->corr[l] : shapes->single[l];
+        return rbgs_corr_effective<T>(n);
+    }
+
     // ns red-black sweeps on level l; pairs of sweeps run as one fused launch.
     // With uc != NULL the correction u += P uc is applied before the first
     // sweep: inside its launch, or by a prolong-add launch of its own where
@@ -229,7 +239,7 @@ struct Multigrid {
                 launch_rbgs2_shape<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], uc, sh, s, nb);
                 ns -= 2;
             } else {
-                const SmootherShape sh = shapes ? shapes->single[l] : rbgs_shape<T>(v.n);
+                const SmootherShape sh = corr_shape(l, uc != nullptr);
                 launch_rbgs_shape<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], sh, s, nb, uc);
                 ns -= 1;
             }
@@ -341,11 +351,12 @@ struct Multigrid {
         for (int l = lt; l <= J; ++l) {
             const int n = lv[l].n;
             const SmootherShape a = shapes ? shapes->single[l] : rbgs_shape<T>(n);
+            const SmootherShape c = corr_shape(l, true);
             const SmootherShape b = shapes ? shapes->fused[l] : rbgs2_shape<T>(n);
             const int uf = shapes ? shapes->use_fused[l] : use_fused<T>(n);
             const int rr = shapes ? shapes->rr[l] : rr_variant<T>(n);
             const int sp = shapes ? shapes->split[l] : split_prolong<T>(n);
-            v.insert(v.end(), {a.variant, a.kchunk, b.variant, b.kchunk, uf, rr, sp});
+            v.insert(v.end(), {a.variant, a.kchunk, c.variant, c.kchunk, b.variant, b.kchunk, uf, rr, sp});
         }
         v.insert(v.end(), {fused ? 1 : 0, npre, npost});
         return v;

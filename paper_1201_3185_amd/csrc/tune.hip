@@ -23,26 +23,34 @@ bool good_n(int n) { return n >= 5 && n <= 1025 && qm::log2_exact(n - 1) >= 2; }
 
 const int kChunks[] = {2, 4, 8, 16, 32, 64, 128, 256, 0};
 
+// Time every single-sweep shape (fused: every two-sweep shape; corr: every
+// single-sweep shape applying a coarse-grid correction) on a level of n
+// points and install the fastest.
 template <typename T>
-qumond_status tune_one(int n, int reps, hipStream_t s, double &best_us, bool fused)
+qumond_status tune_one(int n, int reps, hipStream_t s, double &best_us, bool fused, bool corr = false)
 {
     const size_t N = (size_t)n * n * n;
-    T *f = nullptr, *u0 = nullptr, *u1 = nullptr;
+    const int nc = (n + 1) / 2;
+    const size_t Nc = (size_t)nc * nc * nc;
+    T *f = nullptr, *u0 = nullptr, *u1 = nullptr, *uc = nullptr;
     if (hipMalloc((void **)&f, N * sizeof(T)) != hipSuccess || hipMalloc((void **)&u0, N * sizeof(T)) != hipSuccess ||
-        hipMalloc((void **)&u1, N * sizeof(T)) != hipSuccess) {
+        hipMalloc((void **)&u1, N * sizeof(T)) != hipSuccess ||
+        (corr && hipMalloc((void **)&uc, Nc * sizeof(T)) != hipSuccess)) {
         (void)hipFree(f);
         (void)hipFree(u0);
+        (void)hipFree(u1);
         qm_set_last_error("qumond_autotune: allocation failed");
         return QUMOND_ERR_OOM;
     }
     qm::launch_fill<T>(f, N, T(1), s);
     qm::launch_fill<T>(u0, N, T(0.5), s);
     qm::launch_fill<T>(u1, N, T(0.5), s);
+    if (corr) qm::launch_fill<T>(uc, Nc, T(0.001), s);
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
-    qm::SmootherShape &slot = fused ? qm::rbgs2_shape<T>(n) : qm::rbgs_shape<T>(n);
-    qm::SmootherShape best = slot;
+    qm::SmootherShape &slot = fused ? qm::rbgs2_shape<T>(n) : (corr ? qm::rbgs_corr_shape<T>(n) : qm::rbgs_shape<T>(n));
+    qm::SmootherShape best = corr ? qm::rbgs_corr_effective<T>(n) : slot;
     best_us = 1e30;
     const double h = 1.0 / (n - 1);
     auto run = [&](const T *a, T *b, const qm::SmootherShape &sh) {
@@ -50,7 +58,7 @@ qumond_status tune_one(int n, int reps, hipStream_t s, double &best_us, bool fus
             slot = sh;
             qm::launch_rbgs2<T>(n, h, f, a, b, nullptr, s);
         } else {
-            qm::launch_rbgs_shape<T>(n, h, f, a, b, sh, s);
+            qm::launch_rbgs_shape<T>(n, h, f, a, b, sh, s, 1, uc);
         }
     };
     const int nvar = fused ? qm::kFusedVariants : qm::kSmootherVariants;
@@ -84,6 +92,7 @@ qumond_status tune_one(int n, int reps, hipStream_t s, double &best_us, bool fus
     (void)hipFree(f);
     (void)hipFree(u0);
     (void)hipFree(u1);
+    if (uc) (void)hipFree(uc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         qm_set_last_error(hipGetErrorString(e));
@@ -242,6 +251,25 @@ qumond_status qumond_tune_get(int32_t n, int32_t fp32, int32_t *variant, int32_t
     return QUMOND_OK;
 }
 
+qumond_status qumond_tune_set_corr(int32_t n, int32_t fp32, int32_t variant, int32_t kchunk)
+{
+    if (!good_n(n) || variant < -1 || variant >= qm::kSmootherVariants || kchunk < 0)
+        return tfail("qumond_tune_set_corr: bad argument");
+    const qm::SmootherShape sh{variant, variant < 0 ? 0 : kchunk};
+    if (fp32) qm::rbgs_corr_shape<float>(n) = sh;
+    else qm::rbgs_corr_shape<double>(n) = sh;
+    return QUMOND_OK;
+}
+
+qumond_status qumond_tune_get_corr(int32_t n, int32_t fp32, int32_t *variant, int32_t *kchunk)
+{
+    if (!good_n(n) || !variant || !kchunk) return tfail("qumond_tune_get_corr: bad argument");
+    const qm::SmootherShape sh = fp32 ? qm::rbgs_corr_shape<float>(n) : qm::rbgs_corr_shape<double>(n);
+    *variant = sh.variant;
+    *kchunk = sh.kchunk;
+    return QUMOND_OK;
+}
+
 qumond_status qumond_tune_set_fused(int32_t n, int32_t fp32, int32_t variant, int32_t kchunk)
 {
     if (!good_n(n) || variant < 0 || variant >= qm::kFusedVariants || kchunk < 0)
@@ -349,6 +377,18 @@ qumond_status qumond_autotune(int32_t n_max, int32_t both, int32_t reps, const c
                 first = false;
                 us_pair[fz] = us;
             }
+            {   // the single sweep that applies the coarse-grid correction
+                double us = 0.0;
+                qumond_status st = prec ? tune_one<float>(n, reps, s, us, false, true)
+                                        : tune_one<double>(n, reps, s, us, false, true);
+                if (st != QUMOND_OK) return st;
+                const qm::SmootherShape sh = prec ? qm::rbgs_corr_shape<float>(n) : qm::rbgs_corr_shape<double>(n);
+                char buf[200];
+                std::snprintf(buf, sizeof buf,
+                              ", {\"n\": %d, \"fp32\": %d, \"corr_variant\": %d, \"corr_kchunk\": %d, \"us\": %.3f}", n,
+                              prec, sh.variant, sh.kchunk, us);
+                js += buf;
+            }
             // fused launch (two sweeps) against two single sweeps
             const int fuse = us_pair[1] < 2.0 * us_pair[0] ? 1 : 0;
             if (prec) qm::use_fused<float>(n) = fuse;
@@ -400,6 +440,16 @@ qumond_status qumond_tune_load(const char *json_path)
             const qumond_status st = fz ? qumond_tune_set_fused(n, fp32, variant, kchunk)
                                         : qumond_tune_set(n, fp32, variant, kchunk);
             if (st != QUMOND_OK) return QUMOND_ERR_INVALID;
+            ++loaded;
+        }
+        ++pos;
+    }
+    pos = 0;
+    while ((pos = txt.find("{\"n\":", pos)) != std::string::npos) {
+        int n = 0, fp32 = 0, variant = 0, kchunk = 0;
+        if (std::sscanf(txt.c_str() + pos, "{\"n\": %d, \"fp32\": %d, \"corr_variant\": %d, \"corr_kchunk\": %d", &n,
+                        &fp32, &variant, &kchunk) == 4) {
+            if (qumond_tune_set_corr(n, fp32, variant, kchunk) != QUMOND_OK) return QUMOND_ERR_INVALID;
             ++loaded;
         }
         ++pos;

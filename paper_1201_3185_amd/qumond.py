@@ -125,6 +125,8 @@ _SIGNATURES = {
     "qumond_k_conv3d_wgrad": (_I32, [_I32, _I32, _P, _I32, _P, _I32, _P, _P]),
     "qumond_tune_set": (_I32, [_I32, _I32, _I32, _I32]),
     "qumond_tune_get": (_I32, [_I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "qumond_tune_set_corr": (_I32, [_I32, _I32, _I32, _I32]),
+    "qumond_tune_get_corr": (_I32, [_I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "qumond_tune_set_fused": (_I32, [_I32, _I32, _I32, _I32]),
     "qumond_tune_get_fused": (_I32, [_I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "qumond_k_rbgs_sweep_shape": (_I32, [_I32, _D, _P, _P, _P, _I32, _I32, _P, _P]),
@@ -486,6 +488,18 @@ def tune_set(n, variant, kchunk, fp32=False):
 def tune_get(n, fp32=False):
     v, k = ctypes.c_int32(0), ctypes.c_int32(0)
     check(lib().qumond_tune_get(int(n), int(bool(fp32)), ctypes.byref(v), ctypes.byref(k)), "qumond_tune_get")
+    return int(v.value), int(k.value)
+
+
+def tune_set_corr(n, variant, kchunk, fp32=False):
+    """Shape of the single sweep that applies the coarse-grid correction
+    (variant -1: the level's plain-sweep shape)."""
+    check(lib().qumond_tune_set_corr(int(n), int(bool(fp32)), int(variant), int(kchunk)), "qumond_tune_set_corr")
+
+
+def tune_get_corr(n, fp32=False):
+    v, k = ctypes.c_int32(0), ctypes.c_int32(0)
+    check(lib().qumond_tune_get_corr(int(n), int(bool(fp32)), ctypes.byref(v), ctypes.byref(k)), "qumond_tune_get_corr")
     return int(v.value), int(k.value)
 
 

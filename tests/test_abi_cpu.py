@@ -151,8 +151,10 @@ def test_batch_null_handles(Q):
 def test_tune_tables_keep_entries_of_both_precisions():
     """Setting a launch shape for one precision never resets the other's
     table (the defaults are written once for both), so the entries of a
-    loaded table survive whatever order its FP64 and FP32 rows come in.  Run
-    in a fresh process: the first use of each precision's table is the case."""
+    loaded table survive whatever order its FP64 and FP32 rows come in; the
+    correcting sweep's shape defaults to the plain sweep's (-1), is set per
+    precision and is read from a table.  Run in a fresh process: the first
+    use of each precision's table is the case."""
     import sys
     code = (
         "import sys; sys.path.insert(0, %r)\n"
@@ -165,6 +167,21 @@ def test_tune_tables_keep_entries_of_both_precisions():
         "assert Q.tune_get(33, fp32=False) == (9, 0)\n"
         "assert Q.tune_get_fused(33, fp32=True) == (4, 0)\n"
         "assert Q.tune_get(33, fp32=True) == (10, 0)\n"
+        "assert Q.tune_get_corr(65, fp32=False) == (-1, 0)\n"
+        "Q.tune_set_corr(65, 13, 32, fp32=False)\n"
+        "assert Q.tune_get_corr(65, fp32=False) == (13, 32) and Q.tune_get_corr(65, fp32=True) == (-1, 0)\n"
+        "import json, tempfile\n"
+        "t = tempfile.NamedTemporaryFile('w', suffix='.json', delete=False)\n"
+        "json.dump({'smoother': [{'n': 129, 'fp32': 1, 'corr_variant': 11, 'corr_kchunk': 8, 'us': 1.0}]}, t)\n"
+        "t.close()\n"
+        "Q.tune_load(t.name)\n"
+        "assert Q.tune_get_corr(129, fp32=True) == (11, 8)\n"
+        "assert Q.tune_get_corr(65, fp32=False) == (13, 32)\n"
+        "try:\n"
+        "    Q.tune_set_corr(65, 99, 0)\n"
+        "    raise SystemExit('bad variant accepted')\n"
+        "except Q.QumondError:\n"
+        "    pass\n"
         "print('ok')\n" % ROOT)
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr

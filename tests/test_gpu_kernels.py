@@ -373,6 +373,26 @@ def test_single_sweep_with_correction_is_bitwise_identical(n):
             assert np.array_equal(host(out), ref), (v, kc)
 
 
+def test_correcting_sweep_shape_keeps_the_bits():
+    """The correcting sweep's own launch shape, set apart from the plain
+    sweep's, changes only the schedule: an FMG solve whose 129^3 level folds
+    the correction into single sweeps gives the same bits in every shape."""
+    n, L = 129, 10.0
+    f, u = _bc_problem(n, L, 4242)
+    saved = Q.tune_get_corr(n)
+    outs = []
+    try:
+        for shape in ((-1, 0), (13, 32), (7, 16), (11, 0)):
+            Q.tune_set_corr(n, *shape)
+            d = dev(u)
+            Q.k_fmg(dev(f), d, L, ncycle=2, max_extra=0, tol=0.0)
+            outs.append(host(d))
+    finally:
+        Q.tune_set_corr(n, *saved)
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
 @pytest.mark.parametrize("n", [5, 17, 33, 65, 129])
 def test_every_fused_shape_is_bitwise_identical(n):
     """The fused two-sweep smoother in every shape (z-march tiles, 8^3, 6^3 and
