@@ -381,12 +381,15 @@ hipError_t tune_class(qumond_batch *B, Class &C, int reps)
         }
         char buf[400];
         std::snprintf(buf, sizeof buf,
-                      "%s{\"n\": %d, \"single\": [%d, %d, %.2f], \"fused\": [%d, %d, %.2f], \"use_fused\": %d, "
-                      "\"rr\": [%d, %.2f, %.2f, %.2f, %.2f, %.2f, %.2f, %.2f], \"split_prolong\": [%d, %.2f, %.2f]}",
+                      "%s{\"n\": %d, \"single\": [%d, %d, %.2f], \"fused\": [%d, %d, %.2f], \"use_fused\": %d, \"rr\": [%d",
                       first ? "" : ", ", n, C.shapes.single[l].variant, C.shapes.single[l].kchunk, best[0],
-                      C.shapes.fused[l].variant, C.shapes.fused[l].kchunk, best[1], C.shapes.use_fused[l],
-                      C.shapes.rr[l], rr_us[0], rr_us[1], rr_us[2], rr_us[3], rr_us[4], rr_us[5], rr_us[6], C.shapes.split[l], sp_us[0],
-                      sp_us[1]);
+                      C.shapes.fused[l].variant, C.shapes.fused[l].kchunk, best[1], C.shapes.use_fused[l], C.shapes.rr[l]);
+        js += buf;
+        for (int v = 0; v < qm::kRrVariants; ++v) {
+            std::snprintf(buf, sizeof buf, ", %.2f", rr_us[v]);
+            js += buf;
+        }
+        std::snprintf(buf, sizeof buf, "], \"split_prolong\": [%d, %.2f, %.2f]}", C.shapes.split[l], sp_us[0], sp_us[1]);
         js += buf;
         first = false;
     }

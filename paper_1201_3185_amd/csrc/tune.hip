@@ -402,12 +402,15 @@ qumond_status qumond_autotune(int32_t n_max, int32_t both, int32_t reps, const c
             if (st2 != QUMOND_OK) return st2;
             const int spv = prec ? qm::split_prolong<float>(n) : qm::split_prolong<double>(n);
             char buf[400];
-            std::snprintf(buf, sizeof buf,
-                          ", {\"n\": %d, \"fp32\": %d, \"use_fused\": %d}, {\"n\": %d, \"fp32\": %d, \"rr\": %d, "
-                          "\"rr_us\": [%.3f, %.3f, %.3f, %.3f, %.3f, %.3f, %.3f]}, {\"n\": %d, \"fp32\": %d, \"split_prolong\": %d, "
-                          "\"us\": [%.3f, %.3f]}",
-                          n, prec, fuse, n, prec, rrv, rr_us[0], rr_us[1], rr_us[2], rr_us[3], rr_us[4], rr_us[5], rr_us[6], n, prec, spv,
-                          sp_us[0], sp_us[1]);
+            std::snprintf(buf, sizeof buf, ", {\"n\": %d, \"fp32\": %d, \"use_fused\": %d}, {\"n\": %d, \"fp32\": %d, \"rr\": %d, \"rr_us\": [",
+                          n, prec, fuse, n, prec, rrv);
+            js += buf;
+            for (int v = 0; v < qm::kRrVariants; ++v) {
+                std::snprintf(buf, sizeof buf, "%s%.3f", v ? ", " : "", rr_us[v]);
+                js += buf;
+            }
+            std::snprintf(buf, sizeof buf, "]}, {\"n\": %d, \"fp32\": %d, \"split_prolong\": %d, \"us\": [%.3f, %.3f]}", n, prec,
+                          spv, sp_us[0], sp_us[1]);
             js += buf;
         }
     }
