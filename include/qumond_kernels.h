@@ -49,6 +49,16 @@ qumond_status qumond_k_rbgs_double_sweep(int32_t n, double h, const double *f, c
 qumond_status qumond_k_residual_restrict(int32_t nf, double h, const double *f, const double *u, double *fc,
                                          double *uc0, double *uc1, void *stream);
 
+/* One red-black sweep u_in -> u_out (as qumond_k_rbgs_sweep, u_in != u_out)
+ * and the residual restriction of u_out (as qumond_k_residual_restrict) in one
+ * launch: the last pre-smoothing sweep of a V-cycle and the coarse right-hand
+ * side it produces (Sec. 2, the multigrid solves of Eq. 1 and Eq. 2).  Same
+ * values as the two separate calls.  n = 2^J + 1 with 9 <= n <= 1025;
+ * u_in, u_out, f: n^3 doubles; fc, uc0 (and uc1, optional): nc^3 doubles,
+ * nc = (n + 1) / 2.  Errors: bad sizes or NULL arrays -> QUMOND_ERR_INVALID. */
+qumond_status qumond_k_rbgs_sweep_restrict(int32_t n, double h, const double *f, const double *u_in, double *u_out,
+                                           double *fc, double *uc0, double *uc1, void *stream);
+
 /* dst = full-weighting restriction of src (interior of the coarse grid; 0 on
  * its boundary). */
 qumond_status qumond_k_restrict(int32_t nf, const double *src, double *dst, void *stream);

@@ -67,6 +67,17 @@ qumond_status qumond_tune_get_rr(int32_t n, int32_t fp32, int32_t *variant);
  * the level's smoother form and keeps the faster).  Errors: n not 2^J + 1 in
  * 5..1025 or split outside {0, 1} -> QUMOND_ERR_INVALID. */
 qumond_status qumond_tune_set_split(int32_t n, int32_t fp32, int32_t split);
+
+/* Last pre-smoothing sweep of a level of n points and the residual restriction
+ * that follows it (the u_l, f_{l-1} steps of a V-cycle): fused = 1 runs them as
+ * one launch, each workgroup marching a whole z column and repeating its
+ * neighbours' updates on a four-node ring so that it can form the residuals
+ * at its edges; fused = 0 (default) as a sweep launch and a restriction launch
+ * (identical results; the autotuner times both and keeps the faster).  Used
+ * where the level sweeps one sweep per launch.  Errors: n not 2^J + 1 in
+ * 5..1025 or fused outside {0, 1} -> QUMOND_ERR_INVALID. */
+qumond_status qumond_tune_set_sweep_restrict(int32_t n, int32_t fp32, int32_t fused);
+qumond_status qumond_tune_get_sweep_restrict(int32_t n, int32_t fp32, int32_t *fused);
 qumond_status qumond_tune_get_split(int32_t n, int32_t fp32, int32_t *split);
 
 /* One smoother sweep with an explicit shape (see qumond_k_rbgs_sweep); with

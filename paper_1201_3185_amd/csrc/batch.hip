@@ -569,6 +569,7 @@ qumond_status qumond_batch_create(const qumond_batch_config *cfg, const int32_t 
             const int nl = (1 << l) + 1;
             C.shapes.single[l] = qm::rbgs_shape<float>(nl < 5 ? 5 : nl);
             C.shapes.corr[l] = qm::SmootherShape{-1, 0};   // the correcting sweep as the batch's own single sweep
+            C.shapes.sr[l] = 0;                              // sweep and residual restriction as two launches
             C.shapes.fused[l] = qm::rbgs2_shape<float>(nl < 5 ? 5 : nl);
             C.shapes.use_fused[l] = qm::use_fused<float>(nl < 5 ? 5 : nl);
             C.shapes.rr[l] = qm::rr_variant<float>(nl < 5 ? 5 : nl);

@@ -176,6 +176,18 @@ template <typename T> void launch_residual_restrict_variant(int nf, double h, co
                                                            T *uc1, int variant, hipStream_t s, int nb = 1);
 template <typename T> int &rr_variant(int nf);
 template <typename T> void launch_restrict(int nf, const T *src, T *dst, hipStream_t s, int nb = 1);
+// ---- sweep_restrict.hip
+// One smoother sweep uin -> uout fused with the residual restriction of uout
+// (fc = FW(f - A_h uout) on the next coarser level, uc0 = 0, uc1 = 0 on its
+// boundary): the same values as launch_rbgs then launch_residual_restrict.
+// Each workgroup marches a whole z column, so the grid needs n >= 9.
+template <typename T> bool rbgs_restrict_fits(int n);
+template <typename T> void launch_rbgs_restrict(int n, double h, const T *f, const T *uin, T *uout, T *fc, T *uc0, T *uc1,
+                                               hipStream_t s, int nb = 1);
+// Whether the last pre-smoothing sweep of a level of n points runs fused with
+// its residual restriction (1) or as a sweep launch and a restriction launch
+// (0, the default); identical results, chosen by the autotuner.
+template <typename T> int &sweep_restrict(int n);
 template <typename T> void launch_prolong_add(int nc, const T *uc, T *uf, hipStream_t s, int nb = 1);
 template <typename T> void launch_interp(int nc, const T *uc, T *uf, hipStream_t s, int nb = 1);
 template <typename T> void launch_inject_boundary(int nfine, const T *ufine, int nl, T *u0, T *u1, hipStream_t s,

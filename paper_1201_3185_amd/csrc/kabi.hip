@@ -104,6 +104,16 @@ qumond_status qumond_k_residual_restrict(int32_t nf, double h, const double *f, 
     return kcheck("qumond_k_residual_restrict");
 }
 
+qumond_status qumond_k_rbgs_sweep_restrict(int32_t n, double h, const double *f, const double *u_in, double *u_out,
+                                           double *fc, double *uc0, double *uc1, void *stream)
+{
+    if (!good_n(n) || !qm::rbgs_restrict_fits<double>(n) || !(h > 0.0) || !f || !u_in || !u_out || u_in == u_out ||
+        !fc || !uc0)
+        return kfail("qumond_k_rbgs_sweep_restrict: bad argument");
+    qm::launch_rbgs_restrict<double>(n, h, f, u_in, u_out, fc, uc0, uc1, (hipStream_t)stream);
+    return kcheck("qumond_k_rbgs_sweep_restrict");
+}
+
 qumond_status qumond_k_restrict(int32_t nf, const double *src, double *dst, void *stream)
 {
     if (!good_n(nf) || !src || !dst) return kfail("qumond_k_restrict: bad argument");

@@ -84,6 +84,7 @@ struct LevelShapes {
     int use_fused[11];
     int rr[11];   // residual-restriction kernel of fine level l
     int split[11];   // coarse-grid correction of level l as its own launch
+    int sr[11];   // last pre-smoothing sweep of level l fused with its residual restriction
 };
 
 template <typename T>
@@ -253,17 +254,41 @@ struct Multigrid {
     void vcycle(int l)
     {
         Level<T> &v = lv[l];
-        smooth(l, npre);
+        Level<T> &c = lv[l - 1];
+        if (fuse_sweep_restrict(l)) {
+            smooth(l, npre - 1);
+            launch_rbgs_restrict<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], c.f, c.u[c.cur], c.u[1 - c.cur], s, nb);
+            v.cur ^= 1;
+        } else {
+            smooth(l, npre);
+            restrict_residual(l);
+        }
+        // the restriction zeroed the correction: the tail need not read it
+        if (l - 1 == lt) launch_coarse_tail<T>(lt, L, c.f, c.u[c.cur], npre, npost, 1, 2, 1, s, nb);
+        else vcycle(l - 1);
+        smooth(l, npost, c.u[c.cur]);
+    }
+
+    // Whether level l's last pre-smoothing sweep runs fused with the residual
+    // restriction: where the table asks for it, the level sweeps one sweep per
+    // launch, and that sweep reads an iterate (not the zero-iterate first sweep).
+    bool fuse_sweep_restrict(int l) const
+    {
+        const int n = lv[l].n;
+        if (!(shapes ? shapes->sr[l] : sweep_restrict<T>(n)) || !rbgs_restrict_fits<T>(n) || npre < 1) return false;
+        if (fused && (shapes ? shapes->use_fused[l] : use_fused<T>(n)) != 0 && npre >= 2) return false;
+        return !(zero_start && l == J && npre == 1);
+    }
+
+    void restrict_residual(int l)
+    {
+        Level<T> &v = lv[l];
         Level<T> &c = lv[l - 1];
         if (shapes)
             launch_residual_restrict_variant<T>(v.n, v.h, v.f, v.u[v.cur], c.f, c.u[c.cur], c.u[1 - c.cur],
                                                 shapes->rr[l], s, nb);
         else
             launch_residual_restrict<T>(v.n, v.h, v.f, v.u[v.cur], c.f, c.u[c.cur], c.u[1 - c.cur], s, nb);
-        // the restriction zeroed the correction: the tail need not read it
-        if (l - 1 == lt) launch_coarse_tail<T>(lt, L, c.f, c.u[c.cur], npre, npost, 1, 2, 1, s, nb);
-        else vcycle(l - 1);
-        smooth(l, npost, c.u[c.cur]);
     }
 
     // The finest-level cycle used after the FMG schedule.
@@ -356,7 +381,8 @@ struct Multigrid {
             const int uf = shapes ? shapes->use_fused[l] : use_fused<T>(n);
             const int rr = shapes ? shapes->rr[l] : rr_variant<T>(n);
             const int sp = shapes ? shapes->split[l] : split_prolong<T>(n);
-            v.insert(v.end(), {a.variant, a.kchunk, c.variant, c.kchunk, b.variant, b.kchunk, uf, rr, sp});
+            const int sr = shapes ? shapes->sr[l] : sweep_restrict<T>(n);
+            v.insert(v.end(), {a.variant, a.kchunk, c.variant, c.kchunk, b.variant, b.kchunk, uf, rr, sp, sr});
         }
         v.insert(v.end(), {fused ? 1 : 0, npre, npost});
         return v;

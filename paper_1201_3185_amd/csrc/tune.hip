@@ -160,6 +160,69 @@ qumond_status tune_rr(int n, int reps, hipStream_t s, double us[qm::kRrVariants]
     return QUMOND_OK;
 }
 
+// Time the last pre-smoothing sweep of a level of n points followed by its
+// residual restriction (us[0], the level's own sweep shape and restriction
+// kernel) against the fused sweep-and-restriction launch (us[1]), and install
+// the faster.
+template <typename T>
+qumond_status tune_sweep_restrict(int n, int reps, hipStream_t s, double us[2])
+{
+    us[0] = us[1] = 0.0;
+    if (!qm::rbgs_restrict_fits<T>(n)) return QUMOND_OK;
+    const int nc = (n + 1) / 2;
+    const size_t N = (size_t)n * n * n, Nc = (size_t)nc * nc * nc;
+    T *f = nullptr, *u0 = nullptr, *u1 = nullptr, *fc = nullptr, *c0 = nullptr, *c1 = nullptr;
+    if (hipMalloc((void **)&f, N * sizeof(T)) != hipSuccess || hipMalloc((void **)&u0, N * sizeof(T)) != hipSuccess ||
+        hipMalloc((void **)&u1, N * sizeof(T)) != hipSuccess || hipMalloc((void **)&fc, Nc * sizeof(T)) != hipSuccess ||
+        hipMalloc((void **)&c0, Nc * sizeof(T)) != hipSuccess || hipMalloc((void **)&c1, Nc * sizeof(T)) != hipSuccess) {
+        for (T *p : {f, u0, u1, fc, c0, c1}) (void)hipFree(p);
+        qm_set_last_error("qumond_autotune: allocation failed");
+        return QUMOND_ERR_OOM;
+    }
+    qm::launch_fill<T>(f, N, T(1), s);
+    qm::launch_fill<T>(u0, N, T(0.5), s);
+    qm::launch_fill<T>(u1, N, T(0.5), s);
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const double h = 1.0 / (n - 1);
+    for (int fz = 0; fz < 2; ++fz) {
+        auto run = [&](int r) {
+            const T *a = (r & 1) ? u1 : u0;
+            T *b = (r & 1) ? u0 : u1;
+            if (fz) {
+                qm::launch_rbgs_restrict<T>(n, h, f, a, b, fc, c0, c1, s);
+            } else {
+                qm::launch_rbgs<T>(n, h, f, a, b, s);
+                qm::launch_residual_restrict<T>(n, h, f, b, fc, c0, c1, s);
+            }
+        };
+        run(0);
+        std::vector<float> t;
+        for (int r = 0; r < reps; ++r) {
+            (void)hipEventRecord(e0, s);
+            run(r);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            t.push_back(ms);
+        }
+        std::sort(t.begin(), t.end());
+        us[fz] = 1e3 * t[t.size() / 2];
+    }
+    qm::sweep_restrict<T>(n) = us[1] < us[0] ? 1 : 0;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (T *p : {f, u0, u1, fc, c0, c1}) (void)hipFree(p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        qm_set_last_error(hipGetErrorString(e));
+        return QUMOND_ERR_HIP;
+    }
+    return QUMOND_OK;
+}
+
 // Time the first post-smoothing launch of a level of n points with the
 // coarse-grid correction applied inside it (us[0]) against a prolong-add
 // launch followed by the same smoother launch without it (us[1]), in the
@@ -304,6 +367,21 @@ qumond_status qumond_tune_get_rr(int32_t n, int32_t fp32, int32_t *variant)
     return QUMOND_OK;
 }
 
+qumond_status qumond_tune_set_sweep_restrict(int32_t n, int32_t fp32, int32_t fused)
+{
+    if (!good_n(n) || fused < 0 || fused > 1) return tfail("qumond_tune_set_sweep_restrict: bad argument");
+    if (fp32) qm::sweep_restrict<float>(n) = fused;
+    else qm::sweep_restrict<double>(n) = fused;
+    return QUMOND_OK;
+}
+
+qumond_status qumond_tune_get_sweep_restrict(int32_t n, int32_t fp32, int32_t *fused)
+{
+    if (!good_n(n) || !fused) return tfail("qumond_tune_get_sweep_restrict: bad argument");
+    *fused = fp32 ? qm::sweep_restrict<float>(n) : qm::sweep_restrict<double>(n);
+    return QUMOND_OK;
+}
+
 qumond_status qumond_tune_set_split(int32_t n, int32_t fp32, int32_t split)
 {
     if (!good_n(n) || split < 0 || split > 1) return tfail("qumond_tune_set_split: bad argument");
@@ -401,6 +479,11 @@ qumond_status qumond_autotune(int32_t n_max, int32_t both, int32_t reps, const c
             const qumond_status st2 = prec ? tune_split<float>(n, reps, s, sp_us) : tune_split<double>(n, reps, s, sp_us);
             if (st2 != QUMOND_OK) return st2;
             const int spv = prec ? qm::split_prolong<float>(n) : qm::split_prolong<double>(n);
+            double sr_us[2] = {};
+            const qumond_status st3 =
+                prec ? tune_sweep_restrict<float>(n, reps, s, sr_us) : tune_sweep_restrict<double>(n, reps, s, sr_us);
+            if (st3 != QUMOND_OK) return st3;
+            const int srv = prec ? qm::sweep_restrict<float>(n) : qm::sweep_restrict<double>(n);
             char buf[400];
             std::snprintf(buf, sizeof buf, ", {\"n\": %d, \"fp32\": %d, \"use_fused\": %d}, {\"n\": %d, \"fp32\": %d, \"rr\": %d, \"rr_us\": [",
                           n, prec, fuse, n, prec, rrv);
@@ -411,6 +494,9 @@ qumond_status qumond_autotune(int32_t n_max, int32_t both, int32_t reps, const c
             }
             std::snprintf(buf, sizeof buf, "]}, {\"n\": %d, \"fp32\": %d, \"split_prolong\": %d, \"us\": [%.3f, %.3f]}", n, prec,
                           spv, sp_us[0], sp_us[1]);
+            js += buf;
+            std::snprintf(buf, sizeof buf, ", {\"n\": %d, \"fp32\": %d, \"sweep_restrict\": %d, \"us\": [%.3f, %.3f]}", n,
+                          prec, srv, sr_us[0], sr_us[1]);
             js += buf;
         }
     }
@@ -453,6 +539,15 @@ qumond_status qumond_tune_load(const char *json_path)
         if (std::sscanf(txt.c_str() + pos, "{\"n\": %d, \"fp32\": %d, \"corr_variant\": %d, \"corr_kchunk\": %d", &n,
                         &fp32, &variant, &kchunk) == 4) {
             if (qumond_tune_set_corr(n, fp32, variant, kchunk) != QUMOND_OK) return QUMOND_ERR_INVALID;
+            ++loaded;
+        }
+        ++pos;
+    }
+    pos = 0;
+    while ((pos = txt.find("{\"n\":", pos)) != std::string::npos) {
+        int n = 0, fp32 = 0, srv = 0;
+        if (std::sscanf(txt.c_str() + pos, "{\"n\": %d, \"fp32\": %d, \"sweep_restrict\": %d", &n, &fp32, &srv) == 3) {
+            if (qumond_tune_set_sweep_restrict(n, fp32, srv) != QUMOND_OK) return QUMOND_ERR_INVALID;
             ++loaded;
         }
         ++pos;

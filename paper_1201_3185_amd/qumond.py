@@ -101,6 +101,7 @@ _SIGNATURES = {
     "qumond_k_rbgs_sweep_from_zero": (_I32, [_I32, _D, _P, _P, _P]),
     "qumond_k_rbgs_double_sweep": (_I32, [_I32, _D, _P, _P, _P, _P, _P]),
     "qumond_k_residual_restrict": (_I32, [_I32, _D, _P, _P, _P, _P, _P, _P]),
+    "qumond_k_rbgs_sweep_restrict": (_I32, [_I32, _D, _P, _P, _P, _P, _P, _P, _P]),
     "qumond_k_restrict": (_I32, [_I32, _P, _P, _P]),
     "qumond_k_prolong_add": (_I32, [_I32, _P, _P, _P]),
     "qumond_k_interp": (_I32, [_I32, _P, _P, _P]),
@@ -126,6 +127,8 @@ _SIGNATURES = {
     "qumond_tune_set": (_I32, [_I32, _I32, _I32, _I32]),
     "qumond_tune_get": (_I32, [_I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "qumond_tune_set_corr": (_I32, [_I32, _I32, _I32, _I32]),
+    "qumond_tune_set_sweep_restrict": (_I32, [_I32, _I32, _I32]),
+    "qumond_tune_get_sweep_restrict": (_I32, [_I32, _I32, ctypes.POINTER(_I32)]),
     "qumond_tune_get_corr": (_I32, [_I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "qumond_tune_set_fused": (_I32, [_I32, _I32, _I32, _I32]),
     "qumond_tune_get_fused": (_I32, [_I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
@@ -423,6 +426,12 @@ def k_residual_restrict(f, u, h, fc, uc0, uc1=None):
                                            _s()), "qumond_k_residual_restrict")
 
 
+def k_rbgs_sweep_restrict(f, u_in, u_out, h, fc, uc0, uc1=None):
+    """One sweep u_in -> u_out fused with the residual restriction of u_out."""
+    check(lib().qumond_k_rbgs_sweep_restrict(u_out.shape[0], float(h), _ptr(f), _ptr(u_in), _ptr(u_out), _ptr(fc),
+                                             _ptr(uc0), _ptr(uc1), _s()), "qumond_k_rbgs_sweep_restrict")
+
+
 def k_restrict(src, dst):
     check(lib().qumond_k_restrict(src.shape[0], _ptr(src), _ptr(dst), _s()), "qumond_k_restrict")
 
@@ -501,6 +510,19 @@ def tune_get_corr(n, fp32=False):
     v, k = ctypes.c_int32(0), ctypes.c_int32(0)
     check(lib().qumond_tune_get_corr(int(n), int(bool(fp32)), ctypes.byref(v), ctypes.byref(k)), "qumond_tune_get_corr")
     return int(v.value), int(k.value)
+
+
+def tune_set_sweep_restrict(n, fused, fp32=False):
+    """1: the last pre-smoothing sweep of level n runs fused with its residual
+    restriction; 0: two launches."""
+    check(lib().qumond_tune_set_sweep_restrict(int(n), int(bool(fp32)), int(fused)), "qumond_tune_set_sweep_restrict")
+
+
+def tune_get_sweep_restrict(n, fp32=False):
+    v = ctypes.c_int32(0)
+    check(lib().qumond_tune_get_sweep_restrict(int(n), int(bool(fp32)), ctypes.byref(v)),
+          "qumond_tune_get_sweep_restrict")
+    return int(v.value)
 
 
 def tune_set_fused(n, variant, kchunk, fp32=False):

@@ -177,6 +177,14 @@ def test_tune_tables_keep_entries_of_both_precisions():
         "Q.tune_load(t.name)\n"
         "assert Q.tune_get_corr(129, fp32=True) == (11, 8)\n"
         "assert Q.tune_get_corr(65, fp32=False) == (13, 32)\n"
+        "assert Q.tune_get_sweep_restrict(257) == 0\n"
+        "Q.tune_set_sweep_restrict(257, 1)\n"
+        "assert Q.tune_get_sweep_restrict(257) == 1 and Q.tune_get_sweep_restrict(257, fp32=True) == 0\n"
+        "t2 = tempfile.NamedTemporaryFile('w', suffix='.json', delete=False)\n"
+        "json.dump({'smoother': [{'n': 513, 'fp32': 1, 'sweep_restrict': 1, 'us': [2.0, 1.0]}]}, t2)\n"
+        "t2.close()\n"
+        "Q.tune_load(t2.name)\n"
+        "assert Q.tune_get_sweep_restrict(513, fp32=True) == 1\n"
         "try:\n"
         "    Q.tune_set_corr(65, 99, 0)\n"
         "    raise SystemExit('bad variant accepted')\n"

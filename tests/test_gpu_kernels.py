@@ -373,6 +373,60 @@ def test_single_sweep_with_correction_is_bitwise_identical(n):
             assert np.array_equal(host(out), ref), (v, kc)
 
 
+@pytest.mark.parametrize("n", [9, 17, 33, 65, 129, 257])
+def test_sweep_restrict_equals_sweep_then_restriction(n):
+    """The fused last pre-smoothing sweep and residual restriction gives the
+    bits of a sweep launch followed by a restriction launch: the swept u,
+    the coarse right-hand side, the zeroed coarse iterate and the other coarse
+    buffer zeroed on its boundary only (ring recomputation, several tiles at
+    129^3 and 257^3, ragged edges)."""
+    L = 5.5
+    h = L / (n - 1)
+    f, u = rand_state(n, 5100 + n)
+    nc = (n + 1) // 2
+    fd = dev(f)
+    ref_u = dev(u)
+    Q.k_rbgs_sweep(fd, dev(u), ref_u, h)
+    ref = [dev(np.full((nc,) * 3, 3.0)) for _ in range(3)]
+    Q.k_residual_restrict(fd, ref_u, h, *ref)
+    out_u = dev(np.full((n,) * 3, -7.0))
+    bnd = np.ones((n,) * 3, bool)
+    bnd[1:-1, 1:-1, 1:-1] = False
+    got = [dev(np.full((nc,) * 3, 3.0)) for _ in range(3)]
+    Q.k_rbgs_sweep_restrict(fd, dev(u), out_u, h, *got)
+    gu, ru = host(out_u), host(ref_u)
+    assert np.array_equal(gu[~bnd], ru[~bnd])
+    assert np.all(gu[bnd] == -7.0)   # boundary nodes are not written
+    for a, b in zip(got, ref):
+        assert np.array_equal(host(a), host(b))
+    # and against the oracle's sweep and restriction
+    uo = O.rbgs_sweep(f, u.copy(), h)
+    assert rel(gu[~bnd], uo[~bnd]) < 1e-14
+    assert rel(host(got[0]), O.restrict_fw(O.residual(f, uo, h))) < 1e-12
+
+
+@pytest.mark.parametrize("n", [65, 129])
+def test_fmg_with_fused_sweep_restrict_keeps_the_bits(n):
+    """An FMG solve whose levels fuse the last pre-smoothing sweep with the
+    residual restriction gives the bits of the solve without the fusion."""
+    L = 9.0
+    f, u = _bc_problem(n, L, 4300 + n)
+    levels = [m for m in (9, 17, 33, 65, 129) if m <= n]
+    saved = {m: Q.tune_get_sweep_restrict(m) for m in levels}
+    outs = []
+    try:
+        for flag in (0, 1):
+            for m in levels:
+                Q.tune_set_sweep_restrict(m, flag)
+            d = dev(u)
+            Q.k_fmg(dev(f), d, L, ncycle=2, max_extra=0, tol=0.0)
+            outs.append(host(d))
+    finally:
+        for m, v in saved.items():
+            Q.tune_set_sweep_restrict(m, v)
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_correcting_sweep_shape_keeps_the_bits():
     """The correcting sweep's own launch shape, set apart from the plain
     sweep's, changes only the schedule: an FMG solve whose 129^3 level folds
