@@ -318,6 +318,41 @@ hipError_t tune_class(qumond_batch *B, Class &C, int reps)
                 }
         }
         C.shapes.use_fused[l] = best[1] < 2.0 * best[0] ? 1 : 0;
+        // the single sweep that also applies the coarse-grid correction: its own shape, timed with a correction
+        const int ncl = (n + 1) / 2;
+        float *ucr = C.mg.lv[l - 1].u[0];
+        qm::launch_fill<float>(ucr, (size_t)ncl * ncl * ncl * C.P, 0.001f, s);
+        double best_corr = 1e30;
+        for (int v = 0; v < qm::kSmootherVariants; ++v)
+            for (int kc : kTuneChunks) {
+                if (kc != 0 && kc >= n - 2) continue;
+                if (qm::is_brick_variant(v, false) && kc != 0) continue;
+                const int nzc = kc ? (n - 2 + kc - 1) / kc : 1;
+                if (nzc > zmax) continue;
+                const qm::SmootherShape sh{v, kc};
+                auto run = [&](int r) {
+                    const float *a = (r & 1) ? u1 : u0;
+                    float *b = (r & 1) ? u0 : u1;
+                    qm::launch_rbgs_shape<float>(n, h, f, a, b, sh, s, C.P, ucr);
+                };
+                run(0);
+                std::vector<float> t;
+                for (int r = 0; r < reps; ++r) {
+                    (void)hipEventRecord(e0, s);
+                    run(r);
+                    (void)hipEventRecord(e1, s);
+                    if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    t.push_back(ms);
+                }
+                std::sort(t.begin(), t.end());
+                const double us = 1e3 * t[t.size() / 2];
+                if (us < best_corr) {
+                    best_corr = us;
+                    C.shapes.corr[l] = sh;
+                }
+            }
         // residual restriction from this level: both kernels on the batch's own grids
         double rr_us[qm::kRrVariants] = {};
         {
@@ -361,7 +396,7 @@ hipError_t tune_class(qumond_batch *B, Class &C, int reps)
                         c = nullptr;
                     }
                     if (fz) qm::launch_rbgs2_shape<float>(n, h, f, a, b, c, C.shapes.fused[l], s, C.P);
-                    else qm::launch_rbgs_shape<float>(n, h, f, a, b, C.shapes.single[l], s, C.P, c);
+                    else qm::launch_rbgs_shape<float>(n, h, f, a, b, c ? C.shapes.corr[l] : C.shapes.single[l], s, C.P, c);
                 };
                 run(0);
                 std::vector<float> t;
@@ -381,9 +416,11 @@ hipError_t tune_class(qumond_batch *B, Class &C, int reps)
         }
         char buf[400];
         std::snprintf(buf, sizeof buf,
-                      "%s{\"n\": %d, \"single\": [%d, %d, %.2f], \"fused\": [%d, %d, %.2f], \"use_fused\": %d, \"rr\": [%d",
+                      "%s{\"n\": %d, \"single\": [%d, %d, %.2f], \"corr\": [%d, %d, %.2f], \"fused\": [%d, %d, %.2f], "
+                      "\"use_fused\": %d, \"rr\": [%d",
                       first ? "" : ", ", n, C.shapes.single[l].variant, C.shapes.single[l].kchunk, best[0],
-                      C.shapes.fused[l].variant, C.shapes.fused[l].kchunk, best[1], C.shapes.use_fused[l], C.shapes.rr[l]);
+                      C.shapes.corr[l].variant, C.shapes.corr[l].kchunk, best_corr, C.shapes.fused[l].variant,
+                      C.shapes.fused[l].kchunk, best[1], C.shapes.use_fused[l], C.shapes.rr[l]);
         js += buf;
         for (int v = 0; v < qm::kRrVariants; ++v) {
             std::snprintf(buf, sizeof buf, ", %.2f", rr_us[v]);
@@ -568,7 +605,7 @@ qumond_status qumond_batch_create(const qumond_batch_config *cfg, const int32_t 
         for (int l = 0; l <= 10 && l <= C.J; ++l) {
             const int nl = (1 << l) + 1;
             C.shapes.single[l] = qm::rbgs_shape<float>(nl < 5 ? 5 : nl);
-            C.shapes.corr[l] = qm::SmootherShape{-1, 0};   // the correcting sweep as the batch's own single sweep
+            C.shapes.corr[l] = qm::SmootherShape{-1, 0};   // until tuned: the correcting sweep as the single sweep
             C.shapes.sr[l] = 0;                              // sweep and residual restriction as two launches
             C.shapes.fused[l] = qm::rbgs2_shape<float>(nl < 5 ? 5 : nl);
             C.shapes.use_fused[l] = qm::use_fused<float>(nl < 5 ? 5 : nl);
