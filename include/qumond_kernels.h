@@ -38,7 +38,9 @@ qumond_status qumond_k_rbgs_sweep_from_zero(int32_t n, double h, const double *f
 /* Two sweeps in one launch (same result, bit for bit, as two calls of
  * qumond_k_rbgs_sweep).  uc (optional): a coarse grid of (n+1)/2 points per side
  * whose trilinear prolongation is added to u_in's interior first, as the
- * coarse-grid correction of a V-cycle (qumond_k_prolong_add) does. */
+ * coarse-grid correction of a V-cycle (qumond_k_prolong_add) does.  u_in NULL
+ * (with uc NULL): a zero iterate, read from nowhere, as in
+ * qumond_k_rbgs_sweep_from_zero; u_out's boundary must then hold zeros. */
 qumond_status qumond_k_rbgs_double_sweep(int32_t n, double h, const double *f, const double *u_in, double *u_out,
                                          const double *uc, void *stream);
 

@@ -167,13 +167,17 @@ template <typename T> int &use_fused(int n);
 // prolong-add launch (1) or is folded into the first post-smoothing launch (0);
 // identical results, chosen by the autotuner from measured times.
 template <typename T> int &split_prolong(int n);
+// zero_u = false leaves the interior of uc0 unwritten (its boundary is still
+// zeroed): for a caller whose next use of the coarse correction takes it as
+// zero without reading it.
 template <typename T> void launch_residual_restrict(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1,
-                                                   hipStream_t s, int nb = 1);
-// The two implementations of the residual restriction (0: per-node gather,
-// 1: LDS tile; identical results) and the table entry that selects one per
-// fine level size (set by the autotuner).
+                                                   hipStream_t s, int nb = 1, bool zero_u = true);
+// The implementations of the residual restriction (per-node gather, LDS tiles,
+// z-march; identical results) and the table entry that selects one per fine
+// level size (set by the autotuner).
 template <typename T> void launch_residual_restrict_variant(int nf, double h, const T *f, const T *u, T *fc, T *uc0,
-                                                           T *uc1, int variant, hipStream_t s, int nb = 1);
+                                                           T *uc1, int variant, hipStream_t s, int nb = 1,
+                                                           bool zero_u = true);
 template <typename T> int &rr_variant(int nf);
 template <typename T> void launch_restrict(int nf, const T *src, T *dst, hipStream_t s, int nb = 1);
 // ---- sweep_restrict.hip
@@ -183,7 +187,7 @@ template <typename T> void launch_restrict(int nf, const T *src, T *dst, hipStre
 // Each workgroup marches a whole z column, so the grid needs n >= 9.
 template <typename T> bool rbgs_restrict_fits(int n);
 template <typename T> void launch_rbgs_restrict(int n, double h, const T *f, const T *uin, T *uout, T *fc, T *uc0, T *uc1,
-                                               hipStream_t s, int nb = 1);
+                                               hipStream_t s, int nb = 1, bool zero_u = true);
 // Whether the last pre-smoothing sweep of a level of n points runs fused with
 // its residual restriction (1) or as a sweep launch and a restriction launch
 // (0, the default); identical results, chosen by the autotuner.

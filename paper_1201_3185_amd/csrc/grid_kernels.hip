@@ -998,11 +998,11 @@ rbgs2_zmarch(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
     }
     T v[NL], w[NFL];
     auto prefetch_u = [&](int k) {
-        const T *src = uin + (size_t)k * nn;
+        const T *src = uin ? uin + (size_t)k * nn : nullptr;   // null: a zero iterate, read from nowhere
         const bool inner_plane = k >= 1 && k <= n - 2;
 #pragma unroll
         for (int r = 0; r < NL; ++r) {
-            T x = goff[r] >= 0 ? src[goff[r]] : T(0);
+            T x = goff[r] >= 0 ? (src ? src[goff[r]] : T(0)) : T(0);
             if (PROLONG && inner_plane && goff[r] >= 0 && gi[r] >= 1 && gi[r] <= n - 2 && gj[r] >= 1 && gj[r] <= n - 2)
                 x += prolong_at(nc, uc, gi[r], gj[r], k);
             v[r] = x;
@@ -1424,10 +1424,13 @@ void launch_rbgs(int n, double h, const T *f, const T *uin, T *uout, hipStream_t
 
 // Coarse node (I,J,K): fc = sum_{a,b,c} w_a w_b w_c r(2I+a, 2J+b, 2K+c) with
 // r = f - A_h u, w = (1/4, 1/2, 1/4); coarse boundary 0.  Also zeroes the
-// coarse correction (uc0 everywhere, uc1 on the boundary).
+// coarse correction (uc0 everywhere, uc1 on the boundary); with zu = 0 the
+// interior of uc0 is left as it is, for a caller whose next use of the coarse
+// correction takes it as zero without reading it (every residual-restriction
+// kernel takes zu the same way).
 template <typename T>
 __global__ void residual_restrict_k(int nf, T ih2, const T *__restrict__ f, const T *__restrict__ u, T *__restrict__ fc,
-                                    T *__restrict__ uc0, T *__restrict__ uc1, int zb)
+                                    T *__restrict__ uc0, T *__restrict__ uc1, int zb, int zu)
 {
 #pragma clang fp contract(off)
     const int nc = (nf + 1) / 2;
@@ -1444,7 +1447,7 @@ __global__ void residual_restrict_k(int nf, T ih2, const T *__restrict__ f, cons
     if (uc1) uc1 += pb * Nc;
     const size_t C = id3(nc, I, J, K);
     const bool bnd = I == 0 || J == 0 || K == 0 || I == nc - 1 || J == nc - 1 || K == nc - 1;
-    uc0[C] = T(0);
+    if (zu || bnd) uc0[C] = T(0);
     if (bnd) {
         if (uc1) uc1[C] = T(0);
         fc[C] = T(0);
@@ -1505,7 +1508,7 @@ static dim3 grid3(int m, dim3 blk, int nb, int &zb)
 template <typename T, int CX, int CY, int CZ>
 __global__ void __launch_bounds__(256)
 residual_restrict_tile_k(int nf, T ih2, const T *__restrict__ f, const T *__restrict__ u, T *__restrict__ fc,
-                         T *__restrict__ uc0, T *__restrict__ uc1, int tx, int ty, int tz)
+                         T *__restrict__ uc0, T *__restrict__ uc1, int tx, int ty, int tz, int zu)
 {
 #pragma clang fp contract(off)
     static_assert(CX * CY * CZ <= 256, "one coarse node per thread");
@@ -1573,8 +1576,9 @@ residual_restrict_tile_k(int nf, T ih2, const T *__restrict__ f, const T *__rest
     const int I = I0 + li, J = J0 + lj, K = K0 + lk;
     if (I >= nc || J >= nc || K >= nc) return;
     const size_t C = id3(nc, I, J, K);
-    uc0[C] = T(0);
-    if (I == 0 || J == 0 || K == 0 || I == nc - 1 || J == nc - 1 || K == nc - 1) {
+    const bool bnd = I == 0 || J == 0 || K == 0 || I == nc - 1 || J == nc - 1 || K == nc - 1;
+    if (zu || bnd) uc0[C] = T(0);
+    if (bnd) {
         if (uc1) uc1[C] = T(0);
         fc[C] = T(0);
         return;
@@ -1598,7 +1602,7 @@ residual_restrict_tile_k(int nf, T ih2, const T *__restrict__ f, const T *__rest
 template <typename T, int CX, int CY>
 __global__ void __launch_bounds__(256)
 residual_restrict_zmarch_k(int nf, T ih2, const T *__restrict__ f, const T *__restrict__ u, T *__restrict__ fc,
-                           T *__restrict__ uc0, T *__restrict__ uc1, int tx, int ty, int tzc, int kc)
+                           T *__restrict__ uc0, T *__restrict__ uc1, int tx, int ty, int tzc, int kc, int zu)
 {
 #pragma clang fp contract(off)
     constexpr int NT = 256;
@@ -1706,7 +1710,7 @@ residual_restrict_zmarch_k(int nf, T ih2, const T *__restrict__ f, const T *__re
                     acc += (w[a + 1] * w[b + 1] * w[c + 1]) * Rp[(2 * ci + 1 + a) + RX * (2 * cj + 1 + b)];
         }
         const size_t C = id3(nc, I, J, K);
-        uc0[C] = T(0);
+        if (zu) uc0[C] = T(0);
         fc[C] = acc;
     };
 
@@ -1777,14 +1781,15 @@ int &rr_variant(int nf)
 
 template <typename T>
 void launch_residual_restrict_variant(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1, int variant,
-                                      hipStream_t s, int nb)
+                                      hipStream_t s, int nb, bool zero_u)
 {
+    const int zu = zero_u ? 1 : 0;
     const int nc = (nf + 1) / 2;
     if (variant == 0) {
         dim3 blk(16, 4, 4);
         int zb;
         const dim3 g = grid3(nc, blk, nb, zb);
-        hipLaunchKernelGGL(residual_restrict_k<T>, g, blk, 0, s, nf, T(1.0 / (h * h)), f, u, fc, uc0, uc1, zb);
+        hipLaunchKernelGGL(residual_restrict_k<T>, g, blk, 0, s, nf, T(1.0 / (h * h)), f, u, fc, uc0, uc1, zb, zu);
         return;
     }
     if (variant >= 2 && variant <= 4) {   // z-march with chunks of 4, 8 or 16 coarse planes
@@ -1793,33 +1798,34 @@ void launch_residual_restrict_variant(int nf, double h, const T *f, const T *u, 
         const int tx = (nc + CX - 1) / CX, ty = (nc + CY - 1) / CY, tzc = (nc - 2 + kc - 1) / kc;
         const dim3 g((unsigned)((size_t)tx * ty * tzc * nb));
         hipLaunchKernelGGL((residual_restrict_zmarch_k<T, CX, CY>), g, dim3(256), 0, s, nf, T(1.0 / (h * h)), f, u, fc,
-                           uc0, uc1, tx, ty, tzc, kc);
+                           uc0, uc1, tx, ty, tzc, kc, zu);
         return;
     }
     if (variant == 5) {   // 4 x 4 x 4 coarse tiles
         const int tx = (nc + 3) / 4, ty = (nc + 3) / 4, tz = (nc + 3) / 4;
         const dim3 g((unsigned)((size_t)tx * ty * tz * nb));
         hipLaunchKernelGGL((residual_restrict_tile_k<T, 4, 4, 4>), g, dim3(256), 0, s, nf, T(1.0 / (h * h)), f, u, fc,
-                           uc0, uc1, tx, ty, tz);
+                           uc0, uc1, tx, ty, tz, zu);
         return;
     }
     if (variant == 6) {   // 4 x 4 x 2 coarse tiles
         const int tx = (nc + 3) / 4, ty = (nc + 3) / 4, tz = (nc + 1) / 2;
         const dim3 g((unsigned)((size_t)tx * ty * tz * nb));
         hipLaunchKernelGGL((residual_restrict_tile_k<T, 4, 4, 2>), g, dim3(256), 0, s, nf, T(1.0 / (h * h)), f, u, fc,
-                           uc0, uc1, tx, ty, tz);
+                           uc0, uc1, tx, ty, tz, zu);
         return;
     }
     const int tx = (nc + 7) / 8, ty = (nc + 7) / 8, tz = (nc + 3) / 4;
     const dim3 g((unsigned)((size_t)tx * ty * tz * nb));
     hipLaunchKernelGGL((residual_restrict_tile_k<T, 8, 8, 4>), g, dim3(256), 0, s, nf, T(1.0 / (h * h)), f, u, fc, uc0,
-                       uc1, tx, ty, tz);
+                       uc1, tx, ty, tz, zu);
 }
 
 template <typename T>
-void launch_residual_restrict(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1, hipStream_t s, int nb)
+void launch_residual_restrict(int nf, double h, const T *f, const T *u, T *fc, T *uc0, T *uc1, hipStream_t s, int nb,
+                              bool zero_u)
 {
-    launch_residual_restrict_variant<T>(nf, h, f, u, fc, uc0, uc1, rr_variant<T>(nf), s, nb);
+    launch_residual_restrict_variant<T>(nf, h, f, u, fc, uc0, uc1, rr_variant<T>(nf), s, nb, zero_u);
 }
 
 template <typename T>
@@ -1860,18 +1866,36 @@ __global__ void __launch_bounds__(256) prolong_k(int nc, const T *__restrict__ u
     const T d0 = uc[id3(nc, q, jb, kb)], d1 = uc[id3(nc, q + 1, jb, kb)];
     const T h = T(0.5), one = T(1), zero = T(0);
     const size_t p = id3(nf, 2 * q + 1, j, k);
+    T vo, ve = T(0);
     {   // odd i: weights 1/2, 1/2 between coarse q and q + 1
         const T xa = h * a0 + h * a1, xb = h * b0 + h * b1, xc = h * c0 + h * c1, xd = h * d0 + h * d1;
-        const T v = wka * (wja * xa + wjb * xb) + wkb * (wja * xc + wjb * xd);
-        if (ADD) uf[p] += v;
-        else uf[p] = v;
+        vo = wka * (wja * xa + wjb * xb) + wkb * (wja * xc + wjb * xd);
     }
-    if (2 * q + 2 <= nf - 2) {   // even i: coarse q + 1 with weights 1, 0
+    const bool even = 2 * q + 2 <= nf - 2;
+    if (even) {   // even i: coarse q + 1 with weights 1, 0
         const T xa = one * a1 + zero * a1, xb = one * b1 + zero * b1, xc = one * c1 + zero * c1,
                 xd = one * d1 + zero * d1;
-        const T v = wka * (wja * xa + wjb * xb) + wkb * (wja * xc + wjb * xd);
-        if (ADD) uf[p + 1] += v;
-        else uf[p + 1] = v;
+        ve = wka * (wja * xa + wjb * xb) + wkb * (wja * xc + wjb * xd);
+    }
+    // the pair is adjacent in memory: one two-element access (aligned to one
+    // element only) instead of two half-filled strided ones
+    typedef T pair_t __attribute__((ext_vector_type(2), aligned(sizeof(T))));
+    if (even) {
+        pair_t *dst = reinterpret_cast<pair_t *>(uf + p);
+        pair_t o;
+        if (ADD) {
+            o = *dst;
+            o.x += vo;
+            o.y += ve;
+        } else {
+            o.x = vo;
+            o.y = ve;
+        }
+        *dst = o;
+    } else if (ADD) {
+        uf[p] += vo;
+    } else {
+        uf[p] = vo;
     }
 }
 
@@ -2734,9 +2758,9 @@ void launch_guess_interior(int n, const void *g, int kind, double *u, hipStream_
     template void launch_rbgs2_shape<T>(int, double, const T *, const T *, T *, const T *, SmootherShape,        \
                                         hipStream_t, int);                                                      \
     template void launch_residual_restrict<T>(int, double, const T *, const T *, T *, T *, T *, hipStream_t,    \
-                                              int);                                                             \
+                                              int, bool);                                                       \
     template void launch_residual_restrict_variant<T>(int, double, const T *, const T *, T *, T *, T *, int,     \
-                                                      hipStream_t, int);                                        \
+                                                      hipStream_t, int, bool);                                  \
     template int &rr_variant<T>(int);                                                                           \
     template void launch_restrict<T>(int, const T *, T *, hipStream_t, int);                                   \
     template void launch_prolong_add<T>(int, const T *, T *, hipStream_t, int);                                \

@@ -90,7 +90,7 @@ qumond_status qumond_k_rbgs_sweep_from_zero(int32_t n, double h, const double *f
 qumond_status qumond_k_rbgs_double_sweep(int32_t n, double h, const double *f, const double *u_in, double *u_out,
                                          const double *uc, void *stream)
 {
-    if (!good_n(n) || !(h > 0.0) || !f || !u_in || !u_out || u_in == u_out)
+    if (!good_n(n) || !(h > 0.0) || !f || !u_out || u_in == u_out || (!u_in && uc))
         return kfail("qumond_k_rbgs_double_sweep: bad argument");
     qm::launch_rbgs2<double>(n, h, f, u_in, u_out, uc, (hipStream_t)stream);
     return kcheck("qumond_k_rbgs_double_sweep");

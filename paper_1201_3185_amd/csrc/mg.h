@@ -112,6 +112,9 @@ struct Multigrid {
     // boundaries must hold zeros.  Valid where zero_start_ok().
     bool zero_start = false;
     bool zero_start_ok() const { return J > lt && npre > 0; }
+    // Level l's coarse correction is zero on its interior but was not written
+    // there by the restriction: its first pre-smoothing sweep reads no iterate.
+    bool zin[11] = {};
     float *r32_out = nullptr;
 
     struct GraphEntry {
@@ -232,16 +235,20 @@ struct Multigrid {
             uc = nullptr;
         }
         const bool fuse = fused && (shapes ? shapes->use_fused[l] != 0 : use_fused<T>(v.n) != 0);
+        bool zi = zin[l] && !uc && ns > 0;   // a zero correction the restriction left unwritten
+        zin[l] = false;
         while (ns > 0) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
-            time_begin(&e0, &e1, 3.0 * sizeof(T) * pts * nb, v.n, uc != nullptr);
+            time_begin(&e0, &e1, (zi ? 2.0 : 3.0) * sizeof(T) * pts * nb, v.n, uc != nullptr);
+            const T *uin = zi ? nullptr : v.u[v.cur];
+            zi = false;
             if (ns >= 2 && fuse) {
                 const SmootherShape sh = shapes ? shapes->fused[l] : rbgs2_shape<T>(v.n);
-                launch_rbgs2_shape<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], uc, sh, s, nb);
+                launch_rbgs2_shape<T>(v.n, v.h, v.f, uin, v.u[1 - v.cur], uc, sh, s, nb);
                 ns -= 2;
             } else {
                 const SmootherShape sh = corr_shape(l, uc != nullptr);
-                launch_rbgs_shape<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], sh, s, nb, uc);
+                launch_rbgs_shape<T>(v.n, v.h, v.f, uin, v.u[1 - v.cur], sh, s, nb, uc);
                 ns -= 1;
             }
             uc = nullptr;
@@ -257,7 +264,10 @@ struct Multigrid {
         Level<T> &c = lv[l - 1];
         if (fuse_sweep_restrict(l)) {
             smooth(l, npre - 1);
-            launch_rbgs_restrict<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], c.f, c.u[c.cur], c.u[1 - c.cur], s, nb);
+            const bool zu = !coarse_reads_no_iterate(l - 1);
+            launch_rbgs_restrict<T>(v.n, v.h, v.f, v.u[v.cur], v.u[1 - v.cur], c.f, c.u[c.cur], c.u[1 - c.cur], s, nb,
+                                    zu);
+            zin[l - 1] = !zu && l - 1 > lt;
             v.cur ^= 1;
         } else {
             smooth(l, npre);
@@ -280,15 +290,27 @@ struct Multigrid {
         return !(zero_start && l == J && npre == 1);
     }
 
+    // Whether the V-cycle on coarse level c starts without reading its
+    // (zero) correction: the coarse tail takes it as zero, and so does a first
+    // pre-smoothing sweep of smooth(); a fused sweep-and-restriction reads it.
+    bool coarse_reads_no_iterate(int c) const
+    {
+        if (c == lt) return true;
+        if (npre < 1) return false;
+        return !(npre == 1 && fuse_sweep_restrict(c));
+    }
+
     void restrict_residual(int l)
     {
         Level<T> &v = lv[l];
         Level<T> &c = lv[l - 1];
+        const bool zu = !coarse_reads_no_iterate(l - 1);
         if (shapes)
             launch_residual_restrict_variant<T>(v.n, v.h, v.f, v.u[v.cur], c.f, c.u[c.cur], c.u[1 - c.cur],
-                                                shapes->rr[l], s, nb);
+                                                shapes->rr[l], s, nb, zu);
         else
-            launch_residual_restrict<T>(v.n, v.h, v.f, v.u[v.cur], c.f, c.u[c.cur], c.u[1 - c.cur], s, nb);
+            launch_residual_restrict<T>(v.n, v.h, v.f, v.u[v.cur], c.f, c.u[c.cur], c.u[1 - c.cur], s, nb, zu);
+        zin[l - 1] = !zu && l - 1 > lt;
     }
 
     // The finest-level cycle used after the FMG schedule.

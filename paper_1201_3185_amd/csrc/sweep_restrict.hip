@@ -33,7 +33,7 @@ namespace {
 template <typename T, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY / 2)
 rbgs_restrict_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2, T ih2,
-                T *__restrict__ fc, T *__restrict__ uc0, T *__restrict__ uc1)
+                T *__restrict__ fc, T *__restrict__ uc0, T *__restrict__ uc1, int zu)
 {
 #pragma clang fp contract(off)
     constexpr int NT = TX * TY / 2;
@@ -133,7 +133,7 @@ rbgs_restrict_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__rest
                 for (int a = -1; a <= 1; ++a) acc += (w[a + 1] * w[b + 1] * w[c + 1]) * R[rbase + a + RX * b];
         }
         const size_t C = (size_t)oI + (size_t)nc * ((size_t)oJ + (size_t)nc * K);
-        uc0[C] = T(0);
+        if (zu) uc0[C] = T(0);
         fc[C] = acc;
     };
 
@@ -318,13 +318,13 @@ int &sweep_restrict(int n)
 
 template <typename T>
 void launch_rbgs_restrict(int n, double h, const T *f, const T *uin, T *uout, T *fc, T *uc0, T *uc1, hipStream_t s,
-                          int nb)
+                          int nb, bool zero_u)
 {
     constexpr int TX = 64, TY = 16;
     const int m = n - 2;
     dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, nb);
     hipLaunchKernelGGL((rbgs_restrict_k<T, TX, TY>), grid, dim3(TX * TY / 2), 0, s, uin, uout, f, n, T(h * h),
-                       T(1.0 / (h * h)), fc, uc0, uc1);
+                       T(1.0 / (h * h)), fc, uc0, uc1, zero_u ? 1 : 0);
 }
 
 template int &sweep_restrict<double>(int);
@@ -332,8 +332,8 @@ template int &sweep_restrict<float>(int);
 template bool rbgs_restrict_fits<double>(int);
 template bool rbgs_restrict_fits<float>(int);
 template void launch_rbgs_restrict<double>(int, double, const double *, const double *, double *, double *, double *,
-                                           double *, hipStream_t, int);
+                                           double *, hipStream_t, int, bool);
 template void launch_rbgs_restrict<float>(int, double, const float *, const float *, float *, float *, float *, float *,
-                                          hipStream_t, int);
+                                          hipStream_t, int, bool);
 
 }  // namespace qm

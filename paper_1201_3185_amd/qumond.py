@@ -417,7 +417,8 @@ def k_rbgs_sweep(f, u_in, u_out, h):
 
 
 def k_rbgs_double_sweep(f, u_in, u_out, h, uc=None):
-    check(lib().qumond_k_rbgs_double_sweep(u_in.shape[0], float(h), _ptr(f), _ptr(u_in), _ptr(u_out), _ptr(uc), _s()),
+    """Two sweeps u_in -> u_out in one launch; u_in None = a zero iterate."""
+    check(lib().qumond_k_rbgs_double_sweep(u_out.shape[0], float(h), _ptr(f), _ptr(u_in), _ptr(u_out), _ptr(uc), _s()),
           "qumond_k_rbgs_double_sweep")
 
 

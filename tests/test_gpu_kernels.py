@@ -450,8 +450,9 @@ def test_correcting_sweep_shape_keeps_the_bits():
 @pytest.mark.parametrize("n", [5, 17, 33, 65, 129])
 def test_every_fused_shape_is_bitwise_identical(n):
     """The fused two-sweep smoother in every shape (z-march tiles, 8^3, 6^3 and
-    4^3 bricks, ragged at the far faces) equals two single sweeps bit for bit, and
-    with a coarse correction equals prolong-add then two sweeps."""
+    4^3 bricks, ragged at the far faces) equals two single sweeps bit for bit,
+    from a zero iterate without an input array too, and with a coarse
+    correction equals prolong-add then two sweeps."""
     L = 5.0
     h = L / (n - 1)
     f, u = rand_state(n, 1700 + n)
@@ -470,6 +471,14 @@ def test_every_fused_shape_is_bitwise_identical(n):
     Q.k_rbgs_sweep(fd, pa, b2, h)
     Q.k_rbgs_sweep(fd, b2, c2, h)
     two_p = host(c2)
+    # from a zero iterate: no input array, only the output's interior written
+    z = np.zeros((n, n, n))
+    za, zb = dev(z), dev(z)
+    Q.k_rbgs_sweep(fd, dev(z), za, h)
+    Q.k_rbgs_sweep(fd, za, zb, h)
+    two_z = host(zb)
+    start = np.full((n, n, n), -5.0)
+    start[0] = start[-1] = start[:, 0] = start[:, -1] = start[:, :, 0] = start[:, :, -1] = 0.0
     before = Q.tune_get_fused(n)
     try:
         for v in Q.FUSED_VARIANTS:
@@ -478,6 +487,9 @@ def test_every_fused_shape_is_bitwise_identical(n):
                 out = dev(u)
                 Q.k_rbgs_double_sweep(fd, dev(u), out, h)
                 assert np.array_equal(host(out), two), (v, kc)
+                out = dev(start)
+                Q.k_rbgs_double_sweep(fd, None, out, h)
+                assert np.array_equal(host(out), two_z), (v, kc, "zero iterate")
                 out = dev(u)
                 Q.k_rbgs_double_sweep(fd, dev(u), out, h, uc=ucd)
                 assert np.array_equal(host(out), two_p), (v, kc, "prolong")
