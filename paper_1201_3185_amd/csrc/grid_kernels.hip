@@ -1599,13 +1599,19 @@ residual_restrict_tile_k(int nf, T ih2, const T *__restrict__ f, const T *__rest
 // is kept from the step before), then restricts planes 2K-1..2K+1 to plane K.
 // Every fine residual is formed once, with the expression and summation order
 // of residual_restrict_k, so the two kernels give identical results.
-template <typename T, int CX, int CY>
-__global__ void __launch_bounds__(256)
+// O1: tiles start at coarse column 1 rather than 0, so that 2^m interior-plus-
+// one columns split into whole tiles (a 257^3 coarse grid into 8 x 32 tiles
+// of 32 x 8, one workgroup per CU marching the whole column as the smoother
+// does, neighbours on one XCD sharing their halos in L2); the owner of a
+// column next to the low faces (I = 1 or J = 1) also zeroes the boundary
+// column beyond it.  DEPTH 2 fetches each step's planes two steps ahead, into
+// two register sets used by alternate steps.
+template <typename T, int CX, int CY, int NT = 256, bool O1 = false, int DEPTH = 1>
+__global__ void __launch_bounds__(NT)
 residual_restrict_zmarch_k(int nf, T ih2, const T *__restrict__ f, const T *__restrict__ u, T *__restrict__ fc,
                            T *__restrict__ uc0, T *__restrict__ uc1, int tx, int ty, int tzc, int kc, int zu)
 {
 #pragma clang fp contract(off)
-    constexpr int NT = 256;
     constexpr int RX = 2 * CX + 1, RY = 2 * CY + 1, RP = RX * RY;   // fine residual region of a plane
     constexpr int UX = RX + 2, UY = RY + 2, UP = UX * UY;           // u region (one-node ring)
     constexpr int NU = (UP + NT - 1) / NT, NR = (RP + NT - 1) / NT;
@@ -1628,7 +1634,7 @@ residual_restrict_zmarch_k(int nf, T ih2, const T *__restrict__ f, const T *__re
     uc0 += pb * Nc;
     if (uc1) uc1 += pb * Nc;
     const int tid = threadIdx.x;
-    const int I0 = bx * CX, J0 = by * CY;
+    const int I0 = (O1 ? 1 : 0) + bx * CX, J0 = (O1 ? 1 : 0) + by * CY;
     const int fi0 = 2 * I0 - 1, fj0 = 2 * J0 - 1;   // origin of the fine residual region
     // this thread's share of a u plane and of a residual plane
     int uoff[NU], foff[NR], rq[NR];
@@ -1652,13 +1658,23 @@ residual_restrict_zmarch_k(int nf, T ih2, const T *__restrict__ f, const T *__re
     const int I = I0 + ci, J = J0 + cj;
     const bool c_thread = tid < CX * CY && I < nc && J < nc;
     const bool c_inner = c_thread && I >= 1 && I <= nc - 2 && J >= 1 && J <= nc - 2;
+    const bool ex = O1 && c_thread && I == 1, ey = O1 && c_thread && J == 1;   // also own column 0 / row 0
     const int Kb = 1 + bz * kc, Ke = min(Kb + kc - 1, nc - 2);
 
-    auto zero_node = [&](int K) {
-        const size_t C = id3(nc, I, J, K);
+    auto zero_at = [&](int Ix, int Jx, int K) {
+        const size_t C = id3(nc, Ix, Jx, K);
         uc0[C] = T(0);
         if (uc1) uc1[C] = T(0);
         fc[C] = T(0);
+    };
+    auto zero_extra = [&](int K) {   // the boundary columns beyond this thread's (O1 tiles only)
+        if (ex) zero_at(0, J, K);
+        if (ey) zero_at(I, 0, K);
+        if (ex && ey) zero_at(0, 0, K);
+    };
+    auto zero_node = [&](int K) {
+        zero_at(I, J, K);
+        zero_extra(K);
     };
     if (c_thread && bz == 0) zero_node(0);
     if (c_thread && bz == tzc - 1) zero_node(nc - 1);
@@ -1701,6 +1717,7 @@ residual_restrict_zmarch_k(int nf, T ih2, const T *__restrict__ f, const T *__re
             zero_node(K);
             return;
         }
+        zero_extra(K);
         const T w[3] = {T(0.25), T(0.5), T(0.25)};
         T acc = T(0);
         for (int c = -1; c <= 1; ++c) {
@@ -1742,32 +1759,70 @@ residual_restrict_zmarch_k(int nf, T ih2, const T *__restrict__ f, const T *__re
     load_f(2 * Kb, fa);
     load_f(2 * Kb + 1, fb);
     __syncthreads();
-    for (int K = Kb; K <= Ke; ++K) {
-        store_u(2 * K + 1, ua);   // slots of planes 2K-3 and 2K-2, last read before the previous barrier
-        store_u(2 * K + 2, ub);
-        T fc0[NR], fc1[NR];
+    if constexpr (DEPTH == 1) {
+        for (int K = Kb; K <= Ke; ++K) {
+            store_u(2 * K + 1, ua);   // slots of planes 2K-3 and 2K-2, last read before the previous barrier
+            store_u(2 * K + 2, ub);
+            T fc0[NR], fc1[NR];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            fc0[r] = fa[r];
-            fc1[r] = fb[r];
+            for (int r = 0; r < NR; ++r) {
+                fc0[r] = fa[r];
+                fc1[r] = fb[r];
+            }
+            if (K + 1 <= Ke) {   // the next step's planes, in flight during this one
+                fetch_u(2 * K + 3, ua);
+                fetch_u(2 * K + 4, ub);
+                load_f(2 * K + 2, fa);
+                load_f(2 * K + 3, fb);
+            }
+            __syncthreads();
+            resid(2 * K, fc0);
+            resid(2 * K + 1, fc1);
+            __syncthreads();
+            restrict_plane(K);
         }
-        if (K + 1 <= Ke) {   // the next step's planes, in flight during this one
-            fetch_u(2 * K + 3, ua);
-            fetch_u(2 * K + 4, ub);
-            load_f(2 * K + 2, fa);
-            load_f(2 * K + 3, fb);
+    } else {
+        // step K's planes sit in register set K - Kb mod 2, fetched two steps ahead
+        T ua2[NU], ub2[NU], fa2[NR], fb2[NR];
+        if (Kb + 1 <= Ke) {
+            fetch_u(2 * Kb + 3, ua2);
+            fetch_u(2 * Kb + 4, ub2);
+            load_f(2 * Kb + 2, fa2);
+            load_f(2 * Kb + 3, fb2);
         }
-        __syncthreads();
-        resid(2 * K, fc0);
-        resid(2 * K + 1, fc1);
-        __syncthreads();
-        restrict_plane(K);
+        auto step = [&](int K, T *xa, T *xb, T *ya, T *yb) {
+            store_u(2 * K + 1, xa);
+            store_u(2 * K + 2, xb);
+            T fc0[NR], fc1[NR];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                fc0[r] = ya[r];
+                fc1[r] = yb[r];
+            }
+            if (K + 2 <= Ke) {   // step K + 2's planes into the set just emptied
+                fetch_u(2 * K + 5, xa);
+                fetch_u(2 * K + 6, xb);
+                load_f(2 * K + 4, ya);
+                load_f(2 * K + 5, yb);
+            }
+            __syncthreads();
+            resid(2 * K, fc0);
+            resid(2 * K + 1, fc1);
+            __syncthreads();
+            restrict_plane(K);
+        };
+        for (int K = Kb; K <= Ke; K += 2) {
+            step(K, ua, ub, fa, fb);
+            if (K + 1 <= Ke) step(K + 1, ua2, ub2, fa2, fb2);
+        }
     }
 }
 
 // Which residual-restriction kernel a fine level of n points uses (0: per-node
 // gather, 1: 8x8x4 LDS tile, 2/3/4: z-march over chunks of 4/8/16 coarse planes,
-// 5: 4x4x4, 6: 4x4x2 LDS tiles), per
+// 5: 4x4x4, 6: 4x4x2 LDS tiles, 7/8: whole-column z-march of 32x8 / 64x4
+// columns with 512 threads loading two steps ahead, 9: 32x8 columns over
+// 64-plane chunks), per
 // precision; set by the autotuner, gather by default.
 static int g_rr_variant[2][11] = {{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
 
@@ -1799,6 +1854,30 @@ void launch_residual_restrict_variant(int nf, double h, const T *f, const T *u, 
         const dim3 g((unsigned)((size_t)tx * ty * tzc * nb));
         hipLaunchKernelGGL((residual_restrict_zmarch_k<T, CX, CY>), g, dim3(256), 0, s, nf, T(1.0 / (h * h)), f, u, fc,
                            uc0, uc1, tx, ty, tzc, kc, zu);
+        return;
+    }
+    if (variant >= 7 && variant <= 9) {   // tiles from coarse column 1 (see residual_restrict_zmarch_k)
+        const T ih2 = T(1.0 / (h * h));
+        if (variant == 8) {   // 64 x 4 columns, whole column, two steps ahead, 512 threads
+            constexpr int CX = 64, CY = 4;
+            const int tx = (nc - 1 + CX - 1) / CX, ty = (nc - 1 + CY - 1) / CY;
+            const dim3 g((unsigned)((size_t)tx * ty * nb));
+            hipLaunchKernelGGL((residual_restrict_zmarch_k<T, CX, CY, 512, true, 2>), g, dim3(512), 0, s, nf, ih2, f,
+                               u, fc, uc0, uc1, tx, ty, 1, nc - 2, zu);
+            return;
+        }
+        constexpr int CX = 32, CY = 8;
+        const int tx = (nc - 1 + CX - 1) / CX, ty = (nc - 1 + CY - 1) / CY;
+        if (variant == 7) {   // 32 x 8 columns, whole column, two steps ahead, 512 threads
+            const dim3 g((unsigned)((size_t)tx * ty * nb));
+            hipLaunchKernelGGL((residual_restrict_zmarch_k<T, CX, CY, 512, true, 2>), g, dim3(512), 0, s, nf, ih2, f,
+                               u, fc, uc0, uc1, tx, ty, 1, nc - 2, zu);
+            return;
+        }
+        const int kc = 64, tzc = (nc - 2 + kc - 1) / kc;   // 32 x 8 columns, 64-plane chunks, 256 threads
+        const dim3 g((unsigned)((size_t)tx * ty * tzc * nb));
+        hipLaunchKernelGGL((residual_restrict_zmarch_k<T, CX, CY, 256, true, 1>), g, dim3(256), 0, s, nf, ih2, f, u,
+                           fc, uc0, uc1, tx, ty, tzc, kc, zu);
         return;
     }
     if (variant == 5) {   // 4 x 4 x 4 coarse tiles
