@@ -661,6 +661,19 @@ rbgs_zmarch_pair_deep(const T *__restrict__ uin, T *__restrict__ uout, const T *
         const int ab = black_a(k), ar = ab == lo ? lo + 1 : lo;
         const int ib = i0 - 2 + ab, ir = i0 - 2 + ar;
         T *dst = uout + (size_t)k * nn + (size_t)n * jb;
+        // with the correction, both nodes of the pair as one two-element store (aligned to one element; measured:
+        // faster there, slower in the plain sweep's whole-column march)
+        if (PROLONG && ilo + 1 <= n - 2) {
+            typedef T pair_t __attribute__((ext_vector_type(2), aligned(sizeof(T))));
+            const int c = bb * PX + ab;
+            const T s = P[c - 1] + P[c + 1] + P[c - PX] + P[c + PX] + Pm[c] + Pp[c];
+            const T vb = (s - h2 * fv) * sixth, vr = P[bb * PX + ar];
+            pair_t o;
+            o.x = ab == lo ? vb : vr;
+            o.y = ab == lo ? vr : vb;
+            *reinterpret_cast<pair_t *>(dst + ilo) = o;
+            return;
+        }
         if (ib <= n - 2) {
             const int c = bb * PX + ab;
             const T s = P[c - 1] + P[c + 1] + P[c - PX] + P[c + PX] + Pm[c] + Pp[c];
