@@ -57,9 +57,10 @@ qumond_status qumond_tune_get_fused(int32_t n, int32_t fp32, int32_t *variant, i
  * fine block, 2, 3, 4 = z-march over chunks of 4, 8, 16 coarse planes forming
  * each fine residual once, 5 = 4x4x4, 6 = 4x4x2 coarse LDS tiles, 7, 8 = z-march
  * over the whole column of 32x8, 64x4 coarse columns (tiles from coarse column
- * 1, 512 threads, loads two steps ahead), 9 = 32x8 columns over 64-plane chunks
- * (identical results; the autotuner picks the fastest).  Errors: variant
- * outside 0..9 -> QUMOND_ERR_INVALID. */
+ * 1, 512 threads, loads two steps ahead), 9 = 32x8 columns over 64-plane chunks,
+ * 10, 11 = 32x8 whole columns loading three, four steps ahead (identical
+ * results; the autotuner picks the fastest).  Errors: variant outside 0..11 ->
+ * QUMOND_ERR_INVALID. */
 qumond_status qumond_tune_set_rr(int32_t n, int32_t fp32, int32_t variant);
 qumond_status qumond_tune_get_rr(int32_t n, int32_t fp32, int32_t *variant);
 

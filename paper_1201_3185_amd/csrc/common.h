@@ -130,9 +130,10 @@ struct SmootherShape {
     int kchunk;
 };
 constexpr int kSmootherVariants = 16;
-constexpr int kRrVariants = 10;   // residual restriction: gather, 8x8x4 LDS tile, z-march with 4/8/16-plane
+constexpr int kRrVariants = 12;   // residual restriction: gather, 8x8x4 LDS tile, z-march with 4/8/16-plane
                                   // chunks, 4x4x4 and 4x4x2 LDS tiles, whole-column z-march of 32x8 / 64x4
-                                  // columns (512 threads), 32x8 columns over 64-plane chunks
+                                  // columns (512 threads), 32x8 columns over 64-plane chunks, 32x8 whole
+                                  // columns loading three / four steps ahead
 // bricks hold their whole block in LDS and take no z-chunk
 inline bool is_brick_variant(int v, bool fused) { return fused ? (v >= 2 && v <= 4) : (v == 5 || v == 9 || v == 10); }
 constexpr int kFusedVariants = 8;   // two sweeps: 0: 32x8, 1: 64x4 z-march, 2: 8^3, 3: 4^3, 4: 6^3 bricks,

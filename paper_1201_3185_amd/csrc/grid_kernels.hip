@@ -1617,8 +1617,8 @@ residual_restrict_tile_k(int nf, T ih2, const T *__restrict__ f, const T *__rest
 // of 32 x 8, one workgroup per CU marching the whole column as the smoother
 // does, neighbours on one XCD sharing their halos in L2); the owner of a
 // column next to the low faces (I = 1 or J = 1) also zeroes the boundary
-// column beyond it.  DEPTH 2 fetches each step's planes two steps ahead, into
-// two register sets used by alternate steps.
+// column beyond it.  DEPTH 2, 3 or 4 fetches each step's planes that many
+// steps ahead, into as many register sets used by the steps in turn.
 template <typename T, int CX, int CY, int NT = 256, bool O1 = false, int DEPTH = 1>
 __global__ void __launch_bounds__(NT)
 residual_restrict_zmarch_k(int nf, T ih2, const T *__restrict__ f, const T *__restrict__ u, T *__restrict__ fc,
@@ -1795,14 +1795,17 @@ residual_restrict_zmarch_k(int nf, T ih2, const T *__restrict__ f, const T *__re
             restrict_plane(K);
         }
     } else {
-        // step K's planes sit in register set K - Kb mod 2, fetched two steps ahead
-        T ua2[NU], ub2[NU], fa2[NR], fb2[NR];
-        if (Kb + 1 <= Ke) {
-            fetch_u(2 * Kb + 3, ua2);
-            fetch_u(2 * Kb + 4, ub2);
-            load_f(2 * Kb + 2, fa2);
-            load_f(2 * Kb + 3, fb2);
-        }
+        // step K's planes sit in register set (K - Kb) mod DEPTH, fetched DEPTH steps ahead
+        T ua2[NU], ub2[NU], fa2[NR], fb2[NR], ua3[NU], ub3[NU], fa3[NR], fb3[NR], ua4[NU], ub4[NU], fa4[NR], fb4[NR];
+        auto fetch_step = [&](int K, T *xa, T *xb, T *ya, T *yb) {
+            fetch_u(2 * K + 1, xa);
+            fetch_u(2 * K + 2, xb);
+            load_f(2 * K, ya);
+            load_f(2 * K + 1, yb);
+        };
+        if (Kb + 1 <= Ke) fetch_step(Kb + 1, ua2, ub2, fa2, fb2);
+        if (DEPTH >= 3 && Kb + 2 <= Ke) fetch_step(Kb + 2, ua3, ub3, fa3, fb3);
+        if (DEPTH >= 4 && Kb + 3 <= Ke) fetch_step(Kb + 3, ua4, ub4, fa4, fb4);
         auto step = [&](int K, T *xa, T *xb, T *ya, T *yb) {
             store_u(2 * K + 1, xa);
             store_u(2 * K + 2, xb);
@@ -1812,21 +1815,18 @@ residual_restrict_zmarch_k(int nf, T ih2, const T *__restrict__ f, const T *__re
                 fc0[r] = ya[r];
                 fc1[r] = yb[r];
             }
-            if (K + 2 <= Ke) {   // step K + 2's planes into the set just emptied
-                fetch_u(2 * K + 5, xa);
-                fetch_u(2 * K + 6, xb);
-                load_f(2 * K + 4, ya);
-                load_f(2 * K + 5, yb);
-            }
+            if (K + DEPTH <= Ke) fetch_step(K + DEPTH, xa, xb, ya, yb);   // into the set just emptied
             __syncthreads();
             resid(2 * K, fc0);
             resid(2 * K + 1, fc1);
             __syncthreads();
             restrict_plane(K);
         };
-        for (int K = Kb; K <= Ke; K += 2) {
+        for (int K = Kb; K <= Ke; K += DEPTH) {
             step(K, ua, ub, fa, fb);
             if (K + 1 <= Ke) step(K + 1, ua2, ub2, fa2, fb2);
+            if (DEPTH >= 3 && K + 2 <= Ke) step(K + 2, ua3, ub3, fa3, fb3);
+            if (DEPTH >= 4 && K + 3 <= Ke) step(K + 3, ua4, ub4, fa4, fb4);
         }
     }
 }
@@ -1835,7 +1835,8 @@ residual_restrict_zmarch_k(int nf, T ih2, const T *__restrict__ f, const T *__re
 // gather, 1: 8x8x4 LDS tile, 2/3/4: z-march over chunks of 4/8/16 coarse planes,
 // 5: 4x4x4, 6: 4x4x2 LDS tiles, 7/8: whole-column z-march of 32x8 / 64x4
 // columns with 512 threads loading two steps ahead, 9: 32x8 columns over
-// 64-plane chunks), per
+// 64-plane chunks, 10/11: 32x8 whole columns loading three / four steps
+// ahead), per
 // precision; set by the autotuner, gather by default.
 static int g_rr_variant[2][11] = {{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
 
@@ -1869,7 +1870,7 @@ void launch_residual_restrict_variant(int nf, double h, const T *f, const T *u, 
                            uc0, uc1, tx, ty, tzc, kc, zu);
         return;
     }
-    if (variant >= 7 && variant <= 9) {   // tiles from coarse column 1 (see residual_restrict_zmarch_k)
+    if (variant >= 7 && variant <= 11) {   // tiles from coarse column 1 (see residual_restrict_zmarch_k)
         const T ih2 = T(1.0 / (h * h));
         if (variant == 8) {   // 64 x 4 columns, whole column, two steps ahead, 512 threads
             constexpr int CX = 64, CY = 4;
@@ -1885,6 +1886,16 @@ void launch_residual_restrict_variant(int nf, double h, const T *f, const T *u, 
             const dim3 g((unsigned)((size_t)tx * ty * nb));
             hipLaunchKernelGGL((residual_restrict_zmarch_k<T, CX, CY, 512, true, 2>), g, dim3(512), 0, s, nf, ih2, f,
                                u, fc, uc0, uc1, tx, ty, 1, nc - 2, zu);
+            return;
+        }
+        if (variant == 10 || variant == 11) {   // 32 x 8 columns, whole column, three / four steps ahead
+            const dim3 g((unsigned)((size_t)tx * ty * nb));
+            if (variant == 10)
+                hipLaunchKernelGGL((residual_restrict_zmarch_k<T, CX, CY, 512, true, 3>), g, dim3(512), 0, s, nf, ih2,
+                                   f, u, fc, uc0, uc1, tx, ty, 1, nc - 2, zu);
+            else
+                hipLaunchKernelGGL((residual_restrict_zmarch_k<T, CX, CY, 512, true, 4>), g, dim3(512), 0, s, nf, ih2,
+                                   f, u, fc, uc0, uc1, tx, ty, 1, nc - 2, zu);
             return;
         }
         const int kc = 64, tzc = (nc - 2 + kc - 1) / kc;   // 32 x 8 columns, 64-plane chunks, 256 threads

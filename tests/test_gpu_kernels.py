@@ -94,8 +94,9 @@ def test_residual_restrict(n):
 @pytest.mark.parametrize("n", [9, 17, 33, 65, 129, 257])
 def test_residual_restrict_variants_bitwise(n):
     """The gather, LDS-tile (three tile sizes) and z-march (three chunk sizes;
-    32x8 and 64x4 columns from coarse column 1 over the whole column, 32x8 over
-    64-plane chunks) residual restrictions give the same bits."""
+    32x8 and 64x4 columns from coarse column 1 over the whole column, loading
+    two to four steps ahead, 32x8 over 64-plane chunks) residual restrictions
+    give the same bits."""
     L = 3.0
     h = L / (n - 1)
     f, u = rand_state(n, 400 + n)
@@ -103,14 +104,14 @@ def test_residual_restrict_variants_bitwise(n):
     before = Q.tune_get_rr(n)
     outs = []
     try:
-        for v in range(10):
+        for v in range(12):
             Q.tune_set_rr(n, v)
             fc, uc0, uc1 = (dev(np.full((nc,) * 3, 3.0)) for _ in range(3))
             Q.k_residual_restrict(dev(f), dev(u), h, fc, uc0, uc1)
             outs.append((host(fc), host(uc0), host(uc1)))
     finally:
         Q.tune_set_rr(n, before)
-    for v in range(1, 10):
+    for v in range(1, 12):
         for a, b in zip(outs[0], outs[v]):
             assert np.array_equal(a, b), v
 
