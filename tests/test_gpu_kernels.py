@@ -116,6 +116,40 @@ def test_residual_restrict_variants_bitwise(n):
             assert np.array_equal(a, b), v
 
 
+def test_restrict_513():
+    """At 513^3 the restriction of f gives the bits of the per-node gather of the
+    residual restriction with a zero iterate (r = f exactly), and sampled coarse
+    nodes equal the weighted sum written out in the same order."""
+    n, nc = 513, 257
+    g = torch.Generator(device="cuda")
+    g.manual_seed(513)
+    f = torch.randn((n,) * 3, dtype=torch.float64, device="cuda", generator=g)
+    fc = torch.zeros((nc,) * 3, dtype=torch.float64, device="cuda")
+    Q.k_restrict(f, fc)
+    before = Q.tune_get_rr(n)
+    try:
+        Q.tune_set_rr(n, 0)
+        u = torch.zeros_like(f)
+        ref, c0 = (torch.zeros((nc,) * 3, dtype=torch.float64, device="cuda") for _ in range(2))
+        Q.k_residual_restrict(f, u, 1.0, ref, c0)
+        del u
+    finally:
+        Q.tune_set_rr(n, before)
+    assert torch.equal(fc, ref)
+    w = np.array([0.25, 0.5, 0.25])
+    rng = np.random.default_rng(5)
+    for _ in range(16):
+        I, J, K = (int(x) for x in rng.integers(1, nc - 1, 3))
+        blk = f[2 * K - 1:2 * K + 2, 2 * J - 1:2 * J + 2, 2 * I - 1:2 * I + 2].cpu().numpy()
+        want = 0.0
+        for c in range(3):
+            for b in range(3):
+                for a in range(3):
+                    want += (w[a] * w[b] * w[c]) * blk[c, b, a]
+        assert fc[K, J, I].item() == want
+    assert torch.count_nonzero(fc[0]) == 0 and torch.count_nonzero(fc[:, :, -1]) == 0
+
+
 @pytest.mark.parametrize("n", SIZES)
 def test_restrict(n):
     src = rand_state(n, 300 + n)[0]
