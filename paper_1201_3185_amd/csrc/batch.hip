@@ -287,7 +287,7 @@ hipError_t tune_class(qumond_batch *B, Class &C, int reps)
             for (int v = 0; v < nvar; ++v)
                 for (int kc : kTuneChunks) {
                     if (kc != 0 && kc >= n - 2) continue;
-                    if (qm::is_brick_variant(v, fz != 0) && kc != 0) continue;
+                    if (qm::takes_no_chunk(v, fz != 0) && kc != 0) continue;
                     if (fz && kc != 0 && kc < 4) continue;   // the two-sweep march needs 4-plane chunks
                     const int nzc = kc ? (n - 2 + kc - 1) / kc : 1;
                     if (nzc > zmax) continue;

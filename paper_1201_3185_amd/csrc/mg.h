@@ -242,8 +242,10 @@ struct Multigrid {
             time_begin(&e0, &e1, (zi ? 2.0 : 3.0) * sizeof(T) * pts * nb, v.n, uc != nullptr);
             const T *uin = zi ? nullptr : v.u[v.cur];
             zi = false;
-            if (ns >= 2 && fuse) {
-                const SmootherShape sh = shapes ? shapes->fused[l] : rbgs2_shape<T>(v.n);
+            const SmootherShape shf = fuse ? (shapes ? shapes->fused[l] : rbgs2_shape<T>(v.n)) : SmootherShape{0, 0};
+            // the skewed two-sweep march takes no correction: with one, the correcting sweep goes first
+            if (ns >= 2 && fuse && !(uc && shf.variant == kSkewVariant)) {
+                const SmootherShape sh = shf;
                 launch_rbgs2_shape<T>(v.n, v.h, v.f, uin, v.u[1 - v.cur], uc, sh, s, nb);
                 ns -= 2;
             } else {

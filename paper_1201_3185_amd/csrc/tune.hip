@@ -65,7 +65,7 @@ qumond_status tune_one(int n, int reps, hipStream_t s, double &best_us, bool fus
     for (int v = 0; v < nvar; ++v)
         for (int kc : kChunks) {
             if (kc != 0 && kc >= n - 2) continue;
-            if (qm::is_brick_variant(v, fused) && kc != 0) continue;   // bricks have no z-chunk
+            if (qm::takes_no_chunk(v, fused) && kc != 0) continue;   // bricks and whole-column marches
             if (fused && kc != 0 && kc < 4) continue;   // the two-sweep march needs 4-plane chunks
             const qm::SmootherShape sh{v, kc};
             std::vector<float> t;

@@ -518,7 +518,7 @@ def test_every_fused_shape_is_bitwise_identical(n):
     before = Q.tune_get_fused(n)
     try:
         for v in Q.FUSED_VARIANTS:
-            for kc in ((0,) if v in (2, 3, 4) else (4, 16, 0)):
+            for kc in ((0,) if v in (2, 3, 4, 8) else (4, 16, 0)):
                 Q.tune_set_fused(n, v, kc)
                 out = dev(u)
                 Q.k_rbgs_double_sweep(fd, dev(u), out, h)
@@ -529,6 +529,39 @@ def test_every_fused_shape_is_bitwise_identical(n):
                 out = dev(u)
                 Q.k_rbgs_double_sweep(fd, dev(u), out, h, uc=ucd)
                 assert np.array_equal(host(out), two_p), (v, kc, "prolong")
+    finally:
+        Q.tune_set_fused(n, *before)
+
+
+@pytest.mark.parametrize("n", [257, 513])
+def test_skewed_double_sweep_full_size(n):
+    """The skewed two-sweep march (whole 64x16 columns, the four half-sweeps two
+    planes apart) equals two single sweeps bit for bit at full size, from a
+    given iterate and from a zero one."""
+    h = 1.0 / (n - 1)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(n)
+    f = torch.randn((n,) * 3, dtype=torch.float64, device="cuda", generator=g)
+    u = torch.randn((n,) * 3, dtype=torch.float64, device="cuda", generator=g)
+    u[0] = u[-1] = u[:, 0] = u[:, -1] = u[:, :, 0] = u[:, :, -1] = 0.0
+    a, b = u.clone(), u.clone()
+    Q.k_rbgs_sweep(f, u, a, h)
+    Q.k_rbgs_sweep(f, a, b, h)
+    z = torch.zeros_like(u)
+    za, zb = z.clone(), z.clone()
+    Q.k_rbgs_sweep(f, z, za, h)
+    Q.k_rbgs_sweep(f, za, zb, h)
+    before = Q.tune_get_fused(n)
+    try:
+        Q.tune_set_fused(n, 8, 0)
+        out = torch.full_like(u, 3.0)
+        out[0] = out[-1] = out[:, 0] = out[:, -1] = out[:, :, 0] = out[:, :, -1] = 0.0
+        Q.k_rbgs_double_sweep(f, u, out, h)
+        assert torch.equal(out, b)
+        out.fill_(-2.0)
+        out[0] = out[-1] = out[:, 0] = out[:, -1] = out[:, :, 0] = out[:, :, -1] = 0.0
+        Q.k_rbgs_double_sweep(f, None, out, h)
+        assert torch.equal(out, zb)
     finally:
         Q.tune_set_fused(n, *before)
 
