@@ -16,9 +16,11 @@ FMG level, both solves to a 1e-10 relative residual, plain FP64.
 value = 513^3 grid points / wall time of one step (host syncs of the stopping
 tests included).  The roofline object reports the red-black smoother on the
 finest (513^3) level, the dominant kernel: algorithmic bytes (read u, read f,
-write u: 24 B per node) of those launches over their average duration, from
-hipEvents the library records around each of them, on the stream it runs on,
-during the timed steps.  cpu_baseline runs the CPU oracle on the full headline
+write u: 24 B per node per launch, of one sweep or, where the launch table
+fuses the pre-smoothing pair, of two) of those launches over their average
+duration, from hipEvents the library records around each of them, on the
+stream it runs on, during the timed steps; with fused pairs it also reports
+the single plain sweep timed on its own.  cpu_baseline runs the CPU oracle on the full headline
 workload (its node-parallel loops on the stated number of host threads), and
 its potentials are the reference for every error figure of the 513^3 legs.
 
@@ -66,20 +68,48 @@ def host_cpu():
     return model, cores
 
 
-def smoother_traffic(key):
+def smoother_traffic(key, sweeps):
     """HBM traffic per launch of the finest-level smoother from the committed
     rocprofv3 counter runs (copy-calibrated FETCH_SIZE + WRITE_SIZE), valid only
-    while the kernel source is unchanged (null otherwise)."""
+    for the same kind of launch (sweeps per launch) while the kernel's source
+    file is unchanged (null otherwise)."""
     path = os.path.join(HERE, "profiles", "smoother_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(key)
-    if not rec:
+    if not rec or rec.get("sweeps_per_launch", 1) != sweeps:
         return None
-    src = open(os.path.join(HERE, "paper_1201_3185_amd", "csrc", "grid_kernels.hip"), "rb").read()
-    if rec.get("grid_kernels_sha256") != hashlib.sha256(src).hexdigest():
+    src = open(os.path.join(HERE, rec.get("kernel_source", "paper_1201_3185_amd/csrc/grid_kernels.hip")), "rb").read()
+    if rec.get("source_sha256", rec.get("grid_kernels_sha256")) != hashlib.sha256(src).hexdigest():
         return None
     return rec.get("bytes_per_launch")
+
+
+def single_sweep_roofline(Q, torch, n=513, reps=15):
+    """The single plain sweep at n^3 with the loaded launch shape, timed on its
+    own (hipEvents around each launch, median of reps): where the multigrid
+    fuses the pre-smoothing pair, it still runs one of these per V-cycle."""
+    h = 1.0 / (n - 1)
+    f = torch.ones((n,) * 3, dtype=torch.float64, device="cuda")
+    u = [torch.full_like(f, 0.5), torch.full_like(f, 0.5)]
+    for r in range(3):
+        Q.k_rbgs_sweep(f, u[r & 1], u[1 - (r & 1)], h)
+    ts = []
+    for r in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        Q.k_rbgs_sweep(f, u[r & 1], u[1 - (r & 1)], h)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del f, u
+    torch.cuda.empty_cache()
+    med_ms = sorted(ts)[len(ts) // 2]
+    achieved = 24.0 * n ** 3 / (med_ms * 1e-3) / 1e9
+    return {"median_launch_us": round(med_ms * 1e3, 2), "achieved": round(achieved, 1),
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "timed": f"median of {reps} launches on {n}^3 fields, apart from the step",
+            "traffic": smoother_traffic("fp64_513_single", 1)}
 
 
 def load_shapes(Q, args, n_max):
@@ -549,13 +579,21 @@ def main():
     avg_ms = st["total_ms"] / max(st["launches"], 1)
     per_launch = st["alg_bytes"] / max(st["launches"], 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    sweeps = st.get("sweeps_per_launch", 1) or 1
+    if sweeps == 2:
+        kern = ("red-black smoother, finest (513^3) level: the skewed two-sweep launches (rbgs2_skew_k, the "
+                "pre-smoothing pair of each V-cycle in one pass: 24 B per node per launch of two sweeps), FP64")
+    else:
+        kern = ("red-black smoother, finest (513^3) level, plain sweeps (one per launch; the first "
+                "post-smoothing sweep, which also applies the coarse-grid correction, is left out), FP64 "
+                "(24 B per node)")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": smoother_traffic("fp64_513"),
-            "kernel": "red-black smoother, finest (513^3) level, plain sweeps (one per launch; the first "
-                      "post-smoothing sweep, which also applies the coarse-grid correction, is left out), FP64 "
-                      "(24 B per node)",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": smoother_traffic("fp64_513", sweeps),
+            "kernel": kern, "sweeps_per_launch": sweeps,
             "launches_per_step": st["launches"] // args.steps, "avg_launch_us": round(avg_ms * 1e3, 2),
             "alg_bytes_per_launch": per_launch}
+    if sweeps == 2:
+        roof["single_sweep"] = single_sweep_roofline(Q, torch)
     log(f"513^3 FP64 step {ms:.2f} ms, {value:.4g} grid-pts/s; finest smoother {st['launches']} launches, "
         f"avg {avg_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic")
 

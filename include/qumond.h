@@ -249,18 +249,22 @@ qumond_status qumond_set_field(qumond_ctx *ctx, int32_t box, int32_t field, cons
 /* Timing of the red-black smoother, the solve's dominant kernel: when
  * enabled, every smoother launch of the context's FP64 solves is bracketed by
  * two hipEvents on the stream it runs on.  on = 0 disables, on = 1 records
- * every level, on = n (2^J + 1 >= 5) records only the plain sweeps on levels
- * of n points per side (n = the box's n: the finest level), leaving out the
- * sweeps that also apply the coarse-grid correction as they load u; any other
- * value returns QUMOND_ERR_INVALID.  The first sweep of a correction from a
- * zero iterate is not recorded.  qumond_profile_read synchronises, returns the
- * number of launches, their summed duration and their summed algorithmic
- * traffic (read u, read f, write u: 3 values per node of the level), and
+ * every level, on = n (2^J + 1 >= 5) records only the plain launches on
+ * levels of n points per side (n = the box's n: the finest level), leaving out
+ * the sweeps that also apply the coarse-grid correction as they load u, and of
+ * the plain launches only the kind the level smooths pairs of sweeps with: the
+ * two-sweep launches where its launch table fuses pairs, single sweeps
+ * otherwise; any other value returns QUMOND_ERR_INVALID.  The first sweep of a
+ * correction from a zero iterate is not recorded.  qumond_profile_read
+ * synchronises, returns the number of launches, their summed duration, their
+ * summed algorithmic traffic (read u, read f, write u: 3 values per node of
+ * the level, per launch of one or two sweeps) and the sweeps per launch, and
  * clears the record. */
 typedef struct qumond_kernel_stats {
     int64_t launches;
     double total_ms;
     double alg_bytes;
+    int32_t sweeps_per_launch; /* 2 where the profiled level runs its sweeps in pairs, else 1 (0: none timed) */
 } qumond_kernel_stats;
 qumond_status qumond_profile_enable(qumond_ctx *ctx, int32_t on);
 qumond_status qumond_profile_read(qumond_ctx *ctx, qumond_kernel_stats *out);

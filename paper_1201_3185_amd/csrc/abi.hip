@@ -2,6 +2,7 @@
 // per-context grids of every nested box, the call-order state machine, and the
 // box-by-box chaining of Sec. 2 (outer Dirichlet value, then each inner box's
 // boundary interpolated from the coarser box's converged solution).
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <condition_variable>
@@ -296,8 +297,10 @@ qumond_status qumond_profile_read(qumond_ctx *ctx, qumond_kernel_stats *out)
     out->launches = 0;
     out->total_ms = 0.0;
     out->alg_bytes = 0.0;
+    out->sweeps_per_launch = 0;
     for (qm::SmootherProfile *p : {&ctx->mg.prof, &ctx->mg2.prof}) {
         out->launches += (int64_t)p->used;
+        if (p->used) out->sweeps_per_launch = std::max(out->sweeps_per_launch, (int32_t)p->sweeps);
         for (size_t i = 0; i < p->used; ++i) {
             float ms = 0.0f;
             if ((e = hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1])) != hipSuccess)

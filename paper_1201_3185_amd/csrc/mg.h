@@ -48,7 +48,10 @@ struct Level {
 // with its algorithmic traffic: read u, read f, write u = 3 values per node.
 struct SmootherProfile {
     bool on = false;
-    int only_n = 0;   // if > 0, only the plain sweeps (no folded correction) on levels of only_n points per side
+    int only_n = 0;   // if > 0, only the plain launches (no folded correction) on levels of only_n points per side,
+                      // and of those only the kind the level runs its pre-smoothing with: two-sweep launches
+                      // where it fuses pairs of sweeps, single sweeps otherwise
+    int sweeps = 0;   // sweeps per recorded launch (1 or 2; 0 before the first)
     std::vector<hipEvent_t> ev;
     std::vector<double> bytes;
     size_t used = 0;
@@ -194,9 +197,12 @@ struct Multigrid {
         for (int l = 1; l <= J; ++l) lv[l].cur = 0;
     }
 
-    void time_begin(hipEvent_t *e0, hipEvent_t *e1, double bytes, int n, bool folds_correction)
+    void time_begin(hipEvent_t *e0, hipEvent_t *e1, double bytes, int n, bool folds_correction, int sweeps,
+                    bool level_fuses)
     {
-        if (!prof.on || (prof.only_n > 0 && (prof.only_n != n || folds_correction))) return;
+        if (!prof.on || (prof.only_n > 0 && (prof.only_n != n || folds_correction || sweeps != (level_fuses ? 2 : 1))))
+            return;
+        prof.sweeps = sweeps;
         prof.record_pair(s, e0, e1);
         prof.bytes.push_back(bytes);
         (void)hipEventRecord(*e0, s);
@@ -239,12 +245,13 @@ struct Multigrid {
         zin[l] = false;
         while (ns > 0) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
-            time_begin(&e0, &e1, (zi ? 2.0 : 3.0) * sizeof(T) * pts * nb, v.n, uc != nullptr);
-            const T *uin = zi ? nullptr : v.u[v.cur];
-            zi = false;
             const SmootherShape shf = fuse ? (shapes ? shapes->fused[l] : rbgs2_shape<T>(v.n)) : SmootherShape{0, 0};
             // the skewed two-sweep march takes no correction: with one, the correcting sweep goes first
-            if (ns >= 2 && fuse && !(uc && shf.variant == kSkewVariant)) {
+            const bool two = ns >= 2 && fuse && !(uc && shf.variant == kSkewVariant);
+            time_begin(&e0, &e1, (zi ? 2.0 : 3.0) * sizeof(T) * pts * nb, v.n, uc != nullptr, two ? 2 : 1, fuse);
+            const T *uin = zi ? nullptr : v.u[v.cur];
+            zi = false;
+            if (two) {
                 const SmootherShape sh = shf;
                 launch_rbgs2_shape<T>(v.n, v.h, v.f, uin, v.u[1 - v.cur], uc, sh, s, nb);
                 ns -= 2;

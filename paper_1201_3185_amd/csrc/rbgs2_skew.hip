@@ -25,12 +25,11 @@ namespace qm {
 
 namespace {
 
-template <typename T, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY / 2)
+template <typename T, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT)
 rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2)
 {
 #pragma clang fp contract(off)
-    constexpr int NT = TX * TY / 2;
     constexpr int RG = 4;                                  // ring of the region held in LDS
     constexpr int PX = TX + 2 * RG, PY = TY + 2 * RG, PL = PX * PY;
     constexpr int NS = 10;                                 // planes s - 7 .. s + 2
@@ -41,7 +40,7 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
     constexpr int R2 = ((TX + 4) / 2 * (TY + 4) + NT - 1) / NT;
     constexpr int R1 = ((TX + 2) / 2 * (TY + 2) + NT - 1) / NT;
     constexpr int NF = R3 + R2 + R1 + 1;                   // f values of one step
-    static_assert(TX % 2 == 0 && HX * TY == NT, "one pair of tile nodes per thread");
+    static_assert(TX % 2 == 0 && HX * TY <= NT, "at most one pair of tile nodes per thread");
     __shared__ T pl[NS][PL];
     const T sixth = T(1) / T(6);
     const int tid = threadIdx.x;
@@ -141,6 +140,7 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
         if (k < 1 || k > n - 2) return;
         int cl, gi, gj;
         node(W0{}, 0, k, 1, cl, gi, gj);
+        if (tid >= HX * TY) return;   // threads beyond the tile's pairs
         const int br = tid / HX, q = tid % HX;
         const int j = j0 + br;
         if (j > n - 2) return;
@@ -204,10 +204,10 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
 template <typename T>
 void launch_rbgs2_skew(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s, int nb)
 {
-    constexpr int TX = 64, TY = 16;
+    constexpr int TX = 64, TY = 16, NT = 1024;   // two threads per pair of tile nodes
     const int m = n - 2;
     const dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, nb);
-    hipLaunchKernelGGL((rbgs2_skew_k<T, TX, TY>), grid, dim3(TX * TY / 2), 0, s, uin, uout, f, n, T(h * h));
+    hipLaunchKernelGGL((rbgs2_skew_k<T, TX, TY, NT>), grid, dim3(NT), 0, s, uin, uout, f, n, T(h * h));
 }
 
 template void launch_rbgs2_skew<double>(int, double, const double *, const double *, double *, hipStream_t, int);

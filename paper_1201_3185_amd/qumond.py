@@ -73,7 +73,8 @@ class qumond_batch_problem_info(ctypes.Structure):
 
 
 class qumond_kernel_stats(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double)]
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double),
+                ("sweeps_per_launch", ctypes.c_int32)]
 
 
 _P, _I32, _I64, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
@@ -389,7 +390,8 @@ class Context:
     def profile_read(self) -> dict:
         st = qumond_kernel_stats()
         check(lib().qumond_profile_read(self._h, ctypes.byref(st)), "qumond_profile_read")
-        return {"launches": int(st.launches), "total_ms": float(st.total_ms), "alg_bytes": float(st.alg_bytes)}
+        return {"launches": int(st.launches), "total_ms": float(st.total_ms), "alg_bytes": float(st.alg_bytes),
+                "sweeps_per_launch": int(st.sweeps_per_launch)}
 
     def set_field(self, box: int, fld: int, src: torch.Tensor):
         _f64(src, "src")
