@@ -95,18 +95,23 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
         gi = i;
         gj = j;
     };
-    auto f_stage = [&](auto wc, int k, int c, T *fv) {
+    // the f values a stage on plane k will need, with its nodes' LDS offsets
+    // (-1: none) and, for the tile's black node, its grid column: requested two
+    // steps ahead, so the stage itself does no index arithmetic
+    auto f_stage = [&](auto wc, int k, int c, T *fv, int *cv, int *gv) {
         constexpr int W = decltype(wc)::value;
         constexpr int RW = ((TX + 2 * W) / 2 * (TY + 2 * W) + NT - 1) / NT;
         const bool kin = k >= 1 && k <= n - 2;
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
-            int cl, gi, gj;
+            int cl, gi = 0, gj = 0;
             node(wc, r, k, c, cl, gi, gj);
+            cv[r] = kin ? cl : -1;
+            if (W == 0) *gv = gi;
             fv[r] = (kin && cl >= 0) ? f[(size_t)k * nn + gi + (size_t)n * gj] : T(0);
         }
     };
-    auto stage = [&](auto wc, int k, int c, const T *fv) {
+    auto stage = [&](auto wc, int k, const T *fv, const int *cv) {
         constexpr int W = decltype(wc)::value;
         constexpr int RW = ((TX + 2 * W) / 2 * (TY + 2 * W) + NT - 1) / NT;
         if (k < 1 || k > n - 2) return;
@@ -115,8 +120,7 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
         const T *Pp = pl[(k + 1) % NS];
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
-            int cl, gi, gj;
-            node(wc, r, k, c, cl, gi, gj);
+            const int cl = cv[r];
             if (cl < 0) continue;
             const T s = P[cl - 1] + P[cl + 1] + P[cl - PX] + P[cl + PX] + Pm[cl] + Pp[cl];
             P[cl] = (s - h2 * fv[r]) * sixth;
@@ -128,18 +132,16 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
     using W3 = std::integral_constant<int, 3>;
     // the f values of step s: red of plane s (ring 3), black of s - 2 (ring 2),
     // red of s - 4 (ring 1), black of s - 6 (the tile)
-    auto f_step = [&](int s, T *fv) {
-        f_stage(W3{}, s, 0, fv);
-        f_stage(W2{}, s - 2, 1, fv + R3);
-        f_stage(W1{}, s - 4, 0, fv + R3 + R2);
-        f_stage(W0{}, s - 6, 1, fv + R3 + R2 + R1);
+    auto f_step = [&](int s, T *fv, int *cv, int *gv) {
+        f_stage(W3{}, s, 0, fv, cv, gv);
+        f_stage(W2{}, s - 2, 1, fv + R3, cv + R3, gv);
+        f_stage(W1{}, s - 4, 0, fv + R3 + R2, cv + R3 + R2, gv);
+        f_stage(W0{}, s - 6, 1, fv + R3 + R2 + R1, cv + R3 + R2 + R1, gv);
     };
     // the last stage of plane k, then the tile's pair of nodes of row j0 + tid / HX
     // goes out: the black node just updated and the red node final since step k + 4
-    auto stage_out = [&](int k, T fb) {
+    auto stage_out = [&](int k, T fb, int cl, int gi) {
         if (k < 1 || k > n - 2) return;
-        int cl, gi, gj;
-        node(W0{}, 0, k, 1, cl, gi, gj);
         if (tid >= HX * TY) return;   // threads beyond the tile's pairs
         const int br = tid / HX, q = tid % HX;
         const int j = j0 + br;
@@ -169,33 +171,39 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
         for (int q = 0; q < 3; ++q) commit(q, w[q]);
     }
     T vA[NL], vB[NL], fA[NF], fB[NF];
+    int cA[NF], cB[NF], gA = 0, gB = 0;
 #pragma unroll
     for (int r = 0; r < NL; ++r) vA[r] = vB[r] = T(0);
     if (3 <= n - 1) fetch(3, vA);
     if (4 <= n - 1) fetch(4, vB);
-    f_step(1, fA);
-    f_step(2, fB);
+    f_step(1, fA, cA, &gA);
+    f_step(2, fB, cB, &gB);
     __syncthreads();
 
     const int smax = n + 4;   // the last black update of the second sweep is plane n - 2
-    auto step = [&](int s, T *vX, T *fX) {
+    auto step = [&](int s, T *vX, T *fX, int *cX, int &gX) {
         T fc[NF];
+        int cc[NF];
 #pragma unroll
-        for (int r = 0; r < NF; ++r) fc[r] = fX[r];
-        if (s + 2 <= smax) f_step(s + 2, fX);   // the set just emptied serves step s + 2
+        for (int r = 0; r < NF; ++r) {
+            fc[r] = fX[r];
+            cc[r] = cX[r];
+        }
+        const int gc = gX;
+        if (s + 2 <= smax) f_step(s + 2, fX, cX, &gX);   // the set just emptied serves step s + 2
         if (s + 2 <= n - 1) {
             commit(s + 2, vX);   // into the slot of plane s - 8, last read in step s - 1
             if (s + 4 <= n - 1) fetch(s + 4, vX);
         }
-        stage(W3{}, s, 0, fc);
-        stage(W2{}, s - 2, 1, fc + R3);
-        stage(W1{}, s - 4, 0, fc + R3 + R2);
-        stage_out(s - 6, fc[R3 + R2 + R1]);
+        stage(W3{}, s, fc, cc);
+        stage(W2{}, s - 2, fc + R3, cc + R3);
+        stage(W1{}, s - 4, fc + R3 + R2, cc + R3 + R2);
+        stage_out(s - 6, fc[R3 + R2 + R1], cc[R3 + R2 + R1], gc);
         __syncthreads();
     };
     for (int s = 1; s <= smax; s += 2) {
-        step(s, vA, fA);
-        if (s + 1 <= smax) step(s + 1, vB, fB);
+        step(s, vA, fA, cA, gA);
+        if (s + 1 <= smax) step(s + 1, vB, fB, cB, gB);
     }
 }
 
