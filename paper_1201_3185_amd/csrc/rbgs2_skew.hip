@@ -55,14 +55,16 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
         const int i = i0 - RG + t % PX, j = j0 - RG + t / PX;
         goff[r] = (t < PL && i >= 0 && i < n && j >= 0 && j < n) ? i + n * j : -1;
     }
-    // a plane of u is requested into registers as it is (offsets clamped into
-    // the grid) and masked where it is stored, two steps later, so nothing
-    // waits for the load in between
+    // a plane of u is requested into registers as it is and masked where it
+    // is stored, two steps later, so nothing waits for the load in between; a
+    // lane with nothing to load reads the tile's corner node (lanes of all
+    // workgroups meeting on one cache line would queue on it)
+    const int idle = i0 + n * j0;
     auto fetch = [&](int k, T *vv) {
         if (ZERO) return;
         const T *src = uin + (size_t)k * nn;
 #pragma unroll
-        for (int r = 0; r < NL; ++r) vv[r] = src[max(goff[r], 0)];
+        for (int r = 0; r < NL; ++r) vv[r] = src[goff[r] >= 0 ? goff[r] : idle];
     };
     auto commit = [&](int k, const T *vv) {
         T *P = pl[k % NS];
@@ -91,9 +93,10 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
                     ok |= 1u << (2 * w + e);
             }
     }
-    // f of the pair on plane k (in range: both columns lie in the grid when either is interior)
+    // f of the pair on plane k (in range: both columns lie in the grid when
+    // either is interior; else the tile's corner pair)
     const bool fok = (ok >> 6) != 0;
-    const size_t frow = fok ? (size_t)il + (size_t)n * jp : 0;
+    const size_t frow = fok ? (size_t)il + (size_t)n * jp : (size_t)idle;
     auto f_pair = [&](int k) { return *reinterpret_cast<const pair_t *>(f + (size_t)k * nn + frow); };
     // node e of the pair on plane k takes its update from f value fv
     auto update = [&](int k, int e, T fv) {
@@ -158,10 +161,12 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
         }
         __syncthreads();
     };
-    for (int s = 1; s <= smax; s += 2) {
+    int s = 1;
+    for (; s + 1 <= smax; s += 2) {   // whole pairs of steps: no branch inside the loop
         step(s, vA, pA);
-        if (s + 1 <= smax) step(s + 1, vB, pB);
+        step(s + 1, vB, pB);
     }
+    if (s <= smax) step(s, vA, pA);
 }
 
 }  // namespace
