@@ -87,8 +87,8 @@ def smoother_traffic(key, sweeps):
 
 def single_sweep_roofline(Q, torch, n=513, reps=15):
     """The single plain sweep at n^3 with the loaded launch shape, timed on its
-    own (hipEvents around each launch, median of reps): where the multigrid
-    fuses the pre-smoothing pair, it still runs one of these per V-cycle."""
+    own (hipEvents around each launch, median of reps): the kernel of the
+    levels that sweep once per launch, reported beside the two-sweep launch."""
     h = 1.0 / (n - 1)
     f = torch.ones((n,) * 3, dtype=torch.float64, device="cuda")
     u = [torch.full_like(f, 0.5), torch.full_like(f, 0.5)]
@@ -581,8 +581,9 @@ def main():
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
     sweeps = st.get("sweeps_per_launch", 1) or 1
     if sweeps == 2:
-        kern = ("red-black smoother, finest (513^3) level: the skewed two-sweep launches (rbgs2_skew_k, the "
-                "pre-smoothing pair of each V-cycle in one pass: 24 B per node per launch of two sweeps), FP64")
+        kern = ("red-black smoother, finest (513^3) level: the skewed two-sweep launches (rbgs2_skew_k: each "
+                "smoothing pair of a V-cycle in one pass, the coarse-grid correction added by a launch of its own "
+                "before the post-smoothing pair; 24 B per node per launch of two sweeps), FP64")
     else:
         kern = ("red-black smoother, finest (513^3) level, plain sweeps (one per launch; the first "
                 "post-smoothing sweep, which also applies the coarse-grid correction, is left out), FP64 "
