@@ -395,11 +395,7 @@ hipError_t tune_class(qumond_batch *B, Class &C, int reps)
                         qm::launch_prolong_add<float>(nc, uc, a, s, C.P);
                         c = nullptr;
                     }
-                    if (fz && c && C.shapes.fused[l].variant == qm::kSkewVariant) {
-                        // the skewed two-sweep march takes no correction: the correcting sweep, then a plain one
-                        qm::launch_rbgs_shape<float>(n, h, f, a, b, C.shapes.corr[l], s, C.P, c);
-                        qm::launch_rbgs_shape<float>(n, h, f, b, a, C.shapes.single[l], s, C.P);
-                    } else if (fz) {
+                    if (fz) {
                         qm::launch_rbgs2_shape<float>(n, h, f, a, b, c, C.shapes.fused[l], s, C.P);
                     } else {
                         qm::launch_rbgs_shape<float>(n, h, f, a, b, c ? C.shapes.corr[l] : C.shapes.single[l], s, C.P, c);

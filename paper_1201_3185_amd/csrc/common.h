@@ -169,9 +169,10 @@ template <typename T> SmootherShape &rbgs2_shape(int n);
 // ---- rbgs2_skew.hip
 // Two sweeps uin -> uout in one whole-column march with the four half-sweeps
 // skewed two planes apart (same bits as two single sweeps); uin null is a zero
-// iterate.  No coarse-grid correction: launch_rbgs2_shape applies one with the
-// 64x16 two-sweep march instead.
-template <typename T> void launch_rbgs2_skew(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s, int nb);
+// iterate; with uc != NULL the correction u += P uc (uc on the next coarser
+// level) is applied first, in the same launch (same bits as a prolong-add).
+template <typename T> void launch_rbgs2_skew(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s, int nb,
+                                            const T *uc = nullptr);
 // Whether the multigrid uses the fused kernel on a level of n points per side
 // (set by the autotuner from measured times; n <= 65 by default).
 template <typename T> int &use_fused(int n);

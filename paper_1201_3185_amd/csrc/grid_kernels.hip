@@ -1294,10 +1294,7 @@ void launch_rbgs2_shape(int n, double h, const T *f, const T *uin, T *uout, cons
     case 5: rbgs2_deep_launch<T, 64, 16>(n, h, f, uin, uout, kc, uc, nb, s); break;
     case 6: rbgs2_deep_launch<T, 64, 8>(n, h, f, uin, uout, kc, uc, nb, s); break;
     case 7: rbgs2_deep_launch<T, 32, 16>(n, h, f, uin, uout, kc, uc, nb, s); break;
-    case kSkewVariant:   // whole columns; with a correction, the 64x16 two-sweep march over whole columns
-        if (uc) rbgs2_deep_launch<T, 64, 16>(n, h, f, uin, uout, n, uc, nb, s);
-        else launch_rbgs2_skew<T>(n, h, f, uin, uout, s, nb);
-        break;
+    case kSkewVariant: launch_rbgs2_skew<T>(n, h, f, uin, uout, s, nb, uc); break;   // whole columns
     default: rbgs2_launch<T, 64, 4>(n, h, f, uin, uout, kc, uc, nb, s); break;
     }
 }

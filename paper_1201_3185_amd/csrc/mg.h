@@ -246,8 +246,7 @@ struct Multigrid {
         while (ns > 0) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             const SmootherShape shf = fuse ? (shapes ? shapes->fused[l] : rbgs2_shape<T>(v.n)) : SmootherShape{0, 0};
-            // the skewed two-sweep march takes no correction: with one, the correcting sweep goes first
-            const bool two = ns >= 2 && fuse && !(uc && shf.variant == kSkewVariant);
+            const bool two = ns >= 2 && fuse;
             time_begin(&e0, &e1, (zi ? 2.0 : 3.0) * sizeof(T) * pts * nb, v.n, uc != nullptr, two ? 2 : 1, fuse);
             const T *uin = zi ? nullptr : v.u[v.cur];
             zi = false;

@@ -23,10 +23,16 @@ namespace qm {
 
 namespace {
 
-// ZERO: the iterate is zero (uin is not read)
-template <typename T, int TX, int TY, int NT, bool ZERO>
+// ZERO: the iterate is zero (uin is not read).  PROLONG: the coarse-grid
+// correction u += P uc (uc on the grid of nc = (n + 1) / 2 points) is added to
+// every interior node as its plane is stored to LDS, with the trilinear
+// expression of the prolong-add kernel evaluated in the same order (along x,
+// then y, then z) on coarse planes staged in LDS, so the result is that of a
+// prolong-add launch followed by the two sweeps, bit for bit.
+template <typename T, int TX, int TY, int NT, bool ZERO, bool PROLONG>
 __global__ void __launch_bounds__(NT)
-rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2)
+rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restrict__ f, int n, T h2,
+             const T *__restrict__ uc, int nc)
 {
 #pragma clang fp contract(off)
     typedef T pair_t __attribute__((ext_vector_type(2), aligned(sizeof(T))));
@@ -36,7 +42,11 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
     constexpr int NL = (PL + NT - 1) / NT;
     constexpr int HP = PX / 2, NP = HP * (TY + 6);         // node pairs: four-node ring in x, three in y
     static_assert(TX % 2 == 0 && NP <= NT, "at most one pair of nodes per thread");
+    // coarse footprint of the LDS region (tile origins are odd): TX / 2 + 5 by TY / 2 + 5 coarse nodes
+    constexpr int CPX = TX / 2 + 5, CPY = TY / 2 + 5, CPL = CPX * CPY;
+    static_assert(!PROLONG || CPL <= NT, "one coarse node per thread");
     __shared__ T pl[NS][PL];
+    __shared__ T cpl[PROLONG ? 3 : 1][PROLONG ? CPL : 1];   // coarse planes c in slot c % 3
     const T sixth = T(1) / T(6);
     const int tid = threadIdx.x;
     const unsigned tl = xcd_tile(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
@@ -47,6 +57,7 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
     if (!ZERO) uin += (size_t)pb * nn * n;
     uout += (size_t)pb * nn * n;
     f += (size_t)pb * nn * n;
+    if (PROLONG) uc += (size_t)pb * nc * nc * nc;
 
     int goff[NL];
 #pragma unroll
@@ -66,12 +77,59 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
 #pragma unroll
         for (int r = 0; r < NL; ++r) vv[r] = src[goff[r] >= 0 ? goff[r] : idle];
     };
-    auto commit = [&](int k, const T *vv) {
-        T *P = pl[k % NS];
+    // The correction's coarse data: this thread's coarse node of the footprint
+    // (coff, or -1; a lane with nothing to load reads the footprint's corner)
+    // and, per LDS node r of a plane that is interior in x and y, the offset of
+    // its lower coarse neighbour in the footprint with the parities of i and j
+    // in bits 16 and 17 (else -1).
+    const int ci0 = (i0 - RG) >> 1, cj0 = (j0 - RG) >> 1;
+    int coff = -1, cidle = 0, cnb[NL];
+    if constexpr (PROLONG) {
+        const int I = ci0 + tid % CPX, J = cj0 + tid / CPX;
+        coff = (tid < CPL && I >= 0 && I < nc && J >= 0 && J < nc) ? I + nc * J : -1;
+        cidle = max(ci0, 0) + nc * max(cj0, 0);
 #pragma unroll
         for (int r = 0; r < NL; ++r) {
             const int t = tid + r * NT;
-            if (t < PL) P[t] = (!ZERO && goff[r] >= 0) ? vv[r] : T(0);
+            const int i = i0 - RG + t % PX, j = j0 - RG + t / PX;
+            cnb[r] = (t < PL && i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2)
+                         ? ((i >> 1) - ci0) + CPX * ((j >> 1) - cj0) + ((i & 1) << 16) + ((j & 1) << 17)
+                         : -1;
+        }
+    }
+    T cv = T(0);
+    auto fetch_c = [&](int c) {   // coarse plane c (clamped into the grid) into cv
+        if constexpr (PROLONG) cv = uc[(size_t)min(c, nc - 1) * nc * nc + (coff >= 0 ? coff : cidle)];
+    };
+    auto store_c = [&](int c) {   // ... into its LDS slot
+        if constexpr (PROLONG) {
+            if (c <= nc - 1 && tid < CPL) cpl[c % 3][tid] = coff >= 0 ? cv : T(0);
+        }
+    };
+    // the correction at a node of plane k (1 <= k <= n - 2) from its packed coarse offset
+    auto corr = [&](int cw, int k) {
+        const int o = cw & 0xffff, di = (cw >> 16) & 1, dj = (cw >> 17) & 1;
+        const T wia = di ? T(0.5) : T(1), wib = di ? T(0.5) : T(0);
+        const T wja = dj ? T(0.5) : T(1), wjb = dj ? T(0.5) : T(0);
+        const T wka = (k & 1) ? T(0.5) : T(1), wkb = (k & 1) ? T(0.5) : T(0);
+        const T *Ca = cpl[(k >> 1) % 3], *Cb = cpl[((k + 1) >> 1) % 3];
+        const int oj = o + dj * CPX;
+        const T xa = wia * Ca[o] + wib * Ca[o + di];
+        const T xb = wia * Ca[oj] + wib * Ca[oj + di];
+        const T xc = wia * Cb[o] + wib * Cb[o + di];
+        const T xd = wia * Cb[oj] + wib * Cb[oj + di];
+        return wka * (wja * xa + wjb * xb) + wkb * (wja * xc + wjb * xd);
+    };
+    auto commit = [&](int k, const T *vv) {
+        T *P = pl[k % NS];
+        const bool kin = k >= 1 && k <= n - 2;
+#pragma unroll
+        for (int r = 0; r < NL; ++r) {
+            const int t = tid + r * NT;
+            if (t >= PL) continue;
+            T x = (!ZERO && goff[r] >= 0) ? vv[r] : T(0);
+            if (PROLONG && kin && cnb[r] >= 0) x += corr(cnb[r], k);
+            P[t] = x;
         }
     };
 
@@ -110,14 +168,24 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
         return v;
     };
 
-    // warm-up: planes 0, 1, 2 in LDS; planes 3, 4 and the f pairs of planes 1, 2 in flight
+    // warm-up: planes 0, 1, 2 in LDS (with the correction: coarse planes 0, 1, 2
+    // first); planes 3, 4, the f pairs of planes 1, 2 and coarse plane 3 in flight
     {
         T w[3][NL];
 #pragma unroll
         for (int z = 0; z < 3; ++z) fetch(z, w[z]);
+        if constexpr (PROLONG) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                fetch_c(c);
+                store_c(c);
+            }
+            __syncthreads();
+        }
 #pragma unroll
         for (int z = 0; z < 3; ++z) commit(z, w[z]);
     }
+    fetch_c(3);
     T vA[NL], vB[NL];
 #pragma unroll
     for (int r = 0; r < NL; ++r) vA[r] = vB[r] = T(0);
@@ -135,7 +203,10 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
     __syncthreads();
 
     const int smax = n + 4;   // the last black update of the second sweep is plane n - 2
-    auto step = [&](int s, T *vX, pair_t &pX) {
+    // even: s is even (the loop's second step of a pair); with the correction,
+    // an even step s stores coarse plane (s + 4) / 2, first read by the commit
+    // of fine plane s + 3 in step s + 1, and requests plane (s + 6) / 2
+    auto step = [&](int s, T *vX, pair_t &pX, bool even) {
         const int er = (il + jp + s) & 1;   // the red node of the pair on planes s, s - 4
         const int eb = er ^ 1;              // the black one on planes s - 2, s - 6
 #pragma unroll
@@ -145,6 +216,10 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
         fr[0] = er ? pX.y : pX.x;
         fb[0] = er ? pX.x : pX.y;
         if (s + 2 <= n - 1) commit(s + 2, vX);   // into the slot of plane s - 8, last read in step s - 1
+        if (PROLONG && even) {   // into the slot of coarse plane s / 2 - 1, last read in step s - 3
+            store_c((s + 4) / 2);
+            fetch_c((s + 6) / 2);
+        }
         // the next requests, their planes clamped into the grid (what the last
         // steps fetch beyond plane n - 1, or n - 2 for f, is never used)
         fetch(min(s + 4, n - 1), vX);
@@ -163,27 +238,38 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
     };
     int s = 1;
     for (; s + 1 <= smax; s += 2) {   // whole pairs of steps: no branch inside the loop
-        step(s, vA, pA);
-        step(s + 1, vB, pB);
+        step(s, vA, pA, false);
+        step(s + 1, vB, pB, true);
     }
-    if (s <= smax) step(s, vA, pA);
+    if (s <= smax) step(s, vA, pA, false);
 }
 
 }  // namespace
 
 template <typename T>
-void launch_rbgs2_skew(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s, int nb)
+void launch_rbgs2_skew(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s, int nb, const T *uc)
 {
     constexpr int TX = 64, TY = 16, NT = 1024;   // two threads per pair of tile nodes
     const int m = n - 2;
     const dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, nb);
-    if (uin)
-        hipLaunchKernelGGL((rbgs2_skew_k<T, TX, TY, NT, false>), grid, dim3(NT), 0, s, uin, uout, f, n, T(h * h));
+    const int nc = (n + 1) / 2;
+    if (uc && uin)
+        hipLaunchKernelGGL((rbgs2_skew_k<T, TX, TY, NT, false, true>), grid, dim3(NT), 0, s, uin, uout, f, n, T(h * h),
+                           uc, nc);
+    else if (uc)
+        hipLaunchKernelGGL((rbgs2_skew_k<T, TX, TY, NT, true, true>), grid, dim3(NT), 0, s, uin, uout, f, n, T(h * h),
+                           uc, nc);
+    else if (uin)
+        hipLaunchKernelGGL((rbgs2_skew_k<T, TX, TY, NT, false, false>), grid, dim3(NT), 0, s, uin, uout, f, n, T(h * h),
+                           uc, nc);
     else
-        hipLaunchKernelGGL((rbgs2_skew_k<T, TX, TY, NT, true>), grid, dim3(NT), 0, s, uin, uout, f, n, T(h * h));
+        hipLaunchKernelGGL((rbgs2_skew_k<T, TX, TY, NT, true, false>), grid, dim3(NT), 0, s, uin, uout, f, n, T(h * h),
+                           uc, nc);
 }
 
-template void launch_rbgs2_skew<double>(int, double, const double *, const double *, double *, hipStream_t, int);
-template void launch_rbgs2_skew<float>(int, double, const float *, const float *, float *, hipStream_t, int);
+template void launch_rbgs2_skew<double>(int, double, const double *, const double *, double *, hipStream_t, int,
+                                        const double *);
+template void launch_rbgs2_skew<float>(int, double, const float *, const float *, float *, hipStream_t, int,
+                                       const float *);
 
 }  // namespace qm

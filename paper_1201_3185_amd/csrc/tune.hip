@@ -259,12 +259,7 @@ qumond_status tune_split(int n, int reps, hipStream_t s, double us[2])
                 qm::launch_prolong_add<T>(nc, uc, a, s);
                 c = nullptr;
             }
-            if (fz && c && qm::rbgs2_shape<T>(n).variant == qm::kSkewVariant) {
-                // the skewed two-sweep march takes no correction: the multigrid runs
-                // the correcting sweep and a plain sweep instead
-                qm::launch_rbgs<T>(n, h, f, a, b, s, 1, c);
-                qm::launch_rbgs<T>(n, h, f, b, a, s, 1, nullptr);
-            } else if (fz) {
+            if (fz) {
                 qm::launch_rbgs2<T>(n, h, f, a, b, c, s);
             } else {
                 qm::launch_rbgs<T>(n, h, f, a, b, s, 1, c);

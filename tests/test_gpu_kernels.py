@@ -537,7 +537,8 @@ def test_every_fused_shape_is_bitwise_identical(n):
 def test_skewed_double_sweep_full_size(n):
     """The skewed two-sweep march (whole 64x16 columns, the four half-sweeps two
     planes apart) equals two single sweeps bit for bit at full size, from a
-    given iterate and from a zero one."""
+    given iterate and from a zero one, and with the coarse-grid correction
+    applied in the same launch it equals a prolong-add and then two sweeps."""
     h = 1.0 / (n - 1)
     g = torch.Generator(device="cuda")
     g.manual_seed(n)
@@ -562,6 +563,18 @@ def test_skewed_double_sweep_full_size(n):
         out[0] = out[-1] = out[:, 0] = out[:, -1] = out[:, :, 0] = out[:, :, -1] = 0.0
         Q.k_rbgs_double_sweep(f, None, out, h)
         assert torch.equal(out, zb)
+        nc = (n + 1) // 2
+        uc = torch.randn((nc,) * 3, dtype=torch.float64, device="cuda", generator=g)
+        uc[0] = uc[-1] = uc[:, 0] = uc[:, -1] = uc[:, :, 0] = uc[:, :, -1] = 0.0
+        p = u.clone()
+        Q.k_prolong_add(uc, p)
+        pa, pb = p.clone(), p.clone()
+        Q.k_rbgs_sweep(f, p, pa, h)
+        Q.k_rbgs_sweep(f, pa, pb, h)
+        out.fill_(5.0)
+        out[0] = out[-1] = out[:, 0] = out[:, -1] = out[:, :, 0] = out[:, :, -1] = 0.0
+        Q.k_rbgs_double_sweep(f, u, out, h, uc=uc)
+        assert torch.equal(out, pb), "prolong"
     finally:
         Q.tune_set_fused(n, *before)
 
