@@ -39,12 +39,13 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
     constexpr int RG = 4;                                  // ring of the region held in LDS
     constexpr int PX = TX + 2 * RG, PY = TY + 2 * RG, PL = PX * PY;
     constexpr int NS = 10;                                 // planes s - 7 .. s + 2
-    constexpr int NL = (PL + NT - 1) / NT;
+    constexpr int HPX = PX / 2, NPL = HPX * PY;            // x-pairs of nodes of an LDS plane
     constexpr int HP = PX / 2, NP = HP * (TY + 6);         // node pairs: four-node ring in x, three in y
     static_assert(TX % 2 == 0 && NP <= NT, "at most one pair of nodes per thread");
     // coarse footprint of the LDS region (tile origins are odd): TX / 2 + 5 by TY / 2 + 5 coarse nodes
     constexpr int CPX = TX / 2 + 5, CPY = TY / 2 + 5, CPL = CPX * CPY;
     static_assert(!PROLONG || CPL <= NT, "one coarse node per thread");
+    static_assert(NPL <= NT, "one pair of an LDS plane per thread");
     __shared__ T pl[NS][PL];
     __shared__ T cpl[PROLONG ? 3 : 1][PROLONG ? CPL : 1];   // coarse planes c in slot c % 3
     const T sixth = T(1) / T(6);
@@ -59,40 +60,39 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
     f += (size_t)pb * nn * n;
     if (PROLONG) uc += (size_t)pb * nc * nc * nc;
 
-    int goff[NL];
-#pragma unroll
-    for (int r = 0; r < NL; ++r) {
-        const int t = tid + r * NT;
-        const int i = i0 - RG + t % PX, j = j0 - RG + t / PX;
-        goff[r] = (t < PL && i >= 0 && i < n && j >= 0 && j < n) ? i + n * j : -1;
-    }
-    // a plane of u is requested into registers as it is and masked where it
-    // is stored, two steps later, so nothing waits for the load in between; a
-    // lane with nothing to load reads the tile's corner node (lanes of all
-    // workgroups meeting on one cache line would queue on it)
+    // A plane of u arrives as one x-pair of nodes per thread (iq, iq + 1 of
+    // row jq; LDS offset lq): one 16-byte load from a base clamped into the
+    // grid's row (node iq + e sits at element e + sh of the load), requested
+    // into registers as it is and masked where it is stored, two steps later,
+    // so nothing waits for the load in between; a lane with nothing to load
+    // reads the tile's corner pair (lanes of all workgroups meeting on one
+    // cache line would queue on it).
+    const int qa = tid % HPX, qb = tid / HPX;
+    const int iq = i0 - RG + 2 * qa, jq = j0 - RG + qb, lq = qb * PX + 2 * qa;
+    const bool qrow = tid < NPL && jq >= 0 && jq < n;
+    const int sh = iq - min(max(iq, 0), n - 2);
+    const bool in0 = qrow && iq >= 0 && iq <= n - 1, in1 = qrow && iq + 1 >= 0 && iq + 1 <= n - 1;
     const int idle = i0 + n * j0;
-    auto fetch = [&](int k, T *vv) {
+    const int qoff = qrow ? min(max(iq, 0), n - 2) + n * jq : idle;
+    auto fetch = [&](int k, pair_t &vv) {
         if (ZERO) return;
-        const T *src = uin + (size_t)k * nn;
-#pragma unroll
-        for (int r = 0; r < NL; ++r) vv[r] = src[goff[r] >= 0 ? goff[r] : idle];
+        vv = *reinterpret_cast<const pair_t *>(uin + (size_t)k * nn + qoff);
     };
     // The correction's coarse data: this thread's coarse node of the footprint
     // (coff, or -1; a lane with nothing to load reads the footprint's corner)
-    // and, per LDS node r of a plane that is interior in x and y, the offset of
-    // its lower coarse neighbour in the footprint with the parities of i and j
-    // in bits 16 and 17 (else -1).
+    // and, per node e of the thread's pair that is interior in x and y, the
+    // offset of its lower coarse neighbour in the footprint with the parities
+    // of i and j in bits 16 and 17 (else -1).
     const int ci0 = (i0 - RG) >> 1, cj0 = (j0 - RG) >> 1;
-    int coff = -1, cidle = 0, cnb[NL];
+    int coff = -1, cidle = 0, cnb[2] = {-1, -1};
     if constexpr (PROLONG) {
         const int I = ci0 + tid % CPX, J = cj0 + tid / CPX;
         coff = (tid < CPL && I >= 0 && I < nc && J >= 0 && J < nc) ? I + nc * J : -1;
         cidle = max(ci0, 0) + nc * max(cj0, 0);
 #pragma unroll
-        for (int r = 0; r < NL; ++r) {
-            const int t = tid + r * NT;
-            const int i = i0 - RG + t % PX, j = j0 - RG + t / PX;
-            cnb[r] = (t < PL && i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2)
+        for (int e = 0; e < 2; ++e) {
+            const int i = iq + e, j = jq;
+            cnb[e] = (tid < NPL && i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2)
                          ? ((i >> 1) - ci0) + CPX * ((j >> 1) - cj0) + ((i & 1) << 16) + ((j & 1) << 17)
                          : -1;
         }
@@ -120,17 +120,25 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
         const T xd = wia * Cb[oj] + wib * Cb[oj + di];
         return wka * (wja * xa + wjb * xb) + wkb * (wja * xc + wjb * xd);
     };
-    auto commit = [&](int k, const T *vv) {
-        T *P = pl[k % NS];
-        const bool kin = k >= 1 && k <= n - 2;
-#pragma unroll
-        for (int r = 0; r < NL; ++r) {
-            const int t = tid + r * NT;
-            if (t >= PL) continue;
-            T x = (!ZERO && goff[r] >= 0) ? vv[r] : T(0);
-            if (PROLONG && kin && cnb[r] >= 0) x += corr(cnb[r], k);
-            P[t] = x;
+    // With the correction only the black node of a pair takes it: a red
+    // node's own value is replaced by the first sweep's red update before any
+    // update reads it, and red nodes of the outer ring are not read at all.
+    auto commit = [&](int k, const pair_t &vv) {
+        if (tid >= NPL) return;
+        T x0 = (!ZERO && in0) ? (sh == 0 ? vv.x : vv.y) : T(0);
+        T x1 = (!ZERO && in1) ? (sh == 0 ? vv.y : vv.x) : T(0);
+        if (PROLONG && k >= 1 && k <= n - 2) {
+            const int eb = (iq + jq + k + 1) & 1;   // the pair's black node
+            const int cw = eb ? cnb[1] : cnb[0];
+            if (cw >= 0) {
+                const T c = corr(cw, k);
+                if (eb) x1 += c;
+                else x0 += c;
+            }
         }
+        T *P = pl[k % NS] + lq;
+        P[0] = x0;
+        P[1] = x1;
     };
 
     // This thread's pair of nodes: grid columns il, il + 1 of row jp, LDS
@@ -171,7 +179,7 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
     // warm-up: planes 0, 1, 2 in LDS (with the correction: coarse planes 0, 1, 2
     // first); planes 3, 4, the f pairs of planes 1, 2 and coarse plane 3 in flight
     {
-        T w[3][NL];
+        pair_t w[3] = {};
 #pragma unroll
         for (int z = 0; z < 3; ++z) fetch(z, w[z]);
         if constexpr (PROLONG) {
@@ -186,9 +194,7 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
         for (int z = 0; z < 3; ++z) commit(z, w[z]);
     }
     fetch_c(3);
-    T vA[NL], vB[NL];
-#pragma unroll
-    for (int r = 0; r < NL; ++r) vA[r] = vB[r] = T(0);
+    pair_t vA = {T(0), T(0)}, vB = {T(0), T(0)};
     if (3 <= n - 1) fetch(3, vA);
     if (4 <= n - 1) fetch(4, vB);
     pair_t pA = {T(0), T(0)}, pB = {T(0), T(0)};
@@ -206,7 +212,7 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
     // even: s is even (the loop's second step of a pair); with the correction,
     // an even step s stores coarse plane (s + 4) / 2, first read by the commit
     // of fine plane s + 3 in step s + 1, and requests plane (s + 6) / 2
-    auto step = [&](int s, T *vX, pair_t &pX, bool even) {
+    auto step = [&](int s, pair_t &vX, pair_t &pX, bool even) {
         const int er = (il + jp + s) & 1;   // the red node of the pair on planes s, s - 4
         const int eb = er ^ 1;              // the black one on planes s - 2, s - 6
 #pragma unroll
