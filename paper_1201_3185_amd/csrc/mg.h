@@ -229,19 +229,25 @@ struct Multigrid {
     {
         Level<T> &v = lv[l];
         const double pts = (double)v.n * v.n * v.n;
+        const bool fuse = fused && (shapes ? shapes->use_fused[l] != 0 : use_fused<T>(v.n) != 0);
+        bool zs = false;   // the first fused launch reads no iterate
         if (zero_start && l == J && ns > 0 && !uc) {   // the iterate is zero: first sweep without reading it
-            const SmootherShape sh = shapes ? shapes->single[l] : rbgs_shape<T>(v.n);
-            launch_rbgs_shape<T>(v.n, v.h, v.f, nullptr, v.u[1 - v.cur], sh, s, nb);
-            v.cur ^= 1;
-            --ns;
             zero_start = false;
+            if (fuse && ns >= 2) {
+                zs = true;
+            } else {
+                const SmootherShape sh = shapes ? shapes->single[l] : rbgs_shape<T>(v.n);
+                launch_rbgs_shape<T>(v.n, v.h, v.f, nullptr, v.u[1 - v.cur], sh, s, nb);
+                v.cur ^= 1;
+                --ns;
+            }
         }
         if (uc && (ns == 0 || (shapes ? shapes->split[l] : split_prolong<T>(v.n)) != 0)) {
             launch_prolong_add<T>(lv[l - 1].n, uc, v.u[v.cur], s, nb);
             uc = nullptr;
         }
-        const bool fuse = fused && (shapes ? shapes->use_fused[l] != 0 : use_fused<T>(v.n) != 0);
-        bool zi = zin[l] && !uc && ns > 0;   // a zero correction the restriction left unwritten
+        // a zero iterate, or a zero correction the restriction left unwritten
+        bool zi = (zin[l] || zs) && !uc && ns > 0;
         zin[l] = false;
         while (ns > 0) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
