@@ -48,9 +48,10 @@ qumond_status qumond_tune_get_corr(int32_t n, int32_t fp32, int32_t *variant, in
 /* The same for the fused two-sweep smoother (variant 0 = 32x8, 1 = 64x4
  * z-march, 2 = 8^3, 3 = 4^3, 4 = 6^3 bricks, 5 = 64x16, 6 = 64x8, 7 = 32x16
  * z-march with one thread per pair of tile nodes and loads two steps
- * ahead, 8 = 64x16 whole-column march with the four half-sweeps skewed two
- * planes apart, which applies the coarse-grid correction in the same launch
- * from coarse planes staged in LDS; 8 takes no z-chunk). */
+ * ahead, 8 = 64x16 and 9 = 32x8 whole-column marches with the four
+ * half-sweeps skewed two planes apart, which apply the coarse-grid correction
+ * in the same launch from coarse planes staged in LDS; 8 and 9 take no
+ * z-chunk). */
 qumond_status qumond_tune_set_fused(int32_t n, int32_t fp32, int32_t variant, int32_t kchunk);
 qumond_status qumond_tune_get_fused(int32_t n, int32_t fp32, int32_t *variant, int32_t *kchunk);
 

@@ -136,12 +136,16 @@ constexpr int kRrVariants = 12;   // residual restriction: gather, 8x8x4 LDS til
                                   // columns loading three / four steps ahead
 // bricks hold their whole block in LDS and take no z-chunk
 inline bool is_brick_variant(int v, bool fused) { return fused ? (v >= 2 && v <= 4) : (v == 5 || v == 9 || v == 10); }
-constexpr int kFusedVariants = 9;   // two sweeps: 0: 32x8, 1: 64x4 z-march, 2: 8^3, 3: 4^3, 4: 6^3 bricks,
+constexpr int kFusedVariants = 10;  // two sweeps: 0: 32x8, 1: 64x4 z-march, 2: 8^3, 3: 4^3, 4: 6^3 bricks,
                                     // 5: 64x16, 6: 64x8, 7: 32x16 pair z-march with loads two steps ahead,
-                                    // 8: 64x16 whole columns with the four half-sweeps skewed (rbgs2_skew.hip)
-constexpr int kSkewVariant = 8;
-// shapes that take no z-chunk: the bricks, and the skewed two-sweep march (whole columns)
-inline bool takes_no_chunk(int v, bool fused) { return is_brick_variant(v, fused) || (fused && v == kSkewVariant); }
+                                    // 8: 64x16, 9: 32x8 whole columns with the four half-sweeps skewed
+                                    // (rbgs2_skew.hip)
+constexpr int kSkewVariant = 8, kSkew32Variant = 9;
+// shapes that take no z-chunk: the bricks, and the skewed two-sweep marches (whole columns)
+inline bool takes_no_chunk(int v, bool fused)
+{
+    return is_brick_variant(v, fused) || (fused && (v == kSkewVariant || v == kSkew32Variant));
+}
 // Every grid launcher takes nb, the number of problems stored back to back
 // (problem p of a level with n points per side at offset p n^3); nb = 1 is the
 // single-problem case.
@@ -171,8 +175,9 @@ template <typename T> SmootherShape &rbgs2_shape(int n);
 // skewed two planes apart (same bits as two single sweeps); uin null is a zero
 // iterate; with uc != NULL the correction u += P uc (uc on the next coarser
 // level) is applied first, in the same launch (same bits as a prolong-add).
+// tile 0: 64x16 columns (1024 threads), 1: 32x8 columns (320 threads).
 template <typename T> void launch_rbgs2_skew(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s, int nb,
-                                            const T *uc = nullptr);
+                                            const T *uc = nullptr, int tile = 0);
 // Whether the multigrid uses the fused kernel on a level of n points per side
 // (set by the autotuner from measured times; n <= 65 by default).
 template <typename T> int &use_fused(int n);

@@ -1294,7 +1294,8 @@ void launch_rbgs2_shape(int n, double h, const T *f, const T *uin, T *uout, cons
     case 5: rbgs2_deep_launch<T, 64, 16>(n, h, f, uin, uout, kc, uc, nb, s); break;
     case 6: rbgs2_deep_launch<T, 64, 8>(n, h, f, uin, uout, kc, uc, nb, s); break;
     case 7: rbgs2_deep_launch<T, 32, 16>(n, h, f, uin, uout, kc, uc, nb, s); break;
-    case kSkewVariant: launch_rbgs2_skew<T>(n, h, f, uin, uout, s, nb, uc); break;   // whole columns
+    case kSkewVariant: launch_rbgs2_skew<T>(n, h, f, uin, uout, s, nb, uc, 0); break;     // whole columns
+    case kSkew32Variant: launch_rbgs2_skew<T>(n, h, f, uin, uout, s, nb, uc, 1); break;
     default: rbgs2_launch<T, 64, 4>(n, h, f, uin, uout, kc, uc, nb, s); break;
     }
 }

@@ -252,10 +252,9 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
 
 }  // namespace
 
-template <typename T>
-void launch_rbgs2_skew(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s, int nb, const T *uc)
+template <typename T, int TX, int TY, int NT>
+static void skew_launch(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s, int nb, const T *uc)
 {
-    constexpr int TX = 64, TY = 16, NT = 1024;   // two threads per pair of tile nodes
     const int m = n - 2;
     const dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, nb);
     const int nc = (n + 1) / 2;
@@ -273,9 +272,16 @@ void launch_rbgs2_skew(int n, double h, const T *f, const T *uin, T *uout, hipSt
                            uc, nc);
 }
 
+template <typename T>
+void launch_rbgs2_skew(int n, double h, const T *f, const T *uin, T *uout, hipStream_t s, int nb, const T *uc, int tile)
+{
+    if (tile == 1) skew_launch<T, 32, 8, 320>(n, h, f, uin, uout, s, nb, uc);   // 55 KB of LDS: two workgroups per CU
+    else skew_launch<T, 64, 16, 1024>(n, h, f, uin, uout, s, nb, uc);          // 146 KB: one per CU
+}
+
 template void launch_rbgs2_skew<double>(int, double, const double *, const double *, double *, hipStream_t, int,
-                                        const double *);
+                                        const double *, int);
 template void launch_rbgs2_skew<float>(int, double, const float *, const float *, float *, hipStream_t, int,
-                                       const float *);
+                                       const float *, int);
 
 }  // namespace qm

@@ -490,7 +490,7 @@ SMOOTHER_VARIANTS = {0: (32, 8), 1: (64, 4), 2: (64, 8), 3: (128, 4), 4: (32, 16
                      11: "pairs32x16", 12: "pairs32x8", 13: "pairs64x16_deep", 14: "pairs128x8_deep",
                      15: "pairs64x32_deep"}
 FUSED_VARIANTS = {0: (32, 8), 1: (64, 4), 2: "brick8", 3: "brick4", 4: "brick6", 5: "pairs64x16_deep",
-                  6: "pairs64x8_deep", 7: "pairs32x16_deep", 8: "skew64x16"}
+                  6: "pairs64x8_deep", 7: "pairs32x16_deep", 8: "skew64x16", 9: "skew32x8"}
 
 
 def tune_set(n, variant, kchunk, fp32=False):

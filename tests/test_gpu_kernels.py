@@ -518,7 +518,7 @@ def test_every_fused_shape_is_bitwise_identical(n):
     before = Q.tune_get_fused(n)
     try:
         for v in Q.FUSED_VARIANTS:
-            for kc in ((0,) if v in (2, 3, 4, 8) else (4, 16, 0)):
+            for kc in ((0,) if v in (2, 3, 4, 8, 9) else (4, 16, 0)):
                 Q.tune_set_fused(n, v, kc)
                 out = dev(u)
                 Q.k_rbgs_double_sweep(fd, dev(u), out, h)
@@ -554,27 +554,28 @@ def test_skewed_double_sweep_full_size(n):
     Q.k_rbgs_sweep(f, za, zb, h)
     before = Q.tune_get_fused(n)
     try:
-        Q.tune_set_fused(n, 8, 0)
-        out = torch.full_like(u, 3.0)
-        out[0] = out[-1] = out[:, 0] = out[:, -1] = out[:, :, 0] = out[:, :, -1] = 0.0
-        Q.k_rbgs_double_sweep(f, u, out, h)
-        assert torch.equal(out, b)
-        out.fill_(-2.0)
-        out[0] = out[-1] = out[:, 0] = out[:, -1] = out[:, :, 0] = out[:, :, -1] = 0.0
-        Q.k_rbgs_double_sweep(f, None, out, h)
-        assert torch.equal(out, zb)
-        nc = (n + 1) // 2
-        uc = torch.randn((nc,) * 3, dtype=torch.float64, device="cuda", generator=g)
-        uc[0] = uc[-1] = uc[:, 0] = uc[:, -1] = uc[:, :, 0] = uc[:, :, -1] = 0.0
-        p = u.clone()
-        Q.k_prolong_add(uc, p)
-        pa, pb = p.clone(), p.clone()
-        Q.k_rbgs_sweep(f, p, pa, h)
-        Q.k_rbgs_sweep(f, pa, pb, h)
-        out.fill_(5.0)
-        out[0] = out[-1] = out[:, 0] = out[:, -1] = out[:, :, 0] = out[:, :, -1] = 0.0
-        Q.k_rbgs_double_sweep(f, u, out, h, uc=uc)
-        assert torch.equal(out, pb), "prolong"
+        for v in (8, 9):
+            Q.tune_set_fused(n, v, 0)
+            out = torch.full_like(u, 3.0)
+            out[0] = out[-1] = out[:, 0] = out[:, -1] = out[:, :, 0] = out[:, :, -1] = 0.0
+            Q.k_rbgs_double_sweep(f, u, out, h)
+            assert torch.equal(out, b), v
+            out.fill_(-2.0)
+            out[0] = out[-1] = out[:, 0] = out[:, -1] = out[:, :, 0] = out[:, :, -1] = 0.0
+            Q.k_rbgs_double_sweep(f, None, out, h)
+            assert torch.equal(out, zb), v
+            nc = (n + 1) // 2
+            uc = torch.randn((nc,) * 3, dtype=torch.float64, device="cuda", generator=g)
+            uc[0] = uc[-1] = uc[:, 0] = uc[:, -1] = uc[:, :, 0] = uc[:, :, -1] = 0.0
+            p = u.clone()
+            Q.k_prolong_add(uc, p)
+            pa, pb = p.clone(), p.clone()
+            Q.k_rbgs_sweep(f, p, pa, h)
+            Q.k_rbgs_sweep(f, pa, pb, h)
+            out.fill_(5.0)
+            out[0] = out[-1] = out[:, 0] = out[:, -1] = out[:, :, 0] = out[:, :, -1] = 0.0
+            Q.k_rbgs_double_sweep(f, u, out, h, uc=uc)
+            assert torch.equal(out, pb), (v, "prolong")
     finally:
         Q.tune_set_fused(n, *before)
 
