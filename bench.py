@@ -581,9 +581,9 @@ def main():
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
     sweeps = st.get("sweeps_per_launch", 1) or 1
     if sweeps == 2:
-        kern = ("red-black smoother, finest (513^3) level: the skewed two-sweep launches (rbgs2_skew_k: each "
-                "smoothing pair of a V-cycle in one pass, the coarse-grid correction added by a launch of its own "
-                "before the post-smoothing pair; 24 B per node per launch of two sweeps), FP64")
+        kern = ("red-black smoother, finest (513^3) level: the skewed two-sweep launches (rbgs2_skew_k: the "
+                "pre-smoothing pair of each V-cycle in one pass; the post-smoothing pair, which also applies the "
+                "coarse-grid correction in its launch, is left out; 24 B per node per launch of two sweeps), FP64")
     else:
         kern = ("red-black smoother, finest (513^3) level, plain sweeps (one per launch; the first "
                 "post-smoothing sweep, which also applies the coarse-grid correction, is left out), FP64 "
