@@ -42,12 +42,12 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
     constexpr int HPX = PX / 2, NPL = HPX * PY;            // x-pairs of nodes of an LDS plane
     constexpr int HP = PX / 2, NP = HP * (TY + 6);         // node pairs: four-node ring in x, three in y
     static_assert(TX % 2 == 0 && NP <= NT, "at most one pair of nodes per thread");
-    // coarse footprint of the LDS region (tile origins are odd): TX / 2 + 5 by TY / 2 + 5 coarse nodes
-    constexpr int CPX = TX / 2 + 5, CPY = TY / 2 + 5, CPL = CPX * CPY;
-    static_assert(!PROLONG || CPL <= NT, "one coarse node per thread");
+    // coarse rows of the LDS region (tile origins are odd): TY / 2 + 5; a coarse
+    // plane is staged interpolated along x, on the region's fine columns
+    constexpr int CPY = TY / 2 + 5, XPL = PX * CPY, NXL = (XPL + NT - 1) / NT;
     static_assert(NPL <= NT, "one pair of an LDS plane per thread");
     __shared__ T pl[NS][PL];
-    __shared__ T cpl[PROLONG ? 3 : 1][PROLONG ? CPL : 1];   // coarse planes c in slot c % 3
+    __shared__ T cpl[PROLONG ? 3 : 1][PROLONG ? XPL : 1];   // coarse plane c, along x, in slot c % 3
     const T sixth = T(1) / T(6);
     const int tid = threadIdx.x;
     const unsigned tl = xcd_tile(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
@@ -78,46 +78,68 @@ rbgs2_skew_k(const T *__restrict__ uin, T *__restrict__ uout, const T *__restric
         if (ZERO) return;
         vv = *reinterpret_cast<const pair_t *>(uin + (size_t)k * nn + qoff);
     };
-    // The correction's coarse data: this thread's coarse node of the footprint
-    // (coff, or -1; a lane with nothing to load reads the footprint's corner)
-    // and, per node e of the thread's pair that is interior in x and y, the
-    // offset of its lower coarse neighbour in the footprint with the parities
-    // of i and j in bits 16 and 17 (else -1).
-    const int ci0 = (i0 - RG) >> 1, cj0 = (j0 - RG) >> 1;
-    int coff = -1, cidle = 0, cnb[2] = {-1, -1};
+    // The correction's coarse data: per staged entry r of this thread (fine
+    // column a = t % PX, coarse row cj0 + t / PX of the region), the two
+    // coarse nodes its x-interpolation weighs (xo, or -1 where the column is
+    // not interior or the row is outside the grid: a lane with nothing to load
+    // reads the first of the region's coarse nodes) and the column's parity;
+    // per node e of the thread's pair that is interior in x and y, the offset
+    // of its column and lower coarse row in the staged plane with the parity
+    // of j in bit 16 (else -1).
+    const int cj0 = (j0 - RG) >> 1;
+    int xo[NXL], cnb[2] = {-1, -1};
+    bool xodd[NXL];
+    const int cidle = max((i0 - RG) >> 1, 0) + nc * max(cj0, 0);
     if constexpr (PROLONG) {
-        const int I = ci0 + tid % CPX, J = cj0 + tid / CPX;
-        coff = (tid < CPL && I >= 0 && I < nc && J >= 0 && J < nc) ? I + nc * J : -1;
-        cidle = max(ci0, 0) + nc * max(cj0, 0);
+#pragma unroll
+        for (int r = 0; r < NXL; ++r) {
+            const int t = tid + r * NT;
+            const int i = i0 - RG + t % PX, J = cj0 + t / PX;
+            xo[r] = (t < XPL && i >= 1 && i <= n - 2 && J >= 0 && J < nc) ? (i >> 1) + nc * J : -1;
+            xodd[r] = i & 1;
+        }
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-            const int i = iq + e, j = jq;
+            const int a = 2 * qa + e, i = iq + e, j = jq;
             cnb[e] = (tid < NPL && i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2)
-                         ? ((i >> 1) - ci0) + CPX * ((j >> 1) - cj0) + ((i & 1) << 16) + ((j & 1) << 17)
+                         ? a + PX * ((j >> 1) - cj0) + ((j & 1) << 16)
                          : -1;
         }
     }
-    T cv = T(0);
-    auto fetch_c = [&](int c) {   // coarse plane c (clamped into the grid) into cv
-        if constexpr (PROLONG) cv = uc[(size_t)min(c, nc - 1) * nc * nc + (coff >= 0 ? coff : cidle)];
-    };
-    auto store_c = [&](int c) {   // ... into its LDS slot
+    T cv0[NXL], cv1[NXL];
+    auto fetch_c = [&](int c) {   // the coarse nodes of plane c (clamped into the grid) into cv0, cv1
         if constexpr (PROLONG) {
-            if (c <= nc - 1 && tid < CPL) cpl[c % 3][tid] = coff >= 0 ? cv : T(0);
+            const T *C = uc + (size_t)min(c, nc - 1) * nc * nc;
+#pragma unroll
+            for (int r = 0; r < NXL; ++r) {
+                const int o = xo[r] >= 0 ? xo[r] : cidle;
+                cv0[r] = C[o];
+                cv1[r] = C[xodd[r] && xo[r] >= 0 ? o + 1 : o];
+            }
         }
     };
-    // the correction at a node of plane k (1 <= k <= n - 2) from its packed coarse offset
+    // ... interpolated along x into its LDS slot (prolong_at's x step: weights 1, 0 at even columns, 1/2, 1/2 at odd)
+    auto store_c = [&](int c) {
+        if constexpr (PROLONG) {
+            if (c > nc - 1) return;
+#pragma unroll
+            for (int r = 0; r < NXL; ++r) {
+                const int t = tid + r * NT;
+                if (t >= XPL) continue;
+                const T wia = xodd[r] ? T(0.5) : T(1), wib = xodd[r] ? T(0.5) : T(0);
+                cpl[c % 3][t] = xo[r] >= 0 ? wia * cv0[r] + wib * cv1[r] : T(0);
+            }
+        }
+    };
+    // the correction at a node of plane k (1 <= k <= n - 2) from its packed offset:
+    // prolong_at's y and z steps on the staged planes
     auto corr = [&](int cw, int k) {
-        const int o = cw & 0xffff, di = (cw >> 16) & 1, dj = (cw >> 17) & 1;
-        const T wia = di ? T(0.5) : T(1), wib = di ? T(0.5) : T(0);
+        const int o = cw & 0xffff, dj = (cw >> 16) & 1;
         const T wja = dj ? T(0.5) : T(1), wjb = dj ? T(0.5) : T(0);
         const T wka = (k & 1) ? T(0.5) : T(1), wkb = (k & 1) ? T(0.5) : T(0);
-        const T *Ca = cpl[(k >> 1) % 3], *Cb = cpl[((k + 1) >> 1) % 3];
-        const int oj = o + dj * CPX;
-        const T xa = wia * Ca[o] + wib * Ca[o + di];
-        const T xb = wia * Ca[oj] + wib * Ca[oj + di];
-        const T xc = wia * Cb[o] + wib * Cb[o + di];
-        const T xd = wia * Cb[oj] + wib * Cb[oj + di];
+        const T *Xa = cpl[(k >> 1) % 3], *Xb = cpl[((k + 1) >> 1) % 3];
+        const int oj = o + dj * PX;
+        const T xa = Xa[o], xb = Xa[oj], xc = Xb[o], xd = Xb[oj];
         return wka * (wja * xa + wjb * xb) + wkb * (wja * xc + wjb * xd);
     };
     // With the correction only the black node of a pair takes it: a red
